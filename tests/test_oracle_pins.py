@@ -1,0 +1,465 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics:
+closed forms, brute force over all pairs on tiny graphs, invariants, special
+cases and hand-derived values (tests/golden/hand_derived.json)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_08909_amd import graphs as G
+from tests import brute
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "hand_derived.json")))
+
+
+def _graph(spec):
+    if spec["family"] == "path":
+        return G.path(spec["n"])
+    if spec["family"] == "grid":
+        return G.grid(spec["rows"], spec["cols"])
+    if spec["family"] == "edges":
+        return G.csr_from_edges(spec["n"], np.array(spec["edges"]))
+    raise ValueError(spec)
+
+
+def _tiny_graphs():
+    out = [G.path(9), G.cycle(10), G.cycle(7), G.star(8), G.complete(6), G.grid(4, 5),
+           G.tri_grid(4, 4)]
+    for s in range(4):
+        out.append(G.random_connected(14 + s, 0.15, seed=s))
+        out.append(G.tree_plus(16 + s, seed=s))
+    out.append(G.rgg(60, seed=3, mean_degree=7.0))
+    out.append(G.barabasi_albert(40, 2, seed=5))
+    return out
+
+
+# ------------------------------------------------------------------ BFS
+
+def _closed_form_rows(g, kind, shape=None):
+    n = g.n
+    i = np.arange(n)
+    if kind == "path":
+        return np.abs(i[:, None] - i[None, :])
+    if kind == "cycle":
+        a = np.abs(i[:, None] - i[None, :])
+        return np.minimum(a, n - a)
+    if kind == "star":
+        d = np.where((i[:, None] == 0) | (i[None, :] == 0), 1, 2)
+        d[i, i] = 0
+        return d
+    if kind == "complete":
+        return (i[:, None] != i[None, :]).astype(int)
+    R, C = shape
+    r, c = i // C, i % C
+    dr = r[None, :] - r[:, None]
+    dc = c[None, :] - c[:, None]
+    if kind == "grid":
+        return np.abs(dr) + np.abs(dc)
+    if kind == "tri":
+        same = dr * dc >= 0
+        return np.where(same, np.maximum(np.abs(dr), np.abs(dc)), np.abs(dr) + np.abs(dc))
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("g,kind,shape", [
+    (G.path(23), "path", None), (G.cycle(17), "cycle", None), (G.cycle(18), "cycle", None),
+    (G.star(9), "star", None), (G.complete(7), "complete", None),
+    (G.grid(6, 9), "grid", (6, 9)), (G.tri_grid(7, 5), "tri", (7, 5)),
+])
+def test_bfs_closed_forms(g, kind, shape):
+    want = _closed_form_rows(g, kind, shape)
+    for s in range(g.n):
+        assert np.array_equal(oracle.bfs(g.n, g.row_ptr, g.col_idx, s), want[s])
+
+
+def test_bfs_matches_all_pairs():
+    for g in _tiny_graphs():
+        D = brute.apsp(g)
+        for s in range(g.n):
+            assert np.array_equal(oracle.bfs(g.n, g.row_ptr, g.col_idx, s), D[s]), g.name
+
+
+def test_bfs_invariants():
+    for g in _tiny_graphs():
+        k = min(6, g.n)
+        piv, dist = oracle.select_pivots(g.n, g.row_ptr, g.col_idx, k, 0)
+        e = g.edges()
+        assert np.all(np.abs(dist[:, e[:, 0]] - dist[:, e[:, 1]]) <= 1)
+        assert np.array_equal(dist[:, piv], dist[:, piv].T)
+        assert np.all(dist[np.arange(k), piv] == 0)
+
+
+# --------------------------------------------------------------- pivots
+
+@pytest.mark.parametrize("key", ["maxmin_path30_k5", "maxmin_grid50_first4"])
+def test_maxmin_golden(key):
+    gd = GOLDEN[key]
+    g = _graph(gd["graph"])
+    piv, _ = oracle.select_pivots(g.n, g.row_ptr, g.col_idx, gd["k"], gd["first"])
+    assert piv.tolist() == gd["pivots"]
+
+
+def test_maxmin_brute():
+    for g in _tiny_graphs():
+        D = brute.apsp(g)
+        for k in sorted({1, 2, 3, g.n // 2, g.n}):
+            for first in (0, g.n - 1):
+                piv, dist = oracle.select_pivots(g.n, g.row_ptr, g.col_idx, k, first)
+                assert piv.tolist() == brute.maxmin_brute(D, k, first), (g.name, k, first)
+                assert np.array_equal(dist, D[piv])
+                assert len(set(piv.tolist())) == k
+
+
+# -------------------------------------------------------------- regions
+
+@pytest.mark.parametrize("key", ["regions_path5_equal_sizes", "regions_tie_to_smaller"])
+def test_regions_golden(key):
+    gd = GOLDEN[key]
+    g = _graph(gd["graph"])
+    dist = oracle.bfs_pivots(g.n, g.row_ptr, g.col_idx, gd["pivots"])
+    _, region, _, _ = oracle.regions(dist)
+    assert region.tolist() == gd["region"]
+    if "pivots_swapped" in gd:
+        dist = oracle.bfs_pivots(g.n, g.row_ptr, g.col_idx, gd["pivots_swapped"])
+        _, region, _, _ = oracle.regions(dist)
+        assert region.tolist() == gd["region_swapped"]
+
+
+def _check_region_rule(dist, delta, region, size):
+    """A-posteriori check of the tie rule: every tied node at level l sits in a
+    candidate region whose size (all members below l plus the single-candidate
+    members at l) is minimal, lowest rank among equals."""
+    k, n = dist.shape
+    ncand = (dist == delta[None, :]).sum(0)
+    for lvl in np.unique(delta):
+        at = np.flatnonzero(delta == lvl)
+        below = np.bincount(region[delta < lvl], minlength=k)
+        single = at[ncand[at] == 1]
+        snap = below + np.bincount(region[single], minlength=k)
+        for i in at[ncand[at] > 1]:
+            cands = np.flatnonzero(dist[:, i] == lvl)
+            best = min(cands, key=lambda t: (snap[t], t))
+            assert region[i] == best
+
+
+def test_regions_invariants():
+    for g in _tiny_graphs() + [G.grid(50, 50)]:
+        for k in sorted({1, 2, min(5, g.n), g.n // 3 or 1}):
+            piv, dist = oracle.select_pivots(g.n, g.row_ptr, g.col_idx, k, 0)
+            delta, region, size, dm = oracle.regions(dist)
+            assert np.array_equal(delta, dist.min(0))
+            assert dm == delta.max()
+            assert region.min() >= 0 and region.max() < k
+            assert np.array_equal(np.bincount(region, minlength=k), size)   # partition
+            assert np.all(region[piv] == np.arange(k))                       # p in R(p)
+            assert np.all(dist[region, np.arange(g.n)] == delta)             # nearest pivot
+            _check_region_rule(dist, delta, region, size)
+
+
+def test_regions_k_equals_n():
+    for g in _tiny_graphs():
+        piv, dist = oracle.select_pivots(g.n, g.row_ptr, g.col_idx, g.n, 0)
+        _, region, size, dm = oracle.regions(dist)
+        assert dm == 0 and np.all(size == 1)
+        assert np.array_equal(piv[region], np.arange(g.n))
+
+
+def test_regions_grid50_k50():
+    g = G.grid(50, 50)
+    piv, dist = oracle.select_pivots(g.n, g.row_ptr, g.col_idx, 50, 0)
+    delta, region, size, dm = oracle.regions(dist)
+    assert dm == 6 and size.min() == 21 and size.max() == 78
+    assert int(((dist == delta[None, :]).sum(0) > 1).sum()) == 277
+
+
+# -------------------------------------------------------------- weights
+
+def test_weights_golden():
+    gd = GOLDEN["regions_tie_to_smaller"]
+    g = _graph(gd["graph"])
+    dist = oracle.bfs_pivots(g.n, g.row_ptr, g.col_idx, gd["pivots"])
+    T = oracle.build_terms(g.row_ptr, g.col_idx, gd["pivots"], dist)
+    for i, t, w in gd["weights"]["node_pivotrank_weight"]:
+        assert T.wtab[t, dist[t, i]] == w
+
+
+def test_weights_brute():
+    for g in _tiny_graphs() + [G.grid(12, 13)]:
+        D = brute.apsp(g)
+        for k in sorted({2, min(5, g.n), g.n // 2, g.n}):
+            piv, dist = oracle.select_pivots(g.n, g.row_ptr, g.col_idx, k, 0)
+            T = oracle.build_terms(g.row_ptr, g.col_idx, piv, dist)
+            Wb = brute.weights_brute(D, piv, T.region)
+            Wo = T.wtab[np.arange(k)[None, :], dist.T]
+            assert np.array_equal(Wo, Wb), (g.name, k)
+            # s >= 1 wherever a pivot term exists
+            s = np.rint(Wo * dist.T.astype(float) ** 2)
+            assert np.all(s[dist.T >= 2] >= 1)
+            assert np.all(Wo[dist.T < 2] == 0)
+            deg = np.diff(g.row_ptr)
+            assert np.array_equal(T.den, deg + Wb.sum(1)) or np.allclose(T.den, deg + Wb.sum(1), rtol=1e-15)
+
+
+def test_weights_k_equals_n_full_model():
+    for g in _tiny_graphs():
+        piv, dist = oracle.select_pivots(g.n, g.row_ptr, g.col_idx, g.n, 0)
+        T = oracle.build_terms(g.row_ptr, g.col_idx, piv, dist)
+        W = T.wtab[np.arange(g.n)[None, :], dist.T]
+        d = dist.T.astype(float)
+        want = np.where(d >= 2, 1.0 / np.where(d > 0, d, 1) ** 2, 0.0)
+        assert np.array_equal(W, want)
+
+
+def test_weights_path_two_pivots_closed_form():
+    for n in (9, 10, 31, 32):
+        g = G.path(n)
+        piv = [0, n - 1]
+        dist = oracle.bfs_pivots(g.n, g.row_ptr, g.col_idx, piv)
+        T = oracle.build_terms(g.row_ptr, g.col_idx, piv, dist)
+        sizes = [(n + 1) // 2, n // 2]   # odd n: the middle node joins rank 0
+        assert T.size.tolist() == sizes
+        for t in range(2):
+            for i in range(n):
+                d = int(dist[t, i])
+                if d < 2:
+                    continue
+                s = min(d // 2 + 1, sizes[t])
+                assert T.wtab[t, d] == s / (d * d)
+
+
+# ------------------------------------------------------------- PivotMDS
+
+def test_pmds_centering_and_gram():
+    for g in [G.grid(20, 30), G.rgg(400, seed=2), G.barabasi_albert(300, 3, seed=1)]:
+        piv, dist = oracle.select_pivots(g.n, g.row_ptr, g.col_idx, 20, 0)
+        C = oracle.pmds_center(dist)
+        scale = np.abs(C).max()
+        assert np.abs(C.sum(0)).max() <= 1e-12 * scale * g.n
+        assert np.abs(C.sum(1)).max() <= 1e-12 * scale * 20
+        M = oracle.gram(C)
+        assert np.allclose(M, C.T @ C, rtol=1e-12, atol=1e-12 * np.abs(M).max())
+        ev, E = oracle.sym_eig(M)
+        wn, vn = np.linalg.eigh(M)
+        assert np.allclose(np.sort(ev), wn, rtol=0, atol=1e-12 * wn.max())
+        x, V, lam = oracle.pivotmds(dist)
+        assert np.allclose(lam, wn[::-1][:2], rtol=1e-12)
+        for a in range(2):
+            v = vn[:, -1 - a]
+            v = v * np.sign(v[np.argmax(np.abs(v))])
+            assert np.allclose(V[:, a], v, atol=1e-10)
+            assert V[np.argmax(np.abs(V[:, a])), a] > 0
+        assert np.allclose(x, C @ V, rtol=1e-12, atol=1e-12 * np.abs(x).max())
+
+
+def test_pmds_path_is_exact():
+    """A path's pivot distances are Euclidean on a line: PivotMDS is exact and
+    after the rescale every edge has length 1 (zero full stress)."""
+    for n, k in [(30, 5), (57, 8)]:
+        g = G.path(n)
+        piv, dist = oracle.select_pivots(g.n, g.row_ptr, g.col_idx, k, 0)
+        x0 = oracle.rescale(g.row_ptr, g.col_idx, oracle.pivotmds(dist)[0])
+        assert oracle.stress_full(g.row_ptr, g.col_idx, x0) < 1e-20
+        assert brute.full_stress(brute.apsp(g), x0) < 1e-20
+
+
+def test_rescale_closed_form():
+    g = G.rgg(300, seed=5)
+    x = np.random.default_rng(0).normal(size=(g.n, 2))
+    y = oracle.rescale(g.row_ptr, g.col_idx, x)
+    e = g.edges()
+    assert abs(np.linalg.norm(y[e[:, 0]] - y[e[:, 1]], axis=1).sum() - g.m) < 1e-9 * g.m
+    c = y / x
+    assert np.allclose(c, c[0, 0])
+
+
+# ---------------------------------------------------------- majorization
+
+def _terms_full(g):
+    piv, dist = oracle.select_pivots(g.n, g.row_ptr, g.col_idx, g.n, 0)
+    return oracle.build_terms(g.row_ptr, g.col_idx, piv, dist)
+
+
+def test_k_equals_n_update_is_localized_full_stress():
+    rng = np.random.default_rng(1)
+    for g in _tiny_graphs():
+        T = _terms_full(g)
+        D = brute.apsp(g)
+        x = rng.normal(size=(g.n, 2)) * 3
+        x1, _ = oracle.majorize(g.row_ptr, g.col_idx, T.pivots, T.dist, T.wtab, T.den, x, 1)
+        assert np.allclose(x1, brute.localized_full_step(D, x), rtol=1e-12, atol=1e-12), g.name
+
+
+def test_monotone_full_stress_k_equals_n():
+    rng = np.random.default_rng(2)
+    for g in _tiny_graphs():
+        T = _terms_full(g)
+        D = brute.apsp(g)
+        x = rng.normal(size=(g.n, 2)) * 2
+        s_prev = brute.full_stress(D, x)
+        for _ in range(15):
+            x, _ = oracle.majorize(g.row_ptr, g.col_idx, T.pivots, T.dist, T.wtab, T.den, x, 1)
+            s = brute.full_stress(D, x)
+            assert s <= s_prev * (1 + 1e-12) + 1e-12, g.name
+            s_prev = s
+
+
+def test_zero_stress_path_is_fixed():
+    for n, k in [(20, 3), (20, 7), (31, 31)]:
+        g = G.path(n)
+        piv, dist = oracle.select_pivots(g.n, g.row_ptr, g.col_idx, k, 0)
+        T = oracle.build_terms(g.row_ptr, g.col_idx, piv, dist)
+        ang = 0.3
+        x = np.stack([np.arange(n) * math.cos(ang), np.arange(n) * math.sin(ang)], 1) + [2.0, -1.0]
+        x1, _ = oracle.majorize(g.row_ptr, g.col_idx, T.pivots, T.dist, T.wtab, T.den, x, 3)
+        assert np.abs(x1 - x).max() < 1e-12
+
+
+def _ngon_radius(n):
+    h = np.arange(1, n)
+    d = np.minimum(h, n - h).astype(float)
+    c = 2 * np.sin(np.pi * h / n)
+    w = 1 / d ** 2
+    return (w * d * c).sum() / (w * c * c).sum()
+
+
+def test_regular_polygon_fixed_point():
+    n = 12
+    g = G.cycle(n)
+    T = _terms_full(g)
+    r = _ngon_radius(n)
+    assert abs(r - 2.1854946005562663) < 1e-14
+    a = 2 * np.pi * np.arange(n) / n
+    x = r * np.stack([np.cos(a), np.sin(a)], 1)
+    x1, _ = oracle.majorize(g.row_ptr, g.col_idx, T.pivots, T.dist, T.wtab, T.den, x, 1)
+    assert np.abs(x1 - x).max() < 1e-13
+
+
+def test_stress_closed_forms():
+    g = G.path(25)
+    x = np.stack([np.arange(25.0), np.zeros(25)], 1)
+    assert oracle.stress_full(g.row_ptr, g.col_idx, x) == 0.0
+    n, r = 12, 1.7
+    g = G.cycle(n)
+    a = 2 * np.pi * np.arange(n) / n
+    x = r * np.stack([np.cos(a), np.sin(a)], 1)
+    h = np.arange(1, n)
+    d = np.minimum(h, n - h)
+    want = n / 2 * ((2 * r * np.sin(np.pi * h / n) - d) ** 2 / d ** 2).sum()
+    assert abs(oracle.stress_full(g.row_ptr, g.col_idx, x) - want) < 1e-12 * want
+    R, C = 7, 9
+    g = G.grid(R, C)
+    rr, cc = np.divmod(np.arange(R * C), C)
+    x = np.stack([cc, rr], 1).astype(float)
+    want = 0.0
+    for aa in range(R):
+        for bb in range(C):
+            if aa == 0 and bb == 0:
+                continue
+            mult = (R - aa) * (C - bb) * (2 if aa > 0 and bb > 0 else 1)
+            want += mult * (math.hypot(aa, bb) - (aa + bb)) ** 2 / (aa + bb) ** 2
+    assert abs(oracle.stress_full(g.row_ptr, g.col_idx, x) - want) < 1e-12 * want
+
+
+def test_sparse_stress_brute_and_full_identity():
+    rng = np.random.default_rng(3)
+    for g in _tiny_graphs():
+        D = brute.apsp(g)
+        x = rng.normal(size=(g.n, 2)) * 2
+        for k in sorted({2, min(5, g.n), g.n}):
+            piv, dist = oracle.select_pivots(g.n, g.row_ptr, g.col_idx, k, 0)
+            T = oracle.build_terms(g.row_ptr, g.col_idx, piv, dist)
+            s, se, sp = oracle.stress_sparse(g.row_ptr, g.col_idx, piv, dist, T.wtab, x, parts=True)
+            W = brute.weights_brute(D, piv, T.region)
+            r = np.linalg.norm(x[:, None, :] - x[None, piv, :], axis=-1)
+            want_p = (W * (r - D[:, piv]) ** 2).sum()
+            e = g.edges()
+            want_e = ((np.linalg.norm(x[e[:, 0]] - x[e[:, 1]], axis=1) - 1) ** 2).sum()
+            assert abs(sp - want_p) <= 1e-12 * max(1, want_p)
+            assert abs(se - want_e) <= 1e-12 * max(1, want_e)
+            if k == g.n:   # each non-edge pair appears once from each side
+                full = brute.full_stress(D, x)
+                assert abs(s - (se + 2 * (full - se))) <= 1e-11 * full
+
+
+def test_rigid_motion_equivariance():
+    """Eq. 5 commutes with rotations, reflections and translations.  The start
+    layout is random: PivotMDS puts nodes with equal pivot-distance vectors on
+    one point, where the update's direction term is discontinuous (r = 0), so
+    rounding alone would decide how such twins separate."""
+    g = G.rgg(200, seed=8)
+    T = oracle.preprocess(g.n, g.row_ptr, g.col_idx, 12)
+    x0 = np.random.default_rng(4).normal(size=(g.n, 2)) * 5
+    th = 0.77
+    R = np.array([[math.cos(th), -math.sin(th)], [math.sin(th), math.cos(th)]])
+    F = np.diag([1.0, -1.0])
+    args = (g.row_ptr, g.col_idx, T.pivots, T.dist, T.wtab, T.den)
+    x1, _ = oracle.majorize(*args, x0, 20)
+    y1, _ = oracle.majorize(*args, x0 @ R.T @ F + [5.0, -3.0], 20)
+    assert np.abs(y1 - (x1 @ R.T @ F + [5.0, -3.0])).max() < 1e-9 * np.abs(x1).max()
+
+
+def test_resume_and_thread_independence():
+    g = G.grid(20, 20)
+    T = oracle.preprocess(g.n, g.row_ptr, g.col_idx, 10)
+    x0 = oracle.initial_layout(g.row_ptr, g.col_idx, T)
+    args = (g.row_ptr, g.col_idx, T.pivots, T.dist, T.wtab, T.den)
+    a, _ = oracle.majorize(*args, x0, 30)
+    b, _ = oracle.majorize(*args, x0, 12)
+    b, _ = oracle.majorize(*args, b, 18)
+    c, _ = oracle.majorize(*args, x0, 30, threads=4)
+    assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
+def test_tolerance_stop():
+    """The early stop fires at the first sweep whose relative change is within
+    tol.  k = n (symmetric weights) converges to a fixed point; with k < n the
+    asymmetric w' leave a steady rigid drift, so a raw change never vanishes."""
+    g = G.grid(8, 8)
+    T = oracle.preprocess(g.n, g.row_ptr, g.col_idx, g.n)
+    x0 = oracle.initial_layout(g.row_ptr, g.col_idx, T)
+    args = (g.row_ptr, g.col_idx, T.pivots, T.dist, T.wtab, T.den)
+    x, done = oracle.majorize(*args, x0, 1000, tol=1e-4)
+    assert 0 < done < 1000
+    prev, _ = oracle.majorize(*args, x0, done - 1)
+    assert np.linalg.norm(x - prev) / np.linalg.norm(prev) <= 1e-4
+    prev2, _ = oracle.majorize(*args, x0, done - 2)
+    assert np.linalg.norm(prev - prev2) / np.linalg.norm(prev2) > 1e-4
+
+
+def test_sparse_layout_tracks_full_stress():
+    """Soft check of the paper's trend (Table 2): more pivots, full stress
+    closer to the full-stress (k = n) layout."""
+    g = G.grid(20, 20)
+    D = brute.apsp(g)
+    out = {}
+    for k in (10, 40, g.n):
+        x, T, x0, _ = oracle.layout(g.n, g.row_ptr, g.col_idx, k, 200)
+        x = x * ((D[np.triu_indices(g.n, 1)] ** -1.0 * np.linalg.norm(
+            x[:, None] - x[None], axis=-1)[np.triu_indices(g.n, 1)]).sum()
+            / (np.linalg.norm(x[:, None] - x[None], axis=-1)[np.triu_indices(g.n, 1)] ** 2
+               * D[np.triu_indices(g.n, 1)] ** -2.0).sum())
+        out[k] = brute.full_stress(D, x)
+    assert out[g.n] <= out[40] * 1.01 and out[40] <= out[10] * 1.05
+
+
+# ------------------------------------------------------------- contract
+
+def test_validate_rejects_bad_input():
+    g = G.grid(3, 3)
+    assert oracle.validate(g.n, g.row_ptr, g.col_idx) == oracle.OK
+    ci = g.col_idx.copy(); ci[0] = 0                       # self loop at node 0
+    assert oracle.validate(g.n, g.row_ptr, ci) == oracle.INVAL
+    ci = g.col_idx.copy(); ci[1] = ci[0]                   # duplicate in row 0
+    assert oracle.validate(g.n, g.row_ptr, ci) == oracle.INVAL
+    e = np.array([[0, 1], [1, 2]])
+    h = G.csr_from_edges(3, e)
+    rp = np.array([0, 1, 2, 3], dtype=np.int32)            # 0->1, 1->2, 2->1: asymmetric
+    assert oracle.validate(3, rp, np.array([1, 2, 1], dtype=np.int32)) == oracle.INVAL
+    d = G.csr_from_edges(4, np.array([[0, 1], [2, 3]]))
+    with pytest.raises(oracle.OracleError) as ei:
+        oracle.select_pivots(d.n, d.row_ptr, d.col_idx, 2, 0)
+    assert ei.value.status == oracle.DISCONNECTED
+    assert oracle.validate(h.n, h.row_ptr, h.col_idx) == oracle.OK

@@ -400,22 +400,29 @@ int orc_rescale(int n, const int* rp, const int* ci, double* x) {
 /* ------------------------------------------------------------ majorization */
 
 /* One node's Eq. 5 update read from the layout `src`.  Neighbour terms first
- * (CSR order, w = 1, d = 1), then pivot terms for d >= 2 in ascending rank.
+ * (w = 1, d = 1): those at a positive distance in CSR order, then those at
+ * distance zero; then pivot terms for d >= 2 in ascending rank.
  * vote(q, d) = x_q + d (x_i - x_q) / ||x_i - x_q||, or x_q when the distance
- * is zero. */
+ * is zero.  The paper leaves the order of the sums open.  Putting the
+ * zero-distance votes (each equal to x_i) last makes the update of two
+ * adjacent nodes with the same position and the same closed neighbourhood
+ * identical, as it is in exact arithmetic; summed in CSR order the two would
+ * drift apart by rounding alone. */
 static void update_node(int i, int n, const int* rp, const int* ci, int k, const int* pivots,
                         const int* dist, const double* wtab, int dmax, const double* den,
                         const double* src, double* out) {
     double xi = src[2 * (size_t)i], yi = src[2 * (size_t)i + 1];
     double nx = 0.0, ny = 0.0;
+    int zero = 0;
     for (int e = rp[i]; e < rp[i + 1]; ++e) {
         int j = ci[e];
         double xj = src[2 * (size_t)j], yj = src[2 * (size_t)j + 1];
         double dx = xi - xj, dy = yi - yj;
         double r = sqrt(dx * dx + dy * dy);
         if (r > 0.0) { nx += xj + 1.0 * dx / r; ny += yj + 1.0 * dy / r; }
-        else { nx += xj; ny += yj; }
+        else ++zero;
     }
+    for (int z = 0; z < zero; ++z) { nx += xi; ny += yi; }
     for (int t = 0; t < k; ++t) {
         int d = dist[(size_t)t * n + i];
         if (d < 2) continue;

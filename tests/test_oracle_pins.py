@@ -306,6 +306,29 @@ def test_monotone_full_stress_k_equals_n():
             s_prev = s
 
 
+def test_twins_stay_together():
+    """Two adjacent nodes with the same closed neighbourhood have the same
+    pivot distances, so PivotMDS puts them on one point; in exact arithmetic
+    Eq. 5 then moves them identically forever (their vote to each other is at
+    distance zero).  The oracle must reproduce that exactly, whatever the CSR
+    order puts between them."""
+    # twins 3 and 9 (ids far apart, other neighbours in between), plus a
+    # false twin pair 5, 7 (same open neighbourhood, not adjacent)
+    e = [[0, 1], [1, 2], [2, 0], [3, 9], [3, 1], [9, 1], [3, 4], [9, 4], [3, 8], [9, 8],
+         [4, 6], [6, 10], [10, 11], [8, 11], [5, 6], [7, 6], [2, 11], [4, 2]]
+    g = G.csr_from_edges(12, np.array(e))
+    N = [set(g.col_idx[g.row_ptr[i]:g.row_ptr[i + 1]].tolist()) for i in range(g.n)]
+    assert N[3] | {3} == N[9] | {9} and N[5] == N[7]
+    for k in (3, 4, 5):   # from node 6 no twin becomes a pivot (a pivot breaks the symmetry)
+        T = oracle.preprocess(g.n, g.row_ptr, g.col_idx, k, first=6)
+        assert not set(T.pivots.tolist()) & {3, 9, 5, 7}
+        x0 = oracle.initial_layout(g.row_ptr, g.col_idx, T)
+        assert np.array_equal(x0[3], x0[9]) and np.array_equal(x0[5], x0[7])
+        x, _ = oracle.majorize(g.row_ptr, g.col_idx, T.pivots, T.dist, T.wtab, T.den, x0, 300)
+        assert np.array_equal(x[3], x[9]) and np.array_equal(x[5], x[7])
+        assert np.abs(x[3] - x[1]).max() > 1e-3
+
+
 def test_zero_stress_path_is_fixed():
     for n, k in [(20, 3), (20, 7), (31, 31)]:
         g = G.path(n)

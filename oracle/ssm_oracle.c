@@ -29,7 +29,8 @@
  *     is x_q).
  *   - PivotMDS (cited, not defined, in the paper): x = C v for the top two
  *     eigenvectors v of C^T C, C the double-centred squared pivot distances;
- *     each eigenvector's largest-magnitude entry is made positive.
+ *     each eigenvector's largest-magnitude entry is made positive (entries
+ *     within a relative 1e-9 of the largest count as tied; lowest index wins).
  *   - Rescale target: sum over edges of the edge length (m for unit lengths).
  */
 #include <math.h>
@@ -341,7 +342,7 @@ int orc_sym_eig(int k, const double* M, double* evals, double* evecs) {
 
 /* PivotMDS: x_i = (C V)_i for V the eigenvectors of C^T C of the two largest
  * eigenvalues (descending); each column's largest-|.| entry is made positive
- * (lowest index on ties).  x is n x 2 interleaved; V (k x 2) and lambda (2)
+ * (lowest index among entries within a relative 1e-9 of the largest).  x is n x 2 interleaved; V (k x 2) and lambda (2)
  * are returned as well.  Needs k >= 3 (centring makes C 1 = 0, so rank <= k-1). */
 int orc_pivotmds(int n, int k, const int* dist, double* x, double* V, double* lambda) {
     if (k < 3) return ORC_INVAL;
@@ -360,9 +361,15 @@ int orc_pivotmds(int n, int k, const int* dist, double* x, double* V, double* la
         if (c != c0 && (c1 < 0 || ev[c] > ev[c1])) c1 = c;
     int cols[2] = {c0, c1};
     for (int a = 0; a < 2; ++a) {
+        /* sign rule: the entry of largest magnitude is made positive; entries
+         * within a relative 1e-9 of the largest count as tied (ties that are
+         * exact in exact arithmetic, as on symmetric graphs, are not exact
+         * after rounding) and the lowest index among them decides */
+        double mx = 0.0;
+        for (int t = 0; t < k; ++t)
+            if (fabs(E[(size_t)t * k + cols[a]]) > mx) mx = fabs(E[(size_t)t * k + cols[a]]);
         int big = 0;
-        for (int t = 1; t < k; ++t)
-            if (fabs(E[(size_t)t * k + cols[a]]) > fabs(E[(size_t)big * k + cols[a]])) big = t;
+        while (big < k - 1 && fabs(E[(size_t)big * k + cols[a]]) < mx * (1.0 - 1e-9)) ++big;
         double sgn = E[(size_t)big * k + cols[a]] < 0.0 ? -1.0 : 1.0;
         for (int t = 0; t < k; ++t) V[t * 2 + a] = sgn * E[(size_t)t * k + cols[a]];
         lambda[a] = ev[cols[a]];

@@ -248,10 +248,21 @@ def test_pmds_centering_and_gram():
         assert np.allclose(lam, wn[::-1][:2], rtol=1e-12)
         for a in range(2):
             v = vn[:, -1 - a]
-            v = v * np.sign(v[np.argmax(np.abs(v))])
+            big = np.flatnonzero(np.abs(v) >= np.abs(v).max() * (1 - 1e-9))[0]
+            v = v * np.sign(v[big])
             assert np.allclose(V[:, a], v, atol=1e-10)
             assert V[np.argmax(np.abs(V[:, a])), a] > 0
         assert np.allclose(x, C @ V, rtol=1e-12, atol=1e-12 * np.abs(x).max())
+
+
+def test_pmds_sign_rule_on_symmetric_star():
+    """Star with pivots [centre, leaf, leaf]: the dominant eigenvector has two
+    entries of equal magnitude in exact arithmetic; the lower index decides."""
+    g = G.star(12)
+    piv, dist = oracle.select_pivots(g.n, g.row_ptr, g.col_idx, 3, 0)
+    x, V, lam = oracle.pivotmds(dist)
+    assert abs(abs(V[1, 0]) - abs(V[2, 0])) < 1e-12 and V[1, 0] > 0
+    assert lam[0] == pytest.approx(4.0) and lam[1] == pytest.approx(1.5)
 
 
 def test_pmds_path_is_exact():

@@ -1,0 +1,165 @@
+/*
+ * ssm.h - C ABI of libssm, the MI355X (gfx950) implementation of the hot path
+ * of the sparse stress model (Ortmann, Klimenta, Brandes, "A Sparse Stress
+ * Model"): max/min pivot sampling, the pivots' BFS distances, the regions
+ * R(p), the adapted weights w'_ip, the PivotMDS start layout and the
+ * iterative localized majorization of Eq. 5.
+ *
+ * Conventions for every call:
+ *   - Pointers named *_host are host memory; every other pointer is device
+ *     memory on the current HIP device.  The caller owns every buffer except
+ *     an ssm_terms handle, which the library owns until ssm_terms_free.
+ *   - The graph is a simple undirected graph in symmetric CSR form (Section 1
+ *     of the paper): int32 row_ptr[n+1], int32 col_idx[nnz], nnz = 2m, no
+ *     self-loops, no duplicate arcs, every arc (u,v) matched by (v,u); edge
+ *     lengths are 1 (unweighted).  The method needs a connected graph (the
+ *     paper keeps the largest component, Section 4 "Data").  Rows need not be
+ *     sorted; the CSR order is the order in which neighbour terms are summed.
+ *   - Work is enqueued on `stream`.  A call that returns a value to the host
+ *     (a status found on the device, a stress value, an iteration count)
+ *     synchronizes that stream before it returns.
+ *   - Host-detectable argument errors return before anything is enqueued and
+ *     write nothing.  On any status other than SSM_OK, ssm_last_error()
+ *     returns a message for the calling thread.
+ *   - Layouts x are n x 2 interleaved (x_i^1, x_i^2), of type double for
+ *     SSM_FP64 and float for SSM_FP32.
+ *   - The distance table dist is k x n int32, pivot-major: row t holds the
+ *     hop distances from pivots[t] to every node.
+ */
+#ifndef SSM_H
+#define SSM_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SSM_OK = 0,
+    SSM_E_INVAL = 1,         /* bad argument or malformed graph */
+    SSM_E_RANGE = 2,         /* size outside what the library supports */
+    SSM_E_DISCONNECTED = 3,  /* a BFS did not reach every node */
+    SSM_E_NOMEM = 4,         /* device allocation failed */
+    SSM_E_DEVICE = 5         /* a HIP call failed */
+} ssm_status;
+
+typedef enum { SSM_FP64 = 0, SSM_FP32 = 1 } ssm_prec;
+
+typedef enum { SSM_STRESS_SPARSE = 0, SSM_STRESS_FULL = 1 } ssm_stress_kind;
+
+typedef struct {
+    int32_t n;               /* nodes, >= 1 */
+    int32_t nnz;             /* arcs = 2 m */
+    const int32_t* row_ptr;  /* device [n+1] */
+    const int32_t* col_idx;  /* device [nnz] */
+} ssm_csr;
+
+typedef struct ssm_terms ssm_terms; /* opaque, library-owned device state */
+
+/* Checks on the device that g is a simple symmetric CSR: row_ptr monotone
+ * from 0 to nnz, indices in range, no self-loop, no duplicate arc, every arc
+ * matched by its reverse.  SSM_OK or SSM_E_INVAL.  Synchronizes. */
+ssm_status ssm_validate_csr(const ssm_csr* g, hipStream_t stream);
+
+/* Max/min shortest-path sampling (Section 4.1, "max/min sp"): pivots[0] =
+ * first; pivots[t+1] is the node whose hop distance to the nearest of
+ * pivots[0..t] is largest, the lowest node id on ties.  k in [1, n].
+ * Writes pivots (device int32 [k]); if dist is not NULL also the k x n
+ * distance table of those pivots.  SSM_E_DISCONNECTED if the graph is not
+ * connected.  Synchronizes. */
+ssm_status ssm_select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pivots,
+                             int32_t* dist, hipStream_t stream);
+
+/* BFS from every pivot (the unweighted multi-source shortest paths of
+ * Section 3, "Asymptotic running time") and the regions R(p) (Section 3):
+ * dist (k x n), delta[i] = min_t dist[t][i] (distance to the nearest pivot),
+ * region[i] = rank t of the pivot whose region holds i.  A node with one
+ * nearest pivot joins it; ties favour the currently smallest region, read
+ * level by level in delta: at level l the single-candidate nodes join first,
+ * then each tied node joins the candidate with the smallest (size after
+ * those joins, rank).  pivots must be distinct.  SSM_E_DISCONNECTED if a BFS
+ * misses a node.  Synchronizes. */
+ssm_status ssm_bfs_pivots(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dist,
+                          int32_t* delta, int32_t* region, hipStream_t stream);
+
+/* Regions only, from a distance table already computed (same rule as
+ * ssm_bfs_pivots).  Synchronizes. */
+ssm_status ssm_regions(int32_t n, int32_t k, const int32_t* dist, int32_t* delta,
+                       int32_t* region, hipStream_t stream);
+
+/* Term set of Eq. 3 and Eq. 5 (Section 3, adapted weights): a pivot term
+ * (i, t) exists iff dist[t][i] >= 2; its weight is w'_it = s / d^2 with
+ * d = dist[t][i] and s = |{ j in R(pivots[t]) : delta_j <= floor(d / 2) }|,
+ * i.e. the members of the region no farther from the pivot than half of d.
+ * Builds the library-owned handle *out: a compressed copy of dist, the
+ * cumulative region histograms H[t][l], the weight tables in FP64 and FP32
+ * (FP64 by one correctly rounded division), the per-node denominators of
+ * Eq. 5 (degree plus the pivot weights in ascending rank) and the scratch the
+ * sweeps need.  Synchronizes.  Inputs are not retained. */
+ssm_status ssm_build_terms(const ssm_csr* g, int32_t k, const int32_t* pivots,
+                           const int32_t* dist, const int32_t* delta, const int32_t* region,
+                           ssm_terms** out, hipStream_t stream);
+
+void ssm_terms_free(ssm_terms* t);
+
+/* Shape of a handle: k, delta_max (= max delta) and dmax (= max dist). */
+ssm_status ssm_terms_dims(const ssm_terms* t, int32_t* k_host, int32_t* delta_max_host,
+                          int32_t* dmax_host);
+
+/* Copies tables out of a handle to host buffers (NULL skips one):
+ * H [k][delta_max+1], wtab64 and wtab32 [k][dmax+1], den64 and den32 [n].
+ * Synchronizes. */
+ssm_status ssm_terms_export(const ssm_terms* t, int32_t* H_host, double* wtab64_host,
+                            float* wtab32_host, double* den64_host, float* den32_host);
+
+/* Algorithm 1, lines 3-4: PivotMDS start layout on the handle's pivots, then
+ * a uniform rescale so that the summed layout length of the edges equals the
+ * summed edge lengths (m).  PivotMDS: with S_ti = dist[t][i]^2, mu_t its mean
+ * over nodes, nu_i its mean over pivots and gamma the mean of all entries,
+ * C_it = -1/2 (S_ti - mu_t - nu_i + gamma); x = C V for V the eigenvectors of
+ * the two largest eigenvalues of C^T C, each scaled so that its
+ * largest-magnitude entry is positive.  Needs k >= 3.  x is written in the
+ * precision p (the eigen step and the rescale run in FP64 either way).
+ * Synchronizes. */
+ssm_status ssm_pivotmds_init(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* x,
+                             hipStream_t stream);
+
+/* Eigen data of the last ssm_pivotmds_init on this handle: V [k][2],
+ * lambda [2], the iteration count of the eigen solver.  Synchronizes. */
+ssm_status ssm_pivotmds_eig(const ssm_terms* t, double* V_host, double* lambda_host,
+                            int32_t* iters_host);
+
+/* The k x k Gram matrix C^T C of the last ssm_pivotmds_init on this handle
+ * (row-major).  Synchronizes. */
+ssm_status ssm_pivotmds_gram(const ssm_terms* t, double* M_host);
+
+/* Algorithm 1, lines 5-8, with the update of Eq. 5 in Jacobi order (every
+ * node reads the previous iterate): num_i = sum over neighbours j of
+ * (x_j + (x_i - x_j)/r_ij) plus, over pivot terms, w'_it (x_p + d (x_i -
+ * x_p)/r_ip); x_i <- num_i / den_i.  A vote whose distance r is 0 keeps only
+ * x_q.  Runs `iters` sweeps in place on x (precision p); with tol > 0 stops
+ * after the first sweep whose relative change ||x_new - x_old|| / ||x_old||
+ * (Frobenius) is <= tol.  iters_done_host (may be NULL) receives the number
+ * of sweeps run.  With tol == 0 the call is asynchronous unless
+ * iters_done_host is given.  The FP64 form sums every node's terms in the
+ * order stated (neighbours in CSR order, then pivots by ascending rank) with
+ * correctly rounded square roots and divisions and no fused multiply-add. */
+ssm_status ssm_majorize(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* x, int32_t iters,
+                        double tol, int32_t* iters_done_host, hipStream_t stream);
+
+/* Stress of layout x, accumulated in FP64: SSM_STRESS_SPARSE is s'(x) of
+ * Eq. 3 (edges with w = 1, d = 1, plus every pivot term with w'_it);
+ * SSM_STRESS_FULL is s(x) of Eq. 1 over all pairs with d the hop distance
+ * and w = d^-2 (n <= 65536).  Writes out_host[0].  Synchronizes. */
+ssm_status ssm_stress(const ssm_csr* g, ssm_terms* t, ssm_prec p, const void* x,
+                      ssm_stress_kind kind, double* out_host, hipStream_t stream);
+
+/* Message for the last non-OK status returned on the calling thread. */
+const char* ssm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SSM_H */

@@ -1,0 +1,216 @@
+// C ABI entry points of libssm: argument checks, error reporting, dispatch.
+#include <stdio.h>
+
+#include <string>
+
+#include "ssm_internal.h"
+
+namespace ssm {
+
+static thread_local std::string g_last_error;
+
+ssm_status fail(ssm_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+ssm_status hip_fail(hipError_t e, const char* what) {
+    char buf[512];
+    snprintf(buf, sizeof buf, "%s failed: %s", what, hipGetErrorString(e));
+    if (e == hipErrorOutOfMemory) return fail(SSM_E_NOMEM, buf);
+    return fail(SSM_E_DEVICE, buf);
+}
+
+ssm_status dalloc(void** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        char buf[160];
+        snprintf(buf, sizeof buf, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+        return fail(e == hipErrorOutOfMemory ? SSM_E_NOMEM : SSM_E_DEVICE, buf);
+    }
+    return SSM_OK;
+}
+
+ssm_status check_csr(const ssm_csr* g) {
+    if (!g) return fail(SSM_E_INVAL, "graph is NULL");
+    if (g->n < 1) return fail(SSM_E_INVAL, "graph has no nodes");
+    if (g->nnz < 0) return fail(SSM_E_INVAL, "negative arc count");
+    if (!g->row_ptr || (g->nnz > 0 && !g->col_idx))
+        return fail(SSM_E_INVAL, "graph pointers are NULL");
+    if (g->n > (1 << 30)) return fail(SSM_E_RANGE, "n above 2^30");
+    return SSM_OK;
+}
+
+int num_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
+}  // namespace ssm
+
+using namespace ssm;
+
+extern "C" {
+
+const char* ssm_last_error(void) { return g_last_error.c_str(); }
+
+ssm_status ssm_select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pivots,
+                             int32_t* dist, hipStream_t stream) {
+    ssm_status st = check_csr(g);
+    if (st != SSM_OK) return st;
+    if (k < 1 || k > g->n) return fail(SSM_E_INVAL, "k must lie in [1, n]");
+    if (first < 0 || first >= g->n) return fail(SSM_E_INVAL, "first must lie in [0, n)");
+    if (!pivots) return fail(SSM_E_INVAL, "pivots is NULL");
+    if ((long long)k * g->n >= (1LL << 40)) return fail(SSM_E_RANGE, "k * n too large");
+    st = select_pivots(g, k, first, pivots, stream);
+    if (st != SSM_OK || !dist) return st;
+    int32_t dmax = 0;
+    return mssp(g, k, pivots, dist, &dmax, stream);
+}
+
+ssm_status ssm_bfs_pivots(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dist,
+                          int32_t* delta, int32_t* region, hipStream_t stream) {
+    ssm_status st = check_csr(g);
+    if (st != SSM_OK) return st;
+    if (k < 1 || k > g->n) return fail(SSM_E_INVAL, "k must lie in [1, n]");
+    if (!pivots || !dist || !delta || !region) return fail(SSM_E_INVAL, "NULL output or pivots");
+    if ((long long)k * g->n >= (1LL << 40)) return fail(SSM_E_RANGE, "k * n too large");
+    int32_t dmax = 0;
+    st = mssp(g, k, pivots, dist, &dmax, stream);
+    if (st != SSM_OK) return st;
+    return regions(g->n, k, dist, delta, region, stream);
+}
+
+ssm_status ssm_regions(int32_t n, int32_t k, const int32_t* dist, int32_t* delta, int32_t* region,
+                       hipStream_t stream) {
+    if (n < 1 || k < 1 || k > n) return fail(SSM_E_INVAL, "need 1 <= k <= n");
+    if (!dist || !delta || !region) return fail(SSM_E_INVAL, "NULL pointer");
+    return regions(n, k, dist, delta, region, stream);
+}
+
+ssm_status ssm_build_terms(const ssm_csr* g, int32_t k, const int32_t* pivots,
+                           const int32_t* dist, const int32_t* delta, const int32_t* region,
+                           ssm_terms** out, hipStream_t stream) {
+    ssm_status st = check_csr(g);
+    if (st != SSM_OK) return st;
+    if (!out) return fail(SSM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (k < 1 || k > g->n) return fail(SSM_E_INVAL, "k must lie in [1, n]");
+    if (!pivots || !dist || !delta || !region) return fail(SSM_E_INVAL, "NULL input");
+    return build_terms(g, k, pivots, dist, delta, region, out, stream);
+}
+
+void ssm_terms_free(ssm_terms* t) {
+    if (!t) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(t->device);
+    void* ptrs[] = {t->pivots, t->H,    t->wtab64, t->wtab32, t->wt2,   t->Hf, t->invd, t->den64, t->den32,
+                    t->dpk,    t->xtmp, t->red,    t->eig,    t->eig_iters, t->gram};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    (void)hipSetDevice(cur);
+    delete t;
+}
+
+ssm_status ssm_terms_dims(const ssm_terms* t, int32_t* k_host, int32_t* delta_max_host,
+                          int32_t* dmax_host) {
+    if (!t) return fail(SSM_E_INVAL, "terms is NULL");
+    if (k_host) *k_host = t->k;
+    if (delta_max_host) *delta_max_host = t->delta_max;
+    if (dmax_host) *dmax_host = t->dmax;
+    return SSM_OK;
+}
+
+ssm_status ssm_terms_export(const ssm_terms* t, int32_t* H_host, double* wtab64_host,
+                            float* wtab32_host, double* den64_host, float* den32_host) {
+    if (!t) return fail(SSM_E_INVAL, "terms is NULL");
+    SSM_HIP(hipDeviceSynchronize());
+    size_t kw = (size_t)t->k * t->W;
+    if (H_host)
+        SSM_HIP(hipMemcpy(H_host, t->H, sizeof(int32_t) * (size_t)t->k * (t->delta_max + 1),
+                          hipMemcpyDeviceToHost));
+    if (wtab64_host)
+        SSM_HIP(hipMemcpy(wtab64_host, t->wtab64, sizeof(double) * kw, hipMemcpyDeviceToHost));
+    if (wtab32_host)
+        SSM_HIP(hipMemcpy(wtab32_host, t->wtab32, sizeof(float) * kw, hipMemcpyDeviceToHost));
+    if (den64_host)
+        SSM_HIP(hipMemcpy(den64_host, t->den64, sizeof(double) * t->n, hipMemcpyDeviceToHost));
+    if (den32_host)
+        SSM_HIP(hipMemcpy(den32_host, t->den32, sizeof(float) * t->n, hipMemcpyDeviceToHost));
+    return SSM_OK;
+}
+
+ssm_status ssm_pivotmds_init(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* x,
+                             hipStream_t stream) {
+    ssm_status st = check_csr(g);
+    if (st != SSM_OK) return st;
+    if (!t || !x) return fail(SSM_E_INVAL, "NULL terms or layout");
+    if (t->n != g->n) return fail(SSM_E_INVAL, "terms were built for another graph");
+    if (p != SSM_FP64 && p != SSM_FP32) return fail(SSM_E_INVAL, "unknown precision");
+    if (t->k < 3) return fail(SSM_E_INVAL, "PivotMDS needs k >= 3");
+    return pivotmds(g, t, p, x, stream);
+}
+
+ssm_status ssm_pivotmds_eig(const ssm_terms* t, double* V_host, double* lambda_host,
+                            int32_t* iters_host) {
+    if (!t) return fail(SSM_E_INVAL, "terms is NULL");
+    SSM_HIP(hipDeviceSynchronize());
+    if (V_host)
+        SSM_HIP(hipMemcpy(V_host, t->eig, sizeof(double) * 2 * t->k, hipMemcpyDeviceToHost));
+    if (lambda_host)
+        SSM_HIP(hipMemcpy(lambda_host, t->eig + 2 * t->k, sizeof(double) * 2,
+                          hipMemcpyDeviceToHost));
+    if (iters_host)
+        SSM_HIP(hipMemcpy(iters_host, t->eig_iters, sizeof(int32_t), hipMemcpyDeviceToHost));
+    return SSM_OK;
+}
+
+ssm_status ssm_pivotmds_gram(const ssm_terms* t, double* M_host) {
+    if (!t || !M_host) return fail(SSM_E_INVAL, "NULL argument");
+    SSM_HIP(hipDeviceSynchronize());
+    SSM_HIP(hipMemcpy(M_host, t->gram, sizeof(double) * (size_t)t->k * t->k, hipMemcpyDeviceToHost));
+    return SSM_OK;
+}
+
+ssm_status ssm_majorize(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* x, int32_t iters,
+                        double tol, int32_t* iters_done_host, hipStream_t stream) {
+    ssm_status st = check_csr(g);
+    if (st != SSM_OK) return st;
+    if (!t || !x) return fail(SSM_E_INVAL, "NULL terms or layout");
+    if (t->n != g->n || t->nnz != g->nnz) return fail(SSM_E_INVAL, "terms were built for another graph");
+    if (p != SSM_FP64 && p != SSM_FP32) return fail(SSM_E_INVAL, "unknown precision");
+    if (iters < 0) return fail(SSM_E_INVAL, "negative iteration count");
+    if (!(tol >= 0.0)) return fail(SSM_E_INVAL, "tol must be >= 0");
+    return majorize(g, t, p, x, iters, tol, iters_done_host, stream);
+}
+
+ssm_status ssm_stress(const ssm_csr* g, ssm_terms* t, ssm_prec p, const void* x,
+                      ssm_stress_kind kind, double* out_host, hipStream_t stream) {
+    ssm_status st = check_csr(g);
+    if (st != SSM_OK) return st;
+    if (!x || !out_host) return fail(SSM_E_INVAL, "NULL layout or output");
+    if (p != SSM_FP64 && p != SSM_FP32) return fail(SSM_E_INVAL, "unknown precision");
+    if (kind == SSM_STRESS_SPARSE) {
+        if (!t) return fail(SSM_E_INVAL, "sparse stress needs terms");
+        if (t->n != g->n) return fail(SSM_E_INVAL, "terms were built for another graph");
+        return stress_sparse(g, t, p, x, out_host, stream);
+    }
+    if (kind == SSM_STRESS_FULL) {
+        if (g->n > 65536) return fail(SSM_E_RANGE, "full stress supports n <= 65536");
+        return stress_full(g, p, x, out_host, stream);
+    }
+    return fail(SSM_E_INVAL, "unknown stress kind");
+}
+
+}  // extern "C"

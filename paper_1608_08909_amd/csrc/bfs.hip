@@ -1,0 +1,598 @@
+// Breadth-first searches from the pivots, max/min pivot sampling and the
+// nearest-pivot regions R(p) (paper Section 3 and Section 4.1).
+#include <hip/hip_cooperative_groups.h>
+#include <limits.h>
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <vector>
+
+#include "ssm_internal.h"
+#include "wave.h"
+
+namespace cg = cooperative_groups;
+
+namespace ssm {
+
+constexpr int kBfsBlock = 1024;
+constexpr int kSelBlock = 512;
+constexpr int kInf = INT_MAX;
+
+// Launch-shape override from the environment (tuning only; 0 = automatic).
+static int env_int(const char* name) {
+    const char* v = getenv(name);
+    return v ? atoi(v) : 0;
+}
+
+// Lanes per frontier node: the power of two nearest the mean degree, in [2, 64].
+static int virtual_warp(const ssm_csr* g) {
+    int forced = env_int("SSM_BFS_LANES");
+    if (forced == 2 || forced == 4 || forced == 8 || forced == 16 || forced == 32 || forced == 64) return forced;
+    double avg = g->n > 0 ? (double)g->nnz / g->n : 1.0;
+    int vw = 2;
+    while (vw < 64 && vw < avg) vw <<= 1;
+    return vw;
+}
+
+// ------------------------------------------------------------ validation
+
+// Every arc (u, v): v in range, v != u, and the reverse arc (v, u) present
+// exactly once in row v (this also rejects duplicate arcs).  Row v is scanned
+// linearly, so rows need not be sorted.
+__global__ void k_validate(int n, int nnz, const int* __restrict__ rp, const int* __restrict__ ci,
+                           int* bad) {
+    for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+        int a = rp[u], b = rp[u + 1];
+        if (a < 0 || b < a || b > nnz || (u == 0 && a != 0) || (u == n - 1 && b != nnz)) {
+            atomicOr(bad, 1);
+            continue;
+        }
+        for (int e = a; e < b; ++e) {
+            int v = ci[e];
+            if (v < 0 || v >= n || v == u) {
+                atomicOr(bad, 2);
+                continue;
+            }
+            int c0 = rp[v], c1 = rp[v + 1];
+            if (c0 < 0 || c1 < c0 || c1 > nnz) {
+                atomicOr(bad, 1);
+                continue;
+            }
+            int hits = 0;
+            for (int f = c0; f < c1; ++f) hits += (ci[f] == u);
+            int same = 0;
+            for (int f = a; f < b; ++f) same += (ci[f] == v);
+            if (hits != 1 || same != 1) atomicOr(bad, 4);
+        }
+    }
+}
+
+// ------------------------------------------------- one BFS per workgroup
+
+// Block b runs a level-synchronous BFS from pivots[b] and writes
+// dist[b][*] (pre-set to -1).  Frontier nodes are spread over groups of VW
+// lanes; a node is claimed by compare-and-swap on its distance and appended
+// to the next frontier with one atomic per wave.  reached[b] = nodes found;
+// *ecc_max = largest eccentricity seen.
+template <int VW>
+__global__ __launch_bounds__(kBfsBlock) void k_bfs_wg(int n, const int* __restrict__ rp,
+                                                      const int* __restrict__ ci,
+                                                      const int* __restrict__ pivots, int* dist,
+                                                      int* queues, int* reached, int* ecc_max) {
+    const int b = blockIdx.x;
+    int* D = dist + (size_t)b * n;
+    int* qa = queues + (size_t)b * 2 * n;
+    int* qb = qa + n;
+    __shared__ int s_tail, s_len;
+    const int src = pivots[b];
+    if (threadIdx.x == 0) {
+        D[src] = 0;
+        qa[0] = src;
+        s_len = 1;
+        s_tail = 0;
+    }
+    __syncthreads();
+    const int sub = threadIdx.x % VW, grp = threadIdx.x / VW, ngrp = blockDim.x / VW;
+    int level = 0, total = 1;
+    for (;;) {
+        const int len = min(s_len, n);
+        if (len == 0) break;
+        for (int base = 0; base < len; base += ngrp) {
+            int qi = base + grp;
+            int e0 = 0, e1 = 0;
+            if (qi < len) {
+                int u = qa[qi];
+                if ((unsigned)u < (unsigned)n) {
+                    e0 = rp[u];
+                    e1 = rp[u + 1];
+                }
+            }
+            for (int e = e0 + sub; e < e1; e += VW) {
+                int v = ci[e];
+                bool claim = false;
+                if (D[v] < 0) claim = atomicCAS(&D[v], -1, level + 1) == -1;
+                int slot = wave_append(claim, &s_tail);
+                if (claim) qb[slot] = v;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            s_len = s_tail;
+            s_tail = 0;
+        }
+        int* tmp = qa;
+        qa = qb;
+        qb = tmp;
+        ++level;
+        __syncthreads();
+        total += s_len;
+    }
+    if (threadIdx.x == 0) {
+        reached[b] = total;
+        atomicMax(ecc_max, level - 1);
+    }
+}
+
+template <int VW>
+static void launch_bfs_wg(int blocks, hipStream_t s, int n, const int* rp, const int* ci,
+                          const int* pivots, int* dist, int* queues, int* reached, int* ecc) {
+    hipLaunchKernelGGL(k_bfs_wg<VW>, dim3(blocks), dim3(kBfsBlock), 0, s, n, rp, ci, pivots, dist,
+                       queues, reached, ecc);
+}
+
+ssm_status mssp(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dist,
+                int32_t* dmax_out_host, hipStream_t s) {
+    const int n = g->n;
+    // Sources run in batches so that the frontier queues stay bounded.
+    const long long qcap = 1LL << 29;  // ints of queue memory (2 GiB)
+    int batch = (int)std::max<long long>(1, std::min<long long>(k, qcap / (2LL * n)));
+    int* queues = nullptr;
+    int* aux = nullptr;  // reached[k], ecc
+    ssm_status st = dalloc((void**)&queues, sizeof(int) * 2 * (size_t)n * batch);
+    if (st != SSM_OK) return st;
+    st = dalloc((void**)&aux, sizeof(int) * ((size_t)k + 1));
+    if (st != SSM_OK) {
+        (void)hipFree(queues);
+        return st;
+    }
+    hipError_t e = hipMemsetAsync(dist, 0xff, sizeof(int) * (size_t)k * n, s);
+    if (e == hipSuccess) e = hipMemsetAsync(aux, 0, sizeof(int) * ((size_t)k + 1), s);
+    if (e == hipSuccess) e = hipMemsetAsync(queues, 0, sizeof(int) * 2 * (size_t)n * batch, s);
+    int vw = virtual_warp(g);
+    for (int b0 = 0; b0 < k && e == hipSuccess; b0 += batch) {
+        int nb = std::min(batch, k - b0);
+        int* D = dist + (size_t)b0 * n;
+        int* reached = aux + b0;
+        int* ecc = aux + k;
+        switch (vw) {
+            case 2: launch_bfs_wg<2>(nb, s, n, g->row_ptr, g->col_idx, pivots + b0, D, queues, reached, ecc); break;
+            case 4: launch_bfs_wg<4>(nb, s, n, g->row_ptr, g->col_idx, pivots + b0, D, queues, reached, ecc); break;
+            case 8: launch_bfs_wg<8>(nb, s, n, g->row_ptr, g->col_idx, pivots + b0, D, queues, reached, ecc); break;
+            case 16: launch_bfs_wg<16>(nb, s, n, g->row_ptr, g->col_idx, pivots + b0, D, queues, reached, ecc); break;
+            case 32: launch_bfs_wg<32>(nb, s, n, g->row_ptr, g->col_idx, pivots + b0, D, queues, reached, ecc); break;
+            default: launch_bfs_wg<64>(nb, s, n, g->row_ptr, g->col_idx, pivots + b0, D, queues, reached, ecc); break;
+        }
+        e = hipGetLastError();
+    }
+    std::vector<int> host((size_t)k + 1);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(host.data(), aux, sizeof(int) * ((size_t)k + 1), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(queues);
+    (void)hipFree(aux);
+    if (e != hipSuccess) return hip_fail(e, "multi-source BFS");
+    for (int t = 0; t < k; ++t)
+        if (host[t] != n) return fail(SSM_E_DISCONNECTED, "graph is not connected (a BFS missed nodes)");
+    *dmax_out_host = host[k];
+    return SSM_OK;
+}
+
+// ------------------------------------------------- max/min pivot sampling
+
+__device__ __forceinline__ void grid_barrier(cg::grid_group& grid) {
+    if (gridDim.x == 1)
+        __syncthreads();
+    else
+        grid.sync();
+}
+
+__device__ __forceinline__ int load_agent(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One launch per pivot t.  BFS from pivots[t] that only continues through
+// nodes whose distance to the new pivot is smaller than m (their distance to
+// the nearest earlier pivot), updating m on the way.  This is exact for
+// m <- min(m, d_t): m is 1-Lipschitz along edges, so a node with d_t >= m
+// cannot lead to a node where d_t < m.  Then pivots[t+1] = argmax m, lowest
+// id on ties.  ctl[0..2] rotate as frontier counters; keys holds one partial
+// argmax per block.  status[0] is set to 1 if the first BFS misses a node.
+template <int VW>
+__global__ __launch_bounds__(kSelBlock) void k_select(int n, const int* __restrict__ rp,
+                                                      const int* __restrict__ ci, int t, int k,
+                                                      int first, int* pivots, int* m, int* vis,
+                                                      int* qa, int* qb, int* ctl,
+                                                      unsigned long long* keys, int* status) {
+    cg::grid_group grid = cg::this_grid();
+    const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nthreads = gridDim.x * blockDim.x;
+    const int src = (t == 0) ? first : pivots[t];
+    if (gtid == 0) {
+        if (t == 0) pivots[0] = first;
+        vis[src] = t;
+        m[src] = 0;
+        qa[0] = src;
+        ctl[0] = 1;
+        ctl[1] = 0;
+        ctl[2] = 0;
+    }
+    grid_barrier(grid);
+    const int sub = gtid % VW, grp = gtid / VW, ngrp = nthreads / VW;
+    int level = 0;
+    int* cur = qa;
+    int* nxt = qb;
+    for (;;) {
+        const int len = min(load_agent(&ctl[level % 3]), n);
+        if (len == 0) break;
+        int* tail = &ctl[(level + 1) % 3];
+        if (gtid == 0) ctl[(level + 2) % 3] = 0;
+        const int dv = level + 1;
+        for (int base = 0; base < len; base += ngrp) {
+            int qi = base + grp;
+            int e0 = 0, e1 = 0;
+            if (qi < len) {
+                int u = cur[qi];
+                if ((unsigned)u < (unsigned)n) {
+                    e0 = rp[u];
+                    e1 = rp[u + 1];
+                }
+            }
+            for (int e = e0 + sub; e < e1; e += VW) {
+                int v = ci[e];
+                bool push = false;
+                if (vis[v] != t && atomicExch(&vis[v], t) != t) {
+                    if (dv < m[v]) {
+                        m[v] = dv;
+                        push = true;
+                    }
+                }
+                int slot = wave_append(push, tail);
+                if (push) nxt[slot] = v;
+            }
+        }
+        grid_barrier(grid);
+        int* tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+        ++level;
+    }
+    if (t + 1 >= k && t != 0) return;
+    // argmax of m, lowest id on ties: maximize (m << 32) | ~id
+    unsigned long long best = 0;
+    for (int i = gtid; i < n; i += nthreads) {
+        unsigned long long key =
+            ((unsigned long long)(unsigned)m[i] << 32) | (unsigned long long)(0xffffffffu - (unsigned)i);
+        best = key > best ? key : best;
+    }
+    __shared__ unsigned long long s_red[kSelBlock / kWave];
+    best = block_max(best, s_red);
+    if (threadIdx.x == 0) keys[blockIdx.x] = best;
+    grid_barrier(grid);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        unsigned long long b = 0;
+        for (int q = 0; q < (int)gridDim.x; ++q) {
+            unsigned long long kq = __hip_atomic_load(&keys[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            b = kq > b ? kq : b;
+        }
+        int mbest = (int)(b >> 32);
+        if (t == 0 && mbest == kInf) status[0] = 1;
+        if (t + 1 < k) pivots[t + 1] = (int)(0xffffffffu - (unsigned)(b & 0xffffffffu));
+    }
+}
+
+__global__ void k_fill_int(int* p, int v, long long count) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+template <int VW>
+static hipError_t launch_select(int blocks, hipStream_t s, int n, const int* rp, const int* ci,
+                                int t, int k, int first, int* pivots, int* m, int* vis, int* qa,
+                                int* qb, int* ctl, unsigned long long* keys, int* status) {
+    void* args[] = {&n, &rp, &ci, &t, &k, &first, &pivots, &m, &vis, &qa, &qb, &ctl, &keys, &status};
+    return hipLaunchCooperativeKernel((const void*)k_select<VW>, dim3(blocks), dim3(kSelBlock), args,
+                                      0, s);
+}
+
+template <int VW>
+static int select_max_blocks() {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_select<VW>, kSelBlock, 0) !=
+            hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    return per_cu * num_cus();
+}
+
+ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pivots, hipStream_t s) {
+    const int n = g->n;
+    // workspace: m[n], vis[n], qa[n], qb[n], ctl[4], status[1], keys[max blocks]
+    int vw = virtual_warp(g);
+    int maxb = 1;
+    switch (vw) {
+        case 2: maxb = select_max_blocks<2>(); break;
+        case 4: maxb = select_max_blocks<4>(); break;
+        case 8: maxb = select_max_blocks<8>(); break;
+        case 16: maxb = select_max_blocks<16>(); break;
+        case 32: maxb = select_max_blocks<32>(); break;
+        default: maxb = select_max_blocks<64>(); break;
+    }
+    // Grid size: small graphs run in one workgroup (no grid barrier), larger
+    // ones on up to one block per CU.
+    int blocks = std::max(1, std::min(std::min(maxb, num_cus()), div_up(n, 8192)));
+    if (env_int("SSM_SELECT_BLOCKS") > 0) blocks = std::min(maxb, env_int("SSM_SELECT_BLOCKS"));
+    size_t ints = 4 * (size_t)n + 8;
+    int* ws = nullptr;
+    unsigned long long* keys = nullptr;
+    ssm_status st = dalloc((void**)&ws, sizeof(int) * ints);
+    if (st != SSM_OK) return st;
+    st = dalloc((void**)&keys, sizeof(unsigned long long) * blocks);
+    if (st != SSM_OK) {
+        (void)hipFree(ws);
+        return st;
+    }
+    int* m = ws;
+    int* vis = ws + n;
+    int* qa = ws + 2 * (size_t)n;
+    int* qb = ws + 3 * (size_t)n;
+    int* ctl = ws + 4 * (size_t)n;
+    int* status = ctl + 4;
+    hipError_t e = hipSuccess;
+    hipLaunchKernelGGL(k_fill_int, dim3(std::min(div_up(n, 256), 4096)), dim3(256), 0, s, m, kInf, (long long)n);
+    hipLaunchKernelGGL(k_fill_int, dim3(std::min(div_up(n, 256), 4096)), dim3(256), 0, s, vis, -1, (long long)n);
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, ctl, 0, (long long)8);
+    hipLaunchKernelGGL(k_fill_int, dim3(std::min(div_up(2 * (long long)n, 256), 4096)), dim3(256), 0, s, qa, 0,
+                       2 * (long long)n);
+    e = hipGetLastError();
+    for (int t = 0; t < k && e == hipSuccess; ++t) {
+        switch (vw) {
+            case 2: e = launch_select<2>(blocks, s, n, g->row_ptr, g->col_idx, t, k, first, pivots, m, vis, qa, qb, ctl, keys, status); break;
+            case 4: e = launch_select<4>(blocks, s, n, g->row_ptr, g->col_idx, t, k, first, pivots, m, vis, qa, qb, ctl, keys, status); break;
+            case 8: e = launch_select<8>(blocks, s, n, g->row_ptr, g->col_idx, t, k, first, pivots, m, vis, qa, qb, ctl, keys, status); break;
+            case 16: e = launch_select<16>(blocks, s, n, g->row_ptr, g->col_idx, t, k, first, pivots, m, vis, qa, qb, ctl, keys, status); break;
+            case 32: e = launch_select<32>(blocks, s, n, g->row_ptr, g->col_idx, t, k, first, pivots, m, vis, qa, qb, ctl, keys, status); break;
+            default: e = launch_select<64>(blocks, s, n, g->row_ptr, g->col_idx, t, k, first, pivots, m, vis, qa, qb, ctl, keys, status); break;
+        }
+    }
+    int hstatus = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hstatus, status, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(ws);
+    (void)hipFree(keys);
+    if (e != hipSuccess) return hip_fail(e, "pivot selection");
+    if (hstatus) return fail(SSM_E_DISCONNECTED, "graph is not connected (the first BFS missed nodes)");
+    return SSM_OK;
+}
+
+// ---------------------------------------------------------------- regions
+
+constexpr int kMaxCand = 4;
+
+// Per node: delta = min_t dist[t][i]; the candidates (ranks at that
+// distance, ascending, the first kMaxCand kept; cand.w = count).  A node with
+// one candidate joins it at once.  aux[0] = max delta, aux[1] = tied nodes.
+__global__ __launch_bounds__(256) void k_reg_scan(int n, int k, const int* __restrict__ dist, int* __restrict__ delta,
+                           int* __restrict__ region, int4* __restrict__ cand, int* aux) {
+    int tied = 0, dm = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        int best = kInf, cnt = 0;
+        int c[kMaxCand] = {-1, -1, -1, -1};
+        for (int t = 0; t < k; ++t) {
+            int d = dist[(size_t)t * n + i];
+            if (d < best) {
+                best = d;
+                cnt = 1;
+                c[0] = t;
+            } else if (d == best) {
+                if (cnt < kMaxCand) c[cnt] = t;
+                ++cnt;
+            }
+        }
+        delta[i] = best;
+        region[i] = cnt == 1 ? c[0] : -1;
+        cand[i] = make_int4(c[0], c[1], c[2], cnt);
+        tied += cnt > 1;
+        dm = best > dm ? best : dm;
+    }
+    __shared__ int red[256 / kWave];
+    tied = block_sum(tied, red);
+    dm = block_max(dm, red);
+    if (threadIdx.x == 0) {  // one atomic per block
+        if (tied) atomicAdd(&aux[1], tied);
+        atomicMax(&aux[0], dm);
+    }
+}
+
+// Histogram of single-candidate nodes per (pivot, level) and count of tied
+// nodes per level.
+__global__ void k_reg_hist(int n, int L, const int* __restrict__ delta, const int4* __restrict__ cand,
+                           int* __restrict__ U, int* __restrict__ tcount) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        int4 c = cand[i];
+        if (c.w == 1)
+            atomicAdd(&U[(size_t)c.x * L + delta[i]], 1);
+        else
+            atomicAdd(&tcount[delta[i]], 1);
+    }
+}
+
+// Exclusive prefix over levels (one thread; L is small).
+__global__ void k_reg_prefix(int L, const int* __restrict__ tcount, int* __restrict__ tstart,
+                             int* __restrict__ cursor) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        int acc = 0;
+        for (int l = 0; l < L; ++l) {
+            tstart[l] = acc;
+            cursor[l] = acc;
+            acc += tcount[l];
+        }
+        tstart[L] = acc;
+    }
+}
+
+__global__ void k_reg_scatter(int n, const int* __restrict__ delta, const int4* __restrict__ cand,
+                              int* __restrict__ cursor, int* __restrict__ list) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        if (cand[i].w > 1) list[atomicAdd(&cursor[delta[i]], 1)] = i;
+    }
+}
+
+// Level-synchronous tie resolution in one workgroup.  cum[t] = region size
+// from all levels below l; at level l the snapshot is cum[t] + U[t][l] (the
+// single-candidate joins of level l); every tied node of level l takes the
+// candidate with the smallest (snapshot, rank); then cum absorbs level l.
+// The result does not depend on the order of nodes inside a level.
+__global__ __launch_bounds__(1024) void k_reg_resolve(int n, int k, int L, const int* __restrict__ dist,
+                                                      const int* __restrict__ U,
+                                                      const int* __restrict__ tstart,
+                                                      const int* __restrict__ list,
+                                                      const int4* __restrict__ cand,
+                                                      int* __restrict__ region, int* cum, int* Tl) {
+    for (int t = threadIdx.x; t < k; t += blockDim.x) {
+        cum[t] = 0;
+        Tl[t] = 0;
+    }
+    __syncthreads();
+    for (int l = 0; l < L; ++l) {
+        const int a = tstart[l], b = tstart[l + 1];
+        for (int q = a + threadIdx.x; q < b; q += blockDim.x) {
+            int i = list[q];
+            int4 c = cand[i];
+            int pick = -1;
+            long long pkey = 0;
+            if (c.w <= kMaxCand) {
+                int cs[kMaxCand] = {c.x, c.y, c.z, -1};
+                if (c.w == kMaxCand) {  // fourth candidate was not stored: find it
+                    for (int t = c.z + 1; t < k; ++t)
+                        if (dist[(size_t)t * n + i] == l) {
+                            cs[3] = t;
+                            break;
+                        }
+                }
+                for (int j = 0; j < c.w; ++j) {
+                    int t = cs[j];
+                    long long key = ((long long)(cum[t] + U[(size_t)t * L + l]) << 32) | t;
+                    if (pick < 0 || key < pkey) {
+                        pick = t;
+                        pkey = key;
+                    }
+                }
+            } else {
+                for (int t = 0; t < k; ++t) {
+                    if (dist[(size_t)t * n + i] != l) continue;
+                    long long key = ((long long)(cum[t] + U[(size_t)t * L + l]) << 32) | t;
+                    if (pick < 0 || key < pkey) {
+                        pick = t;
+                        pkey = key;
+                    }
+                }
+            }
+            region[i] = pick;
+            atomicAdd(&Tl[pick], 1);
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < k; t += blockDim.x) {
+            cum[t] += U[(size_t)t * L + l] + Tl[t];
+            Tl[t] = 0;
+        }
+        __syncthreads();
+    }
+}
+
+ssm_status regions(int32_t n, int32_t k, const int32_t* dist, int32_t* delta, int32_t* region,
+                   hipStream_t s) {
+    int4* cand = nullptr;
+    int* aux = nullptr;
+    ssm_status st = dalloc((void**)&cand, sizeof(int4) * (size_t)n);
+    if (st != SSM_OK) return st;
+    st = dalloc((void**)&aux, sizeof(int) * 2);
+    if (st != SSM_OK) {
+        (void)hipFree(cand);
+        return st;
+    }
+    int grid = std::min(div_up(n, 256), 8192);
+    int haux[2] = {0, 0};
+    hipError_t e = hipMemsetAsync(aux, 0, sizeof(int) * 2, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_reg_scan, dim3(grid), dim3(256), 0, s, n, k, dist, delta, region, cand, aux);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(haux, aux, sizeof haux, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipFree(cand);
+        (void)hipFree(aux);
+        return hip_fail(e, "region scan");
+    }
+    if (haux[1] > 0) {
+        const int L = haux[0] + 1;
+        // U[k][L], tcount[L], tstart[L+1], cursor[L], list[ntied], cum[k], Tl[k]
+        size_t ints = (size_t)k * L + 3 * (size_t)L + 1 + (size_t)haux[1] + 2 * (size_t)k;
+        int* ws = nullptr;
+        st = dalloc((void**)&ws, sizeof(int) * ints);
+        if (st != SSM_OK) {
+            (void)hipFree(cand);
+            (void)hipFree(aux);
+            return st;
+        }
+        int* U = ws;
+        int* tcount = U + (size_t)k * L;
+        int* tstart = tcount + L;
+        int* cursor = tstart + L + 1;
+        int* list = cursor + L;
+        int* cum = list + haux[1];
+        int* Tl = cum + k;
+        e = hipMemsetAsync(ws, 0, sizeof(int) * ((size_t)k * L + L), s);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_reg_hist, dim3(grid), dim3(256), 0, s, n, L, delta, cand, U, tcount);
+            hipLaunchKernelGGL(k_reg_prefix, dim3(1), dim3(64), 0, s, L, tcount, tstart, cursor);
+            hipLaunchKernelGGL(k_reg_scatter, dim3(grid), dim3(256), 0, s, n, delta, cand, cursor, list);
+            hipLaunchKernelGGL(k_reg_resolve, dim3(1), dim3(1024), 0, s, n, k, L, dist, U, tstart, list,
+                               cand, region, cum, Tl);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        (void)hipFree(ws);
+    }
+    (void)hipFree(cand);
+    (void)hipFree(aux);
+    if (e != hipSuccess) return hip_fail(e, "region assignment");
+    return SSM_OK;
+}
+
+}  // namespace ssm
+
+extern "C" ssm_status ssm_validate_csr(const ssm_csr* g, hipStream_t stream) {
+    using namespace ssm;
+    ssm_status st = check_csr(g);
+    if (st != SSM_OK) return st;
+    int* bad = nullptr;
+    st = dalloc((void**)&bad, sizeof(int));
+    if (st != SSM_OK) return st;
+    int hbad = 0;
+    hipError_t e = hipMemsetAsync(bad, 0, sizeof(int), stream);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_validate, dim3(std::min(div_up(g->n, 256), 8192)), dim3(256), 0, stream,
+                           g->n, g->nnz, g->row_ptr, g->col_idx, bad);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    (void)hipFree(bad);
+    if (e != hipSuccess) return hip_fail(e, "CSR validation");
+    if (hbad & 1) return fail(SSM_E_INVAL, "row_ptr is not monotone from 0 to nnz");
+    if (hbad & 2) return fail(SSM_E_INVAL, "column index out of range or self-loop");
+    if (hbad & 4) return fail(SSM_E_INVAL, "adjacency is not symmetric or has duplicate arcs");
+    return SSM_OK;
+}

@@ -1,0 +1,545 @@
+// PivotMDS start layout and the rescale of Algorithm 1 (lines 3-4).
+// The paper cites PivotMDS without defining it; the steps here follow the
+// method it cites: double-centred squared pivot distances C (n x k), the
+// Gram matrix C^T C (FP64 matrix cores), its two dominant eigenvectors by
+// orthogonal iteration in FP64, and the projection x = C V.
+#include <math.h>
+
+#include <vector>
+
+#include "ssm_internal.h"
+#include "wave.h"
+
+namespace ssm {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// colsum[t] = sum_i dist[t][i]^2 (exact in int64), from the packed copy:
+// block b sums word row b (ranks b*VEC .. b*VEC+VEC-1).
+template <typename DT, int VEC>
+__global__ __launch_bounds__(256) void k_pmds_colsum(int n, int k, const uint4* __restrict__ dpk,
+                                                     long long* __restrict__ colsum) {
+    const int b = blockIdx.x;
+    long long s[VEC];
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) s[j] = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        union {
+            uint4 v;
+            DT e[VEC];
+        } u;
+        u.v = dpk[(size_t)b * n + i];
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) s[j] += (long long)u.e[j] * u.e[j];
+    }
+    __shared__ long long red[256 / kWave];
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) {
+        long long tot = block_sum(s[j], red);
+        if (threadIdx.x == 0 && b * VEC + j < k) colsum[b * VEC + j] = tot;
+    }
+}
+
+// mu[t] = colsum[t] / n; stats[0] = gamma = sum_t colsum[t] / (n k).  Integer
+// sums are exact, so these equal a serial double evaluation bit for bit.
+__global__ void k_pmds_mu(int n, int k, const long long* __restrict__ colsum, double* __restrict__ mu,
+                          double* __restrict__ stats) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        long long total = 0;
+        for (int t = 0; t < k; ++t) {
+            mu[t] = (double)colsum[t] / (double)n;
+            total += colsum[t];
+        }
+        stats[0] = (double)total / ((double)n * (double)k);
+    }
+}
+
+// nu[i] = sum_t dist[t][i]^2 / k (padding ranks hold 0 and add nothing).
+template <typename DT, int VEC>
+__global__ void k_pmds_nu(int n, int k, int nwords, const uint4* __restrict__ dpk, double* __restrict__ nu) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        long long s = 0;
+        for (int b = 0; b < nwords; ++b) {
+            union {
+                uint4 v;
+                DT e[VEC];
+            } u;
+            u.v = dpk[(size_t)b * n + i];
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) s += (long long)u.e[j] * u.e[j];
+        }
+        nu[i] = (double)s / (double)k;
+    }
+}
+
+__device__ __forceinline__ double centred(int d, double mu_t, double nu_i, double gamma) {
+#pragma clang fp contract(off)
+    double dd = (double)d;
+    return -0.5 * (dd * dd - mu_t - nu_i + gamma);
+}
+
+constexpr int kGramSub = 8;   // nodes staged per LDS round (two K-steps of 4)
+constexpr int kGramTPW = 8;   // output tiles per wave
+constexpr int kGramWaves = 4;
+
+// Split-K Gram product M = C^T C on v_mfma_f64_16x16x4_f64.  Block (c, g):
+// node chunk c, tile group g (kGramWaves * kGramTPW tiles of the upper
+// triangle).  C is formed on the fly from the packed distances and staged in
+// LDS (kGramSub nodes x kp columns); each wave accumulates its tiles and
+// writes the chunk's partial tiles.  Operand layout per lane l: A[i][q] and
+// B[q][j] with i = j = l % 16, q = l / 16; result lane l, element v holds
+// row 4 v + l / 16, column l % 16.
+template <typename DT, int VEC>
+__global__ __launch_bounds__(256) void k_pmds_gram(int n, int k, int kp, int kpad, int chunk,
+                                                   const uint4* __restrict__ dpk,
+                                                   const double* __restrict__ mu,
+                                                   const double* __restrict__ nu,
+                                                   const double* __restrict__ stats,
+                                                   const int2* __restrict__ tiles, int ntiles,
+                                                   double* __restrict__ part) {
+    extern __shared__ double smem[];
+    double* Cs = smem;                    // [kGramSub][kp]
+    double* smu = smem + kGramSub * kp;   // [kp]
+    const int c = blockIdx.x, grp = blockIdx.y;
+    const int lane = lane_id(), w = threadIdx.x / kWave;
+    const double gamma = stats[0];
+    for (int t = threadIdx.x; t < kp; t += blockDim.x) smu[t] = t < k ? mu[t] : 0.0;
+    int my_tiles[kGramTPW];
+    int nmine = 0;
+#pragma unroll
+    for (int j = 0; j < kGramTPW; ++j) {
+        int id = (grp * kGramWaves + w) * kGramTPW + j;
+        my_tiles[j] = id < ntiles ? id : -1;
+        nmine += id < ntiles;
+    }
+    dbl4 acc[kGramTPW];
+#pragma unroll
+    for (int j = 0; j < kGramTPW; ++j) acc[j] = (dbl4){0.0, 0.0, 0.0, 0.0};
+    const int i_begin = c * chunk, i_end = min(n, i_begin + chunk);
+    const int nwords = kpad / VEC;
+    __syncthreads();
+    for (int i0 = i_begin; i0 < i_end; i0 += kGramSub) {
+        // stage C for nodes i0 .. i0 + kGramSub - 1 (zero past n and past k)
+        for (int q = threadIdx.x; q < kGramSub * nwords; q += blockDim.x) {
+            int r = q % kGramSub, b = q / kGramSub;
+            int i = i0 + r;
+            union {
+                uint4 v;
+                DT e[VEC];
+            } u;
+            u.v = i < i_end ? dpk[(size_t)b * n + i] : make_uint4(0, 0, 0, 0);
+            double nui = i < i_end ? nu[i] : 0.0;
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                int t = b * VEC + j;
+                double val = (i < i_end && t < k) ? centred((int)u.e[j], smu[t], nui, gamma) : 0.0;
+                Cs[r * kp + t] = val;
+            }
+        }
+        for (int q = threadIdx.x; q < kGramSub * (kp - kpad); q += blockDim.x) {
+            int r = q / (kp - kpad), t = kpad + q % (kp - kpad);
+            Cs[r * kp + t] = 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < kGramSub / 4; ++ks) {
+            const double* row = Cs + (ks * 4 + lane / 16) * kp + (lane % 16);
+#pragma unroll
+            for (int j = 0; j < kGramTPW; ++j) {
+                if (j < nmine) {
+                    int2 ab = tiles[my_tiles[j]];
+                    double a = row[16 * ab.x];
+                    double bb = row[16 * ab.y];
+                    acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc[j], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < kGramTPW; ++j) {
+        if (j < nmine) {
+            double* out = part + ((size_t)c * ntiles + my_tiles[j]) * 256;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) out[(4 * v + lane / 16) * 16 + (lane % 16)] = acc[j][v];
+        }
+    }
+}
+
+// M (k x k, row-major) = sum over chunks in ascending order of the partial
+// tiles; the lower triangle mirrors the upper one.
+__global__ void k_pmds_gram_reduce(int k, int nchunks, int ntiles, const int2* __restrict__ tiles,
+                                   const double* __restrict__ part, double* __restrict__ M) {
+    long long total = (long long)ntiles * 256;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total;
+         q += (long long)gridDim.x * blockDim.x) {
+        int tile = (int)(q / 256), e = (int)(q % 256);
+        double s = 0.0;
+        for (int c = 0; c < nchunks; ++c) s += part[((size_t)c * ntiles + tile) * 256 + e];
+        int2 ab = tiles[tile];
+        int r = 16 * ab.x + e / 16, col = 16 * ab.y + e % 16;
+        if (r < k && col < k) {
+            M[(size_t)r * k + col] = s;
+            M[(size_t)col * k + r] = s;
+        }
+    }
+}
+
+__device__ __forceinline__ double splitmix_uniform(unsigned long long& state) {
+    unsigned long long z = (state += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;  // [-1, 1)
+}
+
+constexpr int kEigThreads = 1024;
+constexpr int kEigRows = 16;  // rows of M per wave kept in registers (k <= 256)
+constexpr int kEigCols = 4;   // columns per lane (k <= 256)
+
+// Orthogonal (subspace) iteration for the two dominant eigenvectors of the
+// symmetric k x k matrix M, one workgroup.  Start: SplitMix64 values in
+// [-1, 1) (seed 0x53534D00 + column).  Each step: Z = M V, Gram-Schmidt;
+// stop once every column of Z lies in span(V) to within `tol` per entry, or
+// after max_iter steps.  Then Rayleigh-Ritz on the 2 x 2 V^T M V (larger
+// eigenvalue first) and the sign rule: each column's largest-magnitude entry
+// is positive (entries within a relative 1e-9 of the largest count as tied;
+// the lowest index among them decides).  out: V (k x 2), lambda[2]; iters[0].
+template <bool REG>
+__global__ __launch_bounds__(kEigThreads) void k_pmds_eig(int k, const double* __restrict__ M, double tol,
+                                                         int max_iter, double* __restrict__ out,
+                                                         int* __restrict__ iters) {
+    extern __shared__ double sh[];
+    double* v0 = sh;
+    double* v1 = sh + k;
+    double* z0 = sh + 2 * k;
+    double* z1 = sh + 3 * k;
+    __shared__ double red[kEigThreads / kWave];
+    const int lane = lane_id(), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    double mreg[REG ? kEigRows : 1][REG ? kEigCols : 1];
+    if (REG) {
+#pragma unroll
+        for (int q = 0; q < kEigRows; ++q)
+#pragma unroll
+            for (int c = 0; c < kEigCols; ++c) {
+                int r = w + nw * q, j = lane + kWave * c;
+                mreg[REG ? q : 0][REG ? c : 0] = (r < k && j < k) ? M[(size_t)r * k + j] : 0.0;
+            }
+    }
+    if (threadIdx.x == 0) {
+        unsigned long long s0 = 0x53534D00ull, s1 = 0x53534D01ull;
+        for (int t = 0; t < k; ++t) {
+            v0[t] = splitmix_uniform(s0);
+            v1[t] = splitmix_uniform(s1);
+        }
+    }
+    __syncthreads();
+    auto matvec = [&]() {
+        if (REG) {
+#pragma unroll
+            for (int q = 0; q < kEigRows; ++q) {
+                const int r = w + nw * q;
+                if (r < k) {  // uniform across the wave
+                    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+                    for (int c = 0; c < kEigCols; ++c) {
+                        int j = lane + kWave * c;
+                        if (j < k) {
+                            double mv = mreg[REG ? q : 0][REG ? c : 0];
+                            a0 += mv * v0[j];
+                            a1 += mv * v1[j];
+                        }
+                    }
+                    a0 = wave_sum(a0);
+                    a1 = wave_sum(a1);
+                    if (lane == 0) {
+                        z0[r] = a0;
+                        z1[r] = a1;
+                    }
+                }
+            }
+        } else {
+            for (int r = w; r < k; r += nw) {
+                double a0 = 0.0, a1 = 0.0;
+                for (int j = lane; j < k; j += kWave) {
+                    double mv = M[(size_t)r * k + j];
+                    a0 += mv * v0[j];
+                    a1 += mv * v1[j];
+                }
+                a0 = wave_sum(a0);
+                a1 = wave_sum(a1);
+                if (lane == 0) {
+                    z0[r] = a0;
+                    z1[r] = a1;
+                }
+            }
+        }
+        __syncthreads();
+    };
+    auto dot = [&](const double* a, const double* b) {
+        double s = 0.0;
+        for (int t = threadIdx.x; t < k; t += blockDim.x) s += a[t] * b[t];
+        return block_sum(s, red);
+    };
+    // normalize v0, orthonormalize v1 against it (start vectors)
+    {
+        double nn = sqrt(dot(v0, v0));
+        for (int t = threadIdx.x; t < k; t += blockDim.x) v0[t] /= nn;
+        __syncthreads();
+        for (int pass = 0; pass < 2; ++pass) {
+            double d = dot(v0, v1);
+            for (int t = threadIdx.x; t < k; t += blockDim.x) v1[t] -= d * v0[t];
+            __syncthreads();
+        }
+        double n1 = sqrt(dot(v1, v1));
+        for (int t = threadIdx.x; t < k; t += blockDim.x) v1[t] /= n1;
+        __syncthreads();
+    }
+    int it = 0;
+    for (; it < max_iter; ++it) {
+        matvec();
+        double n0 = sqrt(dot(z0, z0));
+        for (int t = threadIdx.x; t < k; t += blockDim.x) z0[t] /= n0;
+        __syncthreads();
+        // Gram-Schmidt twice: once is not enough when z1 is nearly parallel to z0
+        for (int pass = 0; pass < 2; ++pass) {
+            double d01 = dot(z0, z1);
+            for (int t = threadIdx.x; t < k; t += blockDim.x) z1[t] -= d01 * z0[t];
+            __syncthreads();
+        }
+        double n1 = sqrt(dot(z1, z1));
+        // a second column negligible against the first: M has numerical rank 1
+        const bool rank1 = !(n1 > 1e-13 * n0);
+        if (rank1) {
+            // any unit vector orthogonal to z0 will do: keep v1 made orthogonal to z0
+            for (int t = threadIdx.x; t < k; t += blockDim.x) z1[t] = v1[t];
+            __syncthreads();
+            for (int pass = 0; pass < 2; ++pass) {
+                double d = dot(z0, z1);
+                for (int t = threadIdx.x; t < k; t += blockDim.x) z1[t] -= d * z0[t];
+                __syncthreads();
+            }
+            n1 = sqrt(dot(z1, z1));
+        }
+        for (int t = threadIdx.x; t < k; t += blockDim.x) z1[t] /= n1;
+        __syncthreads();
+        // distance of span(Z) from span(V): residual of projecting Z on V
+        double p00 = dot(v0, z0), p10 = dot(v1, z0), p01 = dot(v0, z1), p11 = dot(v1, z1);
+        double res0 = 0.0, res1 = 0.0;
+        for (int t = threadIdx.x; t < k; t += blockDim.x) {
+            double r0 = z0[t] - p00 * v0[t] - p10 * v1[t];
+            double r1 = z1[t] - p01 * v0[t] - p11 * v1[t];
+            res0 = fmax(res0, fabs(r0));
+            res1 = fmax(res1, fabs(r1));
+        }
+        res0 = block_max(res0, red);
+        res1 = block_max(res1, red);
+        for (int t = threadIdx.x; t < k; t += blockDim.x) {
+            v0[t] = z0[t];
+            v1[t] = z1[t];
+        }
+        __syncthreads();
+        if (res0 < tol && (res1 < tol || rank1)) {
+            ++it;
+            break;
+        }
+    }
+    // Rayleigh-Ritz on span(V)
+    matvec();
+    double b00 = dot(v0, z0), b11 = dot(v1, z1);
+    double b01 = 0.5 * (dot(v0, z1) + dot(v1, z0));
+    double th = 0.5 * atan2(2.0 * b01, b00 - b11);
+    double cs = cos(th), sn = sin(th);
+    double l0 = b00 * cs * cs + 2.0 * b01 * cs * sn + b11 * sn * sn;
+    double l1 = b00 * sn * sn - 2.0 * b01 * cs * sn + b11 * cs * cs;
+    for (int t = threadIdx.x; t < k; t += blockDim.x) {
+        double a = v0[t], b = v1[t];
+        z0[t] = cs * a + sn * b;
+        z1[t] = -sn * a + cs * b;
+    }
+    __syncthreads();
+    // sign rule
+    for (int col = 0; col < 2; ++col) {
+        double* z = col == 0 ? z0 : z1;
+        double mx = 0.0;
+        for (int t = threadIdx.x; t < k; t += blockDim.x) mx = fmax(mx, fabs(z[t]));
+        mx = block_max(mx, red);
+        int idx = k;  // lowest index within a relative 1e-9 of the largest magnitude
+        for (int t = threadIdx.x; t < k; t += blockDim.x)
+            if (fabs(z[t]) >= mx * (1.0 - 1e-9) && t < idx) idx = t;
+        idx = -block_max(-idx, (int*)red);
+        if (idx >= k) idx = 0;
+        double sg = z[idx] < 0.0 ? -1.0 : 1.0;
+        for (int t = threadIdx.x; t < k; t += blockDim.x) out[2 * t + col] = sg * z[t];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[2 * k] = l0;
+        out[2 * k + 1] = l1;
+        iters[0] = it;
+    }
+}
+
+// x_i = sum over t ascending of C_it V_t (per column), FP64.
+template <typename DT, int VEC>
+__global__ void k_pmds_project(int n, int k, int nwords, const uint4* __restrict__ dpk,
+                               const double* __restrict__ mu, const double* __restrict__ nu,
+                               const double* __restrict__ stats, const double* __restrict__ V,
+                               double2* __restrict__ x) {
+#pragma clang fp contract(off)
+    const double gamma = stats[0];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        double s0 = 0.0, s1 = 0.0, nui = nu[i];
+        for (int b = 0; b < nwords; ++b) {
+            union {
+                uint4 v;
+                DT e[VEC];
+            } u;
+            u.v = dpk[(size_t)b * n + i];
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                int t = b * VEC + j;
+                if (t < k) {
+                    double c = centred((int)u.e[j], mu[t], nui, gamma);
+                    s0 += c * V[2 * t];
+                    s1 += c * V[2 * t + 1];
+                }
+            }
+        }
+        x[i] = make_double2(s0, s1);
+    }
+}
+
+// Per-block partial sums of ||x_i - x_j|| over edges with j > i.
+__global__ __launch_bounds__(256) void k_pmds_edgelen(int n, const int* __restrict__ rp,
+                                                      const int* __restrict__ ci,
+                                                      const double2* __restrict__ x,
+                                                      double* __restrict__ partials) {
+    double s = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        double2 xi = x[i];
+        for (int e = rp[i]; e < rp[i + 1]; ++e) {
+            int j = ci[e];
+            if (j <= i) continue;
+            double2 xj = x[j];
+            double dx = xi.x - xj.x, dy = xi.y - xj.y;
+            s += sqrt(dx * dx + dy * dy);
+        }
+    }
+    __shared__ double red[256 / kWave];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// x_out = c x with c = m / (summed edge lengths); flag[0] = 1 if that sum is 0.
+template <typename T2>
+__global__ void k_pmds_scale(int n, long long m, const double2* __restrict__ x, const double* __restrict__ have,
+                             T2* __restrict__ out, int* flag) {
+    const double h = have[0];
+    if (h == 0.0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) flag[0] = 1;
+        return;
+    }
+    const double c = (double)m / h;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        double2 v = x[i];
+        out[i].x = v.x * c;
+        out[i].y = v.y * c;
+    }
+}
+
+ssm_status pivotmds(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* x, hipStream_t s) {
+    const int n = t->n, k = t->k;
+    if (k > 1024) return fail(SSM_E_RANGE, "PivotMDS supports k <= 1024");
+    const int kp = div_up(k, 16) * 16, T = kp / 16;
+    std::vector<int2> htiles;
+    for (int a = 0; a < T; ++a)
+        for (int b = a; b < T; ++b) htiles.push_back(make_int2(a, b));
+    const int ntiles = (int)htiles.size();
+    const int per_group = kGramWaves * kGramTPW;
+    const int ngroups = div_up(ntiles, per_group);
+    int nchunks = std::max(1, std::min(div_up(n, 1024), std::max(1, 4 * num_cus() / ngroups)));
+    int chunk = div_up(div_up(n, nchunks), kGramSub) * kGramSub;
+    nchunks = div_up(n, chunk);
+    // workspace: colsum (k ll), mu (k), nu (n), stats (4), M (k*k), part, tiles, edge partials
+    const int eblocks = std::min(div_up(n, 256), 2048);
+    size_t bytes = sizeof(long long) * k + sizeof(double) * ((size_t)k + n + 4) +
+                   sizeof(double) * (size_t)nchunks * ntiles * 256 + sizeof(int2) * ntiles +
+                   sizeof(double) * ((size_t)eblocks + 2) + 64 * 8;
+    char* ws = nullptr;
+    ssm_status st = dalloc((void**)&ws, bytes);
+    if (st != SSM_OK) return st;
+    char* cur = ws;
+    auto take = [&](size_t b) {
+        char* r = cur;
+        cur += (b + 63) / 64 * 64;
+        return r;
+    };
+    long long* colsum = (long long*)take(sizeof(long long) * k);
+    double* mu = (double*)take(sizeof(double) * k);
+    double* nu = (double*)take(sizeof(double) * n);
+    double* stats = (double*)take(sizeof(double) * 4);
+    double* M = t->gram;
+    double* part = (double*)take(sizeof(double) * (size_t)nchunks * ntiles * 256);
+    int2* tiles = (int2*)take(sizeof(int2) * ntiles);
+    double* epart = (double*)take(sizeof(double) * ((size_t)eblocks + 2));
+    int* flag = (int*)(epart + eblocks + 1);
+    hipError_t e = hipMemcpyAsync(tiles, htiles.data(), sizeof(int2) * ntiles, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(flag, 0, sizeof(int), s);
+    const int nwords = t->kpad / t->vec;
+    const int gn = std::min(div_up(n, 256), 8192);
+    const uint4* dpk = (const uint4*)t->dpk;
+    if (e == hipSuccess) {
+        if (t->dbytes == 1) {
+            hipLaunchKernelGGL((k_pmds_colsum<uint8_t, 16>), dim3(nwords), dim3(256), 0, s, n, k, dpk, colsum);
+            hipLaunchKernelGGL((k_pmds_nu<uint8_t, 16>), dim3(gn), dim3(256), 0, s, n, k, nwords, dpk, nu);
+        } else {
+            hipLaunchKernelGGL((k_pmds_colsum<uint16_t, 8>), dim3(nwords), dim3(256), 0, s, n, k, dpk, colsum);
+            hipLaunchKernelGGL((k_pmds_nu<uint16_t, 8>), dim3(gn), dim3(256), 0, s, n, k, nwords, dpk, nu);
+        }
+        hipLaunchKernelGGL(k_pmds_mu, dim3(1), dim3(64), 0, s, n, k, colsum, mu, stats);
+        size_t lds = sizeof(double) * ((size_t)kGramSub * kp + kp);
+        dim3 gg(nchunks, ngroups);
+        if (t->dbytes == 1)
+            hipLaunchKernelGGL((k_pmds_gram<uint8_t, 16>), gg, dim3(256), lds, s, n, k, kp, t->kpad, chunk,
+                               (const uint4*)t->dpk, mu, nu, stats, tiles, ntiles, part);
+        else
+            hipLaunchKernelGGL((k_pmds_gram<uint16_t, 8>), gg, dim3(256), lds, s, n, k, kp, t->kpad, chunk,
+                               (const uint4*)t->dpk, mu, nu, stats, tiles, ntiles, part);
+        hipLaunchKernelGGL(k_pmds_gram_reduce, dim3(std::min(div_up((long long)ntiles * 256, 256), 4096)),
+                           dim3(256), 0, s, k, nchunks, ntiles, tiles, part, M);
+        size_t elds = sizeof(double) * 4 * k;
+        if (k <= kEigRows * (kEigThreads / kWave) && k <= kEigCols * kWave)
+            hipLaunchKernelGGL(k_pmds_eig<true>, dim3(1), dim3(kEigThreads), elds, s, k, M, 1e-13, 20000,
+                               t->eig, t->eig_iters);
+        else
+            hipLaunchKernelGGL(k_pmds_eig<false>, dim3(1), dim3(kEigThreads), elds, s, k, M, 1e-13, 20000,
+                               t->eig, t->eig_iters);
+        double2* xd = (double2*)t->xtmp;
+        if (t->dbytes == 1)
+            hipLaunchKernelGGL((k_pmds_project<uint8_t, 16>), dim3(gn), dim3(256), 0, s, n, k, nwords, dpk, mu,
+                               nu, stats, t->eig, xd);
+        else
+            hipLaunchKernelGGL((k_pmds_project<uint16_t, 8>), dim3(gn), dim3(256), 0, s, n, k, nwords, dpk, mu,
+                               nu, stats, t->eig, xd);
+        hipLaunchKernelGGL(k_pmds_edgelen, dim3(eblocks), dim3(256), 0, s, n, g->row_ptr, g->col_idx, xd,
+                           epart);
+        launch_sum_partials(epart, eblocks, epart + eblocks, s);
+        if (p == SSM_FP64)
+            hipLaunchKernelGGL(k_pmds_scale<double2>, dim3(std::min(div_up(n, 256), 8192)), dim3(256), 0, s, n,
+                               (long long)(g->nnz / 2), xd, epart + eblocks, (double2*)x, flag);
+        else
+            hipLaunchKernelGGL(k_pmds_scale<float2>, dim3(std::min(div_up(n, 256), 8192)), dim3(256), 0, s, n,
+                               (long long)(g->nnz / 2), xd, epart + eblocks, (float2*)x, flag);
+        e = hipGetLastError();
+    }
+    int hflag = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(ws);
+    if (e != hipSuccess) return hip_fail(e, "PivotMDS");
+    if (hflag) return fail(SSM_E_INVAL, "PivotMDS layout has zero total edge length; cannot rescale");
+    return SSM_OK;
+}
+
+}  // namespace ssm

@@ -1,0 +1,263 @@
+"""Thin ctypes binding of libssm (the HIP library).  Argument marshalling only:
+every step runs in the library's kernels.  Device buffers are torch tensors
+(used for device memory and streams only); the current torch stream is passed
+to every call.
+
+Raises RuntimeError at first use if libssm.so is missing: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libssm.so")
+
+OK, E_INVAL, E_RANGE, E_DISCONNECTED, E_NOMEM, E_DEVICE = range(6)
+FP64, FP32 = 0, 1
+STRESS_SPARSE, STRESS_FULL = 0, 1
+
+_lock = threading.Lock()
+_lib = None
+
+
+class SSMError(RuntimeError):
+    def __init__(self, status: int, func: str, msg: str):
+        super().__init__(f"{func}: status {status}: {msg}")
+        self.status = status
+
+
+class _CSR(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int32),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p)]
+
+
+EXPORTS = [
+    "ssm_validate_csr", "ssm_select_pivots", "ssm_bfs_pivots", "ssm_regions", "ssm_build_terms",
+    "ssm_terms_free", "ssm_terms_dims", "ssm_terms_export", "ssm_pivotmds_init",
+    "ssm_pivotmds_eig", "ssm_pivotmds_gram", "ssm_majorize", "ssm_stress", "ssm_last_error",
+]
+
+
+def load(path: str | None = None):
+    """Load libssm.so (once) and declare its signatures."""
+    global _lib
+    with _lock:
+        if _lib is not None and path is None:
+            return _lib
+        p = path or LIB_PATH
+        if not os.path.exists(p):
+            raise RuntimeError(f"libssm.so not built ({p}); run __graft_entry__.build()")
+        lib = ctypes.CDLL(p)
+        V, I, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+        S = ctypes.c_int
+        P = ctypes.POINTER(_CSR)
+        sig = {
+            "ssm_validate_csr": (S, [P, V]),
+            "ssm_select_pivots": (S, [P, I, I, V, V, V]),
+            "ssm_bfs_pivots": (S, [P, I, V, V, V, V, V]),
+            "ssm_regions": (S, [I, I, V, V, V, V]),
+            "ssm_build_terms": (S, [P, I, V, V, V, V, ctypes.POINTER(V), V]),
+            "ssm_terms_free": (None, [V]),
+            "ssm_terms_dims": (S, [V, V, V, V]),
+            "ssm_terms_export": (S, [V, V, V, V, V, V]),
+            "ssm_pivotmds_init": (S, [P, V, I, V, V]),
+            "ssm_pivotmds_eig": (S, [V, V, V, V]),
+            "ssm_pivotmds_gram": (S, [V, V]),
+            "ssm_majorize": (S, [P, V, I, V, I, D, V, V]),
+            "ssm_stress": (S, [P, V, I, V, I, V, V]),
+            "ssm_last_error": (ctypes.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        if path is None:
+            _lib = lib
+        return lib
+
+
+def _check(st: int, func: str):
+    if st != OK:
+        msg = load().ssm_last_error()
+        raise SSMError(st, func, msg.decode() if msg else "")
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _hptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class DeviceGraph:
+    """A CSR graph resident in device memory (int32 row_ptr and col_idx)."""
+
+    def __init__(self, n: int, row_ptr: torch.Tensor, col_idx: torch.Tensor):
+        assert row_ptr.dtype == torch.int32 and col_idx.dtype == torch.int32
+        self.n = int(n)
+        self.row_ptr = row_ptr.contiguous()
+        self.col_idx = col_idx.contiguous()
+        self.nnz = int(self.col_idx.numel())
+        self._c = _CSR(self.n, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr())
+
+    @classmethod
+    def from_csr(cls, g, device="cuda"):
+        rp = torch.from_numpy(g.row_ptr).to(device)
+        ci = torch.from_numpy(g.col_idx).to(device) if g.nnz else torch.zeros(1, dtype=torch.int32, device=device)
+        return cls(g.n, rp, ci)
+
+    @property
+    def cref(self):
+        return ctypes.byref(self._c)
+
+
+class Terms:
+    """Owner of an ssm_terms handle (freed with the object)."""
+
+    def __init__(self, handle: int, graph: DeviceGraph, k: int):
+        self.handle = ctypes.c_void_p(handle)
+        self.graph = graph
+        self.k = k
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.ssm_terms_free(h)
+            self.handle = None
+
+    def dims(self):
+        k, dm, dx = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(load().ssm_terms_dims(self.handle, ctypes.byref(k), ctypes.byref(dm), ctypes.byref(dx)),
+               "ssm_terms_dims")
+        return k.value, dm.value, dx.value
+
+    def export(self):
+        import numpy as np
+        k, dm, dx = self.dims()
+        n = self.graph.n
+        H = np.empty((k, dm + 1), dtype=np.int32)
+        w64 = np.empty((k, dx + 1), dtype=np.float64)
+        w32 = np.empty((k, dx + 1), dtype=np.float32)
+        d64 = np.empty(n, dtype=np.float64)
+        d32 = np.empty(n, dtype=np.float32)
+        _check(load().ssm_terms_export(self.handle, _hptr(H), _hptr(w64), _hptr(w32), _hptr(d64), _hptr(d32)),
+               "ssm_terms_export")
+        return {"H": H, "wtab64": w64, "wtab32": w32, "den64": d64, "den32": d32,
+                "delta_max": dm, "dmax": dx}
+
+
+# ------------------------------------------------------------------- calls
+
+def validate_csr(g: DeviceGraph):
+    _check(load().ssm_validate_csr(g.cref, _stream()), "ssm_validate_csr")
+
+
+def select_pivots(g: DeviceGraph, k: int, first: int = 0, with_dist: bool = False):
+    piv = torch.empty(k, dtype=torch.int32, device="cuda")
+    dist = torch.empty((k, g.n), dtype=torch.int32, device="cuda") if with_dist else None
+    _check(load().ssm_select_pivots(g.cref, k, first, _ptr(piv), _ptr(dist), _stream()), "ssm_select_pivots")
+    return (piv, dist) if with_dist else piv
+
+
+def bfs_pivots(g: DeviceGraph, pivots: torch.Tensor):
+    k = int(pivots.numel())
+    dist = torch.empty((k, g.n), dtype=torch.int32, device="cuda")
+    delta = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    region = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    _check(load().ssm_bfs_pivots(g.cref, k, _ptr(pivots), _ptr(dist), _ptr(delta), _ptr(region), _stream()),
+           "ssm_bfs_pivots")
+    return dist, delta, region
+
+
+def regions(dist: torch.Tensor):
+    k, n = dist.shape
+    delta = torch.empty(n, dtype=torch.int32, device="cuda")
+    region = torch.empty(n, dtype=torch.int32, device="cuda")
+    _check(load().ssm_regions(n, k, _ptr(dist), _ptr(delta), _ptr(region), _stream()), "ssm_regions")
+    return delta, region
+
+
+def build_terms(g: DeviceGraph, pivots, dist, delta, region) -> Terms:
+    k = int(pivots.numel())
+    h = ctypes.c_void_p()
+    _check(load().ssm_build_terms(g.cref, k, _ptr(pivots), _ptr(dist), _ptr(delta), _ptr(region),
+                                  ctypes.byref(h), _stream()), "ssm_build_terms")
+    return Terms(h.value, g, k)
+
+
+def _xtensor(n: int, prec: int):
+    return torch.empty((n, 2), dtype=torch.float64 if prec == FP64 else torch.float32, device="cuda")
+
+
+def _prec_of(x: torch.Tensor) -> int:
+    if x.dtype == torch.float64:
+        return FP64
+    if x.dtype == torch.float32:
+        return FP32
+    raise ValueError("layout must be float64 or float32")
+
+
+def pivotmds_init(g: DeviceGraph, terms: Terms, prec: int = FP64, out: torch.Tensor | None = None):
+    x = out if out is not None else _xtensor(g.n, prec)
+    _check(load().ssm_pivotmds_init(g.cref, terms.handle, _prec_of(x), _ptr(x), _stream()), "ssm_pivotmds_init")
+    return x
+
+
+def pivotmds_eig(terms: Terms):
+    import numpy as np
+    V = np.empty((terms.k, 2), dtype=np.float64)
+    lam = np.empty(2, dtype=np.float64)
+    it = ctypes.c_int32()
+    _check(load().ssm_pivotmds_eig(terms.handle, _hptr(V), _hptr(lam), ctypes.byref(it)), "ssm_pivotmds_eig")
+    return V, lam, it.value
+
+
+def pivotmds_gram(terms: Terms):
+    import numpy as np
+    M = np.empty((terms.k, terms.k), dtype=np.float64)
+    _check(load().ssm_pivotmds_gram(terms.handle, _hptr(M)), "ssm_pivotmds_gram")
+    return M
+
+
+def majorize(g: DeviceGraph, terms: Terms, x: torch.Tensor, iters: int, tol: float = 0.0,
+             sync: bool = False):
+    """Runs the sweeps in place on x; returns the sweep count if sync or tol > 0."""
+    done = ctypes.c_int32(-1)
+    want = sync or tol > 0
+    _check(load().ssm_majorize(g.cref, terms.handle, _prec_of(x), _ptr(x), int(iters), float(tol),
+                               ctypes.byref(done) if want else None, _stream()), "ssm_majorize")
+    return done.value if want else None
+
+
+def stress(g: DeviceGraph, terms: Terms | None, x: torch.Tensor, kind: int = STRESS_SPARSE) -> float:
+    out = ctypes.c_double()
+    h = terms.handle if terms is not None else None
+    _check(load().ssm_stress(g.cref, h, _prec_of(x), _ptr(x), int(kind), ctypes.byref(out), _stream()),
+           "ssm_stress")
+    return out.value
+
+
+def layout(g: DeviceGraph, k: int, iters: int, prec: int = FP64, first: int = 0):
+    """Algorithm 1 end to end on the device; returns (x, terms, pivots, dist, delta, region)."""
+    piv = select_pivots(g, k, first)
+    dist, delta, region = bfs_pivots(g, piv)
+    terms = build_terms(g, piv, dist, delta, region)
+    x = pivotmds_init(g, terms, prec)
+    majorize(g, terms, x, iters)
+    return x, terms, piv, dist, delta, region

@@ -1,0 +1,305 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Integer outputs (pivots, distances, nearest-pivot distances, regions,
+histograms) and the FP64 weight tables and denominators must match bit for
+bit; the FP64 sweeps mirror the oracle's operation order and must match bit
+for bit too; PivotMDS (a different eigen solver and summation order) within
+1e-9 of the layout's RMS radius; FP32 sweeps within 1e-4 relative stress.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_08909_amd import graphs as G
+from tests import brute
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_1608_08909_amd import ssm
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ssm.load()
+    yield
+    torch.cuda.synchronize()
+
+
+def _cases():
+    return [
+        (G.path(30), 5), (G.cycle(17), 4), (G.star(12), 3), (G.complete(9), 4),
+        (G.grid(7, 9), 63), (G.tri_grid(9, 11), 10), (G.random_connected(40, 0.1, 3), 7),
+        (G.tree_plus(300, 2), 17), (G.rgg(1500, 4), 33), (G.barabasi_albert(2000, 5, 7), 50),
+        (G.grid(50, 50), 50), (G.holed_mesh(120, 130, 6, 4, 12, 5), 40),
+    ]
+
+
+CASES = _cases()
+IDS = [f"{g.name}-k{k}" for g, k in CASES]
+
+
+def _device_pipeline(g, k):
+    dg = ssm.DeviceGraph.from_csr(g)
+    piv, dist_sel = ssm.select_pivots(dg, k, 0, with_dist=True)
+    dist, delta, region = ssm.bfs_pivots(dg, piv)
+    terms = ssm.build_terms(dg, piv, dist, delta, region)
+    return dg, piv, dist_sel, dist, delta, region, terms
+
+
+@pytest.mark.parametrize("g,k", CASES, ids=IDS)
+def test_preprocessing_bit_exact(g, k):
+    say("case", g.name, "k", k)
+    ref = oracle.preprocess(g.n, g.row_ptr, g.col_idx, k)
+    dg, piv, dist_sel, dist, delta, region, terms = _device_pipeline(g, k)
+    assert np.array_equal(piv.cpu().numpy(), ref.pivots)
+    assert np.array_equal(dist_sel.cpu().numpy(), ref.dist)
+    assert np.array_equal(dist.cpu().numpy(), ref.dist)
+    assert np.array_equal(delta.cpu().numpy(), ref.delta)
+    assert np.array_equal(region.cpu().numpy(), ref.region)
+    ex = terms.export()
+    assert ex["delta_max"] == ref.delta_max and ex["dmax"] == ref.dmax
+    assert np.array_equal(ex["H"], ref.H)
+    assert np.array_equal(ex["wtab64"], ref.wtab)
+    assert np.array_equal(ex["wtab32"], ref.wtab.astype(np.float32))
+    assert np.array_equal(ex["den64"], ref.den)
+    assert np.array_equal(ex["den32"], ref.den.astype(np.float32))
+
+
+def test_regions_with_given_pivots():
+    g = G.tri_grid(30, 31)
+    piv_h = np.array([0, 929, 15, 465, 900, 30, 300, 777], dtype=np.int32)
+    dref = oracle.bfs_pivots(g.n, g.row_ptr, g.col_idx, piv_h)
+    delta_r, region_r, _, _ = oracle.regions(dref)
+    d = torch.from_numpy(dref).cuda()
+    delta, region = ssm.regions(d)
+    assert np.array_equal(delta.cpu().numpy(), delta_r)
+    assert np.array_equal(region.cpu().numpy(), region_r)
+
+
+@pytest.mark.parametrize("g,k", [c for c in CASES if c[1] >= 3], ids=[i for c, i in zip(CASES, IDS) if c[1] >= 3])
+def test_pivotmds_parity(g, k):
+    say("case", g.name, "k", k)
+    ref = oracle.preprocess(g.n, g.row_ptr, g.col_idx, k)
+    xo, Vo, lamo = oracle.pivotmds(ref.dist)
+    x0 = oracle.rescale(g.row_ptr, g.col_idx, xo)
+    dg, piv, _, dist, delta, region, terms = _device_pipeline(g, k)
+    x = ssm.pivotmds_init(dg, terms, ssm.FP64).cpu().numpy()
+    M = ssm.pivotmds_gram(terms)
+    Mo = oracle.gram(oracle.pmds_center(ref.dist))
+    assert np.abs(M - Mo).max() <= 1e-12 * np.abs(Mo).max()
+    V, lam, iters = ssm.pivotmds_eig(terms)
+    assert np.allclose(lam, lamo, rtol=1e-10, atol=1e-12 * abs(lamo[0]))
+    w = np.linalg.eigvalsh(oracle.gram(oracle.pmds_center(ref.dist)))[::-1]
+    gap12 = (w[0] - w[1]) / w[0]
+    gap23 = (w[1] - w[2]) / w[0]
+    if w[1] > 1e-8 * w[0] and gap23 < 1e-6:
+        return   # the dominant plane itself is not unique: only the eigenvalues are fixed
+    if gap12 > 1e-3 and w[1] > 1e-8 * w[0]:
+        # well separated: eigenvectors and layout match directly
+        assert np.abs(V - Vo).max() < 1e-9
+        assert brute.coord_error(x, x0) < 1e-9
+    else:
+        # near-degenerate pair (the plane is fixed, its axes are not) or a
+        # negligible second axis: compare after a rigid alignment
+        assert brute.coord_error(x, x0, align=True) < 1e-9
+    assert iters < 20000
+
+
+@pytest.mark.parametrize("g,k", CASES, ids=IDS)
+def test_sweeps_f64_bit_exact(g, k):
+    say("case", g.name, "k", k)
+    iters = 25
+    ref = oracle.preprocess(g.n, g.row_ptr, g.col_idx, k)
+    rng = np.random.default_rng(11)
+    x0 = rng.normal(size=(g.n, 2)) * np.sqrt(g.n)
+    dg, *_, terms = _device_pipeline(g, k)
+    xg = torch.from_numpy(x0).cuda()
+    ssm.majorize(dg, terms, xg, iters, sync=True)
+    xr, _ = oracle.majorize(g.row_ptr, g.col_idx, ref.pivots, ref.dist, ref.wtab, ref.den, x0, iters)
+    assert np.array_equal(xg.cpu().numpy(), xr)
+    s = ssm.stress(dg, terms, xg)
+    sr = oracle.stress_sparse(g.row_ptr, g.col_idx, ref.pivots, ref.dist, ref.wtab, xr)
+    assert abs(s - sr) <= 1e-9 * sr
+
+
+@pytest.mark.parametrize("g,k", [c for c in CASES if c[0].n >= 60], ids=[i for c, i in zip(CASES, IDS) if c[0].n >= 60])
+def test_sweeps_f32_stress(g, k):
+    say("case", g.name, "k", k)
+    iters = 60
+    ref = oracle.preprocess(g.n, g.row_ptr, g.col_idx, k)
+    x0 = oracle.initial_layout(g.row_ptr, g.col_idx, ref) if k >= 3 else \
+        np.random.default_rng(1).normal(size=(g.n, 2)) * 10
+    x0 = x0.astype(np.float32).astype(np.float64)
+    dg, *_, terms = _device_pipeline(g, k)
+    xg = torch.from_numpy(x0.astype(np.float32)).cuda()
+    ssm.majorize(dg, terms, xg, iters, sync=True)
+    xr, _ = oracle.majorize(g.row_ptr, g.col_idx, ref.pivots, ref.dist, ref.wtab, ref.den, x0, iters)
+    s32 = ssm.stress(dg, terms, xg)
+    sr = oracle.stress_sparse(g.row_ptr, g.col_idx, ref.pivots, ref.dist, ref.wtab, xr)
+    assert abs(s32 - sr) <= 1e-4 * sr, (s32, sr)
+
+
+TWIN_EDGES = [[0, 1], [1, 2], [2, 0], [3, 9], [3, 1], [9, 1], [3, 4], [9, 4], [3, 8], [9, 8],
+              [4, 6], [6, 10], [10, 11], [8, 11], [5, 6], [7, 6], [2, 11], [4, 2]]
+
+
+def test_twins_stay_together():
+    """Adjacent nodes with one closed neighbourhood (3, 9) and nodes with one
+    open neighbourhood (5, 7) start on one point and stay there in both
+    precisions, as in exact arithmetic."""
+    g = G.csr_from_edges(12, np.array(TWIN_EDGES))
+    dg = ssm.DeviceGraph.from_csr(g)
+    for k in (3, 5):
+        piv = ssm.select_pivots(dg, k, 6)
+        dist, delta, region = ssm.bfs_pivots(dg, piv)
+        terms = ssm.build_terms(dg, piv, dist, delta, region)
+        for prec in (ssm.FP64, ssm.FP32):
+            x = ssm.pivotmds_init(dg, terms, prec)
+            ssm.majorize(dg, terms, x, 300, sync=True)
+            xa = x.cpu().numpy()
+            assert np.array_equal(xa[3], xa[9]) and np.array_equal(xa[5], xa[7])
+            assert np.abs(xa[3] - xa[1]).max() > 1e-3
+
+
+def test_sweeps_f32_coordinates_rgg():
+    """Random geometric graph (many twins): FP32 sweeps track the FP64 oracle
+    in coordinates, not only in stress."""
+    g, k, iters = G.rgg(4000, 21), 60, 200
+    ref = oracle.preprocess(g.n, g.row_ptr, g.col_idx, k)
+    x0 = oracle.initial_layout(g.row_ptr, g.col_idx, ref).astype(np.float32).astype(np.float64)
+    dg, *_, terms = _device_pipeline(g, k)
+    xg = torch.from_numpy(x0.astype(np.float32)).cuda()
+    ssm.majorize(dg, terms, xg, iters, sync=True)
+    xr, _ = oracle.majorize(g.row_ptr, g.col_idx, ref.pivots, ref.dist, ref.wtab, ref.den, x0, iters)
+    err = brute.coord_error(xg.cpu().numpy().astype(np.float64), xr)
+    say("rgg fp32 coordinate error", err)
+    assert err < 1e-4
+
+
+def test_sweeps_f32_coordinates_on_grid():
+    """A grid is bipartite, so no two adjacent nodes share a position in the
+    start layout and the FP32 trajectory tracks the FP64 one."""
+    g, k, iters = G.grid(50, 50), 50, 200
+    ref = oracle.preprocess(g.n, g.row_ptr, g.col_idx, k)
+    x0 = oracle.initial_layout(g.row_ptr, g.col_idx, ref).astype(np.float32).astype(np.float64)
+    dg, *_, terms = _device_pipeline(g, k)
+    xg = torch.from_numpy(x0.astype(np.float32)).cuda()
+    ssm.majorize(dg, terms, xg, iters, sync=True)
+    xr, _ = oracle.majorize(g.row_ptr, g.col_idx, ref.pivots, ref.dist, ref.wtab, ref.den, x0, iters)
+    assert brute.coord_error(xg.cpu().numpy().astype(np.float64), xr) < 1e-4
+
+
+def test_end_to_end_grid50_fp64():
+    """50 x 50 grid, k = 50, maxmin from node 0, PivotMDS, 200 sweeps, FP64."""
+    g, k, iters = G.grid(50, 50), 50, 200
+    xr, ref, x0r, _ = oracle.layout(g.n, g.row_ptr, g.col_idx, k, iters)
+    dg = ssm.DeviceGraph.from_csr(g)
+    x, terms, piv, dist, delta, region = ssm.layout(dg, k, iters, ssm.FP64)
+    assert np.array_equal(piv.cpu().numpy(), ref.pivots)
+    assert np.array_equal(region.cpu().numpy(), ref.region)
+    xa = x.cpu().numpy()
+    assert brute.coord_error(xa, xr, align=True) < 1e-9
+    s = ssm.stress(dg, terms, x)
+    sr = oracle.stress_sparse(g.row_ptr, g.col_idx, ref.pivots, ref.dist, ref.wtab, xr)
+    assert abs(s - sr) <= 1e-9 * sr
+    full = ssm.stress(dg, None, x, ssm.STRESS_FULL)
+    full_r = oracle.stress_full(g.row_ptr, g.col_idx, xr)
+    assert abs(full - full_r) <= 1e-9 * full_r
+
+
+def test_full_stress_matches_oracle():
+    for g in [G.cycle(12), G.grid(9, 11), G.rgg(700, 9)]:
+        x = np.random.default_rng(2).normal(size=(g.n, 2))
+        dg = ssm.DeviceGraph.from_csr(g)
+        s = ssm.stress(dg, None, torch.from_numpy(x).cuda(), ssm.STRESS_FULL)
+        sr = oracle.stress_full(g.row_ptr, g.col_idx, x)
+        assert abs(s - sr) <= 1e-9 * sr
+        s32 = ssm.stress(dg, None, torch.from_numpy(x.astype(np.float32)).cuda(), ssm.STRESS_FULL)
+        sr32 = oracle.stress_full(g.row_ptr, g.col_idx, x.astype(np.float32).astype(np.float64))
+        assert abs(s32 - sr32) <= 1e-9 * sr32
+
+
+def test_resume_and_determinism():
+    g, k = G.rgg(3000, 5), 40
+    dg, *_, terms = _device_pipeline(g, k)
+    for dt in (torch.float64, torch.float32):
+        x0 = torch.from_numpy(np.random.default_rng(3).normal(size=(g.n, 2)) * 30).to(dt).cuda()
+        a = x0.clone()
+        ssm.majorize(dg, terms, a, 40)
+        b = x0.clone()
+        ssm.majorize(dg, terms, b, 15)
+        ssm.majorize(dg, terms, b, 25)
+        c = x0.clone()
+        ssm.majorize(dg, terms, c, 40)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b) and torch.equal(a, c)
+
+
+def test_tolerance_stop_matches_oracle():
+    g = G.grid(8, 8)
+    ref = oracle.preprocess(g.n, g.row_ptr, g.col_idx, g.n)
+    x0 = oracle.initial_layout(g.row_ptr, g.col_idx, ref)
+    xr, done_r = oracle.majorize(g.row_ptr, g.col_idx, ref.pivots, ref.dist, ref.wtab, ref.den, x0, 1000, tol=1e-4)
+    dg, *_, terms = _device_pipeline(g, g.n)
+    xg = torch.from_numpy(x0).cuda()
+    done = ssm.majorize(dg, terms, xg, 1000, tol=1e-4)
+    assert done == done_r
+    assert np.array_equal(xg.cpu().numpy(), xr)
+
+
+def test_edge_cases():
+    # k = 1 and k = n
+    g = G.path(6)
+    dg = ssm.DeviceGraph.from_csr(g)
+    for k in (1, g.n):
+        piv = ssm.select_pivots(dg, k, 2)
+        pr, _ = oracle.select_pivots(g.n, g.row_ptr, g.col_idx, k, 2)
+        assert np.array_equal(piv.cpu().numpy(), pr)
+    # PivotMDS needs k >= 3
+    piv = ssm.select_pivots(dg, 2, 0)
+    dist, delta, region = ssm.bfs_pivots(dg, piv)
+    terms = ssm.build_terms(dg, piv, dist, delta, region)
+    with pytest.raises(ssm.SSMError) as ei:
+        ssm.pivotmds_init(dg, terms)
+    assert ei.value.status == ssm.E_INVAL
+    # zero sweeps leave x alone
+    x = torch.arange(12, dtype=torch.float64, device="cuda").reshape(6, 2)
+    y = x.clone()
+    ssm.majorize(dg, terms, y, 0, sync=True)
+    assert torch.equal(x, y)
+    # disconnected input
+    d = G.csr_from_edges(6, np.array([[0, 1], [1, 2], [3, 4], [4, 5]]))
+    dd = ssm.DeviceGraph.from_csr(d)
+    with pytest.raises(ssm.SSMError) as ei:
+        ssm.select_pivots(dd, 2, 0)
+    assert ei.value.status == ssm.E_DISCONNECTED
+    with pytest.raises(ssm.SSMError) as ei:
+        ssm.bfs_pivots(dd, torch.tensor([0, 3], dtype=torch.int32, device="cuda"))
+    assert ei.value.status == ssm.E_DISCONNECTED
+
+
+def test_validate_csr():
+    g = G.grid(5, 6)
+    ssm.validate_csr(ssm.DeviceGraph.from_csr(g))
+    bad = []
+    ci = g.col_idx.copy(); ci[0] = 0
+    bad.append(ci)                                    # self-loop
+    ci = g.col_idx.copy(); ci[1] = ci[0]
+    bad.append(ci)                                    # duplicate arc
+    ci = g.col_idx.copy(); ci[3] = g.n + 5
+    bad.append(ci)                                    # out of range
+    ci = g.col_idx.copy(); ci[2] = (ci[2] + 7) % g.n
+    bad.append(ci)                                    # asymmetric
+    for c in bad:
+        dg = ssm.DeviceGraph(g.n, torch.from_numpy(g.row_ptr).cuda(), torch.from_numpy(c).cuda())
+        with pytest.raises(ssm.SSMError) as ei:
+            ssm.validate_csr(dg)
+        assert ei.value.status == ssm.E_INVAL

@@ -77,6 +77,8 @@ def main():
     ap.add_argument("--workload", default="rgg", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=10)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -108,9 +110,12 @@ def main():
         ev[2].record(stream)
         terms = ssm.build_terms(dg, piv, dist, delta, region)
         ev[3].record(stream)
-        x = ssm.pivotmds_init(dg, terms, prec)
+        x = ssm.pivotmds_init(dg, terms, ssm.FP64)
         ev[4].record(stream)
-        ssm.majorize(dg, terms, x, iters)
+        if prec == ssm.FP32:
+            x = ssm.majorize_mixed(dg, terms, x, iters, warm=1)
+        else:
+            ssm.majorize(dg, terms, x, iters)
         ev[5].record(stream)
         s = ssm.stress(dg, terms, x)
         ev[6].record(stream)
@@ -156,6 +161,11 @@ def main():
     ssm.majorize(dg, terms, x64, iters)
     s64 = ssm.stress(dg, terms, x64)
     rel = abs(s32 - s64) / s64
+    # The method's own sensitivity: FP64 sweeps from the start layout rounded
+    # to FP32 once, against FP64 sweeps from the exact start.
+    xr = ssm.pivotmds_init(dg, terms, ssm.FP64).float().double()
+    ssm.majorize(dg, terms, xr, iters)
+    band = abs(ssm.stress(dg, terms, xr) - s64) / s64
 
     out = {
         "metric": "node-updates/sec & layouts/sec (p50/p99) at equal final stress vs plain, 1 GPU",
@@ -180,11 +190,18 @@ def main():
         "final_stress": s32,
         "final_stress_fp64_plain": s64,
         "final_stress_rel_diff": rel,
+        "fp64_sensitivity_to_fp32_rounded_start": band,
         "roofline": {"bound": "hbm", "kernel": "k_sweep_f32" if prec == ssm.FP32 else "k_sweep_f64",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_launch": nbytes},
     }
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = src.numel() * 4
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, k, iters, args.cpu_sweeps)
     print(json.dumps(out), flush=True)

@@ -149,6 +149,17 @@ ssm_status ssm_pivotmds_gram(const ssm_terms* t, double* M_host);
 ssm_status ssm_majorize(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* x, int32_t iters,
                         double tol, int32_t* iters_done_host, hipStream_t stream);
 
+/* Mixed-precision sweeps: the first `warm` sweeps (1 <= warm) run in FP64
+ * on the start layout x64 (in place); the layout is then rounded into x32 and
+ * the remaining iters - warm sweeps run in FP32 on x32 (if iters <= warm, x32
+ * just receives the rounded FP64 result).  The PivotMDS start places many
+ * nodes within rounding distance of each other, where the update's
+ * direction term (x_i - x_q) / r is ill-conditioned: rounding that start to
+ * FP32 alone moves the final stress by ~1e-4, while rounding after one FP64
+ * sweep moves it by ~1e-10.  Asynchronous. */
+ssm_status ssm_majorize_mixed(const ssm_csr* g, ssm_terms* t, double* x64, float* x32, int32_t iters,
+                              int32_t warm, hipStream_t stream);
+
 /* Stress of layout x, accumulated in FP64: SSM_STRESS_SPARSE is s'(x) of
  * Eq. 3 (edges with w = 1, d = 1, plus every pivot term with w'_it);
  * SSM_STRESS_FULL is s(x) of Eq. 1 over all pairs with d the hop distance

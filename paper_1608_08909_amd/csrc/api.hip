@@ -195,6 +195,17 @@ ssm_status ssm_majorize(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* x, int
     return majorize(g, t, p, x, iters, tol, iters_done_host, stream);
 }
 
+ssm_status ssm_majorize_mixed(const ssm_csr* g, ssm_terms* t, double* x64, float* x32, int32_t iters,
+                              int32_t warm, hipStream_t stream) {
+    ssm_status st = check_csr(g);
+    if (st != SSM_OK) return st;
+    if (!t || !x64 || !x32) return fail(SSM_E_INVAL, "NULL terms or layout");
+    if (t->n != g->n || t->nnz != g->nnz) return fail(SSM_E_INVAL, "terms were built for another graph");
+    if (iters < 0) return fail(SSM_E_INVAL, "negative iteration count");
+    if (warm < 1) return fail(SSM_E_INVAL, "warm must be >= 1");
+    return majorize_mixed(g, t, x64, x32, iters, warm, stream);
+}
+
 ssm_status ssm_stress(const ssm_csr* g, ssm_terms* t, ssm_prec p, const void* x,
                       ssm_stress_kind kind, double* out_host, hipStream_t stream) {
     ssm_status st = check_csr(g);

@@ -69,11 +69,31 @@ __global__ void k_validate(int n, int nnz, const int* __restrict__ rp, const int
 
 // ------------------------------------------------- one BFS per workgroup
 
+// Frontier queue of one workgroup: the first kQcap entries live in LDS, the
+// rest in a global overflow area of n entries.
+constexpr int kQcap = 4096;
+
+__device__ __forceinline__ int wg_load(const int* p) {  // L2-coherent within the workgroup
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ int queue_get(const int* lds, const int* glob, int idx) {
+    return idx < kQcap ? lds[idx] : wg_load(glob + (idx - kQcap));
+}
+
+__device__ __forceinline__ void queue_put(int* lds, int* glob, int idx, int v) {
+    if (idx < kQcap)
+        lds[idx] = v;
+    else
+        glob[idx - kQcap] = v;
+}
+
 // Block b runs a level-synchronous BFS from pivots[b] and writes
 // dist[b][*] (pre-set to -1).  Frontier nodes are spread over groups of VW
-// lanes; a node is claimed by compare-and-swap on its distance and appended
-// to the next frontier with one atomic per wave.  reached[b] = nodes found;
-// *ecc_max = largest eccentricity seen.
+// lanes; a node is claimed by compare-and-swap on its distance (workgroup
+// scope: the row belongs to this block) and appended to the next frontier
+// with one LDS atomic per wave.  reached[b] = nodes found; *ecc_max = largest
+// eccentricity seen.
 template <int VW>
 __global__ __launch_bounds__(kBfsBlock) void k_bfs_wg(int n, const int* __restrict__ rp,
                                                       const int* __restrict__ ci,
@@ -81,18 +101,23 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_wg(int n, const int* __restri
                                                       int* queues, int* reached, int* ecc_max) {
     const int b = blockIdx.x;
     int* D = dist + (size_t)b * n;
-    int* qa = queues + (size_t)b * 2 * n;
-    int* qb = qa + n;
+    int* ga = queues + (size_t)b * 2 * n;
+    int* gb = ga + n;
+    __shared__ int sqa[kQcap], sqb[kQcap];
     __shared__ int s_tail, s_len;
     const int src = pivots[b];
     if (threadIdx.x == 0) {
         D[src] = 0;
-        qa[0] = src;
+        sqa[0] = src;
         s_len = 1;
         s_tail = 0;
     }
     __syncthreads();
     const int sub = threadIdx.x % VW, grp = threadIdx.x / VW, ngrp = blockDim.x / VW;
+    int* lcur = sqa;
+    int* lnxt = sqb;
+    int* gcur = ga;
+    int* gnxt = gb;
     int level = 0, total = 1;
     for (;;) {
         const int len = min(s_len, n);
@@ -101,7 +126,7 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_wg(int n, const int* __restri
             int qi = base + grp;
             int e0 = 0, e1 = 0;
             if (qi < len) {
-                int u = qa[qi];
+                int u = queue_get(lcur, gcur, qi);
                 if ((unsigned)u < (unsigned)n) {
                     e0 = rp[u];
                     e1 = rp[u + 1];
@@ -110,9 +135,13 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_wg(int n, const int* __restri
             for (int e = e0 + sub; e < e1; e += VW) {
                 int v = ci[e];
                 bool claim = false;
-                if (D[v] < 0) claim = atomicCAS(&D[v], -1, level + 1) == -1;
+                if (wg_load(&D[v]) < 0) {
+                    int expected = -1;
+                    claim = __hip_atomic_compare_exchange_strong(&D[v], &expected, level + 1, __ATOMIC_RELAXED,
+                                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
                 int slot = wave_append(claim, &s_tail);
-                if (claim) qb[slot] = v;
+                if (claim) queue_put(lnxt, gnxt, slot, v);
             }
         }
         __syncthreads();
@@ -120,9 +149,12 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_wg(int n, const int* __restri
             s_len = s_tail;
             s_tail = 0;
         }
-        int* tmp = qa;
-        qa = qb;
-        qb = tmp;
+        int* t0 = lcur;
+        lcur = lnxt;
+        lnxt = t0;
+        int* t1 = gcur;
+        gcur = gnxt;
+        gnxt = t1;
         ++level;
         __syncthreads();
         total += s_len;
@@ -290,6 +322,183 @@ __global__ __launch_bounds__(kSelBlock) void k_select(int n, const int* __restri
     }
 }
 
+// All k pivots in one cooperative launch.  For each t: BFS from pivots[t]
+// that continues only through nodes whose distance to the new pivot is below
+// m (their distance to the nearest earlier pivot): a relaxation lowers m with
+// one atomicMin and the node joins the next frontier iff the atomic lowered
+// it.  This is exact for m <- min(m, d_t) because m is 1-Lipschitz along
+// edges (a node with d_t >= m cannot lead to a node where d_t < m).  Then
+// pivots[t+1] = argmax m, lowest id on ties.  m is pre-set to INT_MAX.
+template <int VW>
+__global__ __launch_bounds__(kSelBlock) void k_select_all(int n, const int* __restrict__ rp,
+                                                          const int* __restrict__ ci, int k, int first,
+                                                          int* pivots, int* m, int* qa, int* qb, int* ctl,
+                                                          unsigned long long* keys, int* status) {
+    cg::grid_group grid = cg::this_grid();
+    const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nthreads = gridDim.x * blockDim.x;
+    const int sub = gtid % VW, grp = gtid / VW, ngrp = nthreads / VW;
+    __shared__ unsigned long long s_red[kSelBlock / kWave];
+    for (int t = 0; t < k; ++t) {
+        const int src = (t == 0) ? first : load_agent(&pivots[t]);
+        if (gtid == 0) {
+            if (t == 0) pivots[0] = first;
+            m[src] = 0;
+            qa[0] = src;
+            ctl[0] = 1;
+            ctl[1] = 0;
+            ctl[2] = 0;
+        }
+        grid_barrier(grid);
+        int level = 0;
+        int* cur = qa;
+        int* nxt = qb;
+        for (;;) {
+            const int len = min(load_agent(&ctl[level % 3]), n);
+            if (len == 0) break;
+            int* tail = &ctl[(level + 1) % 3];
+            if (gtid == 0) ctl[(level + 2) % 3] = 0;
+            const int dv = level + 1;
+            for (int base = 0; base < len; base += ngrp) {
+                int qi = base + grp;
+                int e0 = 0, e1 = 0;
+                if (qi < len) {
+                    int u = cur[qi];
+                    if ((unsigned)u < (unsigned)n) {
+                        e0 = rp[u];
+                        e1 = rp[u + 1];
+                    }
+                }
+                for (int e = e0 + sub; e < e1; e += VW) {
+                    int v = ci[e];
+                    bool push = false;
+                    if (m[v] > dv) push = atomicMin(&m[v], dv) > dv;  // stale reads are only larger
+                    int slot = wave_append(push, tail);
+                    if (push) nxt[slot] = v;
+                }
+            }
+            grid_barrier(grid);
+            int* tmp = cur;
+            cur = nxt;
+            nxt = tmp;
+            ++level;
+        }
+        if (t + 1 >= k && t != 0) break;
+        unsigned long long best = 0;
+        for (int i = gtid; i < n; i += nthreads) {
+            unsigned long long key =
+                ((unsigned long long)(unsigned)m[i] << 32) | (unsigned long long)(0xffffffffu - (unsigned)i);
+            best = key > best ? key : best;
+        }
+        best = block_max(best, s_red);
+        if (threadIdx.x == 0) keys[blockIdx.x] = best;
+        grid_barrier(grid);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            unsigned long long b = 0;
+            for (int q = 0; q < (int)gridDim.x; ++q) {
+                unsigned long long kq = __hip_atomic_load(&keys[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                b = kq > b ? kq : b;
+            }
+            if (t == 0 && (int)(b >> 32) == kInf) status[0] = 1;
+            if (t + 1 < k) pivots[t + 1] = (int)(0xffffffffu - (unsigned)(b & 0xffffffffu));
+        }
+        grid_barrier(grid);
+        if (t == 0 && load_agent(&status[0]) != 0) break;  // disconnected: stop (uniform)
+    }
+}
+
+// All k pivots in one workgroup (no grid barrier): the same pruned BFS and
+// argmax as k_select_all, with the frontier in LDS (global overflow), LDS
+// counters and workgroup-scope atomics on m.
+template <int VW>
+__global__ __launch_bounds__(kBfsBlock) void k_select_wg(int n, const int* __restrict__ rp,
+                                                         const int* __restrict__ ci, int k, int first,
+                                                         int* pivots, int* m, int* queues, int* status) {
+    __shared__ int sqa[kQcap], sqb[kQcap];
+    __shared__ int s_tail, s_len, s_src;
+    __shared__ unsigned long long s_red[kBfsBlock / kWave];
+    const int sub = threadIdx.x % VW, grp = threadIdx.x / VW, ngrp = blockDim.x / VW;
+    int* ga = queues;
+    int* gb = queues + n;
+    if (threadIdx.x == 0) s_src = first;
+    __syncthreads();
+    for (int t = 0; t < k; ++t) {
+        const int src = s_src;
+        if (threadIdx.x == 0) {
+            pivots[t] = src;
+            __hip_atomic_store(&m[src], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            sqa[0] = src;
+            s_len = 1;
+            s_tail = 0;
+        }
+        __syncthreads();
+        int* lcur = sqa;
+        int* lnxt = sqb;
+        int* gcur = ga;
+        int* gnxt = gb;
+        int level = 0;
+        for (;;) {
+            const int len = min(s_len, n);
+            if (len == 0) break;
+            const int dv = level + 1;
+            for (int base = 0; base < len; base += ngrp) {
+                int qi = base + grp;
+                int e0 = 0, e1 = 0;
+                if (qi < len) {
+                    int u = queue_get(lcur, gcur, qi);
+                    if ((unsigned)u < (unsigned)n) {
+                        e0 = rp[u];
+                        e1 = rp[u + 1];
+                    }
+                }
+                for (int e = e0 + sub; e < e1; e += VW) {
+                    int v = ci[e];
+                    bool push = false;
+                    if (wg_load(&m[v]) > dv)  // m only decreases: a stale value is only larger
+                        push = __hip_atomic_fetch_min(&m[v], dv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) > dv;
+                    int slot = wave_append(push, &s_tail);
+                    if (push) queue_put(lnxt, gnxt, slot, v);
+                }
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                s_len = s_tail;
+                s_tail = 0;
+            }
+            int* t0 = lcur;
+            lcur = lnxt;
+            lnxt = t0;
+            int* t1 = gcur;
+            gcur = gnxt;
+            gnxt = t1;
+            ++level;
+            __syncthreads();
+        }
+        if (t + 1 >= k && t != 0) break;
+        unsigned long long best = 0;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            unsigned long long key = ((unsigned long long)(unsigned)wg_load(&m[i]) << 32) |
+                                     (unsigned long long)(0xffffffffu - (unsigned)i);
+            best = key > best ? key : best;
+        }
+        best = block_max(best, s_red);
+        if (threadIdx.x == 0) {
+            if (t == 0 && (int)(best >> 32) == kInf) status[0] = 1;
+            s_src = (int)(0xffffffffu - (unsigned)(best & 0xffffffffu));
+        }
+        __syncthreads();
+        if (t == 0 && (int)(best >> 32) == kInf) break;  // disconnected (uniform)
+    }
+}
+
+template <int VW>
+static hipError_t launch_select_all(int blocks, hipStream_t s, int n, const int* rp, const int* ci, int k,
+                                    int first, int* pivots, int* m, int* qa, int* qb, int* ctl,
+                                    unsigned long long* keys, int* status) {
+    void* args[] = {&n, &rp, &ci, &k, &first, &pivots, &m, &qa, &qb, &ctl, &keys, &status};
+    return hipLaunchCooperativeKernel((const void*)k_select_all<VW>, dim3(blocks), dim3(kSelBlock), args, 0, s);
+}
+
 __global__ void k_fill_int(int* p, int v, long long count) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
          i += (long long)gridDim.x * blockDim.x)
@@ -307,12 +516,13 @@ static hipError_t launch_select(int blocks, hipStream_t s, int n, const int* rp,
 
 template <int VW>
 static int select_max_blocks() {
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_select<VW>, kSelBlock, 0) !=
-            hipSuccess ||
-        per_cu < 1)
-        per_cu = 1;
-    return per_cu * num_cus();
+    int a = 0, b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, (const void*)k_select<VW>, kSelBlock, 0) != hipSuccess)
+        a = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, (const void*)k_select_all<VW>, kSelBlock, 0) !=
+        hipSuccess)
+        b = 1;
+    return std::max(1, std::min(a, b)) * num_cus();
 }
 
 ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pivots, hipStream_t s) {
@@ -355,7 +565,32 @@ ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pi
     hipLaunchKernelGGL(k_fill_int, dim3(std::min(div_up(2 * (long long)n, 256), 4096)), dim3(256), 0, s, qa, 0,
                        2 * (long long)n);
     e = hipGetLastError();
-    for (int t = 0; t < k && e == hipSuccess; ++t) {
+    // Mode: one workgroup (no grid barrier) unless the frontiers are large.
+    int mode = env_int("SSM_SELECT_MODE");  // 1 = one workgroup, 2 = cooperative grid, 3 = per pivot
+    if (mode < 1 || mode > 3) mode = (long long)n <= (1LL << 18) ? 1 : 2;
+    const bool per_pivot = mode == 3;
+    if (mode == 1 && e == hipSuccess) {
+        switch (vw) {
+            case 2: hipLaunchKernelGGL(k_select_wg<2>, dim3(1), dim3(kBfsBlock), 0, s, n, g->row_ptr, g->col_idx, k, first, pivots, m, qa, status); break;
+            case 4: hipLaunchKernelGGL(k_select_wg<4>, dim3(1), dim3(kBfsBlock), 0, s, n, g->row_ptr, g->col_idx, k, first, pivots, m, qa, status); break;
+            case 8: hipLaunchKernelGGL(k_select_wg<8>, dim3(1), dim3(kBfsBlock), 0, s, n, g->row_ptr, g->col_idx, k, first, pivots, m, qa, status); break;
+            case 16: hipLaunchKernelGGL(k_select_wg<16>, dim3(1), dim3(kBfsBlock), 0, s, n, g->row_ptr, g->col_idx, k, first, pivots, m, qa, status); break;
+            case 32: hipLaunchKernelGGL(k_select_wg<32>, dim3(1), dim3(kBfsBlock), 0, s, n, g->row_ptr, g->col_idx, k, first, pivots, m, qa, status); break;
+            default: hipLaunchKernelGGL(k_select_wg<64>, dim3(1), dim3(kBfsBlock), 0, s, n, g->row_ptr, g->col_idx, k, first, pivots, m, qa, status); break;
+        }
+        e = hipGetLastError();
+    }
+    if (mode == 2 && e == hipSuccess) {
+        switch (vw) {
+            case 2: e = launch_select_all<2>(blocks, s, n, g->row_ptr, g->col_idx, k, first, pivots, m, qa, qb, ctl, keys, status); break;
+            case 4: e = launch_select_all<4>(blocks, s, n, g->row_ptr, g->col_idx, k, first, pivots, m, qa, qb, ctl, keys, status); break;
+            case 8: e = launch_select_all<8>(blocks, s, n, g->row_ptr, g->col_idx, k, first, pivots, m, qa, qb, ctl, keys, status); break;
+            case 16: e = launch_select_all<16>(blocks, s, n, g->row_ptr, g->col_idx, k, first, pivots, m, qa, qb, ctl, keys, status); break;
+            case 32: e = launch_select_all<32>(blocks, s, n, g->row_ptr, g->col_idx, k, first, pivots, m, qa, qb, ctl, keys, status); break;
+            default: e = launch_select_all<64>(blocks, s, n, g->row_ptr, g->col_idx, k, first, pivots, m, qa, qb, ctl, keys, status); break;
+        }
+    }
+    for (int t = 0; per_pivot && t < k && e == hipSuccess; ++t) {
         switch (vw) {
             case 2: e = launch_select<2>(blocks, s, n, g->row_ptr, g->col_idx, t, k, first, pivots, m, vis, qa, qb, ctl, keys, status); break;
             case 4: e = launch_select<4>(blocks, s, n, g->row_ptr, g->col_idx, t, k, first, pivots, m, vis, qa, qb, ctl, keys, status); break;

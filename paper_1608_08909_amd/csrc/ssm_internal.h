@@ -75,6 +75,8 @@ ssm_status pivotmds(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* x, hipStre
 // ---- sweeps and stress (sweep.hip)
 ssm_status majorize(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* x, int32_t iters,
                     double tol, int32_t* iters_done_host, hipStream_t s);
+ssm_status majorize_mixed(const ssm_csr* g, ssm_terms* t, double* x64, float* x32, int32_t iters, int32_t warm,
+                          hipStream_t s);
 ssm_status stress_sparse(const ssm_csr* g, ssm_terms* t, ssm_prec p, const void* x,
                          double* out_host, hipStream_t s);
 ssm_status stress_full(const ssm_csr* g, ssm_prec p, const void* x, double* out_host,

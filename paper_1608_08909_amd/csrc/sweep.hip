@@ -119,8 +119,7 @@ enum WeightMode { kTableLds = 0, kHistLds = 1, kTableGlobal = 2 };
 // added in a fixed order.  Weights: kTableLds stages (w', w'd) for every
 // (pivot, distance); kHistLds stages the region histograms H and (1/d^2, 1/d)
 // and forms w' = H[t][min(d/2, delta_max)] / d^2; kTableGlobal reads the table
-// from memory.  1/r is the hardware reciprocal square root; r^2 below FLT_MIN
-// counts as r = 0.
+// from memory.  1/r is the hardware reciprocal square root of r^2 + 1e-30.
 template <typename DT, int VEC, int WAVES, int MODE>
 __global__ __launch_bounds__(64 * WAVES) void k_sweep_f32(
     int n, int kpad, int W, int L, const int* __restrict__ rp, const int* __restrict__ ci,
@@ -140,51 +139,68 @@ __global__ __launch_bounds__(64 * WAVES) void k_sweep_f32(
         for (int q = threadIdx.x; q < kpad * L; q += blockDim.x) sH[q] = Hf[q];
     }
     __syncthreads();
-    const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+    const int lane = threadIdx.x % 64;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);  // wave-uniform
     const int nwords = kpad / VEC;
+    // r^2 gets 1e-30 added: a vote at distance zero then has a finite factor
+    // times a zero displacement, i.e. contributes exactly 0
+    const float tiny = 1e-30f;
     for (int base = blockIdx.x * 64; base < n; base += gridDim.x * 64) {
         const int i = base + lane;
         float ax = 0.f, ay = 0.f;
         if (i < n) {
             const float2 xi = xo[i];
             if (w == 0) {
-                const int e1 = rp[i + 1];
-                for (int e = rp[i]; e < e1; ++e) {
-                    const float2 xj = xo[ci[e]];
-                    float dx = xj.x - xi.x, dy = xj.y - xi.y;
-                    float r2 = dx * dx + dy * dy;
-                    float inv = r2 >= FLT_MIN ? __builtin_amdgcn_rsqf(r2) : 0.f;
-                    float f = 1.f - inv;  // w = 1, d = 1
-                    ax += f * dx;
-                    ay += f * dy;
+                // neighbour votes in CSR order; loads batched four at a time
+                const int e0 = rp[i], e1 = rp[i + 1];
+                for (int e = e0; e < e1; e += 4) {
+                    int j[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) j[q] = e + q < e1 ? ci[e + q] : i;
+                    float2 xj[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) xj[q] = xo[j[q]];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        float dx = xj[q].x - xi.x, dy = xj[q].y - xi.y;
+                        float inv = __builtin_amdgcn_rsqf(dx * dx + (dy * dy + tiny));
+                        float f = 1.f - inv;  // w = 1, d = 1
+                        ax += f * dx;
+                        ay += f * dy;
+                    }
                 }
             }
-            for (int b = w; b < nwords; b += WAVES) {
-                Packed<DT, VEC> u;
-                u.v = dpk[(size_t)b * n + i];
+            if (w < nwords) {
+                Packed<DT, VEC> nextw;
+                nextw.v = dpk[(size_t)w * n + i];
+                for (int b = w; b < nwords; b += WAVES) {
+                    Packed<DT, VEC> u = nextw;
+                    if (b + WAVES < nwords) nextw.v = dpk[(size_t)(b + WAVES) * n + i];  // prefetch
 #pragma unroll
-                for (int j = 0; j < VEC; ++j) {
-                    const int t = b * VEC + j;
-                    const int d = (int)u.e[j];
-                    float wv, wd;
-                    if (MODE == kHistLds) {
-                        const int l = min(d >> 1, L - 1);
-                        const float h = sH[t * L + l];
-                        const float2 id = sTab[d];
-                        wv = h * id.x;
-                        wd = h * id.y;
-                    } else {
-                        const float2 e = MODE == kTableLds ? sTab[t * W + d] : wt2[(size_t)t * W + d];
-                        wv = e.x;
-                        wd = e.y;
+                    for (int jj = 0; jj < VEC; ++jj) {
+                        const int t = b * VEC + jj;  // wave-uniform
+                        const int d = (int)u.e[jj];
+                        float f0, f1, hmul;          // f = hmul * (f0 - f1 * inv)
+                        if (MODE == kHistLds) {
+                            const int l = min(d >> 1, L - 1);
+                            hmul = sH[t * L + l];
+                            const float2 id = sTab[d];
+                            f0 = id.x;
+                            f1 = id.y;
+                        } else {
+                            const float2 e = MODE == kTableLds ? sTab[t * W + d] : wt2[(size_t)t * W + d];
+                            f0 = e.x;
+                            f1 = e.y;
+                            hmul = 1.f;
+                        }
+                        const float2 p = sP[t];
+                        float dx = p.x - xi.x, dy = p.y - xi.y;
+                        float inv = __builtin_amdgcn_rsqf(dx * dx + (dy * dy + tiny));
+                        float f = fmaf(-f1, inv, f0);
+                        if (MODE == kHistLds) f *= hmul;
+                        ax += f * dx;
+                        ay += f * dy;
                     }
-                    const float2 p = sP[t];
-                    float dx = p.x - xi.x, dy = p.y - xi.y;
-                    float r2 = dx * dx + dy * dy;
-                    float inv = r2 >= FLT_MIN ? __builtin_amdgcn_rsqf(r2) : 0.f;
-                    float f = wv - wd * inv;
-                    ax += f * dx;
-                    ay += f * dy;
                 }
             }
         }
@@ -419,6 +435,25 @@ ssm_status majorize(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* x, int32_t
         SSM_HIP(hipStreamSynchronize(s));
         *iters_done_host = done;
     }
+    return SSM_OK;
+}
+
+__global__ void k_round_layout(int n, const double2* __restrict__ a, float2* __restrict__ b) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        double2 v = a[i];
+        b[i] = make_float2((float)v.x, (float)v.y);
+    }
+}
+
+ssm_status majorize_mixed(const ssm_csr* g, ssm_terms* t, double* x64, float* x32, int32_t iters, int32_t warm,
+                          hipStream_t s) {
+    const int first = std::min(iters, warm);
+    ssm_status st = majorize(g, t, SSM_FP64, x64, first, 0.0, nullptr, s);
+    if (st != SSM_OK) return st;
+    hipLaunchKernelGGL(k_round_layout, dim3(std::min(div_up(t->n, 256), 4096)), dim3(256), 0, s, t->n,
+                       (const double2*)x64, (float2*)x32);
+    SSM_HIP(hipGetLastError());
+    if (iters > first) return majorize(g, t, SSM_FP32, x32, iters - first, 0.0, nullptr, s);
     return SSM_OK;
 }
 

@@ -39,7 +39,7 @@ class _CSR(ctypes.Structure):
 EXPORTS = [
     "ssm_validate_csr", "ssm_select_pivots", "ssm_bfs_pivots", "ssm_regions", "ssm_build_terms",
     "ssm_terms_free", "ssm_terms_dims", "ssm_terms_export", "ssm_pivotmds_init",
-    "ssm_pivotmds_eig", "ssm_pivotmds_gram", "ssm_majorize", "ssm_stress", "ssm_last_error",
+    "ssm_pivotmds_eig", "ssm_pivotmds_gram", "ssm_majorize", "ssm_majorize_mixed", "ssm_stress", "ssm_last_error",
 ]
 
 
@@ -69,6 +69,7 @@ def load(path: str | None = None):
             "ssm_pivotmds_eig": (S, [V, V, V, V]),
             "ssm_pivotmds_gram": (S, [V, V]),
             "ssm_majorize": (S, [P, V, I, V, I, D, V, V]),
+            "ssm_majorize_mixed": (S, [P, V, V, V, I, I, V]),
             "ssm_stress": (S, [P, V, I, V, I, V, V]),
             "ssm_last_error": (ctypes.c_char_p, []),
         }
@@ -245,6 +246,18 @@ def majorize(g: DeviceGraph, terms: Terms, x: torch.Tensor, iters: int, tol: flo
     return done.value if want else None
 
 
+def majorize_mixed(g: DeviceGraph, terms: Terms, x64: torch.Tensor, iters: int, warm: int = 1,
+                   out: torch.Tensor | None = None) -> torch.Tensor:
+    """`warm` FP64 sweeps on x64 (in place), then FP32 sweeps on the rounded
+    layout; returns the FP32 layout."""
+    if x64.dtype != torch.float64:
+        raise ValueError("x64 must be float64")
+    x32 = out if out is not None else torch.empty(x64.shape, dtype=torch.float32, device=x64.device)
+    _check(load().ssm_majorize_mixed(g.cref, terms.handle, _ptr(x64), _ptr(x32), int(iters), int(warm),
+                                     _stream()), "ssm_majorize_mixed")
+    return x32
+
+
 def stress(g: DeviceGraph, terms: Terms | None, x: torch.Tensor, kind: int = STRESS_SPARSE) -> float:
     out = ctypes.c_double()
     h = terms.handle if terms is not None else None
@@ -253,11 +266,15 @@ def stress(g: DeviceGraph, terms: Terms | None, x: torch.Tensor, kind: int = STR
     return out.value
 
 
-def layout(g: DeviceGraph, k: int, iters: int, prec: int = FP64, first: int = 0):
-    """Algorithm 1 end to end on the device; returns (x, terms, pivots, dist, delta, region)."""
+def layout(g: DeviceGraph, k: int, iters: int, prec: int = FP64, first: int = 0, warm: int = 1):
+    """Algorithm 1 end to end on the device; returns (x, terms, pivots, dist, delta, region).
+    FP32 runs PivotMDS and the first `warm` sweeps in FP64, the rest in FP32."""
     piv = select_pivots(g, k, first)
     dist, delta, region = bfs_pivots(g, piv)
     terms = build_terms(g, piv, dist, delta, region)
-    x = pivotmds_init(g, terms, prec)
-    majorize(g, terms, x, iters)
+    x = pivotmds_init(g, terms, FP64)
+    if prec == FP32:
+        x = majorize_mixed(g, terms, x, iters, warm)
+    else:
+        majorize(g, terms, x, iters)
     return x, terms, piv, dist, delta, region

@@ -184,6 +184,32 @@ def test_sweeps_f32_coordinates_rgg():
     assert err < 1e-4
 
 
+@pytest.mark.parametrize("g,k,iters", [(G.rgg(20000, 7, 8.0), 100, 300), (G.tree_plus(5000, 4), 60, 200),
+                                        (G.holed_mesh(150, 160, 8, 4, 12, 3), 80, 200)],
+                         ids=["rgg20000", "tree5000", "holedmesh150"])
+def test_mixed_precision_end_to_end(g, k, iters):
+    """FP32 form (PivotMDS and the first sweep in FP64, then FP32) against the
+    oracle's FP64 run from the same start: final stress within 1e-6 relative
+    and coordinates within 1e-4 of the layout radius."""
+    say("case", g.name, "k", k)
+    ref = oracle.preprocess(g.n, g.row_ptr, g.col_idx, k)
+    x0 = oracle.initial_layout(g.row_ptr, g.col_idx, ref)
+    xr, _ = oracle.majorize(g.row_ptr, g.col_idx, ref.pivots, ref.dist, ref.wtab, ref.den, x0, iters, threads=8)
+    sr = oracle.stress_sparse(g.row_ptr, g.col_idx, ref.pivots, ref.dist, ref.wtab, xr)
+    dg, *_, terms = _device_pipeline(g, k)
+    x64 = torch.from_numpy(x0).cuda()
+    x32 = ssm.majorize_mixed(dg, terms, x64, iters, warm=1)
+    s32 = ssm.stress(dg, terms, x32)
+    say("rel stress", abs(s32 - sr) / sr)
+    assert abs(s32 - sr) <= 1e-6 * sr
+    assert brute.coord_error(x32.cpu().numpy().astype(np.float64), xr) < 1e-4
+    # one sweep: the FP32 result is the rounded oracle sweep, bit for bit
+    x64 = torch.from_numpy(x0).cuda()
+    x1 = ssm.majorize_mixed(dg, terms, x64, 1, warm=1)
+    xr1, _ = oracle.majorize(g.row_ptr, g.col_idx, ref.pivots, ref.dist, ref.wtab, ref.den, x0, 1)
+    assert np.array_equal(x1.cpu().numpy(), xr1.astype(np.float32))
+
+
 def test_sweeps_f32_coordinates_on_grid():
     """A grid is bipartite, so no two adjacent nodes share a position in the
     start layout and the FP32 trajectory tracks the FP64 one."""

@@ -70,18 +70,36 @@ __global__ void k_validate(int n, int nnz, const int* __restrict__ rp, const int
 // ------------------------------------------------- one BFS per workgroup
 
 // Frontier queue of one workgroup: the first kQcap entries live in LDS, the
-// rest in a global overflow area of n entries.
-constexpr int kQcap = 4096;
+// rest in a global overflow area of n entries.  An entry is the row bounds
+// (row_ptr[v], row_ptr[v+1]) of a frontier node, loaded when the node is
+// pushed, so that the next level starts with its neighbour loads.
+constexpr int kQcap = 3072;
 
 __device__ __forceinline__ int wg_load(const int* p) {  // L2-coherent within the workgroup
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-__device__ __forceinline__ int queue_get(const int* lds, const int* glob, int idx) {
-    return idx < kQcap ? lds[idx] : wg_load(glob + (idx - kQcap));
+__device__ __forceinline__ int2 queue_get(const int2* lds, const int2* glob, int idx) {
+    if (idx < kQcap) return lds[idx];
+    const int* g = (const int*)(glob + (idx - kQcap));
+    return make_int2(wg_load(g), wg_load(g + 1));
 }
 
-__device__ __forceinline__ void queue_put(int* lds, int* glob, int idx, int v) {
+// Row bounds of the frontier entry `q`: stored directly (ROWQ) or looked up
+// from the stored node id (entry.x).
+template <bool ROWQ>
+__device__ __forceinline__ int2 entry_row(int2 q, const int* __restrict__ rp, int n) {
+    if (ROWQ) return q;
+    return (unsigned)q.x < (unsigned)n ? make_int2(rp[q.x], rp[q.x + 1]) : make_int2(0, 0);
+}
+
+template <bool ROWQ>
+__device__ __forceinline__ int2 make_entry(int v, const int* __restrict__ rp) {
+    if (ROWQ) return make_int2(rp[v], rp[v + 1]);
+    return make_int2(v, 0);
+}
+
+__device__ __forceinline__ void queue_put(int2* lds, int2* glob, int idx, int2 v) {
     if (idx < kQcap)
         lds[idx] = v;
     else
@@ -94,54 +112,50 @@ __device__ __forceinline__ void queue_put(int* lds, int* glob, int idx, int v) {
 // scope: the row belongs to this block) and appended to the next frontier
 // with one LDS atomic per wave.  reached[b] = nodes found; *ecc_max = largest
 // eccentricity seen.
-template <int VW>
+template <int VW, bool ROWQ>
 __global__ __launch_bounds__(kBfsBlock) void k_bfs_wg(int n, const int* __restrict__ rp,
                                                       const int* __restrict__ ci,
                                                       const int* __restrict__ pivots, int* dist,
-                                                      int* queues, int* reached, int* ecc_max) {
+                                                      int2* queues, int* reached, int* ecc_max) {
     const int b = blockIdx.x;
     int* D = dist + (size_t)b * n;
-    int* ga = queues + (size_t)b * 2 * n;
-    int* gb = ga + n;
-    __shared__ int sqa[kQcap], sqb[kQcap];
+    int2* ga = queues + (size_t)b * 2 * n;
+    int2* gb = ga + n;
+    __shared__ int2 sqa[kQcap], sqb[kQcap];
     __shared__ int s_tail, s_len;
     const int src = pivots[b];
     if (threadIdx.x == 0) {
         D[src] = 0;
-        sqa[0] = src;
+        sqa[0] = make_entry<ROWQ>(src, rp);
         s_len = 1;
         s_tail = 0;
     }
     __syncthreads();
     const int sub = threadIdx.x % VW, grp = threadIdx.x / VW, ngrp = blockDim.x / VW;
-    int* lcur = sqa;
-    int* lnxt = sqb;
-    int* gcur = ga;
-    int* gnxt = gb;
+    int2* lcur = sqa;
+    int2* lnxt = sqb;
+    int2* gcur = ga;
+    int2* gnxt = gb;
     int level = 0, total = 1;
     for (;;) {
         const int len = min(s_len, n);
         if (len == 0) break;
         for (int base = 0; base < len; base += ngrp) {
             int qi = base + grp;
-            int e0 = 0, e1 = 0;
-            if (qi < len) {
-                int u = queue_get(lcur, gcur, qi);
-                if ((unsigned)u < (unsigned)n) {
-                    e0 = rp[u];
-                    e1 = rp[u + 1];
-                }
-            }
-            for (int e = e0 + sub; e < e1; e += VW) {
+            int2 row = make_int2(0, 0);
+            if (qi < len) row = entry_row<ROWQ>(queue_get(lcur, gcur, qi), rp, n);
+            for (int e = row.x + sub; e < row.y; e += VW) {
                 int v = ci[e];
                 bool claim = false;
-                if (wg_load(&D[v]) < 0) {
+                int2 vrow;
+                if ((unsigned)v < (unsigned)n && wg_load(&D[v]) < 0) {
                     int expected = -1;
                     claim = __hip_atomic_compare_exchange_strong(&D[v], &expected, level + 1, __ATOMIC_RELAXED,
                                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if (claim) vrow = make_entry<ROWQ>(v, rp);
                 }
                 int slot = wave_append(claim, &s_tail);
-                if (claim) queue_put(lnxt, gnxt, slot, v);
+                if (claim) queue_put(lnxt, gnxt, slot, vrow);
             }
         }
         __syncthreads();
@@ -149,10 +163,10 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_wg(int n, const int* __restri
             s_len = s_tail;
             s_tail = 0;
         }
-        int* t0 = lcur;
+        int2* t0 = lcur;
         lcur = lnxt;
         lnxt = t0;
-        int* t1 = gcur;
+        int2* t1 = gcur;
         gcur = gnxt;
         gnxt = t1;
         ++level;
@@ -165,22 +179,345 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_wg(int n, const int* __restri
     }
 }
 
+// Ids of the nodes with degree > kHeavyDegree in ascending order: blocks
+// count their range, a single thread scans the counts, blocks write their ids
+// at their offset (ballot compaction keeps the id order inside a block).
+constexpr int kHeavySpan = 4096;  // nodes per block
+
+__global__ __launch_bounds__(256) void k_heavy_count(int n, const int* __restrict__ rp, int* __restrict__ counts) {
+    const int i0 = blockIdx.x * kHeavySpan;
+    int c = 0;
+    for (int i = i0 + threadIdx.x; i < min(n, i0 + kHeavySpan); i += blockDim.x) c += rp[i + 1] - rp[i] > kHeavyDegree;
+    __shared__ int red[256 / kWave];
+    c = block_sum(c, red);
+    if (threadIdx.x == 0) counts[blockIdx.x] = c;
+}
+
+__global__ void k_heavy_scan(int nb, int* __restrict__ counts, int* __restrict__ total) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        int acc = 0;
+        for (int b = 0; b < nb; ++b) {
+            int c = counts[b];
+            counts[b] = acc;
+            acc += c;
+        }
+        total[0] = acc;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_heavy_write(int n, const int* __restrict__ rp, const int* __restrict__ offsets,
+                                                     int* __restrict__ heavy) {
+    __shared__ int s_base;
+    __shared__ int s_wave[256 / kWave];
+    const int i0 = blockIdx.x * kHeavySpan;
+    if (threadIdx.x == 0) s_base = offsets[blockIdx.x];
+    __syncthreads();
+    const int lane = lane_id(), w = threadIdx.x / kWave;
+    for (int c0 = i0; c0 < min(n, i0 + kHeavySpan); c0 += blockDim.x) {
+        const int i = c0 + threadIdx.x;
+        const bool h = i < min(n, i0 + kHeavySpan) && rp[i + 1] - rp[i] > kHeavyDegree;
+        const uint64_t mask = __ballot(h);
+        if (lane == 0) s_wave[w] = __popcll(mask);
+        __syncthreads();
+        int before = s_base;
+        for (int q = 0; q < w; ++q) before += s_wave[q];
+        if (h) heavy[before + mask_rank(mask)] = i;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int tot = 0;
+            for (int q = 0; q < (int)(blockDim.x / kWave); ++q) tot += s_wave[q];
+            s_base += tot;
+        }
+        __syncthreads();
+    }
+}
+
+ssm_status heavy_list(const ssm_csr* g, int** heavy, int32_t* count, hipStream_t s) {
+    const int n = g->n;
+    const int nb = div_up(n, kHeavySpan);
+    *heavy = nullptr;
+    *count = 0;
+    int* buf = nullptr;  // counts[nb], total, ids[n]
+    ssm_status st = dalloc((void**)&buf, sizeof(int) * ((size_t)nb + 1 + n));
+    if (st != SSM_OK) return st;
+    int* counts = buf;
+    int* total = buf + nb;
+    int* ids = total + 1;
+    hipLaunchKernelGGL(k_heavy_count, dim3(nb), dim3(256), 0, s, n, g->row_ptr, counts);
+    hipLaunchKernelGGL(k_heavy_scan, dim3(1), dim3(64), 0, s, nb, counts, total);
+    hipLaunchKernelGGL(k_heavy_write, dim3(nb), dim3(256), 0, s, n, g->row_ptr, counts, ids);
+    hipError_t e = hipGetLastError();
+    int nh = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&nh, total, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) {
+        st = dalloc((void**)heavy, sizeof(int) * (size_t)std::max(nh, 1));
+        if (st != SSM_OK) {
+            (void)hipFree(buf);
+            return st;
+        }
+        if (nh > 0) e = hipMemcpyAsync(*heavy, ids, sizeof(int) * (size_t)nh, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    (void)hipFree(buf);
+    if (e != hipSuccess) {
+        if (*heavy) (void)hipFree(*heavy);
+        *heavy = nullptr;
+        return hip_fail(e, "heavy-node list");
+    }
+    *count = nh;
+    return SSM_OK;
+}
+
+// ---------------------------------------- bit-parallel multi-source BFS
+
+// One bit per pivot: vis[v][w] marks the pivots whose BFS has reached v,
+// cur[v][w] those that reached v at the previous level.  Level L (bottom-up):
+// every node ORs its neighbours' cur words, keeps the bits it has not seen
+// and records dist[t][v] = L for each new bit t.  Efficient when the graph
+// has few levels (hub-heavy graphs); the level loop runs on the host.
+template <int NW>
+__global__ __launch_bounds__(256) void k_msbfs_init(int n, int k, const int* __restrict__ pivots,
+                                                   unsigned long long* __restrict__ vis,
+                                                   unsigned long long* __restrict__ cur, int* __restrict__ dist) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < k; t += gridDim.x * blockDim.x) {
+        const int p = pivots[t];
+        atomicOr(&vis[(size_t)p * NW + t / 64], 1ull << (t % 64));
+        atomicOr(&cur[(size_t)p * NW + t / 64], 1ull << (t % 64));
+        dist[(size_t)t * n + p] = 0;
+    }
+}
+
+template <int NW>
+__global__ __launch_bounds__(256) void k_msbfs_level(int n, int k, int level, const int* __restrict__ rp,
+                                                    const int* __restrict__ ci,
+                                                    unsigned long long* __restrict__ vis,
+                                                    const unsigned long long* __restrict__ cur,
+                                                    unsigned long long* __restrict__ nxt, int* __restrict__ dist,
+                                                    unsigned long long* __restrict__ settled) {
+    const int lane = lane_id();
+    unsigned long long found = 0;
+    for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        const int v = base + threadIdx.x;
+        unsigned long long nw[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) nw[w] = 0;
+        if (v < n) {
+            unsigned long long seen[NW], acc[NW];
+            bool open = false;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const int bits = min(64, k - 64 * w);
+                const unsigned long long full = bits == 64 ? ~0ull : ((1ull << bits) - 1);
+                seen[w] = vis[(size_t)v * NW + w];
+                acc[w] = 0;
+                open |= seen[w] != full;
+            }
+            if (open && rp[v + 1] - rp[v] > kHeavyDegree) open = false;  // k_msbfs_heavy's node
+            if (open) {
+                for (int e = rp[v]; e < rp[v + 1]; ++e) {
+                    const int u = ci[e];
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) acc[w] |= cur[(size_t)u * NW + w];
+                }
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    nw[w] = acc[w] & ~seen[w];
+                    if (nw[w]) vis[(size_t)v * NW + w] = seen[w] | nw[w];
+                }
+            }
+            if (rp[v + 1] - rp[v] <= kHeavyDegree) {
+#pragma unroll
+                for (int w = 0; w < NW; ++w) nxt[(size_t)v * NW + w] = nw[w];
+            }
+        }
+        // write distances pivot by pivot: loop over the bits set anywhere in
+        // the wave, so lanes of a wave store consecutive nodes of one row
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            found += __popcll(nw[w]);
+            unsigned long long wave_bits = nw[w];
+            for (int off = 32; off > 0; off >>= 1) wave_bits |= __shfl_xor(wave_bits, off);
+            while (wave_bits) {
+                const int b = __ffsll(wave_bits) - 1;
+                wave_bits &= wave_bits - 1;
+                if ((nw[w] >> b) & 1ull) dist[(size_t)(64 * w + b) * n + v] = level;
+            }
+        }
+    }
+    found = wave_sum(found);
+    if (found && lane == 0) atomicAdd(settled, found);
+}
+
+// The same level for the high-degree nodes, one wavefront per node: lanes
+// OR strided slices of the neighbour list, a butterfly combines them.
+template <int NW>
+__global__ __launch_bounds__(256) void k_msbfs_heavy(int n, int k, int level, int nheavy,
+                                                    const int* __restrict__ heavy, const int* __restrict__ rp,
+                                                    const int* __restrict__ ci, unsigned long long* __restrict__ vis,
+                                                    const unsigned long long* __restrict__ cur,
+                                                    unsigned long long* __restrict__ nxt, int* __restrict__ dist,
+                                                    unsigned long long* __restrict__ settled) {
+    const int lane = lane_id();
+    unsigned long long found = 0;
+    for (int h = (blockIdx.x * blockDim.x + threadIdx.x) / kWave; h < nheavy;
+         h += gridDim.x * blockDim.x / kWave) {
+        const int v = heavy[h];
+        unsigned long long seen[NW], acc[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            seen[w] = vis[(size_t)v * NW + w];
+            acc[w] = 0;
+        }
+        for (int e = rp[v] + lane; e < rp[v + 1]; e += kWave) {
+            const int u = ci[e];
+#pragma unroll
+            for (int w = 0; w < NW; ++w) acc[w] |= cur[(size_t)u * NW + w];
+        }
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            for (int off = 32; off > 0; off >>= 1) acc[w] |= __shfl_xor(acc[w], off);
+            const int bits = min(64, k - 64 * w);
+            const unsigned long long full = bits == 64 ? ~0ull : ((1ull << bits) - 1);
+            const unsigned long long nw = acc[w] & ~seen[w] & full;
+            if (lane == 0) {
+                nxt[(size_t)v * NW + w] = nw;
+                if (nw) vis[(size_t)v * NW + w] = seen[w] | nw;
+                found += __popcll(nw);
+            }
+            if ((nw >> lane) & 1ull) dist[(size_t)(64 * w + lane) * n + v] = level;
+        }
+    }
+    found = wave_sum(found);
+    if (found && lane == 0) atomicAdd(settled, found);
+}
+
+template <int NW>
+static ssm_status msbfs(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dist, int budget,
+                        bool* done, int32_t* levels_out, hipStream_t s) {
+    const int n = g->n;
+    *done = false;
+    unsigned long long* buf = nullptr;
+    ssm_status st = dalloc((void**)&buf, sizeof(unsigned long long) * (3 * (size_t)n * NW + 8));
+    if (st != SSM_OK) return st;
+    unsigned long long* vis = buf;
+    unsigned long long* cur = vis + (size_t)n * NW;
+    unsigned long long* nxt = cur + (size_t)n * NW;
+    unsigned long long* settled = nxt + (size_t)n * NW;  // [0] this level, [1] all levels
+    hipError_t e = hipMemsetAsync(buf, 0, sizeof(unsigned long long) * 2 * (size_t)n * NW, s);
+    if (e == hipSuccess) e = hipMemsetAsync(dist, 0xff, sizeof(int) * (size_t)k * n, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_msbfs_init<NW>, dim3(div_up(k, 256)), dim3(256), 0, s, n, k, pivots, vis, cur, dist);
+        e = hipGetLastError();
+    }
+    int* heavy = nullptr;
+    int32_t nheavy = 0;
+    if (e == hipSuccess) {
+        st = heavy_list(g, &heavy, &nheavy, s);
+        if (st != SSM_OK) {
+            (void)hipFree(buf);
+            return st;
+        }
+    }
+    const int grid = std::min(div_up(n, 256), num_cus() * 8);
+    const double pairs = (double)k * n;
+    double total = k;  // the pivots themselves
+    int level = 0;
+    while (e == hipSuccess && level < budget) {
+        ++level;
+        unsigned long long h = 0;
+        e = hipMemsetAsync(settled, 0, sizeof(unsigned long long), s);
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(k_msbfs_level<NW>, dim3(grid), dim3(256), 0, s, n, k, level, g->row_ptr, g->col_idx, vis,
+                           cur, nxt, dist, settled);
+        if (nheavy > 0)
+            hipLaunchKernelGGL(k_msbfs_heavy<NW>, dim3(std::min(div_up(nheavy, 4), 4096)), dim3(256), 0, s, n, k,
+                               level, nheavy, heavy, g->row_ptr, g->col_idx, vis, cur, nxt, dist, settled);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(&h, settled, sizeof(h), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) break;
+        std::swap(cur, nxt);
+        total += (double)h;
+        if (h == 0) {
+            *done = true;
+            break;
+        }
+        // a graph with many levels settles slowly: hand it to the per-workgroup BFS early
+        if (level >= 3 && total < 0.2 * pairs) break;
+    }
+    (void)hipFree(buf);
+    if (heavy) (void)hipFree(heavy);
+    if (e != hipSuccess) return hip_fail(e, "bit-parallel BFS");
+    *levels_out = level - 1;  // the last level found nothing
+    return SSM_OK;
+}
+
+// Checks every row of dist for an unreached node (-1); counts into *bad.
+__global__ void k_count_unreached(long long total, const int* __restrict__ dist, int* bad) {
+    int c = 0;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total;
+         q += (long long)gridDim.x * blockDim.x)
+        c += dist[q] < 0;
+    c = wave_sum(c);
+    if (c && lane_id() == 0) atomicAdd(bad, c);
+}
+
 template <int VW>
 static void launch_bfs_wg(int blocks, hipStream_t s, int n, const int* rp, const int* ci,
-                          const int* pivots, int* dist, int* queues, int* reached, int* ecc) {
-    hipLaunchKernelGGL(k_bfs_wg<VW>, dim3(blocks), dim3(kBfsBlock), 0, s, n, rp, ci, pivots, dist,
-                       queues, reached, ecc);
+                          const int* pivots, int* dist, int2* queues, int* reached, int* ecc) {
+    if (env_int("SSM_BFS_ROWQ") != 2)  // row bounds in the queue (2 = node ids; tuning)
+        hipLaunchKernelGGL((k_bfs_wg<VW, true>), dim3(blocks), dim3(kBfsBlock), 0, s, n, rp, ci, pivots, dist,
+                           queues, reached, ecc);
+    else
+        hipLaunchKernelGGL((k_bfs_wg<VW, false>), dim3(blocks), dim3(kBfsBlock), 0, s, n, rp, ci, pivots, dist,
+                           queues, reached, ecc);
 }
 
 ssm_status mssp(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dist,
                 int32_t* dmax_out_host, hipStream_t s) {
     const int n = g->n;
+    // Few levels (hub-heavy graphs): bit-parallel BFS over all pivots at once.
+    // It gives up after `budget` levels, and the per-workgroup BFS runs instead.
+    const int budget = env_int("SSM_MSBFS_BUDGET") > 0 ? env_int("SSM_MSBFS_BUDGET") : 24;
+    if (k <= 1024 && env_int("SSM_MSBFS_OFF") == 0) {
+        bool done = false;
+        int32_t levels = 0;
+        ssm_status st;
+        const int nw = div_up(k, 64);
+        if (nw <= 1) st = msbfs<1>(g, k, pivots, dist, budget, &done, &levels, s);
+        else if (nw <= 2) st = msbfs<2>(g, k, pivots, dist, budget, &done, &levels, s);
+        else if (nw <= 4) st = msbfs<4>(g, k, pivots, dist, budget, &done, &levels, s);
+        else if (nw <= 8) st = msbfs<8>(g, k, pivots, dist, budget, &done, &levels, s);
+        else st = msbfs<16>(g, k, pivots, dist, budget, &done, &levels, s);
+        if (st != SSM_OK) return st;
+        if (done) {
+            int* bad = nullptr;
+            st = dalloc((void**)&bad, sizeof(int));
+            if (st != SSM_OK) return st;
+            int hbad = 0;
+            hipError_t e = hipMemsetAsync(bad, 0, sizeof(int), s);
+            if (e == hipSuccess) {
+                long long total = (long long)k * n;
+                hipLaunchKernelGGL(k_count_unreached, dim3((int)std::min<long long>((total + 255) / 256, 4096)),
+                                   dim3(256), 0, s, total, dist, bad);
+                e = hipGetLastError();
+            }
+            if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            (void)hipFree(bad);
+            if (e != hipSuccess) return hip_fail(e, "bit-parallel BFS check");
+            if (hbad) return fail(SSM_E_DISCONNECTED, "graph is not connected (a BFS missed nodes)");
+            *dmax_out_host = levels;
+            return SSM_OK;
+        }
+    }
     // Sources run in batches so that the frontier queues stay bounded.
-    const long long qcap = 1LL << 29;  // ints of queue memory (2 GiB)
+    const long long qcap = 1LL << 31;  // queue entries (16 GiB)
     int batch = (int)std::max<long long>(1, std::min<long long>(k, qcap / (2LL * n)));
-    int* queues = nullptr;
+    int2* queues = nullptr;
     int* aux = nullptr;  // reached[k], ecc
-    ssm_status st = dalloc((void**)&queues, sizeof(int) * 2 * (size_t)n * batch);
+    ssm_status st = dalloc((void**)&queues, sizeof(int2) * 2 * (size_t)n * batch);
     if (st != SSM_OK) return st;
     st = dalloc((void**)&aux, sizeof(int) * ((size_t)k + 1));
     if (st != SSM_OK) {
@@ -189,7 +526,7 @@ ssm_status mssp(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dis
     }
     hipError_t e = hipMemsetAsync(dist, 0xff, sizeof(int) * (size_t)k * n, s);
     if (e == hipSuccess) e = hipMemsetAsync(aux, 0, sizeof(int) * ((size_t)k + 1), s);
-    if (e == hipSuccess) e = hipMemsetAsync(queues, 0, sizeof(int) * 2 * (size_t)n * batch, s);
+    if (e == hipSuccess) e = hipMemsetAsync(queues, 0, sizeof(int2) * 2 * (size_t)n * batch, s);
     int vw = virtual_warp(g);
     for (int b0 = 0; b0 < k && e == hipSuccess; b0 += batch) {
         int nb = std::min(batch, k - b0);
@@ -410,16 +747,16 @@ __global__ __launch_bounds__(kSelBlock) void k_select_all(int n, const int* __re
 // All k pivots in one workgroup (no grid barrier): the same pruned BFS and
 // argmax as k_select_all, with the frontier in LDS (global overflow), LDS
 // counters and workgroup-scope atomics on m.
-template <int VW>
+template <int VW, bool ROWQ, int PRE>
 __global__ __launch_bounds__(kBfsBlock) void k_select_wg(int n, const int* __restrict__ rp,
                                                          const int* __restrict__ ci, int k, int first,
-                                                         int* pivots, int* m, int* queues, int* status) {
-    __shared__ int sqa[kQcap], sqb[kQcap];
+                                                         int* pivots, int* m, int2* queues, int* status) {
+    __shared__ int2 sqa[kQcap], sqb[kQcap];
     __shared__ int s_tail, s_len, s_src;
     __shared__ unsigned long long s_red[kBfsBlock / kWave];
     const int sub = threadIdx.x % VW, grp = threadIdx.x / VW, ngrp = blockDim.x / VW;
-    int* ga = queues;
-    int* gb = queues + n;
+    int2* ga = queues;
+    int2* gb = queues + n;
     if (threadIdx.x == 0) s_src = first;
     __syncthreads();
     for (int t = 0; t < k; ++t) {
@@ -427,15 +764,15 @@ __global__ __launch_bounds__(kBfsBlock) void k_select_wg(int n, const int* __res
         if (threadIdx.x == 0) {
             pivots[t] = src;
             __hip_atomic_store(&m[src], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            sqa[0] = src;
+            sqa[0] = make_entry<ROWQ>(src, rp);
             s_len = 1;
             s_tail = 0;
         }
         __syncthreads();
-        int* lcur = sqa;
-        int* lnxt = sqb;
-        int* gcur = ga;
-        int* gnxt = gb;
+        int2* lcur = sqa;
+        int2* lnxt = sqb;
+        int2* gcur = ga;
+        int2* gnxt = gb;
         int level = 0;
         for (;;) {
             const int len = min(s_len, n);
@@ -443,21 +780,21 @@ __global__ __launch_bounds__(kBfsBlock) void k_select_wg(int n, const int* __res
             const int dv = level + 1;
             for (int base = 0; base < len; base += ngrp) {
                 int qi = base + grp;
-                int e0 = 0, e1 = 0;
-                if (qi < len) {
-                    int u = queue_get(lcur, gcur, qi);
-                    if ((unsigned)u < (unsigned)n) {
-                        e0 = rp[u];
-                        e1 = rp[u + 1];
-                    }
-                }
-                for (int e = e0 + sub; e < e1; e += VW) {
+                int2 row = make_int2(0, 0);
+                if (qi < len) row = entry_row<ROWQ>(queue_get(lcur, gcur, qi), rp, n);
+                for (int e = row.x + sub; e < row.y; e += VW) {
                     int v = ci[e];
                     bool push = false;
-                    if (wg_load(&m[v]) > dv)  // m only decreases: a stale value is only larger
-                        push = __hip_atomic_fetch_min(&m[v], dv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) > dv;
+                    int2 vrow;
+                    if ((unsigned)v < (unsigned)n) {
+                        // precheck (m only decreases, so a stale value is only larger)
+                        const bool try_it = PRE == 0 ? true : PRE == 1 ? m[v] > dv : wg_load(&m[v]) > dv;
+                        if (try_it)
+                            push = __hip_atomic_fetch_min(&m[v], dv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) > dv;
+                        if (push) vrow = make_entry<ROWQ>(v, rp);
+                    }
                     int slot = wave_append(push, &s_tail);
-                    if (push) queue_put(lnxt, gnxt, slot, v);
+                    if (push) queue_put(lnxt, gnxt, slot, vrow);
                 }
             }
             __syncthreads();
@@ -465,10 +802,10 @@ __global__ __launch_bounds__(kBfsBlock) void k_select_wg(int n, const int* __res
                 s_len = s_tail;
                 s_tail = 0;
             }
-            int* t0 = lcur;
+            int2* t0 = lcur;
             lcur = lnxt;
             lnxt = t0;
-            int* t1 = gcur;
+            int2* t1 = gcur;
             gcur = gnxt;
             gnxt = t1;
             ++level;
@@ -489,6 +826,43 @@ __global__ __launch_bounds__(kBfsBlock) void k_select_wg(int n, const int* __res
         __syncthreads();
         if (t == 0 && (int)(best >> 32) == kInf) break;  // disconnected (uniform)
     }
+}
+
+template <int VW, bool ROWQ, int PRE>
+static void launch_select_wg_t(hipStream_t s, int n, const int* rp, const int* ci, int k, int first, int* pivots,
+                               int* m, int2* q, int* status) {
+    hipLaunchKernelGGL((k_select_wg<VW, ROWQ, PRE>), dim3(1), dim3(kBfsBlock), 0, s, n, rp, ci, k, first, pivots, m, q,
+                       status);
+}
+
+template <int VW>
+static void launch_select_wg_v(hipStream_t s, int n, const int* rp, const int* ci, int k, int first, int* pivots,
+                               int* m, int2* q, int* status) {
+    // queue style and relaxation precheck: defaults measured on MI355X; the
+    // environment overrides them for tuning
+    const int rowq = env_int("SSM_SELECT_ROWQ"), pre = env_int("SSM_SELECT_PRE");
+    if (rowq != 2) {  // row bounds in the queue (2 = node ids; tuning)
+        if (pre == 1) launch_select_wg_t<VW, true, 1>(s, n, rp, ci, k, first, pivots, m, q, status);
+        else if (pre == 3) launch_select_wg_t<VW, true, 0>(s, n, rp, ci, k, first, pivots, m, q, status);
+        else launch_select_wg_t<VW, true, 2>(s, n, rp, ci, k, first, pivots, m, q, status);
+    } else {
+        if (pre == 2) launch_select_wg_t<VW, false, 2>(s, n, rp, ci, k, first, pivots, m, q, status);
+        else if (pre == 3) launch_select_wg_t<VW, false, 0>(s, n, rp, ci, k, first, pivots, m, q, status);
+        else launch_select_wg_t<VW, false, 1>(s, n, rp, ci, k, first, pivots, m, q, status);
+    }
+}
+
+static hipError_t launch_select_wg(int vw, hipStream_t s, int n, const int* rp, const int* ci, int k, int first,
+                                   int* pivots, int* m, int2* q, int* status) {
+    switch (vw) {
+        case 2: launch_select_wg_v<2>(s, n, rp, ci, k, first, pivots, m, q, status); break;
+        case 4: launch_select_wg_v<4>(s, n, rp, ci, k, first, pivots, m, q, status); break;
+        case 8: launch_select_wg_v<8>(s, n, rp, ci, k, first, pivots, m, q, status); break;
+        case 16: launch_select_wg_v<16>(s, n, rp, ci, k, first, pivots, m, q, status); break;
+        case 32: launch_select_wg_v<32>(s, n, rp, ci, k, first, pivots, m, q, status); break;
+        default: launch_select_wg_v<64>(s, n, rp, ci, k, first, pivots, m, q, status); break;
+    }
+    return hipGetLastError();
 }
 
 template <int VW>
@@ -542,7 +916,9 @@ ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pi
     // ones on up to one block per CU.
     int blocks = std::max(1, std::min(std::min(maxb, num_cus()), div_up(n, 8192)));
     if (env_int("SSM_SELECT_BLOCKS") > 0) blocks = std::min(maxb, env_int("SSM_SELECT_BLOCKS"));
-    size_t ints = 4 * (size_t)n + 8;
+    // m[n], vis[n], queue area (4n ints: two int queues of n, or two int2
+    // queues of n for the one-workgroup kernel), control words
+    size_t ints = 6 * (size_t)n + 8;
     int* ws = nullptr;
     unsigned long long* keys = nullptr;
     ssm_status st = dalloc((void**)&ws, sizeof(int) * ints);
@@ -556,29 +932,21 @@ ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pi
     int* vis = ws + n;
     int* qa = ws + 2 * (size_t)n;
     int* qb = ws + 3 * (size_t)n;
-    int* ctl = ws + 4 * (size_t)n;
+    int* ctl = ws + 6 * (size_t)n;
     int* status = ctl + 4;
     hipError_t e = hipSuccess;
     hipLaunchKernelGGL(k_fill_int, dim3(std::min(div_up(n, 256), 4096)), dim3(256), 0, s, m, kInf, (long long)n);
     hipLaunchKernelGGL(k_fill_int, dim3(std::min(div_up(n, 256), 4096)), dim3(256), 0, s, vis, -1, (long long)n);
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, ctl, 0, (long long)8);
-    hipLaunchKernelGGL(k_fill_int, dim3(std::min(div_up(2 * (long long)n, 256), 4096)), dim3(256), 0, s, qa, 0,
-                       2 * (long long)n);
+    hipLaunchKernelGGL(k_fill_int, dim3(std::min(div_up(4 * (long long)n, 256), 4096)), dim3(256), 0, s, qa, 0,
+                       4 * (long long)n);
     e = hipGetLastError();
     // Mode: one workgroup (no grid barrier) unless the frontiers are large.
     int mode = env_int("SSM_SELECT_MODE");  // 1 = one workgroup, 2 = cooperative grid, 3 = per pivot
     if (mode < 1 || mode > 3) mode = (long long)n <= (1LL << 18) ? 1 : 2;
     const bool per_pivot = mode == 3;
     if (mode == 1 && e == hipSuccess) {
-        switch (vw) {
-            case 2: hipLaunchKernelGGL(k_select_wg<2>, dim3(1), dim3(kBfsBlock), 0, s, n, g->row_ptr, g->col_idx, k, first, pivots, m, qa, status); break;
-            case 4: hipLaunchKernelGGL(k_select_wg<4>, dim3(1), dim3(kBfsBlock), 0, s, n, g->row_ptr, g->col_idx, k, first, pivots, m, qa, status); break;
-            case 8: hipLaunchKernelGGL(k_select_wg<8>, dim3(1), dim3(kBfsBlock), 0, s, n, g->row_ptr, g->col_idx, k, first, pivots, m, qa, status); break;
-            case 16: hipLaunchKernelGGL(k_select_wg<16>, dim3(1), dim3(kBfsBlock), 0, s, n, g->row_ptr, g->col_idx, k, first, pivots, m, qa, status); break;
-            case 32: hipLaunchKernelGGL(k_select_wg<32>, dim3(1), dim3(kBfsBlock), 0, s, n, g->row_ptr, g->col_idx, k, first, pivots, m, qa, status); break;
-            default: hipLaunchKernelGGL(k_select_wg<64>, dim3(1), dim3(kBfsBlock), 0, s, n, g->row_ptr, g->col_idx, k, first, pivots, m, qa, status); break;
-        }
-        e = hipGetLastError();
+        e = launch_select_wg(vw, s, n, g->row_ptr, g->col_idx, k, first, pivots, m, (int2*)qa, status);
     }
     if (mode == 2 && e == hipSuccess) {
         switch (vw) {
@@ -613,6 +981,7 @@ ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pi
 // ---------------------------------------------------------------- regions
 
 constexpr int kMaxCand = 4;
+constexpr int kRegOneWgMax = 16384;  // tied nodes resolved by one workgroup
 
 // Per node: delta = min_t dist[t][i]; the candidates (ranks at that
 // distance, ascending, the first kMaxCand kept; cand.w = count).  A node with
@@ -683,11 +1052,45 @@ __global__ void k_reg_scatter(int n, const int* __restrict__ delta, const int4* 
     }
 }
 
-// Level-synchronous tie resolution in one workgroup.  cum[t] = region size
-// from all levels below l; at level l the snapshot is cum[t] + U[t][l] (the
-// single-candidate joins of level l); every tied node of level l takes the
-// candidate with the smallest (snapshot, rank); then cum absorbs level l.
-// The result does not depend on the order of nodes inside a level.
+// Choice of a tied node i at level l: the candidate t with the smallest
+// (key(t), t).  cand holds the first kMaxCand - 1 candidates and the count;
+// with exactly kMaxCand candidates the last one is found by a scan from the
+// third, with more every rank is scanned.
+template <typename Key>
+__device__ __forceinline__ int reg_pick(int n, int k, int l, int i, int4 c, const int* __restrict__ dist, Key key) {
+    int pick = -1;
+    long long pkey = 0;
+    auto consider = [&](int t) {
+        long long kk = ((long long)key(t) << 32) | t;
+        if (pick < 0 || kk < pkey) {
+            pick = t;
+            pkey = kk;
+        }
+    };
+    if (c.w <= kMaxCand) {
+        consider(c.x);
+        consider(c.y);
+        if (c.w >= 3) consider(c.z);
+        if (c.w == kMaxCand) {
+            for (int t = c.z + 1; t < k; ++t)
+                if (dist[(size_t)t * n + i] == l) {
+                    consider(t);
+                    break;
+                }
+        }
+    } else {
+        for (int t = 0; t < k; ++t)
+            if (dist[(size_t)t * n + i] == l) consider(t);
+    }
+    return pick;
+}
+
+// Level-synchronous tie resolution in one workgroup (few tied nodes).
+// cum[t] = region size from all levels below l; at level l the snapshot is
+// cum[t] + U[t][l] (the single-candidate joins of level l); every tied node
+// of level l takes the candidate with the smallest (snapshot, rank); then cum
+// absorbs level l.  The result does not depend on the order of nodes inside
+// a level.
 __global__ __launch_bounds__(1024) void k_reg_resolve(int n, int k, int L, const int* __restrict__ dist,
                                                       const int* __restrict__ U,
                                                       const int* __restrict__ tstart,
@@ -702,37 +1105,9 @@ __global__ __launch_bounds__(1024) void k_reg_resolve(int n, int k, int L, const
     for (int l = 0; l < L; ++l) {
         const int a = tstart[l], b = tstart[l + 1];
         for (int q = a + threadIdx.x; q < b; q += blockDim.x) {
-            int i = list[q];
-            int4 c = cand[i];
-            int pick = -1;
-            long long pkey = 0;
-            if (c.w <= kMaxCand) {
-                int cs[kMaxCand] = {c.x, c.y, c.z, -1};
-                if (c.w == kMaxCand) {  // fourth candidate was not stored: find it
-                    for (int t = c.z + 1; t < k; ++t)
-                        if (dist[(size_t)t * n + i] == l) {
-                            cs[3] = t;
-                            break;
-                        }
-                }
-                for (int j = 0; j < c.w; ++j) {
-                    int t = cs[j];
-                    long long key = ((long long)(cum[t] + U[(size_t)t * L + l]) << 32) | t;
-                    if (pick < 0 || key < pkey) {
-                        pick = t;
-                        pkey = key;
-                    }
-                }
-            } else {
-                for (int t = 0; t < k; ++t) {
-                    if (dist[(size_t)t * n + i] != l) continue;
-                    long long key = ((long long)(cum[t] + U[(size_t)t * L + l]) << 32) | t;
-                    if (pick < 0 || key < pkey) {
-                        pick = t;
-                        pkey = key;
-                    }
-                }
-            }
+            const int i = list[q];
+            const int pick = reg_pick(n, k, l, i, cand[i], dist,
+                                      [&](int t) { return cum[t] + U[(size_t)t * L + l]; });
             region[i] = pick;
             atomicAdd(&Tl[pick], 1);
         }
@@ -743,6 +1118,91 @@ __global__ __launch_bounds__(1024) void k_reg_resolve(int n, int k, int L, const
         }
         __syncthreads();
     }
+}
+
+// Inclusive prefix of U over levels, in place: U[t][l] becomes the number of
+// single-candidate nodes of region t at levels <= l.
+__global__ void k_reg_ucum(int k, int L, int* __restrict__ U) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= k) return;
+    int acc = 0;
+    for (int l = 0; l < L; ++l) {
+        acc += U[(size_t)t * L + l];
+        U[(size_t)t * L + l] = acc;
+    }
+}
+
+constexpr int kRegLdsMaxK = 8192;  // keys and counts of up to this many pivots in LDS
+
+// One tied level l over many workgroups (the j-th level that has ties).
+// With Ucum the inclusive level prefix of U, Tc_prev[t] the tied joins over
+// the tied levels before the (j-1)-th and Tj[j-1][t] those of the (j-1)-th,
+// the snapshot of level l is Ucum[t][l] + Tc_prev[t] + Tj[j-1][t]; workgroup
+// 0 stores Tc_prev + Tj[j-1] into Tc_next for the next tied level (double
+// buffer: launches on one stream run in order).  FULL scans every node for
+// delta == l (coalesced distance reads when most nodes tie); otherwise the
+// level's slice [a, b) of the tied-node list is processed.
+template <bool FULL, bool LDS>
+__global__ __launch_bounds__(256) void k_reg_level(int n, int k, int L, int l, int j, const int* __restrict__ dist,
+                                                   const int* __restrict__ delta, const int4* __restrict__ cand,
+                                                   const int* __restrict__ Ucum, const int* __restrict__ list, int a,
+                                                   int b, const int* __restrict__ Tc_prev, int* __restrict__ Tc_next,
+                                                   int* __restrict__ Tj, int* __restrict__ region) {
+    extern __shared__ int sm[];  // LDS: key[k], cnt[k]
+    int* key = sm;
+    int* cnt = sm + k;
+    const int* Tlast = j > 0 ? Tj + (size_t)(j - 1) * k : nullptr;
+    int* Tcur = Tj + (size_t)j * k;
+    for (int t = threadIdx.x; t < k; t += blockDim.x) {
+        const int c = Tc_prev[t] + (Tlast ? Tlast[t] : 0);
+        if (blockIdx.x == 0) Tc_next[t] = c;
+        if (LDS) {
+            key[t] = Ucum[(size_t)t * L + l] + c;
+            cnt[t] = 0;
+        }
+    }
+    __syncthreads();
+    auto keyf = [&](int t) {
+        if (LDS) return key[t];
+        return Ucum[(size_t)t * L + l] + Tc_prev[t] + (Tlast ? Tlast[t] : 0);
+    };
+    auto one = [&](int i, int4 c) {
+        const int pick = reg_pick(n, k, l, i, c, dist, keyf);
+        region[i] = pick;
+        if (LDS)
+            atomicAdd(&cnt[pick], 1);
+        else
+            atomicAdd(&Tcur[pick], 1);
+    };
+    if (FULL) {
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+            if (delta[i] != l) continue;
+            const int4 c = cand[i];
+            if (c.w > 1) one(i, c);
+        }
+    } else {
+        for (int q = a + blockIdx.x * blockDim.x + threadIdx.x; q < b; q += gridDim.x * blockDim.x) {
+            const int i = list[q];
+            one(i, cand[i]);
+        }
+    }
+    if (LDS) {
+        __syncthreads();
+        for (int t = threadIdx.x; t < k; t += blockDim.x)
+            if (cnt[t]) atomicAdd(&Tcur[t], cnt[t]);
+    }
+}
+
+template <bool FULL>
+static void launch_reg_level(int blocks, hipStream_t s, int n, int k, int L, int l, int j, const int* dist,
+                             const int* delta, const int4* cand, const int* Ucum, const int* list, int a, int b,
+                             const int* Tc_prev, int* Tc_next, int* Tj, int* region) {
+    if (k <= kRegLdsMaxK)
+        hipLaunchKernelGGL((k_reg_level<FULL, true>), dim3(blocks), dim3(256), sizeof(int) * 2 * (size_t)k, s, n, k,
+                           L, l, j, dist, delta, cand, Ucum, list, a, b, Tc_prev, Tc_next, Tj, region);
+    else
+        hipLaunchKernelGGL((k_reg_level<FULL, false>), dim3(blocks), dim3(256), 0, s, n, k, L, l, j, dist, delta,
+                           cand, Ucum, list, a, b, Tc_prev, Tc_next, Tj, region);
 }
 
 ssm_status regions(int32_t n, int32_t k, const int32_t* dist, int32_t* delta, int32_t* region,
@@ -788,14 +1248,62 @@ ssm_status regions(int32_t n, int32_t k, const int32_t* dist, int32_t* delta, in
         int* list = cursor + L;
         int* cum = list + haux[1];
         int* Tl = cum + k;
+        // Few tied nodes: one workgroup walks the levels.  Many: one
+        // multi-workgroup launch per level that has ties (tuning override
+        // SSM_REGION_MODE: 1 one workgroup, 2 per level).
+        const int mode = env_int("SSM_REGION_MODE");
+        const bool per_level = mode == 2 || (mode != 1 && haux[1] > kRegOneWgMax);
+        std::vector<int> hstart(L + 1);
         e = hipMemsetAsync(ws, 0, sizeof(int) * ((size_t)k * L + L), s);
         if (e == hipSuccess) {
             hipLaunchKernelGGL(k_reg_hist, dim3(grid), dim3(256), 0, s, n, L, delta, cand, U, tcount);
             hipLaunchKernelGGL(k_reg_prefix, dim3(1), dim3(64), 0, s, L, tcount, tstart, cursor);
             hipLaunchKernelGGL(k_reg_scatter, dim3(grid), dim3(256), 0, s, n, delta, cand, cursor, list);
-            hipLaunchKernelGGL(k_reg_resolve, dim3(1), dim3(1024), 0, s, n, k, L, dist, U, tstart, list,
-                               cand, region, cum, Tl);
+            if (!per_level)
+                hipLaunchKernelGGL(k_reg_resolve, dim3(1), dim3(1024), 0, s, n, k, L, dist, U, tstart, list,
+                                   cand, region, cum, Tl);
             e = hipGetLastError();
+        }
+        if (e == hipSuccess && per_level) {
+            e = hipMemcpyAsync(hstart.data(), tstart, sizeof(int) * (L + 1), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            int nlev = 0;
+            for (int l = 0; l < L; ++l) nlev += hstart[l + 1] > hstart[l];
+            // Tc[2][k] double buffer, Tj[nlev][k]
+            int* ws2 = nullptr;
+            if (e == hipSuccess) {
+                st = dalloc((void**)&ws2, sizeof(int) * (size_t)k * (2 + nlev));
+                if (st != SSM_OK) {
+                    (void)hipFree(ws);
+                    (void)hipFree(cand);
+                    (void)hipFree(aux);
+                    return st;
+                }
+                e = hipMemsetAsync(ws2, 0, sizeof(int) * (size_t)k * (2 + nlev), s);
+            }
+            if (e == hipSuccess) {
+                hipLaunchKernelGGL(k_reg_ucum, dim3(div_up(k, 256)), dim3(256), 0, s, k, L, U);
+                int* Tc[2] = {ws2, ws2 + k};
+                int* Tj = ws2 + 2 * (size_t)k;
+                const int full_grid = std::min(div_up(n, 256), 4 * num_cus());
+                int j = 0;
+                for (int l = 0; l < L; ++l) {
+                    const int a = hstart[l], b = hstart[l + 1];
+                    if (b == a) continue;
+                    const int* prev = Tc[j & 1];
+                    int* next = Tc[(j + 1) & 1];
+                    if ((long long)(b - a) * 16 >= n)
+                        launch_reg_level<true>(full_grid, s, n, k, L, l, j, dist, delta, cand, U, list, a, b, prev,
+                                               next, Tj, region);
+                    else
+                        launch_reg_level<false>(std::min(div_up(b - a, 256), 4 * num_cus()), s, n, k, L, l, j, dist,
+                                                delta, cand, U, list, a, b, prev, next, Tj, region);
+                    ++j;
+                }
+                e = hipGetLastError();
+            }
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (ws2) (void)hipFree(ws2);
         }
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         (void)hipFree(ws);

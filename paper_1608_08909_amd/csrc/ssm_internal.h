@@ -34,9 +34,16 @@ struct ssm_terms {
     double* eig = nullptr;      // [2k + 2] V (k x 2) then lambda (2)
     double* gram = nullptr;     // [k][k] C^T C of the last PivotMDS
     int32_t* eig_iters = nullptr;  // [1]
+    int32_t nheavy = 0;            // nodes whose degree exceeds kHeavyDegree
+    int32_t* heavy = nullptr;      // [nheavy] their ids, ascending
+    float2* heavy_sum = nullptr;   // [nheavy] neighbour displacement sums (FP32 sweep scratch)
 };
 
 namespace ssm {
+
+// Nodes with more neighbours than this get their neighbour terms summed by a
+// whole wavefront in the FP32 sweep.
+constexpr int kHeavyDegree = 64;
 
 // Thread-local error reporting.
 ssm_status fail(ssm_status st, const std::string& msg);
@@ -61,6 +68,9 @@ ssm_status mssp(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dis
                 int32_t* dmax_out_host, hipStream_t s);
 ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pivots,
                          hipStream_t s);
+// Ids of the nodes with degree > kHeavyDegree, ascending; *heavy is a new
+// device allocation of max(count, 1) ints owned by the caller.  Synchronizes.
+ssm_status heavy_list(const ssm_csr* g, int** heavy, int32_t* count, hipStream_t s);
 ssm_status regions(int32_t n, int32_t k, const int32_t* dist, int32_t* delta, int32_t* region,
                    hipStream_t s);
 

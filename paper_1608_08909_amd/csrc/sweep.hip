@@ -2,6 +2,7 @@
 // Jacobi order, and the stress of Eq. 3 and Eq. 1.
 #include <float.h>
 #include <math.h>
+#include <stdlib.h>
 
 #include <vector>
 
@@ -115,17 +116,58 @@ enum WeightMode { kTableLds = 0, kHistLds = 1, kTableGlobal = 2 };
 // sums the packed distance words b = w, w + WAVES, ... (one coalesced 16-byte
 // load per lane covers VEC pivots; every lane of the wave reads the same
 // pivot, so its coordinates and table row come from LDS as broadcasts);
-// wave 0 also sums the neighbour terms in CSR order.  The WAVES partials are
+// the last wave (fewest words) also sums the neighbour terms in CSR order.  The WAVES partials are
 // added in a fixed order.  Weights: kTableLds stages (w', w'd) for every
 // (pivot, distance); kHistLds stages the region histograms H and (1/d^2, 1/d)
 // and forms w' = H[t][min(d/2, delta_max)] / d^2; kTableGlobal reads the table
 // from memory.  1/r is the hardware reciprocal square root of r^2 + 1e-30.
+// Neighbour displacement sums of the high-degree nodes, one wavefront each:
+// lane l sums the neighbours e = l, l + 64, ... of its row in order, then the
+// 64 partials are combined by a fixed butterfly.  Same terms as the FP32
+// sweep's neighbour loop: (1 - 1/r) (x_j - x_i).
+__global__ __launch_bounds__(256) void k_heavy_edges(int nheavy, const int* __restrict__ heavy,
+                                                     const int* __restrict__ rp, const int* __restrict__ ci,
+                                                     const float2* __restrict__ xo, float2* __restrict__ out) {
+    const int lane = lane_id();
+    const float tiny = 1e-30f;
+    for (int h = (blockIdx.x * blockDim.x + threadIdx.x) / kWave; h < nheavy;
+         h += gridDim.x * blockDim.x / kWave) {
+        const int i = heavy[h];
+        const float2 xi = xo[i];
+        float ax = 0.f, ay = 0.f;
+        for (int e = rp[i] + lane; e < rp[i + 1]; e += kWave) {
+            const float2 xj = xo[ci[e]];
+            float dx = xj.x - xi.x, dy = xj.y - xi.y;
+            float f = 1.f - __builtin_amdgcn_rsqf(dx * dx + (dy * dy + tiny));
+            ax += f * dx;
+            ay += f * dy;
+        }
+        ax = wave_sum(ax);
+        ay = wave_sum(ay);
+        if (lane == 0) out[h] = make_float2(ax, ay);
+    }
+}
+
+// Position of node i in the ascending heavy list (binary search).
+__device__ __forceinline__ int heavy_index(const int* __restrict__ heavy, int nheavy, int i) {
+    int lo = 0, hi = nheavy - 1;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (heavy[mid] < i)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
 template <typename DT, int VEC, int WAVES, int MODE>
 __global__ __launch_bounds__(64 * WAVES) void k_sweep_f32(
     int n, int kpad, int W, int L, const int* __restrict__ rp, const int* __restrict__ ci,
     const float2* __restrict__ xo, float2* __restrict__ xn, const uint4* __restrict__ dpk,
     const int* __restrict__ piv, const float2* __restrict__ wt2, const float* __restrict__ Hf,
-    const float2* __restrict__ invd, const float* __restrict__ den) {
+    const float2* __restrict__ invd, const float* __restrict__ den, const int* __restrict__ heavy, int nheavy,
+    const float2* __restrict__ heavy_sum) {
     extern __shared__ float4 smem4[];
     float2* sP = (float2*)smem4;                 // [kpad]
     float2* sPart = sP + kpad;                   // [WAVES][64]
@@ -150,10 +192,16 @@ __global__ __launch_bounds__(64 * WAVES) void k_sweep_f32(
         float ax = 0.f, ay = 0.f;
         if (i < n) {
             const float2 xi = xo[i];
-            if (w == 0) {
-                // neighbour votes in CSR order; loads batched four at a time
+            if (w == WAVES - 1) {  // the last wave holds the fewest packed words
+                // neighbour votes in CSR order; loads batched four at a time;
+                // high-degree rows were summed by k_heavy_edges
                 const int e0 = rp[i], e1 = rp[i + 1];
-                for (int e = e0; e < e1; e += 4) {
+                if (e1 - e0 > kHeavyDegree) {
+                    const float2 hs = heavy_sum[heavy_index(heavy, nheavy, i)];
+                    ax = hs.x;
+                    ay = hs.y;
+                }
+                for (int e = e0; e1 - e0 <= kHeavyDegree && e < e1; e += 4) {
                     int j[4];
 #pragma unroll
                     for (int q = 0; q < 4; ++q) j[q] = e + q < e1 ? ci[e + q] : i;
@@ -320,7 +368,7 @@ static void launch_f32(const SweepPlan& pl, hipStream_t s, const ssm_csr* g, con
                        const float2* xo, float2* xn) {
     hipLaunchKernelGGL((k_sweep_f32<DT, VEC, WAVES, MODE>), dim3(pl.grid), dim3(64 * WAVES), pl.lds, s, t->n,
                        t->kpad, t->W, t->delta_max + 1, g->row_ptr, g->col_idx, xo, xn, (const uint4*)t->dpk,
-                       t->pivots, t->wt2, t->Hf, t->invd, t->den32);
+                       t->pivots, t->wt2, t->Hf, t->invd, t->den32, t->heavy, t->nheavy, t->heavy_sum);
 }
 
 template <typename DT, int VEC, int WAVES>
@@ -357,6 +405,9 @@ static void sweep_once(const SweepPlan& pl, ssm_prec p, hipStream_t s, const ssm
                                (const uint4*)t->dpk, t->pivots, t->wtab64, t->den64);
         return;
     }
+    if (t->nheavy > 0)
+        hipLaunchKernelGGL(k_heavy_edges, dim3(std::min(div_up(t->nheavy, 4), 4096)), dim3(256), 0, s, t->nheavy,
+                           t->heavy, g->row_ptr, g->col_idx, (const float2*)xo, t->heavy_sum);
     if (t->dbytes == 1)
         dispatch_waves<uint8_t, 16>(pl, s, g, t, (const float2*)xo, (float2*)xn);
     else
@@ -372,11 +423,15 @@ static SweepPlan plan_sweep(const ssm_terms* t, ssm_prec p) {
         pl.grid = std::max(1, std::min(div_up(t->n, pl.block), num_cus() * 8));
         return pl;
     }
-    // waves per 64-node chunk: enough resident waves to fill the chip, never
-    // more waves than packed words
+    // waves per 64-node chunk: aim at 8 resident waves per SIMD, never more
+    // waves than packed words
     const long long chunks = div_up(t->n, 64);
     int waves = 1;
-    while (waves < 8 && chunks * waves < 16LL * num_cus() && waves * 2 <= nwords) waves <<= 1;
+    while (waves < 4 && chunks * waves < 32LL * num_cus() && waves * 2 <= nwords) waves <<= 1;
+    if (const char* v = getenv("SSM_SWEEP_WAVES")) {  // tuning override
+        int f = atoi(v);
+        if ((f == 1 || f == 2 || f == 4 || f == 8) && f <= nwords) waves = f;
+    }
     pl.waves = waves;
     pl.block = 64 * waves;
     const size_t base = sizeof(float2) * ((size_t)t->kpad + 64 * (size_t)waves);
@@ -393,8 +448,10 @@ static SweepPlan plan_sweep(const ssm_terms* t, ssm_prec p) {
         pl.mode = kTableGlobal;
         pl.lds = base;
     }
-    // equal share of 64-node chunks per block
-    const long long max_grid = std::max<long long>(1, num_cus() * 16LL / waves);
+    // equal share of 64-node chunks per block; one chunk per block until the
+    // LDS staging per block would matter (about 8 blocks per CU)
+    long long max_grid = std::max<long long>(1, num_cus() * 8LL);
+    if (const char* v = getenv("SSM_SWEEP_BLOCKS_PER_CU")) max_grid = std::max(1, atoi(v)) * (long long)num_cus();
     const long long per = (chunks + max_grid - 1) / max_grid;
     pl.grid = (int)std::max<long long>(1, (chunks + per - 1) / per);
     return pl;

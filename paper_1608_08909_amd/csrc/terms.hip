@@ -224,6 +224,13 @@ ssm_status build_terms(const ssm_csr* g, int32_t k, const int32_t* pivots, const
         ssm_terms_free(t);
         return hip_fail(e, "terms: build");
     }
+    // high-degree nodes (their neighbour sums get a whole wavefront)
+    st = heavy_list(g, &t->heavy, &t->nheavy, s);
+    if (st == SSM_OK) st = dalloc((void**)&t->heavy_sum, sizeof(float2) * (size_t)std::max(t->nheavy, 1));
+    if (st != SSM_OK) {
+        ssm_terms_free(t);
+        return st;
+    }
     *out = t;
     return SSM_OK;
 }

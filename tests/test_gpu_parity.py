@@ -84,6 +84,49 @@ def test_regions_with_given_pivots():
     assert np.array_equal(region.cpu().numpy(), region_r)
 
 
+# Launch-shape overrides the library reads from the environment: each selects
+# another kernel variant (cooperative-grid or per-pivot selection, node-id
+# queues, another precheck, the per-workgroup BFS instead of the bit-parallel
+# one, per-level tie resolution over many workgroups, other lanes per node).
+VARIANTS = [
+    {"SSM_SELECT_MODE": "2"}, {"SSM_SELECT_MODE": "2", "SSM_SELECT_BLOCKS": "3"}, {"SSM_SELECT_MODE": "3"},
+    {"SSM_SELECT_ROWQ": "2"}, {"SSM_SELECT_ROWQ": "2", "SSM_SELECT_PRE": "3"}, {"SSM_SELECT_PRE": "1"},
+    {"SSM_BFS_ROWQ": "2", "SSM_MSBFS_OFF": "1"}, {"SSM_MSBFS_OFF": "1"}, {"SSM_MSBFS_BUDGET": "3"},
+    {"SSM_REGION_MODE": "1"}, {"SSM_REGION_MODE": "2"}, {"SSM_BFS_LANES": "2"}, {"SSM_BFS_LANES": "64"},
+]
+VARIANT_CASES = [(G.barabasi_albert(2000, 5, 7), 50), (G.rgg(1500, 4), 33), (G.holed_mesh(120, 130, 6, 4, 12, 5), 40),
+                 (G.tree_plus(300, 2), 17), (G.star(12), 3)]
+
+
+@pytest.mark.parametrize("env", VARIANTS, ids=["-".join(f"{a[4:]}={b}" for a, b in v.items()) for v in VARIANTS])
+def test_kernel_variants_bit_exact(env, monkeypatch):
+    for name, val in env.items():
+        monkeypatch.setenv(name, val)
+    for g, k in VARIANT_CASES:
+        say("variant", env, "case", g.name, "k", k)
+        ref = oracle.preprocess(g.n, g.row_ptr, g.col_idx, k)
+        dg, piv, dist_sel, dist, delta, region, terms = _device_pipeline(g, k)
+        assert np.array_equal(piv.cpu().numpy(), ref.pivots)
+        assert np.array_equal(dist_sel.cpu().numpy(), ref.dist)
+        assert np.array_equal(dist.cpu().numpy(), ref.dist)
+        assert np.array_equal(delta.cpu().numpy(), ref.delta)
+        assert np.array_equal(region.cpu().numpy(), ref.region)
+
+
+def test_regions_many_ties_per_level_path():
+    """Enough tied nodes that the default takes the multi-workgroup per-level
+    resolution, on levels both sparse (tied-node list) and dense (full scan)."""
+    g = G.barabasi_albert(60000, 3, 11)
+    k = 64
+    say("case", g.name, "k", k)
+    _, dref = oracle.select_pivots(g.n, g.row_ptr, g.col_idx, k, 0)
+    delta_r, region_r, _, _ = oracle.regions(dref)
+    assert int((np.sum(dref == delta_r[None, :], axis=0) > 1).sum()) > 16384
+    delta, region = ssm.regions(torch.from_numpy(dref).cuda())
+    assert np.array_equal(delta.cpu().numpy(), delta_r)
+    assert np.array_equal(region.cpu().numpy(), region_r)
+
+
 @pytest.mark.parametrize("g,k", [c for c in CASES if c[1] >= 3], ids=[i for c, i in zip(CASES, IDS) if c[1] >= 3])
 def test_pivotmds_parity(g, k):
     say("case", g.name, "k", k)

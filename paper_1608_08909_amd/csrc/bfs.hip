@@ -463,6 +463,287 @@ __global__ void k_count_unreached(long long total, const int* __restrict__ dist,
     if (c && lane_id() == 0) atomicAdd(bad, c);
 }
 
+// ------------------------------------------------ padded adjacency (ELL)
+
+// Row v of the padded adjacency holds the start of v's CSR row in W slots;
+// unused slots hold -1.  A row longer than W keeps W - 1 entries and
+// kEllMore in its last slot; the rest is read from the CSR row.  A frontier
+// node's neighbours then arrive with one load that needs no row bounds.
+constexpr int kEllMore = -2;
+
+__global__ void k_ell_build(int n, int W, const int* __restrict__ rp, const int* __restrict__ ci,
+                            int* __restrict__ ell) {
+    const long long total = (long long)n * W;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total;
+         q += (long long)gridDim.x * blockDim.x) {
+        const int v = (int)(q / W), j = (int)(q - (long long)v * W);
+        const int a = rp[v], d = rp[v + 1] - a;
+        int val = -1;
+        if (d > W && j == W - 1)
+            val = kEllMore;
+        else if (j < d)
+            val = ci[a + j];
+        ell[q] = val;
+    }
+}
+
+// Slots per padded row: the mean degree rounded up to 8, 16 or 32.
+static int ell_width(const ssm_csr* g) {
+    const double avg = g->n > 0 ? (double)g->nnz / g->n : 0.0;
+    return avg <= 4.0 ? 8 : avg <= 12.0 ? 16 : 32;
+}
+
+static hipError_t ell_build(const ssm_csr* g, int W, int* ell, hipStream_t s) {
+    const long long total = (long long)g->n * W;
+    hipLaunchKernelGGL(k_ell_build, dim3(std::min(div_up(total, 256), 8192)), dim3(256), 0, s, g->n, W, g->row_ptr,
+                       g->col_idx, ell);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------ LDS-resident BFS levels
+//
+// A workgroup runs a level-synchronous BFS whose visited set is one LDS bit
+// per node: a neighbour is claimed by an LDS atomic OR, so the claiming lane
+// owns the node for this BFS and writes its global state with plain stores.
+// Frontiers are node ids: the first kLdsQ in LDS, the rest in a global
+// overflow area of n entries.  Rows longer than W are listed (kHeavyCap in
+// LDS, then global) and their CSR rest is read by whole waves after the
+// regular part of the level.
+
+constexpr int kLdsQ = 2048;
+constexpr int kHeavyCap = 512;
+constexpr int kLdsFixed = (2 * kLdsQ + kHeavyCap) * 4;  // LDS bytes besides the visited bits
+constexpr int kBfsRows = 2;  // frontier nodes per lane group and pass in the per-pivot BFS
+
+__host__ __device__ constexpr size_t lds_bits_bytes(long long n) { return (size_t)((n + 31) / 32) * 4; }
+
+struct Frontier {
+    const int* lcur;  // current frontier: LDS part, global part
+    const int* gcur;
+    int* lnxt;  // next frontier
+    int* gnxt;
+    int* tail;  // LDS size counter of the next frontier
+    int* lheavy;  // long rows of the current frontier: LDS part, global part
+    int* gheavy;
+    int* nheavy;  // LDS counter of those
+};
+
+// Entry i of a list split into an LDS part (first CAP entries) and a global
+// part.  The explicit address spaces keep the two loads apart (a select of
+// the two pointers would become one slower flat load).
+template <int CAP>
+__device__ __forceinline__ int split_get(const int* l, const int* g, int i) {
+    if (i < CAP) return ((const __attribute__((address_space(3))) int*)l)[i];
+    return ((const __attribute__((address_space(1))) int*)g)[i - CAP];
+}
+
+__device__ __forceinline__ int q_get(const int* l, const int* g, int i) { return split_get<kLdsQ>(l, g, i); }
+
+// Claims u[0..N) in the visited bits (one batch of LDS atomics); ok[j] is
+// set where this lane claimed u[j] now.
+template <int N>
+__device__ __forceinline__ void claim(const int (&u)[N], bool (&ok)[N], unsigned* bits, int n) {
+    unsigned old[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        ok[j] = (unsigned)u[j] < (unsigned)n;  // padding, continuation mark, bad index
+        old[j] = ok[j] ? atomicOr(&bits[u[j] >> 5], 1u << (u[j] & 31)) : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) ok[j] = ok[j] && !(old[j] & (1u << (u[j] & 31)));
+}
+
+// Appends the u[j] with ok[j] to the next frontier: one reservation per wave.
+// Call with every lane of the wave active.
+template <int N>
+__device__ __forceinline__ void append(const int (&u)[N], const bool (&ok)[N], const Frontier& f) {
+    uint64_t mk[N];
+    int tot = 0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        mk[j] = __ballot(ok[j]);
+        tot += __popcll(mk[j]);
+    }
+    if (tot == 0) return;
+    int at = 0;
+    if (lane_id() == 0) at = atomicAdd(f.tail, tot);
+    at = __builtin_amdgcn_readfirstlane(at);  // lane 0 is active: every lane is
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        if (ok[j]) {
+            const int slot = at + mask_rank(mk[j]);
+            if (slot < kLdsQ)
+                f.lnxt[slot] = u[j];
+            else
+                f.gnxt[slot - kLdsQ] = u[j];
+        }
+        at += __popcll(mk[j]);
+    }
+}
+
+// One level over the current frontier [0, len): each group of W/4 lanes takes
+// P frontier nodes per pass (P row loads in flight per lane).
+// visit(u, ok) receives the nodes this lane claimed and clears ok[j] for
+// those that stay out of the next frontier.  Ends with every thread past a
+// barrier and the next frontier complete.  Call from uniform control flow
+// with blockDim.x a multiple of 64.
+template <int W, int P, typename Visit>
+__device__ __forceinline__ void ell_level(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                          const int* __restrict__ ell, int len, const Frontier& f,
+                                          unsigned* bits, Visit visit) {
+    constexpr int VW = W / 4;
+    static_assert(VW >= 1 && VW <= kWave && (kWave % VW) == 0, "lanes per node");
+    const int sub = threadIdx.x % VW, grp = threadIdx.x / VW, ngrp = blockDim.x / VW;
+    for (int base = 0; base < len; base += P * ngrp) {
+        int4 nb[P];
+        int v[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int qi = base + p * ngrp + grp;
+            v[p] = qi < len ? q_get(f.lcur, f.gcur, qi) : -1;
+            nb[p] = make_int4(-1, -1, -1, -1);
+            if ((unsigned)v[p] < (unsigned)n) nb[p] = *(const int4*)(ell + (size_t)v[p] * W + 4 * sub);
+        }
+        int u[4 * P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            if (sub == VW - 1 && nb[p].w == kEllMore) {
+                const int h = atomicAdd(f.nheavy, 1);
+                if (h < kHeavyCap)
+                    f.lheavy[h] = v[p];
+                else
+                    f.gheavy[h - kHeavyCap] = v[p];
+            }
+            u[4 * p] = nb[p].x;
+            u[4 * p + 1] = nb[p].y;
+            u[4 * p + 2] = nb[p].z;
+            u[4 * p + 3] = nb[p].w;
+        }
+        bool ok[4 * P];
+        claim(u, ok, bits, n);
+        visit(u, ok);
+        append(u, ok, f);
+    }
+    __syncthreads();
+    const int nh = min(*f.nheavy, n);
+    if (nh > 0) {  // uniform
+        const int wave = threadIdx.x / kWave, nwaves = blockDim.x / kWave, lane = lane_id();
+        for (int h = wave; h < nh; h += nwaves) {
+            const int v = split_get<kHeavyCap>(f.lheavy, f.gheavy, h);
+            const int e0 = rp[v] + W - 1, e1 = rp[v + 1];
+            for (int e = e0; e < e1; e += 4 * kWave) {
+                int u[4];
+                bool ok[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int ee = e + lane + j * kWave;
+                    u[j] = ee < e1 ? ci[ee] : -1;
+                }
+                claim(u, ok, bits, n);
+                visit(u, ok);
+                append(u, ok, f);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Block b: BFS from pivots[b] writing dist[b][*] for every node it reaches.
+// gq holds 3 n ints per block (two frontier overflows, long-row overflow).
+// reached[b] = nodes found; *ecc_max = largest eccentricity seen.
+template <int W, int POOL>
+__global__ __launch_bounds__(kBfsBlock) void k_bfs_ell(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                       const int* __restrict__ ell, const int* __restrict__ pivots,
+                                                       int* dist, int* gq, int* reached, int* ecc_max) {
+    __shared__ __align__(16) unsigned char pool[POOL];
+    __shared__ int s_cnt[3], s_nh[3];
+    int* qa = (int*)pool;
+    int* qb = qa + kLdsQ;
+    int* lheavy = qb + kLdsQ;
+    unsigned* bits = (unsigned*)(lheavy + kHeavyCap);
+    const int b = blockIdx.x;
+    int* D = dist + (size_t)b * n;
+    int* ga = gq + (size_t)b * 3 * n;
+    int* gb = ga + n;
+    int* gh = gb + n;
+    const int nbw = (n + 31) / 32;
+    for (int w = threadIdx.x; w < nbw; w += blockDim.x) bits[w] = 0u;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int src = pivots[b];
+        D[src] = 0;
+        bits[src >> 5] |= 1u << (src & 31);
+        qa[0] = src;
+        s_cnt[0] = 1;
+        s_cnt[1] = s_cnt[2] = 0;
+        s_nh[0] = s_nh[1] = s_nh[2] = 0;
+    }
+    __syncthreads();
+    Frontier f{qa, ga, qb, gb, nullptr, lheavy, gh, nullptr};
+    int level = 0, total = 1;
+    for (;; ++level) {
+        // Counters rotate over three slots so that one barrier per level
+        // suffices: level l reads s_cnt[l%3], appends to s_cnt[(l+1)%3],
+        // lists long rows in s_nh[l%3]; slots used two levels ago are cleared.
+        const int len = min(s_cnt[level % 3], n);
+        if (len == 0) break;
+        if (threadIdx.x == 0) {
+            s_cnt[(level + 2) % 3] = 0;
+            s_nh[(level + 1) % 3] = 0;
+        }
+        f.tail = &s_cnt[(level + 1) % 3];
+        f.nheavy = &s_nh[level % 3];
+        const int dv = level + 1;
+        ell_level<W, kBfsRows>(n, rp, ci, ell, len, f, bits, [&](const auto& u, auto& ok) {
+            constexpr int N = sizeof(u) / sizeof(u[0]);
+#pragma unroll
+            for (int j = 0; j < N; ++j)
+                if (ok[j]) D[u[j]] = dv;
+        });
+        total += s_cnt[(level + 1) % 3];
+        const int* tl = f.lcur;
+        f.lcur = f.lnxt;
+        f.lnxt = (int*)tl;
+        const int* tg = f.gcur;
+        f.gcur = f.gnxt;
+        f.gnxt = (int*)tg;
+    }
+    if (threadIdx.x == 0) {
+        reached[b] = total;
+        atomicMax(ecc_max, level - 1);
+    }
+}
+
+// LDS pool sizes of k_bfs_ell (several workgroups share a CU when small).
+constexpr int kPoolS = 32768, kPoolM = 65536, kPoolL = 155648;
+
+static int bfs_ell_pool(int n) {
+    const size_t need = kLdsFixed + lds_bits_bytes(n);
+    return need <= (size_t)kPoolS ? kPoolS : need <= (size_t)kPoolM ? kPoolM : need <= (size_t)kPoolL ? kPoolL : 0;
+}
+
+template <int W>
+static hipError_t launch_bfs_ell_w(int pool, int blocks, hipStream_t s, int n, const int* rp, const int* ci,
+                                   const int* ell, const int* pivots, int* dist, int* gq, int* reached, int* ecc) {
+    if (pool == kPoolS)
+        hipLaunchKernelGGL((k_bfs_ell<W, kPoolS>), dim3(blocks), dim3(kBfsBlock), 0, s, n, rp, ci, ell, pivots, dist,
+                           gq, reached, ecc);
+    else if (pool == kPoolM)
+        hipLaunchKernelGGL((k_bfs_ell<W, kPoolM>), dim3(blocks), dim3(kBfsBlock), 0, s, n, rp, ci, ell, pivots, dist,
+                           gq, reached, ecc);
+    else
+        hipLaunchKernelGGL((k_bfs_ell<W, kPoolL>), dim3(blocks), dim3(kBfsBlock), 0, s, n, rp, ci, ell, pivots, dist,
+                           gq, reached, ecc);
+    return hipGetLastError();
+}
+
+static hipError_t launch_bfs_ell(int W, int pool, int blocks, hipStream_t s, int n, const int* rp, const int* ci,
+                                 const int* ell, const int* pivots, int* dist, int* gq, int* reached, int* ecc) {
+    if (W == 8) return launch_bfs_ell_w<8>(pool, blocks, s, n, rp, ci, ell, pivots, dist, gq, reached, ecc);
+    if (W == 16) return launch_bfs_ell_w<16>(pool, blocks, s, n, rp, ci, ell, pivots, dist, gq, reached, ecc);
+    return launch_bfs_ell_w<32>(pool, blocks, s, n, rp, ci, ell, pivots, dist, gq, reached, ecc);
+}
+
 template <int VW>
 static void launch_bfs_wg(int blocks, hipStream_t s, int n, const int* rp, const int* ci,
                           const int* pivots, int* dist, int2* queues, int* reached, int* ecc) {
@@ -511,6 +792,43 @@ ssm_status mssp(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dis
             *dmax_out_host = levels;
             return SSM_OK;
         }
+    }
+    // LDS-resident BFS per pivot when the visited bits fit in LDS (tuning
+    // override SSM_BFS_ELL=2 keeps the global-memory form).
+    const int pool = bfs_ell_pool(n);
+    if (pool > 0 && env_int("SSM_BFS_ELL") != 2) {
+        const int W = ell_width(g);
+        const long long qcap = 1LL << 31;  // overflow ints (8 GiB)
+        const int batch = (int)std::max<long long>(1, std::min<long long>(k, qcap / (3LL * n)));
+        int* ell = nullptr;
+        int* gq = nullptr;
+        int* aux = nullptr;  // reached[k], ecc
+        ssm_status st = dalloc((void**)&ell, sizeof(int) * (size_t)n * W);
+        if (st == SSM_OK) st = dalloc((void**)&gq, sizeof(int) * 3 * (size_t)n * batch);
+        if (st == SSM_OK) st = dalloc((void**)&aux, sizeof(int) * ((size_t)k + 1));
+        hipError_t e = hipSuccess;
+        std::vector<int> host((size_t)k + 1);
+        if (st == SSM_OK) {
+            e = hipMemsetAsync(aux, 0, sizeof(int) * ((size_t)k + 1), s);
+            if (e == hipSuccess) e = ell_build(g, W, ell, s);
+            for (int b0 = 0; b0 < k && e == hipSuccess; b0 += batch) {
+                const int nb = std::min(batch, k - b0);
+                e = launch_bfs_ell(W, pool, nb, s, n, g->row_ptr, g->col_idx, ell, pivots + b0,
+                                   dist + (size_t)b0 * n, gq, aux + b0, aux + k);
+            }
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(host.data(), aux, sizeof(int) * ((size_t)k + 1), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+        }
+        if (ell) (void)hipFree(ell);
+        if (gq) (void)hipFree(gq);
+        if (aux) (void)hipFree(aux);
+        if (st != SSM_OK) return st;
+        if (e != hipSuccess) return hip_fail(e, "multi-source BFS");
+        for (int t = 0; t < k; ++t)
+            if (host[t] != n) return fail(SSM_E_DISCONNECTED, "graph is not connected (a BFS missed nodes)");
+        *dmax_out_host = host[k];
+        return SSM_OK;
     }
     // Sources run in batches so that the frontier queues stay bounded.
     const long long qcap = 1LL << 31;  // queue entries (16 GiB)
@@ -828,6 +1146,201 @@ __global__ __launch_bounds__(kBfsBlock) void k_select_wg(int n, const int* __res
     }
 }
 
+// ----------------------------------- one-workgroup selection, LDS-resident
+
+// LDS pool of k_select_ell: the frontier queues, the long-row list, the
+// visited bits and, when it fits, a byte copy of m saturated at kM8Sat.
+constexpr int kSelPool = 155648;
+constexpr int kM8Sat = 255;
+
+static bool sel_bits_fit(int n) { return kLdsFixed + lds_bits_bytes(n) <= (size_t)kSelPool; }
+static size_t sel_bits_words_padded(int n) { return (((size_t)n + 31) / 32 + 3) & ~(size_t)3; }
+static bool sel_m8_fits(int n) {
+    return kLdsFixed + 4 * sel_bits_words_padded(n) + (((size_t)n + 15) & ~(size_t)15) <= (size_t)kSelPool;
+}
+
+// Key of node i with value m for the argmax: the largest m wins, then the
+// lowest id.
+__device__ __forceinline__ unsigned long long argmax_key(int m, int i) {
+    return ((unsigned long long)(unsigned)m << 32) | (unsigned long long)(0xffffffffu - (unsigned)i);
+}
+
+// This thread's best key over m[0..n) (16-byte loads, 4 in flight).  Each
+// thread visits its indices in increasing order, so a strict comparison
+// keeps the lowest id among equal values.
+__device__ __forceinline__ unsigned long long argmax_m_global(const int* __restrict__ m, int n) {
+    constexpr int U = 4;
+    const int n4 = n / 4;
+    const int4* m4 = (const int4*)m;
+    int bv = -1, bi = 0;
+    for (int w0 = threadIdx.x; w0 < n4; w0 += U * blockDim.x) {
+        int4 q[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int w = w0 + j * (int)blockDim.x;
+            q[j] = w < n4 ? m4[w] : make_int4(-1, -1, -1, -1);
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int i = 4 * (w0 + j * (int)blockDim.x);
+            if (q[j].x > bv) { bv = q[j].x; bi = i; }
+            if (q[j].y > bv) { bv = q[j].y; bi = i + 1; }
+            if (q[j].z > bv) { bv = q[j].z; bi = i + 2; }
+            if (q[j].w > bv) { bv = q[j].w; bi = i + 3; }
+        }
+    }
+    unsigned long long best = bv >= 0 ? argmax_key(bv, bi) : 0ull;
+    for (int i = 4 * n4 + threadIdx.x; i < n; i += blockDim.x) {  // tail
+        const unsigned long long key = argmax_key(m[i], i);
+        if (key > best) best = key;
+    }
+    return best;
+}
+
+// Same over the LDS byte copy (16 bytes per read).  m8 is 16-byte aligned
+// and padded with zeros to a multiple of 16 bytes.
+__device__ __forceinline__ unsigned long long argmax_m8(const unsigned char* m8, int n) {
+    const uint4* w16 = (const uint4*)m8;
+    const int nw = (n + 15) / 16;
+    int bv = -1, bi = 0;
+    for (int w = threadIdx.x; w < nw; w += blockDim.x) {
+        const uint4 q = w16[w];
+        const unsigned part[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int val = (int)((part[a] >> (8 * b)) & 255u);
+                if (val > bv) {
+                    bv = val;
+                    bi = 16 * w + 4 * a + b;
+                }
+            }
+        }
+    }
+    return bv >= 0 ? argmax_key(bv, bi) : 0ull;
+}
+
+// All k pivots in one workgroup: for each new pivot the BFS that only
+// continues through nodes whose distance to it is below m (as k_select_all),
+// on LDS-resident levels; the claiming lane owns m[v] for the level.  With M8
+// the pruning test m[v] > dv reads the LDS byte copy of m (exact below
+// kM8Sat, global m otherwise), and the argmax scans the byte copy unless its
+// maximum is saturated.  gq holds 3 n ints.
+template <int W, bool M8>
+__global__ __launch_bounds__(kBfsBlock) void k_select_ell(int n, const int* __restrict__ rp,
+                                                          const int* __restrict__ ci, const int* __restrict__ ell,
+                                                          int k, int first, int* pivots, int* m, int* gq,
+                                                          int* status) {
+    __shared__ __align__(16) unsigned char pool[kSelPool];
+    __shared__ int s_cnt[3], s_nh[3];
+    __shared__ int s_src;
+    __shared__ unsigned long long s_red[kBfsBlock / kWave];
+    int* qa = (int*)pool;
+    int* qb = qa + kLdsQ;
+    int* lheavy = qb + kLdsQ;
+    unsigned* bits = (unsigned*)(lheavy + kHeavyCap);
+    const int nbw = (n + 31) / 32;
+    unsigned char* m8 = (unsigned char*)(bits + ((nbw + 3) & ~3));  // 16-byte aligned
+    int* ga = gq;
+    int* gb = gq + n;
+    int* gh = gb + n;
+
+    if (M8)
+        for (int i = threadIdx.x; i < ((n + 15) & ~15); i += blockDim.x) m8[i] = i < n ? (unsigned char)kM8Sat : 0;
+    if (threadIdx.x == 0) s_src = first;
+    __syncthreads();
+    for (int t = 0; t < k; ++t) {
+        const int src = s_src;
+        for (int w = threadIdx.x; w < nbw; w += blockDim.x) bits[w] = 0u;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            pivots[t] = src;
+            m[src] = 0;
+            if (M8) m8[src] = 0;
+            bits[src >> 5] |= 1u << (src & 31);
+            qa[0] = src;
+            s_cnt[0] = 1;
+            s_cnt[1] = s_cnt[2] = 0;
+            s_nh[0] = s_nh[1] = s_nh[2] = 0;
+        }
+        __syncthreads();
+        Frontier f{qa, ga, qb, gb, nullptr, lheavy, gh, nullptr};
+        for (int level = 0;; ++level) {
+            const int len = min(s_cnt[level % 3], n);  // rotating counters as in k_bfs_ell
+            if (len == 0) break;
+            if (threadIdx.x == 0) {
+                s_cnt[(level + 2) % 3] = 0;
+                s_nh[(level + 1) % 3] = 0;
+            }
+            f.tail = &s_cnt[(level + 1) % 3];
+            f.nheavy = &s_nh[level % 3];
+            const int dv = level + 1;
+            ell_level<W, 1>(n, rp, ci, ell, len, f, bits, [&](const auto& u, auto& ok) {
+                constexpr int N = sizeof(u) / sizeof(u[0]);
+                // all reads first, then all stores: a wait for a read must
+                // not also wait for this level's stores
+                int mv[N];
+                if (M8 && dv < kM8Sat) {  // uniform: the byte copy decides (255 means >= 255 > dv)
+#pragma unroll
+                    for (int j = 0; j < N; ++j) mv[j] = ok[j] ? (int)m8[u[j]] : 0;
+                } else {
+#pragma unroll
+                    for (int j = 0; j < N; ++j) mv[j] = ok[j] ? m[u[j]] : 0;
+                }
+#pragma unroll
+                for (int j = 0; j < N; ++j) {
+                    ok[j] = ok[j] && mv[j] > dv;
+                    if (ok[j]) {
+                        if (M8) m8[u[j]] = (unsigned char)min(dv, kM8Sat);
+                        m[u[j]] = dv;
+                    }
+                }
+            });
+            const int* tl = f.lcur;
+            f.lcur = f.lnxt;
+            f.lnxt = (int*)tl;
+            const int* tg = f.gcur;
+            f.gcur = f.gnxt;
+            f.gnxt = (int*)tg;
+        }
+        if (t + 1 >= k && t != 0) break;
+        unsigned long long best;
+        if (M8) {
+            best = block_max(argmax_m8(m8, n), s_red);
+            if ((int)(best >> 32) == kM8Sat) best = block_max(argmax_m_global(m, n), s_red);  // uniform
+        } else {
+            best = block_max(argmax_m_global(m, n), s_red);
+        }
+        if (threadIdx.x == 0) {
+            if (t == 0 && (int)(best >> 32) == kInf) status[0] = 1;
+            s_src = (int)(0xffffffffu - (unsigned)(best & 0xffffffffu));
+        }
+        __syncthreads();
+        if (t == 0 && (int)(best >> 32) == kInf) break;  // disconnected (uniform)
+    }
+}
+
+template <int W, bool M8>
+static hipError_t launch_select_ell_t(hipStream_t s, int n, const int* rp, const int* ci, const int* ell, int k,
+                                      int first, int* pivots, int* m, int* q, int* status) {
+    hipLaunchKernelGGL((k_select_ell<W, M8>), dim3(1), dim3(kBfsBlock), 0, s, n, rp, ci, ell, k, first, pivots, m,
+                       q, status);
+    return hipGetLastError();
+}
+
+static hipError_t launch_select_ell(int W, bool m8, hipStream_t s, int n, const int* rp, const int* ci,
+                                    const int* ell, int k, int first, int* pivots, int* m, int* q, int* status) {
+    if (m8) {
+        if (W == 8) return launch_select_ell_t<8, true>(s, n, rp, ci, ell, k, first, pivots, m, q, status);
+        if (W == 16) return launch_select_ell_t<16, true>(s, n, rp, ci, ell, k, first, pivots, m, q, status);
+        return launch_select_ell_t<32, true>(s, n, rp, ci, ell, k, first, pivots, m, q, status);
+    }
+    if (W == 8) return launch_select_ell_t<8, false>(s, n, rp, ci, ell, k, first, pivots, m, q, status);
+    if (W == 16) return launch_select_ell_t<16, false>(s, n, rp, ci, ell, k, first, pivots, m, q, status);
+    return launch_select_ell_t<32, false>(s, n, rp, ci, ell, k, first, pivots, m, q, status);
+}
+
 template <int VW, bool ROWQ, int PRE>
 static void launch_select_wg_t(hipStream_t s, int n, const int* rp, const int* ci, int k, int first, int* pivots,
                                int* m, int2* q, int* status) {
@@ -945,7 +1458,23 @@ ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pi
     int mode = env_int("SSM_SELECT_MODE");  // 1 = one workgroup, 2 = cooperative grid, 3 = per pivot
     if (mode < 1 || mode > 3) mode = (long long)n <= (1LL << 18) ? 1 : 2;
     const bool per_pivot = mode == 3;
-    if (mode == 1 && e == hipSuccess) {
+    // One workgroup: the LDS-resident form when the visited bits fit (tuning
+    // override SSM_SELECT_ELL=2 keeps the global-memory form).
+    int* ell = nullptr;
+    const bool use_ell = mode == 1 && sel_bits_fit(n) && env_int("SSM_SELECT_ELL") != 2;
+    const int W = ell_width(g);
+    if (use_ell && e == hipSuccess) {
+        st = dalloc((void**)&ell, sizeof(int) * (size_t)n * W);
+        if (st != SSM_OK) {
+            (void)hipFree(ws);
+            (void)hipFree(keys);
+            return st;
+        }
+        e = ell_build(g, W, ell, s);
+        const bool m8 = sel_m8_fits(n) && env_int("SSM_SELECT_M8") != 2;
+        if (e == hipSuccess)
+            e = launch_select_ell(W, m8, s, n, g->row_ptr, g->col_idx, ell, k, first, pivots, m, qa, status);
+    } else if (mode == 1 && e == hipSuccess) {
         e = launch_select_wg(vw, s, n, g->row_ptr, g->col_idx, k, first, pivots, m, (int2*)qa, status);
     }
     if (mode == 2 && e == hipSuccess) {
@@ -973,6 +1502,7 @@ ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pi
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(ws);
     (void)hipFree(keys);
+    if (ell) (void)hipFree(ell);
     if (e != hipSuccess) return hip_fail(e, "pivot selection");
     if (hstatus) return fail(SSM_E_DISCONNECTED, "graph is not connected (the first BFS missed nodes)");
     return SSM_OK;

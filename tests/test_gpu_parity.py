@@ -90,12 +90,15 @@ def test_regions_with_given_pivots():
 # one, per-level tie resolution over many workgroups, other lanes per node).
 VARIANTS = [
     {"SSM_SELECT_MODE": "2"}, {"SSM_SELECT_MODE": "2", "SSM_SELECT_BLOCKS": "3"}, {"SSM_SELECT_MODE": "3"},
-    {"SSM_SELECT_ROWQ": "2"}, {"SSM_SELECT_ROWQ": "2", "SSM_SELECT_PRE": "3"}, {"SSM_SELECT_PRE": "1"},
-    {"SSM_BFS_ROWQ": "2", "SSM_MSBFS_OFF": "1"}, {"SSM_MSBFS_OFF": "1"}, {"SSM_MSBFS_BUDGET": "3"},
+    {"SSM_SELECT_M8": "2"}, {"SSM_SELECT_ELL": "2"}, {"SSM_SELECT_ELL": "2", "SSM_SELECT_ROWQ": "2"},
+    {"SSM_SELECT_ELL": "2", "SSM_SELECT_ROWQ": "2", "SSM_SELECT_PRE": "3"},
+    {"SSM_SELECT_ELL": "2", "SSM_SELECT_PRE": "1"},
+    {"SSM_BFS_ROWQ": "2", "SSM_MSBFS_OFF": "1", "SSM_BFS_ELL": "2"}, {"SSM_MSBFS_OFF": "1", "SSM_BFS_ELL": "2"},
+    {"SSM_MSBFS_OFF": "1"}, {"SSM_MSBFS_BUDGET": "3"},
     {"SSM_REGION_MODE": "1"}, {"SSM_REGION_MODE": "2"}, {"SSM_BFS_LANES": "2"}, {"SSM_BFS_LANES": "64"},
 ]
 VARIANT_CASES = [(G.barabasi_albert(2000, 5, 7), 50), (G.rgg(1500, 4), 33), (G.holed_mesh(120, 130, 6, 4, 12, 5), 40),
-                 (G.tree_plus(300, 2), 17), (G.star(12), 3)]
+                 (G.tree_plus(300, 2), 17), (G.star(12), 3), (G.path(600), 6)]
 
 
 @pytest.mark.parametrize("env", VARIANTS, ids=["-".join(f"{a[4:]}={b}" for a, b in v.items()) for v in VARIANTS])
@@ -111,6 +114,34 @@ def test_kernel_variants_bit_exact(env, monkeypatch):
         assert np.array_equal(dist.cpu().numpy(), ref.dist)
         assert np.array_equal(delta.cpu().numpy(), ref.delta)
         assert np.array_equal(region.cpu().numpy(), ref.region)
+
+
+@pytest.mark.parametrize("g,k", [(G.rgg(150000, 21, 8.0), 24), (G.grid(400, 400), 8), (G.barabasi_albert(120000, 2, 5), 30)],
+                         ids=["rgg150000-k24", "grid400x400-k8", "ba120000-k30"])
+def test_select_beyond_byte_copy(g, k):
+    """Graphs too large for the LDS byte copy of m but within one workgroup's
+    visited bits; the grid has eccentricities far above 255."""
+    say("case", g.name, "k", k)
+    piv_r, _ = oracle.select_pivots(g.n, g.row_ptr, g.col_idx, k, 0)
+    dg = ssm.DeviceGraph.from_csr(g)
+    assert np.array_equal(ssm.select_pivots(dg, k, 0).cpu().numpy(), piv_r)
+
+
+@pytest.mark.parametrize("msbfs_off", ["0", "1"])
+def test_bfs_large_frontiers(msbfs_off, monkeypatch):
+    """Frontiers beyond the LDS queue and more long rows per level than the
+    LDS list holds: the global overflow areas of the per-pivot BFS."""
+    monkeypatch.setenv("SSM_MSBFS_OFF", msbfs_off)
+    g = G.barabasi_albert(60000, 5, 3)
+    piv = np.array([0, 17, 999, 30000, 59999, 12345, 4242, 777], dtype=np.int32)
+    say("case", g.name, "pivots", piv.tolist(), "msbfs_off", msbfs_off)
+    dref = oracle.bfs_pivots(g.n, g.row_ptr, g.col_idx, piv)
+    dg = ssm.DeviceGraph.from_csr(g)
+    dist, delta, region = ssm.bfs_pivots(dg, torch.from_numpy(piv).cuda())
+    assert np.array_equal(dist.cpu().numpy(), dref)
+    delta_r, region_r, _, _ = oracle.regions(dref)
+    assert np.array_equal(delta.cpu().numpy(), delta_r)
+    assert np.array_equal(region.cpu().numpy(), region_r)
 
 
 def test_regions_many_ties_per_level_path():

@@ -34,6 +34,13 @@ static int virtual_warp(const ssm_csr* g) {
     return vw;
 }
 
+// Fills p[0..count) with v.
+__global__ void k_fill_int(int* p, int v, long long count) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
 // ------------------------------------------------------------ validation
 
 // Every arc (u, v): v in range, v != u, and the reverse arc (v, u) present
@@ -583,14 +590,13 @@ __device__ __forceinline__ void append(const int (&u)[N], const bool (&ok)[N], c
 
 // One level over the current frontier [0, len): each group of W/4 lanes takes
 // P frontier nodes per pass (P row loads in flight per lane).
-// visit(u, ok) receives the nodes this lane claimed and clears ok[j] for
-// those that stay out of the next frontier.  Ends with every thread past a
-// barrier and the next frontier complete.  Call from uniform control flow
-// with blockDim.x a multiple of 64.
-template <int W, int P, typename Visit>
+// take(u, ok) claims the neighbours u[j] (entries outside [0, n) are
+// padding) and sets ok[j] for those that join the next frontier.  Ends with
+// every thread past a barrier and the next frontier complete.  Call from
+// uniform control flow with blockDim.x a multiple of 64.
+template <int W, int P, typename Take>
 __device__ __forceinline__ void ell_level(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                          const int* __restrict__ ell, int len, const Frontier& f,
-                                          unsigned* bits, Visit visit) {
+                                          const int* __restrict__ ell, int len, const Frontier& f, Take take) {
     constexpr int VW = W / 4;
     static_assert(VW >= 1 && VW <= kWave && (kWave % VW) == 0, "lanes per node");
     const int sub = threadIdx.x % VW, grp = threadIdx.x / VW, ngrp = blockDim.x / VW;
@@ -620,8 +626,7 @@ __device__ __forceinline__ void ell_level(int n, const int* __restrict__ rp, con
             u[4 * p + 3] = nb[p].w;
         }
         bool ok[4 * P];
-        claim(u, ok, bits, n);
-        visit(u, ok);
+        take(u, ok);
         append(u, ok, f);
     }
     __syncthreads();
@@ -639,8 +644,7 @@ __device__ __forceinline__ void ell_level(int n, const int* __restrict__ rp, con
                     const int ee = e + lane + j * kWave;
                     u[j] = ee < e1 ? ci[ee] : -1;
                 }
-                claim(u, ok, bits, n);
-                visit(u, ok);
+                take(u, ok);
                 append(u, ok, f);
             }
         }
@@ -648,9 +652,21 @@ __device__ __forceinline__ void ell_level(int n, const int* __restrict__ rp, con
     }
 }
 
-// Block b: BFS from pivots[b] writing dist[b][*] for every node it reaches.
-// gq holds 3 n ints per block (two frontier overflows, long-row overflow).
-// reached[b] = nodes found; *ecc_max = largest eccentricity seen.
+// ell_level with P = 4 rows per lane group and pass for frontiers wider than
+// one pass, P = 1 otherwise (uniform choice).
+template <int W, typename Take>
+__device__ __forceinline__ void ell_level_auto(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                               const int* __restrict__ ell, int len, const Frontier& f, Take take) {
+    if (len > (int)blockDim.x / (W / 4))
+        ell_level<W, 4>(n, rp, ci, ell, len, f, take);
+    else
+        ell_level<W, 1>(n, rp, ci, ell, len, f, take);
+}
+
+// Block b: BFS from pivots[b] writing dist[b][*] for every node it reaches,
+// with the visited set in LDS bits.  gq holds 3 n ints per block (two
+// frontier overflows, long-row overflow).  reached[b] = nodes found;
+// *ecc_max = largest eccentricity seen.
 template <int W, int POOL>
 __global__ __launch_bounds__(kBfsBlock) void k_bfs_ell(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                        const int* __restrict__ ell, const int* __restrict__ pivots,
@@ -694,8 +710,9 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_ell(int n, const int* __restr
         f.tail = &s_cnt[(level + 1) % 3];
         f.nheavy = &s_nh[level % 3];
         const int dv = level + 1;
-        ell_level<W, kBfsRows>(n, rp, ci, ell, len, f, bits, [&](const auto& u, auto& ok) {
+        ell_level_auto<W>(n, rp, ci, ell, len, f, [&](const auto& u, auto& ok) {
             constexpr int N = sizeof(u) / sizeof(u[0]);
+            claim(u, ok, bits, n);
 #pragma unroll
             for (int j = 0; j < N; ++j)
                 if (ok[j]) D[u[j]] = dv;
@@ -714,7 +731,8 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_ell(int n, const int* __restr
     }
 }
 
-// LDS pool sizes of k_bfs_ell (several workgroups share a CU when small).
+// LDS pool sizes of k_bfs_ell (several workgroups share a CU when small);
+// 0 = the visited bits do not fit.
 constexpr int kPoolS = 32768, kPoolM = 65536, kPoolL = 155648;
 
 static int bfs_ell_pool(int n) {
@@ -758,10 +776,11 @@ static void launch_bfs_wg(int blocks, hipStream_t s, int n, const int* rp, const
 ssm_status mssp(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dist,
                 int32_t* dmax_out_host, hipStream_t s) {
     const int n = g->n;
-    // Few levels (hub-heavy graphs): bit-parallel BFS over all pivots at once.
+    // Bit-parallel BFS over all pivots at once (opt-in with SSM_MSBFS=1: the
+    // per-pivot LDS-resident BFS below was faster on every graph measured).
     // It gives up after `budget` levels, and the per-workgroup BFS runs instead.
     const int budget = env_int("SSM_MSBFS_BUDGET") > 0 ? env_int("SSM_MSBFS_BUDGET") : 24;
-    if (k <= 1024 && env_int("SSM_MSBFS_OFF") == 0) {
+    if (k <= 1024 && env_int("SSM_MSBFS") == 1) {
         bool done = false;
         int32_t levels = 0;
         ssm_status st;
@@ -1223,10 +1242,11 @@ __device__ __forceinline__ unsigned long long argmax_m8(const unsigned char* m8,
 
 // All k pivots in one workgroup: for each new pivot the BFS that only
 // continues through nodes whose distance to it is below m (as k_select_all),
-// on LDS-resident levels; the claiming lane owns m[v] for the level.  With M8
-// the pruning test m[v] > dv reads the LDS byte copy of m (exact below
-// kM8Sat, global m otherwise), and the argmax scans the byte copy unless its
-// maximum is saturated.  gq holds 3 n ints.
+// on LDS-resident levels (LDS visited bits; the claiming lane owns m[v]
+// for the level and writes it with plain stores).  With M8 the pruning test
+// m[v] > dv reads an LDS byte copy of m (exact below kM8Sat, global m above)
+// and the argmax scans the byte copy unless its maximum is saturated.
+// gq holds 3 n ints.
 template <int W, bool M8>
 __global__ __launch_bounds__(kBfsBlock) void k_select_ell(int n, const int* __restrict__ rp,
                                                           const int* __restrict__ ci, const int* __restrict__ ell,
@@ -1276,8 +1296,9 @@ __global__ __launch_bounds__(kBfsBlock) void k_select_ell(int n, const int* __re
             f.tail = &s_cnt[(level + 1) % 3];
             f.nheavy = &s_nh[level % 3];
             const int dv = level + 1;
-            ell_level<W, 1>(n, rp, ci, ell, len, f, bits, [&](const auto& u, auto& ok) {
+            ell_level_auto<W>(n, rp, ci, ell, len, f, [&](const auto& u, auto& ok) {
                 constexpr int N = sizeof(u) / sizeof(u[0]);
+                claim(u, ok, bits, n);
                 // all reads first, then all stores: a wait for a read must
                 // not also wait for this level's stores
                 int mv[N];
@@ -1386,11 +1407,6 @@ static hipError_t launch_select_all(int blocks, hipStream_t s, int n, const int*
     return hipLaunchCooperativeKernel((const void*)k_select_all<VW>, dim3(blocks), dim3(kSelBlock), args, 0, s);
 }
 
-__global__ void k_fill_int(int* p, int v, long long count) {
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
-         i += (long long)gridDim.x * blockDim.x)
-        p[i] = v;
-}
 
 template <int VW>
 static hipError_t launch_select(int blocks, hipStream_t s, int n, const int* rp, const int* ci,
@@ -1412,6 +1428,11 @@ static int select_max_blocks() {
     return std::max(1, std::min(a, b)) * num_cus();
 }
 
+// One workgroup up to this many nodes (its levels cost no grid barrier); the
+// cooperative grid above (frontiers too wide for one workgroup).
+constexpr long long kSelOneWgMaxN = 1LL << 18;
+constexpr int kSelGridBlocks = 32;
+
 ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pivots, hipStream_t s) {
     const int n = g->n;
     // workspace: m[n], vis[n], qa[n], qb[n], ctl[4], status[1], keys[max blocks]
@@ -1425,9 +1446,10 @@ ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pi
         case 32: maxb = select_max_blocks<32>(); break;
         default: maxb = select_max_blocks<64>(); break;
     }
-    // Grid size: small graphs run in one workgroup (no grid barrier), larger
-    // ones on up to one block per CU.
-    int blocks = std::max(1, std::min(std::min(maxb, num_cus()), div_up(n, 8192)));
+    // Grid size for the cooperative forms: a grid barrier per BFS level costs
+    // more with more blocks, so a few dozen (measured best on MI355X for
+    // 1M-node power-law and 3M-node mesh graphs).
+    int blocks = std::max(1, std::min(std::min(maxb, kSelGridBlocks), div_up(n, 8192)));
     if (env_int("SSM_SELECT_BLOCKS") > 0) blocks = std::min(maxb, env_int("SSM_SELECT_BLOCKS"));
     // m[n], vis[n], queue area (4n ints: two int queues of n, or two int2
     // queues of n for the one-workgroup kernel), control words
@@ -1456,7 +1478,7 @@ ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pi
     e = hipGetLastError();
     // Mode: one workgroup (no grid barrier) unless the frontiers are large.
     int mode = env_int("SSM_SELECT_MODE");  // 1 = one workgroup, 2 = cooperative grid, 3 = per pivot
-    if (mode < 1 || mode > 3) mode = (long long)n <= (1LL << 18) ? 1 : 2;
+    if (mode < 1 || mode > 3) mode = (long long)n <= kSelOneWgMaxN ? 1 : 2;
     const bool per_pivot = mode == 3;
     // One workgroup: the LDS-resident form when the visited bits fit (tuning
     // override SSM_SELECT_ELL=2 keeps the global-memory form).
@@ -1471,6 +1493,7 @@ ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pi
             return st;
         }
         e = ell_build(g, W, ell, s);
+        // with the byte copy of m when it fits (tuning override SSM_SELECT_M8=2: without)
         const bool m8 = sel_m8_fits(n) && env_int("SSM_SELECT_M8") != 2;
         if (e == hipSuccess)
             e = launch_select_ell(W, m8, s, n, g->row_ptr, g->col_idx, ell, k, first, pivots, m, qa, status);
@@ -1548,16 +1571,36 @@ __global__ __launch_bounds__(256) void k_reg_scan(int n, int k, const int* __res
     }
 }
 
+constexpr int kRegHistLds = 8192;  // counters a block keeps in LDS before flushing
+
 // Histogram of single-candidate nodes per (pivot, level) and count of tied
-// nodes per level.
-__global__ void k_reg_hist(int n, int L, const int* __restrict__ delta, const int4* __restrict__ cand,
-                           int* __restrict__ U, int* __restrict__ tcount) {
+// nodes per level.  With LDS the block counts into LDS ((k + 1) L counters)
+// and adds its nonzero counts to the global ones at the end.
+template <bool LDS>
+__global__ __launch_bounds__(256) void k_reg_hist(int n, int k, int L, const int* __restrict__ delta,
+                                                  const int4* __restrict__ cand, int* __restrict__ U,
+                                                  int* __restrict__ tcount) {
+    extern __shared__ int sh[];
+    int* sU = sh;                   // [k][L]
+    int* sT = sh + (size_t)k * L;   // [L]
+    if (LDS) {
+        for (int q = threadIdx.x; q < (k + 1) * L; q += blockDim.x) sh[q] = 0;
+        __syncthreads();
+    }
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        int4 c = cand[i];
+        const int4 c = cand[i];
+        const int l = delta[i];
         if (c.w == 1)
-            atomicAdd(&U[(size_t)c.x * L + delta[i]], 1);
+            atomicAdd(LDS ? &sU[(size_t)c.x * L + l] : &U[(size_t)c.x * L + l], 1);
         else
-            atomicAdd(&tcount[delta[i]], 1);
+            atomicAdd(LDS ? &sT[l] : &tcount[l], 1);
+    }
+    if (LDS) {
+        __syncthreads();
+        for (int q = threadIdx.x; q < (k + 1) * L; q += blockDim.x) {
+            const int v = sh[q];
+            if (v) atomicAdd(q < k * L ? &U[q] : &tcount[q - k * L], v);
+        }
     }
 }
 
@@ -1575,10 +1618,42 @@ __global__ void k_reg_prefix(int L, const int* __restrict__ tcount, int* __restr
     }
 }
 
-__global__ void k_reg_scatter(int n, const int* __restrict__ delta, const int4* __restrict__ cand,
-                              int* __restrict__ cursor, int* __restrict__ list) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+// Lists the tied nodes by level with one global atomic per node (many levels).
+__global__ void k_reg_scatter_global(int n, const int* __restrict__ delta, const int4* __restrict__ cand,
+                                     int* __restrict__ cursor, int* __restrict__ list) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
         if (cand[i].w > 1) list[atomicAdd(&cursor[delta[i]], 1)] = i;
+}
+
+// Lists the tied nodes by level: a block counts its tied nodes per level in
+// LDS, reserves one range per level with a global atomic, then places them
+// (the order inside a level does not matter to the resolution).  LDS holds
+// 2 L ints.
+__global__ __launch_bounds__(256) void k_reg_scatter(int n, int L, const int* __restrict__ delta,
+                                                     const int4* __restrict__ cand, int* __restrict__ cursor,
+                                                     int* __restrict__ list) {
+    extern __shared__ int sh[];
+    int* cnt = sh;
+    int* base = sh + L;
+    for (int q = threadIdx.x; q < L; q += blockDim.x) cnt[q] = 0;
+    __syncthreads();
+    for (int i0 = blockIdx.x * blockDim.x; i0 < n; i0 += gridDim.x * blockDim.x) {  // uniform rounds
+        const int i = i0 + threadIdx.x;
+        int l = -1, pos = 0;
+        if (i < n && cand[i].w > 1) {
+            l = delta[i];
+            pos = atomicAdd(&cnt[l], 1);
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < L; q += blockDim.x) {
+            const int c = cnt[q];
+            if (c) base[q] = atomicAdd(&cursor[q], c);
+        }
+        __syncthreads();
+        if (l >= 0) list[base[l] + pos] = i;
+        __syncthreads();
+        for (int q = threadIdx.x; q < L; q += blockDim.x) cnt[q] = 0;
+        __syncthreads();
     }
 }
 
@@ -1786,9 +1861,18 @@ ssm_status regions(int32_t n, int32_t k, const int32_t* dist, int32_t* delta, in
         std::vector<int> hstart(L + 1);
         e = hipMemsetAsync(ws, 0, sizeof(int) * ((size_t)k * L + L), s);
         if (e == hipSuccess) {
-            hipLaunchKernelGGL(k_reg_hist, dim3(grid), dim3(256), 0, s, n, L, delta, cand, U, tcount);
+            const long long hist_ints = (long long)(k + 1) * L;
+            if (hist_ints <= kRegHistLds)
+                hipLaunchKernelGGL(k_reg_hist<true>, dim3(std::min(grid, 4 * num_cus())), dim3(256),
+                                   sizeof(int) * hist_ints, s, n, k, L, delta, cand, U, tcount);
+            else
+                hipLaunchKernelGGL(k_reg_hist<false>, dim3(grid), dim3(256), 0, s, n, k, L, delta, cand, U, tcount);
             hipLaunchKernelGGL(k_reg_prefix, dim3(1), dim3(64), 0, s, L, tcount, tstart, cursor);
-            hipLaunchKernelGGL(k_reg_scatter, dim3(grid), dim3(256), 0, s, n, delta, cand, cursor, list);
+            if (2LL * L <= kRegHistLds)
+                hipLaunchKernelGGL(k_reg_scatter, dim3(std::min(grid, 4 * num_cus())), dim3(256),
+                                   sizeof(int) * 2 * L, s, n, L, delta, cand, cursor, list);
+            else
+                hipLaunchKernelGGL(k_reg_scatter_global, dim3(grid), dim3(256), 0, s, n, delta, cand, cursor, list);
             if (!per_level)
                 hipLaunchKernelGGL(k_reg_resolve, dim3(1), dim3(1024), 0, s, n, k, L, dist, U, tstart, list,
                                    cand, region, cum, Tl);

@@ -416,16 +416,15 @@ __global__ __launch_bounds__(256) void k_pmds_edgelen(int n, const int* __restri
                                                       const double2* __restrict__ x,
                                                       double* __restrict__ partials) {
     double s = 0.0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        double2 xi = x[i];
-        for (int e = rp[i]; e < rp[i + 1]; ++e) {
-            int j = ci[e];
-            if (j <= i) continue;
-            double2 xj = x[j];
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int nwaves = gridDim.x * blockDim.x / kWave;
+    for (int i0 = wave * kWave; i0 < n; i0 += nwaves * kWave)  // uniform per wave
+        wave_arcs(n, rp, ci, i0, [&](int i, int j) {
+            if (j <= i) return;
+            const double2 xi = x[i], xj = x[j];
             double dx = xi.x - xj.x, dy = xi.y - xj.y;
             s += sqrt(dx * dx + dy * dy);
-        }
-    }
+        });
     __shared__ double red[256 / kWave];
     s = block_sum(s, red);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;

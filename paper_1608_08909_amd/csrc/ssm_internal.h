@@ -25,6 +25,8 @@ struct ssm_terms {
     float2* wt2 = nullptr;      // [kpad][W] FP32 (w', w' d) for the FP32 sweep
     float* Hf = nullptr;        // [kpad][delta_max+1] H as float, zero rows for padding
     float2* invd = nullptr;     // [W] (1/d^2, 1/d) for d >= 2, zero below
+    int32_t* prank = nullptr;   // [n] rank of the pivot at node i, -1 for other nodes
+    float2* pc = nullptr;       // [2][kpad] FP32 sweep: pivot coordinates of the current and next iterate
     double* den64 = nullptr;    // [n]
     float* den32 = nullptr;     // [n]
     void* dpk = nullptr;        // [kpad/vec][n][vec] packed distances (uint8 or uint16)
@@ -36,14 +38,19 @@ struct ssm_terms {
     int32_t* eig_iters = nullptr;  // [1]
     int32_t nheavy = 0;            // nodes whose degree exceeds kHeavyDegree
     int32_t* heavy = nullptr;      // [nheavy] their ids, ascending
-    float2* heavy_sum = nullptr;   // [nheavy] neighbour displacement sums (FP32 sweep scratch)
+    int32_t nseg = 0;              // segments of kHeavySeg arcs over the heavy rows
+    int32_t* seg_start = nullptr;  // [nheavy + 1] first segment of each heavy row
+    int32_t* seg_owner = nullptr;  // [nseg] heavy row of each segment
+    int2* seg_range = nullptr;     // [n] at a heavy node's id: its segments [x, y)
+    float2* seg_sum = nullptr;     // [nseg] FP32 sweep scratch: neighbour displacement sum per segment
 };
 
 namespace ssm {
 
-// Nodes with more neighbours than this get their neighbour terms summed by a
-// whole wavefront in the FP32 sweep.
+// Nodes with more neighbours than this get their neighbour terms summed by
+// whole wavefronts in the FP32 sweep, one per segment of kHeavySeg arcs.
 constexpr int kHeavyDegree = 64;
+constexpr int kHeavySeg = 512;
 
 // Thread-local error reporting.
 ssm_status fail(ssm_status st, const std::string& msg);
@@ -71,6 +78,9 @@ ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pi
 // Ids of the nodes with degree > kHeavyDegree, ascending; *heavy is a new
 // device allocation of max(count, 1) ints owned by the caller.  Synchronizes.
 ssm_status heavy_list(const ssm_csr* g, int** heavy, int32_t* count, hipStream_t s);
+
+// Heavy list, its arc segments and the FP32 sweep's scratch for them.
+ssm_status heavy_segments(const ssm_csr* g, ssm_terms* t, hipStream_t s);
 ssm_status regions(int32_t n, int32_t k, const int32_t* dist, int32_t* delta, int32_t* region,
                    hipStream_t s);
 

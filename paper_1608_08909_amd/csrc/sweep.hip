@@ -111,31 +111,29 @@ enum WeightMode { kTableLds = 0, kHistLds = 1, kTableGlobal = 2 };
 // keeps FP32 rounding relative to the (small) move rather than to the
 // coordinates, and a vote at distance zero contributes exactly 0, so two
 // coincident nodes with one closed neighbourhood get identical updates.
-//
-// Block = WAVES wavefronts over 64 consecutive nodes (lane = node): wave w
-// sums the packed distance words b = w, w + WAVES, ... (one coalesced 16-byte
-// load per lane covers VEC pivots; every lane of the wave reads the same
-// pivot, so its coordinates and table row come from LDS as broadcasts);
-// the last wave (fewest words) also sums the neighbour terms in CSR order.  The WAVES partials are
-// added in a fixed order.  Weights: kTableLds stages (w', w'd) for every
-// (pivot, distance); kHistLds stages the region histograms H and (1/d^2, 1/d)
-// and forms w' = H[t][min(d/2, delta_max)] / d^2; kTableGlobal reads the table
-// from memory.  1/r is the hardware reciprocal square root of r^2 + 1e-30.
-// Neighbour displacement sums of the high-degree nodes, one wavefront each:
-// lane l sums the neighbours e = l, l + 64, ... of its row in order, then the
-// 64 partials are combined by a fixed butterfly.  Same terms as the FP32
-// sweep's neighbour loop: (1 - 1/r) (x_j - x_i).
-__global__ __launch_bounds__(256) void k_heavy_edges(int nheavy, const int* __restrict__ heavy,
-                                                     const int* __restrict__ rp, const int* __restrict__ ci,
-                                                     const float2* __restrict__ xo, float2* __restrict__ out) {
+// 1/r is the hardware reciprocal square root of r^2 + 1e-30 (a zero
+// displacement then still contributes exactly 0).
+
+// Neighbour displacement sums of the heavy rows (degree > kHeavyDegree):
+// one wavefront per segment of kHeavySeg arcs (lane l sums arcs l, l + 64,
+// ... of the segment, then a fixed butterfly); the sweep adds a row's
+// segments in order.  Same terms as the sweep's neighbour loop:
+// (1 - 1/r) (x_j - x_i).
+__global__ __launch_bounds__(256) void k_heavy_edges(int nseg, const int* __restrict__ heavy,
+                                                     const int* __restrict__ seg_start,
+                                                     const int* __restrict__ seg_owner, const int* __restrict__ rp,
+                                                     const int* __restrict__ ci, const float2* __restrict__ xo,
+                                                     float2* __restrict__ seg_sum) {
     const int lane = lane_id();
     const float tiny = 1e-30f;
-    for (int h = (blockIdx.x * blockDim.x + threadIdx.x) / kWave; h < nheavy;
-         h += gridDim.x * blockDim.x / kWave) {
+    for (int q = (blockIdx.x * blockDim.x + threadIdx.x) / kWave; q < nseg; q += gridDim.x * blockDim.x / kWave) {
+        const int h = seg_owner[q];
         const int i = heavy[h];
+        const int a = rp[i] + (q - seg_start[h]) * kHeavySeg;
+        const int b = min(rp[i + 1], a + kHeavySeg);
         const float2 xi = xo[i];
         float ax = 0.f, ay = 0.f;
-        for (int e = rp[i] + lane; e < rp[i + 1]; e += kWave) {
+        for (int e = a + lane; e < b; e += kWave) {
             const float2 xj = xo[ci[e]];
             float dx = xj.x - xi.x, dy = xj.y - xi.y;
             float f = 1.f - __builtin_amdgcn_rsqf(dx * dx + (dy * dy + tiny));
@@ -144,132 +142,238 @@ __global__ __launch_bounds__(256) void k_heavy_edges(int nheavy, const int* __re
         }
         ax = wave_sum(ax);
         ay = wave_sum(ay);
-        if (lane == 0) out[h] = make_float2(ax, ay);
+        if (lane == 0) seg_sum[q] = make_float2(ax, ay);
     }
 }
 
-// Position of node i in the ascending heavy list (binary search).
-__device__ __forceinline__ int heavy_index(const int* __restrict__ heavy, int nheavy, int i) {
-    int lo = 0, hi = nheavy - 1;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (heavy[mid] < i)
-            lo = mid + 1;
-        else
-            hi = mid;
+// Copies nbytes (a multiple of 4) from global to LDS with 16-byte loads,
+// several in flight per thread (both sides 16-byte aligned).
+__device__ __forceinline__ void stage_lds(void* dst, const void* __restrict__ src, size_t nbytes) {
+    constexpr int U = 4;
+    const size_t n16 = nbytes / 16;
+    uint4* d = (uint4*)dst;
+    const uint4* g = (const uint4*)src;
+    for (size_t q0 = threadIdx.x; q0 < n16; q0 += U * (size_t)blockDim.x) {
+        uint4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const size_t q = q0 + (size_t)u * blockDim.x;
+            if (q < n16) v[u] = g[q];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const size_t q = q0 + (size_t)u * blockDim.x;
+            if (q < n16) d[q] = v[u];
+        }
     }
-    return lo;
+    for (size_t q = 16 * n16 / 4 + threadIdx.x; q < nbytes / 4; q += blockDim.x)
+        ((unsigned*)dst)[q] = ((const unsigned*)src)[q];
 }
 
-template <typename DT, int VEC, int WAVES, int MODE>
-__global__ __launch_bounds__(64 * WAVES) void k_sweep_f32(
+// Block = CPB groups of SPLIT wavefronts; a group takes 64 consecutive nodes
+// (lane = node) and its SPLIT waves share the node's terms: wave s sums the
+// packed distance words b = s, s + SPLIT, ... (one coalesced 16-byte load
+// per lane covers VEC pivots; two words stay in flight).  The last wave of
+// the group, which holds the fewest words, also sums the neighbour terms in
+// CSR order (heavy rows: their segment sums in order).  Wave 0 adds the
+// SPLIT partials in a fixed order.  Blocks loop over the chunks, so the LDS
+// tables are staged once per block.
+//
+// Every lane of a wave reads the same pivot t, so the pivot's coordinates
+// are wave-uniform loads from the contiguous array pc (kept current by the
+// sweep itself: the node of pivot t writes its new coordinates into
+// pc_next[t]).  The pivot term is f = w' - (w' d) / r: kTableLds stages
+// (w', w' d) for every (pivot, distance) in LDS; kHistLds stages the region
+// histograms H and (1/d^2, 1/d), w' = H[t][min(d/2, delta_max)] / d^2, so
+// f = H (1/d^2 - (1/d) / r); kTableGlobal reads (w', w' d) from memory.
+template <typename DT, int VEC, int SPLIT, int CPB, int MODE>
+__global__ __launch_bounds__(64 * SPLIT * CPB) void k_sweep_f32(
     int n, int kpad, int W, int L, const int* __restrict__ rp, const int* __restrict__ ci,
     const float2* __restrict__ xo, float2* __restrict__ xn, const uint4* __restrict__ dpk,
-    const int* __restrict__ piv, const float2* __restrict__ wt2, const float* __restrict__ Hf,
-    const float2* __restrict__ invd, const float* __restrict__ den, const int* __restrict__ heavy, int nheavy,
-    const float2* __restrict__ heavy_sum) {
+    const float2* __restrict__ pc, float2* __restrict__ pc_next, const int* __restrict__ prank,
+    const float2* __restrict__ wt2, const float* __restrict__ Hf, const float2* __restrict__ invd,
+    const float* __restrict__ den, const int2* __restrict__ seg_range, const float2* __restrict__ seg_sum) {
+    constexpr int NW = SPLIT * CPB;
     extern __shared__ float4 smem4[];
-    float2* sP = (float2*)smem4;                 // [kpad]
-    float2* sPart = sP + kpad;                   // [WAVES][64]
-    float2* sTab = sPart + WAVES * 64;           // kTableLds: [kpad][W]; kHistLds: invd [W]
-    float* sH = (float*)(sTab + (MODE == kHistLds ? W : 0));  // kHistLds: [kpad][L]
-    for (int t = threadIdx.x; t < kpad; t += blockDim.x) sP[t] = xo[piv[t]];
-    if (MODE == kTableLds)
-        for (int q = threadIdx.x; q < kpad * W; q += blockDim.x) sTab[q] = wt2[q];
+    float2* sP = (float2*)smem4;                                  // [kpad] pivot coordinates
+    float2* sPart = sP + kpad;                                    // [2][NW][64] (SPLIT > 1)
+    float2* sTab = sPart + (SPLIT > 1 ? 2 * NW * 64 : 0);         // kTableLds: [kpad][W]; kHistLds: invd [W]
+    float* sH = (float*)(sTab + (MODE == kHistLds ? (W + 1) / 2 * 2 : 0));  // kHistLds: H [kpad][L]
+    stage_lds(sP, pc, sizeof(float2) * (size_t)kpad);
+    if (MODE == kTableLds) stage_lds(sTab, wt2, sizeof(float2) * (size_t)kpad * W);
     if (MODE == kHistLds) {
-        for (int q = threadIdx.x; q < W; q += blockDim.x) sTab[q] = invd[q];
-        for (int q = threadIdx.x; q < kpad * L; q += blockDim.x) sH[q] = Hf[q];
+        stage_lds(sTab, invd, sizeof(float2) * (size_t)W);
+        stage_lds(sH, Hf, sizeof(float) * (size_t)kpad * L);
     }
     __syncthreads();
     const int lane = threadIdx.x % 64;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);  // wave-uniform
+    const int grp = w / SPLIT, sw = w % SPLIT;
     const int nwords = kpad / VEC;
-    // r^2 gets 1e-30 added: a vote at distance zero then has a finite factor
-    // times a zero displacement, i.e. contributes exactly 0
+    const int nchunks = (n + 63) / 64;
     const float tiny = 1e-30f;
-    for (int base = blockIdx.x * 64; base < n; base += gridDim.x * 64) {
-        const int i = base + lane;
+    int buf = 0;
+    for (int c0 = blockIdx.x * CPB; c0 < nchunks; c0 += gridDim.x * CPB) {  // uniform over the block
+        const int i = (c0 + grp) * 64 + lane;
         float ax = 0.f, ay = 0.f;
+        float2 xi = make_float2(0.f, 0.f);
         if (i < n) {
-            const float2 xi = xo[i];
-            if (w == WAVES - 1) {  // the last wave holds the fewest packed words
-                // neighbour votes in CSR order; loads batched four at a time;
-                // high-degree rows were summed by k_heavy_edges
+            xi = xo[i];
+            Packed<DT, VEC> wa, wb;
+            wa.v = sw < nwords ? dpk[(size_t)sw * n + i] : make_uint4(0, 0, 0, 0);
+            wb.v = sw + SPLIT < nwords ? dpk[(size_t)(sw + SPLIT) * n + i] : make_uint4(0, 0, 0, 0);
+            if (sw == SPLIT - 1) {
                 const int e0 = rp[i], e1 = rp[i + 1];
-                if (e1 - e0 > kHeavyDegree) {
-                    const float2 hs = heavy_sum[heavy_index(heavy, nheavy, i)];
-                    ax = hs.x;
-                    ay = hs.y;
-                }
-                for (int e = e0; e1 - e0 <= kHeavyDegree && e < e1; e += 4) {
-                    int j[4];
+                if (e1 - e0 > kHeavyDegree) {  // the row's segment sums, in order
+                    const int2 r = seg_range[i];
+                    for (int q = r.x; q < r.y; ++q) {
+                        const float2 hs = seg_sum[q];
+                        ax += hs.x;
+                        ay += hs.y;
+                    }
+                } else {
+                    // neighbour votes in CSR order, four gathers in flight
+                    // (unconditional loads: a missing slot reads x_i itself)
+                    for (int e = e0; e < e1; e += 4) {
+                        int j[4];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) j[q] = e + q < e1 ? ci[e + q] : i;
-                    float2 xj[4];
+                        for (int q = 0; q < 4; ++q) {
+                            const int c = ci[min(e + q, e1 - 1)];  // unconditional load
+                            j[q] = e + q < e1 ? c : i;
+                        }
+                        float2 xj[4];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) xj[q] = xo[j[q]];
+                        for (int q = 0; q < 4; ++q) xj[q] = xo[j[q]];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        float dx = xj[q].x - xi.x, dy = xj[q].y - xi.y;
-                        float inv = __builtin_amdgcn_rsqf(dx * dx + (dy * dy + tiny));
-                        float f = 1.f - inv;  // w = 1, d = 1
-                        ax += f * dx;
-                        ay += f * dy;
+                        for (int q = 0; q < 4; ++q) {
+                            // a missing slot holds x_i: zero displacement, adds exactly 0
+                            float dx = xj[q].x - xi.x, dy = xj[q].y - xi.y;
+                            float inv = __builtin_amdgcn_rsqf(dx * dx + (dy * dy + tiny));
+                            float f = 1.f - inv;  // w = 1, d = 1
+                            ax += f * dx;
+                            ay += f * dy;
+                        }
                     }
                 }
             }
-            if (w < nwords) {
-                Packed<DT, VEC> nextw;
-                nextw.v = dpk[(size_t)w * n + i];
-                for (int b = w; b < nwords; b += WAVES) {
-                    Packed<DT, VEC> u = nextw;
-                    if (b + WAVES < nwords) nextw.v = dpk[(size_t)(b + WAVES) * n + i];  // prefetch
+            for (int b = sw; b < nwords; b += SPLIT) {
+                const Packed<DT, VEC> u = wa;
+                wa = wb;
+                if (b + 2 * SPLIT < nwords) wb.v = dpk[(size_t)(b + 2 * SPLIT) * n + i];  // two words ahead
 #pragma unroll
-                    for (int jj = 0; jj < VEC; ++jj) {
-                        const int t = b * VEC + jj;  // wave-uniform
-                        const int d = (int)u.e[jj];
-                        float f0, f1, hmul;          // f = hmul * (f0 - f1 * inv)
-                        if (MODE == kHistLds) {
-                            const int l = min(d >> 1, L - 1);
-                            hmul = sH[t * L + l];
-                            const float2 id = sTab[d];
-                            f0 = id.x;
-                            f1 = id.y;
-                        } else {
-                            const float2 e = MODE == kTableLds ? sTab[t * W + d] : wt2[(size_t)t * W + d];
-                            f0 = e.x;
-                            f1 = e.y;
-                            hmul = 1.f;
-                        }
-                        const float2 p = sP[t];
-                        float dx = p.x - xi.x, dy = p.y - xi.y;
-                        float inv = __builtin_amdgcn_rsqf(dx * dx + (dy * dy + tiny));
-                        float f = fmaf(-f1, inv, f0);
-                        if (MODE == kHistLds) f *= hmul;
-                        ax += f * dx;
-                        ay += f * dy;
+                for (int jj = 0; jj < VEC; ++jj) {
+                    const int t = b * VEC + jj;  // wave-uniform
+                    const int d = (int)u.e[jj];
+                    float f0, f1, hmul;  // f = hmul (f0 - f1 / r)
+                    if (MODE == kHistLds) {
+                        hmul = sH[t * L + min(d >> 1, L - 1)];
+                        const float2 id = sTab[d];
+                        f0 = id.x;
+                        f1 = id.y;
+                    } else {
+                        const float2 e = MODE == kTableLds ? sTab[t * W + d] : wt2[(size_t)t * W + d];
+                        f0 = e.x;
+                        f1 = e.y;
+                        hmul = 1.f;
                     }
+                    const float2 p = sP[t];  // LDS broadcast
+                    float dx = p.x - xi.x, dy = p.y - xi.y;
+                    float inv = __builtin_amdgcn_rsqf(dx * dx + (dy * dy + tiny));
+                    float f = fmaf(-f1, inv, f0);
+                    if (MODE == kHistLds) f *= hmul;
+                    ax += f * dx;
+                    ay += f * dy;
                 }
             }
         }
-        if (WAVES > 1) {
-            sPart[w * 64 + lane] = make_float2(ax, ay);
+        if (SPLIT > 1) {
+            // partials double-buffered: one barrier per chunk group
+            sPart[(buf * NW + w) * 64 + lane] = make_float2(ax, ay);
             __syncthreads();
-            if (w == 0) {
-                for (int q = 1; q < WAVES; ++q) {
-                    float2 o = sPart[q * 64 + lane];
+            if (sw == 0) {
+#pragma unroll
+                for (int q = 1; q < SPLIT; ++q) {
+                    const float2 o = sPart[(buf * NW + w + q) * 64 + lane];
                     ax += o.x;
                     ay += o.y;
                 }
             }
+            buf ^= 1;
         }
-        if (w == 0 && i < n) {
-            const float2 xi = xo[i];
+        if (sw == 0 && i < n) {
             const float dn = den[i];
-            xn[i] = make_float2(xi.x + ax / dn, xi.y + ay / dn);
+            const float2 v = make_float2(xi.x + ax / dn, xi.y + ay / dn);
+            xn[i] = v;
+            const int r = prank[i];
+            if (r >= 0) pc_next[r] = v;
         }
-        if (WAVES > 1) __syncthreads();
     }
+}
+
+// pc[t] = pc[kpad + t] = x[pivots[t]] for every padded rank (padding repeats
+// pivots[0]; the sweeps keep only the real ranks current, the padded ones
+// stay finite and carry zero weight).
+__global__ void k_gather_pivots(int kpad, const int* __restrict__ piv, const float2* __restrict__ x,
+                                float2* __restrict__ pc) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < kpad; t += gridDim.x * blockDim.x) {
+        const float2 v = x[piv[t]];
+        pc[t] = v;
+        pc[kpad + t] = v;
+    }
+}
+
+// Heavy list, segments and scratch of a handle (called by build_terms).
+__global__ void k_heavy_segcount(int nheavy, const int* __restrict__ heavy, const int* __restrict__ rp,
+                                 int* __restrict__ seg_start) {
+    for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < nheavy; h += gridDim.x * blockDim.x) {
+        const int i = heavy[h];
+        seg_start[h] = (rp[i + 1] - rp[i] + kHeavySeg - 1) / kHeavySeg;
+    }
+}
+
+__global__ void k_heavy_segscan(int nheavy, int* __restrict__ seg_start) {  // exclusive, one thread
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        int acc = 0;
+        for (int h = 0; h < nheavy; ++h) {
+            const int c = seg_start[h];
+            seg_start[h] = acc;
+            acc += c;
+        }
+        seg_start[nheavy] = acc;
+    }
+}
+
+__global__ void k_heavy_segowner(int nheavy, const int* __restrict__ heavy, const int* __restrict__ seg_start,
+                                 int* __restrict__ seg_owner, int2* __restrict__ seg_range) {
+    for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < nheavy; h += gridDim.x * blockDim.x) {
+        seg_range[heavy[h]] = make_int2(seg_start[h], seg_start[h + 1]);
+        for (int q = seg_start[h]; q < seg_start[h + 1]; ++q) seg_owner[q] = h;
+    }
+}
+
+ssm_status heavy_segments(const ssm_csr* g, ssm_terms* t, hipStream_t s) {
+    ssm_status st = heavy_list(g, &t->heavy, &t->nheavy, s);
+    if (st != SSM_OK) return st;
+    const int nh = t->nheavy;
+    st = dalloc((void**)&t->seg_start, sizeof(int) * ((size_t)nh + 1));
+    if (st == SSM_OK) st = dalloc((void**)&t->seg_range, sizeof(int2) * (size_t)g->n);
+    if (st != SSM_OK) return st;
+    const int hb = std::max(1, std::min(div_up(nh, 256), 1024));
+    hipLaunchKernelGGL(k_heavy_segcount, dim3(hb), dim3(256), 0, s, nh, t->heavy, g->row_ptr, t->seg_start);
+    hipLaunchKernelGGL(k_heavy_segscan, dim3(1), dim3(64), 0, s, nh, t->seg_start);
+    SSM_HIP(hipGetLastError());
+    int nseg = 0;
+    SSM_HIP(hipMemcpyAsync(&nseg, t->seg_start + nh, sizeof(int), hipMemcpyDeviceToHost, s));
+    SSM_HIP(hipStreamSynchronize(s));
+    t->nseg = nseg;
+    st = dalloc((void**)&t->seg_owner, sizeof(int) * (size_t)std::max(nseg, 1));
+    if (st == SSM_OK) st = dalloc((void**)&t->seg_sum, sizeof(float2) * (size_t)std::max(nseg, 1));
+    if (st != SSM_OK) return st;
+    hipLaunchKernelGGL(k_heavy_segowner, dim3(hb), dim3(256), 0, s, nh, t->heavy, t->seg_start, t->seg_owner,
+                       t->seg_range);
+    SSM_HIP(hipGetLastError());
+    SSM_HIP(hipStreamSynchronize(s));
+    return SSM_OK;
 }
 
 // ----------------------------------------------------------- stress
@@ -291,16 +395,21 @@ __global__ __launch_bounds__(256) void k_stress(int n, int kpad, int W, const in
     __syncthreads();
     const int nwords = kpad / VEC;
     double acc = 0.0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const double2 xi = as_d2(x[i]);
-        for (int e = rp[i]; e < rp[i + 1]; ++e) {
-            int j = ci[e];
-            if (j <= i) continue;
-            double2 xj = as_d2(x[j]);
+    // waves walk chunks of 64 nodes: edge terms (i < j) over the chunk's arcs,
+    // then every node's pivot terms
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int nwaves = gridDim.x * blockDim.x / kWave;
+    for (int i0 = wave * kWave; i0 < n; i0 += nwaves * kWave) {
+        wave_arcs(n, rp, ci, i0, [&](int i, int j) {
+            if (j <= i) return;
+            const double2 xi = as_d2(x[i]), xj = as_d2(x[j]);
             double dx = xi.x - xj.x, dy = xi.y - xj.y;
             double r = sqrt(dx * dx + dy * dy);
             acc += (r - 1.0) * (r - 1.0);
-        }
+        });
+        const int i = i0 + lane_id();
+        if (i >= n) continue;
+        const double2 xi = as_d2(x[i]);
         for (int b = 0; b < nwords; ++b) {
             Packed<DT, VEC> u;
             u.v = dpk[(size_t)b * n + i];
@@ -359,41 +468,57 @@ __global__ __launch_bounds__(256) void k_sum_pairs(const double* __restrict__ pa
 // -------------------------------------------------------------- driver
 
 struct SweepPlan {
-    int grid = 1, block = 256, waves = 4, mode = kTableGlobal;
+    int grid = 1, block = 256, split = 4, cpb = 4, mode = kTableGlobal;
     size_t lds = 0;
 };
 
-template <typename DT, int VEC, int WAVES, int MODE>
+template <typename DT, int VEC, int SPLIT, int CPB, int MODE>
 static void launch_f32(const SweepPlan& pl, hipStream_t s, const ssm_csr* g, const ssm_terms* t,
-                       const float2* xo, float2* xn) {
-    hipLaunchKernelGGL((k_sweep_f32<DT, VEC, WAVES, MODE>), dim3(pl.grid), dim3(64 * WAVES), pl.lds, s, t->n,
-                       t->kpad, t->W, t->delta_max + 1, g->row_ptr, g->col_idx, xo, xn, (const uint4*)t->dpk,
-                       t->pivots, t->wt2, t->Hf, t->invd, t->den32, t->heavy, t->nheavy, t->heavy_sum);
+                       const float2* xo, float2* xn, const float2* pc, float2* pc_next) {
+    if (pl.lds > 64 * 1024)  // above the default dynamic LDS limit
+        (void)hipFuncSetAttribute((const void*)k_sweep_f32<DT, VEC, SPLIT, CPB, MODE>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds);
+    hipLaunchKernelGGL((k_sweep_f32<DT, VEC, SPLIT, CPB, MODE>), dim3(pl.grid), dim3(64 * SPLIT * CPB), pl.lds, s,
+                       t->n, t->kpad, t->W, t->delta_max + 1, g->row_ptr, g->col_idx, xo, xn, (const uint4*)t->dpk,
+                       pc, pc_next, t->prank, t->wt2, t->Hf, t->invd, t->den32, t->seg_range, t->seg_sum);
 }
 
-template <typename DT, int VEC, int WAVES>
+template <typename DT, int VEC, int SPLIT, int CPB>
 static void dispatch_mode(const SweepPlan& pl, hipStream_t s, const ssm_csr* g, const ssm_terms* t,
-                          const float2* xo, float2* xn) {
+                          const float2* xo, float2* xn, const float2* pc, float2* pc_next) {
     switch (pl.mode) {
-        case kTableLds: launch_f32<DT, VEC, WAVES, kTableLds>(pl, s, g, t, xo, xn); break;
-        case kHistLds: launch_f32<DT, VEC, WAVES, kHistLds>(pl, s, g, t, xo, xn); break;
-        default: launch_f32<DT, VEC, WAVES, kTableGlobal>(pl, s, g, t, xo, xn); break;
+        case kTableLds: launch_f32<DT, VEC, SPLIT, CPB, kTableLds>(pl, s, g, t, xo, xn, pc, pc_next); break;
+        case kHistLds: launch_f32<DT, VEC, SPLIT, CPB, kHistLds>(pl, s, g, t, xo, xn, pc, pc_next); break;
+        default: launch_f32<DT, VEC, SPLIT, CPB, kTableGlobal>(pl, s, g, t, xo, xn, pc, pc_next); break;
     }
 }
 
+// Blocks of 4 waves (small LDS tables) or 16 waves (one large table per CU):
+// SPLIT waves per 64-node chunk.
 template <typename DT, int VEC>
-static void dispatch_waves(const SweepPlan& pl, hipStream_t s, const ssm_csr* g, const ssm_terms* t,
-                           const float2* xo, float2* xn) {
-    switch (pl.waves) {
-        case 1: dispatch_mode<DT, VEC, 1>(pl, s, g, t, xo, xn); break;
-        case 2: dispatch_mode<DT, VEC, 2>(pl, s, g, t, xo, xn); break;
-        case 4: dispatch_mode<DT, VEC, 4>(pl, s, g, t, xo, xn); break;
-        default: dispatch_mode<DT, VEC, 8>(pl, s, g, t, xo, xn); break;
+static void dispatch_split(const SweepPlan& pl, hipStream_t s, const ssm_csr* g, const ssm_terms* t,
+                           const float2* xo, float2* xn, const float2* pc, float2* pc_next) {
+    const bool big = pl.block == 1024;
+    switch (pl.split) {
+        case 1:
+            if (big) dispatch_mode<DT, VEC, 1, 16>(pl, s, g, t, xo, xn, pc, pc_next);
+            else dispatch_mode<DT, VEC, 1, 4>(pl, s, g, t, xo, xn, pc, pc_next);
+            break;
+        case 2:
+            if (big) dispatch_mode<DT, VEC, 2, 8>(pl, s, g, t, xo, xn, pc, pc_next);
+            else dispatch_mode<DT, VEC, 2, 2>(pl, s, g, t, xo, xn, pc, pc_next);
+            break;
+        default:
+            if (big) dispatch_mode<DT, VEC, 4, 4>(pl, s, g, t, xo, xn, pc, pc_next);
+            else dispatch_mode<DT, VEC, 4, 1>(pl, s, g, t, xo, xn, pc, pc_next);
+            break;
     }
 }
 
+// One sweep xo -> xn.  FP32: pc holds the pivot coordinates of xo; the sweep
+// writes those of xn into pc_next.
 static void sweep_once(const SweepPlan& pl, ssm_prec p, hipStream_t s, const ssm_csr* g, const ssm_terms* t,
-                       const void* xo, void* xn) {
+                       const void* xo, void* xn, const float2* pc = nullptr, float2* pc_next = nullptr) {
     if (p == SSM_FP64) {
         if (t->dbytes == 1)
             hipLaunchKernelGGL((k_sweep_f64<uint8_t, 16>), dim3(pl.grid), dim3(pl.block), pl.lds, s, t->n, t->kpad,
@@ -405,14 +530,17 @@ static void sweep_once(const SweepPlan& pl, ssm_prec p, hipStream_t s, const ssm
                                (const uint4*)t->dpk, t->pivots, t->wtab64, t->den64);
         return;
     }
-    if (t->nheavy > 0)
-        hipLaunchKernelGGL(k_heavy_edges, dim3(std::min(div_up(t->nheavy, 4), 4096)), dim3(256), 0, s, t->nheavy,
-                           t->heavy, g->row_ptr, g->col_idx, (const float2*)xo, t->heavy_sum);
+    if (t->nseg > 0)
+        hipLaunchKernelGGL(k_heavy_edges, dim3(std::min(div_up(t->nseg, 4), 4096)), dim3(256), 0, s, t->nseg,
+                           t->heavy, t->seg_start, t->seg_owner, g->row_ptr, g->col_idx, (const float2*)xo,
+                           t->seg_sum);
     if (t->dbytes == 1)
-        dispatch_waves<uint8_t, 16>(pl, s, g, t, (const float2*)xo, (float2*)xn);
+        dispatch_split<uint8_t, 16>(pl, s, g, t, (const float2*)xo, (float2*)xn, pc, pc_next);
     else
-        dispatch_waves<uint16_t, 8>(pl, s, g, t, (const float2*)xo, (float2*)xn);
+        dispatch_split<uint16_t, 8>(pl, s, g, t, (const float2*)xo, (float2*)xn, pc, pc_next);
 }
+
+constexpr size_t kSweepLdsMax = 150 * 1024;  // LDS of one FP32 sweep block (160 KB per CU)
 
 static SweepPlan plan_sweep(const ssm_terms* t, ssm_prec p) {
     SweepPlan pl;
@@ -423,37 +551,42 @@ static SweepPlan plan_sweep(const ssm_terms* t, ssm_prec p) {
         pl.grid = std::max(1, std::min(div_up(t->n, pl.block), num_cus() * 8));
         return pl;
     }
-    // waves per 64-node chunk: aim at 8 resident waves per SIMD, never more
-    // waves than packed words
-    const long long chunks = div_up(t->n, 64);
-    int waves = 1;
-    while (waves < 4 && chunks * waves < 32LL * num_cus() && waves * 2 <= nwords) waves <<= 1;
-    if (const char* v = getenv("SSM_SWEEP_WAVES")) {  // tuning override
-        int f = atoi(v);
-        if ((f == 1 || f == 2 || f == 4 || f == 8) && f <= nwords) waves = f;
-    }
-    pl.waves = waves;
-    pl.block = 64 * waves;
-    const size_t base = sizeof(float2) * ((size_t)t->kpad + 64 * (size_t)waves);
+    // LDS form of the weights: the whole table, else the histograms
     const size_t table = sizeof(float2) * (size_t)t->kpad * t->W;
-    const size_t hist = sizeof(float2) * (size_t)t->W + sizeof(float) * (size_t)t->kpad * (t->delta_max + 1);
-    const size_t budget = 64 * 1024;
-    if (base + table <= budget) {
+    const size_t hist = sizeof(float2) * (size_t)(t->W + 1) / 2 * 2 + sizeof(float) * (size_t)t->kpad * (t->delta_max + 1);
+    const size_t parts = sizeof(float2) * (2 * 16 * 64 + (size_t)t->kpad);  // partials of the largest block, pivots
+    if (table + parts <= kSweepLdsMax)
         pl.mode = kTableLds;
-        pl.lds = base + table;
-    } else if (base + hist <= budget) {
+    else if (hist + parts <= kSweepLdsMax)
         pl.mode = kHistLds;
-        pl.lds = base + hist;
-    } else {
+    else
         pl.mode = kTableGlobal;
-        pl.lds = base;
+    if (const char* v = getenv("SSM_SWEEP_MODE")) {  // tuning override (a form that fits)
+        const int f = atoi(v);
+        if (f == kTableGlobal || (f == kHistLds && hist + parts <= kSweepLdsMax)) pl.mode = f;
     }
-    // equal share of 64-node chunks per block; one chunk per block until the
-    // LDS staging per block would matter (about 8 blocks per CU)
-    long long max_grid = std::max<long long>(1, num_cus() * 8LL);
+    const size_t tab = pl.mode == kTableLds ? table : pl.mode == kHistLds ? hist : 0;
+    // a large table is staged once per CU by a 16-wave block; a small one by
+    // 4-wave blocks (finer load balance)
+    pl.block = tab > 40 * 1024 ? 1024 : 256;
+    const int nw = pl.block / 64;
+    // waves per 64-node chunk (measured on MI355X over 0.1M-3M-node graphs):
+    // two for 4-wave blocks, one for the 16-wave blocks of large tables
+    const long long chunks = div_up(t->n, 64);
+    int split = std::min(pl.block == 1024 ? 1 : 2, nwords);
+    if (const char* v = getenv("SSM_SWEEP_SPLIT")) {  // tuning override
+        const int f = atoi(v);
+        if ((f == 1 || f == 2 || f == 4) && f <= nwords) split = f;
+    }
+    pl.split = split;
+    pl.cpb = nw / split;
+    pl.lds = sizeof(float2) * (size_t)t->kpad + tab + (split > 1 ? sizeof(float2) * 2 * nw * 64 : 0);
+    const int per_cu = pl.block == 1024 ? (pl.lds <= 80 * 1024 ? 2 : 1)
+                                        : std::max(1, std::min(4, (int)((160 * 1024) / std::max<size_t>(pl.lds, 1))));
+    long long max_grid = (long long)num_cus() * per_cu;
     if (const char* v = getenv("SSM_SWEEP_BLOCKS_PER_CU")) max_grid = std::max(1, atoi(v)) * (long long)num_cus();
-    const long long per = (chunks + max_grid - 1) / max_grid;
-    pl.grid = (int)std::max<long long>(1, (chunks + per - 1) / per);
+    const long long groups = div_up(chunks, pl.cpb);
+    pl.grid = (int)std::max<long long>(1, std::min(groups, max_grid));
     return pl;
 }
 
@@ -464,8 +597,12 @@ ssm_status majorize(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* x, int32_t
     void* bufs[2] = {x, t->xtmp};
     int cur = 0, done = 0;
     const int cblocks = std::min(div_up(t->n, 256), 2048);
+    float2* pcb[2] = {t->pc, t->pc + t->kpad};
+    if (p == SSM_FP32 && iters > 0)
+        hipLaunchKernelGGL(k_gather_pivots, dim3(div_up(t->kpad, 256)), dim3(256), 0, s, t->kpad, t->pivots,
+                           (const float2*)x, pcb[0]);
     for (; done < iters; ++done) {
-        sweep_once(pl, p, s, g, t, bufs[cur], bufs[cur ^ 1]);
+        sweep_once(pl, p, s, g, t, bufs[cur], bufs[cur ^ 1], pcb[done & 1], pcb[(done + 1) & 1]);
         if (tol > 0.0) {
             if (p == SSM_FP64)
                 hipLaunchKernelGGL(k_change<double2>, dim3(cblocks), dim3(256), 0, s, t->n,

@@ -32,11 +32,24 @@ __global__ __launch_bounds__(256) void k_terms_max(int n, int k, const int* __re
 
 // Raw histogram of (region, delta), then a per-pivot running sum over the
 // level: H[t][l] = |{ j : region_j = t, delta_j <= l }|.
-__global__ void k_terms_hist(int n, int k, int L, const int* __restrict__ delta, const int* __restrict__ region,
-                             int* __restrict__ H) {
+// With LDS the block counts into LDS (k L counters) and adds its nonzero
+// counts to H at the end.
+template <bool LDS>
+__global__ __launch_bounds__(256) void k_terms_hist(int n, int k, int L, const int* __restrict__ delta,
+                                                    const int* __restrict__ region, int* __restrict__ H) {
+    extern __shared__ int sh[];
+    if (LDS) {
+        for (int q = threadIdx.x; q < k * L; q += blockDim.x) sh[q] = 0;
+        __syncthreads();
+    }
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         unsigned r = (unsigned)region[i], l = (unsigned)delta[i];
-        if (r < (unsigned)k && l < (unsigned)L) atomicAdd(&H[(size_t)r * L + l], 1);
+        if (r < (unsigned)k && l < (unsigned)L) atomicAdd(LDS ? &sh[(size_t)r * L + l] : &H[(size_t)r * L + l], 1);
+    }
+    if (LDS) {
+        __syncthreads();
+        for (int q = threadIdx.x; q < k * L; q += blockDim.x)
+            if (sh[q]) atomicAdd(&H[q], sh[q]);
     }
 }
 
@@ -74,7 +87,8 @@ __global__ void k_terms_wtab(int k, int kpad, int W, int delta_max, const int* _
 }
 
 // Tables of the FP32 sweep: wt2[t][d] = (w', w' d) rounded from FP64;
-// Hf[t][l] = H[t][l] (exact in float); invd[d] = (1/d^2, 1/d) for d >= 2.
+// Hf[t][l] = H[t][l] (exact in float below 2^24); invd[d] = (1/d^2, 1/d)
+// for d >= 2.
 __global__ void k_terms_f32_tables(int k, int kpad, int W, int L, const int* __restrict__ H,
                                    const double* __restrict__ w64, float2* __restrict__ wt2,
                                    float* __restrict__ Hf, float2* __restrict__ invd) {
@@ -94,6 +108,16 @@ __global__ void k_terms_f32_tables(int k, int kpad, int W, int L, const int* __r
     for (int d = blockIdx.x * blockDim.x + threadIdx.x; d < W; d += gridDim.x * blockDim.x)
         invd[d] = d >= 2 ? make_float2((float)(1.0 / ((double)d * (double)d)), (float)(1.0 / (double)d))
                          : make_float2(0.f, 0.f);
+}
+
+// prank[i] = t for i = pivots[t], t < k; -1 elsewhere (pivots are distinct):
+// a fill, then one write per pivot.
+__global__ void k_terms_prank(int n, int* __restrict__ prank) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) prank[i] = -1;
+}
+
+__global__ void k_terms_prank_set(int k, const int* __restrict__ pivots, int* __restrict__ prank) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < k; t += gridDim.x * blockDim.x) prank[pivots[t]] = t;
 }
 
 // den_i = deg(i) * 1 + sum over ranks t ascending of w'_it (d >= 2); summed in
@@ -181,6 +205,8 @@ ssm_status build_terms(const ssm_csr* g, int32_t k, const int32_t* pivots, const
         {(void**)&t->wt2, sizeof(float2) * kw},
         {(void**)&t->Hf, sizeof(float) * (size_t)t->kpad * L},
         {(void**)&t->invd, sizeof(float2) * (size_t)t->W},
+        {(void**)&t->prank, sizeof(int) * (size_t)n},
+        {(void**)&t->pc, sizeof(float2) * 2 * (size_t)t->kpad},
         {(void**)&t->den64, sizeof(double) * (size_t)n},
         {(void**)&t->den32, sizeof(float) * (size_t)n},
         {(void**)&t->dpk, (size_t)t->kpad * n * t->dbytes},
@@ -201,12 +227,18 @@ ssm_status build_terms(const ssm_csr* g, int32_t k, const int32_t* pivots, const
     e = hipMemsetAsync(t->H, 0, sizeof(int) * (size_t)k * L, s);
     if (e == hipSuccess) e = hipMemsetAsync(t->eig_iters, 0, sizeof(int), s);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_terms_hist, dim3(grid_n), dim3(256), 0, s, n, k, L, delta, region, t->H);
+        if ((long long)k * L <= 8192)
+            hipLaunchKernelGGL(k_terms_hist<true>, dim3(std::min(grid_n, 4 * num_cus())), dim3(256),
+                               sizeof(int) * (size_t)k * L, s, n, k, L, delta, region, t->H);
+        else
+            hipLaunchKernelGGL(k_terms_hist<false>, dim3(grid_n), dim3(256), 0, s, n, k, L, delta, region, t->H);
         hipLaunchKernelGGL(k_terms_hist_scan, dim3(div_up(k, 256)), dim3(256), 0, s, k, L, t->H);
         hipLaunchKernelGGL(k_terms_wtab, dim3((int)std::min<long long>((kw + 255) / 256, 8192)), dim3(256), 0,
                            s, k, t->kpad, t->W, t->delta_max, t->H, pivots, t->pivots, t->wtab64, t->wtab32);
         hipLaunchKernelGGL(k_terms_f32_tables, dim3((int)std::min<long long>((kw + 255) / 256, 8192)), dim3(256),
                            0, s, k, t->kpad, t->W, L, t->H, t->wtab64, t->wt2, t->Hf, t->invd);
+        hipLaunchKernelGGL(k_terms_prank, dim3(grid_n), dim3(256), 0, s, n, t->prank);
+        hipLaunchKernelGGL(k_terms_prank_set, dim3(div_up(k, 256)), dim3(256), 0, s, k, pivots, t->prank);
         hipLaunchKernelGGL(k_terms_den, dim3(grid_n), dim3(256), 0, s, n, k, t->W, g->row_ptr, dist,
                            t->wtab64, t->den64, t->den32);
         long long words = (long long)(t->kpad / t->vec) * n;
@@ -224,9 +256,8 @@ ssm_status build_terms(const ssm_csr* g, int32_t k, const int32_t* pivots, const
         ssm_terms_free(t);
         return hip_fail(e, "terms: build");
     }
-    // high-degree nodes (their neighbour sums get a whole wavefront)
-    st = heavy_list(g, &t->heavy, &t->nheavy, s);
-    if (st == SSM_OK) st = dalloc((void**)&t->heavy_sum, sizeof(float2) * (size_t)std::max(t->nheavy, 1));
+    // high-degree nodes (their neighbour sums get whole wavefronts)
+    st = heavy_segments(g, t, s);
     if (st != SSM_OK) {
         ssm_terms_free(t);
         return st;

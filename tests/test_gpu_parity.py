@@ -85,16 +85,18 @@ def test_regions_with_given_pivots():
 
 
 # Launch-shape overrides the library reads from the environment: each selects
-# another kernel variant (cooperative-grid or per-pivot selection, node-id
-# queues, another precheck, the per-workgroup BFS instead of the bit-parallel
-# one, per-level tie resolution over many workgroups, other lanes per node).
+# another kernel variant (cooperative-grid or per-pivot selection, selection
+# without the LDS byte copy or over the plain CSR with node-id queues or
+# another precheck, the CSR per-workgroup BFS, the bit-parallel BFS, one- or
+# many-workgroup region tie resolution, other lanes per node).
 VARIANTS = [
     {"SSM_SELECT_MODE": "2"}, {"SSM_SELECT_MODE": "2", "SSM_SELECT_BLOCKS": "3"}, {"SSM_SELECT_MODE": "3"},
-    {"SSM_SELECT_M8": "2"}, {"SSM_SELECT_ELL": "2"}, {"SSM_SELECT_ELL": "2", "SSM_SELECT_ROWQ": "2"},
+    {"SSM_SELECT_M8": "2"}, {"SSM_SELECT_ELL": "2"}, {"SSM_SELECT_MODE": "1"},
+    {"SSM_SELECT_ELL": "2", "SSM_SELECT_ROWQ": "2"},
     {"SSM_SELECT_ELL": "2", "SSM_SELECT_ROWQ": "2", "SSM_SELECT_PRE": "3"},
     {"SSM_SELECT_ELL": "2", "SSM_SELECT_PRE": "1"},
-    {"SSM_BFS_ROWQ": "2", "SSM_MSBFS_OFF": "1", "SSM_BFS_ELL": "2"}, {"SSM_MSBFS_OFF": "1", "SSM_BFS_ELL": "2"},
-    {"SSM_MSBFS_OFF": "1"}, {"SSM_MSBFS_BUDGET": "3"},
+    {"SSM_BFS_ROWQ": "2", "SSM_BFS_ELL": "2"}, {"SSM_BFS_ELL": "2"}, {"SSM_MSBFS": "1"},
+    {"SSM_MSBFS": "1", "SSM_MSBFS_BUDGET": "3"},
     {"SSM_REGION_MODE": "1"}, {"SSM_REGION_MODE": "2"}, {"SSM_BFS_LANES": "2"}, {"SSM_BFS_LANES": "64"},
 ]
 VARIANT_CASES = [(G.barabasi_albert(2000, 5, 7), 50), (G.rgg(1500, 4), 33), (G.holed_mesh(120, 130, 6, 4, 12, 5), 40),
@@ -118,23 +120,28 @@ def test_kernel_variants_bit_exact(env, monkeypatch):
 
 @pytest.mark.parametrize("g,k", [(G.rgg(150000, 21, 8.0), 24), (G.grid(400, 400), 8), (G.barabasi_albert(120000, 2, 5), 30)],
                          ids=["rgg150000-k24", "grid400x400-k8", "ba120000-k30"])
-def test_select_beyond_byte_copy(g, k):
+@pytest.mark.parametrize("mode", ["0", "2"], ids=["auto", "grid"])
+def test_select_beyond_byte_copy(g, k, mode, monkeypatch):
     """Graphs too large for the LDS byte copy of m but within one workgroup's
-    visited bits; the grid has eccentricities far above 255."""
-    say("case", g.name, "k", k)
+    visited bits, and the cooperative grid form; the grid graph has
+    eccentricities far above 255; the BA graph has frontiers wider than one
+    pass."""
+    monkeypatch.setenv("SSM_SELECT_MODE", mode)
+    say("case", g.name, "k", k, "mode", mode)
     piv_r, _ = oracle.select_pivots(g.n, g.row_ptr, g.col_idx, k, 0)
     dg = ssm.DeviceGraph.from_csr(g)
     assert np.array_equal(ssm.select_pivots(dg, k, 0).cpu().numpy(), piv_r)
 
 
-@pytest.mark.parametrize("msbfs_off", ["0", "1"])
-def test_bfs_large_frontiers(msbfs_off, monkeypatch):
+@pytest.mark.parametrize("env", [{}, {"SSM_MSBFS": "1"}, {"SSM_BFS_ELL": "2"}], ids=["default", "bitparallel", "csr"])
+def test_bfs_large_frontiers(env, monkeypatch):
     """Frontiers beyond the LDS queue and more long rows per level than the
     LDS list holds: the global overflow areas of the per-pivot BFS."""
-    monkeypatch.setenv("SSM_MSBFS_OFF", msbfs_off)
+    for name, val in env.items():
+        monkeypatch.setenv(name, val)
     g = G.barabasi_albert(60000, 5, 3)
     piv = np.array([0, 17, 999, 30000, 59999, 12345, 4242, 777], dtype=np.int32)
-    say("case", g.name, "pivots", piv.tolist(), "msbfs_off", msbfs_off)
+    say("case", g.name, "pivots", piv.tolist(), "env", env)
     dref = oracle.bfs_pivots(g.n, g.row_ptr, g.col_idx, piv)
     dg = ssm.DeviceGraph.from_csr(g)
     dist, delta, region = ssm.bfs_pivots(dg, torch.from_numpy(piv).cuda())
@@ -219,6 +226,32 @@ def test_sweeps_f32_stress(g, k):
     s32 = ssm.stress(dg, terms, xg)
     sr = oracle.stress_sparse(g.row_ptr, g.col_idx, ref.pivots, ref.dist, ref.wtab, xr)
     assert abs(s32 - sr) <= 1e-4 * sr, (s32, sr)
+
+
+SWEEP_VARIANTS = [{"SSM_SWEEP_SPLIT": "1"}, {"SSM_SWEEP_SPLIT": "2"}, {"SSM_SWEEP_SPLIT": "4"},
+                  {"SSM_SWEEP_MODE": "1"}, {"SSM_SWEEP_MODE": "2"}, {"SSM_SWEEP_MODE": "2", "SSM_SWEEP_SPLIT": "4"},
+                  {"SSM_SWEEP_BLOCKS_PER_CU": "1"}]
+
+
+@pytest.mark.parametrize("env", SWEEP_VARIANTS, ids=["-".join(f"{a[10:]}={b}" for a, b in v.items()) for v in SWEEP_VARIANTS])
+def test_sweep_f32_variants(env, monkeypatch):
+    """Every FP32 sweep form (waves per chunk, LDS table, LDS histograms,
+    global table, one block per CU) against the FP64 oracle's stress, on a
+    graph with rows of more than one segment (their neighbour sums) and on a
+    low-degree one."""
+    for name, val in env.items():
+        monkeypatch.setenv(name, val)
+    for g, k in [(G.barabasi_albert(60000, 5, 3), 32), (G.rgg(3000, 5), 48)]:
+        say("sweep variant", env, "case", g.name, "k", k)
+        ref = oracle.preprocess(g.n, g.row_ptr, g.col_idx, k)
+        x0 = oracle.initial_layout(g.row_ptr, g.col_idx, ref).astype(np.float32).astype(np.float64)
+        dg, *_, terms = _device_pipeline(g, k)
+        xg = torch.from_numpy(x0.astype(np.float32)).cuda()
+        ssm.majorize(dg, terms, xg, 40, sync=True)
+        xr, _ = oracle.majorize(g.row_ptr, g.col_idx, ref.pivots, ref.dist, ref.wtab, ref.den, x0, 40)
+        s32 = ssm.stress(dg, terms, xg)
+        sr = oracle.stress_sparse(g.row_ptr, g.col_idx, ref.pivots, ref.dist, ref.wtab, xr)
+        assert abs(s32 - sr) <= 1e-4 * sr, (s32, sr)
 
 
 TWIN_EDGES = [[0, 1], [1, 2], [2, 0], [3, 9], [3, 1], [9, 1], [3, 4], [9, 4], [3, 8], [9, 8],

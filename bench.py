@@ -34,6 +34,27 @@ WORKLOADS = {
 }
 
 HBM_PEAK_GBS = 8000.0
+PROFILE_LABEL = {"rgg": "rgg100k_k200", "ba": "ba1m_k200", "mesh": "mesh2000_k100", "grid": "grid50_k50"}
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE, calibrated by a copy kernel), or None when no
+    summary exists or the sweep source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{PROFILE_LABEL.get(workload, workload)}_sweep_f32_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("#", " ", "-")):
+            a, b = line.split(":", 1)
+            fields[a.strip()] = b.strip()
+    src = os.path.join(ROOT, "paper_1608_08909_amd", "csrc", "sweep.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if fields.get("sweep_source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
 
 
 def sweep_bytes(n: int, m: int, k: int, dbytes: int, prec: str) -> int:
@@ -193,8 +214,9 @@ def main():
         "fp64_sensitivity_to_fp32_rounded_start": band,
         "roofline": {"bound": "hbm", "kernel": "k_sweep_f32" if prec == ssm.FP32 else "k_sweep_f64",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": nbytes},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(args.workload) if prec == ssm.FP32 else None,
+                     "bytes_per_launch": nbytes, "launch_us": sweep_us},
     }
     if args.copy_calibration:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")

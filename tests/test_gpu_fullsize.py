@@ -1,0 +1,184 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times (the library's defaults): the random geometric graph (n = 99,882,
+k = 200), the Barabasi-Albert graph (n = 10^6, k = 200) and the holed mesh
+(n = 3.25 M, k = 100).
+
+What the oracle cannot recompute in seconds at these sizes is certified by
+properties that hold at any size:
+
+- a distance row d from source s is the BFS distance iff d(s) = 0, every edge
+  changes d by at most 1 and every other node has a neighbour with d - 1;
+- the pivots are max/min iff each next pivot is the lowest id attaining the
+  largest distance to the pivots before it (checked on certified rows).
+
+Everything else is compared with the oracle directly: sampled BFS rows, the
+regions, histograms, weight tables and denominators (bit-exact), one FP64
+sweep (bit-exact) and the FP32 final stress against the plain FP64 path.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_08909_amd import graphs as G
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_1608_08909_amd import ssm
+
+# name: (builder, k, sweeps) as in bench.py
+WORKLOADS = {
+    "rgg": (lambda: G.rgg(100000, 12345, 8.0), 200, 500),
+    "ba": (lambda: G.barabasi_albert(1000000, 5, 7), 200, 300),
+    "mesh": (lambda: G.holed_mesh(2000, 2000, 200, 10, 60, 12345), 100, 300),
+}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+class Run:
+    pass
+
+
+@pytest.fixture(scope="module", params=sorted(WORKLOADS))
+def run(request):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    name = request.param
+    build, k, iters = WORKLOADS[name]
+    say("full-size workload", name)
+    g = build()
+    r = Run()
+    r.name, r.g, r.k, r.iters = name, g, k, iters
+    r.dg = ssm.DeviceGraph.from_csr(g)
+    r.piv, r.dist_sel = ssm.select_pivots(r.dg, k, 0, with_dist=True)
+    r.dist, r.delta, r.region = ssm.bfs_pivots(r.dg, r.piv)
+    r.terms = ssm.build_terms(r.dg, r.piv, r.dist, r.delta, r.region)
+    torch.cuda.synchronize()
+    yield r
+    del r.terms, r.dist, r.dist_sel
+    torch.cuda.empty_cache()
+
+
+def _arcs(g):
+    src = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.row_ptr))
+    return torch.from_numpy(src).cuda(), torch.from_numpy(g.col_idx.astype(np.int64)).cuda()
+
+
+def _certify_bfs_rows(dist, piv, g):
+    """Every row of dist is the BFS distance from its pivot (see the module
+    docstring for the characterization)."""
+    k, n = dist.shape
+    src, dst = _arcs(g)
+    pv = piv.long()
+    assert torch.all(dist[torch.arange(k, device="cuda"), pv] == 0)
+    for t in range(k):
+        d = dist[t].long()
+        assert int(d.min()) >= 0 and int(d.max()) < n
+        du, dv = d[src], d[dst]
+        assert int((du - dv).abs().max()) <= 1, f"row {t}: an edge changes the distance by more than 1"
+        nb_min = torch.full((n,), n + 1, dtype=torch.long, device="cuda")
+        nb_min.scatter_reduce_(0, src, dv, reduce="amin")
+        ok = nb_min == d - 1
+        ok[pv[t]] = True
+        assert bool(ok.all()), f"row {t}: a node has no neighbour one step closer"
+
+
+def _certify_maxmin(dist, piv, first):
+    k, n = dist.shape
+    p = piv.long().cpu().numpy()
+    assert p[0] == first
+    ids = torch.arange(n, device="cuda", dtype=torch.long)
+    m = dist[0].long()
+    for t in range(1, k):
+        key = m * (1 << 32) + ((1 << 32) - 1 - ids)  # largest m, then lowest id
+        assert int(torch.argmax(key)) == p[t], f"pivot {t}"
+        m = torch.minimum(m, dist[t].long())
+
+
+def test_fullsize_preprocessing(run):
+    g, k = run.g, run.k
+    say("case", run.name, "n", g.n, "k", k)
+    assert torch.equal(run.dist_sel, run.dist)
+    _certify_bfs_rows(run.dist, run.piv, g)
+    _certify_maxmin(run.dist, run.piv, 0)
+    piv = run.piv.cpu().numpy()
+    dist = run.dist.cpu().numpy()
+    for t in sorted({0, 1, k // 2, k - 1}):  # sampled rows straight from the oracle
+        assert np.array_equal(dist[t], oracle.bfs(g.n, g.row_ptr, g.col_idx, int(piv[t])))
+    if g.n <= 200000:  # the whole selection by the oracle
+        piv_r, dist_r = oracle.select_pivots(g.n, g.row_ptr, g.col_idx, k, 0)
+        assert np.array_equal(piv, piv_r)
+        assert np.array_equal(dist, dist_r)
+    # regions and terms by the oracle from the certified distances
+    T = oracle.build_terms(g.row_ptr, g.col_idx, piv, dist)
+    assert np.array_equal(run.delta.cpu().numpy(), T.delta)
+    assert np.array_equal(run.region.cpu().numpy(), T.region)
+    ex = run.terms.export()
+    assert ex["delta_max"] == T.delta_max and ex["dmax"] == T.dmax
+    assert np.array_equal(ex["H"], T.H)
+    assert np.array_equal(ex["wtab64"], T.wtab)
+    assert np.array_equal(ex["wtab32"], T.wtab.astype(np.float32))
+    assert np.array_equal(ex["den64"], T.den)
+    assert np.array_equal(ex["den32"], T.den.astype(np.float32))
+
+
+def test_fullsize_sweeps(run):
+    """One FP64 sweep bit-exact against the oracle from the GPU's start
+    layout; the FP32 (mixed) layout after the benchmark's sweep count has the
+    plain FP64 path's final stress within 1e-4."""
+    g, k, iters = run.g, run.k, run.iters
+    say("case", run.name, "sweeps", iters)
+    x0 = ssm.pivotmds_init(run.dg, run.terms, ssm.FP64)
+    x0h = x0.cpu().numpy()
+    x1 = x0.clone()
+    ssm.majorize(run.dg, run.terms, x1, 1, sync=True)
+    piv = run.piv.cpu().numpy()
+    dist = run.dist.cpu().numpy()
+    ex = run.terms.export()
+    xr, _ = oracle.majorize(g.row_ptr, g.col_idx, piv, dist, ex["wtab64"], ex["den64"], x0h, 1)
+    assert np.array_equal(x1.cpu().numpy(), xr)
+    x64 = x0.clone()
+    ssm.majorize(run.dg, run.terms, x64, iters)
+    s64 = ssm.stress(run.dg, run.terms, x64)
+    x32 = ssm.majorize_mixed(run.dg, run.terms, x0.clone(), iters, warm=1)
+    s32 = ssm.stress(run.dg, run.terms, x32)
+    say("final stress", s64, s32, abs(s32 - s64) / s64)
+    assert abs(s32 - s64) <= 1e-4 * s64
+
+
+def test_fullsize_pivotmds(run):
+    """The Gram matrix against a plain FP64 product, the eigenvectors against
+    numpy's symmetric solver, the start layout against C V rescaled so that
+    the summed edge lengths equal m."""
+    g, k = run.g, run.k
+    say("case", run.name, "pivotmds")
+    x = ssm.pivotmds_init(run.dg, run.terms, ssm.FP64)
+    M = ssm.pivotmds_gram(run.terms)
+    V, lam, _ = ssm.pivotmds_eig(run.terms)
+    S = run.dist.double() ** 2                           # k x n
+    mu = S.mean(dim=1, keepdim=True)
+    nu = S.mean(dim=0, keepdim=True)
+    C = (-0.5 * (S - mu - nu + S.mean())).t().contiguous()  # n x k
+    Mr = (C.t() @ C).cpu().numpy()
+    assert np.abs(M - Mr).max() <= 1e-12 * np.abs(Mr).max()
+    w, E = np.linalg.eigh(Mr)
+    order = np.argsort(w)[::-1][:2]
+    assert np.allclose(lam, w[order], rtol=1e-10, atol=0)
+    gap = (w[order[1]] - w[np.argsort(w)[::-1][2]]) / w[order[0]]
+    for c in range(2):
+        e = E[:, order[c]]
+        i = int(np.argmax(np.abs(e)))
+        e = e if e[i] > 0 else -e
+        assert np.abs(V[:, c] - e).max() <= max(1e-9, 1e-12 / max(gap, 1e-300)), (c, gap)
+    Vt = torch.from_numpy(V).cuda()
+    xr = C @ Vt
+    src, dst = _arcs(g)
+    keep = src < dst
+    el = (xr[src[keep]] - xr[dst[keep]]).norm(dim=1).sum()
+    xr = xr * (g.m / el)
+    rms = float(xr.pow(2).sum(dim=1).mean().sqrt())
+    assert float((x - xr).norm(dim=1).max()) <= 1e-9 * rms

@@ -1,7 +1,11 @@
 // C ABI entry points of libssm: argument checks, error reporting, dispatch.
 #include <stdio.h>
 
+#include <algorithm>
+#include <mutex>
 #include <string>
+#include <unordered_map>
+#include <vector>
 
 #include "ssm_internal.h"
 
@@ -32,6 +36,77 @@ ssm_status dalloc(void** p, size_t bytes) {
         return fail(e == hipErrorOutOfMemory ? SSM_E_NOMEM : SSM_E_DEVICE, buf);
     }
     return SSM_OK;
+}
+
+// Scratch cache: buffers released by sfree stay allocated and serve later
+// salloc calls of at most four times smaller size on the same device, up to
+// kScratchCacheBytes in total (the largest are released first beyond it).
+// Every caller releases scratch only after synchronizing the stream that
+// used it, so a cached buffer is idle when it is handed out again.
+namespace {
+struct CachedBlock {
+    int dev;
+    void* p;
+    size_t bytes;
+};
+std::mutex g_scratch_mu;
+std::vector<CachedBlock> g_scratch_free;
+std::unordered_map<void*, CachedBlock> g_scratch_live;
+size_t g_scratch_free_bytes = 0;
+constexpr size_t kScratchCacheBytes = 8ull << 30;
+constexpr size_t kScratchGrain = 2u << 20;
+}  // namespace
+
+ssm_status salloc(void** p, size_t bytes) {
+    *p = nullptr;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    bytes = std::max<size_t>(bytes, 16);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    int best = -1;
+    for (int q = 0; q < (int)g_scratch_free.size(); ++q) {
+        const CachedBlock& b = g_scratch_free[q];
+        if (b.dev == dev && b.bytes >= bytes && b.bytes / 4 <= bytes &&
+            (best < 0 || b.bytes < g_scratch_free[best].bytes))
+            best = q;
+    }
+    if (best >= 0) {
+        CachedBlock b = g_scratch_free[best];
+        g_scratch_free.erase(g_scratch_free.begin() + best);
+        g_scratch_free_bytes -= b.bytes;
+        g_scratch_live[b.p] = b;
+        *p = b.p;
+        return SSM_OK;
+    }
+    const size_t rounded = (bytes + kScratchGrain - 1) / kScratchGrain * kScratchGrain;
+    ssm_status st = dalloc(p, rounded);
+    if (st != SSM_OK) return st;
+    g_scratch_live[*p] = CachedBlock{dev, *p, rounded};
+    return SSM_OK;
+}
+
+void sfree(void* p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_live.find(p);
+    if (it == g_scratch_live.end()) {
+        (void)hipFree(p);
+        return;
+    }
+    g_scratch_free.push_back(it->second);
+    g_scratch_free_bytes += it->second.bytes;
+    g_scratch_live.erase(it);
+    while (g_scratch_free_bytes > kScratchCacheBytes) {
+        auto big = std::max_element(g_scratch_free.begin(), g_scratch_free.end(),
+                                    [](const CachedBlock& a, const CachedBlock& b) { return a.bytes < b.bytes; });
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(big->dev);
+        (void)hipFree(big->p);
+        (void)hipSetDevice(cur);
+        g_scratch_free_bytes -= big->bytes;
+        g_scratch_free.erase(big);
+    }
 }
 
 ssm_status check_csr(const ssm_csr* g) {

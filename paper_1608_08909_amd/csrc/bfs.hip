@@ -245,7 +245,7 @@ ssm_status heavy_list(const ssm_csr* g, int** heavy, int32_t* count, hipStream_t
     *heavy = nullptr;
     *count = 0;
     int* buf = nullptr;  // counts[nb], total, ids[n]
-    ssm_status st = dalloc((void**)&buf, sizeof(int) * ((size_t)nb + 1 + n));
+    ssm_status st = salloc((void**)&buf, sizeof(int) * ((size_t)nb + 1 + n));
     if (st != SSM_OK) return st;
     int* counts = buf;
     int* total = buf + nb;
@@ -260,13 +260,14 @@ ssm_status heavy_list(const ssm_csr* g, int** heavy, int32_t* count, hipStream_t
     if (e == hipSuccess) {
         st = dalloc((void**)heavy, sizeof(int) * (size_t)std::max(nh, 1));
         if (st != SSM_OK) {
-            (void)hipFree(buf);
+            sfree(buf);  // the stream was synchronized above
             return st;
         }
         if (nh > 0) e = hipMemcpyAsync(*heavy, ids, sizeof(int) * (size_t)nh, hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
     }
-    (void)hipFree(buf);
+    (void)hipStreamSynchronize(s);  // idle before the scratch is reused (also after an error)
+    sfree(buf);
     if (e != hipSuccess) {
         if (*heavy) (void)hipFree(*heavy);
         *heavy = nullptr;
@@ -405,7 +406,7 @@ static ssm_status msbfs(const ssm_csr* g, int32_t k, const int32_t* pivots, int3
     const int n = g->n;
     *done = false;
     unsigned long long* buf = nullptr;
-    ssm_status st = dalloc((void**)&buf, sizeof(unsigned long long) * (3 * (size_t)n * NW + 8));
+    ssm_status st = salloc((void**)&buf, sizeof(unsigned long long) * (3 * (size_t)n * NW + 8));
     if (st != SSM_OK) return st;
     unsigned long long* vis = buf;
     unsigned long long* cur = vis + (size_t)n * NW;
@@ -422,7 +423,7 @@ static ssm_status msbfs(const ssm_csr* g, int32_t k, const int32_t* pivots, int3
     if (e == hipSuccess) {
         st = heavy_list(g, &heavy, &nheavy, s);
         if (st != SSM_OK) {
-            (void)hipFree(buf);
+            sfree(buf);
             return st;
         }
     }
@@ -453,7 +454,8 @@ static ssm_status msbfs(const ssm_csr* g, int32_t k, const int32_t* pivots, int3
         // a graph with many levels settles slowly: hand it to the per-workgroup BFS early
         if (level >= 3 && total < 0.2 * pairs) break;
     }
-    (void)hipFree(buf);
+    (void)hipStreamSynchronize(s);  // idle before the scratch is reused
+    sfree(buf);
     if (heavy) (void)hipFree(heavy);
     if (e != hipSuccess) return hip_fail(e, "bit-parallel BFS");
     *levels_out = level - 1;  // the last level found nothing
@@ -793,7 +795,7 @@ ssm_status mssp(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dis
         if (st != SSM_OK) return st;
         if (done) {
             int* bad = nullptr;
-            st = dalloc((void**)&bad, sizeof(int));
+            st = salloc((void**)&bad, sizeof(int));
             if (st != SSM_OK) return st;
             int hbad = 0;
             hipError_t e = hipMemsetAsync(bad, 0, sizeof(int), s);
@@ -805,7 +807,8 @@ ssm_status mssp(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dis
             }
             if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s);
             if (e == hipSuccess) e = hipStreamSynchronize(s);
-            (void)hipFree(bad);
+            (void)hipStreamSynchronize(s);
+            sfree(bad);
             if (e != hipSuccess) return hip_fail(e, "bit-parallel BFS check");
             if (hbad) return fail(SSM_E_DISCONNECTED, "graph is not connected (a BFS missed nodes)");
             *dmax_out_host = levels;
@@ -822,9 +825,9 @@ ssm_status mssp(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dis
         int* ell = nullptr;
         int* gq = nullptr;
         int* aux = nullptr;  // reached[k], ecc
-        ssm_status st = dalloc((void**)&ell, sizeof(int) * (size_t)n * W);
-        if (st == SSM_OK) st = dalloc((void**)&gq, sizeof(int) * 3 * (size_t)n * batch);
-        if (st == SSM_OK) st = dalloc((void**)&aux, sizeof(int) * ((size_t)k + 1));
+        ssm_status st = salloc((void**)&ell, sizeof(int) * (size_t)n * W);
+        if (st == SSM_OK) st = salloc((void**)&gq, sizeof(int) * 3 * (size_t)n * batch);
+        if (st == SSM_OK) st = salloc((void**)&aux, sizeof(int) * ((size_t)k + 1));
         hipError_t e = hipSuccess;
         std::vector<int> host((size_t)k + 1);
         if (st == SSM_OK) {
@@ -839,9 +842,10 @@ ssm_status mssp(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dis
                 e = hipMemcpyAsync(host.data(), aux, sizeof(int) * ((size_t)k + 1), hipMemcpyDeviceToHost, s);
             if (e == hipSuccess) e = hipStreamSynchronize(s);
         }
-        if (ell) (void)hipFree(ell);
-        if (gq) (void)hipFree(gq);
-        if (aux) (void)hipFree(aux);
+        (void)hipStreamSynchronize(s);  // idle before the scratch is reused
+        if (ell) sfree(ell);
+        if (gq) sfree(gq);
+        if (aux) sfree(aux);
         if (st != SSM_OK) return st;
         if (e != hipSuccess) return hip_fail(e, "multi-source BFS");
         for (int t = 0; t < k; ++t)
@@ -854,11 +858,11 @@ ssm_status mssp(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dis
     int batch = (int)std::max<long long>(1, std::min<long long>(k, qcap / (2LL * n)));
     int2* queues = nullptr;
     int* aux = nullptr;  // reached[k], ecc
-    ssm_status st = dalloc((void**)&queues, sizeof(int2) * 2 * (size_t)n * batch);
+    ssm_status st = salloc((void**)&queues, sizeof(int2) * 2 * (size_t)n * batch);
     if (st != SSM_OK) return st;
-    st = dalloc((void**)&aux, sizeof(int) * ((size_t)k + 1));
+    st = salloc((void**)&aux, sizeof(int) * ((size_t)k + 1));
     if (st != SSM_OK) {
-        (void)hipFree(queues);
+        sfree(queues);
         return st;
     }
     hipError_t e = hipMemsetAsync(dist, 0xff, sizeof(int) * (size_t)k * n, s);
@@ -883,9 +887,9 @@ ssm_status mssp(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dis
     std::vector<int> host((size_t)k + 1);
     if (e == hipSuccess)
         e = hipMemcpyAsync(host.data(), aux, sizeof(int) * ((size_t)k + 1), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(queues);
-    (void)hipFree(aux);
+    (void)hipStreamSynchronize(s);  // idle before the scratch is reused (also after an error)
+    sfree(queues);
+    sfree(aux);
     if (e != hipSuccess) return hip_fail(e, "multi-source BFS");
     for (int t = 0; t < k; ++t)
         if (host[t] != n) return fail(SSM_E_DISCONNECTED, "graph is not connected (a BFS missed nodes)");
@@ -1456,11 +1460,11 @@ ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pi
     size_t ints = 6 * (size_t)n + 8;
     int* ws = nullptr;
     unsigned long long* keys = nullptr;
-    ssm_status st = dalloc((void**)&ws, sizeof(int) * ints);
+    ssm_status st = salloc((void**)&ws, sizeof(int) * ints);
     if (st != SSM_OK) return st;
-    st = dalloc((void**)&keys, sizeof(unsigned long long) * blocks);
+    st = salloc((void**)&keys, sizeof(unsigned long long) * blocks);
     if (st != SSM_OK) {
-        (void)hipFree(ws);
+        sfree(ws);
         return st;
     }
     int* m = ws;
@@ -1486,10 +1490,11 @@ ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pi
     const bool use_ell = mode == 1 && sel_bits_fit(n) && env_int("SSM_SELECT_ELL") != 2;
     const int W = ell_width(g);
     if (use_ell && e == hipSuccess) {
-        st = dalloc((void**)&ell, sizeof(int) * (size_t)n * W);
+        st = salloc((void**)&ell, sizeof(int) * (size_t)n * W);
         if (st != SSM_OK) {
-            (void)hipFree(ws);
-            (void)hipFree(keys);
+            (void)hipStreamSynchronize(s);  // fills queued on ws: idle before reuse
+            sfree(ws);
+            sfree(keys);
             return st;
         }
         e = ell_build(g, W, ell, s);
@@ -1522,10 +1527,10 @@ ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pi
     }
     int hstatus = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&hstatus, status, sizeof(int), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(ws);
-    (void)hipFree(keys);
-    if (ell) (void)hipFree(ell);
+    (void)hipStreamSynchronize(s);  // idle before the scratch is reused (also after an error)
+    sfree(ws);
+    sfree(keys);
+    if (ell) sfree(ell);
     if (e != hipSuccess) return hip_fail(e, "pivot selection");
     if (hstatus) return fail(SSM_E_DISCONNECTED, "graph is not connected (the first BFS missed nodes)");
     return SSM_OK;
@@ -1814,11 +1819,11 @@ ssm_status regions(int32_t n, int32_t k, const int32_t* dist, int32_t* delta, in
                    hipStream_t s) {
     int4* cand = nullptr;
     int* aux = nullptr;
-    ssm_status st = dalloc((void**)&cand, sizeof(int4) * (size_t)n);
+    ssm_status st = salloc((void**)&cand, sizeof(int4) * (size_t)n);
     if (st != SSM_OK) return st;
-    st = dalloc((void**)&aux, sizeof(int) * 2);
+    st = salloc((void**)&aux, sizeof(int) * 2);
     if (st != SSM_OK) {
-        (void)hipFree(cand);
+        sfree(cand);
         return st;
     }
     int grid = std::min(div_up(n, 256), 8192);
@@ -1831,8 +1836,8 @@ ssm_status regions(int32_t n, int32_t k, const int32_t* dist, int32_t* delta, in
     if (e == hipSuccess) e = hipMemcpyAsync(haux, aux, sizeof haux, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
-        (void)hipFree(cand);
-        (void)hipFree(aux);
+        sfree(cand);
+        sfree(aux);
         return hip_fail(e, "region scan");
     }
     if (haux[1] > 0) {
@@ -1840,10 +1845,10 @@ ssm_status regions(int32_t n, int32_t k, const int32_t* dist, int32_t* delta, in
         // U[k][L], tcount[L], tstart[L+1], cursor[L], list[ntied], cum[k], Tl[k]
         size_t ints = (size_t)k * L + 3 * (size_t)L + 1 + (size_t)haux[1] + 2 * (size_t)k;
         int* ws = nullptr;
-        st = dalloc((void**)&ws, sizeof(int) * ints);
+        st = salloc((void**)&ws, sizeof(int) * ints);
         if (st != SSM_OK) {
-            (void)hipFree(cand);
-            (void)hipFree(aux);
+            sfree(cand);
+            sfree(aux);
             return st;
         }
         int* U = ws;
@@ -1886,11 +1891,11 @@ ssm_status regions(int32_t n, int32_t k, const int32_t* dist, int32_t* delta, in
             // Tc[2][k] double buffer, Tj[nlev][k]
             int* ws2 = nullptr;
             if (e == hipSuccess) {
-                st = dalloc((void**)&ws2, sizeof(int) * (size_t)k * (2 + nlev));
-                if (st != SSM_OK) {
-                    (void)hipFree(ws);
-                    (void)hipFree(cand);
-                    (void)hipFree(aux);
+                st = salloc((void**)&ws2, sizeof(int) * (size_t)k * (2 + nlev));
+                if (st != SSM_OK) {  // the stream was synchronized above
+                    sfree(ws);
+                    sfree(cand);
+                    sfree(aux);
                     return st;
                 }
                 e = hipMemsetAsync(ws2, 0, sizeof(int) * (size_t)k * (2 + nlev), s);
@@ -1917,13 +1922,15 @@ ssm_status regions(int32_t n, int32_t k, const int32_t* dist, int32_t* delta, in
                 e = hipGetLastError();
             }
             if (e == hipSuccess) e = hipStreamSynchronize(s);
-            if (ws2) (void)hipFree(ws2);
+            if (ws2) sfree(ws2);
         }
         if (e == hipSuccess) e = hipStreamSynchronize(s);
-        (void)hipFree(ws);
+        (void)hipStreamSynchronize(s);  // idle before the scratch is reused (also after an error)
+        sfree(ws);
     }
-    (void)hipFree(cand);
-    (void)hipFree(aux);
+    (void)hipStreamSynchronize(s);
+    sfree(cand);
+    sfree(aux);
     if (e != hipSuccess) return hip_fail(e, "region assignment");
     return SSM_OK;
 }
@@ -1935,7 +1942,7 @@ extern "C" ssm_status ssm_validate_csr(const ssm_csr* g, hipStream_t stream) {
     ssm_status st = check_csr(g);
     if (st != SSM_OK) return st;
     int* bad = nullptr;
-    st = dalloc((void**)&bad, sizeof(int));
+    st = salloc((void**)&bad, sizeof(int));
     if (st != SSM_OK) return st;
     int hbad = 0;
     hipError_t e = hipMemsetAsync(bad, 0, sizeof(int), stream);
@@ -1946,7 +1953,8 @@ extern "C" ssm_status ssm_validate_csr(const ssm_csr* g, hipStream_t stream) {
     }
     if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    (void)hipFree(bad);
+    (void)hipStreamSynchronize(stream);
+    sfree(bad);
     if (e != hipSuccess) return hip_fail(e, "CSR validation");
     if (hbad & 1) return fail(SSM_E_INVAL, "row_ptr is not monotone from 0 to nnz");
     if (hbad & 2) return fail(SSM_E_INVAL, "column index out of range or self-loop");

@@ -466,7 +466,7 @@ ssm_status pivotmds(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* x, hipStre
                    sizeof(double) * (size_t)nchunks * ntiles * 256 + sizeof(int2) * ntiles +
                    sizeof(double) * ((size_t)eblocks + 2) + 64 * 8;
     char* ws = nullptr;
-    ssm_status st = dalloc((void**)&ws, bytes);
+    ssm_status st = salloc((void**)&ws, bytes);
     if (st != SSM_OK) return st;
     char* cur = ws;
     auto take = [&](size_t b) {
@@ -535,7 +535,8 @@ ssm_status pivotmds(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* x, hipStre
     int hflag = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(ws);
+    (void)hipStreamSynchronize(s);  // idle before the scratch is reused (also after an error)
+    sfree(ws);
     if (e != hipSuccess) return hip_fail(e, "PivotMDS");
     if (hflag) return fail(SSM_E_INVAL, "PivotMDS layout has zero total edge length; cannot rescale");
     return SSM_OK;

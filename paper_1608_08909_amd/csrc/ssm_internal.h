@@ -70,6 +70,12 @@ ssm_status check_csr(const ssm_csr* g);
 // Device scratch: allocation helper that reports SSM_E_NOMEM.
 ssm_status dalloc(void** p, size_t bytes);
 
+// Scratch for the duration of one call: salloc may hand out a cached buffer
+// (contents undefined); sfree returns it to the cache.  Release only after
+// the stream that used the buffer has been synchronized.
+ssm_status salloc(void** p, size_t bytes);
+void sfree(void* p);
+
 // ---- BFS / regions (bfs.hip)
 ssm_status mssp(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dist,
                 int32_t* dmax_out_host, hipStream_t s);

@@ -531,11 +531,19 @@ struct Frontier {
     const int* gcur;
     int* lnxt;  // next frontier
     int* gnxt;
-    int* tail;  // LDS size counter of the next frontier
+    int2* cnt;  // LDS counters of the level: x = long rows listed, y = size of the next frontier
     int* lheavy;  // long rows of the current frontier: LDS part, global part
     int* gheavy;
-    int* nheavy;  // LDS counter of those
 };
+
+// Level counters rotate over three int2 slots: level l counts into slot
+// l % 3, reads it once after its barrier and clears slot (l + 1) % 3 at its
+// start (last read two levels earlier, a barrier ago), so one barrier and
+// one LDS read per level suffice.
+__device__ __forceinline__ void level_begin(int2* slots, int level, Frontier& f) {
+    if (threadIdx.x == 0) slots[(level + 1) % 3] = make_int2(0, 0);
+    f.cnt = &slots[level % 3];
+}
 
 // Entry i of a list split into an LDS part (first CAP entries) and a global
 // part.  The explicit address spaces keep the two loads apart (a select of
@@ -546,7 +554,6 @@ __device__ __forceinline__ int split_get(const int* l, const int* g, int i) {
     return ((const __attribute__((address_space(1))) int*)g)[i - CAP];
 }
 
-__device__ __forceinline__ int q_get(const int* l, const int* g, int i) { return split_get<kLdsQ>(l, g, i); }
 
 // Claims u[0..N) in the visited bits (one batch of LDS atomics); ok[j] is
 // set where this lane claimed u[j] now.
@@ -575,7 +582,7 @@ __device__ __forceinline__ void append(const int (&u)[N], const bool (&ok)[N], c
     }
     if (tot == 0) return;
     int at = 0;
-    if (lane_id() == 0) at = atomicAdd(f.tail, tot);
+    if (lane_id() == 0) at = atomicAdd(&f.cnt->y, tot);
     at = __builtin_amdgcn_readfirstlane(at);  // lane 0 is active: every lane is
 #pragma unroll
     for (int j = 0; j < N; ++j) {
@@ -594,21 +601,29 @@ __device__ __forceinline__ void append(const int (&u)[N], const bool (&ok)[N], c
 // P frontier nodes per pass (P row loads in flight per lane).
 // take(u, ok) claims the neighbours u[j] (entries outside [0, n) are
 // padding) and sets ok[j] for those that join the next frontier.  Ends with
-// every thread past a barrier and the next frontier complete.  Call from
-// uniform control flow with blockDim.x a multiple of 64.
-template <int W, int P, typename Take>
-__device__ __forceinline__ void ell_level(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                          const int* __restrict__ ell, int len, const Frontier& f, Take take) {
+// every thread past a barrier and the next frontier complete; returns its
+// size.  Call from uniform control flow with blockDim.x a multiple of 64.
+template <int W, int P, bool GLOBAL_PART, typename Take>
+__device__ __forceinline__ void ell_passes(int n, const int* __restrict__ ell, int qbeg, int qend, const Frontier& f,
+                                           Take& take) {
     constexpr int VW = W / 4;
-    static_assert(VW >= 1 && VW <= kWave && (kWave % VW) == 0, "lanes per node");
     const int sub = threadIdx.x % VW, grp = threadIdx.x / VW, ngrp = blockDim.x / VW;
-    for (int base = 0; base < len; base += P * ngrp) {
+    const int wave_grp0 = __builtin_amdgcn_readfirstlane(grp - lane_id() / VW);  // first group of this wave
+    for (int base = qbeg; base < qend; base += P * ngrp) {
+        if (base + wave_grp0 >= qend) break;  // uniform per wave: no node of this pass (nor of later ones) here
         int4 nb[P];
         int v[P];
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             const int qi = base + p * ngrp + grp;
-            v[p] = qi < len ? q_get(f.lcur, f.gcur, qi) : -1;
+            // the LDS part and the global part of the queue are walked by
+            // separate passes: a register written by either a global or an
+            // LDS load would make every LDS read wait for all outstanding
+            // global stores
+            if (GLOBAL_PART)
+                v[p] = qi < qend ? ((const __attribute__((address_space(1))) int*)f.gcur)[qi - kLdsQ] : -1;
+            else
+                v[p] = qi < qend ? ((const __attribute__((address_space(3))) int*)f.lcur)[qi] : -1;
             nb[p] = make_int4(-1, -1, -1, -1);
             if ((unsigned)v[p] < (unsigned)n) nb[p] = *(const int4*)(ell + (size_t)v[p] * W + 4 * sub);
         }
@@ -616,7 +631,7 @@ __device__ __forceinline__ void ell_level(int n, const int* __restrict__ rp, con
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             if (sub == VW - 1 && nb[p].w == kEllMore) {
-                const int h = atomicAdd(f.nheavy, 1);
+                const int h = atomicAdd(&f.cnt->x, 1);
                 if (h < kHeavyCap)
                     f.lheavy[h] = v[p];
                 else
@@ -631,8 +646,23 @@ __device__ __forceinline__ void ell_level(int n, const int* __restrict__ rp, con
         take(u, ok);
         append(u, ok, f);
     }
+}
+
+// One level over the current frontier [0, len): each group of W/4 lanes takes
+// P frontier nodes per pass (P row loads in flight per lane).
+// take(u, ok) claims the neighbours u[j] (entries outside [0, n) are
+// padding) and sets ok[j] for those that join the next frontier.  Ends with
+// every thread past a barrier and the next frontier complete; returns its
+// size.  Call from uniform control flow with blockDim.x a multiple of 64.
+template <int W, int P, typename Take>
+__device__ __forceinline__ int ell_level(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                         const int* __restrict__ ell, int len, const Frontier& f, Take take) {
+    static_assert(W / 4 >= 1 && W / 4 <= kWave && (kWave % (W / 4)) == 0, "lanes per node");
+    ell_passes<W, P, false>(n, ell, 0, min(len, kLdsQ), f, take);
+    if (len > kLdsQ) ell_passes<W, P, true>(n, ell, kLdsQ, len, f, take);  // uniform
     __syncthreads();
-    const int nh = min(*f.nheavy, n);
+    const int2 c = *f.cnt;  // long rows, next frontier so far
+    const int nh = min(c.x, n);
     if (nh > 0) {  // uniform
         const int wave = threadIdx.x / kWave, nwaves = blockDim.x / kWave, lane = lane_id();
         for (int h = wave; h < nh; h += nwaves) {
@@ -651,18 +681,18 @@ __device__ __forceinline__ void ell_level(int n, const int* __restrict__ rp, con
             }
         }
         __syncthreads();
+        return min(f.cnt->y, n);
     }
+    return min(c.y, n);
 }
 
 // ell_level with P = 4 rows per lane group and pass for frontiers wider than
 // one pass, P = 1 otherwise (uniform choice).
 template <int W, typename Take>
-__device__ __forceinline__ void ell_level_auto(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                               const int* __restrict__ ell, int len, const Frontier& f, Take take) {
-    if (len > (int)blockDim.x / (W / 4))
-        ell_level<W, 4>(n, rp, ci, ell, len, f, take);
-    else
-        ell_level<W, 1>(n, rp, ci, ell, len, f, take);
+__device__ __forceinline__ int ell_level_auto(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                              const int* __restrict__ ell, int len, const Frontier& f, Take take) {
+    if (len > (int)blockDim.x / (W / 4)) return ell_level<W, 4>(n, rp, ci, ell, len, f, take);
+    return ell_level<W, 1>(n, rp, ci, ell, len, f, take);
 }
 
 // Block b: BFS from pivots[b] writing dist[b][*] for every node it reaches,
@@ -674,7 +704,7 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_ell(int n, const int* __restr
                                                        const int* __restrict__ ell, const int* __restrict__ pivots,
                                                        int* dist, int* gq, int* reached, int* ecc_max) {
     __shared__ __align__(16) unsigned char pool[POOL];
-    __shared__ int s_cnt[3], s_nh[3];
+    __shared__ int2 s_slot[3];
     int* qa = (int*)pool;
     int* qb = qa + kLdsQ;
     int* lheavy = qb + kLdsQ;
@@ -692,34 +722,22 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_ell(int n, const int* __restr
         D[src] = 0;
         bits[src >> 5] |= 1u << (src & 31);
         qa[0] = src;
-        s_cnt[0] = 1;
-        s_cnt[1] = s_cnt[2] = 0;
-        s_nh[0] = s_nh[1] = s_nh[2] = 0;
+        s_slot[0] = make_int2(0, 0);
     }
     __syncthreads();
-    Frontier f{qa, ga, qb, gb, nullptr, lheavy, gh, nullptr};
-    int level = 0, total = 1;
-    for (;; ++level) {
-        // Counters rotate over three slots so that one barrier per level
-        // suffices: level l reads s_cnt[l%3], appends to s_cnt[(l+1)%3],
-        // lists long rows in s_nh[l%3]; slots used two levels ago are cleared.
-        const int len = min(s_cnt[level % 3], n);
-        if (len == 0) break;
-        if (threadIdx.x == 0) {
-            s_cnt[(level + 2) % 3] = 0;
-            s_nh[(level + 1) % 3] = 0;
-        }
-        f.tail = &s_cnt[(level + 1) % 3];
-        f.nheavy = &s_nh[level % 3];
+    Frontier f{qa, ga, qb, gb, nullptr, lheavy, gh};
+    int level = 0, total = 1, len = 1;
+    for (; len > 0; ++level) {
+        level_begin(s_slot, level, f);
         const int dv = level + 1;
-        ell_level_auto<W>(n, rp, ci, ell, len, f, [&](const auto& u, auto& ok) {
+        len = ell_level_auto<W>(n, rp, ci, ell, len, f, [&](const auto& u, auto& ok) {
             constexpr int N = sizeof(u) / sizeof(u[0]);
             claim(u, ok, bits, n);
 #pragma unroll
             for (int j = 0; j < N; ++j)
                 if (ok[j]) D[u[j]] = dv;
         });
-        total += s_cnt[(level + 1) % 3];
+        total += len;
         const int* tl = f.lcur;
         f.lcur = f.lnxt;
         f.lnxt = (int*)tl;
@@ -1171,16 +1189,15 @@ __global__ __launch_bounds__(kBfsBlock) void k_select_wg(int n, const int* __res
 
 // ----------------------------------- one-workgroup selection, LDS-resident
 
-// LDS pool of k_select_ell: the frontier queues, the long-row list, the
-// visited bits and, when it fits, a byte copy of m saturated at kM8Sat.
+// LDS pool of k_select_ell: the frontier queues, the long-row list and
+// either (M8) one state byte per node or (otherwise) one visited bit per
+// node.  The state byte holds min(m, kM7Sat) in bits 0-6 and the visited
+// flag of the running BFS in bit 7.
 constexpr int kSelPool = 155648;
-constexpr int kM8Sat = 255;
+constexpr int kM7Sat = 127;
 
 static bool sel_bits_fit(int n) { return kLdsFixed + lds_bits_bytes(n) <= (size_t)kSelPool; }
-static size_t sel_bits_words_padded(int n) { return (((size_t)n + 31) / 32 + 3) & ~(size_t)3; }
-static bool sel_m8_fits(int n) {
-    return kLdsFixed + 4 * sel_bits_words_padded(n) + (((size_t)n + 15) & ~(size_t)15) <= (size_t)kSelPool;
-}
+static bool sel_m8_fits(int n) { return kLdsFixed + (((size_t)n + 15) & ~(size_t)15) <= (size_t)kSelPool; }
 
 // Key of node i with value m for the argmax: the largest m wins, then the
 // lowest id.
@@ -1220,20 +1237,41 @@ __device__ __forceinline__ unsigned long long argmax_m_global(const int* __restr
     return best;
 }
 
-// Same over the LDS byte copy (16 bytes per read).  m8 is 16-byte aligned
-// and padded with zeros to a multiple of 16 bytes.
-__device__ __forceinline__ unsigned long long argmax_m8(const unsigned char* m8, int n) {
-    const uint4* w16 = (const uint4*)m8;
+// Exact argmax when the state bytes saturate: a byte below kM7Sat is the
+// value, a saturated byte defers to global m (which holds every value of 127
+// and above; it is not kept current below).
+__device__ __forceinline__ unsigned long long argmax_m7_global(const unsigned char* m8, const int* __restrict__ m,
+                                                               int n) {
+    unsigned long long best = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int b = m8[i] & 0x7f;
+        const int v = b < kM7Sat ? b : m[i];
+        const unsigned long long key = argmax_key(v, i);
+        if (key > best) best = key;
+    }
+    return best;
+}
+
+// Same over the LDS state bytes (16 bytes per read): the value is bits 0-6;
+// the pass also clears the visited flags (bit 7) for the next BFS.  The
+// bytes are 16-byte aligned and padded with zeros to a multiple of 16.
+__device__ __forceinline__ unsigned long long argmax_m7_clear(unsigned char* m8, int n) {
+    uint4* w16 = (uint4*)m8;
     const int nw = (n + 15) / 16;
     int bv = -1, bi = 0;
     for (int w = threadIdx.x; w < nw; w += blockDim.x) {
-        const uint4 q = w16[w];
+        uint4 q = w16[w];
+        q.x &= 0x7f7f7f7fu;
+        q.y &= 0x7f7f7f7fu;
+        q.z &= 0x7f7f7f7fu;
+        q.w &= 0x7f7f7f7fu;
+        w16[w] = q;
         const unsigned part[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                const int val = (int)((part[a] >> (8 * b)) & 255u);
+                const int val = (int)((part[a] >> (8 * b)) & 127u);
                 if (val > bv) {
                     bv = val;
                     bi = 16 * w + 4 * a + b;
@@ -1246,79 +1284,105 @@ __device__ __forceinline__ unsigned long long argmax_m8(const unsigned char* m8,
 
 // All k pivots in one workgroup: for each new pivot the BFS that only
 // continues through nodes whose distance to it is below m (as k_select_all),
-// on LDS-resident levels (LDS visited bits; the claiming lane owns m[v]
-// for the level and writes it with plain stores).  With M8 the pruning test
-// m[v] > dv reads an LDS byte copy of m (exact below kM8Sat, global m above)
-// and the argmax scans the byte copy unless its maximum is saturated.
-// gq holds 3 n ints.
+// on LDS-resident levels.
+//   M8: one LDS state byte per node.  A claim is one LDS atomic OR that sets
+//       the node's visited flag and returns its old byte, i.e. the flag and
+//       min(m, 127) together; below 127 the pruning test m > dv is exact on
+//       the byte, at or above it global m decides.  The argmax scans the
+//       bytes (and clears the flags) unless the maximum is saturated.
+//   otherwise: LDS visited bits, global m.
+// The claiming lane owns m[v] for the level and writes it with plain
+// stores.  gq holds 3 n ints.
 template <int W, bool M8>
 __global__ __launch_bounds__(kBfsBlock) void k_select_ell(int n, const int* __restrict__ rp,
                                                           const int* __restrict__ ci, const int* __restrict__ ell,
                                                           int k, int first, int* pivots, int* m, int* gq,
                                                           int* status) {
     __shared__ __align__(16) unsigned char pool[kSelPool];
-    __shared__ int s_cnt[3], s_nh[3];
+    __shared__ int2 s_slot[3];
     __shared__ int s_src;
     __shared__ unsigned long long s_red[kBfsBlock / kWave];
     int* qa = (int*)pool;
     int* qb = qa + kLdsQ;
     int* lheavy = qb + kLdsQ;
-    unsigned* bits = (unsigned*)(lheavy + kHeavyCap);
+    unsigned* bits = (unsigned*)(lheavy + kHeavyCap);  // !M8: visited bits
+    unsigned char* m8 = (unsigned char*)bits;          // M8: state bytes (16-byte aligned)
     const int nbw = (n + 31) / 32;
-    unsigned char* m8 = (unsigned char*)(bits + ((nbw + 3) & ~3));  // 16-byte aligned
     int* ga = gq;
     int* gb = gq + n;
     int* gh = gb + n;
 
     if (M8)
-        for (int i = threadIdx.x; i < ((n + 15) & ~15); i += blockDim.x) m8[i] = i < n ? (unsigned char)kM8Sat : 0;
+        for (int i = threadIdx.x; i < ((n + 15) & ~15); i += blockDim.x) m8[i] = i < n ? (unsigned char)kM7Sat : 0;
     if (threadIdx.x == 0) s_src = first;
     __syncthreads();
     for (int t = 0; t < k; ++t) {
         const int src = s_src;
-        for (int w = threadIdx.x; w < nbw; w += blockDim.x) bits[w] = 0u;
+        if (!M8)
+            for (int w = threadIdx.x; w < nbw; w += blockDim.x) bits[w] = 0u;
         __syncthreads();
         if (threadIdx.x == 0) {
             pivots[t] = src;
             m[src] = 0;
-            if (M8) m8[src] = 0;
-            bits[src >> 5] |= 1u << (src & 31);
+            if (M8)
+                m8[src] = 0x80;  // m = 0, visited
+            else
+                bits[src >> 5] |= 1u << (src & 31);
             qa[0] = src;
-            s_cnt[0] = 1;
-            s_cnt[1] = s_cnt[2] = 0;
-            s_nh[0] = s_nh[1] = s_nh[2] = 0;
+            s_slot[0] = make_int2(0, 0);
         }
         __syncthreads();
-        Frontier f{qa, ga, qb, gb, nullptr, lheavy, gh, nullptr};
-        for (int level = 0;; ++level) {
-            const int len = min(s_cnt[level % 3], n);  // rotating counters as in k_bfs_ell
-            if (len == 0) break;
-            if (threadIdx.x == 0) {
-                s_cnt[(level + 2) % 3] = 0;
-                s_nh[(level + 1) % 3] = 0;
-            }
-            f.tail = &s_cnt[(level + 1) % 3];
-            f.nheavy = &s_nh[level % 3];
+        Frontier f{qa, ga, qb, gb, nullptr, lheavy, gh};
+        int len = 1;
+        for (int level = 0; len > 0; ++level) {
+            level_begin(s_slot, level, f);
             const int dv = level + 1;
-            ell_level_auto<W>(n, rp, ci, ell, len, f, [&](const auto& u, auto& ok) {
+            len = ell_level_auto<W>(n, rp, ci, ell, len, f, [&](const auto& u, auto& ok) {
                 constexpr int N = sizeof(u) / sizeof(u[0]);
-                claim(u, ok, bits, n);
-                // all reads first, then all stores: a wait for a read must
-                // not also wait for this level's stores
                 int mv[N];
-                if (M8 && dv < kM8Sat) {  // uniform: the byte copy decides (255 means >= 255 > dv)
+                if (M8) {
+                    // claim and read the old state byte with one atomic per node
+                    unsigned old[N];
 #pragma unroll
-                    for (int j = 0; j < N; ++j) mv[j] = ok[j] ? (int)m8[u[j]] : 0;
+                    for (int j = 0; j < N; ++j) {
+                        ok[j] = (unsigned)u[j] < (unsigned)n;  // padding, continuation mark, bad index
+                        const int sh = 8 * (u[j] & 3);
+                        old[j] = ok[j] ? atomicOr((unsigned*)(m8 + (u[j] & ~3)), 0x80u << sh) : 0x80u;
+                    }
+#pragma unroll
+                    for (int j = 0; j < N; ++j) {
+                        const unsigned ob = (old[j] >> (8 * (u[j] & 3))) & 0xffu;
+                        ok[j] = ok[j] && !(ob & 0x80u);
+                        mv[j] = (int)(ob & 0x7fu);
+                    }
+                    if (dv >= kM7Sat) {  // uniform: the byte is saturated, global m decides
+#pragma unroll
+                        for (int j = 0; j < N; ++j)
+                            if (ok[j] && mv[j] >= kM7Sat) mv[j] = m[u[j]];
+                    }
+#pragma unroll
+                    for (int j = 0; j < N; ++j) {
+                        // a saturated byte below level 127 means m >= 127 > dv
+                        ok[j] = ok[j] && (mv[j] > dv || (mv[j] >= kM7Sat && dv < kM7Sat));
+                        if (ok[j]) m8[u[j]] = (unsigned char)(0x80 | min(dv, kM7Sat));
+                    }
+                    // global m only holds the values the byte cannot (>= 127):
+                    // no global store on the levels below 127
+                    if (dv >= kM7Sat) {  // uniform
+#pragma unroll
+                        for (int j = 0; j < N; ++j)
+                            if (ok[j]) m[u[j]] = dv;
+                    }
                 } else {
+                    claim(u, ok, bits, n);
+                    // all reads first, then all stores: a wait for a read must
+                    // not also wait for this level's stores
 #pragma unroll
                     for (int j = 0; j < N; ++j) mv[j] = ok[j] ? m[u[j]] : 0;
-                }
 #pragma unroll
-                for (int j = 0; j < N; ++j) {
-                    ok[j] = ok[j] && mv[j] > dv;
-                    if (ok[j]) {
-                        if (M8) m8[u[j]] = (unsigned char)min(dv, kM8Sat);
-                        m[u[j]] = dv;
+                    for (int j = 0; j < N; ++j) {
+                        ok[j] = ok[j] && mv[j] > dv;
+                        if (ok[j]) m[u[j]] = dv;
                     }
                 }
             });
@@ -1332,8 +1396,8 @@ __global__ __launch_bounds__(kBfsBlock) void k_select_ell(int n, const int* __re
         if (t + 1 >= k && t != 0) break;
         unsigned long long best;
         if (M8) {
-            best = block_max(argmax_m8(m8, n), s_red);
-            if ((int)(best >> 32) == kM8Sat) best = block_max(argmax_m_global(m, n), s_red);  // uniform
+            best = block_max(argmax_m7_clear(m8, n), s_red);
+            if ((int)(best >> 32) >= kM7Sat) best = block_max(argmax_m7_global(m8, m, n), s_red);  // uniform
         } else {
             best = block_max(argmax_m_global(m, n), s_red);
         }

@@ -72,6 +72,7 @@ def _load():
                 "orc_majorize": (I, [I, P, P, I, P, P, P, I, P, P, I, D, I, I, P]),
                 "orc_stress_sparse": (D, [I, P, P, I, P, P, P, I, P, P]),
                 "orc_stress_full": (D, [I, P, P, P]),
+                "orc_kmeans_sp": (I, [I, I, P, P, I, P, P, P]),
             }
             for name, (res, args) in sig.items():
                 f = getattr(lib, name)
@@ -239,6 +240,20 @@ def stress_sparse(row_ptr, col_idx, pivots, dist, wtab, x, parts: bool = False):
 def stress_full(row_ptr, col_idx, x) -> float:
     rp, ci, x = _i32(row_ptr), _i32(col_idx), _f64(x)
     return _load().orc_stress_full(x.shape[0], _p(rp), _p(ci), _p(x))
+
+
+def kmeans_sp(dist, pivots, max_iters: int = 50):
+    """k-means sp refinement of max/min pivots (Section 4.1): returns
+    (new_pivots[k], assign[n], iterations)."""
+    dist, pv = _i32(dist), _i32(pivots)
+    k, n = dist.shape
+    newp = np.empty(k, dtype=np.int32)
+    assign = np.empty(n, dtype=np.int32)
+    it = ctypes.c_int(0)
+    st = _load().orc_kmeans_sp(n, k, _p(dist), _p(pv), int(max_iters), _p(newp), _p(assign), ctypes.byref(it))
+    if st != OK:
+        raise OracleError(st, "kmeans_sp")
+    return newp, assign, int(it.value)
 
 
 # ----------------------------------------------------------------- pipeline

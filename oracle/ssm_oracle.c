@@ -540,3 +540,119 @@ double orc_stress_full(int n, const int* rp, const int* ci, const double* x) {
     free(d);
     return s;
 }
+
+/* ------------------------------------------------------------ k-means sp
+ *
+ * Section 4.1, "k-means sp": k pivots are first sampled by max/min sp, then
+ * refined by k-means over the shortest-path entries of those pivots.  The
+ * paper gives no more detail; the reading implemented here (listed in the
+ * design notes):
+ *   - node i's feature vector is y_i = (D[0][i], ..., D[k-1][i]), its hop
+ *     distances to the k max/min pivots;
+ *   - cluster t starts as the single vector y_{p_t} of max/min pivot t;
+ *   - Lloyd iterations, at most max_iters (the paper caps its k-means at 50):
+ *     every node joins the cluster of the nearest centroid, then every
+ *     non-empty cluster's centroid becomes the mean of its members (an empty
+ *     cluster keeps its centroid); it stops early when no node changes;
+ *   - new pivot t is the node nearest to centroid t, nodes already taken by
+ *     a lower t excluded; ties go to the lowest index everywhere.
+ * Decisions are made on exact integers wherever the definition allows: a
+ * cluster is kept as the integer sum S_t of its members and their count
+ * N_t (centroid S_t / N_t); B_ti = y_i . S_t is an exact integer.
+ *   - assignment: argmin over t of f_t(i) = a_t - (2 B_ti) / N_t, with
+ *     a_t = sum_j (S_tj / N_t)^2 summed over j in ascending order in double
+ *     and (2 B_ti) / N_t one correctly rounded double division (||y_i||^2
+ *     is common to all t and dropped);
+ *   - nearest node to centroid t: argmin over i of N_t ||y_i||^2 - 2 B_ti,
+ *     exactly in 64-bit integers.
+ * Returns the number of assignment passes run in *iters. */
+static double km_a(int k, const int64_t* S, int64_t N) {
+    double a = 0.0;
+    for (int j = 0; j < k; ++j) {
+        double c = (double)S[j] / (double)N;
+        a += c * c;
+    }
+    return a;
+}
+
+static int64_t km_dot(int n, int k, const int* D, int i, const int64_t* S) {
+    int64_t b = 0;
+    for (int j = 0; j < k; ++j) b += (int64_t)D[(size_t)j * n + i] * S[j];
+    return b;
+}
+
+int orc_kmeans_sp(int n, int k, const int* D, const int* pivots, int max_iters, int* new_pivots,
+                  int* assign, int* iters) {
+    int64_t* S = (int64_t*)calloc((size_t)k * k, sizeof(int64_t));
+    int64_t* S2 = (int64_t*)calloc((size_t)k * k, sizeof(int64_t));
+    int64_t* N = (int64_t*)calloc((size_t)k, sizeof(int64_t));
+    int64_t* N2 = (int64_t*)calloc((size_t)k, sizeof(int64_t));
+    double* a = (double*)malloc(sizeof(double) * (size_t)k);
+    char* taken = (char*)calloc((size_t)n, 1);
+    if (!S || !S2 || !N || !N2 || !a || !taken) {
+        free(S); free(S2); free(N); free(N2); free(a); free(taken);
+        return -1;
+    }
+    for (int t = 0; t < k; ++t) {
+        for (int j = 0; j < k; ++j) S[(size_t)t * k + j] = D[(size_t)j * n + pivots[t]];
+        N[t] = 1;
+    }
+    for (int i = 0; i < n; ++i) assign[i] = -1;
+    int it = 0;
+    while (it < max_iters) {
+        ++it;
+        for (int t = 0; t < k; ++t) a[t] = km_a(k, S + (size_t)t * k, N[t]);
+        int changed = 0;
+        for (int i = 0; i < n; ++i) {
+            int best = 0;
+            double fbest = 0.0;
+            for (int t = 0; t < k; ++t) {
+                int64_t b = km_dot(n, k, D, i, S + (size_t)t * k);
+                double f = a[t] - (2.0 * (double)b) / (double)N[t];
+                if (t == 0 || f < fbest) {
+                    best = t;
+                    fbest = f;
+                }
+            }
+            if (assign[i] != best) ++changed;
+            assign[i] = best;
+        }
+        /* new centroids: member sums; an empty cluster keeps its centroid */
+        memset(S2, 0, sizeof(int64_t) * (size_t)k * k);
+        memset(N2, 0, sizeof(int64_t) * (size_t)k);
+        for (int i = 0; i < n; ++i) {
+            int t = assign[i];
+            for (int j = 0; j < k; ++j) S2[(size_t)t * k + j] += D[(size_t)j * n + i];
+            ++N2[t];
+        }
+        for (int t = 0; t < k; ++t)
+            if (N2[t] > 0) {
+                memcpy(S + (size_t)t * k, S2 + (size_t)t * k, sizeof(int64_t) * (size_t)k);
+                N[t] = N2[t];
+            }
+        if (!changed) break;
+    }
+    /* nearest node to each centroid, in rank order, each node used once */
+    for (int t = 0; t < k; ++t) {
+        int best = -1;
+        int64_t sbest = 0;
+        for (int i = 0; i < n; ++i) {
+            if (taken[i]) continue;
+            int64_t q = 0;
+            for (int j = 0; j < k; ++j) {
+                int64_t y = D[(size_t)j * n + i];
+                q += y * y;
+            }
+            int64_t sc = N[t] * q - 2 * km_dot(n, k, D, i, S + (size_t)t * k);
+            if (best < 0 || sc < sbest) {
+                best = i;
+                sbest = sc;
+            }
+        }
+        new_pivots[t] = best;
+        taken[best] = 1;
+    }
+    *iters = it;
+    free(S); free(S2); free(N); free(N2); free(a); free(taken);
+    return 0;
+}

@@ -497,3 +497,65 @@ def test_validate_rejects_bad_input():
         oracle.select_pivots(d.n, d.row_ptr, d.col_idx, 2, 0)
     assert ei.value.status == oracle.DISCONNECTED
     assert oracle.validate(h.n, h.row_ptr, h.col_idx) == oracle.OK
+
+
+# ----------------------------------------------------------------- k-means sp
+
+@pytest.mark.parametrize("key,n", [("kmeans_sp_path5_k2", 5), ("kmeans_sp_path9_k2", 9)])
+def test_kmeans_sp_golden(key, n):
+    gd = GOLDEN[key]
+    g = G.path(n)
+    piv, dist = oracle.select_pivots(g.n, g.row_ptr, g.col_idx, 2, 0)
+    assert piv.tolist() == [0, n - 1]
+    newp, assign, it = oracle.kmeans_sp(dist, piv)
+    assert newp.tolist() == gd["pivots"]
+    assert assign.tolist() == gd["assign"]
+    assert it == gd["iterations"]
+
+
+def test_kmeans_sp_k_equals_n_keeps_maxmin_pivots():
+    """With k = n every node is a cluster of its own vector (rows of the full
+    distance matrix are distinct), so the pivots come back unchanged."""
+    g = G.random_connected(25, 0.15, 4)
+    piv, dist = oracle.select_pivots(g.n, g.row_ptr, g.col_idx, g.n, 0)
+    newp, assign, it = oracle.kmeans_sp(dist, piv)
+    assert newp.tolist() == piv.tolist()
+    assert np.array_equal(assign[piv], np.arange(g.n))
+    assert it == 2
+
+
+def _sqdist_exact(y, S, N):
+    """||y - S/N||^2 as an exact rational."""
+    from fractions import Fraction
+    return sum((Fraction(int(a)) - Fraction(int(b), int(N))) ** 2 for a, b in zip(y, S))
+
+
+@pytest.mark.parametrize("g,k", [(G.grid(9, 11), 6), (G.tree_plus(150, 3), 8), (G.rgg(300, 9), 7)],
+                         ids=["grid9x11", "tree150", "rgg300"])
+def test_kmeans_sp_fixed_point(g, k):
+    """At termination before the cap: every node sits in a cluster whose
+    centroid (the exact mean of its members) is nearest to it, and every new
+    pivot is the nearest free node to its centroid (exact rational
+    arithmetic, checked against the definitions, not the implementation)."""
+    from fractions import Fraction
+    piv, dist = oracle.select_pivots(g.n, g.row_ptr, g.col_idx, k, 0)
+    newp, assign, it = oracle.kmeans_sp(dist, piv, 50)
+    assert it < 50
+    Y = dist.T.astype(np.int64)  # n x k feature vectors
+    S = np.zeros((k, k), dtype=np.int64)
+    N = np.zeros(k, dtype=np.int64)
+    for i in range(g.n):
+        S[assign[i]] += Y[i]
+        N[assign[i]] += 1
+    assert N.min() >= 1  # no cluster emptied on these graphs
+    for i in range(g.n):
+        d = [_sqdist_exact(Y[i], S[t], N[t]) for t in range(k)]
+        best = min(d)
+        assert d[assign[i]] == best
+        assert assign[i] == d.index(best)  # lowest rank on ties
+    taken = set()
+    for t in range(k):
+        cand = [(_sqdist_exact(Y[i], S[t], N[t]), i) for i in range(g.n) if i not in taken]
+        assert newp[t] == min(cand)[1]
+        taken.add(int(newp[t]))
+    assert len(set(newp.tolist())) == k

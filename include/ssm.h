@@ -84,6 +84,30 @@ ssm_status ssm_select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t
 ssm_status ssm_bfs_pivots(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dist,
                           int32_t* delta, int32_t* region, hipStream_t stream);
 
+/* k-means sp (Section 4.1, "k-means sp"): refines the max/min pivots by
+ * k-means over the nodes' hop-distance vectors y_i = (dist[0][i], ...,
+ * dist[k-1][i]), the k x n table of those pivots (pivot-major).  Cluster t
+ * starts as y_{pivots[t]}; each pass moves every node to the cluster whose
+ * centroid (the mean of its members) is nearest, lowest rank on ties, then
+ * recomputes the centroids (an empty cluster keeps its centroid); passes stop
+ * when no node moves or after max_iters (the paper caps its k-means at 50).
+ * new_pivots[t] is the node nearest to centroid t among the nodes not taken
+ * by a lower rank, lowest id on ties.  The decisions run on exact integers:
+ * clusters are integer sums S_t and sizes N_t, B_ti = y_i . S_t; a node
+ * joins the t with the smallest a_t - (2 B_ti) / N_t, where
+ * a_t = sum_j (S_tj / N_t)^2 is summed in ascending j in double without fused
+ * multiply-add and the division is correctly rounded; the nearest node to a
+ * centroid minimizes N_t ||y_i||^2 - 2 B_ti in 64-bit integers.
+ * n, k: sizes (1 <= k <= n); pivots (device [k]): the max/min pivots;
+ * dist (device [k][n]): their BFS rows; new_pivots (device [k]); assign
+ * (device [n], may be NULL): the final cluster of every node;
+ * iters_done_host (may be NULL): passes run.  The next step is
+ * ssm_bfs_pivots with new_pivots.  SSM_E_RANGE if k n dmax^2 reaches 2^53.
+ * Synchronizes. */
+ssm_status ssm_kmeans_pivots(int32_t n, int32_t k, const int32_t* pivots, const int32_t* dist,
+                             int32_t max_iters, int32_t* new_pivots, int32_t* assign,
+                             int32_t* iters_done_host, hipStream_t stream);
+
 /* Regions only, from a distance table already computed (same rule as
  * ssm_bfs_pivots).  Synchronizes. */
 ssm_status ssm_regions(int32_t n, int32_t k, const int32_t* dist, int32_t* delta,

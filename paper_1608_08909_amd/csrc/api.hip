@@ -166,6 +166,16 @@ ssm_status ssm_bfs_pivots(const ssm_csr* g, int32_t k, const int32_t* pivots, in
     return regions(g->n, k, dist, delta, region, stream);
 }
 
+ssm_status ssm_kmeans_pivots(int32_t n, int32_t k, const int32_t* pivots, const int32_t* dist,
+                             int32_t max_iters, int32_t* new_pivots, int32_t* assign, int32_t* iters_done_host,
+                             hipStream_t stream) {
+    if (n < 1 || k < 1 || k > n) return fail(SSM_E_INVAL, "need 1 <= k <= n");
+    if (max_iters < 1) return fail(SSM_E_INVAL, "max_iters must be at least 1");
+    if (!pivots || !dist || !new_pivots) return fail(SSM_E_INVAL, "NULL pointer");
+    if ((long long)k * n >= (1LL << 40)) return fail(SSM_E_RANGE, "k * n too large");
+    return kmeans_pivots(n, k, pivots, dist, max_iters, new_pivots, assign, iters_done_host, stream);
+}
+
 ssm_status ssm_regions(int32_t n, int32_t k, const int32_t* dist, int32_t* delta, int32_t* region,
                        hipStream_t stream) {
     if (n < 1 || k < 1 || k > n) return fail(SSM_E_INVAL, "need 1 <= k <= n");

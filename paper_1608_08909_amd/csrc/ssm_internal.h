@@ -85,6 +85,10 @@ ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pi
 // device allocation of max(count, 1) ints owned by the caller.  Synchronizes.
 ssm_status heavy_list(const ssm_csr* g, int** heavy, int32_t* count, hipStream_t s);
 
+// k-means sp refinement of max/min pivots (kmeans.hip).
+ssm_status kmeans_pivots(int32_t n, int32_t k, const int32_t* pivots, const int32_t* dist, int32_t max_iters,
+                         int32_t* new_pivots, int32_t* assign, int32_t* iters_host, hipStream_t s);
+
 // Heavy list, its arc segments and the FP32 sweep's scratch for them.
 ssm_status heavy_segments(const ssm_csr* g, ssm_terms* t, hipStream_t s);
 ssm_status regions(int32_t n, int32_t k, const int32_t* dist, int32_t* delta, int32_t* region,

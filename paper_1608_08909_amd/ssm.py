@@ -37,7 +37,7 @@ class _CSR(ctypes.Structure):
 
 
 EXPORTS = [
-    "ssm_validate_csr", "ssm_select_pivots", "ssm_bfs_pivots", "ssm_regions", "ssm_build_terms",
+    "ssm_validate_csr", "ssm_select_pivots", "ssm_bfs_pivots", "ssm_regions", "ssm_kmeans_pivots", "ssm_build_terms",
     "ssm_terms_free", "ssm_terms_dims", "ssm_terms_export", "ssm_pivotmds_init",
     "ssm_pivotmds_eig", "ssm_pivotmds_gram", "ssm_majorize", "ssm_majorize_mixed", "ssm_stress", "ssm_last_error",
 ]
@@ -61,6 +61,7 @@ def load(path: str | None = None):
             "ssm_select_pivots": (S, [P, I, I, V, V, V]),
             "ssm_bfs_pivots": (S, [P, I, V, V, V, V, V]),
             "ssm_regions": (S, [I, I, V, V, V, V]),
+            "ssm_kmeans_pivots": (S, [I, I, V, V, I, V, V, V, V]),
             "ssm_build_terms": (S, [P, I, V, V, V, V, ctypes.POINTER(V), V]),
             "ssm_terms_free": (None, [V]),
             "ssm_terms_dims": (S, [V, V, V, V]),
@@ -194,6 +195,17 @@ def regions(dist: torch.Tensor):
     return delta, region
 
 
+def kmeans_pivots(pivots: torch.Tensor, dist: torch.Tensor, max_iters: int = 50):
+    """k-means sp refinement of max/min pivots; returns (new_pivots, assign, passes)."""
+    k, n = dist.shape
+    newp = torch.empty(k, dtype=torch.int32, device="cuda")
+    assign = torch.empty(n, dtype=torch.int32, device="cuda")
+    it = ctypes.c_int32()
+    _check(load().ssm_kmeans_pivots(n, k, _ptr(pivots), _ptr(dist), int(max_iters), _ptr(newp), _ptr(assign),
+                                    ctypes.byref(it), _stream()), "ssm_kmeans_pivots")
+    return newp, assign, it.value
+
+
 def build_terms(g: DeviceGraph, pivots, dist, delta, region) -> Terms:
     k = int(pivots.numel())
     h = ctypes.c_void_p()
@@ -266,10 +278,19 @@ def stress(g: DeviceGraph, terms: Terms | None, x: torch.Tensor, kind: int = STR
     return out.value
 
 
-def layout(g: DeviceGraph, k: int, iters: int, prec: int = FP64, first: int = 0, warm: int = 1):
+def layout(g: DeviceGraph, k: int, iters: int, prec: int = FP64, first: int = 0, warm: int = 1,
+           sampling: str = "maxmin"):
     """Algorithm 1 end to end on the device; returns (x, terms, pivots, dist, delta, region).
-    FP32 runs PivotMDS and the first `warm` sweeps in FP64, the rest in FP32."""
-    piv = select_pivots(g, k, first)
+    FP32 runs PivotMDS and the first `warm` sweeps in FP64, the rest in FP32.
+    sampling "kmeans" refines the max/min pivots by k-means sp before the BFS."""
+    if sampling not in ("maxmin", "kmeans"):
+        raise ValueError(f"unknown pivot sampling {sampling!r}")
+    if sampling == "kmeans":
+        piv0, dist0 = select_pivots(g, k, first, with_dist=True)
+        piv, _, _ = kmeans_pivots(piv0, dist0)
+        del dist0
+    else:
+        piv = select_pivots(g, k, first)
     dist, delta, region = bfs_pivots(g, piv)
     terms = build_terms(g, piv, dist, delta, region)
     x = pivotmds_init(g, terms, FP64)

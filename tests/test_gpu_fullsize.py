@@ -182,3 +182,49 @@ def test_fullsize_pivotmds(run):
     xr = xr * (g.m / el)
     rms = float(xr.pow(2).sum(dim=1).mean().sqrt())
     assert float((x - xr).norm(dim=1).max()) <= 1e-9 * rms
+
+
+def test_fullsize_kmeans_sp(run):
+    """k-means sp on the full-size max/min distance table.  The oracle's pass
+    is too slow here, so the result is certified by what defines it:
+    - converged before the pass cap, the final clusters are a fixed point:
+      every node's cluster minimizes a_t - 2 B_ti / N_t (a_t summed in
+      ascending j, no fused multiply-add; lowest t on ties) for the centroids
+      of those same clusters;
+    - new pivot t minimizes N_t ||y_i||^2 - 2 B_ti over the nodes not taken
+      by a lower rank (lowest id on ties)."""
+    if run.name == "mesh":
+        pytest.skip("k-means sp is certified on the random geometric and Barabasi-Albert graphs")
+    k, n = run.dist.shape
+    say("case", run.name, "kmeans sp")
+    newp, assign, it = ssm.kmeans_pivots(run.piv, run.dist)
+    torch.cuda.synchronize()
+    say("passes", it)
+    assert 1 <= it <= 50
+    Y = run.dist.t().double().contiguous()          # n x k features, exact integers
+    a_ = assign.long()
+    assert int(a_.min()) >= 0 and int(a_.max()) < k
+    S = torch.zeros(k, k, dtype=torch.float64, device="cuda").index_add_(0, a_, Y)
+    N = torch.bincount(a_, minlength=k).double()
+    assert bool((N > 0).all()), "an empty final cluster: its kept centroid is not recoverable"
+    B = Y @ S.t().contiguous()                        # n x k, exact (< 2^53)
+    if it < 50:
+        Sh, Nh = S.cpu().numpy(), N.cpu().numpy()
+        a = np.zeros(k)
+        for j in range(k):
+            c = Sh[:, j] / Nh
+            a = a + c * c
+        f = torch.from_numpy(a).cuda()[None, :] - (2.0 * B) / N[None, :]
+        assert torch.equal(torch.argmin(f, dim=1), a_)
+    q = (Y * Y).sum(dim=1).long()
+    score = N.long()[None, :] * q[:, None] - 2 * B.long()
+    free = torch.ones(n, dtype=torch.bool, device="cuda")
+    ids = torch.arange(n, device="cuda")
+    big = torch.iinfo(torch.long).max
+    p = newp.long().cpu().numpy()
+    for t in range(k):
+        st = torch.where(free, score[:, t], big)
+        m = st.min()
+        pick = int(ids[st == m].min())
+        assert pick == p[t], f"pivot {t}"
+        free[pick] = False

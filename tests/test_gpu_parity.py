@@ -419,6 +419,71 @@ def test_edge_cases():
     assert ei.value.status == ssm.E_DISCONNECTED
 
 
+KM_CASES = [(G.path(9), 2), (G.cycle(17), 4), (G.star(12), 3), (G.complete(9), 9), (G.grid(9, 11), 6),
+            (G.tri_grid(20, 23), 12), (G.rgg(300, 3), 7), (G.tree_plus(300, 2), 17),
+            (G.barabasi_albert(2000, 3, 7), 50), (G.holed_mesh(120, 130, 6, 4, 12, 5), 40), (G.rgg(20000, 7, 8.0), 60)]
+
+
+@pytest.mark.parametrize("g,k", KM_CASES, ids=[f"{g.name}-k{k}" for g, k in KM_CASES])
+def test_kmeans_sp_bit_exact(g, k):
+    """k-means sp: refined pivots, final clusters and pass count equal the oracle's."""
+    say("case", g.name, "k", k)
+    dg = ssm.DeviceGraph.from_csr(g)
+    piv, dist = ssm.select_pivots(dg, k, 0, with_dist=True)
+    ph, dh = piv.cpu().numpy(), dist.cpu().numpy()
+    for iters in (50, 1, 2):
+        newp, assign, it = ssm.kmeans_pivots(piv, dist, iters)
+        rp, ra, rit = oracle.kmeans_sp(dh, ph, iters)
+        assert it == rit, iters
+        assert np.array_equal(assign.cpu().numpy(), ra), iters
+        assert np.array_equal(newp.cpu().numpy(), rp), iters
+    # then the BFS from the refined pivots, as in the layout pipeline
+    d2, delta2, region2 = ssm.bfs_pivots(dg, newp)
+    d2r = oracle.bfs_pivots(g.n, g.row_ptr, g.col_idx, rp)
+    assert np.array_equal(d2.cpu().numpy(), d2r)
+    delta_r, region_r, _, _ = oracle.regions(d2r)
+    assert np.array_equal(delta2.cpu().numpy(), delta_r)
+    assert np.array_equal(region2.cpu().numpy(), region_r)
+
+
+def test_kmeans_sp_given_pivots():
+    """Arbitrary start pivots, repeated ones included (the duplicate's cluster
+    stays empty and keeps its centroid)."""
+    g = G.tri_grid(30, 31)
+    dg = ssm.DeviceGraph.from_csr(g)
+    for ph in ([0, 929, 15, 465, 900, 30, 300, 777], [5, 5, 600, 5, 12]):
+        ph = np.array(ph, dtype=np.int32)
+        dh = oracle.bfs_pivots(g.n, g.row_ptr, g.col_idx, ph)
+        newp, assign, it = ssm.kmeans_pivots(torch.from_numpy(ph).cuda(), torch.from_numpy(dh).cuda())
+        rp, ra, rit = oracle.kmeans_sp(dh, ph)
+        assert it == rit
+        assert np.array_equal(assign.cpu().numpy(), ra)
+        assert np.array_equal(newp.cpu().numpy(), rp)
+    with pytest.raises(ssm.SSMError) as ei:
+        ssm.kmeans_pivots(torch.tensor([0, g.n], dtype=torch.int32, device="cuda"),
+                          torch.zeros(2, g.n, dtype=torch.int32, device="cuda"))
+    assert ei.value.status == ssm.E_INVAL
+    with pytest.raises(ssm.SSMError) as ei:
+        ssm.kmeans_pivots(torch.tensor([0, 1], dtype=torch.int32, device="cuda"),
+                          torch.zeros(2, g.n, dtype=torch.int32, device="cuda"), 0)
+    assert ei.value.status == ssm.E_INVAL
+
+
+def test_kmeans_sp_layout_end_to_end():
+    """layout(sampling="kmeans") runs the oracle's pipeline on the refined pivots."""
+    g = G.grid(30, 30)
+    dg = ssm.DeviceGraph.from_csr(g)
+    x, terms, piv, dist, delta, region = ssm.layout(dg, 20, 30, ssm.FP64, sampling="kmeans")
+    p0, d0 = oracle.select_pivots(g.n, g.row_ptr, g.col_idx, 20, 0)
+    rp, _, _ = oracle.kmeans_sp(d0, p0)
+    assert np.array_equal(piv.cpu().numpy(), rp)
+    T = oracle.build_terms(g.row_ptr, g.col_idx, rp, oracle.bfs_pivots(g.n, g.row_ptr, g.col_idx, rp))
+    assert np.array_equal(region.cpu().numpy(), T.region)
+    xr = ssm.pivotmds_init(dg, terms, ssm.FP64)
+    ssm.majorize(dg, terms, xr, 30)
+    assert torch.equal(x, xr)
+
+
 def test_validate_csr():
     g = G.grid(5, 6)
     ssm.validate_csr(ssm.DeviceGraph.from_csr(g))

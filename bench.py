@@ -34,6 +34,7 @@ WORKLOADS = {
 }
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 PROFILE_LABEL = {"rgg": "rgg100k_k200", "ba": "ba1m_k200", "mesh": "mesh2000_k100", "grid": "grid50_k50"}
 
 
@@ -96,6 +97,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rgg", choices=sorted(WORKLOADS))
+    ap.add_argument("--sampling", default="maxmin", choices=["maxmin", "kmeans"],
+                    help="pivot sampling: max/min, or max/min refined by k-means sp")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=10)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -121,11 +124,19 @@ def main():
     stream = torch.cuda.current_stream()
 
     phases = {}
+    km_passes = []
+    kmeans = args.sampling == "kmeans"
 
     def step(record=False):
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(8)]
         ev[0].record(stream)
-        piv = ssm.select_pivots(dg, k, 0)
+        if kmeans:
+            piv0, dist0 = ssm.select_pivots(dg, k, 0, with_dist=True)
+            ev[7].record(stream)
+            piv, _, passes = ssm.kmeans_pivots(piv0, dist0)
+            del dist0
+        else:
+            piv = ssm.select_pivots(dg, k, 0)
         ev[1].record(stream)
         dist, delta, region = ssm.bfs_pivots(dg, piv)
         ev[2].record(stream)
@@ -145,6 +156,10 @@ def main():
             names = ["select", "bfs_regions", "terms", "pivotmds", "sweeps", "stress"]
             for a, name in enumerate(names):
                 phases.setdefault(name, []).append(ev[a].elapsed_time(ev[a + 1]))
+            if kmeans:
+                phases["select"][-1] = ev[0].elapsed_time(ev[7])
+                phases.setdefault("kmeans_sp", []).append(ev[7].elapsed_time(ev[1]))
+                km_passes.append(passes)
         return terms, x, s
 
     for _ in range(args.warmup):
@@ -201,7 +216,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if prec == ssm.FP32 else "f64",
         "data": "synthetic",
-        "config": {"workload": desc, "n": g.n, "m": g.m, "k": k, "iters": iters,
+        "config": {"workload": desc, "sampling": args.sampling, "n": g.n, "m": g.m, "k": k, "iters": iters,
                    "delta_max": delta_max, "dmax": dmax, "graph_sha256": g.sha256()},
         "layouts_per_s": args.steps / elapsed,
         "latency_ms": {"p50": percentile(step_ms, 50), "p99": percentile(step_ms, 99)},
@@ -218,6 +233,15 @@ def main():
                      "traffic": measured_traffic(args.workload) if prec == ssm.FP32 else None,
                      "bytes_per_launch": nbytes, "launch_us": sweep_us},
     }
+    if kmeans:
+        # k-means sp: each pass's assignment is an n x k x k FP64 contraction
+        # (B = Y S^T), 2 n k^2 flops; phase-level rate (all its kernels and
+        # the per-pass host check included).
+        ms = float(np.median(phases["kmeans_sp"]))
+        p = int(np.median(km_passes))
+        tf = 2 * g.n * k * k * p / (ms * 1e-3) / 1e12
+        out["kmeans_sp"] = {"passes": p, "ms": ms, "assign_flops_per_pass": 2 * g.n * k * k,
+                            "phase_tflops": tf, "phase_frac_fp64_peak": tf / FP64_PEAK_TFLOPS}
     if args.copy_calibration:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -446,6 +446,20 @@ def test_kmeans_sp_bit_exact(g, k):
     assert np.array_equal(region2.cpu().numpy(), region_r)
 
 
+@pytest.mark.parametrize("chunk", ["32", "40", "48", "56", "64"])
+def test_kmeans_sp_chunk_variants(chunk, monkeypatch):
+    """Every cluster-chunk width of the assignment kernel, k not a multiple of it."""
+    monkeypatch.setenv("SSM_KM_CHUNK", chunk)
+    g = G.rgg(5000, 11, 8.0)
+    dg = ssm.DeviceGraph.from_csr(g)
+    piv, dist = ssm.select_pivots(dg, 77, 0, with_dist=True)
+    newp, assign, it = ssm.kmeans_pivots(piv, dist)
+    rp, ra, rit = oracle.kmeans_sp(dist.cpu().numpy(), piv.cpu().numpy())
+    assert it == rit
+    assert np.array_equal(assign.cpu().numpy(), ra)
+    assert np.array_equal(newp.cpu().numpy(), rp)
+
+
 def test_kmeans_sp_given_pivots():
     """Arbitrary start pivots, repeated ones included (the duplicate's cluster
     stays empty and keeps its centroid)."""

@@ -191,6 +191,84 @@ ssm_status ssm_majorize_mixed(const ssm_csr* g, ssm_terms* t, double* x64, float
 ssm_status ssm_stress(const ssm_csr* g, ssm_terms* t, ssm_prec p, const void* x,
                       ssm_stress_kind kind, double* out_host, hipStream_t stream);
 
+/* ---- Layout pool: many small graphs laid out together ----------------
+ *
+ * The same method (Algorithm 1: max/min sp pivots, their BFS, regions and
+ * adapted weights of Section 3, PivotMDS, sweeps of Eq. 5) for many graphs
+ * at once: every stage runs for a whole list of graphs per launch, and a
+ * graph's CSR, packed distances, weight tables and coordinates stay resident
+ * in one device arena of fixed capacity.  Graphs have 1 <= n <= 65536 nodes
+ * and 3 <= k <= min(n, 256) pivots.  Calls on one pool are serialized
+ * internally; a pool belongs to the device that was current at creation. */
+typedef struct ssm_pool ssm_pool;
+
+typedef enum {
+    SSM_POOL_PIVOTS = 0,  /* int32 [k] */
+    SSM_POOL_DIST = 1,    /* int32 [k][n] BFS distances of the pivots */
+    SSM_POOL_DELTA = 2,   /* int32 [n] distance to the nearest pivot */
+    SSM_POOL_REGION = 3,  /* int32 [n] region (pivot rank) */
+    SSM_POOL_H = 4,       /* int32 [k][delta_max + 1] cumulative region histograms */
+    SSM_POOL_WTAB64 = 5,  /* double [k][dmax + 1] adapted weights w'(t, d) */
+    SSM_POOL_DEN64 = 6,   /* double [n] denominators of Eq. 5 */
+    SSM_POOL_X32 = 7,     /* float [n][2] current layout */
+    SSM_POOL_X64 = 8      /* double [n][2] FP64 layout after preparation (PivotMDS and the warm-up sweeps) */
+} ssm_pool_table;
+
+typedef enum { SSM_POOL_FREE = 0, SSM_POOL_ADDED = 1, SSM_POOL_READY = 2, SSM_POOL_FAILED = 3 } ssm_pool_state;
+
+/* A pool with one device allocation of capacity_bytes (>= 1 MiB). */
+ssm_status ssm_pool_create(int64_t capacity_bytes, ssm_pool** out);
+void ssm_pool_destroy(ssm_pool* p);
+/* Bytes of the arena in use and its capacity (host outputs, may be NULL). */
+ssm_status ssm_pool_usage(ssm_pool* p, int64_t* used, int64_t* capacity);
+
+/* Admits one graph: checks the host CSR (simple, symmetric), reserves its
+ * resident and preparation buffers and copies the CSR (row_ptr_host [n+1],
+ * col_idx_host [nnz], host memory, read before return).  k pivots by max/min
+ * from `first`; `sweeps` is the graph's total sweep count (Algorithm 1's
+ * iteration bound).  SSM_E_NOMEM when the arena has no room: the caller may
+ * retry after removing finished graphs (admission by memory budget).
+ * Writes the slot id to *slot_out.  Synchronizes. */
+ssm_status ssm_pool_add(ssm_pool* p, int32_t n, int32_t nnz, const int32_t* row_ptr_host,
+                        const int32_t* col_idx_host, int32_t k, int32_t first, int32_t sweeps,
+                        int32_t* slot_out, hipStream_t stream);
+
+/* Preprocessing and start layout of the listed (added) slots: max/min
+ * pivots, k BFS, regions (rule R1), H, w' and denominators, PivotMDS with the
+ * rescale, then `warm` FP64 sweeps (oracle operation order), rounded into the
+ * FP32 layout.  A slot whose graph is disconnected, has zero total PivotMDS
+ * edge length or finds no room for its weight tables becomes
+ * SSM_POOL_FAILED (see ssm_pool_info); the others become SSM_POOL_READY with
+ * `warm` sweeps done.  Releases the preparation buffers.  Synchronizes. */
+ssm_status ssm_pool_prepare(ssm_pool* p, int32_t count, const int32_t* slots_host, int32_t warm,
+                            hipStream_t stream);
+
+/* Up to `iters` FP32 Jacobi sweeps (Eq. 5, displacement form) on every
+ * listed ready slot, never past its sweep count: one launch per sweep covers
+ * all of them.  Asynchronous; a later call that reads a slot (stress,
+ * layout, export, remove) waits for it. */
+ssm_status ssm_pool_sweep(ssm_pool* p, int32_t count, const int32_t* slots_host, int32_t iters,
+                          hipStream_t stream);
+
+/* s'(x) of Eq. 3 in FP64 for each listed ready slot's current layout into
+ * out_host[count].  Synchronizes. */
+ssm_status ssm_pool_stress(ssm_pool* p, int32_t count, const int32_t* slots_host, double* out_host,
+                           hipStream_t stream);
+
+/* Copies a ready slot's current FP32 layout (n x 2) to x_out (device). */
+ssm_status ssm_pool_layout(ssm_pool* p, int32_t slot, float* x_out, hipStream_t stream);
+
+/* Copies one table of a ready slot (ssm_pool_table) to host memory.
+ * Synchronizes. */
+ssm_status ssm_pool_export(ssm_pool* p, int32_t slot, int32_t what, void* host_out, hipStream_t stream);
+
+/* info_host[8] = {state, failure status, n, k, sweeps done, sweep count,
+ * dmax, delta_max}. */
+ssm_status ssm_pool_info(ssm_pool* p, int32_t slot, int32_t* info_host);
+
+/* Releases a slot's buffers (after any queued sweep that reads it). */
+ssm_status ssm_pool_remove(ssm_pool* p, int32_t slot);
+
 /* Message for the last non-OK status returned on the calling thread. */
 const char* ssm_last_error(void);
 

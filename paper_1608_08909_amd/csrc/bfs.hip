@@ -699,26 +699,27 @@ __device__ __forceinline__ int ell_level_auto(int n, const int* __restrict__ rp,
 // with the visited set in LDS bits.  gq holds 3 n ints per block (two
 // frontier overflows, long-row overflow).  reached[b] = nodes found;
 // *ecc_max = largest eccentricity seen.
+// BFS from src writing D[*] for every node it reaches, with the visited set
+// in LDS bits; gq holds 3 n ints (two frontier overflows, long-row
+// overflow).  Thread 0 stores the number of nodes found in *reached and
+// raises *ecc_max to the eccentricity of src.
 template <int W, int POOL>
-__global__ __launch_bounds__(kBfsBlock) void k_bfs_ell(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                                       const int* __restrict__ ell, const int* __restrict__ pivots,
-                                                       int* dist, int* gq, int* reached, int* ecc_max) {
+__device__ __forceinline__ void bfs_ell_body(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                             const int* __restrict__ ell, int src, int* D, int* gq, int* reached,
+                                             int* ecc_max) {
     __shared__ __align__(16) unsigned char pool[POOL];
     __shared__ int2 s_slot[3];
     int* qa = (int*)pool;
     int* qb = qa + kLdsQ;
     int* lheavy = qb + kLdsQ;
     unsigned* bits = (unsigned*)(lheavy + kHeavyCap);
-    const int b = blockIdx.x;
-    int* D = dist + (size_t)b * n;
-    int* ga = gq + (size_t)b * 3 * n;
+    int* ga = gq;
     int* gb = ga + n;
     int* gh = gb + n;
     const int nbw = (n + 31) / 32;
     for (int w = threadIdx.x; w < nbw; w += blockDim.x) bits[w] = 0u;
     __syncthreads();
     if (threadIdx.x == 0) {
-        const int src = pivots[b];
         D[src] = 0;
         bits[src >> 5] |= 1u << (src & 31);
         qa[0] = src;
@@ -746,9 +747,19 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_ell(int n, const int* __restr
         f.gnxt = (int*)tg;
     }
     if (threadIdx.x == 0) {
-        reached[b] = total;
+        *reached = total;
         atomicMax(ecc_max, level - 1);
     }
+}
+
+// Block b: BFS from pivots[b] into dist[b][*]; gq holds 3 n ints per block.
+template <int W, int POOL>
+__global__ __launch_bounds__(kBfsBlock) void k_bfs_ell(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                       const int* __restrict__ ell, const int* __restrict__ pivots,
+                                                       int* dist, int* gq, int* reached, int* ecc_max) {
+    const int b = blockIdx.x;
+    bfs_ell_body<W, POOL>(n, rp, ci, ell, pivots[b], dist + (size_t)b * n, gq + (size_t)b * 3 * n, reached + b,
+                          ecc_max);
 }
 
 // LDS pool sizes of k_bfs_ell (several workgroups share a CU when small);
@@ -1294,10 +1305,9 @@ __device__ __forceinline__ unsigned long long argmax_m7_clear(unsigned char* m8,
 // The claiming lane owns m[v] for the level and writes it with plain
 // stores.  gq holds 3 n ints.
 template <int W, bool M8>
-__global__ __launch_bounds__(kBfsBlock) void k_select_ell(int n, const int* __restrict__ rp,
-                                                          const int* __restrict__ ci, const int* __restrict__ ell,
-                                                          int k, int first, int* pivots, int* m, int* gq,
-                                                          int* status) {
+__device__ __forceinline__ void select_ell_body(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                const int* __restrict__ ell, int k, int first, int* pivots, int* m,
+                                                int* gq, int* status) {
     __shared__ __align__(16) unsigned char pool[kSelPool];
     __shared__ int2 s_slot[3];
     __shared__ int s_src;
@@ -1408,6 +1418,14 @@ __global__ __launch_bounds__(kBfsBlock) void k_select_ell(int n, const int* __re
         __syncthreads();
         if (t == 0 && (int)(best >> 32) == kInf) break;  // disconnected (uniform)
     }
+}
+
+template <int W, bool M8>
+__global__ __launch_bounds__(kBfsBlock) void k_select_ell(int n, const int* __restrict__ rp,
+                                                          const int* __restrict__ ci, const int* __restrict__ ell,
+                                                          int k, int first, int* pivots, int* m, int* gq,
+                                                          int* status) {
+    select_ell_body<W, M8>(n, rp, ci, ell, k, first, pivots, m, gq, status);
 }
 
 template <int W, bool M8>
@@ -1997,6 +2015,72 @@ ssm_status regions(int32_t n, int32_t k, const int32_t* dist, int32_t* delta, in
     sfree(aux);
     if (e != hipSuccess) return hip_fail(e, "region assignment");
     return SSM_OK;
+}
+
+// ------------------------------------------------------------ layout pool
+
+// Per graph (blockIdx.y): m = infinity, pivots = 0 (so that ranks a failed
+// selection leaves unset still name a node), info = 0, and the padded
+// adjacency of width kPoolEllW.
+__global__ void k_pool_prep_init(const PoolGraph* __restrict__ gs) {
+    const PoolGraph& g = gs[blockIdx.y];
+    const int n = g.n;
+    const long long ne = (long long)n * kPoolEllW;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < ne;
+         q += (long long)gridDim.x * blockDim.x) {
+        const int v = (int)(q / kPoolEllW), j = (int)(q % kPoolEllW);
+        const int a = g.rp[v], d = g.rp[v + 1] - a;
+        int val = -1;
+        if (d > kPoolEllW && j == kPoolEllW - 1)
+            val = kEllMore;
+        else if (j < d)
+            val = g.ci[a + j];
+        g.ell[q] = val;
+        if (j == 0) g.m[v] = kInf;
+    }
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < max(g.kpad, 8); q += gridDim.x * blockDim.x) {
+        if (q < g.kpad) g.pivots[q] = 0;
+        if (q < 8) g.info[q] = 0;
+    }
+}
+
+hipError_t pool_prep_init(const PoolGraph* gs, int count, int nmax, hipStream_t s) {
+    const int bx = std::max(1, std::min(div_up((long long)nmax * kPoolEllW, 256), 256));
+    hipLaunchKernelGGL(k_pool_prep_init, dim3(bx, count), dim3(256), 0, s, gs);
+    return hipGetLastError();
+}
+
+// One max/min selection per graph, in one workgroup with LDS state bytes.
+__global__ __launch_bounds__(kBfsBlock) void k_pool_select(const PoolGraph* __restrict__ gs) {
+    const PoolGraph& g = gs[blockIdx.x];
+    select_ell_body<kPoolEllW, true>(g.n, g.rp, g.ci, g.ell, g.k, g.first, g.pivots, g.m, g.gq, g.info);
+}
+
+hipError_t pool_select(const PoolGraph* gs, int count, hipStream_t s) {
+    hipLaunchKernelGGL(k_pool_select, dim3(count), dim3(kBfsBlock), 0, s, gs);
+    return hipGetLastError();
+}
+
+// Items (graph, rank) over a persistent grid: the BFS from that graph's
+// pivot of that rank into its distance row; info[1] = eccentricity maximum.
+__global__ __launch_bounds__(kBfsBlock) void k_pool_bfs(const PoolGraph* __restrict__ gs,
+                                                        const int2* __restrict__ items, int nitems, int* gq,
+                                                        long long gq_stride) {
+    __shared__ int s_reached;
+    int* myq = gq + (size_t)blockIdx.x * gq_stride;
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int2 st = items[it];
+        const PoolGraph& g = gs[st.x];
+        __syncthreads();  // the previous item's last reads of LDS are done
+        bfs_ell_body<kPoolEllW, kPoolS>(g.n, g.rp, g.ci, g.ell, g.pivots[st.y], g.dist + (size_t)st.y * g.n, myq,
+                                         &s_reached, g.info + 1);
+    }
+}
+
+hipError_t pool_bfs(const PoolGraph* gs, const int2* items, int nitems, int* gq, long long gq_stride, int blocks,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_pool_bfs, dim3(blocks), dim3(kBfsBlock), 0, s, gs, items, nitems, gq, gq_stride);
+    return hipGetLastError();
 }
 
 }  // namespace ssm

@@ -90,17 +90,14 @@ constexpr int kGramWaves = 4;
 // B[q][j] with i = j = l % 16, q = l / 16; result lane l, element v holds
 // row 4 v + l / 16, column l % 16.
 template <typename DT, int VEC>
-__global__ __launch_bounds__(256) void k_pmds_gram(int n, int k, int kp, int kpad, int chunk,
-                                                   const uint4* __restrict__ dpk,
-                                                   const double* __restrict__ mu,
-                                                   const double* __restrict__ nu,
-                                                   const double* __restrict__ stats,
-                                                   const int2* __restrict__ tiles, int ntiles,
-                                                   double* __restrict__ part) {
+__device__ __forceinline__ void pmds_gram_body(int c, int grp, int n, int k, int kp, int kpad, int chunk,
+                                               const uint4* __restrict__ dpk, const double* __restrict__ mu,
+                                               const double* __restrict__ nu, const double* __restrict__ stats,
+                                               const int2* __restrict__ tiles, int ntiles,
+                                               double* __restrict__ part) {
     extern __shared__ double smem[];
     double* Cs = smem;                    // [kGramSub][kp]
     double* smu = smem + kGramSub * kp;   // [kp]
-    const int c = blockIdx.x, grp = blockIdx.y;
     const int lane = lane_id(), w = threadIdx.x / kWave;
     const double gamma = stats[0];
     for (int t = threadIdx.x; t < kp; t += blockDim.x) smu[t] = t < k ? mu[t] : 0.0;
@@ -166,6 +163,17 @@ __global__ __launch_bounds__(256) void k_pmds_gram(int n, int k, int kp, int kpa
     }
 }
 
+template <typename DT, int VEC>
+__global__ __launch_bounds__(256) void k_pmds_gram(int n, int k, int kp, int kpad, int chunk,
+                                                   const uint4* __restrict__ dpk,
+                                                   const double* __restrict__ mu,
+                                                   const double* __restrict__ nu,
+                                                   const double* __restrict__ stats,
+                                                   const int2* __restrict__ tiles, int ntiles,
+                                                   double* __restrict__ part) {
+    pmds_gram_body<DT, VEC>(blockIdx.x, blockIdx.y, n, k, kp, kpad, chunk, dpk, mu, nu, stats, tiles, ntiles, part);
+}
+
 // M (k x k, row-major) = sum over chunks in ascending order of the partial
 // tiles; the lower triangle mirrors the upper one.
 __global__ void k_pmds_gram_reduce(int k, int nchunks, int ntiles, const int2* __restrict__ tiles,
@@ -206,9 +214,8 @@ constexpr int kEigCols = 4;   // columns per lane (k <= 256)
 // is positive (entries within a relative 1e-9 of the largest count as tied;
 // the lowest index among them decides).  out: V (k x 2), lambda[2]; iters[0].
 template <bool REG>
-__global__ __launch_bounds__(kEigThreads) void k_pmds_eig(int k, const double* __restrict__ M, double tol,
-                                                         int max_iter, double* __restrict__ out,
-                                                         int* __restrict__ iters) {
+__device__ __forceinline__ void pmds_eig_body(int k, const double* __restrict__ M, double tol, int max_iter,
+                                              double* __restrict__ out, int* __restrict__ iters) {
     extern __shared__ double sh[];
     double* v0 = sh;
     double* v1 = sh + k;
@@ -380,6 +387,13 @@ __global__ __launch_bounds__(kEigThreads) void k_pmds_eig(int k, const double* _
     }
 }
 
+template <bool REG>
+__global__ __launch_bounds__(kEigThreads) void k_pmds_eig(int k, const double* __restrict__ M, double tol,
+                                                         int max_iter, double* __restrict__ out,
+                                                         int* __restrict__ iters) {
+    pmds_eig_body<REG>(k, M, tol, max_iter, out, iters);
+}
+
 // x_i = sum over t ascending of C_it V_t (per column), FP64.
 template <typename DT, int VEC>
 __global__ void k_pmds_project(int n, int k, int nwords, const uint4* __restrict__ dpk,
@@ -540,6 +554,142 @@ ssm_status pivotmds(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* x, hipStre
     if (e != hipSuccess) return hip_fail(e, "PivotMDS");
     if (hflag) return fail(SSM_E_INVAL, "PivotMDS layout has zero total edge length; cannot rescale");
     return SSM_OK;
+}
+
+// ------------------------------------------------------------ layout pool
+
+// Per graph: colsum, mu, gamma and nu from its distance rows (the same exact
+// integer sums and the same divisions as the single-graph path).
+__global__ __launch_bounds__(1024) void k_pool_mds_stats(const PoolGraph* __restrict__ gs) {
+    const PoolGraph& g = gs[blockIdx.x];
+    const int n = g.n, k = g.k;
+    __shared__ long long red[1024 / kWave];
+    for (int t = 0; t < k; ++t) {
+        long long s = 0;
+        const int* row = g.dist + (size_t)t * n;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const long long d = row[i];
+            s += d * d;
+        }
+        s = block_sum(s, red);
+        if (threadIdx.x == 0) g.colsum[t] = s;
+    }
+    if (threadIdx.x == 0) {  // colsum was written by this thread
+        long long total = 0;
+        for (int t = 0; t < k; ++t) {
+            g.mu[t] = (double)g.colsum[t] / (double)n;
+            total += g.colsum[t];
+        }
+        g.stats[0] = (double)total / ((double)n * (double)k);
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        long long s = 0;
+        for (int t = 0; t < k; ++t) {
+            const long long d = g.dist[(size_t)t * n + i];
+            s += d * d;
+        }
+        g.nu[i] = (double)s / (double)k;
+    }
+}
+
+// Items (graph, node chunk, tile group): the Gram partial tiles.
+__global__ __launch_bounds__(256) void k_pool_gram(const PoolGraph* __restrict__ gs, const int4* __restrict__ items,
+                                                   const int2* __restrict__ tiles) {
+    const int4 it = items[blockIdx.x];
+    const PoolGraph& g = gs[it.x];
+    const int kp = (g.k + 15) / 16 * 16;
+    pmds_gram_body<uint16_t, 8>(it.y, it.z, g.n, g.k, kp, g.kpad, kPoolGramChunk, g.dpk, g.mu, g.nu, g.stats, tiles,
+                                g.ntiles, g.gpart);
+}
+
+// Per graph (blockIdx.y): M = the chunks' partial tiles summed in ascending
+// chunk order, mirrored into the lower triangle.
+__global__ void k_pool_gram_reduce(const PoolGraph* __restrict__ gs, const int2* __restrict__ tiles) {
+    const PoolGraph& g = gs[blockIdx.y];
+    const long long total = (long long)g.ntiles * 256;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total;
+         q += (long long)gridDim.x * blockDim.x) {
+        const int tile = (int)(q / 256), e = (int)(q % 256);
+        double s = 0.0;
+        for (int c = 0; c < g.nchunks; ++c) s += g.gpart[((size_t)c * g.ntiles + tile) * 256 + e];
+        const int2 ab = tiles[tile];
+        const int r = 16 * ab.x + e / 16, col = 16 * ab.y + e % 16;
+        if (r < g.k && col < g.k) {
+            g.M[(size_t)r * g.k + col] = s;
+            g.M[(size_t)col * g.k + r] = s;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kEigThreads) void k_pool_eig(const PoolGraph* __restrict__ gs) {
+    const PoolGraph& g = gs[blockIdx.x];
+    pmds_eig_body<true>(g.k, g.M, 1e-13, 20000, g.eig, g.info + 4);
+}
+
+// Per graph: x64[0] = C V (ranks ascending), then the uniform rescale that
+// makes the summed edge lengths equal m; info[3] = 1 if that sum is 0.
+__global__ __launch_bounds__(1024) void k_pool_project(const PoolGraph* __restrict__ gs) {
+#pragma clang fp contract(off)
+    const PoolGraph& g = gs[blockIdx.x];
+    const int n = g.n, k = g.k, nwords = g.kpad / 8;
+    const double gamma = g.stats[0];
+    const double* V = g.eig;
+    double2* x = g.x64[0];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double s0 = 0.0, s1 = 0.0;
+        const double nui = g.nu[i];
+        for (int b = 0; b < nwords; ++b) {
+            union {
+                uint4 v;
+                uint16_t e[8];
+            } u;
+            u.v = g.dpk[(size_t)b * n + i];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int t = b * 8 + j;
+                if (t < k) {
+                    const double c = centred((int)u.e[j], g.mu[t], nui, gamma);
+                    s0 += c * V[2 * t];
+                    s1 += c * V[2 * t + 1];
+                }
+            }
+        }
+        x[i] = make_double2(s0, s1);
+    }
+    __syncthreads();
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double2 xi = x[i];
+        for (int e = g.rp[i]; e < g.rp[i + 1]; ++e) {
+            const int j = g.ci[e];
+            if (j <= i) continue;
+            const double2 xj = x[j];
+            const double dx = xi.x - xj.x, dy = xi.y - xj.y;
+            s += sqrt(dx * dx + dy * dy);
+        }
+    }
+    __shared__ double red[1024 / kWave];
+    const double have = block_sum(s, red);
+    if (have == 0.0) {
+        if (threadIdx.x == 0) g.info[3] = 1;
+        return;
+    }
+    const double c = (double)(g.nnz / 2) / have;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double2 v = x[i];
+        x[i] = make_double2(v.x * c, v.y * c);
+    }
+}
+
+hipError_t pool_pivotmds(const PoolGraph* gs, int count, const int4* gram_items, int ngram, const int2* tiles,
+                         int kp_max, int k_max, hipStream_t s) {
+    hipLaunchKernelGGL(k_pool_mds_stats, dim3(count), dim3(1024), 0, s, gs);
+    hipLaunchKernelGGL(k_pool_gram, dim3(ngram), dim3(256), sizeof(double) * ((size_t)kGramSub * kp_max + kp_max), s,
+                       gs, gram_items, tiles);
+    hipLaunchKernelGGL(k_pool_gram_reduce, dim3(32, count), dim3(256), 0, s, gs, tiles);
+    hipLaunchKernelGGL(k_pool_eig, dim3(count), dim3(kEigThreads), sizeof(double) * 4 * (size_t)k_max, s, gs);
+    hipLaunchKernelGGL(k_pool_project, dim3(count), dim3(1024), 0, s, gs);
+    return hipGetLastError();
 }
 
 }  // namespace ssm

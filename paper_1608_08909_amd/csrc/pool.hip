@@ -1,0 +1,1094 @@
+// Layout pool: many small graphs laid out together (Algorithm 1 per graph,
+// batched across graphs).  Each graph keeps its CSR, distance words, weight
+// tables and coordinates resident in one device arena; every stage runs for
+// a whole list of graphs per launch:
+//   - selection, BFS, regions/terms, PivotMDS statistics and eigen step:
+//     one workgroup per graph (or per (graph, rank) / (graph, chunk) item);
+//   - sweeps: one launch per sweep over the 64-node chunks of every listed
+//     graph (one wavefront per chunk), so a graph of 2,000 nodes costs 32
+//     waves of a launch rather than a launch of its own.
+// The arithmetic of every step is the single-graph path's: the same rule R1
+// regions, adapted weights and denominators (Section 3), PivotMDS with the
+// same eigen solver, the FP64 sweep in the oracle's operation order, and the
+// FP32 displacement form of Eq. 5.
+#include <limits.h>
+#include <math.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "ssm_internal.h"
+#include "wave.h"
+
+namespace ssm {
+
+// ------------------------------------------------------------- kernels
+
+// One workgroup per graph: delta and the candidate count per node, regions
+// by rule R1 level by level (single candidates join first, tied nodes then
+// pick the smallest (size snapshot, rank)), the cumulative histograms H, the
+// weight tables w64 / wt2, the denominators and the packed distances.
+__global__ __launch_bounds__(1024) void k_pool_regions(const PoolGraph* __restrict__ gs) {
+#pragma clang fp contract(off)
+    extern __shared__ int psh[];
+    const PoolGraph& g = gs[blockIdx.x];
+    const int n = g.n, k = g.k, kpad = g.kpad, W = g.W;
+    const int* __restrict__ dist = g.dist;
+    int* size = psh;                                               // [k]
+    int* snap = size + k;                                          // [k]
+    unsigned* tied = (unsigned*)(snap + k);                        // [(n + 31) / 32]
+    unsigned short* dl = (unsigned short*)(tied + (n + 31) / 32);  // [n] delta
+    __shared__ int red[1024 / kWave];
+    for (int t = threadIdx.x; t < k; t += blockDim.x) size[t] = 0;
+    for (int w = threadIdx.x; w < (n + 31) / 32; w += blockDim.x) tied[w] = 0u;
+    __syncthreads();
+    int dm = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        int best = INT_MAX, cnt = 0, at = 0;
+        for (int t = 0; t < k; ++t) {
+            const int d = dist[(size_t)t * n + i];
+            if (d < best) {
+                best = d;
+                cnt = 1;
+                at = t;
+            } else if (d == best) {
+                ++cnt;
+            }
+        }
+        g.delta[i] = best;
+        dl[i] = (unsigned short)best;
+        g.region[i] = cnt == 1 ? at : -1;
+        if (cnt > 1) atomicOr(&tied[i >> 5], 1u << (i & 31));
+        dm = max(dm, best);
+    }
+    const int delta_max = block_max(dm, red);
+    // each node i is visited by the same thread in every pass below
+    for (int l = 0; l <= delta_max; ++l) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x)
+            if (dl[i] == l && !((tied[i >> 5] >> (i & 31)) & 1u)) atomicAdd(&size[g.region[i]], 1);
+        __syncthreads();
+        for (int t = threadIdx.x; t < k; t += blockDim.x) snap[t] = size[t];
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            if (dl[i] != l || !((tied[i >> 5] >> (i & 31)) & 1u)) continue;
+            int pick = -1;
+            for (int t = 0; t < k; ++t) {
+                if (dist[(size_t)t * n + i] != l) continue;
+                if (pick < 0 || snap[t] < snap[pick]) pick = t;
+            }
+            g.region[i] = pick;
+            atomicAdd(&size[pick], 1);
+        }
+        __syncthreads();
+    }
+    // raw histogram of (region, delta) by device atomics, read back by
+    // device-scope loads (no stale line of the zeroed table can be used)
+    const int L = delta_max + 1;
+    for (int q = threadIdx.x; q < k * L; q += blockDim.x) g.H[q] = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) atomicAdd(&g.H[(size_t)g.region[i] * L + dl[i]], 1);
+    __syncthreads();
+    // per rank: running sum over the level and the weight row in one walk
+    // (the level needed for distance d is min(d / 2, delta_max), which never
+    // decreases with d)
+    for (int t = threadIdx.x; t < kpad; t += blockDim.x) {
+        if (t >= k) {
+            for (int d = 0; d < W; ++d) {
+                g.w64[(size_t)t * W + d] = 0.0;
+                g.wt2[(size_t)t * W + d] = make_float2(0.f, 0.f);
+            }
+            g.pivots[t] = g.pivots[0];
+            continue;
+        }
+        int acc = 0, l = -1;
+        for (int d = 0; d < W; ++d) {
+            const int half = min(d / 2, L - 1);
+            while (l < half) {
+                ++l;
+                acc += __hip_atomic_load(&g.H[(size_t)t * L + l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                g.H[(size_t)t * L + l] = acc;
+            }
+            const double val = d >= 2 ? (double)acc / (double)((long long)d * (long long)d) : 0.0;
+            g.w64[(size_t)t * W + d] = val;
+            g.wt2[(size_t)t * W + d] = make_float2((float)val, (float)(val * (double)d));
+        }
+        while (l < L - 1) {
+            ++l;
+            acc += __hip_atomic_load(&g.H[(size_t)t * L + l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            g.H[(size_t)t * L + l] = acc;
+        }
+    }
+    __syncthreads();
+    // den_i = deg(i) + sum over ranks ascending of w'_it (d >= 2)
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double s = 0.0;
+        for (int e = g.rp[i]; e < g.rp[i + 1]; ++e) s += 1.0;
+        for (int t = 0; t < k; ++t) {
+            const int d = dist[(size_t)t * n + i];
+            if (d >= 2) s += g.w64[(size_t)t * W + d];
+        }
+        g.den64[i] = s;
+        g.den32[i] = (float)s;
+    }
+    const long long words = (long long)(kpad / 8) * n;
+    for (long long q = threadIdx.x; q < words; q += blockDim.x) {
+        const int b = (int)(q / n), i = (int)(q % n);
+        union {
+            uint4 v;
+            uint16_t e[8];
+        } u;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int t = b * 8 + j;
+            u.e[j] = t < k ? (uint16_t)dist[(size_t)t * n + i] : (uint16_t)0;
+        }
+        g.dpk[q] = u.v;
+    }
+    if (threadIdx.x == 0) g.info[2] = delta_max;
+}
+
+// FP64 sweep, one thread per node, items (graph, first node of 256): Eq. 5
+// in the oracle's order (neighbours at a positive distance in CSR order,
+// then the zero-distance votes, then pivot terms by ascending rank), from
+// x64[src] into x64[src ^ 1].
+__global__ __launch_bounds__(256) void k_pool_sweep64(const PoolGraph* __restrict__ gs,
+                                                      const int2* __restrict__ items, int src) {
+#pragma clang fp contract(off)
+    const int2 st = items[blockIdx.x];
+    const PoolGraph& g = gs[st.x];
+    const int n = g.n, W = g.W, nwords = g.kpad / 8;
+    const int i = st.y + threadIdx.x;
+    if (i >= n) return;
+    const double2* __restrict__ xo = g.x64[src];
+    double2* __restrict__ xn = g.x64[src ^ 1];
+    const double2 xv = xo[i];
+    const double xi = xv.x, yi = xv.y;
+    double nx = 0.0, ny = 0.0;
+    int zero = 0;
+    for (int e = g.rp[i]; e < g.rp[i + 1]; ++e) {
+        const double2 xj = xo[g.ci[e]];
+        double dx = xi - xj.x, dy = yi - xj.y;
+        double r = sqrt(dx * dx + dy * dy);
+        if (r > 0.0) {
+            nx += xj.x + dx / r;
+            ny += xj.y + dy / r;
+        } else {
+            ++zero;
+        }
+    }
+    for (int z = 0; z < zero; ++z) {
+        nx += xi;
+        ny += yi;
+    }
+    for (int b = 0; b < nwords; ++b) {
+        union {
+            uint4 v;
+            uint16_t e[8];
+        } u;
+        u.v = g.dpk[(size_t)b * n + i];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int d = (int)u.e[j];
+            if (d < 2) continue;
+            const int t = b * 8 + j;
+            const double w = g.w64[(size_t)t * W + d];
+            const double2 p = xo[g.pivots[t]];
+            double dx = xi - p.x, dy = yi - p.y;
+            double r = sqrt(dx * dx + dy * dy);
+            double vx = p.x, vy = p.y;
+            if (r > 0.0) {
+                vx = p.x + (double)d * dx / r;
+                vy = p.y + (double)d * dy / r;
+            }
+            nx += w * vx;
+            ny += w * vy;
+        }
+    }
+    const double dn = g.den64[i];
+    xn[i] = make_double2(nx / dn, ny / dn);
+}
+
+// x32[0] = x64[src] rounded to FP32.
+__global__ __launch_bounds__(256) void k_pool_round(const PoolGraph* __restrict__ gs,
+                                                    const int2* __restrict__ items, int src) {
+    const int2 st = items[blockIdx.x];
+    const PoolGraph& g = gs[st.x];
+    const int i = st.y + threadIdx.x;
+    if (i >= g.n) return;
+    const double2 v = g.x64[src][i];
+    g.x32[0][i] = make_float2((float)v.x, (float)v.y);
+}
+
+constexpr int kPoolSweepWaves = 4;
+
+// FP32 sweep s of a call: one wavefront per 64-node chunk (graph, first
+// node).  A graph takes part while s < its iters; it reads x32[(parity + s)
+// & 1] and writes the other buffer.  Eq. 5 in displacement form as the
+// single-graph FP32 sweep: f = w' - (w' d) / r per term, neighbours in CSR
+// order first, then pivot terms by ascending rank; pivot coordinates are
+// staged in LDS per wave.
+__global__ __launch_bounds__(64 * kPoolSweepWaves) void k_pool_sweep32(const PoolGraph* __restrict__ gs,
+                                                                       const int2* __restrict__ chunks,
+                                                                       int nchunks, int s) {
+    __shared__ float2 sP[kPoolSweepWaves][kPoolMaxK];
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const int c = blockIdx.x * kPoolSweepWaves + w;
+    int2 ch = make_int2(0, 0);
+    bool active = false;
+    if (c < nchunks) {
+        ch = chunks[c];
+        active = s < gs[ch.x].iters;
+    }
+    if (active) {
+        const PoolGraph& g = gs[ch.x];
+        const float2* xo = g.x32[(g.parity + s) & 1];
+        for (int t = lane; t < g.kpad; t += kWave) sP[w][t] = xo[g.pivots[t]];
+    }
+    __syncthreads();
+    if (!active) return;
+    const PoolGraph& g = gs[ch.x];
+    const int n = g.n, W = g.W, nwords = g.kpad / 8;
+    const int p = (g.parity + s) & 1;
+    const float2* __restrict__ xo = g.x32[p];
+    float2* __restrict__ xn = g.x32[p ^ 1];
+    const int i = ch.y + lane;
+    if (i >= n) return;
+    const float tiny = 1e-30f;
+    const float2 xi = xo[i];
+    float ax = 0.f, ay = 0.f;
+    const int e0 = g.rp[i], e1 = g.rp[i + 1];
+    for (int e = e0; e < e1; e += 4) {
+        int j[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int cj = g.ci[min(e + q, e1 - 1)];  // unconditional load
+            j[q] = e + q < e1 ? cj : i;               // a missing slot reads x_i: adds exactly 0
+        }
+        float2 xj[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) xj[q] = xo[j[q]];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float dx = xj[q].x - xi.x, dy = xj[q].y - xi.y;
+            const float inv = __builtin_amdgcn_rsqf(dx * dx + (dy * dy + tiny));
+            const float f = 1.f - inv;  // w = 1, d = 1
+            ax += f * dx;
+            ay += f * dy;
+        }
+    }
+    const uint4* __restrict__ dp = g.dpk + i;
+    uint4 wa = nwords > 0 ? dp[0] : make_uint4(0, 0, 0, 0);
+    uint4 wb = nwords > 1 ? dp[(size_t)n] : make_uint4(0, 0, 0, 0);
+    for (int b = 0; b < nwords; ++b) {
+        union {
+            uint4 v;
+            uint16_t e[8];
+        } u;
+        u.v = wa;
+        wa = wb;
+        if (b + 2 < nwords) wb = dp[(size_t)(b + 2) * n];  // two words ahead
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) {
+            const int t = b * 8 + jj;
+            const int d = (int)u.e[jj];
+            const float2 f01 = g.wt2[(size_t)t * W + d];
+            const float2 pv = sP[w][t];
+            const float dx = pv.x - xi.x, dy = pv.y - xi.y;
+            const float inv = __builtin_amdgcn_rsqf(dx * dx + (dy * dy + tiny));
+            const float f = fmaf(-f01.y, inv, f01.x);
+            ax += f * dx;
+            ay += f * dy;
+        }
+    }
+    const float dn = g.den32[i];
+    xn[i] = make_float2(xi.x + ax / dn, xi.y + ay / dn);
+}
+
+// Sparse stress s' (Eq. 3) in FP64 of each graph's current FP32 iterate
+// x32[parity]: one wavefront per 64-node chunk writes its share to
+// partial[chunk] (edge terms i < j over the chunk's arcs, then the pivot
+// terms of its nodes).
+__global__ __launch_bounds__(256) void k_pool_stress(const PoolGraph* __restrict__ gs, const int2* __restrict__ chunks,
+                                                     int nchunks, double* __restrict__ partial) {
+    const int c = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (c >= nchunks) return;  // whole wave
+    const int2 ch = chunks[c];
+    const PoolGraph& g = gs[ch.x];
+    const int n = g.n, W = g.W, nwords = g.kpad / 8;
+    const float2* __restrict__ x = g.x32[g.parity];
+    double acc = 0.0;
+    wave_arcs(n, g.rp, g.ci, ch.y, [&](int i, int j) {
+        if (j <= i) return;
+        const float2 a = x[i], b = x[j];
+        const double dx = (double)a.x - (double)b.x, dy = (double)a.y - (double)b.y;
+        const double r = sqrt(dx * dx + dy * dy);
+        acc += (r - 1.0) * (r - 1.0);
+    });
+    const int i = ch.y + lane_id();
+    if (i < n) {
+        const float2 a = x[i];
+        for (int b = 0; b < nwords; ++b) {
+            union {
+                uint4 v;
+                uint16_t e[8];
+            } u;
+            u.v = g.dpk[(size_t)b * n + i];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int d = (int)u.e[j];
+                if (d < 2) continue;
+                const int t = b * 8 + j;
+                const float2 pv = x[g.pivots[t]];
+                const double dx = (double)a.x - (double)pv.x, dy = (double)a.y - (double)pv.y;
+                const double r = sqrt(dx * dx + dy * dy);
+                acc += g.w64[(size_t)t * W + d] * (r - d) * (r - d);
+            }
+        }
+    }
+    acc = wave_sum(acc);
+    if (lane_id() == 0) partial[c] = acc;
+}
+
+// out[q] = sum of partial[first[q] .. first[q + 1]) in ascending order.
+__global__ void k_pool_stress_sum(int count, const int* __restrict__ first, const double* __restrict__ partial,
+                                  double* __restrict__ out) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= count) return;
+    double s = 0.0;
+    for (int c = first[q]; c < first[q + 1]; ++c) s += partial[c];
+    out[q] = s;
+}
+
+// info words of each listed graph into one array (for a single copy back).
+__global__ void k_pool_gather_info(const PoolGraph* __restrict__ gs, int count, int* __restrict__ out) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= count * 8) return;
+    out[q] = gs[q / 8].info[q % 8];
+}
+
+// --------------------------------------------------------------- arena
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr size_t kNone = ~(size_t)0;
+
+size_t align_up(size_t b) { return (b + kAlign - 1) & ~(kAlign - 1); }
+
+// First-fit allocator over one device allocation; free ranges are kept by
+// offset and merged with their neighbours on release.
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0, used = 0;
+    std::map<size_t, size_t> free_;
+
+    size_t alloc(size_t bytes) {
+        bytes = align_up(std::max<size_t>(bytes, 1));
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            const size_t off = it->first, rem = it->second - bytes;
+            free_.erase(it);
+            if (rem) free_[off + bytes] = rem;
+            used += bytes;
+            return off;
+        }
+        return kNone;
+    }
+    void release(size_t off, size_t bytes) {
+        if (off == kNone) return;
+        bytes = align_up(std::max<size_t>(bytes, 1));
+        used -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+// Bump layout of one arena block: offsets of consecutive aligned arrays.
+struct Layout {
+    size_t bytes = 0;
+    size_t add(size_t b) {
+        const size_t o = bytes;
+        bytes += align_up(b);
+        return o;
+    }
+};
+
+enum SlotState { kFree = 0, kAdded = 1, kReady = 2, kFailed = 3 };
+
+struct Slot {
+    int state = kFree;
+    int n = 0, nnz = 0, k = 0, kpad = 0, first = 0, target = 0, done = 0, parity = 0;
+    int dmax = 0, delta_max = 0, fail = 0, x64cur = 0;
+    size_t off_p = kNone, sz_p = 0, off_s = kNone, sz_s = 0, off_t = kNone, sz_t = 0;
+    PoolGraph g{};
+};
+
+// Staging of one asynchronous sweep call: host copies and device buffer
+// stay untouched until `done` has fired.
+struct Stage {
+    std::vector<PoolGraph> hg;
+    std::vector<int2> hc;
+    char* dev = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+
+}  // namespace
+
+}  // namespace ssm
+
+struct ssm_pool {
+    int device = 0;
+    ssm::Arena arena;
+    std::vector<ssm::Slot> slots;
+    std::vector<int> free_ids;
+    int2* tiles = nullptr;  // Gram tile list for up to kPoolMaxK / 16 tile columns
+    ssm::Stage stage[2];
+    int flip = 0;
+    std::mutex mu;  // calls on one pool are serialized
+};
+
+namespace ssm {
+namespace {
+
+int tile_cols(int k) { return (k + 15) / 16; }
+
+ssm_status wait_stage(Stage& st) {
+    if (st.pending) {
+        hipError_t e = hipEventSynchronize(st.done);
+        st.pending = false;
+        if (e != hipSuccess) return hip_fail(e, "pool: wait for a previous sweep");
+    }
+    return SSM_OK;
+}
+
+ssm_status wait_all(ssm_pool* p) {
+    for (auto& st : p->stage) {
+        ssm_status r = wait_stage(st);
+        if (r != SSM_OK) return r;
+    }
+    return SSM_OK;
+}
+
+// Fills the device pointers of slot s from its blocks.
+void bind(ssm_pool* p, Slot& s) {
+    PoolGraph& g = s.g;
+    const int n = s.n, k = s.k, kpad = s.kpad;
+    g.n = n;
+    g.nnz = s.nnz;
+    g.k = k;
+    g.kpad = kpad;
+    g.first = s.first;
+    g.W = s.dmax + 1;
+    g.L = s.delta_max + 1;
+    g.parity = s.parity;
+    const int T = tile_cols(k);
+    g.ntiles = T * (T + 1) / 2;
+    g.nchunks = div_up(n, kPoolGramChunk);
+    char* P = p->arena.base + s.off_p;
+    Layout lp;
+    g.rp = (const int*)(P + lp.add(sizeof(int) * (n + 1)));
+    g.ci = (const int*)(P + lp.add(sizeof(int) * (size_t)std::max(s.nnz, 1)));
+    g.pivots = (int*)(P + lp.add(sizeof(int) * kpad));
+    g.dpk = (uint4*)(P + lp.add(sizeof(uint4) * (size_t)(kpad / 8) * n));
+    g.delta = (int*)(P + lp.add(sizeof(int) * n));
+    g.region = (int*)(P + lp.add(sizeof(int) * n));
+    g.den64 = (double*)(P + lp.add(sizeof(double) * n));
+    g.den32 = (float*)(P + lp.add(sizeof(float) * n));
+    g.x64[0] = (double2*)(P + lp.add(sizeof(double2) * n));
+    g.x64[1] = (double2*)(P + lp.add(sizeof(double2) * n));
+    g.x32[0] = (float2*)(P + lp.add(sizeof(float2) * n));
+    g.x32[1] = (float2*)(P + lp.add(sizeof(float2) * n));
+    g.info = (int*)(P + lp.add(sizeof(int) * 8));
+    if (s.off_s != kNone) {
+        char* S = p->arena.base + s.off_s;
+        Layout ls;
+        g.ell = (int*)(S + ls.add(sizeof(int) * (size_t)n * kPoolEllW));
+        g.dist = (int*)(S + ls.add(sizeof(int) * (size_t)k * n));
+        g.m = (int*)(S + ls.add(sizeof(int) * n));
+        g.gq = (int*)(S + ls.add(sizeof(int) * 3 * (size_t)n));
+        g.colsum = (long long*)(S + ls.add(sizeof(long long) * k));
+        g.mu = (double*)(S + ls.add(sizeof(double) * k));
+        g.nu = (double*)(S + ls.add(sizeof(double) * n));
+        g.stats = (double*)(S + ls.add(sizeof(double) * 4));
+        g.M = (double*)(S + ls.add(sizeof(double) * (size_t)k * k));
+        g.eig = (double*)(S + ls.add(sizeof(double) * (2 * (size_t)k + 2)));
+        g.gpart = (double*)(S + ls.add(sizeof(double) * (size_t)g.nchunks * g.ntiles * 256));
+    } else {
+        g.ell = g.dist = g.m = g.gq = nullptr;
+        g.colsum = nullptr;
+        g.mu = g.nu = g.stats = g.M = g.eig = g.gpart = nullptr;
+    }
+    if (s.off_t != kNone) {
+        char* T2 = p->arena.base + s.off_t;
+        Layout lt;
+        const size_t kw = (size_t)kpad * g.W;
+        g.H = (int*)(T2 + lt.add(sizeof(int) * (size_t)k * g.W));
+        g.w64 = (double*)(T2 + lt.add(sizeof(double) * kw));
+        g.wt2 = (float2*)(T2 + lt.add(sizeof(float2) * kw));
+    } else {
+        g.H = nullptr;
+        g.w64 = nullptr;
+        g.wt2 = nullptr;
+    }
+}
+
+size_t persist_bytes(int n, int nnz, int kpad) {
+    Layout l;
+    l.add(sizeof(int) * (n + 1));
+    l.add(sizeof(int) * (size_t)std::max(nnz, 1));
+    l.add(sizeof(int) * kpad);
+    l.add(sizeof(uint4) * (size_t)(kpad / 8) * n);
+    l.add(sizeof(int) * n);
+    l.add(sizeof(int) * n);
+    l.add(sizeof(double) * n);
+    l.add(sizeof(float) * n);
+    l.add(sizeof(double2) * n);
+    l.add(sizeof(double2) * n);
+    l.add(sizeof(float2) * n);
+    l.add(sizeof(float2) * n);
+    l.add(sizeof(int) * 8);
+    return l.bytes;
+}
+
+size_t scratch_bytes(int n, int k) {
+    const int T = tile_cols(k);
+    Layout l;
+    l.add(sizeof(int) * (size_t)n * kPoolEllW);
+    l.add(sizeof(int) * (size_t)k * n);
+    l.add(sizeof(int) * n);
+    l.add(sizeof(int) * 3 * (size_t)n);
+    l.add(sizeof(long long) * k);
+    l.add(sizeof(double) * k);
+    l.add(sizeof(double) * n);
+    l.add(sizeof(double) * 4);
+    l.add(sizeof(double) * (size_t)k * k);
+    l.add(sizeof(double) * (2 * (size_t)k + 2));
+    l.add(sizeof(double) * (size_t)div_up(n, kPoolGramChunk) * (T * (T + 1) / 2) * 256);
+    return l.bytes;
+}
+
+size_t table_bytes(int k, int kpad, int W) {
+    Layout l;
+    l.add(sizeof(int) * (size_t)k * W);
+    l.add(sizeof(double) * (size_t)kpad * W);
+    l.add(sizeof(float2) * (size_t)kpad * W);
+    return l.bytes;
+}
+
+// Simple undirected graph in CSR: rows monotone from 0 to nnz, ids in range,
+// no self-loops, every arc has its reverse, no duplicate arcs.
+ssm_status check_host_csr(int n, int nnz, const int* rp, const int* ci) {
+    if (rp[0] != 0 || rp[n] != nnz) return fail(SSM_E_INVAL, "pool: row_ptr must run from 0 to nnz");
+    for (int i = 0; i < n; ++i)
+        if (rp[i + 1] < rp[i]) return fail(SSM_E_INVAL, "pool: row_ptr is not monotone");
+    std::vector<int> row;
+    for (int i = 0; i < n; ++i) {
+        row.assign(ci + rp[i], ci + rp[i + 1]);
+        std::sort(row.begin(), row.end());
+        for (size_t q = 0; q < row.size(); ++q) {
+            const int j = row[q];
+            if (j < 0 || j >= n || j == i) return fail(SSM_E_INVAL, "pool: column index out of range or self-loop");
+            if (q > 0 && row[q - 1] == j) return fail(SSM_E_INVAL, "pool: duplicate arc");
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int e = rp[i]; e < rp[i + 1]; ++e) {
+            const int j = ci[e];
+            bool back = false;
+            for (int f = rp[j]; f < rp[j + 1] && !back; ++f) back = ci[f] == i;
+            if (!back) return fail(SSM_E_INVAL, "pool: adjacency is not symmetric");
+        }
+    return SSM_OK;
+}
+
+Slot* get_slot(ssm_pool* p, int id) {
+    if (id < 0 || id >= (int)p->slots.size() || p->slots[id].state == kFree) return nullptr;
+    return &p->slots[id];
+}
+
+void release_scratch(ssm_pool* p, Slot& s) {
+    p->arena.release(s.off_s, s.sz_s);
+    s.off_s = kNone;
+    s.sz_s = 0;
+}
+
+}  // namespace
+}  // namespace ssm
+
+using namespace ssm;
+
+extern "C" {
+
+ssm_status ssm_pool_create(int64_t capacity_bytes, ssm_pool** out) {
+    if (!out) return fail(SSM_E_INVAL, "out is NULL");
+    if (capacity_bytes < (int64_t)(1 << 20)) return fail(SSM_E_INVAL, "pool capacity below 1 MiB");
+    ssm_pool* p = new ssm_pool();
+    (void)hipGetDevice(&p->device);
+    p->arena.cap = align_up((size_t)capacity_bytes);
+    if (hipMalloc((void**)&p->arena.base, p->arena.cap) != hipSuccess) {
+        (void)hipGetLastError();
+        delete p;
+        return fail(SSM_E_NOMEM, "pool: device allocation failed");
+    }
+    p->arena.free_[0] = p->arena.cap;
+    const int T = kPoolMaxK / 16;
+    std::vector<int2> ht;
+    for (int b = 0; b < T; ++b)
+        for (int a = 0; a <= b; ++a) ht.push_back(make_int2(a, b));
+    hipError_t e = hipMalloc((void**)&p->tiles, sizeof(int2) * ht.size());
+    if (e == hipSuccess) e = hipMemcpy(p->tiles, ht.data(), sizeof(int2) * ht.size(), hipMemcpyHostToDevice);
+    for (auto& st : p->stage)
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&st.done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        ssm_pool_destroy(p);
+        return hip_fail(e, "pool: create");
+    }
+    *out = p;
+    return SSM_OK;
+}
+
+void ssm_pool_destroy(ssm_pool* p) {
+    if (!p) return;
+    (void)wait_all(p);
+    for (auto& st : p->stage) {
+        if (st.dev) (void)hipFree(st.dev);
+        if (st.done) (void)hipEventDestroy(st.done);
+    }
+    if (p->tiles) (void)hipFree(p->tiles);
+    if (p->arena.base) (void)hipFree(p->arena.base);
+    delete p;
+}
+
+ssm_status ssm_pool_usage(ssm_pool* p, int64_t* used, int64_t* capacity) {
+    if (!p) return fail(SSM_E_INVAL, "pool is NULL");
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (used) *used = (int64_t)p->arena.used;
+    if (capacity) *capacity = (int64_t)p->arena.cap;
+    return SSM_OK;
+}
+
+ssm_status ssm_pool_add(ssm_pool* p, int32_t n, int32_t nnz, const int32_t* row_ptr_host,
+                        const int32_t* col_idx_host, int32_t k, int32_t first, int32_t sweeps, int32_t* slot_out,
+                        hipStream_t stream) {
+    if (!p || !row_ptr_host || (!col_idx_host && nnz > 0) || !slot_out) return fail(SSM_E_INVAL, "NULL argument");
+    if (n < 1 || n > kPoolMaxN) return fail(SSM_E_RANGE, "pool graphs have 1 <= n <= 65536 nodes");
+    if (nnz < 0) return fail(SSM_E_INVAL, "nnz < 0");
+    if (k < 3 || k > n || k > kPoolMaxK) return fail(SSM_E_RANGE, "pool graphs need 3 <= k <= min(n, 256)");
+    if (first < 0 || first >= n) return fail(SSM_E_INVAL, "first must lie in [0, n)");
+    if (sweeps < 1) return fail(SSM_E_INVAL, "sweeps must be at least 1");
+    ssm_status st = check_host_csr(n, nnz, row_ptr_host, col_idx_host);
+    if (st != SSM_OK) return st;
+    std::lock_guard<std::mutex> lk(p->mu);
+    Slot s;
+    s.n = n;
+    s.nnz = nnz;
+    s.k = k;
+    s.kpad = div_up(k, 8) * 8;
+    s.first = first;
+    s.target = sweeps;
+    s.sz_p = persist_bytes(n, nnz, s.kpad);
+    s.sz_s = scratch_bytes(n, k);
+    s.off_p = p->arena.alloc(s.sz_p);
+    if (s.off_p != kNone) s.off_s = p->arena.alloc(s.sz_s);
+    if (s.off_p == kNone || s.off_s == kNone) {
+        p->arena.release(s.off_p, s.sz_p);
+        return fail(SSM_E_NOMEM, "pool: capacity exhausted");
+    }
+    s.state = kAdded;
+    bind(p, s);
+    hipError_t e = hipMemcpyAsync((void*)s.g.rp, row_ptr_host, sizeof(int) * (n + 1), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && nnz > 0)
+        e = hipMemcpyAsync((void*)s.g.ci, col_idx_host, sizeof(int) * (size_t)nnz, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        p->arena.release(s.off_p, s.sz_p);
+        p->arena.release(s.off_s, s.sz_s);
+        return hip_fail(e, "pool: copy graph");
+    }
+    int id;
+    if (!p->free_ids.empty()) {
+        id = p->free_ids.back();
+        p->free_ids.pop_back();
+        p->slots[id] = s;
+    } else {
+        id = (int)p->slots.size();
+        p->slots.push_back(s);
+    }
+    *slot_out = id;
+    return SSM_OK;
+}
+
+ssm_status ssm_pool_prepare(ssm_pool* p, int32_t count, const int32_t* slots, int32_t warm, hipStream_t s) {
+    if (!p || (count > 0 && !slots)) return fail(SSM_E_INVAL, "NULL argument");
+    if (count < 0 || warm < 0) return fail(SSM_E_INVAL, "count and warm must be >= 0");
+    std::lock_guard<std::mutex> lk(p->mu);
+    std::vector<int> ids;
+    for (int q = 0; q < count; ++q) {
+        Slot* sl = get_slot(p, slots[q]);
+        if (!sl || sl->state != kAdded) return fail(SSM_E_INVAL, "pool: prepare needs slots that are added, not yet prepared");
+        for (int r : ids)
+            if (r == slots[q]) return fail(SSM_E_INVAL, "pool: a slot is listed twice");
+        ids.push_back(slots[q]);
+    }
+    if (ids.empty()) return SSM_OK;
+    // per-call device buffers: descriptors, BFS items, Gram items, BFS
+    // overflow queues, info copy
+    int nmax = 0, kmax = 0, kpmax = 0;
+    long long nbfs = 0, ngram = 0;
+    for (int id : ids) {
+        const Slot& sl = p->slots[id];
+        nmax = std::max(nmax, sl.n);
+        kmax = std::max(kmax, sl.k);
+        kpmax = std::max(kpmax, tile_cols(sl.k) * 16);
+        nbfs += sl.k;
+        const int T = tile_cols(sl.k);
+        ngram += (long long)div_up(sl.n, kPoolGramChunk) * div_up(T * (T + 1) / 2, 32);
+    }
+    const int nq = (int)ids.size();
+    const int bfs_blocks = (int)std::min<long long>(nbfs, 2LL * num_cus());
+    const long long gq_stride = 3LL * nmax;
+    Layout lw;
+    const size_t o_g = lw.add(sizeof(PoolGraph) * nq), o_bi = lw.add(sizeof(int2) * nbfs),
+                 o_gi = lw.add(sizeof(int4) * ngram), o_q = lw.add(sizeof(int) * gq_stride * bfs_blocks),
+                 o_info = lw.add(sizeof(int) * 8 * nq);
+    long long nitems = 0;  // 256-node items of the FP64 stages
+    for (int id : ids) nitems += div_up(p->slots[id].n, 256);
+    const size_t o_it = lw.add(sizeof(int2) * nitems);
+    char* ws = nullptr;
+    ssm_status st = salloc((void**)&ws, lw.bytes);
+    if (st != SSM_OK) return st;
+    PoolGraph* dg = (PoolGraph*)(ws + o_g);
+    int2* dbi = (int2*)(ws + o_bi);
+    int4* dgi = (int4*)(ws + o_gi);
+    int* dq = (int*)(ws + o_q);
+    int* dinfo = (int*)(ws + o_info);
+    int2* dit = (int2*)(ws + o_it);
+    std::vector<PoolGraph> hg(nq);
+    std::vector<int2> hbi, hit;
+    std::vector<int4> hgi;
+    for (int q = 0; q < nq; ++q) {
+        Slot& sl = p->slots[ids[q]];
+        bind(p, sl);
+        hg[q] = sl.g;
+        for (int t = 0; t < sl.k; ++t) hbi.push_back(make_int2(q, t));
+        for (int i0 = 0; i0 < sl.n; i0 += 256) hit.push_back(make_int2(q, i0));
+    }
+    hipError_t e = hipMemcpyAsync(dg, hg.data(), sizeof(PoolGraph) * nq, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dbi, hbi.data(), sizeof(int2) * nbfs, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dit, hit.data(), sizeof(int2) * nitems, hipMemcpyHostToDevice, s);
+    // stage 1: selection and BFS
+    if (e == hipSuccess) e = pool_prep_init(dg, nq, nmax, s);
+    if (e == hipSuccess) e = pool_select(dg, nq, s);
+    if (e == hipSuccess) e = pool_bfs(dg, dbi, (int)nbfs, dq, gq_stride, bfs_blocks, s);
+    std::vector<int> hinfo(8 * (size_t)nq);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_pool_gather_info, dim3(div_up(8 * nq, 256)), dim3(256), 0, s, dg, nq, dinfo);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(hinfo.data(), dinfo, sizeof(int) * 8 * nq, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    // stage 2: tables for the connected graphs, then regions, terms,
+    // PivotMDS and the FP64 warm-up sweeps
+    std::vector<int> ok;  // positions in ids
+    if (e == hipSuccess) {
+        for (int q = 0; q < nq; ++q) {
+            Slot& sl = p->slots[ids[q]];
+            if (hinfo[8 * q] != 0) {
+                sl.state = kFailed;
+                sl.fail = SSM_E_DISCONNECTED;
+                continue;
+            }
+            sl.dmax = hinfo[8 * q + 1];
+            sl.sz_t = table_bytes(sl.k, sl.kpad, sl.dmax + 1);
+            sl.off_t = p->arena.alloc(sl.sz_t);
+            if (sl.off_t == kNone) {
+                sl.state = kFailed;
+                sl.fail = SSM_E_NOMEM;
+                continue;
+            }
+            bind(p, sl);
+            hg[q] = sl.g;
+            ok.push_back(q);
+        }
+    }
+    if (e == hipSuccess && !ok.empty()) {
+        // compact the descriptors of the graphs that go on
+        std::vector<PoolGraph> h2;
+        std::vector<int4> hgi2;
+        std::vector<int2> hit2;
+        int kmx = 0, kpmx = 0, nmx = 0;
+        for (size_t r = 0; r < ok.size(); ++r) {
+            const Slot& sl = p->slots[ids[ok[r]]];
+            h2.push_back(hg[ok[r]]);
+            kmx = std::max(kmx, sl.k);
+            kpmx = std::max(kpmx, tile_cols(sl.k) * 16);
+            nmx = std::max(nmx, sl.n);
+            const int T = tile_cols(sl.k), ng = div_up(T * (T + 1) / 2, 32);
+            for (int c = 0; c < div_up(sl.n, kPoolGramChunk); ++c)
+                for (int grp = 0; grp < ng; ++grp) hgi2.push_back(make_int4((int)r, c, grp, 0));
+            for (int i0 = 0; i0 < sl.n; i0 += 256) hit2.push_back(make_int2((int)r, i0));
+        }
+        const int nok = (int)ok.size();
+        e = hipMemcpyAsync(dg, h2.data(), sizeof(PoolGraph) * nok, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(dgi, hgi2.data(), sizeof(int4) * hgi2.size(), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(dit, hit2.data(), sizeof(int2) * hit2.size(), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) {
+            const size_t lds = sizeof(int) * 2 * (size_t)kmx + sizeof(unsigned) * (size_t)div_up(nmx, 32) +
+                               sizeof(unsigned short) * (size_t)nmx;
+            if (lds > 64 * 1024)
+                (void)hipFuncSetAttribute((const void*)k_pool_regions, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          (int)lds);
+            hipLaunchKernelGGL(k_pool_regions, dim3(nok), dim3(1024), lds, s, dg);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = pool_pivotmds(dg, nok, dgi, (int)hgi2.size(), p->tiles, kpmx, kmx, s);
+        int src = 0;
+        for (int w = 0; w < warm && e == hipSuccess; ++w, src ^= 1) {
+            hipLaunchKernelGGL(k_pool_sweep64, dim3((int)hit2.size()), dim3(256), 0, s, dg, dit, src);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_pool_round, dim3((int)hit2.size()), dim3(256), 0, s, dg, dit, src);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_pool_gather_info, dim3(div_up(8 * nok, 256)), dim3(256), 0, s, dg, nok, dinfo);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(hinfo.data(), dinfo, sizeof(int) * 8 * nok, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e == hipSuccess) {
+            for (int r = 0; r < nok; ++r) {
+                Slot& sl = p->slots[ids[ok[r]]];
+                sl.delta_max = hinfo[8 * r + 2];
+                if (hinfo[8 * r + 3] != 0) {
+                    sl.state = kFailed;
+                    sl.fail = SSM_E_INVAL;  // zero total edge length
+                    continue;
+                }
+                sl.state = kReady;
+                sl.done = warm;
+                sl.parity = 0;
+                sl.x64cur = warm & 1;
+            }
+        }
+    }
+    (void)hipStreamSynchronize(s);  // idle before scratch and per-call buffers are reused
+    sfree(ws);
+    for (int id : ids) {
+        Slot& sl = p->slots[id];
+        release_scratch(p, sl);
+        if (sl.state == kAdded) {  // stopped by an error before it was decided
+            sl.state = kFailed;
+            sl.fail = SSM_E_DEVICE;
+        }
+        bind(p, sl);
+    }
+    if (e != hipSuccess) return hip_fail(e, "pool: prepare");
+    return SSM_OK;
+}
+
+ssm_status ssm_pool_sweep(ssm_pool* p, int32_t count, const int32_t* slots, int32_t iters, hipStream_t s) {
+    if (!p || (count > 0 && !slots)) return fail(SSM_E_INVAL, "NULL argument");
+    if (count < 0 || iters < 0) return fail(SSM_E_INVAL, "count and iters must be >= 0");
+    std::lock_guard<std::mutex> lk(p->mu);
+    for (int q = 0; q < count; ++q) {
+        Slot* sl = get_slot(p, slots[q]);
+        if (!sl || sl->state != kReady) return fail(SSM_E_INVAL, "pool: sweep needs prepared slots");
+        for (int r = 0; r < q; ++r)
+            if (slots[r] == slots[q]) return fail(SSM_E_INVAL, "pool: a slot is listed twice");
+    }
+    if (count == 0 || iters == 0) return SSM_OK;
+    Stage& stg = p->stage[p->flip];
+    ssm_status st = wait_stage(stg);
+    if (st != SSM_OK) return st;
+    stg.hg.clear();
+    stg.hc.clear();
+    int most = 0;
+    for (int q = 0; q < count; ++q) {
+        Slot& sl = p->slots[slots[q]];
+        PoolGraph g = sl.g;
+        g.iters = std::max(0, std::min(iters, sl.target - sl.done));
+        g.parity = sl.parity;
+        most = std::max(most, g.iters);
+        stg.hg.push_back(g);
+        for (int i0 = 0; i0 < sl.n; i0 += kWave) stg.hc.push_back(make_int2(q, i0));
+    }
+    if (most == 0) return SSM_OK;
+    const size_t need = align_up(sizeof(PoolGraph) * stg.hg.size()) + sizeof(int2) * stg.hc.size();
+    if (need > stg.cap) {
+        const size_t want = std::max(need, stg.cap * 2);
+        if (stg.dev) (void)hipFree(stg.dev);
+        stg.dev = nullptr;
+        stg.cap = 0;
+        if (hipMalloc((void**)&stg.dev, want) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(SSM_E_NOMEM, "pool: sweep staging buffer");
+        }
+        stg.cap = want;
+    }
+    PoolGraph* dg = (PoolGraph*)stg.dev;
+    int2* dc = (int2*)(stg.dev + align_up(sizeof(PoolGraph) * stg.hg.size()));
+    hipError_t e = hipMemcpyAsync(dg, stg.hg.data(), sizeof(PoolGraph) * stg.hg.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dc, stg.hc.data(), sizeof(int2) * stg.hc.size(), hipMemcpyHostToDevice, s);
+    const int nch = (int)stg.hc.size();
+    for (int it = 0; it < most && e == hipSuccess; ++it) {
+        hipLaunchKernelGGL(k_pool_sweep32, dim3(div_up(nch, kPoolSweepWaves)), dim3(64 * kPoolSweepWaves), 0, s, dg,
+                           dc, nch, it);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(stg.done, s);
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(s);
+        return hip_fail(e, "pool: sweep");
+    }
+    stg.pending = true;
+    p->flip ^= 1;
+    for (int q = 0; q < count; ++q) {
+        Slot& sl = p->slots[slots[q]];
+        const int d = stg.hg[q].iters;
+        sl.done += d;
+        sl.parity = (sl.parity + d) & 1;
+        sl.g.parity = sl.parity;
+    }
+    return SSM_OK;
+}
+
+ssm_status ssm_pool_stress(ssm_pool* p, int32_t count, const int32_t* slots, double* out_host, hipStream_t s) {
+    if (!p || (count > 0 && (!slots || !out_host))) return fail(SSM_E_INVAL, "NULL argument");
+    if (count < 0) return fail(SSM_E_INVAL, "count must be >= 0");
+    std::lock_guard<std::mutex> lk(p->mu);
+    std::vector<PoolGraph> hg;
+    std::vector<int2> hc;
+    std::vector<int> first;
+    for (int q = 0; q < count; ++q) {
+        Slot* sl = get_slot(p, slots[q]);
+        if (!sl || sl->state != kReady) return fail(SSM_E_INVAL, "pool: stress needs prepared slots");
+        hg.push_back(sl->g);
+        first.push_back((int)hc.size());
+        for (int i0 = 0; i0 < sl->n; i0 += kWave) hc.push_back(make_int2(q, i0));
+    }
+    first.push_back((int)hc.size());
+    if (count == 0) return SSM_OK;
+    ssm_status st0 = wait_all(p);  // the slots' last sweeps may run on another stream
+    if (st0 != SSM_OK) return st0;
+    Layout l;
+    const size_t o_g = l.add(sizeof(PoolGraph) * count), o_c = l.add(sizeof(int2) * hc.size()),
+                 o_f = l.add(sizeof(int) * first.size()), o_p = l.add(sizeof(double) * hc.size()),
+                 o_o = l.add(sizeof(double) * count);
+    char* ws = nullptr;
+    ssm_status st = salloc((void**)&ws, l.bytes);
+    if (st != SSM_OK) return st;
+    hipError_t e = hipMemcpyAsync(ws + o_g, hg.data(), sizeof(PoolGraph) * count, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(ws + o_c, hc.data(), sizeof(int2) * hc.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ws + o_f, first.data(), sizeof(int) * first.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        const int nch = (int)hc.size();
+        hipLaunchKernelGGL(k_pool_stress, dim3(div_up(nch, 4)), dim3(256), 0, s, (const PoolGraph*)(ws + o_g),
+                           (const int2*)(ws + o_c), nch, (double*)(ws + o_p));
+        hipLaunchKernelGGL(k_pool_stress_sum, dim3(div_up(count, 64)), dim3(64), 0, s, count,
+                           (const int*)(ws + o_f), (const double*)(ws + o_p), (double*)(ws + o_o));
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(out_host, ws + o_o, sizeof(double) * count, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipStreamSynchronize(s);
+    sfree(ws);
+    if (e != hipSuccess) return hip_fail(e, "pool: stress");
+    return SSM_OK;
+}
+
+ssm_status ssm_pool_layout(ssm_pool* p, int32_t slot, float* x_out, hipStream_t s) {
+    if (!p || !x_out) return fail(SSM_E_INVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(p->mu);
+    Slot* sl = get_slot(p, slot);
+    if (!sl || sl->state != kReady) return fail(SSM_E_INVAL, "pool: layout needs a prepared slot");
+    ssm_status st = wait_all(p);  // the slot's last sweep may run on another stream
+    if (st != SSM_OK) return st;
+    SSM_HIP(hipMemcpyAsync(x_out, sl->g.x32[sl->parity], sizeof(float2) * sl->n, hipMemcpyDeviceToDevice, s));
+    return SSM_OK;
+}
+
+ssm_status ssm_pool_export(ssm_pool* p, int32_t slot, int32_t what, void* host_out, hipStream_t s) {
+    if (!p || !host_out) return fail(SSM_E_INVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(p->mu);
+    Slot* sl = get_slot(p, slot);
+    if (!sl || sl->state != kReady) return fail(SSM_E_INVAL, "pool: export needs a prepared slot");
+    ssm_status st = wait_all(p);
+    if (st != SSM_OK) return st;
+    const PoolGraph& g = sl->g;
+    const size_t n = sl->n, k = sl->k, W = sl->dmax + 1, L = sl->delta_max + 1;
+    const void* src = nullptr;
+    size_t bytes = 0;
+    std::vector<uint4> words;
+    switch (what) {
+        case SSM_POOL_PIVOTS: src = g.pivots; bytes = sizeof(int) * k; break;
+        case SSM_POOL_DELTA: src = g.delta; bytes = sizeof(int) * n; break;
+        case SSM_POOL_REGION: src = g.region; bytes = sizeof(int) * n; break;
+        case SSM_POOL_H: src = g.H; bytes = sizeof(int) * k * L; break;
+        case SSM_POOL_WTAB64: src = g.w64; bytes = sizeof(double) * k * W; break;
+        case SSM_POOL_DEN64: src = g.den64; bytes = sizeof(double) * n; break;
+        case SSM_POOL_X32: src = g.x32[sl->parity]; bytes = sizeof(float2) * n; break;
+        case SSM_POOL_X64: src = g.x64[sl->x64cur]; bytes = sizeof(double2) * n; break;
+        case SSM_POOL_DIST: {
+            words.resize((size_t)(sl->kpad / 8) * n);
+            SSM_HIP(hipMemcpyAsync(words.data(), g.dpk, sizeof(uint4) * words.size(), hipMemcpyDeviceToHost, s));
+            SSM_HIP(hipStreamSynchronize(s));
+            int32_t* out = (int32_t*)host_out;
+            for (size_t t = 0; t < k; ++t)
+                for (size_t i = 0; i < n; ++i) {
+                    const uint16_t* e = (const uint16_t*)&words[(t / 8) * n + i];
+                    out[t * n + i] = e[t % 8];
+                }
+            return SSM_OK;
+        }
+        default: return fail(SSM_E_INVAL, "pool: unknown export");
+    }
+    SSM_HIP(hipMemcpyAsync(host_out, src, bytes, hipMemcpyDeviceToHost, s));
+    SSM_HIP(hipStreamSynchronize(s));
+    return SSM_OK;
+}
+
+ssm_status ssm_pool_info(ssm_pool* p, int32_t slot, int32_t* info_host) {
+    if (!p || !info_host) return fail(SSM_E_INVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(p->mu);
+    Slot* sl = get_slot(p, slot);
+    if (!sl) return fail(SSM_E_INVAL, "pool: no such slot");
+    const int32_t v[8] = {sl->state, sl->fail, sl->n, sl->k, sl->done, sl->target, sl->dmax, sl->delta_max};
+    for (int q = 0; q < 8; ++q) info_host[q] = v[q];
+    return SSM_OK;
+}
+
+ssm_status ssm_pool_remove(ssm_pool* p, int32_t slot) {
+    if (!p) return fail(SSM_E_INVAL, "pool is NULL");
+    std::lock_guard<std::mutex> lk(p->mu);
+    Slot* sl = get_slot(p, slot);
+    if (!sl) return fail(SSM_E_INVAL, "pool: no such slot");
+    ssm_status st = wait_all(p);  // no queued sweep may still read the slot
+    if (st != SSM_OK) return st;
+    p->arena.release(sl->off_p, sl->sz_p);
+    p->arena.release(sl->off_s, sl->sz_s);
+    p->arena.release(sl->off_t, sl->sz_t);
+    *sl = Slot();
+    p->free_ids.push_back(slot);
+    return SSM_OK;
+}
+
+}  // extern "C"

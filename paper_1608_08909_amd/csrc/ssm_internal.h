@@ -112,6 +112,63 @@ ssm_status stress_sparse(const ssm_csr* g, ssm_terms* t, ssm_prec p, const void*
 ssm_status stress_full(const ssm_csr* g, ssm_prec p, const void* x, double* out_host,
                        hipStream_t s);
 
+// ---- layout pool (pool.hip): many small graphs per launch
+//
+// Device descriptor of one pool graph.  Every graph keeps its own CSR with
+// local ids; the batched kernels map a block (or a wave) to a graph through
+// an array of these.
+constexpr int kPoolMaxN = 65536;  // LDS holds a 2-byte delta per node in the regions stage
+constexpr int kPoolMaxK = 256;    // pivot coordinates staged per wave; Gram and eigen step in registers
+constexpr int kPoolEllW = 16;     // padded adjacency width
+constexpr int kPoolGramChunk = 2048;
+
+struct PoolGraph {
+    int n, nnz, k, kpad;   // kpad: k rounded up to 8 (uint16 words)
+    int first, W, L, iters;  // max/min start; table row length dmax + 1; delta_max + 1; sweeps in this call
+    int parity, ntiles, nchunks, pad_;  // FP32 buffer holding the current iterate; Gram tiles, Gram node chunks
+    const int* rp;          // [n + 1] local arc offsets
+    const int* ci;          // [nnz] local ids
+    int* ell;               // [n][kPoolEllW] (preparation)
+    int* pivots;            // [kpad], padding repeats pivots[0]
+    int* dist;              // [k][n] (preparation)
+    uint4* dpk;             // [kpad / 8][n] packed uint16 distances
+    int* delta;             // [n]
+    int* region;            // [n]
+    int* H;                 // [k][L] cumulative region histograms (room for k W)
+    double* w64;            // [kpad][W]
+    float2* wt2;            // [kpad][W]: (w', w' d) in FP32
+    double* den64;          // [n]
+    float* den32;           // [n]
+    double2* x64[2];        // FP64 iterates (PivotMDS, warm-up sweeps)
+    float2* x32[2];         // FP32 iterates
+    int* m;                 // [n] max/min scratch
+    int* gq;                // [3 n] max/min frontier overflow
+    long long* colsum;      // [k]
+    double* mu;             // [k]
+    double* nu;             // [n]
+    double* stats;          // [4]
+    double* M;              // [k][k]
+    double* eig;            // [2 k + 2]
+    double* gpart;          // [nchunks][ntiles][256] Gram partial tiles
+    int* info;              // [8]: disconnected, dmax, delta_max, zero edge length, eigen steps
+};
+
+// Stages (bfs.hip): fill the max/min scratch and the padded adjacency; one
+// max/min selection per graph (one workgroup each); the k BFS per graph as
+// (graph, rank) items over a persistent grid with gq_stride ints of overflow
+// queue per block.
+hipError_t pool_prep_init(const PoolGraph* gs, int count, int nmax, hipStream_t s);
+hipError_t pool_select(const PoolGraph* gs, int count, hipStream_t s);
+hipError_t pool_bfs(const PoolGraph* gs, const int2* items, int nitems, int* gq, long long gq_stride, int blocks,
+                    hipStream_t s);
+// Stages (pmds.hip): centring statistics, Gram partial tiles as
+// (graph, node chunk, tile group) items, their reduction, the eigen step and
+// the projection + rescale into x64[0].  tiles lists the 16 x 16 tiles of the
+// upper triangle column by column, so a graph with T tile columns uses the
+// first T (T + 1) / 2.
+hipError_t pool_pivotmds(const PoolGraph* gs, int count, const int4* gram_items, int ngram, const int2* tiles,
+                         int kp_max, int k_max, hipStream_t s);
+
 // Deterministic FP64 sum of `count` partials on the device into out (device).
 void launch_sum_partials(const double* partials, int count, double* out, hipStream_t s);
 

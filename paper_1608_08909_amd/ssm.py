@@ -40,6 +40,8 @@ EXPORTS = [
     "ssm_validate_csr", "ssm_select_pivots", "ssm_bfs_pivots", "ssm_regions", "ssm_kmeans_pivots", "ssm_build_terms",
     "ssm_terms_free", "ssm_terms_dims", "ssm_terms_export", "ssm_pivotmds_init",
     "ssm_pivotmds_eig", "ssm_pivotmds_gram", "ssm_majorize", "ssm_majorize_mixed", "ssm_stress", "ssm_last_error",
+    "ssm_pool_create", "ssm_pool_destroy", "ssm_pool_usage", "ssm_pool_add", "ssm_pool_prepare", "ssm_pool_sweep",
+    "ssm_pool_stress", "ssm_pool_layout", "ssm_pool_export", "ssm_pool_info", "ssm_pool_remove",
 ]
 
 
@@ -73,6 +75,17 @@ def load(path: str | None = None):
             "ssm_majorize_mixed": (S, [P, V, V, V, I, I, V]),
             "ssm_stress": (S, [P, V, I, V, I, V, V]),
             "ssm_last_error": (ctypes.c_char_p, []),
+            "ssm_pool_create": (S, [ctypes.c_int64, ctypes.POINTER(V)]),
+            "ssm_pool_destroy": (None, [V]),
+            "ssm_pool_usage": (S, [V, V, V]),
+            "ssm_pool_add": (S, [V, I, I, V, V, I, I, I, V, V]),
+            "ssm_pool_prepare": (S, [V, I, V, I, V]),
+            "ssm_pool_sweep": (S, [V, I, V, I, V]),
+            "ssm_pool_stress": (S, [V, I, V, V, V]),
+            "ssm_pool_layout": (S, [V, I, V, V]),
+            "ssm_pool_export": (S, [V, I, I, V, V]),
+            "ssm_pool_info": (S, [V, I, V]),
+            "ssm_pool_remove": (S, [V, I]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -299,3 +312,99 @@ def layout(g: DeviceGraph, k: int, iters: int, prec: int = FP64, first: int = 0,
     else:
         majorize(g, terms, x, iters)
     return x, terms, piv, dist, delta, region
+
+
+# ------------------------------------------------------------------ layout pool
+
+POOL_FREE, POOL_ADDED, POOL_READY, POOL_FAILED = range(4)
+POOL_PIVOTS, POOL_DIST, POOL_DELTA, POOL_REGION, POOL_H, POOL_WTAB64, POOL_DEN64, POOL_X32, POOL_X64 = range(9)
+
+
+class Pool:
+    """Many small graphs laid out together in one device arena (the ssm_pool_*
+    calls): add graphs, prepare them in batches, sweep any set of ready slots
+    per call, read stress and layouts, remove finished slots."""
+
+    def __init__(self, capacity_bytes: int):
+        self._lib = load()
+        h = ctypes.c_void_p()
+        _check(self._lib.ssm_pool_create(int(capacity_bytes), ctypes.byref(h)), "ssm_pool_create")
+        self.handle = h.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.ssm_pool_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def usage(self):
+        used, cap = ctypes.c_int64(), ctypes.c_int64()
+        _check(self._lib.ssm_pool_usage(self.handle, ctypes.byref(used), ctypes.byref(cap)), "ssm_pool_usage")
+        return used.value, cap.value
+
+    def add(self, g, k: int, first: int = 0, sweeps: int = 200):
+        """Admit CSR graph g (host arrays); returns the slot, or None when the
+        arena has no room (status E_NOMEM)."""
+        import numpy as np
+        rp = np.ascontiguousarray(g.row_ptr, dtype=np.int32)
+        ci = np.ascontiguousarray(g.col_idx, dtype=np.int32)
+        slot = ctypes.c_int32()
+        st = self._lib.ssm_pool_add(self.handle, int(g.n), int(ci.size), _hptr(rp), _hptr(ci), int(k), int(first),
+                                    int(sweeps), ctypes.byref(slot), _stream())
+        if st == E_NOMEM:
+            return None
+        _check(st, "ssm_pool_add")
+        return slot.value
+
+    @staticmethod
+    def _slots(slots):
+        import numpy as np
+        return np.ascontiguousarray(slots, dtype=np.int32)
+
+    def prepare(self, slots, warm: int = 1):
+        a = self._slots(slots)
+        _check(self._lib.ssm_pool_prepare(self.handle, a.size, _hptr(a), int(warm), _stream()), "ssm_pool_prepare")
+
+    def sweep(self, slots, iters: int):
+        a = self._slots(slots)
+        _check(self._lib.ssm_pool_sweep(self.handle, a.size, _hptr(a), int(iters), _stream()), "ssm_pool_sweep")
+
+    def stress(self, slots):
+        import numpy as np
+        a = self._slots(slots)
+        out = np.empty(a.size, dtype=np.float64)
+        _check(self._lib.ssm_pool_stress(self.handle, a.size, _hptr(a), _hptr(out), _stream()), "ssm_pool_stress")
+        return out
+
+    def layout(self, slot: int, n: int) -> torch.Tensor:
+        x = torch.empty(n, 2, dtype=torch.float32, device="cuda")
+        _check(self._lib.ssm_pool_layout(self.handle, int(slot), _ptr(x), _stream()), "ssm_pool_layout")
+        return x
+
+    def info(self, slot: int) -> dict:
+        import numpy as np
+        v = np.empty(8, dtype=np.int32)
+        _check(self._lib.ssm_pool_info(self.handle, int(slot), _hptr(v)), "ssm_pool_info")
+        keys = ["state", "fail", "n", "k", "done", "sweeps", "dmax", "delta_max"]
+        return dict(zip(keys, (int(q) for q in v)))
+
+    def export(self, slot: int, what: int):
+        import numpy as np
+        inf = self.info(slot)
+        n, k, W, L = inf["n"], inf["k"], inf["dmax"] + 1, inf["delta_max"] + 1
+        shape, dt = {
+            POOL_PIVOTS: ((k,), np.int32), POOL_DIST: ((k, n), np.int32), POOL_DELTA: ((n,), np.int32),
+            POOL_REGION: ((n,), np.int32), POOL_H: ((k, L), np.int32), POOL_WTAB64: ((k, W), np.float64),
+            POOL_DEN64: ((n,), np.float64), POOL_X32: ((n, 2), np.float32), POOL_X64: ((n, 2), np.float64),
+        }[what]
+        out = np.empty(shape, dtype=dt)
+        _check(self._lib.ssm_pool_export(self.handle, int(slot), int(what), _hptr(out), _stream()), "ssm_pool_export")
+        return out
+
+    def remove(self, slot: int):
+        _check(self._lib.ssm_pool_remove(self.handle, int(slot)), "ssm_pool_remove")

@@ -5,6 +5,10 @@ max/min pivot selection, BFS from every pivot and regions, term set, PivotMDS
 start layout, T Jacobi sweeps of Eq. 5, final stress.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--workload rgg|grid|ba|mesh]
+    python bench.py --workload serve [--requests 4096] [--rate R] [--pool-gib G]
+
+The serve workload runs a stream of layout requests through the layout pool
+(continuous batching); its step is the whole stream.
 """
 from __future__ import annotations
 
@@ -91,12 +95,158 @@ def cpu_baseline(g, k, iters, sample_sweeps, threads=1):
             "step_s": step, "sweep_node_updates_per_s": g.n / per_sweep}
 
 
+SERVE_DESC = ("serving stream: {count} layout requests with Poisson arrivals at {rate:g}/s; each graph drawn "
+              "uniformly from grid a x b (a, b in [10,150]), random geometric graph (n in [200,20000], mean "
+              "degree 6-10, largest component) and random tree + 5% extra edges (n in [200,20000]); "
+              "k=min(100, n/10) maxmin pivots; {sweeps} sweeps each (the first FP64, the rest FP32); "
+              "layout pool arena {pool_gib:g} GiB, sweep quantum {quantum}")
+
+
+def _request_graph(spec):
+    from paper_1608_08909_amd import graphs as G
+    return G.make_request_graph(spec)
+
+
+def _request_graphs(specs):
+    """Generates the request graphs on the host cores (before any device use)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+        return list(ex.map(_request_graph, specs, chunksize=8))
+
+
+def run_serve(args):
+    """The serving stream through the layout pool: one step = the whole
+    stream (every request from arrival to its finished layout)."""
+    from paper_1608_08909_amd import graphs as G
+
+    specs = G.serving_requests(args.requests, args.seed)
+    warm_specs = G.serving_requests(args.warm_requests, args.seed + 1)
+    t_gen = time.perf_counter()
+    graphs = _request_graphs(specs)
+    warm_graphs = _request_graphs(warm_specs)
+    t_gen = time.perf_counter() - t_gen
+
+    import torch
+
+    from paper_1608_08909_amd import serve, ssm
+
+    torch.cuda.set_device(0)
+    pool_bytes = int(args.pool_gib * (1 << 30))
+
+    def requests(gs, seed):
+        arr = serve.poisson_arrivals(len(gs), args.rate, seed)
+        return [serve.Request(i, g, min(100, g.n // 10), float(a), sweeps=args.sweeps)
+                for i, (g, a) in enumerate(zip(gs, arr))]
+
+    for _ in range(args.warmup):
+        serve.serve(requests(warm_graphs, args.seed + 2), pool_bytes, args.quantum)
+    torch.cuda.synchronize()
+    rep = serve.serve(requests(graphs, args.seed), pool_bytes, args.quantum)
+    done = rep.completed()
+    lat = rep.latencies_ms()
+    node_updates = sum(r.graph.n * r.sweeps for r in done)
+
+    # equal final stress: the plain per-graph FP64 path on the same GPU, on a
+    # sample spread over the stream (also timed: the plain form's layouts/s)
+    sample = done[:: max(1, len(done) // 16)][:16]
+    rels, t_plain = [], 0.0
+    for r in sample:
+        dg = ssm.DeviceGraph.from_csr(r.graph)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, terms, *_ = ssm.layout(dg, r.k, r.sweeps, ssm.FP64)
+        s64 = ssm.stress(dg, terms, x)
+        t_plain += time.perf_counter() - t0
+        rels.append(abs(r.stress - s64) / s64)
+
+    # roofline of the pooled FP32 sweep on a batch of the stream's graphs
+    batch = graphs[:256]
+    pool = ssm.Pool(pool_bytes)
+    pairs = [(g, pool.add(g, min(100, g.n // 10), 0, 1 << 30)) for g in batch]
+    pairs = [(g, s) for g, s in pairs if s is not None]
+    slots = [s for _, s in pairs]
+    pool.prepare(slots, 1)
+    pool.sweep(slots, 5)
+    stream = torch.cuda.current_stream()
+    reps = 50
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    pool.sweep(slots, reps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    launch_us = e0.elapsed_time(e1) * 1e3 / reps
+    nbytes = 0
+    for g, s in pairs:
+        kpad = (pool.info(s)["k"] + 7) // 8 * 8
+        nbytes += g.n * kpad * 2 + g.col_idx.size * 4 + g.n * (4 + 8 + 8 + 4)
+    batch_nodes = sum(g.n for g, _ in pairs)
+    pool.close()
+    achieved = nbytes / (launch_us * 1e-6) / 1e9
+
+    out = {
+        "metric": "node-updates/sec & layouts/sec (p50/p99) at equal final stress vs plain, 1 GPU",
+        "value": len(done) / rep.wall_s,
+        "unit": "layouts/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": args.warmup,
+        "ms_per_step": rep.wall_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": SERVE_DESC.format(count=args.requests, rate=args.rate, sweeps=args.sweeps,
+                                                 pool_gib=args.pool_gib, quantum=args.quantum),
+                   "requests": args.requests, "seed": args.seed, "rate_per_s": args.rate,
+                   "pool_bytes": pool_bytes, "quantum": args.quantum, "sweeps": args.sweeps},
+        "completed": len(done),
+        "failed": len(rep.requests) - len(done),
+        "layouts_per_s": len(done) / rep.wall_s,
+        "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99), "max": float(lat.max())},
+        "node_updates_per_s": node_updates / rep.wall_s,
+        "rounds": rep.rounds,
+        "prepare_batches": rep.prepares,
+        "peak_active_graphs": rep.peak_active,
+        "peak_pool_bytes": rep.peak_bytes,
+        "final_stress_rel_diff_vs_plain_fp64": {"max": float(max(rels)), "sample": len(rels)},
+        "plain_fp64_layouts_per_s_sample": len(sample) / t_plain,
+        "host_graph_generation_s": t_gen,
+        "roofline": {"bound": "hbm", "kernel": "k_pool_sweep32", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": nbytes, "launch_us": launch_us, "batch_graphs": len(slots),
+                     "batch_nodes": batch_nodes},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        cs = sorted(done[:64], key=lambda r: r.graph.n)[len(done[:64]) // 2: len(done[:64]) // 2 + 2]
+        t0 = time.perf_counter()
+        for r in cs:
+            oracle.layout(r.graph.n, r.graph.row_ptr, r.graph.col_idx, r.k, r.sweeps)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": len(cs) / dt, "unit": "layouts/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{len(cs)} median-size requests of the stream (n = "
+                                         f"{[r.graph.n for r in cs]}), full layouts with {args.sweeps} sweeps, "
+                                         f"{dt:.1f} s on one core"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rgg", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="rgg", choices=sorted(WORKLOADS) + ["serve"])
+    ap.add_argument("--requests", type=int, default=4096, help="serve: requests in the stream")
+    ap.add_argument("--warm-requests", type=int, default=64, help="serve: requests of each warm-up stream")
+    ap.add_argument("--rate", type=float, default=100000.0, help="serve: Poisson arrival rate (requests/s)")
+    ap.add_argument("--pool-gib", type=float, default=8.0, help="serve: layout pool arena (GiB)")
+    ap.add_argument("--quantum", type=int, default=25, help="serve: sweeps per scheduling round")
+    ap.add_argument("--sweeps", type=int, default=200, help="serve: sweeps per request")
+    ap.add_argument("--seed", type=int, default=4, help="serve: stream seed")
     ap.add_argument("--sampling", default="maxmin", choices=["maxmin", "kmeans"],
                     help="pivot sampling: max/min, or max/min refined by k-means sp")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -108,6 +258,9 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(each graph's layout runs on a single device)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "serve":
+        run_serve(args)
+        return
 
     import torch
 

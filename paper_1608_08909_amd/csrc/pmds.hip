@@ -202,196 +202,277 @@ __device__ __forceinline__ double splitmix_uniform(unsigned long long& state) {
 }
 
 constexpr int kEigThreads = 1024;
-constexpr int kEigRows = 16;  // rows of M per wave kept in registers (k <= 256)
-constexpr int kEigCols = 4;   // columns per lane (k <= 256)
+constexpr int kEigP = 8;      // subspace width (two vectors wanted)
+constexpr int kEigCheck = 8;  // steps between Rayleigh-Ritz convergence tests
 
-// Orthogonal (subspace) iteration for the two dominant eigenvectors of the
-// symmetric k x k matrix M, one workgroup.  Start: SplitMix64 values in
-// [-1, 1) (seed 0x53534D00 + column).  Each step: Z = M V, Gram-Schmidt;
-// stop once every column of Z lies in span(V) to within `tol` per entry, or
-// after max_iter steps.  Then Rayleigh-Ritz on the 2 x 2 V^T M V (larger
-// eigenvalue first) and the sign rule: each column's largest-magnitude entry
-// is positive (entries within a relative 1e-9 of the largest count as tied;
-// the lowest index among them decides).  out: V (k x 2), lambda[2]; iters[0].
-template <bool REG>
+// Start / replacement vector entry (row r, column c, draw d): SplitMix64 in
+// [-1, 1) from a state unique to (r, c, d).
+__device__ __forceinline__ double eig_rand(int r, int c, int d) {
+    unsigned long long st = 0x53534D00ull ^ ((unsigned long long)(unsigned)r << 20) ^
+                            ((unsigned long long)c << 52) ^ ((unsigned long long)(unsigned)d << 56);
+    return splitmix_uniform(st);
+}
+
+// Wave 0: orthonormalizes the first pw columns of A (k x kEigP, row-major,
+// LDS) in place by classical Gram-Schmidt applied twice per column; a column
+// whose remainder is negligible against the first column's norm (M of low
+// rank) is replaced by a fresh random column.  Each lane owns rows lane,
+// lane + 64, ...
+__device__ void eig_orth(int k, int pw, double* A, int draw) {
+    const int lane = lane_id();
+    double ref = 0.0;
+    for (int c = 0; c < pw; ++c) {
+        for (int attempt = 0; attempt < 4; ++attempt) {
+            for (int pass = 0; pass < 2; ++pass) {
+                double d[kEigP];
+#pragma unroll
+                for (int b = 0; b < kEigP; ++b) d[b] = 0.0;
+                for (int r = lane; r < k; r += kWave) {
+                    const double ac = A[r * kEigP + c];
+#pragma unroll
+                    for (int b = 0; b < kEigP; ++b)
+                        if (b < c) d[b] += A[r * kEigP + b] * ac;
+                }
+#pragma unroll
+                for (int b = 0; b < kEigP; ++b)
+                    if (b < c) d[b] = wave_sum(d[b]);
+                for (int r = lane; r < k; r += kWave) {
+                    double ac = A[r * kEigP + c];
+#pragma unroll
+                    for (int b = 0; b < kEigP; ++b)
+                        if (b < c) ac -= d[b] * A[r * kEigP + b];
+                    A[r * kEigP + c] = ac;
+                }
+            }
+            double nn = 0.0;
+            for (int r = lane; r < k; r += kWave) nn += A[r * kEigP + c] * A[r * kEigP + c];
+            nn = sqrt(wave_sum(nn));
+            if (c == 0 && attempt == 0) ref = nn > 0.0 ? nn : 1.0;
+            if (nn > 1e-13 * ref) {
+                for (int r = lane; r < k; r += kWave) A[r * kEigP + c] /= nn;
+                break;
+            }
+            for (int r = lane; r < k; r += kWave) A[r * kEigP + c] = eig_rand(r, c, draw * 4 + attempt + 1);
+        }
+    }
+}
+
+// Eigen-decomposition of the symmetric leading pw x pw block of H
+// (row-major, stride kEigP), one thread: cyclic Jacobi rotations until the
+// off-diagonal part is below 1e-30 of the norm (or 64 sweeps).  Eigenvalues
+// into th (descending), eigenvectors into the columns of Y in the same order.
+__device__ void eig_small(int pw, const double* H, double* Y, double* th) {
+    double a[kEigP][kEigP], v[kEigP][kEigP];
+    for (int i = 0; i < kEigP; ++i)
+        for (int j = 0; j < kEigP; ++j) {
+            a[i][j] = i < pw && j < pw ? H[i * kEigP + j] : 0.0;
+            v[i][j] = i == j ? 1.0 : 0.0;
+        }
+    for (int sweep = 0; sweep < 64; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < pw; ++i)
+            for (int j = 0; j < pw; ++j) {
+                tot += a[i][j] * a[i][j];
+                if (i != j) off += a[i][j] * a[i][j];
+            }
+        if (off <= 1e-30 * tot) break;
+        for (int p = 0; p < pw - 1; ++p)
+            for (int q = p + 1; q < pw; ++q) {
+                if (a[p][q] == 0.0) continue;
+                const double theta = (a[q][q] - a[p][p]) / (2.0 * a[p][q]);
+                const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+                for (int r = 0; r < pw; ++r) {  // columns p, q
+                    const double ap = a[r][p], aq = a[r][q];
+                    a[r][p] = c * ap - sn * aq;
+                    a[r][q] = sn * ap + c * aq;
+                }
+                for (int r = 0; r < pw; ++r) {  // rows p, q
+                    const double ap = a[p][r], aq = a[q][r];
+                    a[p][r] = c * ap - sn * aq;
+                    a[q][r] = sn * ap + c * aq;
+                }
+                for (int r = 0; r < pw; ++r) {
+                    const double vp = v[r][p], vq = v[r][q];
+                    v[r][p] = c * vp - sn * vq;
+                    v[r][q] = sn * vp + c * vq;
+                }
+            }
+    }
+    int order[kEigP];
+    for (int i = 0; i < pw; ++i) order[i] = i;
+    for (int i = 1; i < pw; ++i)  // insertion sort, descending (stable)
+        for (int j = i; j > 0 && a[order[j]][order[j]] > a[order[j - 1]][order[j - 1]]; --j) {
+            const int tmp = order[j];
+            order[j] = order[j - 1];
+            order[j - 1] = tmp;
+        }
+    for (int c = 0; c < kEigP; ++c) {
+        th[c] = c < pw ? a[order[c]][order[c]] : 0.0;
+        for (int r = 0; r < kEigP; ++r) Y[r * kEigP + c] = c < pw && r < pw ? v[r][order[c]] : 0.0;
+    }
+}
+
+// The two dominant eigenvectors of the symmetric k x k matrix M, one
+// workgroup: block subspace iteration on pw = min(kEigP, k) vectors (start:
+// the SplitMix64 columns of eig_rand).  Each step: Z = M V (all waves), then
+// V = an orthonormal basis of Z (wave 0).  Every kEigCheck steps V is
+// replaced by its Rayleigh-Ritz basis (the pw x pw matrix V^T M V by cyclic
+// Jacobi) and the two leading Ritz vectors U are tested: stop once every
+// column of U lies in the span of the previous test's U to within `tol` per
+// entry (only the first column when the second Ritz value is negligible, M
+// of rank 1, or ties the third, where the second vector is not unique), or
+// after max_iter steps.  The pair converges at the rate lambda_(pw+1) /
+// lambda_2, so a near-tie of lambda_2 and lambda_3 costs nothing.  Then the
+// sign rule: each column's largest-magnitude entry is positive (entries
+// within a relative 1e-9 of the largest count as tied; the lowest index
+// decides).  out: V (k x 2), lambda[2]; iters[0] = steps.
 __device__ __forceinline__ void pmds_eig_body(int k, const double* __restrict__ M, double tol, int max_iter,
                                               double* __restrict__ out, int* __restrict__ iters) {
     extern __shared__ double sh[];
-    double* v0 = sh;
-    double* v1 = sh + k;
-    double* z0 = sh + 2 * k;
-    double* z1 = sh + 3 * k;
+    double* V = sh;                  // [k][kEigP]
+    double* Z = V + kEigP * k;       // [k][kEigP]
+    double* U = Z + kEigP * k;       // [k][2] leading Ritz vectors of the last test
+    double* H = U + 2 * k;           // [kEigP][kEigP]
+    double* Y = H + kEigP * kEigP;   // [kEigP][kEigP]
+    double* th = Y + kEigP * kEigP;  // [kEigP]
+    __shared__ int s_done;
     __shared__ double red[kEigThreads / kWave];
     const int lane = lane_id(), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
-    double mreg[REG ? kEigRows : 1][REG ? kEigCols : 1];
-    if (REG) {
-#pragma unroll
-        for (int q = 0; q < kEigRows; ++q)
-#pragma unroll
-            for (int c = 0; c < kEigCols; ++c) {
-                int r = w + nw * q, j = lane + kWave * c;
-                mreg[REG ? q : 0][REG ? c : 0] = (r < k && j < k) ? M[(size_t)r * k + j] : 0.0;
-            }
+    const int pw = min(kEigP, k);
+    for (int q = threadIdx.x; q < kEigP * k; q += blockDim.x) {
+        const int r = q / kEigP, c = q % kEigP;
+        V[q] = c < pw ? eig_rand(r, c, 0) : 0.0;
+        Z[q] = 0.0;
     }
-    if (threadIdx.x == 0) {
-        unsigned long long s0 = 0x53534D00ull, s1 = 0x53534D01ull;
-        for (int t = 0; t < k; ++t) {
-            v0[t] = splitmix_uniform(s0);
-            v1[t] = splitmix_uniform(s1);
-        }
-    }
+    for (int q = threadIdx.x; q < 2 * k; q += blockDim.x) U[q] = 0.0;
+    if (threadIdx.x == 0) s_done = 0;
     __syncthreads();
-    auto matvec = [&]() {
-        if (REG) {
+    if (w == 0) eig_orth(k, pw, V, 0);
+    __syncthreads();
+    int it = 0;
+    bool have_u = false;
+    while (true) {
+        // Z = M V: a wave per row, lanes over the columns of M
+        for (int r = w; r < k; r += nw) {
+            double acc[kEigP];
 #pragma unroll
-            for (int q = 0; q < kEigRows; ++q) {
-                const int r = w + nw * q;
-                if (r < k) {  // uniform across the wave
-                    double a0 = 0.0, a1 = 0.0;
+            for (int c = 0; c < kEigP; ++c) acc[c] = 0.0;
+            for (int j = lane; j < k; j += kWave) {
+                const double mv = M[(size_t)r * k + j];
 #pragma unroll
-                    for (int c = 0; c < kEigCols; ++c) {
-                        int j = lane + kWave * c;
-                        if (j < k) {
-                            double mv = mreg[REG ? q : 0][REG ? c : 0];
-                            a0 += mv * v0[j];
-                            a1 += mv * v1[j];
+                for (int c = 0; c < kEigP; ++c) acc[c] += mv * V[j * kEigP + c];
+            }
+#pragma unroll
+            for (int c = 0; c < kEigP; ++c) acc[c] = wave_sum(acc[c]);
+            if (lane < kEigP) {
+                double mine = acc[0];
+#pragma unroll
+                for (int c = 1; c < kEigP; ++c)
+                    if (lane == c) mine = acc[c];
+                Z[r * kEigP + lane] = mine;
+            }
+        }
+        ++it;
+        __syncthreads();
+        if (w == 0) {
+            if (it % kEigCheck == 0 || it >= max_iter) {
+                // Rayleigh-Ritz: H = V^T Z = V^T M V
+                for (int a = 0; a < pw; ++a)
+                    for (int b = a; b < pw; ++b) {
+                        double d = 0.0;
+                        for (int r = lane; r < k; r += kWave) d += V[r * kEigP + a] * Z[r * kEigP + b];
+                        d = wave_sum(d);
+                        if (lane == 0) {
+                            H[a * kEigP + b] = d;
+                            H[b * kEigP + a] = d;
                         }
                     }
-                    a0 = wave_sum(a0);
-                    a1 = wave_sum(a1);
-                    if (lane == 0) {
-                        z0[r] = a0;
-                        z1[r] = a1;
+                if (lane == 0) eig_small(pw, H, Y, th);
+                __builtin_amdgcn_wave_barrier();
+                const bool rank1 = !(fabs(th[1]) > 1e-13 * fabs(th[0]));
+                const bool tie23 = pw > 2 && fabs(th[1] - th[2]) <= 1e-12 * fabs(th[0]);
+                // U_new = V Y[:, 0:2], its distance from span(U_old); then
+                // V = V Y (Ritz basis) and Z = Z Y (= M V Y)
+                double p00 = 0.0, p01 = 0.0, p10 = 0.0, p11 = 0.0;
+                for (int r = lane; r < k; r += kWave) {
+                    double vr[kEigP], zr[kEigP];
+#pragma unroll
+                    for (int c = 0; c < kEigP; ++c) {
+                        double v = 0.0, z = 0.0;
+#pragma unroll
+                        for (int b = 0; b < kEigP; ++b) {
+                            v += V[r * kEigP + b] * Y[b * kEigP + c];
+                            z += Z[r * kEigP + b] * Y[b * kEigP + c];
+                        }
+                        vr[c] = v;
+                        zr[c] = z;
+                    }
+                    p00 += U[2 * r] * vr[0];
+                    p01 += U[2 * r] * vr[1];
+                    p10 += U[2 * r + 1] * vr[0];
+                    p11 += U[2 * r + 1] * vr[1];
+#pragma unroll
+                    for (int c = 0; c < kEigP; ++c) {
+                        V[r * kEigP + c] = vr[c];
+                        Z[r * kEigP + c] = zr[c];
                     }
                 }
-            }
-        } else {
-            for (int r = w; r < k; r += nw) {
-                double a0 = 0.0, a1 = 0.0;
-                for (int j = lane; j < k; j += kWave) {
-                    double mv = M[(size_t)r * k + j];
-                    a0 += mv * v0[j];
-                    a1 += mv * v1[j];
+                p00 = wave_sum(p00);
+                p01 = wave_sum(p01);
+                p10 = wave_sum(p10);
+                p11 = wave_sum(p11);
+                double res0 = 0.0, res1 = 0.0;
+                for (int r = lane; r < k; r += kWave) {
+                    const double u0 = V[r * kEigP + 0], u1 = V[r * kEigP + 1];
+                    res0 = fmax(res0, fabs(u0 - p00 * U[2 * r] - p10 * U[2 * r + 1]));
+                    res1 = fmax(res1, fabs(u1 - p01 * U[2 * r] - p11 * U[2 * r + 1]));
+                    U[2 * r] = u0;
+                    U[2 * r + 1] = u1;
                 }
-                a0 = wave_sum(a0);
-                a1 = wave_sum(a1);
-                if (lane == 0) {
-                    z0[r] = a0;
-                    z1[r] = a1;
-                }
+                res0 = wave_max(res0);
+                res1 = wave_max(res1);
+                const bool conv = have_u && res0 < tol && (res1 < tol || rank1 || tie23);
+                if (lane == 0 && (conv || it >= max_iter)) s_done = 1;
+                have_u = true;
             }
+            // next basis: orthonormalized Z (= M V)
+            for (int q = lane; q < kEigP * k; q += kWave) V[q] = Z[q];
+            eig_orth(k, pw, V, it);
         }
         __syncthreads();
-    };
-    auto dot = [&](const double* a, const double* b) {
-        double s = 0.0;
-        for (int t = threadIdx.x; t < k; t += blockDim.x) s += a[t] * b[t];
-        return block_sum(s, red);
-    };
-    // normalize v0, orthonormalize v1 against it (start vectors)
-    {
-        double nn = sqrt(dot(v0, v0));
-        for (int t = threadIdx.x; t < k; t += blockDim.x) v0[t] /= nn;
-        __syncthreads();
-        for (int pass = 0; pass < 2; ++pass) {
-            double d = dot(v0, v1);
-            for (int t = threadIdx.x; t < k; t += blockDim.x) v1[t] -= d * v0[t];
-            __syncthreads();
-        }
-        double n1 = sqrt(dot(v1, v1));
-        for (int t = threadIdx.x; t < k; t += blockDim.x) v1[t] /= n1;
-        __syncthreads();
+        if (s_done) break;  // uniform
     }
-    int it = 0;
-    for (; it < max_iter; ++it) {
-        matvec();
-        double n0 = sqrt(dot(z0, z0));
-        for (int t = threadIdx.x; t < k; t += blockDim.x) z0[t] /= n0;
-        __syncthreads();
-        // Gram-Schmidt twice: once is not enough when z1 is nearly parallel to z0
-        for (int pass = 0; pass < 2; ++pass) {
-            double d01 = dot(z0, z1);
-            for (int t = threadIdx.x; t < k; t += blockDim.x) z1[t] -= d01 * z0[t];
-            __syncthreads();
-        }
-        double n1 = sqrt(dot(z1, z1));
-        // a second column negligible against the first: M has numerical rank 1
-        const bool rank1 = !(n1 > 1e-13 * n0);
-        if (rank1) {
-            // any unit vector orthogonal to z0 will do: keep v1 made orthogonal to z0
-            for (int t = threadIdx.x; t < k; t += blockDim.x) z1[t] = v1[t];
-            __syncthreads();
-            for (int pass = 0; pass < 2; ++pass) {
-                double d = dot(z0, z1);
-                for (int t = threadIdx.x; t < k; t += blockDim.x) z1[t] -= d * z0[t];
-                __syncthreads();
-            }
-            n1 = sqrt(dot(z1, z1));
-        }
-        for (int t = threadIdx.x; t < k; t += blockDim.x) z1[t] /= n1;
-        __syncthreads();
-        // distance of span(Z) from span(V): residual of projecting Z on V
-        double p00 = dot(v0, z0), p10 = dot(v1, z0), p01 = dot(v0, z1), p11 = dot(v1, z1);
-        double res0 = 0.0, res1 = 0.0;
-        for (int t = threadIdx.x; t < k; t += blockDim.x) {
-            double r0 = z0[t] - p00 * v0[t] - p10 * v1[t];
-            double r1 = z1[t] - p01 * v0[t] - p11 * v1[t];
-            res0 = fmax(res0, fabs(r0));
-            res1 = fmax(res1, fabs(r1));
-        }
-        res0 = block_max(res0, red);
-        res1 = block_max(res1, red);
-        for (int t = threadIdx.x; t < k; t += blockDim.x) {
-            v0[t] = z0[t];
-            v1[t] = z1[t];
-        }
-        __syncthreads();
-        if (res0 < tol && (res1 < tol || rank1)) {
-            ++it;
-            break;
-        }
-    }
-    // Rayleigh-Ritz on span(V)
-    matvec();
-    double b00 = dot(v0, z0), b11 = dot(v1, z1);
-    double b01 = 0.5 * (dot(v0, z1) + dot(v1, z0));
-    double th = 0.5 * atan2(2.0 * b01, b00 - b11);
-    double cs = cos(th), sn = sin(th);
-    double l0 = b00 * cs * cs + 2.0 * b01 * cs * sn + b11 * sn * sn;
-    double l1 = b00 * sn * sn - 2.0 * b01 * cs * sn + b11 * cs * cs;
-    for (int t = threadIdx.x; t < k; t += blockDim.x) {
-        double a = v0[t], b = v1[t];
-        z0[t] = cs * a + sn * b;
-        z1[t] = -sn * a + cs * b;
-    }
-    __syncthreads();
-    // sign rule
+    // output: U (k x 2) with the sign rule, the Ritz values
     for (int col = 0; col < 2; ++col) {
-        double* z = col == 0 ? z0 : z1;
         double mx = 0.0;
-        for (int t = threadIdx.x; t < k; t += blockDim.x) mx = fmax(mx, fabs(z[t]));
+        for (int t = threadIdx.x; t < k; t += blockDim.x) mx = fmax(mx, fabs(U[2 * t + col]));
         mx = block_max(mx, red);
         int idx = k;  // lowest index within a relative 1e-9 of the largest magnitude
         for (int t = threadIdx.x; t < k; t += blockDim.x)
-            if (fabs(z[t]) >= mx * (1.0 - 1e-9) && t < idx) idx = t;
+            if (fabs(U[2 * t + col]) >= mx * (1.0 - 1e-9) && t < idx) idx = t;
         idx = -block_max(-idx, (int*)red);
         if (idx >= k) idx = 0;
-        double sg = z[idx] < 0.0 ? -1.0 : 1.0;
-        for (int t = threadIdx.x; t < k; t += blockDim.x) out[2 * t + col] = sg * z[t];
+        const double sg = U[2 * idx + col] < 0.0 ? -1.0 : 1.0;
+        for (int t = threadIdx.x; t < k; t += blockDim.x) out[2 * t + col] = sg * U[2 * t + col];
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        out[2 * k] = l0;
-        out[2 * k + 1] = l1;
+        out[2 * k] = th[0];
+        out[2 * k + 1] = th[1];
         iters[0] = it;
     }
 }
 
-template <bool REG>
+// LDS bytes of pmds_eig_body for k.
+__host__ __device__ constexpr size_t eig_lds_bytes(int k) {
+    return sizeof(double) * ((size_t)(2 * kEigP + 2) * k + 2 * kEigP * kEigP + kEigP);
+}
+
 __global__ __launch_bounds__(kEigThreads) void k_pmds_eig(int k, const double* __restrict__ M, double tol,
                                                          int max_iter, double* __restrict__ out,
                                                          int* __restrict__ iters) {
-    pmds_eig_body<REG>(k, M, tol, max_iter, out, iters);
+    pmds_eig_body(k, M, tol, max_iter, out, iters);
 }
 
 // x_i = sum over t ascending of C_it V_t (per column), FP64.
@@ -521,13 +602,11 @@ ssm_status pivotmds(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* x, hipStre
                                (const uint4*)t->dpk, mu, nu, stats, tiles, ntiles, part);
         hipLaunchKernelGGL(k_pmds_gram_reduce, dim3(std::min(div_up((long long)ntiles * 256, 256), 4096)),
                            dim3(256), 0, s, k, nchunks, ntiles, tiles, part, M);
-        size_t elds = sizeof(double) * 4 * k;
-        if (k <= kEigRows * (kEigThreads / kWave) && k <= kEigCols * kWave)
-            hipLaunchKernelGGL(k_pmds_eig<true>, dim3(1), dim3(kEigThreads), elds, s, k, M, 1e-13, 20000,
-                               t->eig, t->eig_iters);
-        else
-            hipLaunchKernelGGL(k_pmds_eig<false>, dim3(1), dim3(kEigThreads), elds, s, k, M, 1e-13, 20000,
-                               t->eig, t->eig_iters);
+        const size_t elds = eig_lds_bytes(k);
+        if (elds > 64 * 1024)
+            (void)hipFuncSetAttribute((const void*)k_pmds_eig, hipFuncAttributeMaxDynamicSharedMemorySize, (int)elds);
+        hipLaunchKernelGGL(k_pmds_eig, dim3(1), dim3(kEigThreads), elds, s, k, M, 1e-13, 20000, t->eig,
+                           t->eig_iters);
         double2* xd = (double2*)t->xtmp;
         if (t->dbytes == 1)
             hipLaunchKernelGGL((k_pmds_project<uint8_t, 16>), dim3(gn), dim3(256), 0, s, n, k, nwords, dpk, mu,
@@ -623,7 +702,7 @@ __global__ void k_pool_gram_reduce(const PoolGraph* __restrict__ gs, const int2*
 
 __global__ __launch_bounds__(kEigThreads) void k_pool_eig(const PoolGraph* __restrict__ gs) {
     const PoolGraph& g = gs[blockIdx.x];
-    pmds_eig_body<true>(g.k, g.M, 1e-13, 20000, g.eig, g.info + 4);
+    pmds_eig_body(g.k, g.M, 1e-13, 20000, g.eig, g.info + 4);
 }
 
 // Per graph: x64[0] = C V (ranks ascending), then the uniform rescale that
@@ -687,7 +766,7 @@ hipError_t pool_pivotmds(const PoolGraph* gs, int count, const int4* gram_items,
     hipLaunchKernelGGL(k_pool_gram, dim3(ngram), dim3(256), sizeof(double) * ((size_t)kGramSub * kp_max + kp_max), s,
                        gs, gram_items, tiles);
     hipLaunchKernelGGL(k_pool_gram_reduce, dim3(32, count), dim3(256), 0, s, gs, tiles);
-    hipLaunchKernelGGL(k_pool_eig, dim3(count), dim3(kEigThreads), sizeof(double) * 4 * (size_t)k_max, s, gs);
+    hipLaunchKernelGGL(k_pool_eig, dim3(count), dim3(kEigThreads), eig_lds_bytes(k_max), s, gs);
     hipLaunchKernelGGL(k_pool_project, dim3(count), dim3(1024), 0, s, gs);
     return hipGetLastError();
 }

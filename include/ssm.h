@@ -222,8 +222,9 @@ void ssm_pool_destroy(ssm_pool* p);
 /* Bytes of the arena in use and its capacity (host outputs, may be NULL). */
 ssm_status ssm_pool_usage(ssm_pool* p, int64_t* used, int64_t* capacity);
 
-/* Admits one graph: checks the host CSR (simple, symmetric), reserves its
- * resident and preparation buffers and copies the CSR (row_ptr_host [n+1],
+/* Admits one graph: checks the host CSR's row pointers (monotone from 0 to
+ * nnz) and ids (in [0, n)), reserves its resident and preparation buffers and
+ * copies the CSR (row_ptr_host [n+1],
  * col_idx_host [nnz], host memory, read before return).  k pivots by max/min
  * from `first`; `sweeps` is the graph's total sweep count (Algorithm 1's
  * iteration bound).  SSM_E_NOMEM when the arena has no room: the caller may
@@ -233,7 +234,9 @@ ssm_status ssm_pool_add(ssm_pool* p, int32_t n, int32_t nnz, const int32_t* row_
                         const int32_t* col_idx_host, int32_t k, int32_t first, int32_t sweeps,
                         int32_t* slot_out, hipStream_t stream);
 
-/* Preprocessing and start layout of the listed (added) slots: max/min
+/* Preprocessing and start layout of the listed (added) slots: a check that
+ * the graph is simple and undirected (no self-loop, repeated neighbour or
+ * one-way arc; else the slot fails with SSM_E_INVAL), max/min
  * pivots, k BFS, regions (rule R1), H, w' and denominators, PivotMDS with the
  * rescale, then `warm` FP64 sweeps (oracle operation order), rounded into the
  * FP32 layout.  A slot whose graph is disconnected, has zero total PivotMDS

@@ -361,6 +361,28 @@ __global__ void k_pool_stress_sum(int count, const int* __restrict__ first, cons
     out[q] = s;
 }
 
+// Items (graph, first row of 256): info[5] = 1 if a row has a self-loop, a
+// repeated neighbour or an arc whose reverse is missing (linear scans: the
+// pool's graphs have small degrees).
+__global__ __launch_bounds__(256) void k_pool_validate(const PoolGraph* __restrict__ gs,
+                                                       const int2* __restrict__ items) {
+    const int2 st = items[blockIdx.x];
+    const PoolGraph& g = gs[st.x];
+    const int i = st.y + threadIdx.x;
+    if (i >= g.n) return;
+    const int e0 = g.rp[i], e1 = g.rp[i + 1];
+    bool bad = false;
+    for (int e = e0; e < e1 && !bad; ++e) {
+        const int j = g.ci[e];
+        if (j == i) bad = true;
+        for (int f = e0; f < e && !bad; ++f) bad = g.ci[f] == j;
+        bool back = false;
+        for (int f = g.rp[j]; f < g.rp[j + 1] && !back; ++f) back = g.ci[f] == i;
+        bad = bad || !back;
+    }
+    if (bad) atomicOr(&g.info[5], 1);
+}
+
 // info words of each listed graph into one array (for a single copy back).
 __global__ void k_pool_gather_info(const PoolGraph* __restrict__ gs, int count, int* __restrict__ out) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -590,29 +612,15 @@ size_t table_bytes(int k, int kpad, int W) {
     return l.bytes;
 }
 
-// Simple undirected graph in CSR: rows monotone from 0 to nnz, ids in range,
-// no self-loops, every arc has its reverse, no duplicate arcs.
+// What every kernel's memory accesses rely on: rows monotone from 0 to nnz
+// and ids in [0, n).  Self-loops, duplicate and one-way arcs are found on the
+// device during preparation (the graph then fails there).
 ssm_status check_host_csr(int n, int nnz, const int* rp, const int* ci) {
     if (rp[0] != 0 || rp[n] != nnz) return fail(SSM_E_INVAL, "pool: row_ptr must run from 0 to nnz");
     for (int i = 0; i < n; ++i)
         if (rp[i + 1] < rp[i]) return fail(SSM_E_INVAL, "pool: row_ptr is not monotone");
-    std::vector<int> row;
-    for (int i = 0; i < n; ++i) {
-        row.assign(ci + rp[i], ci + rp[i + 1]);
-        std::sort(row.begin(), row.end());
-        for (size_t q = 0; q < row.size(); ++q) {
-            const int j = row[q];
-            if (j < 0 || j >= n || j == i) return fail(SSM_E_INVAL, "pool: column index out of range or self-loop");
-            if (q > 0 && row[q - 1] == j) return fail(SSM_E_INVAL, "pool: duplicate arc");
-        }
-    }
-    for (int i = 0; i < n; ++i)
-        for (int e = rp[i]; e < rp[i + 1]; ++e) {
-            const int j = ci[e];
-            bool back = false;
-            for (int f = rp[j]; f < rp[j + 1] && !back; ++f) back = ci[f] == i;
-            if (!back) return fail(SSM_E_INVAL, "pool: adjacency is not symmetric");
-        }
+    for (int e = 0; e < nnz; ++e)
+        if ((unsigned)ci[e] >= (unsigned)n) return fail(SSM_E_INVAL, "pool: column index out of range");
     return SSM_OK;
 }
 
@@ -791,8 +799,12 @@ ssm_status ssm_pool_prepare(ssm_pool* p, int32_t count, const int32_t* slots, in
     hipError_t e = hipMemcpyAsync(dg, hg.data(), sizeof(PoolGraph) * nq, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(dbi, hbi.data(), sizeof(int2) * nbfs, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(dit, hit.data(), sizeof(int2) * nitems, hipMemcpyHostToDevice, s);
-    // stage 1: selection and BFS
+    // stage 1: CSR checks, selection and BFS
     if (e == hipSuccess) e = pool_prep_init(dg, nq, nmax, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_pool_validate, dim3((int)nitems), dim3(256), 0, s, dg, dit);
+        e = hipGetLastError();
+    }
     if (e == hipSuccess) e = pool_select(dg, nq, s);
     if (e == hipSuccess) e = pool_bfs(dg, dbi, (int)nbfs, dq, gq_stride, bfs_blocks, s);
     std::vector<int> hinfo(8 * (size_t)nq);
@@ -808,6 +820,11 @@ ssm_status ssm_pool_prepare(ssm_pool* p, int32_t count, const int32_t* slots, in
     if (e == hipSuccess) {
         for (int q = 0; q < nq; ++q) {
             Slot& sl = p->slots[ids[q]];
+            if (hinfo[8 * q + 5] != 0) {
+                sl.state = kFailed;
+                sl.fail = SSM_E_INVAL;  // not a simple undirected graph
+                continue;
+            }
             if (hinfo[8 * q] != 0) {
                 sl.state = kFailed;
                 sl.fail = SSM_E_DISCONNECTED;

@@ -32,6 +32,7 @@ class Request:
     first: int = 0
     # filled by the loop
     slot: int = -1
+    done: int = 0  # sweeps enqueued
     admitted: float = float("nan")
     finished: float = float("nan")
     stress: float = float("nan")
@@ -101,6 +102,8 @@ def serve(requests, pool_bytes: int, quantum: int = 25, warm: int = 1, max_prepa
         if active:
             with torch.cuda.stream(s_sweep):
                 pool.sweep(list(active), quantum)
+            for r in active.values():
+                r.done = min(r.sweeps, r.done + quantum)
             rounds += 1
         if new:
             with torch.cuda.stream(s_prep):
@@ -112,10 +115,11 @@ def serve(requests, pool_bytes: int, quantum: int = 25, warm: int = 1, max_prepa
                     r.status, r.finished = f"failed:{info['fail']}", clock() - t0
                     pool.remove(r.slot)
                     continue
+                r.done = min(r.sweeps, warm)
                 active[r.slot] = r
         peak_active = max(peak_active, len(active))
         # retire the graphs whose sweep count is reached
-        fin = [s for s, r in active.items() if pool.info(s)["done"] >= r.sweeps]
+        fin = [s for s, r in active.items() if r.done >= r.sweeps]
         if fin:
             with torch.cuda.stream(s_sweep):
                 st = pool.stress(fin)

@@ -168,9 +168,22 @@ def test_pool_admission_and_failures():
     with pytest.raises(ssm.SSMError) as ei:
         pool.add(G.grid(3, 3), 10)        # k > n
     assert ei.value.status == ssm.E_RANGE
-    asym = G.grid(4, 4)
-    ci = asym.col_idx.copy()
-    ci[2] = (ci[2] + 5) % asym.n
-    with pytest.raises(ssm.SSMError):
-        pool.add(G.CSR(asym.n, asym.row_ptr, ci, "bad"), 3)
+    # ids out of range are refused at admission; a one-way arc, a self-loop
+    # or a repeated neighbour fail the graph in preparation
+    g4 = G.grid(4, 4)
+    ci = g4.col_idx.copy()
+    ci[3] = g4.n + 2
+    with pytest.raises(ssm.SSMError) as ei:
+        pool.add(G.CSR(g4.n, g4.row_ptr, ci, "bad"), 3)
+    assert ei.value.status == ssm.E_INVAL
+    bads = []
+    for mutate in (lambda c: (c.__setitem__(2, (c[2] + 5) % g4.n), c)[1],   # one-way arc
+                   lambda c: (c.__setitem__(0, 0), c)[1],                    # self-loop at node 0
+                   lambda c: (c.__setitem__(1, c[0]), c)[1]):                # repeated neighbour
+        bads.append(pool.add(G.CSR(g4.n, g4.row_ptr, mutate(g4.col_idx.copy()), "bad"), 3))
+    ok = pool.add(G.grid(5, 5), 4)
+    pool.prepare(bads + [ok])
+    for b in bads:
+        assert pool.info(b)["state"] == ssm.POOL_FAILED and pool.info(b)["fail"] == ssm.E_INVAL
+    assert pool.info(ok)["state"] == ssm.POOL_READY
     pool.close()

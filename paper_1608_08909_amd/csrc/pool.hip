@@ -93,12 +93,16 @@ __global__ __launch_bounds__(1024) void k_pool_regions(const PoolGraph* __restri
     // per rank: running sum over the level and the weight row in one walk
     // (the level needed for distance d is min(d / 2, delta_max), which never
     // decreases with d)
+    for (int d = threadIdx.x; d < W; d += blockDim.x)
+        g.invd[d] = d >= 2 ? make_float2((float)(1.0 / ((double)d * (double)d)), (float)(1.0 / (double)d))
+                           : make_float2(0.f, 0.f);
     for (int t = threadIdx.x; t < kpad; t += blockDim.x) {
         if (t >= k) {
             for (int d = 0; d < W; ++d) {
                 g.w64[(size_t)t * W + d] = 0.0;
                 g.wt2[(size_t)t * W + d] = make_float2(0.f, 0.f);
             }
+            for (int l = 0; l < L; ++l) g.Hf[(size_t)t * L + l] = 0.f;
             g.pivots[t] = g.pivots[0];
             continue;
         }
@@ -109,6 +113,7 @@ __global__ __launch_bounds__(1024) void k_pool_regions(const PoolGraph* __restri
                 ++l;
                 acc += __hip_atomic_load(&g.H[(size_t)t * L + l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 g.H[(size_t)t * L + l] = acc;
+                g.Hf[(size_t)t * L + l] = (float)acc;
             }
             const double val = d >= 2 ? (double)acc / (double)((long long)d * (long long)d) : 0.0;
             g.w64[(size_t)t * W + d] = val;
@@ -118,6 +123,7 @@ __global__ __launch_bounds__(1024) void k_pool_regions(const PoolGraph* __restri
             ++l;
             acc += __hip_atomic_load(&g.H[(size_t)t * L + l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             g.H[(size_t)t * L + l] = acc;
+            g.Hf[(size_t)t * L + l] = (float)acc;
         }
     }
     __syncthreads();
@@ -221,39 +227,45 @@ __global__ __launch_bounds__(256) void k_pool_round(const PoolGraph* __restrict_
     g.x32[0][i] = make_float2((float)v.x, (float)v.y);
 }
 
-constexpr int kPoolSweepWaves = 4;
+constexpr int kPoolSweepBlock = 256;     // nodes of one graph per block
+constexpr int kPoolHistLds = 40 * 1024;  // LDS for a graph's Hf and invd tables in the FP32 sweep
 
-// FP32 sweep s of a call: one wavefront per 64-node chunk (graph, first
-// node).  A graph takes part while s < its iters; it reads x32[(parity + s)
-// & 1] and writes the other buffer.  Eq. 5 in displacement form as the
-// single-graph FP32 sweep: f = w' - (w' d) / r per term, neighbours in CSR
-// order first, then pivot terms by ascending rank; pivot coordinates are
-// staged in LDS per wave.
-__global__ __launch_bounds__(64 * kPoolSweepWaves) void k_pool_sweep32(const PoolGraph* __restrict__ gs,
-                                                                       const int2* __restrict__ chunks,
-                                                                       int nchunks, int s) {
-    __shared__ float2 sP[kPoolSweepWaves][kPoolMaxK];
-    const int w = threadIdx.x / kWave, lane = lane_id();
-    const int c = blockIdx.x * kPoolSweepWaves + w;
-    int2 ch = make_int2(0, 0);
-    bool active = false;
-    if (c < nchunks) {
-        ch = chunks[c];
-        active = s < gs[ch.x].iters;
-    }
-    if (active) {
-        const PoolGraph& g = gs[ch.x];
-        const float2* xo = g.x32[(g.parity + s) & 1];
-        for (int t = lane; t < g.kpad; t += kWave) sP[w][t] = xo[g.pivots[t]];
-    }
-    __syncthreads();
-    if (!active) return;
+// Whether the FP32 sweep of a graph stages its region histograms and 1/d
+// table in LDS (decided per graph, so a graph's arithmetic never depends on
+// the graphs that share its launch).
+inline int pool_hist_mode(int kpad, int L, int W) {
+    return sizeof(float) * (size_t)kpad * L + sizeof(float2) * (size_t)W <= (size_t)kPoolHistLds;
+}
+
+// FP32 sweep s of a call: a block per 256-node chunk (graph, first node) of
+// one graph.  A graph takes part while s < its iters; it reads x32[(parity +
+// s) & 1] and writes the other buffer.  Eq. 5 in displacement form as the
+// single-graph FP32 sweep: neighbours in CSR order first, then pivot terms by
+// ascending rank with f = w' - (w' d) / r, where w' = H[t][min(d/2,
+// delta_max)] / d^2 comes from the LDS copies of Hf and (1/d^2, 1/d) when the
+// graph's tables fit (else from the (w', w' d) table in global memory).
+// Pivot coordinates are staged in LDS once per block.
+__global__ __launch_bounds__(kPoolSweepBlock) void k_pool_sweep32(const PoolGraph* __restrict__ gs,
+                                                                  const int2* __restrict__ chunks, int s) {
+    extern __shared__ float4 psm[];
+    const int2 ch = chunks[blockIdx.x];
     const PoolGraph& g = gs[ch.x];
-    const int n = g.n, W = g.W, nwords = g.kpad / 8;
+    if (s >= g.iters) return;  // the whole block
+    const int n = g.n, W = g.W, L = g.L, kpad = g.kpad, nwords = kpad / 8;
+    const bool hist = g.hist != 0;
     const int p = (g.parity + s) & 1;
     const float2* __restrict__ xo = g.x32[p];
     float2* __restrict__ xn = g.x32[p ^ 1];
-    const int i = ch.y + lane;
+    float2* sP = (float2*)psm;                   // [kpad]
+    float2* sInv = sP + kpad;                    // [W] (hist)
+    float* sH = (float*)(sInv + (hist ? W : 0));  // [kpad][L] (hist)
+    for (int t = threadIdx.x; t < kpad; t += blockDim.x) sP[t] = xo[g.pivots[t]];
+    if (hist) {
+        for (int d = threadIdx.x; d < W; d += blockDim.x) sInv[d] = g.invd[d];
+        for (int q = threadIdx.x; q < kpad * L; q += blockDim.x) sH[q] = g.Hf[q];
+    }
+    __syncthreads();
+    const int i = ch.y + threadIdx.x;
     if (i >= n) return;
     const float tiny = 1e-30f;
     const float2 xi = xo[i];
@@ -293,11 +305,18 @@ __global__ __launch_bounds__(64 * kPoolSweepWaves) void k_pool_sweep32(const Poo
         for (int jj = 0; jj < 8; ++jj) {
             const int t = b * 8 + jj;
             const int d = (int)u.e[jj];
-            const float2 f01 = g.wt2[(size_t)t * W + d];
-            const float2 pv = sP[w][t];
+            const float2 pv = sP[t];
             const float dx = pv.x - xi.x, dy = pv.y - xi.y;
             const float inv = __builtin_amdgcn_rsqf(dx * dx + (dy * dy + tiny));
-            const float f = fmaf(-f01.y, inv, f01.x);
+            float f;
+            if (hist) {
+                const float h = sH[t * L + min(d >> 1, L - 1)];
+                const float2 id = sInv[d];
+                f = fmaf(-id.y, inv, id.x) * h;
+            } else {
+                const float2 f01 = g.wt2[(size_t)t * W + d];
+                f = fmaf(-f01.y, inv, f01.x);
+            }
             ax += f * dx;
             ay += f * dy;
         }
@@ -562,11 +581,16 @@ void bind(ssm_pool* p, Slot& s) {
         g.H = (int*)(T2 + lt.add(sizeof(int) * (size_t)k * g.W));
         g.w64 = (double*)(T2 + lt.add(sizeof(double) * kw));
         g.wt2 = (float2*)(T2 + lt.add(sizeof(float2) * kw));
+        g.Hf = (float*)(T2 + lt.add(sizeof(float) * kw));
+        g.invd = (float2*)(T2 + lt.add(sizeof(float2) * (size_t)g.W));
     } else {
         g.H = nullptr;
         g.w64 = nullptr;
         g.wt2 = nullptr;
+        g.Hf = nullptr;
+        g.invd = nullptr;
     }
+    g.hist = pool_hist_mode(kpad, g.L, g.W);
 }
 
 size_t persist_bytes(int n, int nnz, int kpad) {
@@ -609,6 +633,8 @@ size_t table_bytes(int k, int kpad, int W) {
     l.add(sizeof(int) * (size_t)k * W);
     l.add(sizeof(double) * (size_t)kpad * W);
     l.add(sizeof(float2) * (size_t)kpad * W);
+    l.add(sizeof(float) * (size_t)kpad * W);
+    l.add(sizeof(float2) * (size_t)W);
     return l.bytes;
 }
 
@@ -937,6 +963,7 @@ ssm_status ssm_pool_sweep(ssm_pool* p, int32_t count, const int32_t* slots, int3
     stg.hg.clear();
     stg.hc.clear();
     int most = 0;
+    size_t lds = 0;
     for (int q = 0; q < count; ++q) {
         Slot& sl = p->slots[slots[q]];
         PoolGraph g = sl.g;
@@ -944,7 +971,9 @@ ssm_status ssm_pool_sweep(ssm_pool* p, int32_t count, const int32_t* slots, int3
         g.parity = sl.parity;
         most = std::max(most, g.iters);
         stg.hg.push_back(g);
-        for (int i0 = 0; i0 < sl.n; i0 += kWave) stg.hc.push_back(make_int2(q, i0));
+        for (int i0 = 0; i0 < sl.n; i0 += kPoolSweepBlock) stg.hc.push_back(make_int2(q, i0));
+        lds = std::max(lds, sizeof(float2) * (size_t)sl.kpad +
+                                (g.hist ? sizeof(float2) * (size_t)g.W + sizeof(float) * (size_t)sl.kpad * g.L : 0));
     }
     if (most == 0) return SSM_OK;
     const size_t need = align_up(sizeof(PoolGraph) * stg.hg.size()) + sizeof(int2) * stg.hc.size();
@@ -965,9 +994,10 @@ ssm_status ssm_pool_sweep(ssm_pool* p, int32_t count, const int32_t* slots, int3
     if (e == hipSuccess)
         e = hipMemcpyAsync(dc, stg.hc.data(), sizeof(int2) * stg.hc.size(), hipMemcpyHostToDevice, s);
     const int nch = (int)stg.hc.size();
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute((const void*)k_pool_sweep32, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     for (int it = 0; it < most && e == hipSuccess; ++it) {
-        hipLaunchKernelGGL(k_pool_sweep32, dim3(div_up(nch, kPoolSweepWaves)), dim3(64 * kPoolSweepWaves), 0, s, dg,
-                           dc, nch, it);
+        hipLaunchKernelGGL(k_pool_sweep32, dim3(nch), dim3(kPoolSweepBlock), lds, s, dg, dc, it);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipEventRecord(stg.done, s);

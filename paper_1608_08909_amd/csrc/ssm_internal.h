@@ -125,7 +125,8 @@ constexpr int kPoolGramChunk = 2048;
 struct PoolGraph {
     int n, nnz, k, kpad;   // kpad: k rounded up to 8 (uint16 words)
     int first, W, L, iters;  // max/min start; table row length dmax + 1; delta_max + 1; sweeps in this call
-    int parity, ntiles, nchunks, pad_;  // FP32 buffer holding the current iterate; Gram tiles, Gram node chunks
+    int parity, ntiles, nchunks, hist;  // FP32 buffer holding the current iterate; Gram tiles, Gram node
+                                        // chunks; 1: the FP32 sweep stages Hf and invd in LDS
     const int* rp;          // [n + 1] local arc offsets
     const int* ci;          // [nnz] local ids
     int* ell;               // [n][kPoolEllW] (preparation)
@@ -137,6 +138,8 @@ struct PoolGraph {
     int* H;                 // [k][L] cumulative region histograms (room for k W)
     double* w64;            // [kpad][W]
     float2* wt2;            // [kpad][W]: (w', w' d) in FP32
+    float* Hf;              // [kpad][L]: H as float (exact below 2^24), zero rows past k
+    float2* invd;           // [W]: (1/d^2, 1/d) for d >= 2, zero below
     double* den64;          // [n]
     float* den32;           // [n]
     double2* x64[2];        // FP64 iterates (PivotMDS, warm-up sweeps)

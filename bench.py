@@ -141,9 +141,11 @@ def run_serve(args):
                 for i, (g, a) in enumerate(zip(gs, arr))]
 
     for _ in range(args.warmup):
-        serve.serve(requests(warm_graphs, args.seed + 2), pool_bytes, args.quantum)
+        serve.serve(requests(warm_graphs, args.seed + 2), pool_bytes, args.quantum, max_prepare=args.max_prepare,
+                    first_prepare=args.first_prepare, prep_quantum=args.prep_quantum)
     torch.cuda.synchronize()
-    rep = serve.serve(requests(graphs, args.seed), pool_bytes, args.quantum)
+    rep = serve.serve(requests(graphs, args.seed), pool_bytes, args.quantum, max_prepare=args.max_prepare,
+                      first_prepare=args.first_prepare, prep_quantum=args.prep_quantum)
     done = rep.completed()
     lat = rep.latencies_ms()
     node_updates = sum(r.graph.n * r.sweeps for r in done)
@@ -202,7 +204,9 @@ def run_serve(args):
         "config": {"workload": SERVE_DESC.format(count=args.requests, rate=args.rate, sweeps=args.sweeps,
                                                  pool_gib=args.pool_gib, quantum=args.quantum),
                    "requests": args.requests, "seed": args.seed, "rate_per_s": args.rate,
-                   "pool_bytes": pool_bytes, "quantum": args.quantum, "sweeps": args.sweeps},
+                   "pool_bytes": pool_bytes, "quantum": args.quantum, "max_prepare": args.max_prepare,
+                   "first_prepare": args.first_prepare, "prep_quantum": args.prep_quantum,
+                   "sweeps": args.sweeps},
         "completed": len(done),
         "failed": len(rep.requests) - len(done),
         "layouts_per_s": len(done) / rep.wall_s,
@@ -212,6 +216,7 @@ def run_serve(args):
         "prepare_batches": rep.prepares,
         "peak_active_graphs": rep.peak_active,
         "peak_pool_bytes": rep.peak_bytes,
+        "host_phase_s": rep.host_s,
         "final_stress_rel_diff_vs_plain_fp64": {"max": float(max(rels)), "sample": len(rels)},
         "plain_fp64_layouts_per_s_sample": len(sample) / t_plain,
         "host_graph_generation_s": t_gen,
@@ -243,8 +248,11 @@ def main():
     ap.add_argument("--requests", type=int, default=4096, help="serve: requests in the stream")
     ap.add_argument("--warm-requests", type=int, default=64, help="serve: requests of each warm-up stream")
     ap.add_argument("--rate", type=float, default=100000.0, help="serve: Poisson arrival rate (requests/s)")
-    ap.add_argument("--pool-gib", type=float, default=8.0, help="serve: layout pool arena (GiB)")
+    ap.add_argument("--pool-gib", type=float, default=32.0, help="serve: layout pool arena (GiB)")
     ap.add_argument("--quantum", type=int, default=25, help="serve: sweeps per scheduling round")
+    ap.add_argument("--max-prepare", type=int, default=1024, help="serve: largest preparation batch")
+    ap.add_argument("--first-prepare", type=int, default=128, help="serve: preparation batch while nothing runs")
+    ap.add_argument("--prep-quantum", type=int, default=100, help="serve: sweeps queued in a round that prepares")
     ap.add_argument("--sweeps", type=int, default=200, help="serve: sweeps per request")
     ap.add_argument("--seed", type=int, default=4, help="serve: stream seed")
     ap.add_argument("--sampling", default="maxmin", choices=["maxmin", "kmeans"],

@@ -1304,11 +1304,11 @@ __device__ __forceinline__ unsigned long long argmax_m7_clear(unsigned char* m8,
 //   otherwise: LDS visited bits, global m.
 // The claiming lane owns m[v] for the level and writes it with plain
 // stores.  gq holds 3 n ints.
-template <int W, bool M8>
+template <int W, bool M8, int SPOOL = kSelPool>
 __device__ __forceinline__ void select_ell_body(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                 const int* __restrict__ ell, int k, int first, int* pivots, int* m,
                                                 int* gq, int* status) {
-    __shared__ __align__(16) unsigned char pool[kSelPool];
+    __shared__ __align__(16) unsigned char pool[SPOOL];
     __shared__ int2 s_slot[3];
     __shared__ int s_src;
     __shared__ unsigned long long s_red[kBfsBlock / kWave];
@@ -2050,22 +2050,34 @@ hipError_t pool_prep_init(const PoolGraph* gs, int count, int nmax, hipStream_t 
     return hipGetLastError();
 }
 
-// One max/min selection per graph, in one workgroup with LDS state bytes.
-__global__ __launch_bounds__(kBfsBlock) void k_pool_select(const PoolGraph* __restrict__ gs) {
+// One max/min selection per graph, in one workgroup with LDS state bytes
+// (LDS sized for the batch's largest graph; smaller pools let several
+// selections share a CU).
+constexpr int kPoolSelS = kLdsFixed + 22528, kPoolSelL = kLdsFixed + kPoolMaxN;
+constexpr int kPoolSelBlock = 512;
+constexpr int kPoolBfsBlock = 256;
+
+template <int SPOOL>
+__global__ __launch_bounds__(kPoolSelBlock) void k_pool_select(const PoolGraph* __restrict__ gs) {
     const PoolGraph& g = gs[blockIdx.x];
-    select_ell_body<kPoolEllW, true>(g.n, g.rp, g.ci, g.ell, g.k, g.first, g.pivots, g.m, g.gq, g.info);
+    select_ell_body<kPoolEllW, true, SPOOL>(g.n, g.rp, g.ci, g.ell, g.k, g.first, g.pivots, g.m, g.gq, g.info);
 }
 
-hipError_t pool_select(const PoolGraph* gs, int count, hipStream_t s) {
-    hipLaunchKernelGGL(k_pool_select, dim3(count), dim3(kBfsBlock), 0, s, gs);
+hipError_t pool_select(const PoolGraph* gs, int count, int nmax, hipStream_t s) {
+    if (kLdsFixed + (((size_t)nmax + 15) & ~(size_t)15) <= (size_t)kPoolSelS)
+        hipLaunchKernelGGL(k_pool_select<kPoolSelS>, dim3(count), dim3(kPoolSelBlock), 0, s, gs);
+    else
+        hipLaunchKernelGGL(k_pool_select<kPoolSelL>, dim3(count), dim3(kPoolSelBlock), 0, s, gs);
     return hipGetLastError();
 }
 
 // Items (graph, rank) over a persistent grid: the BFS from that graph's
 // pivot of that rank into its distance row; info[1] = eccentricity maximum.
-__global__ __launch_bounds__(kBfsBlock) void k_pool_bfs(const PoolGraph* __restrict__ gs,
-                                                        const int2* __restrict__ items, int nitems, int* gq,
-                                                        long long gq_stride) {
+// Small workgroups: the pool's graphs have narrow frontiers, and several
+// BFS then share a CU.
+__global__ __launch_bounds__(kPoolBfsBlock) void k_pool_bfs(const PoolGraph* __restrict__ gs,
+                                                            const int2* __restrict__ items, int nitems, int* gq,
+                                                            long long gq_stride) {
     __shared__ int s_reached;
     int* myq = gq + (size_t)blockIdx.x * gq_stride;
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -2077,9 +2089,11 @@ __global__ __launch_bounds__(kBfsBlock) void k_pool_bfs(const PoolGraph* __restr
     }
 }
 
+int pool_bfs_blocks(int nitems) { return std::max(1, std::min(nitems, 5 * num_cus())); }
+
 hipError_t pool_bfs(const PoolGraph* gs, const int2* items, int nitems, int* gq, long long gq_stride, int blocks,
                     hipStream_t s) {
-    hipLaunchKernelGGL(k_pool_bfs, dim3(blocks), dim3(kBfsBlock), 0, s, gs, items, nitems, gq, gq_stride);
+    hipLaunchKernelGGL(k_pool_bfs, dim3(blocks), dim3(kPoolBfsBlock), 0, s, gs, items, nitems, gq, gq_stride);
     return hipGetLastError();
 }
 

@@ -794,7 +794,7 @@ ssm_status ssm_pool_prepare(ssm_pool* p, int32_t count, const int32_t* slots, in
         ngram += (long long)div_up(sl.n, kPoolGramChunk) * div_up(T * (T + 1) / 2, 32);
     }
     const int nq = (int)ids.size();
-    const int bfs_blocks = (int)std::min<long long>(nbfs, 2LL * num_cus());
+    const int bfs_blocks = pool_bfs_blocks((int)nbfs);
     const long long gq_stride = 3LL * nmax;
     Layout lw;
     const size_t o_g = lw.add(sizeof(PoolGraph) * nq), o_bi = lw.add(sizeof(int2) * nbfs),
@@ -831,7 +831,7 @@ ssm_status ssm_pool_prepare(ssm_pool* p, int32_t count, const int32_t* slots, in
         hipLaunchKernelGGL(k_pool_validate, dim3((int)nitems), dim3(256), 0, s, dg, dit);
         e = hipGetLastError();
     }
-    if (e == hipSuccess) e = pool_select(dg, nq, s);
+    if (e == hipSuccess) e = pool_select(dg, nq, nmax, s);
     if (e == hipSuccess) e = pool_bfs(dg, dbi, (int)nbfs, dq, gq_stride, bfs_blocks, s);
     std::vector<int> hinfo(8 * (size_t)nq);
     if (e == hipSuccess) {

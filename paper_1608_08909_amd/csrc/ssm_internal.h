@@ -161,7 +161,8 @@ struct PoolGraph {
 // (graph, rank) items over a persistent grid with gq_stride ints of overflow
 // queue per block.
 hipError_t pool_prep_init(const PoolGraph* gs, int count, int nmax, hipStream_t s);
-hipError_t pool_select(const PoolGraph* gs, int count, hipStream_t s);
+hipError_t pool_select(const PoolGraph* gs, int count, int nmax, hipStream_t s);
+int pool_bfs_blocks(int nitems);
 hipError_t pool_bfs(const PoolGraph* gs, const int2* items, int nitems, int* gq, long long gq_stride, int blocks,
                     hipStream_t s);
 // Stages (pmds.hip): centring statistics, Gram partial tiles as

@@ -48,6 +48,7 @@ class Report:
     prepares: int
     peak_active: int
     peak_bytes: int
+    host_s: dict  # host time of the loop's phases: admission, sweep enqueue, preparation, retirement, waiting
 
     def completed(self):
         return [r for r in self.requests if r.status == "done"]
@@ -62,9 +63,16 @@ def poisson_arrivals(count: int, rate: float, seed: int) -> np.ndarray:
     return np.cumsum(rng.exponential(1.0 / rate, size=count))
 
 
-def serve(requests, pool_bytes: int, quantum: int = 25, warm: int = 1, max_prepare: int = 512,
-          keep_layouts: bool = False, clock=time.perf_counter) -> Report:
-    """Runs the stream to completion and returns the per-request record."""
+def serve(requests, pool_bytes: int, quantum: int = 25, warm: int = 1, max_prepare: int = 1024,
+          first_prepare: int = 128, prep_quantum: int = 100, keep_layouts: bool = False,
+          clock=time.perf_counter) -> Report:
+    """Runs the stream to completion and returns the per-request record.
+    While nothing is running yet, a preparation batch holds at most
+    `first_prepare` requests, so that sweeping starts early; later batches
+    (prepared while others sweep) hold up to `max_prepare`.  A round that
+    prepares a batch first queues `prep_quantum` sweeps of the running
+    graphs (enough to keep the device busy during the preparation), other
+    rounds `quantum`."""
     pool = ssm.Pool(pool_bytes)
     s_sweep = torch.cuda.Stream()
     s_prep = torch.cuda.Stream()
@@ -72,14 +80,17 @@ def serve(requests, pool_bytes: int, quantum: int = 25, warm: int = 1, max_prepa
     waiting = collections.deque()
     active: dict[int, Request] = {}
     rounds = prepares = peak_active = peak_bytes = 0
+    host = dict.fromkeys(["admit", "sweep", "prepare", "retire", "wait"], 0.0)
     t0 = clock()
     while pending or waiting or active:
         now = clock() - t0
         while pending and pending[0].arrival <= now:
             waiting.append(pending.popleft())
         # admission: as many arrived requests as the arena holds
+        ta = clock()
         new = []
-        while waiting and len(new) < max_prepare:
+        cap_new = max_prepare if active else min(max_prepare, first_prepare)
+        while waiting and len(new) < cap_new:
             r = waiting[0]
             try:
                 slot = pool.add(r.graph, r.k, r.first, r.sweeps)
@@ -97,14 +108,19 @@ def serve(requests, pool_bytes: int, quantum: int = 25, warm: int = 1, max_prepa
             r.slot, r.admitted, r.status = slot, clock() - t0, "admitted"
             new.append(r)
         peak_bytes = max(peak_bytes, pool.usage()[0])
+        tb = clock()
+        host["admit"] += tb - ta
         # one sweep quantum for the running graphs, overlapped with the
         # preparation of the new ones
         if active:
+            q = prep_quantum if new else quantum
             with torch.cuda.stream(s_sweep):
-                pool.sweep(list(active), quantum)
+                pool.sweep(list(active), q)
             for r in active.values():
-                r.done = min(r.sweeps, r.done + quantum)
+                r.done = min(r.sweeps, r.done + q)
             rounds += 1
+        tc = clock()
+        host["sweep"] += tc - tb
         if new:
             with torch.cuda.stream(s_prep):
                 pool.prepare([r.slot for r in new], warm)
@@ -118,6 +134,8 @@ def serve(requests, pool_bytes: int, quantum: int = 25, warm: int = 1, max_prepa
                 r.done = min(r.sweeps, warm)
                 active[r.slot] = r
         peak_active = max(peak_active, len(active))
+        td = clock()
+        host["prepare"] += td - tc
         # retire the graphs whose sweep count is reached
         fin = [s for s, r in active.items() if r.done >= r.sweeps]
         if fin:
@@ -134,11 +152,14 @@ def serve(requests, pool_bytes: int, quantum: int = 25, warm: int = 1, max_prepa
                 for s in fin:
                     del active[s]
                     pool.remove(s)
+        te = clock()
+        host["retire"] += te - td
         if not active and not new and not waiting and pending:
             wait = pending[0].arrival - (clock() - t0)
             if wait > 0:
                 time.sleep(wait)
+            host["wait"] += clock() - te
     torch.cuda.synchronize()
     wall = clock() - t0
     pool.close()
-    return Report(list(requests), wall, rounds, prepares, peak_active, peak_bytes)
+    return Report(list(requests), wall, rounds, prepares, peak_active, peak_bytes, host)

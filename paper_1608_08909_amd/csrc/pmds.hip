@@ -202,7 +202,10 @@ __device__ __forceinline__ double splitmix_uniform(unsigned long long& state) {
 }
 
 constexpr int kEigThreads = 1024;
-constexpr int kEigP = 8;      // subspace width (two vectors wanted)
+constexpr int kEigRows = 16;  // rows of M per wave kept in registers (k <= 256)
+constexpr int kEigCols = 4;   // columns per lane (k <= 256)
+constexpr int kEigFast = 400;  // steps of the two-vector iteration before the block iteration takes over
+constexpr int kEigP = 8;      // subspace width of the block iteration
 constexpr int kEigCheck = 8;  // steps between Rayleigh-Ritz convergence tests
 
 // Start / replacement vector entry (row r, column c, draw d): SplitMix64 in
@@ -327,8 +330,8 @@ __device__ void eig_small(int pw, const double* H, double* Y, double* th) {
 // sign rule: each column's largest-magnitude entry is positive (entries
 // within a relative 1e-9 of the largest count as tied; the lowest index
 // decides).  out: V (k x 2), lambda[2]; iters[0] = steps.
-__device__ __forceinline__ void pmds_eig_body(int k, const double* __restrict__ M, double tol, int max_iter,
-                                              double* __restrict__ out, int* __restrict__ iters) {
+__device__ __forceinline__ void eigp_body(int k, const double* __restrict__ M, double tol, int max_iter,
+                                          int steps0, double* __restrict__ out, int* __restrict__ iters) {
     extern __shared__ double sh[];
     double* V = sh;                  // [k][kEigP]
     double* Z = V + kEigP * k;       // [k][kEigP]
@@ -460,8 +463,205 @@ __device__ __forceinline__ void pmds_eig_body(int k, const double* __restrict__ 
     if (threadIdx.x == 0) {
         out[2 * k] = th[0];
         out[2 * k + 1] = th[1];
+        iters[0] = steps0 + it;
+    }
+}
+
+// Orthogonal (subspace) iteration on two vectors, one workgroup, M kept in
+// registers when REG (k <= 256).  Start: SplitMix64 values in [-1, 1) (seed
+// 0x53534D00 + column).  Each step: Z = M V, Gram-Schmidt; converged once
+// every column of Z lies in span(V) to within `tol` per entry (only the first
+// when M has numerical rank 1).  Then Rayleigh-Ritz on the 2 x 2 V^T M V
+// (larger eigenvalue first) and the sign rule.  Returns false (uniformly,
+// output untouched) when max_iter steps do not converge: the rate is
+// lambda_3 / lambda_2, slow when those two nearly tie.
+template <bool REG>
+__device__ __forceinline__ bool eig2_body(int k, const double* __restrict__ M, double tol, int max_iter,
+                                          double* __restrict__ out, int* __restrict__ iters) {
+    extern __shared__ double sh[];
+    double* v0 = sh;
+    double* v1 = sh + k;
+    double* z0 = sh + 2 * k;
+    double* z1 = sh + 3 * k;
+    __shared__ double red[kEigThreads / kWave];
+    const int lane = lane_id(), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    double mreg[REG ? kEigRows : 1][REG ? kEigCols : 1];
+    if (REG) {
+#pragma unroll
+        for (int q = 0; q < kEigRows; ++q)
+#pragma unroll
+            for (int c = 0; c < kEigCols; ++c) {
+                int r = w + nw * q, j = lane + kWave * c;
+                mreg[REG ? q : 0][REG ? c : 0] = (r < k && j < k) ? M[(size_t)r * k + j] : 0.0;
+            }
+    }
+    if (threadIdx.x == 0) {
+        unsigned long long s0 = 0x53534D00ull, s1 = 0x53534D01ull;
+        for (int t = 0; t < k; ++t) {
+            v0[t] = splitmix_uniform(s0);
+            v1[t] = splitmix_uniform(s1);
+        }
+    }
+    __syncthreads();
+    auto matvec = [&]() {
+        if (REG) {
+#pragma unroll
+            for (int q = 0; q < kEigRows; ++q) {
+                const int r = w + nw * q;
+                if (r < k) {  // uniform across the wave
+                    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+                    for (int c = 0; c < kEigCols; ++c) {
+                        int j = lane + kWave * c;
+                        if (j < k) {
+                            double mv = mreg[REG ? q : 0][REG ? c : 0];
+                            a0 += mv * v0[j];
+                            a1 += mv * v1[j];
+                        }
+                    }
+                    a0 = wave_sum(a0);
+                    a1 = wave_sum(a1);
+                    if (lane == 0) {
+                        z0[r] = a0;
+                        z1[r] = a1;
+                    }
+                }
+            }
+        } else {
+            for (int r = w; r < k; r += nw) {
+                double a0 = 0.0, a1 = 0.0;
+                for (int j = lane; j < k; j += kWave) {
+                    double mv = M[(size_t)r * k + j];
+                    a0 += mv * v0[j];
+                    a1 += mv * v1[j];
+                }
+                a0 = wave_sum(a0);
+                a1 = wave_sum(a1);
+                if (lane == 0) {
+                    z0[r] = a0;
+                    z1[r] = a1;
+                }
+            }
+        }
+        __syncthreads();
+    };
+    auto dot = [&](const double* a, const double* b) {
+        double s = 0.0;
+        for (int t = threadIdx.x; t < k; t += blockDim.x) s += a[t] * b[t];
+        return block_sum(s, red);
+    };
+    // normalize v0, orthonormalize v1 against it (start vectors)
+    {
+        double nn = sqrt(dot(v0, v0));
+        for (int t = threadIdx.x; t < k; t += blockDim.x) v0[t] /= nn;
+        __syncthreads();
+        for (int pass = 0; pass < 2; ++pass) {
+            double d = dot(v0, v1);
+            for (int t = threadIdx.x; t < k; t += blockDim.x) v1[t] -= d * v0[t];
+            __syncthreads();
+        }
+        double n1 = sqrt(dot(v1, v1));
+        for (int t = threadIdx.x; t < k; t += blockDim.x) v1[t] /= n1;
+        __syncthreads();
+    }
+    int it = 0;
+    bool converged = false;
+    for (; it < max_iter; ++it) {
+        matvec();
+        double n0 = sqrt(dot(z0, z0));
+        for (int t = threadIdx.x; t < k; t += blockDim.x) z0[t] /= n0;
+        __syncthreads();
+        // Gram-Schmidt twice: once is not enough when z1 is nearly parallel to z0
+        for (int pass = 0; pass < 2; ++pass) {
+            double d01 = dot(z0, z1);
+            for (int t = threadIdx.x; t < k; t += blockDim.x) z1[t] -= d01 * z0[t];
+            __syncthreads();
+        }
+        double n1 = sqrt(dot(z1, z1));
+        // a second column negligible against the first: M has numerical rank 1
+        const bool rank1 = !(n1 > 1e-13 * n0);
+        if (rank1) {
+            // any unit vector orthogonal to z0 will do: keep v1 made orthogonal to z0
+            for (int t = threadIdx.x; t < k; t += blockDim.x) z1[t] = v1[t];
+            __syncthreads();
+            for (int pass = 0; pass < 2; ++pass) {
+                double d = dot(z0, z1);
+                for (int t = threadIdx.x; t < k; t += blockDim.x) z1[t] -= d * z0[t];
+                __syncthreads();
+            }
+            n1 = sqrt(dot(z1, z1));
+        }
+        for (int t = threadIdx.x; t < k; t += blockDim.x) z1[t] /= n1;
+        __syncthreads();
+        // distance of span(Z) from span(V): residual of projecting Z on V
+        double p00 = dot(v0, z0), p10 = dot(v1, z0), p01 = dot(v0, z1), p11 = dot(v1, z1);
+        double res0 = 0.0, res1 = 0.0;
+        for (int t = threadIdx.x; t < k; t += blockDim.x) {
+            double r0 = z0[t] - p00 * v0[t] - p10 * v1[t];
+            double r1 = z1[t] - p01 * v0[t] - p11 * v1[t];
+            res0 = fmax(res0, fabs(r0));
+            res1 = fmax(res1, fabs(r1));
+        }
+        res0 = block_max(res0, red);
+        res1 = block_max(res1, red);
+        for (int t = threadIdx.x; t < k; t += blockDim.x) {
+            v0[t] = z0[t];
+            v1[t] = z1[t];
+        }
+        __syncthreads();
+        if (res0 < tol && (res1 < tol || rank1)) {
+            ++it;
+            converged = true;
+            break;
+        }
+    }
+    if (!converged) return false;  // uniform: the caller goes on with the block iteration
+    // Rayleigh-Ritz on span(V)
+    matvec();
+    double b00 = dot(v0, z0), b11 = dot(v1, z1);
+    double b01 = 0.5 * (dot(v0, z1) + dot(v1, z0));
+    double th = 0.5 * atan2(2.0 * b01, b00 - b11);
+    double cs = cos(th), sn = sin(th);
+    double l0 = b00 * cs * cs + 2.0 * b01 * cs * sn + b11 * sn * sn;
+    double l1 = b00 * sn * sn - 2.0 * b01 * cs * sn + b11 * cs * cs;
+    for (int t = threadIdx.x; t < k; t += blockDim.x) {
+        double a = v0[t], b = v1[t];
+        z0[t] = cs * a + sn * b;
+        z1[t] = -sn * a + cs * b;
+    }
+    __syncthreads();
+    // sign rule
+    for (int col = 0; col < 2; ++col) {
+        double* z = col == 0 ? z0 : z1;
+        double mx = 0.0;
+        for (int t = threadIdx.x; t < k; t += blockDim.x) mx = fmax(mx, fabs(z[t]));
+        mx = block_max(mx, red);
+        int idx = k;  // lowest index within a relative 1e-9 of the largest magnitude
+        for (int t = threadIdx.x; t < k; t += blockDim.x)
+            if (fabs(z[t]) >= mx * (1.0 - 1e-9) && t < idx) idx = t;
+        idx = -block_max(-idx, (int*)red);
+        if (idx >= k) idx = 0;
+        double sg = z[idx] < 0.0 ? -1.0 : 1.0;
+        for (int t = threadIdx.x; t < k; t += blockDim.x) out[2 * t + col] = sg * z[t];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[2 * k] = l0;
+        out[2 * k + 1] = l1;
         iters[0] = it;
     }
+    return true;
+}
+
+// The two dominant eigenvectors of M: the two-vector iteration for up to
+// kEigFast steps, then, if it has not converged, the block iteration.
+template <bool REG>
+__device__ __forceinline__ void pmds_eig_body(int k, const double* __restrict__ M, double tol, int max_iter,
+                                              double* __restrict__ out, int* __restrict__ iters) {
+    const int fast = min(max_iter, kEigFast);
+    if (eig2_body<REG>(k, M, tol, fast, out, iters)) return;
+    __syncthreads();
+    eigp_body(k, M, tol, max_iter - fast, fast, out, iters);
 }
 
 // LDS bytes of pmds_eig_body for k.
@@ -469,10 +669,11 @@ __host__ __device__ constexpr size_t eig_lds_bytes(int k) {
     return sizeof(double) * ((size_t)(2 * kEigP + 2) * k + 2 * kEigP * kEigP + kEigP);
 }
 
+template <bool REG>
 __global__ __launch_bounds__(kEigThreads) void k_pmds_eig(int k, const double* __restrict__ M, double tol,
                                                          int max_iter, double* __restrict__ out,
                                                          int* __restrict__ iters) {
-    pmds_eig_body(k, M, tol, max_iter, out, iters);
+    pmds_eig_body<REG>(k, M, tol, max_iter, out, iters);
 }
 
 // x_i = sum over t ascending of C_it V_t (per column), FP64.
@@ -603,10 +804,16 @@ ssm_status pivotmds(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* x, hipStre
         hipLaunchKernelGGL(k_pmds_gram_reduce, dim3(std::min(div_up((long long)ntiles * 256, 256), 4096)),
                            dim3(256), 0, s, k, nchunks, ntiles, tiles, part, M);
         const size_t elds = eig_lds_bytes(k);
-        if (elds > 64 * 1024)
-            (void)hipFuncSetAttribute((const void*)k_pmds_eig, hipFuncAttributeMaxDynamicSharedMemorySize, (int)elds);
-        hipLaunchKernelGGL(k_pmds_eig, dim3(1), dim3(kEigThreads), elds, s, k, M, 1e-13, 20000, t->eig,
-                           t->eig_iters);
+        if (k <= kEigRows * (kEigThreads / kWave) && k <= kEigCols * kWave) {
+            hipLaunchKernelGGL(k_pmds_eig<true>, dim3(1), dim3(kEigThreads), elds, s, k, M, 1e-13, 20000, t->eig,
+                               t->eig_iters);
+        } else {
+            if (elds > 64 * 1024)
+                (void)hipFuncSetAttribute((const void*)k_pmds_eig<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          (int)elds);
+            hipLaunchKernelGGL(k_pmds_eig<false>, dim3(1), dim3(kEigThreads), elds, s, k, M, 1e-13, 20000, t->eig,
+                               t->eig_iters);
+        }
         double2* xd = (double2*)t->xtmp;
         if (t->dbytes == 1)
             hipLaunchKernelGGL((k_pmds_project<uint8_t, 16>), dim3(gn), dim3(256), 0, s, n, k, nwords, dpk, mu,
@@ -702,7 +909,7 @@ __global__ void k_pool_gram_reduce(const PoolGraph* __restrict__ gs, const int2*
 
 __global__ __launch_bounds__(kEigThreads) void k_pool_eig(const PoolGraph* __restrict__ gs) {
     const PoolGraph& g = gs[blockIdx.x];
-    pmds_eig_body(g.k, g.M, 1e-13, 20000, g.eig, g.info + 4);
+    pmds_eig_body<true>(g.k, g.M, 1e-13, 20000, g.eig, g.info + 4);
 }
 
 // Per graph: x64[0] = C V (ranks ascending), then the uniform rescale that

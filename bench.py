@@ -239,12 +239,59 @@ def run_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def run_quality(args):
+    """Section 4.1's quality measures on the 50 x 50 grid: the full-stress
+    reference (k = n, 500 FP64 sweeps), then sparse layouts (k = 50, 100, 200;
+    max/min and k-means sp sampling; 200 FP64 sweeps) scored by normalized
+    stress and by the Procrustes statistic against the reference.  One step =
+    the reference layout; `value` is its node-updates/s."""
+    import torch
+
+    from paper_1608_08909_amd import graphs as G
+    from paper_1608_08909_amd import ssm
+
+    torch.cuda.set_device(0)
+    g = G.grid(50, 50)
+    dg = ssm.DeviceGraph.from_csr(g)
+    for _ in range(args.warmup):
+        ssm.full_stress_layout(dg, 20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        xr, _ = ssm.full_stress_layout(dg, 500)
+    torch.cuda.synchronize()
+    t_ref = (time.perf_counter() - t0) / args.steps
+    ns_ref = ssm.normalized_stress(dg, xr)
+    rows = []
+    for sampling in ("maxmin", "kmeans"):
+        for k in (50, 100, 200):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            x, *_ = ssm.layout(dg, k, 200, ssm.FP64, sampling=sampling)
+            torch.cuda.synchronize()
+            rows.append({"sampling": sampling, "k": k, "ms": (time.perf_counter() - t1) * 1e3,
+                         "normalized_stress": ssm.normalized_stress(dg, x), "procrustes": ssm.procrustes(x, xr)})
+    out = {
+        "metric": "node-updates/sec & layouts/sec (p50/p99) at equal final stress vs plain, 1 GPU",
+        "value": g.n * 500 / t_ref,
+        "unit": "node-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_ref * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "quality report on the grid 50x50: full-stress reference (k = n = 2500 pivots, "
+                               "start from PivotMDS on the first 1024, 500 FP64 sweeps) and sparse layouts (k = 50, 100, 200 by max/min and k-means sp, "
+                               "200 FP64 sweeps) scored by normalized stress and the Procrustes statistic"},
+        "reference_normalized_stress": ns_ref,
+        "quality": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rgg", choices=sorted(WORKLOADS) + ["serve"])
+    ap.add_argument("--workload", default="rgg", choices=sorted(WORKLOADS) + ["serve", "quality"])
     ap.add_argument("--requests", type=int, default=4096, help="serve: requests in the stream")
     ap.add_argument("--warm-requests", type=int, default=64, help="serve: requests of each warm-up stream")
     ap.add_argument("--rate", type=float, default=100000.0, help="serve: Poisson arrival rate (requests/s)")
@@ -268,6 +315,9 @@ def main():
         sys.exit(2)
     if args.workload == "serve":
         run_serve(args)
+        return
+    if args.workload == "quality":
+        run_quality(args)
         return
 
     import torch

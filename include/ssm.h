@@ -191,6 +191,19 @@ ssm_status ssm_majorize_mixed(const ssm_csr* g, ssm_terms* t, double* x64, float
 ssm_status ssm_stress(const ssm_csr* g, ssm_terms* t, ssm_prec p, const void* x,
                       ssm_stress_kind kind, double* out_host, hipStream_t stream);
 
+/* Procrustes statistic of layout x against the reference layout y (both
+ * n x 2, interleaved, of precision px / py): the share of y's spread that x
+ * misses after the best translation, rotation and dilation (no reflection),
+ * the measure of Section 4.1 that compares a sparse layout with the
+ * full-stress layout.  With X, Y centred and A = X^T Y:
+ * 1 - (||A||_F^2 + 2 det A) / (tr(X^T X) tr(Y^T Y)), in [0, 1], 0 for a
+ * perfect match.  Accumulated in FP64.  SSM_E_INVAL when a layout has all its
+ * nodes at one point.  Writes out_host[0].  Synchronizes.
+ * The paper's other measure, the normalized stress, is ssm_stress with
+ * SSM_STRESS_FULL divided by n (n - 1) / 2. */
+ssm_status ssm_procrustes(int32_t n, ssm_prec px, const void* x, ssm_prec py, const void* y, double* out_host,
+                          hipStream_t stream);
+
 /* ---- Layout pool: many small graphs laid out together ----------------
  *
  * The same method (Algorithm 1: max/min sp pivots, their BFS, regions and

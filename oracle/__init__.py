@@ -242,6 +242,31 @@ def stress_full(row_ptr, col_idx, x) -> float:
     return _load().orc_stress_full(x.shape[0], _p(rp), _p(ci), _p(x))
 
 
+def normalized_stress(row_ptr, col_idx, x) -> float:
+    """Section 4.1's normalized stress: the full stress of Eq. 1 divided by the
+    number of node pairs n (n - 1) / 2."""
+    n = np.asarray(x).shape[0]
+    return stress_full(row_ptr, col_idx, x) / (n * (n - 1) / 2)
+
+
+def procrustes(x, y) -> float:
+    """Section 4.1's Procrustes statistic of layout x against reference y:
+    after the best translation, dilation and rotation (reflections are not
+    among the allowed operations), the share of the spread left unmatched,
+    in [0, 1].  Computed the textbook way: centre both layouts, take the SVD
+    of X^T Y; the best proper rotation achieves sigma_1 + s sigma_2 with s the
+    sign of det(U V^T) (Kabsch); the statistic is 1 - that squared over
+    tr(X^T X) tr(Y^T Y)."""
+    X = np.asarray(x, dtype=np.float64)
+    Y = np.asarray(y, dtype=np.float64)
+    X = X - X.mean(axis=0)
+    Y = Y - Y.mean(axis=0)
+    U, S, Vt = np.linalg.svd(X.T @ Y)
+    sgn = 1.0 if np.linalg.det(U @ Vt) >= 0 else -1.0
+    t = S[0] + sgn * S[1]
+    return float(1.0 - t * t / ((X * X).sum() * (Y * Y).sum()))
+
+
 def kmeans_sp(dist, pivots, max_iters: int = 50):
     """k-means sp refinement of max/min pivots (Section 4.1): returns
     (new_pivots[k], assign[n], iterations)."""

@@ -310,4 +310,13 @@ ssm_status ssm_stress(const ssm_csr* g, ssm_terms* t, ssm_prec p, const void* x,
     return fail(SSM_E_INVAL, "unknown stress kind");
 }
 
+ssm_status ssm_procrustes(int32_t n, ssm_prec px, const void* x, ssm_prec py, const void* y, double* out_host,
+                          hipStream_t stream) {
+    if (n < 2) return fail(SSM_E_INVAL, "need n >= 2");
+    if (!x || !y || !out_host) return fail(SSM_E_INVAL, "NULL layout or output");
+    if ((px != SSM_FP64 && px != SSM_FP32) || (py != SSM_FP64 && py != SSM_FP32))
+        return fail(SSM_E_INVAL, "unknown precision");
+    return procrustes(n, px, x, py, y, out_host, stream);
+}
+
 }  // extern "C"

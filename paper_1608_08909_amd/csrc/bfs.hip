@@ -1431,7 +1431,10 @@ __global__ __launch_bounds__(kBfsBlock) void k_select_ell(int n, const int* __re
 template <int W, bool M8>
 static hipError_t launch_select_ell_t(hipStream_t s, int n, const int* rp, const int* ci, const int* ell, int k,
                                       int first, int* pivots, int* m, int* q, int* status) {
-    hipLaunchKernelGGL((k_select_ell<W, M8>), dim3(1), dim3(kBfsBlock), 0, s, n, rp, ci, ell, k, first, pivots, m,
+    int threads = kBfsBlock;
+    const int v = env_int("SSM_SELECT_THREADS");  // tuning override: 256, 512 or 1024
+    if (v == 256 || v == 512) threads = v;
+    hipLaunchKernelGGL((k_select_ell<W, M8>), dim3(1), dim3(threads), 0, s, n, rp, ci, ell, k, first, pivots, m,
                        q, status);
     return hipGetLastError();
 }

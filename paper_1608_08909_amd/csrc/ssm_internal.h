@@ -173,6 +173,10 @@ hipError_t pool_bfs(const PoolGraph* gs, const int2* items, int nitems, int* gq,
 hipError_t pool_pivotmds(const PoolGraph* gs, int count, const int4* gram_items, int ngram, const int2* tiles,
                          int kp_max, int k_max, hipStream_t s);
 
+// ---- quality measures (quality.hip)
+ssm_status procrustes(int32_t n, int32_t px, const void* x, int32_t py, const void* y, double* out_host,
+                      hipStream_t s);
+
 // Deterministic FP64 sum of `count` partials on the device into out (device).
 void launch_sum_partials(const double* partials, int count, double* out, hipStream_t s);
 

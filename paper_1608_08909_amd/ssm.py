@@ -41,7 +41,7 @@ EXPORTS = [
     "ssm_terms_free", "ssm_terms_dims", "ssm_terms_export", "ssm_pivotmds_init",
     "ssm_pivotmds_eig", "ssm_pivotmds_gram", "ssm_majorize", "ssm_majorize_mixed", "ssm_stress", "ssm_last_error",
     "ssm_pool_create", "ssm_pool_destroy", "ssm_pool_usage", "ssm_pool_add", "ssm_pool_prepare", "ssm_pool_sweep",
-    "ssm_pool_stress", "ssm_pool_layout", "ssm_pool_export", "ssm_pool_info", "ssm_pool_remove",
+    "ssm_pool_stress", "ssm_pool_layout", "ssm_pool_export", "ssm_pool_info", "ssm_pool_remove", "ssm_procrustes",
 ]
 
 
@@ -86,6 +86,7 @@ def load(path: str | None = None):
             "ssm_pool_export": (S, [V, I, I, V, V]),
             "ssm_pool_info": (S, [V, I, V]),
             "ssm_pool_remove": (S, [V, I]),
+            "ssm_procrustes": (S, [I, I, V, I, V, V, V]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -289,6 +290,43 @@ def stress(g: DeviceGraph, terms: Terms | None, x: torch.Tensor, kind: int = STR
     _check(load().ssm_stress(g.cref, h, _prec_of(x), _ptr(x), int(kind), ctypes.byref(out), _stream()),
            "ssm_stress")
     return out.value
+
+
+def procrustes(x: torch.Tensor, y: torch.Tensor) -> float:
+    """Procrustes statistic of layout x against reference y (0 = perfect match)."""
+    if x.shape != y.shape or x.dim() != 2 or x.shape[1] != 2:
+        raise ValueError("expected two n x 2 layouts")
+    out = ctypes.c_double()
+    _check(load().ssm_procrustes(int(x.shape[0]), _prec_of(x), _ptr(x), _prec_of(y), _ptr(y), ctypes.byref(out),
+                                 _stream()), "ssm_procrustes")
+    return out.value
+
+
+def normalized_stress(g: DeviceGraph, x: torch.Tensor) -> float:
+    """Full stress s(x) (Eq. 1) divided by the number of node pairs."""
+    return stress(g, None, x, STRESS_FULL) / (g.n * (g.n - 1) / 2)
+
+
+def full_stress_layout(g: DeviceGraph, iters: int, first: int = 0, start_k: int | None = None):
+    """The full-stress reference of Section 4.1: the sparse model with k = n
+    (every node a pivot, so every pair carries weight 1/d^2) swept `iters`
+    times in FP64.  Start: PivotMDS on the first start_k max/min pivots
+    (default min(n, 1024); a prefix of the k = n selection).  Returns (x, terms)."""
+    n = g.n
+    k0 = min(n, 1024) if start_k is None else start_k
+    piv = select_pivots(g, n, first)
+    dist, delta, region = bfs_pivots(g, piv)
+    terms = build_terms(g, piv, dist, delta, region)
+    if k0 == n:
+        x = pivotmds_init(g, terms, FP64)
+    else:
+        p0 = piv[:k0].contiguous()
+        d0, de0, r0 = bfs_pivots(g, p0)
+        t0 = build_terms(g, p0, d0, de0, r0)
+        x = pivotmds_init(g, t0, FP64)
+        del t0, d0
+    majorize(g, terms, x, iters)
+    return x, terms
 
 
 def layout(g: DeviceGraph, k: int, iters: int, prec: int = FP64, first: int = 0, warm: int = 1,

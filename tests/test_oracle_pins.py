@@ -559,3 +559,49 @@ def test_kmeans_sp_fixed_point(g, k):
         assert newp[t] == min(cand)[1]
         taken.add(int(newp[t]))
     assert len(set(newp.tolist())) == k
+
+
+# ----------------------------------------------------------- quality measures
+
+def test_procrustes_closed_forms():
+    rng = np.random.Generator(np.random.PCG64(3))
+    x = rng.normal(size=(40, 2))
+    assert abs(oracle.procrustes(x, x)) < 1e-14
+    # a translated, rotated and dilated copy matches perfectly
+    th = 0.7
+    R = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+    y = 3.5 * x @ R.T + np.array([10.0, -4.0])
+    assert abs(oracle.procrustes(y, x)) < 1e-12
+    assert abs(oracle.procrustes(x, y)) < 1e-12
+    # a reflection is not an allowed operation: for centred axis-aligned
+    # spreads a = sum x^2, b = sum y^2 with sum xy = 0, the mirror image leaves
+    # 1 - ((b - a) / (a + b))^2 = 4ab / (a + b)^2 unmatched
+    c = np.array([[1.0, 0.0], [-1.0, 0.0], [0.0, 2.0], [0.0, -2.0]])
+    m = c * np.array([1.0, -1.0])
+    a, b = 2.0, 8.0
+    assert abs(oracle.procrustes(m, c) - 4 * a * b / (a + b) ** 2) < 1e-15
+    # a layout squeezed onto a line against a round one
+    ring = np.array([[np.cos(2 * np.pi * q / 12), np.sin(2 * np.pi * q / 12)] for q in range(12)])
+    line = ring * np.array([1.0, 0.0])
+    # best match explains sigma_1 = sum cos^2 = 6 of the ring's spread 12 and
+    # the line's spread 6: 1 - 36 / (6 * 12) = 1/2
+    assert abs(oracle.procrustes(line, ring) - 0.5) < 1e-12
+
+
+def test_procrustes_range_and_symmetry():
+    rng = np.random.Generator(np.random.PCG64(5))
+    for _ in range(50):
+        x = rng.normal(size=(25, 2))
+        y = rng.normal(size=(25, 2))
+        p = oracle.procrustes(x, y)
+        assert 0.0 <= p <= 1.0
+        assert abs(p - oracle.procrustes(y, x)) < 1e-12
+
+
+def test_normalized_stress_of_a_path():
+    # a path drawn on a line with unit spacing has zero stress; doubling the
+    # spacing gives sum over pairs (2d - d)^2 / d^2 = C(n, 2) pairs of 1
+    g = G.path(9)
+    x = np.stack([np.arange(9, dtype=np.float64), np.zeros(9)], axis=1)
+    assert oracle.normalized_stress(g.row_ptr, g.col_idx, x) == 0.0
+    assert abs(oracle.normalized_stress(g.row_ptr, g.col_idx, 2 * x) - 1.0) < 1e-15

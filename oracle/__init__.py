@@ -73,6 +73,14 @@ def _load():
                 "orc_stress_sparse": (D, [I, P, P, I, P, P, P, I, P, P]),
                 "orc_stress_full": (D, [I, P, P, P]),
                 "orc_kmeans_sp": (I, [I, I, P, P, I, P, P, P]),
+                "orc_sssp": (I, [I, P, P, P, I, P]),
+                "orc_select_pivots_w": (I, [I, P, P, P, I, I, P, P]),
+                "orc_regions_w": (I, [I, I, P, P, P, P]),
+                "orc_terms_w": (I, [I, P, P, P, I, P, P, P, P, P, P]),
+                "orc_majorize_w": (I, [I, P, P, P, I, P, P, P, P, P, I]),
+                "orc_stress_w": (D, [I, P, P, P, I, P, P, P, P]),
+                "orc_pivotmds_w": (I, [I, I, P, P, P, P]),
+                "orc_rescale_w": (I, [I, P, P, P, P]),
             }
             for name, (res, args) in sig.items():
                 f = getattr(lib, name)
@@ -327,3 +335,124 @@ def layout(n, row_ptr, col_idx, k: int, iters: int, first: int = 0, tol: float =
     x, done = majorize(row_ptr, col_idx, t.pivots, t.dist, t.wtab, t.den, x0, iters, tol,
                        threads=threads)
     return x, t, x0, done
+
+
+# ------------------------------------------------------- weighted graphs
+# Algorithm 1's general input: positive edge lengths len[e] per arc (equal in
+# both directions).  Distances are shortest-path lengths summed from the
+# source outwards in FP64; edge terms carry len^-2; pivot terms are Section
+# 3's with real distances.
+
+def sssp(n, row_ptr, col_idx, length, src: int) -> np.ndarray:
+    """Dijkstra's algorithm: FP64 distances from src (inf where unreached)."""
+    rp, ci, ln = _i32(row_ptr), _i32(col_idx), _f64(length)
+    d = np.empty(n, dtype=np.float64)
+    st = _load().orc_sssp(n, _p(rp), _p(ci), _p(ln), int(src), _p(d))
+    if st != OK:
+        raise OracleError(st, "sssp")
+    return d
+
+
+def select_pivots_w(n, row_ptr, col_idx, length, k: int, first: int = 0):
+    """max/min sp on weighted distances; returns (pivots[k], dist[k][n] FP64)."""
+    rp, ci, ln = _i32(row_ptr), _i32(col_idx), _f64(length)
+    piv = np.empty(k, dtype=np.int32)
+    dist = np.empty((k, n), dtype=np.float64)
+    st = _load().orc_select_pivots_w(n, _p(rp), _p(ci), _p(ln), int(k), int(first), _p(piv), _p(dist))
+    if st != OK:
+        raise OracleError(st, "select_pivots_w")
+    return piv, dist
+
+
+def regions_w(dist):
+    """Rule R1 regions on real distances; returns (delta[n], region[n], size[k])."""
+    dist = _f64(dist)
+    k, n = dist.shape
+    delta = np.empty(n, dtype=np.float64)
+    region = np.empty(n, dtype=np.int32)
+    size = np.empty(k, dtype=np.int32)
+    st = _load().orc_regions_w(n, k, _p(dist), _p(delta), _p(region), _p(size))
+    if st != OK:
+        raise OracleError(st, "regions_w")
+    return delta, region, size
+
+
+def terms_w(row_ptr, col_idx, length, pivots, dist, delta, region):
+    """Per-term adapted weights w[k][n] (0 where no term) and denominators."""
+    rp, ci, ln, pv = _i32(row_ptr), _i32(col_idx), _f64(length), _i32(pivots)
+    dist, delta, region = _f64(dist), _f64(delta), _i32(region)
+    k, n = dist.shape
+    w = np.empty((k, n), dtype=np.float64)
+    den = np.empty(n, dtype=np.float64)
+    st = _load().orc_terms_w(n, _p(rp), _p(ci), _p(ln), k, _p(pv), _p(dist), _p(delta), _p(region), _p(w),
+                             _p(den))
+    if st != OK:
+        raise OracleError(st, "terms_w")
+    return w, den
+
+
+def majorize_w(row_ptr, col_idx, length, pivots, dist, w, den, x, iters: int) -> np.ndarray:
+    rp, ci, ln, pv = _i32(row_ptr), _i32(col_idx), _f64(length), _i32(pivots)
+    dist, w, den = _f64(dist), _f64(w), _f64(den)
+    x = _f64(x).copy()
+    k, n = dist.shape
+    st = _load().orc_majorize_w(n, _p(rp), _p(ci), _p(ln), k, _p(pv), _p(dist), _p(w), _p(den), _p(x), int(iters))
+    if st != OK:
+        raise OracleError(st, "majorize_w")
+    return x
+
+
+def stress_w(row_ptr, col_idx, length, pivots, dist, w, x) -> float:
+    rp, ci, ln, pv = _i32(row_ptr), _i32(col_idx), _f64(length), _i32(pivots)
+    dist, w, x = _f64(dist), _f64(w), _f64(x)
+    k, n = dist.shape
+    return _load().orc_stress_w(n, _p(rp), _p(ci), _p(ln), k, _p(pv), _p(dist), _p(w), _p(x))
+
+
+def pivotmds_w(dist):
+    """PivotMDS on real distances; returns (x[n][2], V[k][2], lambda[2])."""
+    dist = _f64(dist)
+    k, n = dist.shape
+    x = np.empty((n, 2), dtype=np.float64)
+    V = np.empty((k, 2), dtype=np.float64)
+    lam = np.empty(2, dtype=np.float64)
+    st = _load().orc_pivotmds_w(n, k, _p(dist), _p(x), _p(V), _p(lam))
+    if st != OK:
+        raise OracleError(st, "pivotmds_w")
+    return x, V, lam
+
+
+def rescale_w(row_ptr, col_idx, length, x) -> np.ndarray:
+    rp, ci, ln = _i32(row_ptr), _i32(col_idx), _f64(length)
+    x = _f64(x).copy()
+    st = _load().orc_rescale_w(x.shape[0], _p(rp), _p(ci), _p(ln), _p(x))
+    if st != OK:
+        raise OracleError(st, "rescale_w")
+    return x
+
+
+@dataclass
+class WTerms:
+    pivots: np.ndarray
+    dist: np.ndarray
+    delta: np.ndarray
+    region: np.ndarray
+    size: np.ndarray
+    w: np.ndarray
+    den: np.ndarray
+
+
+def preprocess_w(n, row_ptr, col_idx, length, k: int, first: int = 0) -> WTerms:
+    piv, dist = select_pivots_w(n, row_ptr, col_idx, length, k, first)
+    delta, region, size = regions_w(dist)
+    w, den = terms_w(row_ptr, col_idx, length, piv, dist, delta, region)
+    return WTerms(piv, dist, delta, region, size, w, den)
+
+
+def layout_w(n, row_ptr, col_idx, length, k: int, iters: int, first: int = 0):
+    """Algorithm 1 with edge lengths (Jacobi order); returns (x, terms, x0)."""
+    t = preprocess_w(n, row_ptr, col_idx, length, k, first)
+    x0, _, _ = pivotmds_w(t.dist)
+    x0 = rescale_w(row_ptr, col_idx, length, x0)
+    x = majorize_w(row_ptr, col_idx, length, t.pivots, t.dist, t.w, t.den, x0, iters)
+    return x, t, x0

@@ -1,7 +1,8 @@
 /*
  * ssm_oracle.c - plain, slow, serial FP64 CPU oracle of the sparse stress
  * model (Ortmann, Klimenta, Brandes: "A Sparse Stress Model", Section 3,
- * Algorithm 1, Eqs. 1, 3, 5).
+ * Algorithm 1, Eqs. 1, 3, 5), for unit edge lengths and, at the end of the
+ * file, for Algorithm 1's general input with positive edge lengths.
  *
  * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
  * benchmark's CPU-baseline leg load this file.  It shares no code, header,
@@ -655,4 +656,368 @@ int orc_kmeans_sp(int n, int k, const int* D, const int* pivots, int max_iters, 
     *iters = it;
     free(S); free(S2); free(N); free(N2); free(a); free(taken);
     return 0;
+}
+
+/* ------------------------------------------------------------ weighted graphs
+ *
+ * Algorithm 1's general input: every edge has a positive length (len[e] per
+ * arc, equal in both directions).  d_ij is the shortest-path length; the sum
+ * along a path is taken from the source outwards in FP64, so d is the least
+ * solution of d(s) = 0, d(v) = min over neighbours u of (d(u) + len(u, v))
+ * evaluated in floating point.  Edge terms carry w_ij = len^-2 (Eq. 1's
+ * weights with d_ij the edge length); pivot terms are as in Section 3 with
+ * real distances: w'_ip = s / d_ip^2, s = |{ j in R(p) : d_jp <= d_ip / 2 }|,
+ * for every pivot p that is neither i nor a neighbour of i. */
+
+typedef struct { double key; int node; } heap_item;
+
+static void heap_push(heap_item* h, int* size, double key, int node) {
+    int c = (*size)++;
+    h[c].key = key;
+    h[c].node = node;
+    while (c > 0) {
+        int p = (c - 1) / 2;
+        if (h[p].key <= h[c].key) break;
+        heap_item t = h[p]; h[p] = h[c]; h[c] = t;
+        c = p;
+    }
+}
+
+static heap_item heap_pop(heap_item* h, int* size) {
+    heap_item top = h[0];
+    h[0] = h[--(*size)];
+    int c = 0;
+    for (;;) {
+        int l = 2 * c + 1, r = l + 1, m = c;
+        if (l < *size && h[l].key < h[m].key) m = l;
+        if (r < *size && h[r].key < h[m].key) m = r;
+        if (m == c) break;
+        heap_item t = h[m]; h[m] = h[c]; h[c] = t;
+        c = m;
+    }
+    return top;
+}
+
+/* Dijkstra's algorithm with a binary heap (entries left behind by a later
+ * improvement are skipped when popped).  Unreached nodes keep +inf. */
+int orc_sssp(int n, const int* rp, const int* ci, const double* len, int src, double* dist) {
+    heap_item* h = (heap_item*)malloc(sizeof(heap_item) * ((size_t)rp[n] + 1));
+    char* done = (char*)calloc((size_t)n, 1);
+    if (!h || !done) { free(h); free(done); return ORC_NOMEM; }
+    for (int i = 0; i < n; ++i) dist[i] = INFINITY;
+    int size = 0;
+    dist[src] = 0.0;
+    heap_push(h, &size, 0.0, src);
+    while (size > 0) {
+        heap_item it = heap_pop(h, &size);
+        int u = it.node;
+        if (done[u] || it.key != dist[u]) continue;
+        done[u] = 1;
+        for (int e = rp[u]; e < rp[u + 1]; ++e) {
+            int v = ci[e];
+            double nd = dist[u] + len[e];
+            if (nd < dist[v]) {
+                dist[v] = nd;
+                heap_push(h, &size, nd, v);
+            }
+        }
+    }
+    free(h);
+    free(done);
+    return ORC_OK;
+}
+
+/* max/min sp on weighted distances (Section 4.1): pivots[0] = first; each
+ * next pivot is the node with the largest distance to the pivots chosen so
+ * far, lowest id on ties.  dist receives the k rows.  ORC_DISCONNECTED when
+ * a node is unreachable. */
+int orc_select_pivots_w(int n, const int* rp, const int* ci, const double* len, int k, int first,
+                        int* pivots, double* dist) {
+    double* m = (double*)malloc(sizeof(double) * (size_t)n);
+    if (!m) return ORC_NOMEM;
+    for (int i = 0; i < n; ++i) m[i] = INFINITY;
+    int p = first;
+    for (int t = 0; t < k; ++t) {
+        pivots[t] = p;
+        double* row = dist + (size_t)t * n;
+        int st = orc_sssp(n, rp, ci, len, p, row);
+        if (st != ORC_OK) { free(m); return st; }
+        for (int i = 0; i < n; ++i) {
+            if (row[i] == INFINITY) { free(m); return ORC_DISCONNECTED; }
+            if (row[i] < m[i]) m[i] = row[i];
+        }
+        int best = 0;
+        for (int i = 1; i < n; ++i)
+            if (m[i] > m[best]) best = i;
+        p = best;
+    }
+    free(m);
+    return ORC_OK;
+}
+
+static const double* g_delta_sort;
+static int cmp_delta_id(const void* a, const void* b) {
+    int i = *(const int*)a, j = *(const int*)b;
+    double di = g_delta_sort[i], dj = g_delta_sort[j];
+    if (di < dj) return -1;
+    if (di > dj) return 1;
+    return (i > j) - (i < j);
+}
+
+/* Regions by rule R1 on real distances: delta_i = min_t dist[t][i]; the
+ * candidates of i are the ranks at exactly that distance.  Levels are the
+ * distinct delta values in ascending order; in a level the single-candidate
+ * nodes join first, then each tied node joins the candidate with the
+ * smallest (size snapshot, rank). */
+int orc_regions_w(int n, int k, const double* dist, double* delta, int* region, int* size) {
+    int* ncand = (int*)malloc(sizeof(int) * (size_t)n);
+    int* order = (int*)malloc(sizeof(int) * (size_t)n);
+    int* snap = (int*)malloc(sizeof(int) * (size_t)k);
+    if (!ncand || !order || !snap) { free(ncand); free(order); free(snap); return ORC_NOMEM; }
+    for (int i = 0; i < n; ++i) {
+        double best = INFINITY;
+        int cnt = 0;
+        for (int t = 0; t < k; ++t) {
+            double d = dist[(size_t)t * n + i];
+            if (d < best) { best = d; cnt = 1; }
+            else if (d == best) cnt++;
+        }
+        delta[i] = best;
+        ncand[i] = cnt;
+        region[i] = -1;
+        order[i] = i;
+    }
+    g_delta_sort = delta;
+    qsort(order, (size_t)n, sizeof(int), cmp_delta_id);
+    for (int t = 0; t < k; ++t) size[t] = 0;
+    for (int a = 0; a < n;) {
+        int b = a;
+        while (b < n && delta[order[b]] == delta[order[a]]) ++b;   /* level [a, b) */
+        double l = delta[order[a]];
+        for (int q = a; q < b; ++q) {
+            int i = order[q];
+            if (ncand[i] != 1) continue;
+            for (int t = 0; t < k; ++t)
+                if (dist[(size_t)t * n + i] == l) { region[i] = t; size[t]++; break; }
+        }
+        memcpy(snap, size, sizeof(int) * (size_t)k);
+        for (int q = a; q < b; ++q) {
+            int i = order[q];
+            if (ncand[i] == 1) continue;
+            int pick = -1;
+            for (int t = 0; t < k; ++t) {
+                if (dist[(size_t)t * n + i] != l) continue;
+                if (pick < 0 || snap[t] < snap[pick]) pick = t;
+            }
+            region[i] = pick;
+        }
+        for (int q = a; q < b; ++q) {
+            int i = order[q];
+            if (ncand[i] != 1) size[region[i]]++;
+        }
+        a = b;
+    }
+    free(ncand); free(order); free(snap);
+    return ORC_OK;
+}
+
+/* Pivot-term weights w[t][i] (0 where no term exists: p_t = i or p_t a
+ * neighbour of i) and denominators den_i = sum over i's arcs in CSR order of
+ * len^-2, then sum over ranks ascending of w[t][i].  s counts the members j of
+ * R(p_t) with delta_j <= d / 2 by scanning the region's member list. */
+int orc_terms_w(int n, const int* rp, const int* ci, const double* len, int k, const int* pivots,
+                const double* dist, const double* delta, const int* region, double* w, double* den) {
+    int* start = (int*)calloc((size_t)k + 1, sizeof(int));
+    int* members = (int*)malloc(sizeof(int) * (size_t)n);
+    int* fill = (int*)malloc(sizeof(int) * ((size_t)k + 1));
+    if (!start || !members || !fill) { free(start); free(members); free(fill); return ORC_NOMEM; }
+    for (int i = 0; i < n; ++i) start[region[i] + 1]++;
+    for (int t = 0; t < k; ++t) start[t + 1] += start[t];
+    for (int t = 0; t <= k; ++t) fill[t] = start[t];
+    for (int i = 0; i < n; ++i) members[fill[region[i]]++] = i;
+    for (int t = 0; t < k; ++t) {
+        int p = pivots[t];
+        for (int i = 0; i < n; ++i) {
+            double val = 0.0;
+            int adjacent = 0;
+            for (int e = rp[i]; e < rp[i + 1]; ++e) adjacent |= ci[e] == p;
+            if (i != p && !adjacent) {
+                double d = dist[(size_t)t * n + i];
+                int s = 0;
+                for (int q = start[t]; q < start[t + 1]; ++q) s += delta[members[q]] <= d / 2.0;
+                val = (double)s / (d * d);
+            }
+            w[(size_t)t * n + i] = val;
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int e = rp[i]; e < rp[i + 1]; ++e) s += 1.0 / (len[e] * len[e]);
+        for (int t = 0; t < k; ++t) s += w[(size_t)t * n + i];
+        den[i] = s;
+    }
+    free(start); free(members); free(fill);
+    return ORC_OK;
+}
+
+/* Eq. 5 with lengths, one node from `src`: neighbour votes at a positive
+ * distance in CSR order, w_e (x_j + len (x_i - x_j) / r) with w_e = len^-2;
+ * then the zero-distance neighbour votes w_e x_i in CSR order; then pivot
+ * terms by ascending rank, w (x_p + d (x_i - x_p) / r), or w x_p at r = 0. */
+static void update_node_w(int i, const int* rp, const int* ci, const double* len, int n, int k,
+                          const int* pivots, const double* dist, const double* w, const double* den,
+                          const double* src, double* out) {
+    double xi = src[2 * (size_t)i], yi = src[2 * (size_t)i + 1];
+    double nx = 0.0, ny = 0.0;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        int j = ci[e];
+        double dx = xi - src[2 * (size_t)j], dy = yi - src[2 * (size_t)j + 1];
+        double r = sqrt(dx * dx + dy * dy);
+        if (r > 0.0) {
+            double we = 1.0 / (len[e] * len[e]);
+            nx += we * (src[2 * (size_t)j] + (len[e] * dx) / r);
+            ny += we * (src[2 * (size_t)j + 1] + (len[e] * dy) / r);
+        }
+    }
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        int j = ci[e];
+        double dx = xi - src[2 * (size_t)j], dy = yi - src[2 * (size_t)j + 1];
+        double r = sqrt(dx * dx + dy * dy);
+        if (!(r > 0.0)) {
+            double we = 1.0 / (len[e] * len[e]);
+            nx += we * xi;
+            ny += we * yi;
+        }
+    }
+    for (int t = 0; t < k; ++t) {
+        double wt = w[(size_t)t * n + i];
+        if (wt == 0.0) continue;
+        int p = pivots[t];
+        double d = dist[(size_t)t * n + i];
+        double px = src[2 * (size_t)p], py = src[2 * (size_t)p + 1];
+        double dx = xi - px, dy = yi - py;
+        double r = sqrt(dx * dx + dy * dy);
+        double vx = px, vy = py;
+        if (r > 0.0) {
+            vx = px + d * dx / r;
+            vy = py + d * dy / r;
+        }
+        nx += wt * vx;
+        ny += wt * vy;
+    }
+    out[2 * (size_t)i] = nx / den[i];
+    out[2 * (size_t)i + 1] = ny / den[i];
+}
+
+/* `iters` Jacobi sweeps of Eq. 5 with lengths, in place on x (n x 2). */
+int orc_majorize_w(int n, const int* rp, const int* ci, const double* len, int k, const int* pivots,
+                   const double* dist, const double* w, const double* den, double* x, int iters) {
+    double* y = (double*)malloc(sizeof(double) * 2 * (size_t)n);
+    if (!y) return ORC_NOMEM;
+    for (int it = 0; it < iters; ++it) {
+        for (int i = 0; i < n; ++i) update_node_w(i, rp, ci, len, n, k, pivots, dist, w, den, x, y);
+        memcpy(x, y, sizeof(double) * 2 * (size_t)n);
+    }
+    free(y);
+    return ORC_OK;
+}
+
+/* s'(x) of Eq. 3 with lengths: edges (i < j) len^-2 (r - len)^2, then every
+ * pivot term w (r - d)^2, in node order. */
+double orc_stress_w(int n, const int* rp, const int* ci, const double* len, int k, const int* pivots,
+                    const double* dist, const double* w, const double* x) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) {
+        for (int e = rp[i]; e < rp[i + 1]; ++e) {
+            int j = ci[e];
+            if (j <= i) continue;
+            double dx = x[2 * (size_t)i] - x[2 * (size_t)j], dy = x[2 * (size_t)i + 1] - x[2 * (size_t)j + 1];
+            double r = sqrt(dx * dx + dy * dy);
+            s += (r - len[e]) * (r - len[e]) / (len[e] * len[e]);
+        }
+        for (int t = 0; t < k; ++t) {
+            double wt = w[(size_t)t * n + i];
+            if (wt == 0.0) continue;
+            int p = pivots[t];
+            double dx = x[2 * (size_t)i] - x[2 * (size_t)p], dy = x[2 * (size_t)i + 1] - x[2 * (size_t)p + 1];
+            double r = sqrt(dx * dx + dy * dy);
+            double d = dist[(size_t)t * n + i];
+            s += wt * (r - d) * (r - d);
+        }
+    }
+    return s;
+}
+
+/* PivotMDS on real distances: C_it = -1/2 (d^2 - mu_t - nu_i + gamma) as for
+ * hop distances; the rest as orc_pivotmds. */
+int orc_pivotmds_w(int n, int k, const double* dist, double* x, double* V, double* lambda) {
+    if (k < 3) return ORC_INVAL;
+    double* C = (double*)malloc(sizeof(double) * (size_t)n * k);
+    double* mu = (double*)calloc((size_t)k, sizeof(double));
+    double* M = (double*)malloc(sizeof(double) * (size_t)k * k);
+    double* ev = (double*)malloc(sizeof(double) * (size_t)k);
+    double* E = (double*)malloc(sizeof(double) * (size_t)k * k);
+    if (!C || !mu || !M || !ev || !E) { free(C); free(mu); free(M); free(ev); free(E); return ORC_NOMEM; }
+    double gamma = 0.0;
+    for (int t = 0; t < k; ++t) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) { double d = dist[(size_t)t * n + i]; s += d * d; }
+        mu[t] = s / (double)n;
+        gamma += s;
+    }
+    gamma /= (double)n * (double)k;
+    for (int i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int t = 0; t < k; ++t) { double d = dist[(size_t)t * n + i]; s += d * d; }
+        double nu = s / (double)k;
+        for (int t = 0; t < k; ++t) {
+            double d = dist[(size_t)t * n + i];
+            C[(size_t)i * k + t] = -0.5 * (d * d - mu[t] - nu + gamma);
+        }
+    }
+    orc_gram(n, k, C, M);
+    orc_sym_eig(k, M, ev, E);
+    int c0 = -1, c1 = -1;
+    for (int c = 0; c < k; ++c)
+        if (c0 < 0 || ev[c] > ev[c0]) c0 = c;
+    for (int c = 0; c < k; ++c)
+        if (c != c0 && (c1 < 0 || ev[c] > ev[c1])) c1 = c;
+    int cols[2] = {c0, c1};
+    for (int a = 0; a < 2; ++a) {
+        double mx = 0.0;
+        for (int t = 0; t < k; ++t)
+            if (fabs(E[(size_t)t * k + cols[a]]) > mx) mx = fabs(E[(size_t)t * k + cols[a]]);
+        int big = 0;
+        while (big < k - 1 && fabs(E[(size_t)big * k + cols[a]]) < mx * (1.0 - 1e-9)) ++big;
+        double sgn = E[(size_t)big * k + cols[a]] < 0.0 ? -1.0 : 1.0;
+        for (int t = 0; t < k; ++t) V[t * 2 + a] = sgn * E[(size_t)t * k + cols[a]];
+        lambda[a] = ev[cols[a]];
+    }
+    for (int i = 0; i < n; ++i)
+        for (int a = 0; a < 2; ++a) {
+            double s = 0.0;
+            for (int t = 0; t < k; ++t) s += C[(size_t)i * k + t] * V[t * 2 + a];
+            x[(size_t)i * 2 + a] = s;
+        }
+    free(C); free(mu); free(M); free(ev); free(E);
+    return ORC_OK;
+}
+
+/* Rescale with lengths: c = (sum of edge lengths) / (sum of drawn edge
+ * lengths), edges i < j in CSR order. */
+int orc_rescale_w(int n, const int* rp, const int* ci, const double* len, double* x) {
+    double target = 0.0, have = 0.0;
+    for (int i = 0; i < n; ++i)
+        for (int e = rp[i]; e < rp[i + 1]; ++e) {
+            int j = ci[e];
+            if (j <= i) continue;
+            double dx = x[2 * (size_t)i] - x[2 * (size_t)j];
+            double dy = x[2 * (size_t)i + 1] - x[2 * (size_t)j + 1];
+            target += len[e];
+            have += sqrt(dx * dx + dy * dy);
+        }
+    if (have == 0.0) return ORC_INVAL;
+    double c = target / have;
+    for (size_t q = 0; q < 2 * (size_t)n; ++q) x[q] *= c;
+    return ORC_OK;
 }

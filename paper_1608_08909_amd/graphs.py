@@ -335,3 +335,20 @@ def make_request_graph(spec: dict) -> CSR:
     if spec["family"] == "tree":
         return tree_plus(spec["n"], spec["seed"])
     raise ValueError(spec)
+
+
+def edge_lengths(g: CSR, seed: int, lo: float = 0.5, hi: float = 2.0, integer: bool = False) -> np.ndarray:
+    """Positive edge lengths per arc (float64 [2m]), the same on both arcs of
+    an edge: uniform in [lo, hi) (PCG64), or uniform integers in
+    [lo, hi] when `integer` (many equal distances, hence region ties)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    src = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.row_ptr))
+    dst = g.col_idx.astype(np.int64)
+    a, b = np.minimum(src, dst), np.maximum(src, dst)
+    key = a * g.n + b
+    uniq, inv = np.unique(key, return_inverse=True)
+    if integer:
+        vals = rng.integers(int(lo), int(hi) + 1, size=uniq.size).astype(np.float64)
+    else:
+        vals = lo + (hi - lo) * rng.random(uniq.size)
+    return vals[inv]

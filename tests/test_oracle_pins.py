@@ -605,3 +605,112 @@ def test_normalized_stress_of_a_path():
     x = np.stack([np.arange(9, dtype=np.float64), np.zeros(9)], axis=1)
     assert oracle.normalized_stress(g.row_ptr, g.col_idx, x) == 0.0
     assert abs(oracle.normalized_stress(g.row_ptr, g.col_idx, 2 * x) - 1.0) < 1e-15
+
+
+# ---------------------------------------------------------- weighted graphs
+
+def _bellman_ford(n, rp, ci, ln, src):
+    """Value iteration to the least fixed point of d(v) = min_u d(u) + len."""
+    d = np.full(n, np.inf)
+    d[src] = 0.0
+    srcs = np.repeat(np.arange(n), np.diff(rp))
+    while True:
+        cand = d[srcs] + ln
+        nd = d.copy()
+        np.minimum.at(nd, ci, cand)
+        if np.array_equal(nd, d):
+            return d
+        d = nd
+
+
+@pytest.mark.parametrize("g,seed,integer", [(G.grid(9, 11), 1, False), (G.rgg(400, 3), 2, False),
+                                            (G.tree_plus(300, 4), 3, True), (G.grid(7, 7), 5, True)])
+def test_sssp_is_the_least_fixed_point(g, seed, integer):
+    ln = G.edge_lengths(g, seed, 1 if integer else 0.5, 4 if integer else 2.0, integer)
+    for src in (0, g.n // 2, g.n - 1):
+        assert np.array_equal(oracle.sssp(g.n, g.row_ptr, g.col_idx, ln, src),
+                              _bellman_ford(g.n, g.row_ptr, g.col_idx, ln, src))
+
+
+def test_weighted_path_closed_form():
+    g = G.path(6)
+    steps = np.array([0.5, 1.25, 2.0, 0.75, 3.5])  # dyadic: every prefix sum is exact
+    ln = np.empty(g.col_idx.size)
+    for i in range(g.n):
+        for e in range(g.row_ptr[i], g.row_ptr[i + 1]):
+            ln[e] = steps[min(i, g.col_idx[e])]
+    pref = np.concatenate([[0.0], np.cumsum(steps)])
+    assert np.array_equal(oracle.sssp(g.n, g.row_ptr, g.col_idx, ln, 0), pref)
+    piv, dist = oracle.select_pivots_w(g.n, g.row_ptr, g.col_idx, ln, 3, 0)
+    # farthest from 0 is node 5 (8.0); then the node maximizing min(d0, d5):
+    # node 3 (min(3.75, 4.25)) against node 2 (min(1.75, 6.25))
+    assert list(piv) == [0, 5, 3]
+
+
+def test_weighted_regions_tie_rule():
+    # path 0 - 1 - 2 with lengths 1.5: node 1 is tied between pivots 0 and 2;
+    # both regions hold one node at its level, so the lower rank wins
+    g = G.path(3)
+    ln = np.full(g.col_idx.size, 1.5)
+    piv, dist = oracle.select_pivots_w(g.n, g.row_ptr, g.col_idx, ln, 2, 0)
+    assert list(piv) == [0, 2]
+    delta, region, size = oracle.regions_w(dist)
+    assert list(region) == [0, 0, 1] and list(size) == [2, 1] and list(delta) == [0.0, 1.5, 0.0]
+
+
+@pytest.mark.parametrize("g,k", [(G.grid(9, 11), 7), (G.tree_plus(300, 2), 17), (G.rgg(500, 4), 25),
+                                 (G.cycle(17), 4)])
+def test_unit_lengths_reproduce_the_unweighted_model(g, k):
+    ln = np.ones(g.col_idx.size)
+    T = oracle.preprocess(g.n, g.row_ptr, g.col_idx, k)
+    W = oracle.preprocess_w(g.n, g.row_ptr, g.col_idx, ln, k)
+    assert np.array_equal(W.pivots, T.pivots)
+    assert np.array_equal(W.dist, T.dist.astype(np.float64))
+    assert np.array_equal(W.region, T.region)
+    assert np.array_equal(W.delta, T.delta.astype(np.float64))
+    wref = np.take_along_axis(T.wtab, T.dist, axis=1)  # w'(t, d_ti) from the table
+    assert np.array_equal(W.w, wref)
+    assert np.array_equal(W.den, T.den)
+    x0 = oracle.initial_layout(g.row_ptr, g.col_idx, T)
+    xa, _ = oracle.majorize(g.row_ptr, g.col_idx, T.pivots, T.dist, T.wtab, T.den, x0, 5)
+    xb = oracle.majorize_w(g.row_ptr, g.col_idx, ln, W.pivots, W.dist, W.w, W.den, x0, 5)
+    assert np.array_equal(xa, xb)
+    sa = oracle.stress_sparse(g.row_ptr, g.col_idx, T.pivots, T.dist, T.wtab, xa)
+    sb = oracle.stress_w(g.row_ptr, g.col_idx, ln, W.pivots, W.dist, W.w, xb)
+    assert abs(sa - sb) <= 1e-12 * sa
+
+
+def test_weights_by_definition_and_power_of_two_scaling():
+    g = G.rgg(300, 6)
+    ln = G.edge_lengths(g, 7)
+    k = 12
+    W = oracle.preprocess_w(g.n, g.row_ptr, g.col_idx, ln, k)
+    # w' and den straight from the definitions (all pairs, numpy)
+    adj = np.zeros((g.n, g.n), dtype=bool)
+    src = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    adj[src, g.col_idx] = True
+    for t in range(k):
+        p = W.pivots[t]
+        d = W.dist[t]
+        s = ((W.region[None, :] == t) & (W.delta[None, :] <= d[:, None] / 2)).sum(axis=1)
+        with np.errstate(divide="ignore"):  # d = 0 at the pivot itself, masked out
+            want = np.where((np.arange(g.n) != p) & ~adj[:, p], s / (d * d), 0.0)
+        assert np.array_equal(W.w[t], want)
+    # den: the arcs' len^-2 in CSR order, then the ranks in order
+    den = np.array([sum(1.0 / (ln[e] * ln[e]) for e in range(g.row_ptr[i], g.row_ptr[i + 1])) for i in range(g.n)])
+    for i in range(g.n):
+        s = den[i]
+        for t in range(k):
+            s += W.w[t, i]
+        assert s == W.den[i]
+    # lengths times 4: distances times 4, same pivots and regions, weights
+    # and denominators divided by 16, layouts times 4 -- all exact
+    W4 = oracle.preprocess_w(g.n, g.row_ptr, g.col_idx, 4 * ln, k)
+    assert np.array_equal(W4.pivots, W.pivots) and np.array_equal(W4.region, W.region)
+    assert np.array_equal(W4.dist, 4 * W.dist)
+    assert np.array_equal(W4.w, W.w / 16) and np.array_equal(W4.den, W.den / 16)
+    x0, _, _ = oracle.pivotmds_w(W.dist)
+    x0 = oracle.rescale_w(g.row_ptr, g.col_idx, ln, x0)
+    x = oracle.majorize_w(g.row_ptr, g.col_idx, ln, W.pivots, W.dist, W.w, W.den, x0, 10)
+    x4 = oracle.majorize_w(g.row_ptr, g.col_idx, 4 * ln, W4.pivots, W4.dist, W4.w, W4.den, 4 * x0, 10)
+    assert np.array_equal(x4, 4 * x)

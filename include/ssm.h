@@ -191,6 +191,56 @@ ssm_status ssm_majorize_mixed(const ssm_csr* g, ssm_terms* t, double* x64, float
 ssm_status ssm_stress(const ssm_csr* g, ssm_terms* t, ssm_prec p, const void* x,
                       ssm_stress_kind kind, double* out_host, hipStream_t stream);
 
+/* ---- Graphs with edge lengths (Algorithm 1's general input) ----------
+ *
+ * len (device, [nnz] doubles): a positive length per arc, equal on both arcs
+ * of an edge.  d_ij is the shortest-path length, summed from the source
+ * outwards in FP64 (the least solution of d(s) = 0, d(v) = min over
+ * neighbours u of d(u) + len(u, v), exactly as Dijkstra's algorithm finds
+ * it).  Edge terms carry w_ij = len^-2; a pivot term (i, p) exists for every
+ * pivot p that is neither i nor a neighbour of i, with Section 3's weight
+ * w'_ip = s / d_ip^2, s = |{ j in R(p) : d_jp <= d_ip / 2 }|, one weight per
+ * (pivot, node).  Regions follow rule R1 with levels at the distinct values
+ * of delta.  Unit lengths give the unweighted model's pivots, regions,
+ * weights and FP64 sweeps exactly. */
+typedef struct ssm_wterms ssm_wterms; /* opaque, library-owned device state */
+
+/* max/min sp on lengths (Section 4.1): pivots[0] = first, each next pivot
+ * the node farthest from the chosen ones (lowest id on ties); dist (may be
+ * NULL) receives the k distance rows [k][n].  SSM_E_DISCONNECTED if a node
+ * is unreachable.  Synchronizes. */
+ssm_status ssm_select_pivots_w(const ssm_csr* g, const double* len, int32_t k, int32_t first, int32_t* pivots,
+                               double* dist, hipStream_t stream);
+/* The k distance rows [k][n] of the given pivots (one label-correcting
+ * search per pivot).  Synchronizes. */
+ssm_status ssm_sssp_pivots(const ssm_csr* g, const double* len, int32_t k, const int32_t* pivots, double* dist,
+                           hipStream_t stream);
+/* Regions, per-term weights and denominators (Section 3 with lengths) into a
+ * new handle (copies pivots and dist).  Synchronizes. */
+ssm_status ssm_build_terms_w(const ssm_csr* g, const double* len, int32_t k, const int32_t* pivots,
+                             const double* dist, ssm_wterms** out, hipStream_t stream);
+void ssm_wterms_free(ssm_wterms* t);
+/* Copies delta [n], region [n], weights [k][n] and denominators [n] to host
+ * buffers (each may be NULL). */
+ssm_status ssm_wterms_export(const ssm_wterms* t, double* delta_host, int32_t* region_host, double* w_host,
+                             double* den_host);
+/* PivotMDS on the real distances, then the rescale to the summed edge
+ * lengths (Algorithm 1's initialisation).  Synchronizes. */
+ssm_status ssm_pivotmds_init_w(const ssm_csr* g, const double* len, const ssm_wterms* t, ssm_prec p, void* x,
+                               hipStream_t stream);
+/* iters Jacobi sweeps of Eq. 5 with lengths: FP64 in the oracle's order
+ * (positive-distance neighbour votes in CSR order, the zero-distance ones,
+ * then pivot terms by rank) or FP32 in displacement form.  Asynchronous. */
+ssm_status ssm_majorize_w(const ssm_csr* g, const double* len, ssm_wterms* t, ssm_prec p, void* x, int32_t iters,
+                          hipStream_t stream);
+/* The first `warm` sweeps in FP64 on x64, rounded into x32, the rest in FP32
+ * (as ssm_majorize_mixed).  Asynchronous. */
+ssm_status ssm_majorize_mixed_w(const ssm_csr* g, const double* len, ssm_wterms* t, double* x64, float* x32,
+                                int32_t iters, int32_t warm, hipStream_t stream);
+/* s'(x) of Eq. 3 with lengths in FP64 into out_host[0].  Synchronizes. */
+ssm_status ssm_stress_w(const ssm_csr* g, const double* len, const ssm_wterms* t, ssm_prec p, const void* x,
+                        double* out_host, hipStream_t stream);
+
 /* Procrustes statistic of layout x against the reference layout y (both
  * n x 2, interleaved, of precision px / py): the share of y's spread that x
  * misses after the best translation, rotation and dilation (no reflection),

@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libssm.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["api.hip", "bfs.hip", "terms.hip", "pmds.hip", "sweep.hip", "kmeans.hip", "pool.hip", "quality.hip"]
+SOURCES = ["api.hip", "bfs.hip", "terms.hip", "pmds.hip", "sweep.hip", "kmeans.hip", "pool.hip", "quality.hip", "wgraph.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -78,6 +78,12 @@ __device__ __forceinline__ double centred(int d, double mu_t, double nu_i, doubl
     return -0.5 * (dd * dd - mu_t - nu_i + gamma);
 }
 
+// The same for a real distance d (graphs with edge lengths).
+__device__ __forceinline__ double centred_d(double d, double mu_t, double nu_i, double gamma) {
+#pragma clang fp contract(off)
+    return -0.5 * (d * d - mu_t - nu_i + gamma);
+}
+
 constexpr int kGramSub = 8;   // nodes staged per LDS round (two K-steps of 4)
 constexpr int kGramTPW = 8;   // output tiles per wave
 constexpr int kGramWaves = 4;
@@ -113,10 +119,18 @@ __device__ __forceinline__ void pmds_gram_body(int c, int grp, int n, int k, int
 #pragma unroll
     for (int j = 0; j < kGramTPW; ++j) acc[j] = (dbl4){0.0, 0.0, 0.0, 0.0};
     const int i_begin = c * chunk, i_end = min(n, i_begin + chunk);
-    const int nwords = kpad / VEC;
+    const int nwords = VEC > 0 ? kpad / VEC : 0;
     __syncthreads();
     for (int i0 = i_begin; i0 < i_end; i0 += kGramSub) {
-        // stage C for nodes i0 .. i0 + kGramSub - 1 (zero past n and past k)
+        // stage C for nodes i0 .. i0 + kGramSub - 1 (zero past n and past k);
+        // VEC == 0: dpk holds real distance rows [k][n] (FP64)
+        if constexpr (VEC == 0) {
+            const double* dd = (const double*)dpk;
+            for (int q = threadIdx.x; q < kGramSub * kp; q += blockDim.x) {
+                const int r = q % kGramSub, t = q / kGramSub, i = i0 + r;
+                Cs[r * kp + t] = (i < i_end && t < k) ? centred_d(dd[(size_t)t * n + i], smu[t], nu[i], gamma) : 0.0;
+            }
+        } else {
         for (int q = threadIdx.x; q < kGramSub * nwords; q += blockDim.x) {
             int r = q % kGramSub, b = q / kGramSub;
             int i = i0 + r;
@@ -136,6 +150,7 @@ __device__ __forceinline__ void pmds_gram_body(int c, int grp, int n, int k, int
         for (int q = threadIdx.x; q < kGramSub * (kp - kpad); q += blockDim.x) {
             int r = q / (kp - kpad), t = kpad + q % (kp - kpad);
             Cs[r * kp + t] = 0.0;
+        }
         }
         __syncthreads();
 #pragma unroll
@@ -976,6 +991,200 @@ hipError_t pool_pivotmds(const PoolGraph* gs, int count, const int4* gram_items,
     hipLaunchKernelGGL(k_pool_eig, dim3(count), dim3(kEigThreads), eig_lds_bytes(k_max), s, gs);
     hipLaunchKernelGGL(k_pool_project, dim3(count), dim3(1024), 0, s, gs);
     return hipGetLastError();
+}
+
+// ------------------------------------------------- graphs with edge lengths
+
+// colsum[t] = sum_i d_ti^2 for real distances (block t).
+__global__ __launch_bounds__(256) void k_wpmds_colsum(int n, const double* __restrict__ dist,
+                                                      double* __restrict__ colsum) {
+    const int t = blockIdx.x;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double d = dist[(size_t)t * n + i];
+        s += d * d;
+    }
+    __shared__ double red[256 / kWave];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) colsum[t] = s;
+}
+
+__global__ void k_wpmds_mu(int n, int k, const double* __restrict__ colsum, double* __restrict__ mu,
+                           double* __restrict__ stats) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        double total = 0.0;
+        for (int t = 0; t < k; ++t) {
+            mu[t] = colsum[t] / (double)n;
+            total += colsum[t];
+        }
+        stats[0] = total / ((double)n * (double)k);
+    }
+}
+
+__global__ void k_wpmds_nu(int n, int k, const double* __restrict__ dist, double* __restrict__ nu) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int t = 0; t < k; ++t) {
+            const double d = dist[(size_t)t * n + i];
+            s += d * d;
+        }
+        nu[i] = s / (double)k;
+    }
+}
+
+__global__ void k_wpmds_project(int n, int k, const double* __restrict__ dist, const double* __restrict__ mu,
+                                const double* __restrict__ nu, const double* __restrict__ stats,
+                                const double* __restrict__ V, double2* __restrict__ x) {
+#pragma clang fp contract(off)
+    const double gamma = stats[0];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        double s0 = 0.0, s1 = 0.0;
+        const double nui = nu[i];
+        for (int t = 0; t < k; ++t) {
+            const double c = centred_d(dist[(size_t)t * n + i], mu[t], nui, gamma);
+            s0 += c * V[2 * t];
+            s1 += c * V[2 * t + 1];
+        }
+        x[i] = make_double2(s0, s1);
+    }
+}
+
+// Per-block partials of the drawn edge lengths and of the edge lengths
+// (edges j > i): partials[b] and partials[nb + b].
+__global__ __launch_bounds__(256) void k_wpmds_edgelen(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                       const double* __restrict__ len, const double2* __restrict__ x,
+                                                       double* __restrict__ partials) {
+    double have = 0.0, target = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double2 xi = x[i];
+        for (int e = rp[i]; e < rp[i + 1]; ++e) {
+            const int j = ci[e];
+            if (j <= i) continue;
+            const double2 xj = x[j];
+            const double dx = xi.x - xj.x, dy = xi.y - xj.y;
+            have += sqrt(dx * dx + dy * dy);
+            target += len[e];
+        }
+    }
+    __shared__ double red[256 / kWave];
+    have = block_sum(have, red);
+    target = block_sum(target, red);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = have;
+        partials[gridDim.x + blockIdx.x] = target;
+    }
+}
+
+// x_out = c x, c = (summed lengths) / (summed drawn lengths); flag if that is 0.
+template <typename T2>
+__global__ void k_wpmds_scale(int n, const double2* __restrict__ x, const double* __restrict__ sums,
+                              T2* __restrict__ out, int* flag) {
+    const double have = sums[0], target = sums[1];
+    if (have == 0.0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) flag[0] = 1;
+        return;
+    }
+    const double c = target / have;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double2 v = x[i];
+        out[i].x = v.x * c;
+        out[i].y = v.y * c;
+    }
+}
+
+// sums[0], sums[1] = the two partial arrays summed in block order.
+__global__ void k_wpmds_sum2(int nb, const double* __restrict__ partials, double* __restrict__ sums) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int q = 0; q < nb; ++q) {
+            a += partials[q];
+            b += partials[nb + q];
+        }
+        sums[0] = a;
+        sums[1] = b;
+    }
+}
+
+ssm_status pivotmds_w(const ssm_csr* g, const double* len, int k, const double* dist, ssm_prec p, void* x,
+                      hipStream_t s) {
+    const int n = g->n;
+    if (k > 1024) return fail(SSM_E_RANGE, "PivotMDS supports k <= 1024");
+    const int kp = div_up(k, 16) * 16, T = kp / 16;
+    std::vector<int2> htiles;
+    for (int a = 0; a < T; ++a)
+        for (int b = a; b < T; ++b) htiles.push_back(make_int2(a, b));
+    const int ntiles = (int)htiles.size();
+    const int ngroups = div_up(ntiles, kGramWaves * kGramTPW);
+    int nchunks = std::max(1, std::min(div_up(n, 1024), std::max(1, 4 * num_cus() / ngroups)));
+    const int chunk = div_up(div_up(n, nchunks), kGramSub) * kGramSub;
+    nchunks = div_up(n, chunk);
+    const int eb = std::min(div_up(n, 256), 2048);
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        const size_t o = off;
+        off += (b + 255) & ~(size_t)255;
+        return o;
+    };
+    const size_t o_cs = take(sizeof(double) * k), o_mu = take(sizeof(double) * k), o_nu = take(sizeof(double) * n),
+                 o_st = take(sizeof(double) * 4), o_M = take(sizeof(double) * (size_t)k * k),
+                 o_part = take(sizeof(double) * (size_t)nchunks * ntiles * 256), o_tiles = take(sizeof(int2) * ntiles),
+                 o_eig = take(sizeof(double) * (2 * (size_t)k + 2)), o_it = take(sizeof(int) * 2),
+                 o_x = take(sizeof(double2) * n), o_ep = take(sizeof(double) * 2 * (size_t)eb),
+                 o_sums = take(sizeof(double) * 2);
+    char* ws = nullptr;
+    ssm_status st = salloc((void**)&ws, off);
+    if (st != SSM_OK) return st;
+    double* colsum = (double*)(ws + o_cs);
+    double* mu = (double*)(ws + o_mu);
+    double* nu = (double*)(ws + o_nu);
+    double* stats = (double*)(ws + o_st);
+    double* M = (double*)(ws + o_M);
+    double* part = (double*)(ws + o_part);
+    int2* tiles = (int2*)(ws + o_tiles);
+    double* eig = (double*)(ws + o_eig);
+    int* its = (int*)(ws + o_it);
+    int* flag = its + 1;
+    double2* xd = (double2*)(ws + o_x);
+    double* epart = (double*)(ws + o_ep);
+    double* sums = (double*)(ws + o_sums);
+    hipError_t e = hipMemcpyAsync(tiles, htiles.data(), sizeof(int2) * ntiles, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(its, 0, sizeof(int) * 2, s);
+    if (e == hipSuccess) {
+        const int gn = std::min(div_up(n, 256), 8192);
+        hipLaunchKernelGGL(k_wpmds_colsum, dim3(k), dim3(256), 0, s, n, dist, colsum);
+        hipLaunchKernelGGL(k_wpmds_mu, dim3(1), dim3(64), 0, s, n, k, colsum, mu, stats);
+        hipLaunchKernelGGL(k_wpmds_nu, dim3(gn), dim3(256), 0, s, n, k, dist, nu);
+        hipLaunchKernelGGL((k_pmds_gram<double, 0>), dim3(nchunks, ngroups), dim3(256),
+                           sizeof(double) * ((size_t)kGramSub * kp + kp), s, n, k, kp, kp, chunk,
+                           (const uint4*)dist, mu, nu, stats, tiles, ntiles, part);
+        hipLaunchKernelGGL(k_pmds_gram_reduce, dim3(std::min(div_up((long long)ntiles * 256, 256), 4096)), dim3(256),
+                           0, s, k, nchunks, ntiles, tiles, part, M);
+        const size_t elds = eig_lds_bytes(k);
+        if (k <= kEigRows * (kEigThreads / kWave) && k <= kEigCols * kWave) {
+            hipLaunchKernelGGL(k_pmds_eig<true>, dim3(1), dim3(kEigThreads), elds, s, k, M, 1e-13, 20000, eig, its);
+        } else {
+            if (elds > 64 * 1024)
+                (void)hipFuncSetAttribute((const void*)k_pmds_eig<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          (int)elds);
+            hipLaunchKernelGGL(k_pmds_eig<false>, dim3(1), dim3(kEigThreads), elds, s, k, M, 1e-13, 20000, eig, its);
+        }
+        hipLaunchKernelGGL(k_wpmds_project, dim3(gn), dim3(256), 0, s, n, k, dist, mu, nu, stats, eig, xd);
+        hipLaunchKernelGGL(k_wpmds_edgelen, dim3(eb), dim3(256), 0, s, n, g->row_ptr, g->col_idx, len, xd, epart);
+        hipLaunchKernelGGL(k_wpmds_sum2, dim3(1), dim3(64), 0, s, eb, epart, sums);
+        if (p == SSM_FP64)
+            hipLaunchKernelGGL(k_wpmds_scale<double2>, dim3(gn), dim3(256), 0, s, n, xd, sums, (double2*)x, flag);
+        else
+            hipLaunchKernelGGL(k_wpmds_scale<float2>, dim3(gn), dim3(256), 0, s, n, xd, sums, (float2*)x, flag);
+        e = hipGetLastError();
+    }
+    int hflag = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipStreamSynchronize(s);
+    sfree(ws);
+    if (e != hipSuccess) return hip_fail(e, "PivotMDS (edge lengths)");
+    if (hflag) return fail(SSM_E_INVAL, "PivotMDS layout has zero total edge length; cannot rescale");
+    return SSM_OK;
 }
 
 }  // namespace ssm

@@ -173,6 +173,14 @@ hipError_t pool_bfs(const PoolGraph* gs, const int2* items, int nitems, int* gq,
 hipError_t pool_pivotmds(const PoolGraph* gs, int count, const int4* gram_items, int ngram, const int2* tiles,
                          int kp_max, int k_max, hipStream_t s);
 
+// ---- graphs with edge lengths (wgraph.hip; PivotMDS in pmds.hip)
+ssm_status pivotmds_w(const ssm_csr* g, const double* len, int k, const double* dist, ssm_prec p, void* x,
+                      hipStream_t s);
+ssm_status select_pivots_w(const ssm_csr* g, const double* len, int32_t k, int32_t first, int32_t* pivots,
+                           hipStream_t s);
+ssm_status sssp_rows(const ssm_csr* g, const double* len, int32_t k, const int32_t* pivots, double* dist,
+                     hipStream_t s);
+
 // ---- quality measures (quality.hip)
 ssm_status procrustes(int32_t n, int32_t px, const void* x, int32_t py, const void* y, double* out_host,
                       hipStream_t s);

@@ -42,6 +42,8 @@ EXPORTS = [
     "ssm_pivotmds_eig", "ssm_pivotmds_gram", "ssm_majorize", "ssm_majorize_mixed", "ssm_stress", "ssm_last_error",
     "ssm_pool_create", "ssm_pool_destroy", "ssm_pool_usage", "ssm_pool_add", "ssm_pool_prepare", "ssm_pool_sweep",
     "ssm_pool_stress", "ssm_pool_layout", "ssm_pool_export", "ssm_pool_info", "ssm_pool_remove", "ssm_procrustes",
+    "ssm_select_pivots_w", "ssm_sssp_pivots", "ssm_build_terms_w", "ssm_wterms_free", "ssm_wterms_export",
+    "ssm_pivotmds_init_w", "ssm_majorize_w", "ssm_majorize_mixed_w", "ssm_stress_w",
 ]
 
 
@@ -87,6 +89,15 @@ def load(path: str | None = None):
             "ssm_pool_info": (S, [V, I, V]),
             "ssm_pool_remove": (S, [V, I]),
             "ssm_procrustes": (S, [I, I, V, I, V, V, V]),
+            "ssm_select_pivots_w": (S, [P, V, I, I, V, V, V]),
+            "ssm_sssp_pivots": (S, [P, V, I, V, V, V]),
+            "ssm_build_terms_w": (S, [P, V, I, V, V, ctypes.POINTER(V), V]),
+            "ssm_wterms_free": (None, [V]),
+            "ssm_wterms_export": (S, [V, V, V, V, V]),
+            "ssm_pivotmds_init_w": (S, [P, V, V, I, V, V]),
+            "ssm_majorize_w": (S, [P, V, V, I, V, I, V]),
+            "ssm_majorize_mixed_w": (S, [P, V, V, V, V, I, I, V]),
+            "ssm_stress_w": (S, [P, V, V, I, V, V, V]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -446,3 +457,96 @@ class Pool:
 
     def remove(self, slot: int):
         _check(self._lib.ssm_pool_remove(self.handle, int(slot)), "ssm_pool_remove")
+
+
+# ------------------------------------------------------- graphs with edge lengths
+
+class WTerms:
+    """Handle of ssm_build_terms_w (regions, per-term weights, denominators)."""
+
+    def __init__(self, handle: int, graph: DeviceGraph, k: int):
+        self.handle, self.graph, self.k = handle, graph, k
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            try:
+                load().ssm_wterms_free(self.handle)
+            except Exception:
+                pass
+            self.handle = None
+
+    def export(self):
+        import numpy as np
+        n, k = self.graph.n, self.k
+        delta = np.empty(n, dtype=np.float64)
+        region = np.empty(n, dtype=np.int32)
+        w = np.empty((k, n), dtype=np.float64)
+        den = np.empty(n, dtype=np.float64)
+        _check(load().ssm_wterms_export(self.handle, _hptr(delta), _hptr(region), _hptr(w), _hptr(den)),
+               "ssm_wterms_export")
+        return {"delta": delta, "region": region, "w": w, "den": den}
+
+
+def select_pivots_w(g: DeviceGraph, length: torch.Tensor, k: int, first: int = 0, with_dist: bool = False):
+    piv = torch.empty(k, dtype=torch.int32, device="cuda")
+    dist = torch.empty(k, g.n, dtype=torch.float64, device="cuda") if with_dist else None
+    _check(load().ssm_select_pivots_w(g.cref, _ptr(length), k, first, _ptr(piv), _ptr(dist), _stream()),
+           "ssm_select_pivots_w")
+    return (piv, dist) if with_dist else piv
+
+
+def sssp_pivots(g: DeviceGraph, length: torch.Tensor, pivots: torch.Tensor) -> torch.Tensor:
+    k = pivots.numel()
+    dist = torch.empty(k, g.n, dtype=torch.float64, device="cuda")
+    _check(load().ssm_sssp_pivots(g.cref, _ptr(length), k, _ptr(pivots), _ptr(dist), _stream()), "ssm_sssp_pivots")
+    return dist
+
+
+def build_terms_w(g: DeviceGraph, length: torch.Tensor, pivots: torch.Tensor, dist: torch.Tensor) -> WTerms:
+    k = pivots.numel()
+    h = ctypes.c_void_p()
+    _check(load().ssm_build_terms_w(g.cref, _ptr(length), k, _ptr(pivots), _ptr(dist), ctypes.byref(h), _stream()),
+           "ssm_build_terms_w")
+    return WTerms(h.value, g, k)
+
+
+def pivotmds_init_w(g: DeviceGraph, length: torch.Tensor, terms: WTerms, prec: int = FP64) -> torch.Tensor:
+    x = _xtensor(g.n, prec)
+    _check(load().ssm_pivotmds_init_w(g.cref, _ptr(length), terms.handle, prec, _ptr(x), _stream()),
+           "ssm_pivotmds_init_w")
+    return x
+
+
+def majorize_w(g: DeviceGraph, length: torch.Tensor, terms: WTerms, x: torch.Tensor, iters: int):
+    _check(load().ssm_majorize_w(g.cref, _ptr(length), terms.handle, _prec_of(x), _ptr(x), int(iters), _stream()),
+           "ssm_majorize_w")
+    return x
+
+
+def majorize_mixed_w(g: DeviceGraph, length: torch.Tensor, terms: WTerms, x64: torch.Tensor, iters: int,
+                     warm: int = 1) -> torch.Tensor:
+    x32 = _xtensor(g.n, FP32)
+    _check(load().ssm_majorize_mixed_w(g.cref, _ptr(length), terms.handle, _ptr(x64), _ptr(x32), int(iters),
+                                       int(warm), _stream()), "ssm_majorize_mixed_w")
+    return x32
+
+
+def stress_w(g: DeviceGraph, length: torch.Tensor, terms: WTerms, x: torch.Tensor) -> float:
+    out = ctypes.c_double()
+    _check(load().ssm_stress_w(g.cref, _ptr(length), terms.handle, _prec_of(x), _ptr(x), ctypes.byref(out),
+                               _stream()), "ssm_stress_w")
+    return out.value
+
+
+def layout_w(g: DeviceGraph, length: torch.Tensor, k: int, iters: int, prec: int = FP64, first: int = 0,
+             warm: int = 1):
+    """Algorithm 1 with edge lengths on the device; returns (x, terms, pivots, dist)."""
+    piv = select_pivots_w(g, length, k, first)
+    dist = sssp_pivots(g, length, piv)
+    terms = build_terms_w(g, length, piv, dist)
+    x = pivotmds_init_w(g, length, terms, FP64)
+    if prec == FP32:
+        x = majorize_mixed_w(g, length, terms, x, iters, warm)
+    else:
+        majorize_w(g, length, terms, x, iters)
+    return x, terms, piv, dist

@@ -38,6 +38,7 @@ struct ssm_wterms {
 namespace ssm {
 
 constexpr int kSsspBlock = 1024;
+constexpr int kSsspLanes = 8;  // lanes per frontier node in the search
 constexpr unsigned long long kInfBits = 0x7FF0000000000000ull;  // +inf; non-negative doubles order as their bits
 
 __device__ __forceinline__ double ld_dist(const unsigned long long* D, int v) {
@@ -68,12 +69,14 @@ __device__ void sssp_body(int n, const int* __restrict__ rp, const int* __restri
     int r = s_round, cnt = 1;
     int* cur = qa;
     int* nxt = qb;
+    // kSsspLanes lanes per frontier node, each over every kSsspLanes-th arc
+    const int sub = threadIdx.x % kSsspLanes, grp = threadIdx.x / kSsspLanes, ngrp = blockDim.x / kSsspLanes;
     while (cnt > 0) {
         ++r;
-        for (int q = threadIdx.x; q < cnt; q += blockDim.x) {
+        for (int q = grp; q < cnt; q += ngrp) {
             const int u = cur[q];
             const double du = ld_dist(D, u);
-            for (int e = rp[u]; e < rp[u + 1]; ++e) {
+            for (int e = rp[u] + sub; e < rp[u + 1]; e += kSsspLanes) {
                 const int v = ci[e];
                 const unsigned long long nb = (unsigned long long)__double_as_longlong(du + len[e]);
                 const unsigned long long old = atomicMin(D + v, nb);
@@ -391,44 +394,80 @@ __global__ __launch_bounds__(256) void k_wsweep_f64(int n, int k, const int* __r
 }
 
 // FP32 sweep, displacement form: x_i' = x_i + (sum_q f_q (x_q - x_i)) / den_i
-// with f = w - (w d) / r per term (neighbours first in CSR order, then pivot
-// terms by ascending rank; a term with w = 0 adds exactly 0).  One thread
-// per node; the (w', w' d) pairs are read coalesced, rank-major.
-__global__ __launch_bounds__(256) void k_wsweep_f32(int n, int k, const int* __restrict__ rp,
-                                                    const int* __restrict__ ci, const float2* __restrict__ wl,
-                                                    const float2* __restrict__ xo, float2* __restrict__ xn,
-                                                    const int* __restrict__ piv, const float2* __restrict__ wd,
-                                                    const float* __restrict__ den) {
-    extern __shared__ float2 sQ[];
+// with f = w - (w d) / r per term (a term with w = 0 adds exactly 0).  A
+// block is kWSplit waves on the same 64 nodes: wave w sums the pivot terms
+// of ranks t = w (mod kWSplit), the last wave also the neighbour terms in
+// CSR order; wave 0 adds the partials in a fixed order.  The (w', w' d) pairs
+// are read coalesced, rank-major, four ranks ahead.
+constexpr int kWSplit = 4;
+
+__global__ __launch_bounds__(64 * kWSplit) void k_wsweep_f32(int n, int k, const int* __restrict__ rp,
+                                                             const int* __restrict__ ci, const float2* __restrict__ wl,
+                                                             const float2* __restrict__ xo, float2* __restrict__ xn,
+                                                             const int* __restrict__ piv,
+                                                             const float2* __restrict__ wd,
+                                                             const float* __restrict__ den) {
+    extern __shared__ float2 sQ[];  // [k] pivot coordinates, then [kWSplit][64] partials
+    float2* part = sQ + k;
     for (int t = threadIdx.x; t < k; t += blockDim.x) sQ[t] = xo[piv[t]];
-    __syncthreads();
+    const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
     const float tiny = 1e-30f;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const float2 xi = xo[i];
+    const int nchunks = (n + 63) / 64;
+    for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {  // uniform over the block
+        __syncthreads();  // pivots staged; the previous chunk's partials consumed
+        const int i = c * 64 + lane;
         float ax = 0.f, ay = 0.f;
-        for (int e = rp[i]; e < rp[i + 1]; ++e) {
-            const float2 xj = xo[ci[e]];
-            const float2 f01 = wl[e];
-            const float dx = xj.x - xi.x, dy = xj.y - xi.y;
-            const float inv = __builtin_amdgcn_rsqf(dx * dx + (dy * dy + tiny));
-            const float f = fmaf(-f01.y, inv, f01.x);
-            ax += f * dx;
-            ay += f * dy;
+        float2 xi = make_float2(0.f, 0.f);
+        if (i < n) {
+            xi = xo[i];
+            if (w == kWSplit - 1) {
+                for (int e = rp[i]; e < rp[i + 1]; ++e) {
+                    const float2 xj = xo[ci[e]];
+                    const float2 f01 = wl[e];
+                    const float dx = xj.x - xi.x, dy = xj.y - xi.y;
+                    const float inv = __builtin_amdgcn_rsqf(dx * dx + (dy * dy + tiny));
+                    const float f = fmaf(-f01.y, inv, f01.x);
+                    ax += f * dx;
+                    ay += f * dy;
+                }
+            }
+            const float2* __restrict__ wp = wd + i;
+            float2 buf[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = w + u * kWSplit;
+                buf[u] = t < k ? wp[(size_t)t * n] : make_float2(0.f, 0.f);
+            }
+            for (int t0 = w; t0 < k; t0 += 4 * kWSplit) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int t = t0 + u * kWSplit;
+                    if (t >= k) break;
+                    const float2 f01 = buf[u];
+                    const int tn = t + 4 * kWSplit;
+                    if (tn < k) buf[u] = wp[(size_t)tn * n];
+                    const float2 pv = sQ[t];
+                    const float dx = pv.x - xi.x, dy = pv.y - xi.y;
+                    const float inv = __builtin_amdgcn_rsqf(dx * dx + (dy * dy + tiny));
+                    const float f = fmaf(-f01.y, inv, f01.x);
+                    ax += f * dx;
+                    ay += f * dy;
+                }
+            }
         }
-        const float2* __restrict__ wp = wd + i;
-        float2 nxt = k > 0 ? wp[0] : make_float2(0.f, 0.f);
-        for (int t = 0; t < k; ++t) {
-            const float2 f01 = nxt;
-            if (t + 1 < k) nxt = wp[(size_t)(t + 1) * n];
-            const float2 p = sQ[t];
-            const float dx = p.x - xi.x, dy = p.y - xi.y;
-            const float inv = __builtin_amdgcn_rsqf(dx * dx + (dy * dy + tiny));
-            const float f = fmaf(-f01.y, inv, f01.x);
-            ax += f * dx;
-            ay += f * dy;
+        part[w * 64 + lane] = make_float2(ax, ay);
+        __syncthreads();
+        if (w == 0 && i < n) {
+            float sx = 0.f, sy = 0.f;
+#pragma unroll
+            for (int q = 0; q < kWSplit; ++q) {
+                const float2 o = part[q * 64 + lane];
+                sx += o.x;
+                sy += o.y;
+            }
+            const float dn = den[i];
+            xn[i] = make_float2(xi.x + sx / dn, xi.y + sy / dn);
         }
-        const float dn = den[i];
-        xn[i] = make_float2(xi.x + ax / dn, xi.y + ay / dn);
     }
 }
 
@@ -789,6 +828,7 @@ ssm_status ssm_majorize_w(const ssm_csr* g, const double* len, ssm_wterms* t, ss
     if (p != SSM_FP64 && p != SSM_FP32) return fail(SSM_E_INVAL, "unknown precision");
     const int n = g->n, k = t->k;
     const int grid = std::max(1, std::min(div_up(n, 256), num_cus() * 8));
+    const int grid32 = std::max(1, std::min(div_up(n, 64), num_cus() * 8));
     void* a = x;
     void* b = t->xtmp;
     for (int it = 0; it < iters; ++it) {
@@ -797,9 +837,9 @@ ssm_status ssm_majorize_w(const ssm_csr* g, const double* len, ssm_wterms* t, ss
                                g->row_ptr, g->col_idx, len, (const double2*)a, (double2*)b, t->pivots, t->dist,
                                t->w64, t->den64);
         else
-            hipLaunchKernelGGL(k_wsweep_f32, dim3(grid), dim3(256), sizeof(float2) * (size_t)k, stream, n, k,
-                               g->row_ptr, g->col_idx, t->wl32, (const float2*)a, (float2*)b, t->pivots, t->wd32,
-                               t->den32);
+            hipLaunchKernelGGL(k_wsweep_f32, dim3(grid32), dim3(64 * kWSplit),
+                               sizeof(float2) * ((size_t)k + 64 * kWSplit), stream, n, k, g->row_ptr, g->col_idx,
+                               t->wl32, (const float2*)a, (float2*)b, t->pivots, t->wd32, t->den32);
         void* c = a;
         a = b;
         b = c;

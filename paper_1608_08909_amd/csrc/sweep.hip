@@ -147,26 +147,26 @@ __global__ __launch_bounds__(256) void k_heavy_edges(int nseg, const int* __rest
 }
 
 // Copies nbytes (a multiple of 4) from global to LDS with 16-byte loads,
-// several in flight per thread (both sides 16-byte aligned).
+// four in flight per thread (both sides 16-byte aligned).  The loads are
+// unconditional (an index past the end rereads the last word) so that they
+// stay in registers and issue together; only the LDS stores are guarded.
 __device__ __forceinline__ void stage_lds(void* dst, const void* __restrict__ src, size_t nbytes) {
-    constexpr int U = 4;
-    const size_t n16 = nbytes / 16;
+    const int n16 = (int)(nbytes / 16);
+    const int step = blockDim.x;
     uint4* d = (uint4*)dst;
     const uint4* g = (const uint4*)src;
-    for (size_t q0 = threadIdx.x; q0 < n16; q0 += U * (size_t)blockDim.x) {
-        uint4 v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const size_t q = q0 + (size_t)u * blockDim.x;
-            if (q < n16) v[u] = g[q];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const size_t q = q0 + (size_t)u * blockDim.x;
-            if (q < n16) d[q] = v[u];
-        }
+    for (int q0 = threadIdx.x; q0 < n16; q0 += 4 * step) {
+        const int last = n16 - 1;
+        const uint4 v0 = g[q0];
+        const uint4 v1 = g[min(q0 + step, last)];
+        const uint4 v2 = g[min(q0 + 2 * step, last)];
+        const uint4 v3 = g[min(q0 + 3 * step, last)];
+        d[q0] = v0;
+        if (q0 + step < n16) d[q0 + step] = v1;
+        if (q0 + 2 * step < n16) d[q0 + 2 * step] = v2;
+        if (q0 + 3 * step < n16) d[q0 + 3 * step] = v3;
     }
-    for (size_t q = 16 * n16 / 4 + threadIdx.x; q < nbytes / 4; q += blockDim.x)
+    for (int q = 4 * n16 + threadIdx.x; q < (int)(nbytes / 4); q += step)
         ((unsigned*)dst)[q] = ((const unsigned*)src)[q];
 }
 

@@ -207,12 +207,14 @@ typedef struct ssm_wterms ssm_wterms; /* opaque, library-owned device state */
 
 /* max/min sp on lengths (Section 4.1): pivots[0] = first, each next pivot
  * the node farthest from the chosen ones (lowest id on ties); dist (may be
- * NULL) receives the k distance rows [k][n].  SSM_E_DISCONNECTED if a node
- * is unreachable.  Synchronizes. */
+ * NULL) receives the k distance rows [k][n].  SSM_E_INVAL if a length is not
+ * positive and finite (checked on the device before any search),
+ * SSM_E_DISCONNECTED if a node is unreachable.  Synchronizes. */
 ssm_status ssm_select_pivots_w(const ssm_csr* g, const double* len, int32_t k, int32_t first, int32_t* pivots,
                                double* dist, hipStream_t stream);
 /* The k distance rows [k][n] of the given pivots (one label-correcting
- * search per pivot).  Synchronizes. */
+ * search per pivot, in near-far bands of the largest length).  SSM_E_INVAL
+ * if a length is not positive and finite.  Synchronizes. */
 ssm_status ssm_sssp_pivots(const ssm_csr* g, const double* len, int32_t k, const int32_t* pivots, double* dist,
                            hipStream_t stream);
 /* Regions, per-term weights and denominators (Section 3 with lengths) into a

@@ -13,6 +13,8 @@
 //   one weight per (pivot, node) since s no longer depends on d alone through
 //   an integer table.
 // - Regions follow rule R1 with levels at the distinct values of delta.
+#include <float.h>
+
 #include <hipcub/hipcub.hpp>
 
 #include <vector>
@@ -39,6 +41,13 @@ namespace ssm {
 
 constexpr int kSsspBlock = 1024;
 constexpr int kSsspLanes = 8;  // lanes per frontier node in the search
+constexpr size_t kSsspLdsBits = 128 * 1024;  // largest LDS of the three near-far bitmaps (n <= 349504)
+
+// Tuning override SSM_SSSP_NEARFAR=0: the plain label-correcting order.
+static bool nearfar_off() {
+    const char* v = getenv("SSM_SSSP_NEARFAR");
+    return v && atoi(v) == 0;
+}
 constexpr unsigned long long kInfBits = 0x7FF0000000000000ull;  // +inf; non-negative doubles order as their bits
 
 __device__ __forceinline__ double ld_dist(const unsigned long long* D, int v) {
@@ -96,15 +105,145 @@ __device__ void sssp_body(int n, const int* __restrict__ rp, const int* __restri
     __syncthreads();
 }
 
+// The same least fixed point in near-far order: a relaxed node whose new
+// value is below the threshold joins the next round (near), any other joins
+// the far list (once: a far bit per node).  When a round leaves nothing near,
+// the threshold rises by delta (at least the largest edge length, so the
+// next band is never empty) and one pass over the far list drops the nodes
+// already expanded (value below the old threshold), moves those now below
+// the threshold to the frontier and keeps the rest.  Each node is expanded
+// about once instead of once per improvement.  qa, qb, fa, fb hold n ints
+// each; sb: three bitmaps of ceil(n / 32) words in LDS (near, alternating
+// by round, then far).
+__device__ void sssp_nearfar(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                             const double* __restrict__ len, int src, unsigned long long* D, int* qa, int* qb,
+                             int* fa, int* fb, unsigned* sb, double delta) {
+    __shared__ int s_next, s_far, s_keep;
+    const int nbw = (n + 31) / 32;
+    unsigned* farb = sb + 2 * nbw;
+    for (int w = threadIdx.x; w < 3 * nbw; w += blockDim.x) sb[w] = 0u;
+    if (threadIdx.x == 0) {
+        atomicMin(D + src, 0ull);
+        qa[0] = src;
+        s_next = 0;
+        s_far = 0;
+        s_keep = 0;
+    }
+    __syncthreads();
+    int r = 0, cnt = 1;
+    int* cur = qa;
+    int* nxt = qb;
+    int* fcur = fa;
+    int* fnxt = fb;
+    double thr = delta;
+    const int sub = threadIdx.x % kSsspLanes, grp = threadIdx.x / kSsspLanes, ngrp = blockDim.x / kSsspLanes;
+    // a node's values never exceed its first, which follows a tree path of
+    // fewer than n edges, so after n passes (each raises the threshold by the
+    // largest length) nothing stays far; the bound 2 n + 2 only guards the
+    // loop
+    for (long long pass = 0; pass <= 2LL * n + 2; ++pass) {
+        while (cnt > 0) {
+            ++r;
+            unsigned* bits = sb + (r & 1) * nbw;
+            for (int q = grp; q < cnt; q += ngrp) {
+                const int u = cur[q];
+                const double du = ld_dist(D, u);
+                for (int e = rp[u] + sub; e < rp[u + 1]; e += kSsspLanes) {
+                    const int v = ci[e];
+                    const double dv = du + len[e];
+                    const unsigned long long nb = (unsigned long long)__double_as_longlong(dv);
+                    const unsigned long long old = atomicMin(D + v, nb);
+                    if (nb < old) {
+                        const unsigned bit = 1u << (v & 31);
+                        if (dv < thr) {
+                            if (!(atomicOr(bits + (v >> 5), bit) & bit)) nxt[atomicAdd(&s_next, 1)] = v;
+                        } else if (!(atomicOr(farb + (v >> 5), bit) & bit)) {
+                            fcur[atomicAdd(&s_far, 1)] = v;
+                        }
+                    }
+                }
+            }
+            __syncthreads();  // every append of the round is done
+            cnt = s_next;
+            __syncthreads();  // every thread has read the count
+            if (threadIdx.x == 0) s_next = 0;
+            unsigned* other = sb + ((r + 1) & 1) * nbw;  // held this round's frontier
+            for (int w = threadIdx.x; w < nbw; w += blockDim.x) other[w] = 0u;
+            __syncthreads();  // the reset and the clear precede the next round
+            int* t = cur;
+            cur = nxt;
+            nxt = t;
+        }
+        // nothing near: next band, one pass over the far list
+        const int nfar = s_far;
+        if (nfar == 0) break;  // uniform (read after the last barrier)
+        const double lo = thr;
+        thr += delta;
+        for (int q = threadIdx.x; q < nfar; q += blockDim.x) {
+            const int v = fcur[q];
+            const double dv = ld_dist(D, v);
+            const unsigned bit = 1u << (v & 31);
+            if (dv < thr) {
+                atomicAnd(farb + (v >> 5), ~bit);
+                if (dv >= lo) cur[atomicAdd(&s_next, 1)] = v;  // below lo: expanded already
+            } else {
+                fnxt[atomicAdd(&s_keep, 1)] = v;
+            }
+        }
+        __syncthreads();  // the pass is done
+        cnt = s_next;
+        const int kept = s_keep;
+        __syncthreads();  // every thread has read the counts
+        if (threadIdx.x == 0) {
+            s_next = 0;
+            s_far = kept;
+            s_keep = 0;
+        }
+        __syncthreads();  // the resets precede the next round
+        int* t = fcur;
+        fcur = fnxt;
+        fnxt = t;
+    }
+}
+
 // Block b: the full search from pivots[b] into row b of D (pre-filled with
-// +inf); stamp, qa, qb: n ints per block.
+// +inf); stamp, qa, qb: n ints per block (stamp unused with LBITS).
+//   NF: near-far order with its bitmaps in LDS; q holds 4 n ints per block
+//   and *delta the band width.  Otherwise the plain search with global
+//   stamps; q holds 2 n ints per block.
+template <bool NF>
 __global__ __launch_bounds__(kSsspBlock) void k_sssp_rows(int n, const int* __restrict__ rp,
                                                           const int* __restrict__ ci, const double* __restrict__ len,
                                                           const int* __restrict__ pivots, unsigned long long* D,
-                                                          int* stamp, int* q, int* rounds) {
+                                                          int* stamp, int* q, int* rounds,
+                                                          const unsigned long long* __restrict__ delta) {
+    extern __shared__ unsigned sbits[];
     const int b = blockIdx.x;
-    sssp_body(n, rp, ci, len, pivots[b], D + (size_t)b * n, stamp + (size_t)b * n, q + (size_t)b * 2 * n,
-              q + (size_t)b * 2 * n + n, rounds + b);
+    if (NF) {
+        int* qb = q + (size_t)b * 4 * n;
+        sssp_nearfar(n, rp, ci, len, pivots[b], D + (size_t)b * n, qb, qb + n, qb + 2 * (size_t)n,
+                     qb + 3 * (size_t)n, sbits, __longlong_as_double((long long)*delta));
+    } else {
+        sssp_body(n, rp, ci, len, pivots[b], D + (size_t)b * n, stamp + (size_t)b * n, q + (size_t)b * 2 * n,
+                  q + (size_t)b * 2 * n + n, rounds + b);
+    }
+}
+
+// out[0] = bits of the largest length (pre-filled with 0; positive doubles
+// order as their bits); *bad = 1 if a length is not positive and finite.
+__global__ void k_len_check(long long count, const double* __restrict__ len, unsigned long long* out, int* bad) {
+    unsigned long long b = 0;
+    bool ok = true;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < count;
+         q += (long long)gridDim.x * blockDim.x) {
+        const double v = len[q];
+        ok = ok && v > 0.0 && v <= DBL_MAX;  // false for NaN too
+        const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+        b = v > 0.0 && u > b ? u : b;
+    }
+    b = wave_max(b);
+    if (lane_id() == 0) atomicMax(out, b);
+    if (!ok) *bad = 1;
 }
 
 __global__ void k_fill_u64(unsigned long long* p, unsigned long long v, long long count) {
@@ -122,10 +261,14 @@ __global__ void k_fill_i32(int* p, int v, long long count) {
 // max/min sp with lengths, one workgroup: m = min over the chosen pivots'
 // distances (each search pruned by m itself), next pivot = largest m, lowest
 // id on ties.  status[0] = 1 if the first search leaves a node unreached.
+//   NF: near-far searches (fa, fb: n ints each, *delta the band width).
+template <bool NF>
 __global__ __launch_bounds__(kSsspBlock) void k_select_w(int n, const int* __restrict__ rp,
                                                          const int* __restrict__ ci, const double* __restrict__ len,
                                                          int k, int first, int* pivots, unsigned long long* m,
-                                                         int* stamp, int* qa, int* qb, int* round, int* status) {
+                                                         int* stamp, int* qa, int* qb, int* fa, int* fb, int* round,
+                                                         int* status, const unsigned long long* __restrict__ delta) {
+    extern __shared__ unsigned sbits[];
     __shared__ double s_bv[kSsspBlock / kWave];
     __shared__ int s_bi[kSsspBlock / kWave];
     __shared__ int s_src;
@@ -134,18 +277,29 @@ __global__ __launch_bounds__(kSsspBlock) void k_select_w(int n, const int* __res
     for (int t = 0; t < k; ++t) {
         const int src = s_src;
         if (threadIdx.x == 0) pivots[t] = src;
-        sssp_body(n, rp, ci, len, src, m, stamp, qa, qb, round);
+        if (NF)
+            sssp_nearfar(n, rp, ci, len, src, m, qa, qb, fa, fb, sbits, __longlong_as_double((long long)*delta));
+        else
+            sssp_body(n, rp, ci, len, src, m, stamp, qa, qb, round);
         if (t + 1 >= k && t != 0) break;
         // argmax of m: strict comparison over ascending ids per thread keeps
-        // the lowest id among equal values
+        // the lowest id among equal values (eight loads in flight)
         double bv = -1.0;
         int bi = n;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            const double v = ld_dist(m, i);
-            if (v > bv) {
-                bv = v;
-                bi = i;
+        constexpr int U = 8;
+        for (int i0 = threadIdx.x; i0 < n; i0 += U * blockDim.x) {
+            double v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * (int)blockDim.x;
+                v[u] = i < n ? ld_dist(m, i) : -1.0;
             }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (v[u] > bv) {
+                    bv = v[u];
+                    bi = i0 + u * (int)blockDim.x;
+                }
         }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
@@ -533,6 +687,22 @@ hipError_t sort_pairs(const K* kin, K* kout, const V* vin, V* vout, int count, i
     return e != hipSuccess ? e : e2;
 }
 
+// Device check of the lengths: *delta = bits of the largest one (the band
+// width of the near-far searches); SSM_E_INVAL if a length is not positive
+// and finite.  Synchronizes.
+ssm_status length_band(const ssm_csr* g, const double* len, unsigned long long* delta, int* bad, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, delta, 0ull, 1LL);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, bad, 0, 1LL);
+    hipLaunchKernelGGL(k_len_check, dim3(std::max(1, std::min(div_up(g->nnz, 256), 1024))), dim3(256), 0, s,
+                       (long long)g->nnz, len, delta, bad);
+    int hb = 0;
+    SSM_HIP(hipGetLastError());
+    SSM_HIP(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    SSM_HIP(hipStreamSynchronize(s));
+    if (hb) return fail(SSM_E_INVAL, "edge lengths must be positive and finite");
+    return SSM_OK;
+}
+
 int bits_for(int v) {  // bits that hold 0 .. v
     int b = 1;
     while ((1LL << b) <= v) ++b;
@@ -545,20 +715,37 @@ ssm_status select_pivots_w(const ssm_csr* g, const double* len, int32_t k, int32
                            hipStream_t s) {
     const int n = g->n;
     char* ws = nullptr;
-    const size_t bytes = sizeof(unsigned long long) * n + sizeof(int) * (3 * (size_t)n + 2);
+    const size_t bytes = sizeof(unsigned long long) * ((size_t)n + 1) + sizeof(int) * (5 * (size_t)n + 3);
     ssm_status st = salloc((void**)&ws, bytes);
     if (st != SSM_OK) return st;
     unsigned long long* m = (unsigned long long*)ws;
-    int* stamp = (int*)(m + n);
+    unsigned long long* delta = m + n;
+    int* stamp = (int*)(delta + 1);
     int* qa = stamp + n;
     int* qb = qa + n;
-    int* ctl = qb + n;  // round, status
+    int* fa = qb + n;
+    int* fb = fa + n;
+    int* ctl = fb + n;  // round, status, length check
+    st = length_band(g, len, delta, ctl + 2, s);
+    if (st != SSM_OK) {
+        (void)hipStreamSynchronize(s);  // idle before the scratch is reused
+        sfree(ws);
+        return st;
+    }
     const int gb = std::min(div_up(n, 256), 4096);
     hipLaunchKernelGGL(k_fill_u64, dim3(gb), dim3(256), 0, s, m, kInfBits, (long long)n);
     hipLaunchKernelGGL(k_fill_i32, dim3(gb), dim3(256), 0, s, stamp, 0, (long long)n);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, ctl, 0, 2LL);
-    hipLaunchKernelGGL(k_select_w, dim3(1), dim3(kSsspBlock), 0, s, n, g->row_ptr, g->col_idx, len, k, first, pivots,
-                       m, stamp, qa, qb, ctl, ctl + 1);
+    const size_t lbits = 3 * sizeof(unsigned) * (size_t)((n + 31) / 32);
+    if (lbits <= kSsspLdsBits && !nearfar_off()) {
+        (void)hipFuncSetAttribute((const void*)k_select_w<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)kSsspLdsBits);
+        hipLaunchKernelGGL(k_select_w<true>, dim3(1), dim3(kSsspBlock), lbits, s, n, g->row_ptr, g->col_idx, len, k,
+                           first, pivots, m, stamp, qa, qb, fa, fb, ctl, ctl + 1, delta);
+    } else {
+        hipLaunchKernelGGL(k_select_w<false>, dim3(1), dim3(kSsspBlock), 0, s, n, g->row_ptr, g->col_idx, len, k,
+                           first, pivots, m, stamp, qa, qb, fa, fb, ctl, ctl + 1, delta);
+    }
     hipError_t e = hipGetLastError();
     int hs = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&hs, ctl + 1, sizeof(int), hipMemcpyDeviceToHost, s);
@@ -573,26 +760,46 @@ ssm_status select_pivots_w(const ssm_csr* g, const double* len, int32_t k, int32
 ssm_status sssp_rows(const ssm_csr* g, const double* len, int32_t k, const int32_t* pivots, double* dist,
                      hipStream_t s) {
     const int n = g->n;
-    const int blocks = std::min(k, 4 * num_cus());  // rows per launch (each block n ints of stamp, 2 n of queues)
+    // rows per launch; each block holds n ints of stamps and 2 n of queues
+    // (plain search) or 4 n of queues (near-far)
+    const int blocks = std::min(k, 4 * num_cus());
+    const size_t lbits = 3 * sizeof(unsigned) * (size_t)((n + 31) / 32);
+    const bool nf = lbits <= kSsspLdsBits && !nearfar_off();
     char* ws = nullptr;
-    const size_t bytes = sizeof(int) * (3 * (size_t)n * blocks + blocks + 1);
+    const size_t per_block = nf ? 4 * (size_t)n : 3 * (size_t)n;
+    const size_t bytes = sizeof(unsigned long long) + sizeof(int) * (per_block * blocks + blocks + 2);
     ssm_status st = salloc((void**)&ws, bytes);
     if (st != SSM_OK) return st;
-    int* stamp = (int*)ws;
-    int* q = stamp + (size_t)n * blocks;
-    int* rounds = q + 2 * (size_t)n * blocks;
+    unsigned long long* delta = (unsigned long long*)ws;
+    int* q = (int*)(delta + 1);
+    int* stamp = nf ? nullptr : q + 2 * (size_t)n * blocks;
+    int* rounds = q + per_block * blocks;
     int* flag = rounds + blocks;
+    st = length_band(g, len, delta, flag + 1, s);
+    if (st != SSM_OK) {
+        (void)hipStreamSynchronize(s);  // idle before the scratch is reused
+        sfree(ws);
+        return st;
+    }
     const long long total = (long long)k * n;
     hipLaunchKernelGGL(k_fill_u64, dim3(std::min(div_up(total, 256), 8192)), dim3(256), 0, s,
                        (unsigned long long*)dist, kInfBits, total);
     hipError_t e = hipGetLastError();
+    if (nf)
+        (void)hipFuncSetAttribute((const void*)k_sssp_rows<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)kSsspLdsBits);
     for (int b0 = 0; b0 < k && e == hipSuccess; b0 += blocks) {
         const int nb = std::min(blocks, k - b0);
-        hipLaunchKernelGGL(k_fill_i32, dim3(std::min(div_up((long long)n * nb, 256), 8192)), dim3(256), 0, s, stamp, 0,
-                           (long long)n * nb);
-        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, rounds, 0, (long long)nb + 1);
-        hipLaunchKernelGGL(k_sssp_rows, dim3(nb), dim3(kSsspBlock), 0, s, n, g->row_ptr, g->col_idx, len, pivots + b0,
-                           (unsigned long long*)(dist + (size_t)b0 * n), stamp, q, rounds);
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, rounds, 0, (long long)blocks + 1);
+        if (nf) {
+            hipLaunchKernelGGL(k_sssp_rows<true>, dim3(nb), dim3(kSsspBlock), lbits, s, n, g->row_ptr, g->col_idx,
+                               len, pivots + b0, (unsigned long long*)(dist + (size_t)b0 * n), stamp, q, rounds, delta);
+        } else {
+            hipLaunchKernelGGL(k_fill_i32, dim3(std::min(div_up((long long)n * nb, 256), 8192)), dim3(256), 0, s,
+                               stamp, 0, (long long)n * nb);
+            hipLaunchKernelGGL(k_sssp_rows<false>, dim3(nb), dim3(kSsspBlock), 0, s, n, g->row_ptr, g->col_idx, len,
+                               pivots + b0, (unsigned long long*)(dist + (size_t)b0 * n), stamp, q, rounds, delta);
+        }
         e = hipGetLastError();
     }
     int hf = 0;

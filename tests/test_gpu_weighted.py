@@ -148,3 +148,40 @@ def test_weighted_large_rows_and_errors():
     with pytest.raises(ssm.SSMError) as ei:
         ssm.sssp_pivots(dd, ld, torch.tensor([0, 3], dtype=torch.int32, device="cuda"))
     assert ei.value.status == ssm.E_DISCONNECTED
+
+
+@pytest.mark.parametrize("order", ["nearfar", "plain"])
+def test_weighted_search_orders(order, monkeypatch):
+    """Both search orders (near-far bands, the default; plain label-correcting
+    rounds) reach the oracle's Dijkstra distances and max/min pivots bit for
+    bit, also on a graph whose searches run through many far passes."""
+    if order == "plain":
+        monkeypatch.setenv("SSM_SSSP_NEARFAR", "0")
+    for g, k, o in [(G.rgg(20000, 9, 8.0), 24, dict(seed=11)), (G.grid(40, 45), 12, dict(seed=12, lo=1, hi=4, integer=True)),
+                    (G.holed_mesh(90, 80, 5, 3, 10, 6), 16, dict(seed=13, lo=0.01, hi=5.0))]:
+        say("order", order, "case", g.name, k, o)
+        ln = _lengths(g, o)
+        ref = oracle.preprocess_w(g.n, g.row_ptr, g.col_idx, ln, k)
+        dg = ssm.DeviceGraph.from_csr(g)
+        lt = torch.from_numpy(ln).cuda()
+        piv = ssm.select_pivots_w(dg, lt, k, 0)
+        assert np.array_equal(piv.cpu().numpy(), ref.pivots)
+        dist = ssm.sssp_pivots(dg, lt, piv)
+        assert np.array_equal(dist.cpu().numpy(), ref.dist)
+
+
+@pytest.mark.parametrize("bad", [0.0, -1.0, float("nan"), float("inf")], ids=["zero", "negative", "nan", "inf"])
+def test_weighted_invalid_lengths(bad):
+    """A length that is not positive and finite is refused (SSM_E_INVAL) by
+    the searches before any of them runs."""
+    g = G.grid(6, 7)
+    ln = G.edge_lengths(g, 3, 0.5, 2.0, False)
+    ln[5] = bad
+    dg = ssm.DeviceGraph.from_csr(g)
+    lt = torch.from_numpy(ln).cuda()
+    with pytest.raises(ssm.SSMError) as ei:
+        ssm.select_pivots_w(dg, lt, 4, 0)
+    assert ei.value.status == ssm.E_INVAL
+    with pytest.raises(ssm.SSMError) as ei:
+        ssm.sssp_pivots(dg, lt, torch.tensor([0, 9], dtype=torch.int32).cuda())
+    assert ei.value.status == ssm.E_INVAL

@@ -118,15 +118,20 @@ __device__ void sssp_body(int n, const int* __restrict__ rp, const int* __restri
 __device__ void sssp_nearfar(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                              const double* __restrict__ len, int src, unsigned long long* D, int* qa, int* qb,
                              int* fa, int* fb, unsigned* sb, double delta) {
-    __shared__ int s_next, s_far, s_keep;
+    // near rounds count their appends into s_cnt[r % 3]: round r clears the
+    // slot of round r + 1 (last read after round r - 2's barrier) and the
+    // bitmap of round r + 1 (last used in round r - 1), so one barrier per
+    // round suffices
+    __shared__ int s_cnt[3], s_far, s_mv, s_keep;
     const int nbw = (n + 31) / 32;
     unsigned* farb = sb + 2 * nbw;
     for (int w = threadIdx.x; w < 3 * nbw; w += blockDim.x) sb[w] = 0u;
     if (threadIdx.x == 0) {
         atomicMin(D + src, 0ull);
         qa[0] = src;
-        s_next = 0;
+        s_cnt[0] = s_cnt[1] = s_cnt[2] = 0;
         s_far = 0;
+        s_mv = 0;
         s_keep = 0;
     }
     __syncthreads();
@@ -144,6 +149,10 @@ __device__ void sssp_nearfar(int n, const int* __restrict__ rp, const int* __res
     for (long long pass = 0; pass <= 2LL * n + 2; ++pass) {
         while (cnt > 0) {
             ++r;
+            int* cntr = &s_cnt[r % 3];
+            if (threadIdx.x == 0) s_cnt[(r + 1) % 3] = 0;
+            unsigned* other = sb + ((r + 1) & 1) * nbw;
+            for (int w = threadIdx.x; w < nbw; w += blockDim.x) other[w] = 0u;
             unsigned* bits = sb + (r & 1) * nbw;
             for (int q = grp; q < cnt; q += ngrp) {
                 const int u = cur[q];
@@ -156,20 +165,15 @@ __device__ void sssp_nearfar(int n, const int* __restrict__ rp, const int* __res
                     if (nb < old) {
                         const unsigned bit = 1u << (v & 31);
                         if (dv < thr) {
-                            if (!(atomicOr(bits + (v >> 5), bit) & bit)) nxt[atomicAdd(&s_next, 1)] = v;
+                            if (!(atomicOr(bits + (v >> 5), bit) & bit)) nxt[atomicAdd(cntr, 1)] = v;
                         } else if (!(atomicOr(farb + (v >> 5), bit) & bit)) {
                             fcur[atomicAdd(&s_far, 1)] = v;
                         }
                     }
                 }
             }
-            __syncthreads();  // every append of the round is done
-            cnt = s_next;
-            __syncthreads();  // every thread has read the count
-            if (threadIdx.x == 0) s_next = 0;
-            unsigned* other = sb + ((r + 1) & 1) * nbw;  // held this round's frontier
-            for (int w = threadIdx.x; w < nbw; w += blockDim.x) other[w] = 0u;
-            __syncthreads();  // the reset and the clear precede the next round
+            __syncthreads();  // every append (and clear) of the round is done
+            cnt = *cntr;
             int* t = cur;
             cur = nxt;
             nxt = t;
@@ -185,17 +189,17 @@ __device__ void sssp_nearfar(int n, const int* __restrict__ rp, const int* __res
             const unsigned bit = 1u << (v & 31);
             if (dv < thr) {
                 atomicAnd(farb + (v >> 5), ~bit);
-                if (dv >= lo) cur[atomicAdd(&s_next, 1)] = v;  // below lo: expanded already
+                if (dv >= lo) cur[atomicAdd(&s_mv, 1)] = v;  // below lo: expanded already
             } else {
                 fnxt[atomicAdd(&s_keep, 1)] = v;
             }
         }
         __syncthreads();  // the pass is done
-        cnt = s_next;
+        cnt = s_mv;
         const int kept = s_keep;
         __syncthreads();  // every thread has read the counts
         if (threadIdx.x == 0) {
-            s_next = 0;
+            s_mv = 0;
             s_far = kept;
             s_keep = 0;
         }
@@ -244,6 +248,12 @@ __global__ void k_len_check(long long count, const double* __restrict__ len, uns
     b = wave_max(b);
     if (lane_id() == 0) atomicMax(out, b);
     if (!ok) *bad = 1;
+}
+
+// *delta *= c (bits of a positive double).
+__global__ void k_band_scale(unsigned long long* delta, double c) {
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        *delta = (unsigned long long)__double_as_longlong(c * __longlong_as_double((long long)*delta));
 }
 
 __global__ void k_fill_u64(unsigned long long* p, unsigned long long v, long long count) {
@@ -687,14 +697,17 @@ hipError_t sort_pairs(const K* kin, K* kout, const V* vin, V* vout, int count, i
     return e != hipSuccess ? e : e2;
 }
 
-// Device check of the lengths: *delta = bits of the largest one (the band
-// width of the near-far searches); SSM_E_INVAL if a length is not positive
-// and finite.  Synchronizes.
-ssm_status length_band(const ssm_csr* g, const double* len, unsigned long long* delta, int* bad, hipStream_t s) {
+// Device check of the lengths: *delta = c times the largest one (the band
+// width of the near-far searches; an integer c >= 1 keeps their far-pass
+// bound); SSM_E_INVAL if a length is not positive and finite.  Synchronizes.
+ssm_status length_band(const ssm_csr* g, const double* len, unsigned long long* delta, int* bad, int c,
+                       hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, delta, 0ull, 1LL);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, bad, 0, 1LL);
     hipLaunchKernelGGL(k_len_check, dim3(std::max(1, std::min(div_up(g->nnz, 256), 1024))), dim3(256), 0, s,
                        (long long)g->nnz, len, delta, bad);
+    if (const char* v = getenv("SSM_SSSP_BAND")) c = atoi(v);  // tuning override
+    if (c > 1) hipLaunchKernelGGL(k_band_scale, dim3(1), dim3(64), 0, s, delta, (double)c);
     int hb = 0;
     SSM_HIP(hipGetLastError());
     SSM_HIP(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -726,7 +739,9 @@ ssm_status select_pivots_w(const ssm_csr* g, const double* len, int32_t k, int32
     int* fa = qb + n;
     int* fb = fa + n;
     int* ctl = fb + n;  // round, status, length check
-    st = length_band(g, len, delta, ctl + 2, s);
+    // many short pruned searches: bands of two lengths (fewer rounds) measured
+    // faster than one on MI355X; the full rows take one
+    st = length_band(g, len, delta, ctl + 2, 2, s);
     if (st != SSM_OK) {
         (void)hipStreamSynchronize(s);  // idle before the scratch is reused
         sfree(ws);
@@ -775,7 +790,7 @@ ssm_status sssp_rows(const ssm_csr* g, const double* len, int32_t k, const int32
     int* stamp = nf ? nullptr : q + 2 * (size_t)n * blocks;
     int* rounds = q + per_block * blocks;
     int* flag = rounds + blocks;
-    st = length_band(g, len, delta, flag + 1, s);
+    st = length_band(g, len, delta, flag + 1, 1, s);
     if (st != SSM_OK) {
         (void)hipStreamSynchronize(s);  // idle before the scratch is reused
         sfree(ws);

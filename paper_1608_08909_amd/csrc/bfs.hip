@@ -1293,6 +1293,110 @@ __device__ __forceinline__ unsigned long long argmax_m7_clear(unsigned char* m8,
     return bv >= 0 ? argmax_key(bv, bi) : 0ull;
 }
 
+// Frontier nodes that one pass of wave 0 covers in wave_levels (W / 4
+// lanes per node, as in the block levels).
+template <int W>
+constexpr int wave_level_nodes() {
+    return kWave / (W / 4);
+}
+
+// Levels whose frontier one wave covers in one pass, run in wave 0 alone
+// (state bytes): W / 4 lanes per frontier node take four ELL slots each, the
+// whole wave then takes the CSR tails of long rows, 64 arcs at a time; the
+// claims are the block levels' and the wave ranks its appends with ballots,
+// so neither an LDS counter nor a barrier separates these levels (LDS
+// operations of one wave complete in order).  Runs while the frontier holds
+// 1 .. wave_level_nodes<W>() nodes and the next level stays below kM7Sat
+// (where the state byte alone decides); returns the frontier size, advances
+// level and counts the queue swaps.
+template <int W, int P>
+__device__ __forceinline__ int wave_levels(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                           const int* __restrict__ ell, unsigned char* m8, const Frontier& f0,
+                                           int len, int& level, int& swaps) {
+    constexpr int G = W / 4;
+    const int lane = lane_id(), sub = lane % G;
+    const int* lcur = f0.lcur;
+    int* lnxt = f0.lnxt;
+    int* gnxt = f0.gnxt;
+    const int* gcur = f0.gcur;
+    while (len > 0 && len <= P * wave_level_nodes<W>() && level + 1 < kM7Sat) {
+        const int dv = level + 1;
+        int v[P];
+        int4 nb[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int q = p * wave_level_nodes<W>() + lane / G;
+            v[p] = q < len ? lcur[q] : -1;  // the LDS part holds the frontier
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            nb[p] = make_int4(-1, -1, -1, -1);
+            if ((unsigned)v[p] < (unsigned)n) nb[p] = *(const int4*)(ell + (size_t)v[p] * W + 4 * sub);
+        }
+        int cnt = 0;
+        // claim u and append it if it joins the next frontier (uniform call)
+        auto take = [&](int u, unsigned old) {
+            const unsigned ob = (old >> (8 * (u & 3))) & 0xffu;
+            const bool ok = (unsigned)u < (unsigned)n && !(ob & 0x80u) && (int)(ob & 0x7fu) > dv;
+            if (ok) m8[u] = (unsigned char)(0x80 | dv);
+            const uint64_t mk = __ballot(ok);
+            if (ok) {
+                const int slot = cnt + mask_rank(mk);
+                if (slot < kLdsQ)
+                    lnxt[slot] = u;
+                else
+                    gnxt[slot - kLdsQ] = u;
+            }
+            cnt += __popcll(mk);
+        };
+        auto claim = [&](int u) {
+            return (unsigned)u < (unsigned)n ? atomicOr((unsigned*)(m8 + (u & ~3)), 0x80u << (8 * (u & 3)))
+                                             : 0x80808080u;
+        };
+        unsigned old[4 * P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            old[4 * p] = claim(nb[p].x);
+            old[4 * p + 1] = claim(nb[p].y);
+            old[4 * p + 2] = claim(nb[p].z);
+            old[4 * p + 3] = claim(nb[p].w);
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            take(nb[p].x, old[4 * p]);
+            take(nb[p].y, old[4 * p + 1]);
+            take(nb[p].z, old[4 * p + 2]);
+            take(nb[p].w, old[4 * p + 3]);
+        }
+        // long rows: the whole wave over each tail, 64 arcs at a time
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          uint64_t hm = __ballot(sub == G - 1 && nb[p].w == kEllMore);
+          while (hm) {
+            const int src_lane = __builtin_ctzll(hm);
+            hm &= hm - 1;
+            const int h = __shfl(v[p], src_lane);
+            const int e1 = rp[h + 1];
+            for (int e = rp[h] + W - 1 + lane; __any(e < e1); e += kWave) {
+                const int t = e < e1 ? ci[e] : -1;
+                take(t, claim(t));
+            }
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+        len = cnt;
+        const int* tl = lcur;
+        lcur = lnxt;
+        lnxt = (int*)tl;
+        const int* tg = gcur;
+        gcur = gnxt;
+        gnxt = (int*)tg;
+        ++swaps;
+        ++level;
+    }
+    return len;
+}
+
 // All k pivots in one workgroup: for each new pivot the BFS that only
 // continues through nodes whose distance to it is below m (as k_select_all),
 // on LDS-resident levels.
@@ -1307,10 +1411,11 @@ __device__ __forceinline__ unsigned long long argmax_m7_clear(unsigned char* m8,
 template <int W, bool M8, int SPOOL = kSelPool>
 __device__ __forceinline__ void select_ell_body(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                 const int* __restrict__ ell, int k, int first, int* pivots, int* m,
-                                                int* gq, int* status) {
+                                                int* gq, int* status, int wave_mode = 1) {
     __shared__ __align__(16) unsigned char pool[SPOOL];
     __shared__ int2 s_slot[3];
     __shared__ int s_src;
+    __shared__ int s_wave[3];
     __shared__ unsigned long long s_red[kBfsBlock / kWave];
     int* qa = (int*)pool;
     int* qb = qa + kLdsQ;
@@ -1345,6 +1450,33 @@ __device__ __forceinline__ void select_ell_body(int n, const int* __restrict__ r
         Frontier f{qa, ga, qb, gb, nullptr, lheavy, gh};
         int len = 1;
         for (int level = 0; len > 0; ++level) {
+            if (M8 && wave_mode > 0 && len <= wave_mode * wave_level_nodes<W>() && level + 1 < kM7Sat) {  // uniform
+                if (threadIdx.x < kWave) {
+                    int lv = level, sw = 0;
+                    const int nl = wave_mode == 1 ? wave_levels<W, 1>(n, rp, ci, ell, m8, f, len, lv, sw)
+                                                  : wave_levels<W, 2>(n, rp, ci, ell, m8, f, len, lv, sw);
+                    if (threadIdx.x == 0) {
+                        s_wave[0] = nl;
+                        s_wave[1] = lv;
+                        s_wave[2] = sw;
+                        // the block levels' counters: clear for whichever level comes next
+                        s_slot[0] = s_slot[1] = s_slot[2] = make_int2(0, 0);
+                    }
+                }
+                __syncthreads();
+                len = s_wave[0];
+                const int nlev = s_wave[1], sw = s_wave[2];
+                if (sw & 1) {
+                    const int* tl = f.lcur;
+                    f.lcur = f.lnxt;
+                    f.lnxt = (int*)tl;
+                    const int* tg = f.gcur;
+                    f.gcur = f.gnxt;
+                    f.gnxt = (int*)tg;
+                }
+                level = nlev - 1;  // the loop steps to nlev
+                continue;
+            }
             level_begin(s_slot, level, f);
             const int dv = level + 1;
             len = ell_level_auto<W>(n, rp, ci, ell, len, f, [&](const auto& u, auto& ok) {
@@ -1424,8 +1556,8 @@ template <int W, bool M8>
 __global__ __launch_bounds__(kBfsBlock) void k_select_ell(int n, const int* __restrict__ rp,
                                                           const int* __restrict__ ci, const int* __restrict__ ell,
                                                           int k, int first, int* pivots, int* m, int* gq,
-                                                          int* status) {
-    select_ell_body<W, M8>(n, rp, ci, ell, k, first, pivots, m, gq, status);
+                                                          int* status, int wave_mode) {
+    select_ell_body<W, M8>(n, rp, ci, ell, k, first, pivots, m, gq, status, wave_mode);
 }
 
 template <int W, bool M8>
@@ -1434,8 +1566,12 @@ static hipError_t launch_select_ell_t(hipStream_t s, int n, const int* rp, const
     int threads = kBfsBlock;
     const int v = env_int("SSM_SELECT_THREADS");  // tuning override: 256, 512 or 1024
     if (v == 256 || v == 512) threads = v;
+    // small frontiers in one wave, one pass per level (tuning override
+    // SSM_SELECT_WAVE: 0 = block levels only, 2 = up to two passes)
+    const char* wv = getenv("SSM_SELECT_WAVE");
+    const int wave_mode = wv ? std::max(0, std::min(2, atoi(wv))) : 1;
     hipLaunchKernelGGL((k_select_ell<W, M8>), dim3(1), dim3(threads), 0, s, n, rp, ci, ell, k, first, pivots, m,
-                       q, status);
+                       q, status, wave_mode);
     return hipGetLastError();
 }
 

@@ -98,9 +98,12 @@ VARIANTS = [
     {"SSM_BFS_ROWQ": "2", "SSM_BFS_ELL": "2"}, {"SSM_BFS_ELL": "2"}, {"SSM_MSBFS": "1"},
     {"SSM_MSBFS": "1", "SSM_MSBFS_BUDGET": "3"},
     {"SSM_REGION_MODE": "1"}, {"SSM_REGION_MODE": "2"}, {"SSM_BFS_LANES": "2"}, {"SSM_BFS_LANES": "64"},
+    {"SSM_SELECT_WAVE": "0"}, {"SSM_SELECT_WAVE": "2"},
 ]
+# (the star's first level overflows the LDS part of the frontier queue; the
+# path's levels pass the state byte's saturation)
 VARIANT_CASES = [(G.barabasi_albert(2000, 5, 7), 50), (G.rgg(1500, 4), 33), (G.holed_mesh(120, 130, 6, 4, 12, 5), 40),
-                 (G.tree_plus(300, 2), 17), (G.star(12), 3), (G.path(600), 6)]
+                 (G.tree_plus(300, 2), 17), (G.star(12), 3), (G.path(600), 6), (G.star(3000), 3)]
 
 
 @pytest.mark.parametrize("env", VARIANTS, ids=["-".join(f"{a[4:]}={b}" for a, b in v.items()) for v in VARIANTS])

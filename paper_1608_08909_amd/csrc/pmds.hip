@@ -865,15 +865,23 @@ __global__ __launch_bounds__(1024) void k_pool_mds_stats(const PoolGraph* __rest
     const PoolGraph& g = gs[blockIdx.x];
     const int n = g.n, k = g.k;
     __shared__ long long red[1024 / kWave];
-    for (int t = 0; t < k; ++t) {
-        long long s = 0;
-        const int* row = g.dist + (size_t)t * n;
+    constexpr int U = 8;  // rows per pass (exact integer sums: any order)
+    for (int t0 = 0; t0 < k; t0 += U) {
+        long long s[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) s[j] = 0;
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            const long long d = row[i];
-            s += d * d;
+            long long d[U];
+#pragma unroll
+            for (int j = 0; j < U; ++j) d[j] = t0 + j < k ? g.dist[(size_t)(t0 + j) * n + i] : 0;
+#pragma unroll
+            for (int j = 0; j < U; ++j) s[j] += d[j] * d[j];
         }
-        s = block_sum(s, red);
-        if (threadIdx.x == 0) g.colsum[t] = s;
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const long long v = block_sum(s[j], red);
+            if (threadIdx.x == 0 && t0 + j < k) g.colsum[t0 + j] = v;
+        }
     }
     if (threadIdx.x == 0) {  // colsum was written by this thread
         long long total = 0;
@@ -885,9 +893,12 @@ __global__ __launch_bounds__(1024) void k_pool_mds_stats(const PoolGraph* __rest
     }
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         long long s = 0;
-        for (int t = 0; t < k; ++t) {
-            const long long d = g.dist[(size_t)t * n + i];
-            s += d * d;
+        for (int t0 = 0; t0 < k; t0 += U) {
+            long long d[U];
+#pragma unroll
+            for (int j = 0; j < U; ++j) d[j] = t0 + j < k ? g.dist[(size_t)(t0 + j) * n + i] : 0;
+#pragma unroll
+            for (int j = 0; j < U; ++j) s += d[j] * d[j];
         }
         g.nu[i] = (double)s / (double)k;
     }
@@ -934,24 +945,36 @@ __global__ __launch_bounds__(1024) void k_pool_project(const PoolGraph* __restri
     const PoolGraph& g = gs[blockIdx.x];
     const int n = g.n, k = g.k, nwords = g.kpad / 8;
     const double gamma = g.stats[0];
-    const double* V = g.eig;
     double2* x = g.x64[0];
+    // mu and the two eigenvectors in LDS (read by every node)
+    __shared__ double s_mu[kPoolMaxK], s_v[2 * kPoolMaxK];
+    for (int t = threadIdx.x; t < k; t += blockDim.x) {
+        s_mu[t] = g.mu[t];
+        s_v[2 * t] = g.eig[2 * t];
+        s_v[2 * t + 1] = g.eig[2 * t + 1];
+    }
+    __syncthreads();
+    constexpr int U = 4;  // packed words in flight per node
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         double s0 = 0.0, s1 = 0.0;
         const double nui = g.nu[i];
-        for (int b = 0; b < nwords; ++b) {
+        for (int b0 = 0; b0 < nwords; b0 += U) {
             union {
                 uint4 v;
                 uint16_t e[8];
-            } u;
-            u.v = g.dpk[(size_t)b * n + i];
+            } u[U];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int t = b * 8 + j;
-                if (t < k) {
-                    const double c = centred((int)u.e[j], g.mu[t], nui, gamma);
-                    s0 += c * V[2 * t];
-                    s1 += c * V[2 * t + 1];
+            for (int w = 0; w < U; ++w) u[w].v = b0 + w < nwords ? g.dpk[(size_t)(b0 + w) * n + i] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+            for (int w = 0; w < U; ++w) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int t = (b0 + w) * 8 + j;  // ranks in ascending order
+                    if (t < k) {
+                        const double c = centred((int)u[w].e[j], s_mu[t], nui, gamma);
+                        s0 += c * s_v[2 * t];
+                        s1 += c * s_v[2 * t + 1];
+                    }
                 }
             }
         }

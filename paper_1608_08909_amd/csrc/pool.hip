@@ -45,16 +45,24 @@ __global__ __launch_bounds__(1024) void k_pool_regions(const PoolGraph* __restri
     for (int w = threadIdx.x; w < (n + 31) / 32; w += blockDim.x) tied[w] = 0u;
     __syncthreads();
     int dm = 0;
+    constexpr int U = 8;  // distance loads in flight per thread
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         int best = INT_MAX, cnt = 0, at = 0;
-        for (int t = 0; t < k; ++t) {
-            const int d = dist[(size_t)t * n + i];
-            if (d < best) {
-                best = d;
-                cnt = 1;
-                at = t;
-            } else if (d == best) {
-                ++cnt;
+        for (int t0 = 0; t0 < k; t0 += U) {
+            int dv[U];
+#pragma unroll
+            for (int j = 0; j < U; ++j) dv[j] = t0 + j < k ? dist[(size_t)(t0 + j) * n + i] : INT_MAX;
+#pragma unroll
+            for (int j = 0; j < U; ++j) {  // ranks in ascending order
+                if (t0 + j >= k) break;
+                const int d = dv[j];
+                if (d < best) {
+                    best = d;
+                    cnt = 1;
+                    at = t0 + j;
+                } else if (d == best) {
+                    ++cnt;
+                }
             }
         }
         g.delta[i] = best;
@@ -74,9 +82,16 @@ __global__ __launch_bounds__(1024) void k_pool_regions(const PoolGraph* __restri
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
             if (dl[i] != l || !((tied[i >> 5] >> (i & 31)) & 1u)) continue;
             int pick = -1;
-            for (int t = 0; t < k; ++t) {
-                if (dist[(size_t)t * n + i] != l) continue;
-                if (pick < 0 || snap[t] < snap[pick]) pick = t;
+            for (int t0 = 0; t0 < k; t0 += U) {
+                int dv[U];
+#pragma unroll
+                for (int j = 0; j < U; ++j) dv[j] = t0 + j < k ? dist[(size_t)(t0 + j) * n + i] : -1;
+#pragma unroll
+                for (int j = 0; j < U; ++j) {  // ranks in ascending order
+                    const int t = t0 + j;
+                    if (dv[j] != l) continue;
+                    if (pick < 0 || snap[t] < snap[pick]) pick = t;
+                }
             }
             g.region[i] = pick;
             atomicAdd(&size[pick], 1);
@@ -131,26 +146,48 @@ __global__ __launch_bounds__(1024) void k_pool_regions(const PoolGraph* __restri
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         double s = 0.0;
         for (int e = g.rp[i]; e < g.rp[i + 1]; ++e) s += 1.0;
-        for (int t = 0; t < k; ++t) {
-            const int d = dist[(size_t)t * n + i];
-            if (d >= 2) s += g.w64[(size_t)t * W + d];
+        for (int t0 = 0; t0 < k; t0 += U) {
+            int dv[U];
+            double wv[U];
+#pragma unroll
+            for (int j = 0; j < U; ++j) dv[j] = t0 + j < k ? dist[(size_t)(t0 + j) * n + i] : 0;
+#pragma unroll
+            for (int j = 0; j < U; ++j) wv[j] = dv[j] >= 2 ? g.w64[(size_t)(t0 + j) * W + dv[j]] : 0.0;
+#pragma unroll
+            for (int j = 0; j < U; ++j)  // ranks in ascending order
+                if (dv[j] >= 2) s += wv[j];
         }
         g.den64[i] = s;
         g.den32[i] = (float)s;
     }
+    // packed words, four per thread and pass: every load of a pass before
+    // its stores
     const long long words = (long long)(kpad / 8) * n;
-    for (long long q = threadIdx.x; q < words; q += blockDim.x) {
-        const int b = (int)(q / n), i = (int)(q % n);
-        union {
-            uint4 v;
-            uint16_t e[8];
-        } u;
+    constexpr int QW = 4;
+    for (long long q0 = threadIdx.x; q0 < words; q0 += QW * (long long)blockDim.x) {
+        int dv[QW][8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int t = b * 8 + j;
-            u.e[j] = t < k ? (uint16_t)dist[(size_t)t * n + i] : (uint16_t)0;
+        for (int w = 0; w < QW; ++w) {
+            const long long q = q0 + (long long)w * blockDim.x;
+            const int b = (int)(q / n), i = (int)(q % n);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int t = b * 8 + j;
+                dv[w][j] = q < words && t < k ? dist[(size_t)t * n + i] : 0;
+            }
         }
-        g.dpk[q] = u.v;
+#pragma unroll
+        for (int w = 0; w < QW; ++w) {
+            const long long q = q0 + (long long)w * blockDim.x;
+            if (q >= words) break;
+            union {
+                uint4 v;
+                uint16_t e[8];
+            } u;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) u.e[j] = (uint16_t)dv[w][j];
+            g.dpk[q] = u.v;
+        }
     }
     if (threadIdx.x == 0) g.info[2] = delta_max;
 }

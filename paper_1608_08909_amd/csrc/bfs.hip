@@ -1771,15 +1771,23 @@ __global__ __launch_bounds__(256) void k_reg_scan(int n, int k, const int* __res
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         int best = kInf, cnt = 0;
         int c[kMaxCand] = {-1, -1, -1, -1};
-        for (int t = 0; t < k; ++t) {
-            int d = dist[(size_t)t * n + i];
-            if (d < best) {
-                best = d;
-                cnt = 1;
-                c[0] = t;
-            } else if (d == best) {
-                if (cnt < kMaxCand) c[cnt] = t;
-                ++cnt;
+        constexpr int U = 8;  // distance loads in flight
+        for (int t0 = 0; t0 < k; t0 += U) {
+            int dv[U];
+#pragma unroll
+            for (int j = 0; j < U; ++j) dv[j] = t0 + j < k ? dist[(size_t)(t0 + j) * n + i] : kInf;
+#pragma unroll
+            for (int j = 0; j < U; ++j) {  // ranks in ascending order
+                if (t0 + j >= k) break;
+                const int d = dv[j], t = t0 + j;
+                if (d < best) {
+                    best = d;
+                    cnt = 1;
+                    c[0] = t;
+                } else if (d == best) {
+                    if (cnt < kMaxCand) c[cnt] = t;
+                    ++cnt;
+                }
             }
         }
         delta[i] = best;

@@ -17,13 +17,17 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // colsum[t] = sum_i dist[t][i]^2 (exact in int64), from the packed copy:
 // block b sums word row b (ranks b*VEC .. b*VEC+VEC-1).
 template <typename DT, int VEC>
-__global__ __launch_bounds__(256) void k_pmds_colsum(int n, int k, const uint4* __restrict__ dpk,
+__global__ __launch_bounds__(256) void k_pmds_colsum(int n, int kpad, const uint4* __restrict__ dpk,
                                                      long long* __restrict__ colsum) {
+    // block (b, y): packed word b over the y-th of gridDim.y node ranges;
+    // partial sums colsum[y][rank] (exact integers, added up by k_pmds_mu)
     const int b = blockIdx.x;
+    const int chunk = (n + gridDim.y - 1) / gridDim.y;
+    const int i0 = blockIdx.y * chunk, i1 = min(n, i0 + chunk);
     long long s[VEC];
 #pragma unroll
     for (int j = 0; j < VEC; ++j) s[j] = 0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
         union {
             uint4 v;
             DT e[VEC];
@@ -36,20 +40,31 @@ __global__ __launch_bounds__(256) void k_pmds_colsum(int n, int k, const uint4* 
 #pragma unroll
     for (int j = 0; j < VEC; ++j) {
         long long tot = block_sum(s[j], red);
-        if (threadIdx.x == 0 && b * VEC + j < k) colsum[b * VEC + j] = tot;
+        if (threadIdx.x == 0) colsum[(size_t)blockIdx.y * kpad + b * VEC + j] = tot;
     }
 }
 
-// mu[t] = colsum[t] / n; stats[0] = gamma = sum_t colsum[t] / (n k).  Integer
-// sums are exact, so these equal a serial double evaluation bit for bit.
-__global__ void k_pmds_mu(int n, int k, const long long* __restrict__ colsum, double* __restrict__ mu,
+// Node ranges of k_pmds_colsum per packed word.
+constexpr int kColSplit = 32;
+
+// mu[t] = colsum[t] / n with colsum[t] the sum of the kColSplit partials;
+// stats[0] = gamma = sum_t colsum[t] / (n k).  Integer sums are exact, so
+// these equal a serial double evaluation bit for bit.
+__global__ void k_pmds_mu(int n, int k, int kpad, const long long* __restrict__ colsum, double* __restrict__ mu,
                           double* __restrict__ stats) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    __shared__ long long tot[64];
+    long long part = 0;
+    for (int t = threadIdx.x; t < k; t += blockDim.x) {
+        long long c = 0;
+        for (int y = 0; y < kColSplit; ++y) c += colsum[(size_t)y * kpad + t];
+        mu[t] = (double)c / (double)n;
+        part += c;
+    }
+    tot[threadIdx.x] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
         long long total = 0;
-        for (int t = 0; t < k; ++t) {
-            mu[t] = (double)colsum[t] / (double)n;
-            total += colsum[t];
-        }
+        for (int q = 0; q < (int)blockDim.x; ++q) total += tot[q];
         stats[0] = (double)total / ((double)n * (double)k);
     }
 }
@@ -773,7 +788,7 @@ ssm_status pivotmds(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* x, hipStre
     nchunks = div_up(n, chunk);
     // workspace: colsum (k ll), mu (k), nu (n), stats (4), M (k*k), part, tiles, edge partials
     const int eblocks = std::min(div_up(n, 256), 2048);
-    size_t bytes = sizeof(long long) * k + sizeof(double) * ((size_t)k + n + 4) +
+    size_t bytes = sizeof(long long) * (size_t)kColSplit * t->kpad + sizeof(double) * ((size_t)k + n + 4) +
                    sizeof(double) * (size_t)nchunks * ntiles * 256 + sizeof(int2) * ntiles +
                    sizeof(double) * ((size_t)eblocks + 2) + 64 * 8;
     char* ws = nullptr;
@@ -785,7 +800,7 @@ ssm_status pivotmds(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* x, hipStre
         cur += (b + 63) / 64 * 64;
         return r;
     };
-    long long* colsum = (long long*)take(sizeof(long long) * k);
+    long long* colsum = (long long*)take(sizeof(long long) * (size_t)kColSplit * t->kpad);
     double* mu = (double*)take(sizeof(double) * k);
     double* nu = (double*)take(sizeof(double) * n);
     double* stats = (double*)take(sizeof(double) * 4);
@@ -801,13 +816,15 @@ ssm_status pivotmds(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* x, hipStre
     const uint4* dpk = (const uint4*)t->dpk;
     if (e == hipSuccess) {
         if (t->dbytes == 1) {
-            hipLaunchKernelGGL((k_pmds_colsum<uint8_t, 16>), dim3(nwords), dim3(256), 0, s, n, k, dpk, colsum);
+            hipLaunchKernelGGL((k_pmds_colsum<uint8_t, 16>), dim3(nwords, kColSplit), dim3(256), 0, s, n, t->kpad, dpk,
+                               colsum);
             hipLaunchKernelGGL((k_pmds_nu<uint8_t, 16>), dim3(gn), dim3(256), 0, s, n, k, nwords, dpk, nu);
         } else {
-            hipLaunchKernelGGL((k_pmds_colsum<uint16_t, 8>), dim3(nwords), dim3(256), 0, s, n, k, dpk, colsum);
+            hipLaunchKernelGGL((k_pmds_colsum<uint16_t, 8>), dim3(nwords, kColSplit), dim3(256), 0, s, n, t->kpad, dpk,
+                               colsum);
             hipLaunchKernelGGL((k_pmds_nu<uint16_t, 8>), dim3(gn), dim3(256), 0, s, n, k, nwords, dpk, nu);
         }
-        hipLaunchKernelGGL(k_pmds_mu, dim3(1), dim3(64), 0, s, n, k, colsum, mu, stats);
+        hipLaunchKernelGGL(k_pmds_mu, dim3(1), dim3(64), 0, s, n, k, t->kpad, colsum, mu, stats);
         size_t lds = sizeof(double) * ((size_t)kGramSub * kp + kp);
         dim3 gg(nchunks, ngroups);
         if (t->dbytes == 1)
@@ -1023,9 +1040,14 @@ __global__ __launch_bounds__(256) void k_wpmds_colsum(int n, const double* __res
                                                       double* __restrict__ colsum) {
     const int t = blockIdx.x;
     double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const double d = dist[(size_t)t * n + i];
-        s += d * d;
+    const int B = blockDim.x;
+    for (int i0 = threadIdx.x; i0 < n; i0 += 4 * B) {
+        double d[4];  // four loads in flight, added in the same order as one at a time
+#pragma unroll
+        for (int j = 0; j < 4; ++j) d[j] = i0 + j * B < n ? dist[(size_t)t * n + i0 + j * B] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (i0 + j * B < n) s += d[j] * d[j];
     }
     __shared__ double red[256 / kWave];
     s = block_sum(s, red);

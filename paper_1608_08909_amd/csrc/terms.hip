@@ -12,14 +12,23 @@ __global__ __launch_bounds__(256) void k_terms_max(int n, int k, const int* __re
                             int* aux) {
     int dm = 0, mx = 0;
     long long total = (long long)k * n;
-    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total;
-         q += (long long)gridDim.x * blockDim.x) {
-        int d = dist[q];
-        mx = d > mx ? d : mx;
-        if (q < n) {
-            int a = delta[q];
-            dm = a > dm ? a : dm;
-        }
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    // 16-byte loads, four in flight, when the caller's table is 16-byte
+    // aligned; the rest (or all of it) one int at a time
+    const long long n4 = ((uintptr_t)dist & 15) == 0 ? total / 4 : 0;
+    const int4* d4 = (const int4*)dist;
+    for (long long q0 = blockIdx.x * (long long)blockDim.x + threadIdx.x; q0 < n4; q0 += 4 * stride) {
+        int4 v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = q0 + j * stride < n4 ? d4[q0 + j * stride] : make_int4(0, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) mx = max(mx, max(max(v[j].x, v[j].y), max(v[j].z, v[j].w)));
+    }
+    for (long long q = 4 * n4 + blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total; q += stride)
+        mx = max(mx, dist[q]);
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += stride) {
+        const int a = delta[q];
+        dm = a > dm ? a : dm;
     }
     __shared__ int red[256 / kWave];
     dm = block_max(dm, red);
@@ -129,9 +138,17 @@ __global__ void k_terms_den(int n, int k, int W, const int* __restrict__ rp, con
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         double s = 0.0;
         for (int e = rp[i]; e < rp[i + 1]; ++e) s += 1.0;
-        for (int t = 0; t < k; ++t) {
-            int d = dist[(size_t)t * n + i];
-            if (d >= 2) s += w64[(size_t)t * W + d];
+        constexpr int U = 8;  // loads in flight; the sum keeps ascending ranks
+        for (int t0 = 0; t0 < k; t0 += U) {
+            int dv[U];
+            double wv[U];
+#pragma unroll
+            for (int j = 0; j < U; ++j) dv[j] = t0 + j < k ? dist[(size_t)(t0 + j) * n + i] : 0;
+#pragma unroll
+            for (int j = 0; j < U; ++j) wv[j] = dv[j] >= 2 ? w64[(size_t)(t0 + j) * W + dv[j]] : 0.0;
+#pragma unroll
+            for (int j = 0; j < U; ++j)
+                if (dv[j] >= 2) s += wv[j];
         }
         den64[i] = s;
         den32[i] = (float)s;
@@ -170,7 +187,8 @@ ssm_status build_terms(const ssm_csr* g, int32_t k, const int32_t* pivots, const
     hipError_t e = hipMemsetAsync(aux, 0, sizeof(int) * 2, s);
     if (e == hipSuccess) {
         long long total = (long long)k * n;
-        hipLaunchKernelGGL(k_terms_max, dim3((int)std::min<long long>((total + 255) / 256, 2048)), dim3(256),
+        // few blocks: each ends in two atomics on the same two words
+        hipLaunchKernelGGL(k_terms_max, dim3((int)std::min<long long>((total + 1023) / 1024, 512)), dim3(256),
                            0, s, n, k, dist, delta, aux);
         e = hipGetLastError();
     }

@@ -518,3 +518,19 @@ def test_validate_csr():
         with pytest.raises(ssm.SSMError) as ei:
             ssm.validate_csr(dg)
         assert ei.value.status == ssm.E_INVAL
+
+
+def test_build_terms_unaligned_table():
+    """A distance table that starts 4 bytes past a 16-byte boundary (a view
+    into a larger buffer) gives the same terms as an aligned one."""
+    g, k = G.rgg(3000, 5), 48
+    dg, piv, _, dist, delta, region, terms = _device_pipeline(g, k)
+    buf = torch.empty(dist.numel() + 1, dtype=torch.int32, device="cuda")
+    buf[1:].copy_(dist.reshape(-1))
+    view = buf[1:].view(dist.shape)
+    assert view.data_ptr() % 16 != 0
+    t2 = ssm.build_terms(dg, piv, view, delta, region)
+    a, b = terms.export(), t2.export()
+    assert a.keys() == b.keys()
+    for key in a:
+        assert np.array_equal(a[key], b[key]), key

@@ -1069,9 +1069,14 @@ __global__ void k_wpmds_mu(int n, int k, const double* __restrict__ colsum, doub
 __global__ void k_wpmds_nu(int n, int k, const double* __restrict__ dist, double* __restrict__ nu) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         double s = 0.0;
-        for (int t = 0; t < k; ++t) {
-            const double d = dist[(size_t)t * n + i];
-            s += d * d;
+        constexpr int U = 8;  // loads in flight; the sum keeps ascending ranks
+        for (int t0 = 0; t0 < k; t0 += U) {
+            double dv[U];
+#pragma unroll
+            for (int j = 0; j < U; ++j) dv[j] = t0 + j < k ? dist[(size_t)(t0 + j) * n + i] : 0.0;
+#pragma unroll
+            for (int j = 0; j < U; ++j)
+                if (t0 + j < k) s += dv[j] * dv[j];
         }
         nu[i] = s / (double)k;
     }
@@ -1138,13 +1143,19 @@ __global__ void k_wpmds_scale(int n, const double2* __restrict__ x, const double
 }
 
 // sums[0], sums[1] = the two partial arrays summed in block order.
+// sums[0..1] = the two rows of partials [2][nb] summed by one wave: lane l
+// adds q = l, l + 64, ... in ascending order, then a fixed-order wave sum
+// (deterministic).
 __global__ void k_wpmds_sum2(int nb, const double* __restrict__ partials, double* __restrict__ sums) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        double a = 0.0, b = 0.0;
-        for (int q = 0; q < nb; ++q) {
-            a += partials[q];
-            b += partials[nb + q];
-        }
+    if (blockIdx.x != 0 || threadIdx.x >= kWave) return;
+    double a = 0.0, b = 0.0;
+    for (int q = threadIdx.x; q < nb; q += kWave) {
+        a += partials[q];
+        b += partials[nb + q];
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (threadIdx.x == 0) {
         sums[0] = a;
         sums[1] = b;
     }

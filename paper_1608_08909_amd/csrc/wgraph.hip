@@ -355,14 +355,22 @@ __global__ void k_wreg_scan(int n, int k, const double* __restrict__ dist, doubl
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         double best = __longlong_as_double((long long)kInfBits);
         int cnt = 0, at = 0;
-        for (int t = 0; t < k; ++t) {
-            const double d = dist[(size_t)t * n + i];
-            if (d < best) {
-                best = d;
-                cnt = 1;
-                at = t;
-            } else if (d == best) {
-                ++cnt;
+        constexpr int U = 8;  // loads in flight; ranks compared in ascending order
+        for (int t0 = 0; t0 < k; t0 += U) {
+            double dv[U];
+#pragma unroll
+            for (int j = 0; j < U; ++j) dv[j] = t0 + j < k ? dist[(size_t)(t0 + j) * n + i] : 0.0;
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                if (t0 + j >= k) break;
+                const double d = dv[j];
+                if (d < best) {
+                    best = d;
+                    cnt = 1;
+                    at = t0 + j;
+                } else if (d == best) {
+                    ++cnt;
+                }
             }
         }
         delta[i] = best;
@@ -491,7 +499,15 @@ __global__ void k_wden(int n, int k, const int* __restrict__ rp, const double* _
             s += we;
             wl32[e] = make_float2((float)we, (float)(we * len[e]));
         }
-        for (int t = 0; t < k; ++t) s += w64[(size_t)t * n + i];
+        constexpr int U = 8;  // loads in flight; the sum keeps ascending ranks
+        for (int t0 = 0; t0 < k; t0 += U) {
+            double wv[U];
+#pragma unroll
+            for (int j = 0; j < U; ++j) wv[j] = t0 + j < k ? w64[(size_t)(t0 + j) * n + i] : 0.0;
+#pragma unroll
+            for (int j = 0; j < U; ++j)
+                if (t0 + j < k) s += wv[j];
+        }
         den64[i] = s;
         den32[i] = (float)s;
     }
@@ -704,7 +720,8 @@ ssm_status length_band(const ssm_csr* g, const double* len, unsigned long long* 
                        hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, delta, 0ull, 1LL);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, bad, 0, 1LL);
-    hipLaunchKernelGGL(k_len_check, dim3(std::max(1, std::min(div_up(g->nnz, 256), 1024))), dim3(256), 0, s,
+    // few blocks: each ends in an atomic on the same word
+    hipLaunchKernelGGL(k_len_check, dim3(std::max(1, std::min(div_up(g->nnz, 1024), 128))), dim3(256), 0, s,
                        (long long)g->nnz, len, delta, bad);
     if (const char* v = getenv("SSM_SSSP_BAND")) c = atoi(v);  // tuning override
     if (c > 1) hipLaunchKernelGGL(k_band_scale, dim3(1), dim3(64), 0, s, delta, (double)c);

@@ -392,7 +392,7 @@ def main():
                     help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(each graph's layout runs on a single device)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "serve":

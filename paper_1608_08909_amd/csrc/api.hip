@@ -200,9 +200,8 @@ void ssm_terms_free(ssm_terms* t) {
     int cur = 0;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(t->device);
-    void* ptrs[] = {t->pivots, t->H,    t->wtab64, t->wtab32, t->wt2, t->prank, t->Hf, t->invd, t->den64, t->den32, t->pc,
-                    t->dpk,    t->xtmp, t->red,    t->eig,    t->eig_iters, t->gram, t->heavy,
-                    t->seg_start, t->seg_owner, t->seg_range, t->seg_sum};
+    // the fixed-size buffers live in the arena; the heavy-row lists are separate
+    void* ptrs[] = {t->arena, t->heavy, t->seg_start, t->seg_owner, t->seg_range, t->seg_sum};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     (void)hipSetDevice(cur);

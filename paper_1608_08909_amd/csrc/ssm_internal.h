@@ -11,6 +11,7 @@
 // Device state behind an ssm_terms handle.
 struct ssm_terms {
     int device = 0;
+    void* arena = nullptr;  // one allocation holding every buffer below up to eig_iters
     int32_t n = 0, k = 0, nnz = 0;
     int32_t kpad = 0;       // k rounded up to a multiple of vec
     int32_t dmax = 0;       // max hop distance in the table

@@ -181,7 +181,7 @@ ssm_status build_terms(const ssm_csr* g, int32_t k, const int32_t* pivots, const
                        hipStream_t s) {
     const int n = g->n;
     int* aux = nullptr;
-    ssm_status st = dalloc((void**)&aux, sizeof(int) * 2);
+    ssm_status st = salloc((void**)&aux, sizeof(int) * 2);
     if (st != SSM_OK) return st;
     int h[2] = {0, 0};
     hipError_t e = hipMemsetAsync(aux, 0, sizeof(int) * 2, s);
@@ -194,7 +194,8 @@ ssm_status build_terms(const ssm_csr* g, int32_t k, const int32_t* pivots, const
     }
     if (e == hipSuccess) e = hipMemcpyAsync(h, aux, sizeof h, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(aux);
+    (void)hipStreamSynchronize(s);  // idle before the scratch is reused
+    sfree(aux);
     if (e != hipSuccess) return hip_fail(e, "terms: table extents");
     if (h[1] > 65535) return fail(SSM_E_RANGE, "distances above 65535 are not supported");
 
@@ -234,12 +235,18 @@ ssm_status build_terms(const ssm_csr* g, int32_t k, const int32_t* pivots, const
         {(void**)&t->gram, sizeof(double) * (size_t)k * k},
         {(void**)&t->eig_iters, sizeof(int)},
     };
+    // one allocation, carved at 256-byte boundaries
+    size_t total = 0;
+    for (auto& a : allocs) total += (a.bytes + 255) / 256 * 256;
+    st = dalloc(&t->arena, total);
+    if (st != SSM_OK) {
+        ssm_terms_free(t);
+        return st;
+    }
+    size_t off = 0;
     for (auto& a : allocs) {
-        st = dalloc(a.p, a.bytes);
-        if (st != SSM_OK) {
-            ssm_terms_free(t);
-            return st;
-        }
+        *a.p = (char*)t->arena + off;
+        off += (a.bytes + 255) / 256 * 256;
     }
     int grid_n = std::min(div_up(n, 256), 8192);
     e = hipMemsetAsync(t->H, 0, sizeof(int) * (size_t)k * L, s);

@@ -25,6 +25,7 @@
 struct ssm_wterms {
     int device = 0;
     int32_t n = 0, k = 0, nnz = 0;
+    void* arena = nullptr;      // one allocation holding every buffer below
     int32_t* pivots = nullptr;  // [k]
     double* dist = nullptr;     // [k][n]
     double* delta = nullptr;    // [n]
@@ -959,9 +960,7 @@ void ssm_wterms_free(ssm_wterms* t) {
     int cur = 0;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(t->device);
-    void* ps[] = {t->pivots, t->dist, t->delta, t->region, t->w64, t->wd32, t->den64, t->den32, t->wl32, t->xtmp};
-    for (void* q : ps)
-        if (q) (void)hipFree(q);
+    if (t->arena) (void)hipFree(t->arena);  // every buffer of the handle
     (void)hipSetDevice(cur);
     delete t;
 }
@@ -1013,12 +1012,18 @@ ssm_status ssm_build_terms_w(const ssm_csr* g, const double* len, int32_t k, con
         {(void**)&t->wl32, sizeof(float2) * (size_t)std::max(g->nnz, 1)},
         {(void**)&t->xtmp, sizeof(double) * 2 * (size_t)n},
     };
+    // one allocation, carved at 256-byte boundaries
+    size_t total = 0;
+    for (auto& a : allocs) total += (a.bytes + 255) / 256 * 256;
+    st = dalloc(&t->arena, total);
+    if (st != SSM_OK) {
+        ssm_wterms_free(t);
+        return st;
+    }
+    size_t off = 0;
     for (auto& a : allocs) {
-        st = dalloc(a.p, a.bytes);
-        if (st != SSM_OK) {
-            ssm_wterms_free(t);
-            return st;
-        }
+        *a.p = (char*)t->arena + off;
+        off += (a.bytes + 255) / 256 * 256;
     }
     hipError_t e = hipMemcpyAsync(t->pivots, pivots, sizeof(int) * (size_t)k, hipMemcpyDeviceToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(t->dist, dist, sizeof(double) * kn, hipMemcpyDeviceToDevice, stream);

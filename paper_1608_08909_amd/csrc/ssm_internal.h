@@ -11,7 +11,7 @@
 // Device state behind an ssm_terms handle.
 struct ssm_terms {
     int device = 0;
-    void* arena = nullptr;  // one allocation holding every buffer below up to eig_iters
+    void* arena = nullptr;  // one allocation holding every fixed-size buffer below
     int32_t n = 0, k = 0, nnz = 0;
     int32_t kpad = 0;       // k rounded up to a multiple of vec
     int32_t dmax = 0;       // max hop distance in the table
@@ -44,6 +44,20 @@ struct ssm_terms {
     int32_t* seg_owner = nullptr;  // [nseg] heavy row of each segment
     int2* seg_range = nullptr;     // [n] at a heavy node's id: its segments [x, y)
     float2* seg_sum = nullptr;     // [nseg] FP32 sweep scratch: neighbour displacement sum per segment
+    // Node order of the FP32 sweep (all null when off): nodes sorted by
+    // (region, delta, id), so that a wavefront's nodes and their neighbours
+    // lie close in memory.  The sweep runs on a renumbered copy of the graph
+    // (every row keeps its neighbour order) and of its per-node data; each
+    // node's arithmetic is unchanged.  The heavy-row lists above then hold
+    // new ids.
+    int32_t* perm = nullptr;    // [n] new id -> node
+    int32_t* inv = nullptr;     // [n] node -> new id
+    int32_t* prp = nullptr;     // [n + 1] renumbered CSR
+    int32_t* pci = nullptr;     // [nnz]
+    void* pdpk = nullptr;       // packed distances, new order
+    float* pden32 = nullptr;    // [n]
+    int32_t* pprank = nullptr;  // [n]
+    int32_t* ppiv = nullptr;    // [kpad] the pivots' new ids
 };
 
 namespace ssm {
@@ -92,6 +106,10 @@ ssm_status kmeans_pivots(int32_t n, int32_t k, const int32_t* pivots, const int3
 
 // Heavy list, its arc segments and the FP32 sweep's scratch for them.
 ssm_status heavy_segments(const ssm_csr* g, ssm_terms* t, hipStream_t s);
+// FP32 sweep order (when t->perm is allocated) and the heavy-row lists.
+ssm_status sweep_order(const ssm_csr* g, ssm_terms* t, const int32_t* dist, const int32_t* delta,
+                       const int32_t* region, hipStream_t s);
+bool sweep_order_enabled();
 ssm_status regions(int32_t n, int32_t k, const int32_t* dist, int32_t* delta, int32_t* region,
                    hipStream_t s);
 

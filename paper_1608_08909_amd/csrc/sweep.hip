@@ -6,6 +6,8 @@
 
 #include <vector>
 
+#include <hipcub/hipcub.hpp>
+
 #include "ssm_internal.h"
 #include "wave.h"
 
@@ -376,6 +378,130 @@ ssm_status heavy_segments(const ssm_csr* g, ssm_terms* t, hipStream_t s) {
     return SSM_OK;
 }
 
+// ------------------------------------------------ FP32 sweep node order
+
+bool sweep_order_enabled() {  // tuning override SSM_SWEEP_PERM=0: the caller's node order
+    const char* v = getenv("SSM_SWEEP_PERM");
+    return !(v && atoi(v) == 0);
+}
+
+__global__ void k_order_keys(int n, const int* __restrict__ delta, const int* __restrict__ region,
+                             unsigned long long* __restrict__ key, int* __restrict__ val) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        key[i] = ((unsigned long long)(unsigned)region[i] << 32) | (unsigned)delta[i];
+        val[i] = i;
+    }
+}
+
+// Per new row r (node perm[r]): inv, row length, denominator, pivot rank.
+__global__ void k_order_rows(int n, const int* __restrict__ perm, const int* __restrict__ rp,
+                             const float* __restrict__ den32, const int* __restrict__ prank, int* __restrict__ inv,
+                             int* __restrict__ deg, float* __restrict__ pden, int* __restrict__ pprank) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) deg[n] = 0;  // the scan's last entry
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+        const int o = perm[r];
+        inv[o] = r;
+        deg[r] = rp[o + 1] - rp[o];
+        pden[r] = den32[o];
+        pprank[r] = prank[o];
+    }
+}
+
+// Renumbered rows: row r is node perm[r]'s row, its neighbours' new ids in
+// the same order.
+__global__ void k_order_csr(int n, const int* __restrict__ perm, const int* __restrict__ inv,
+                            const int* __restrict__ rp, const int* __restrict__ ci, const int* __restrict__ prp,
+                            int* __restrict__ pci) {
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+        const int o = perm[r], a = rp[o], d = rp[o + 1] - a, b = prp[r];
+        for (int j = 0; j < d; ++j) pci[b + j] = inv[ci[a + j]];
+    }
+}
+
+// Packed distances in the new order (as k_terms_pack, node perm[r] at r).
+template <typename DT, int VEC>
+__global__ void k_order_pack(int n, int k, int kpad, const int* __restrict__ perm, const int* __restrict__ dist,
+                             uint4* __restrict__ out) {
+    const long long total = (long long)(kpad / VEC) * n;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total;
+         q += (long long)gridDim.x * blockDim.x) {
+        const int b = (int)(q / n), r = (int)(q % n), o = perm[r];
+        Packed<DT, VEC> u;
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            const int t = b * VEC + j;
+            u.e[j] = t < k ? (DT)dist[(size_t)t * n + o] : (DT)0;
+        }
+        out[q] = u.v;
+    }
+}
+
+__global__ void k_order_piv(int kpad, const int* __restrict__ piv, const int* __restrict__ inv, int* __restrict__ ppiv) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < kpad; t += gridDim.x * blockDim.x) ppiv[t] = inv[piv[t]];
+}
+
+__global__ void k_perm_gather(int n, const int* __restrict__ perm, const float2* __restrict__ x, float2* __restrict__ y) {
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) y[r] = x[perm[r]];
+}
+
+__global__ void k_perm_scatter(int n, const int* __restrict__ perm, const float2* __restrict__ y, float2* __restrict__ x) {
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) x[perm[r]] = y[r];
+}
+
+ssm_status sweep_order(const ssm_csr* g, ssm_terms* t, const int32_t* dist, const int32_t* delta,
+                       const int32_t* region, hipStream_t s) {
+    if (!t->perm) return heavy_segments(g, t, s);
+    const int n = t->n;
+    const int gb = std::min(div_up(n, 256), 8192);
+    // scratch: keys (2 n u64), values (n ints), row lengths (n + 1 ints), sort and scan space
+    size_t sort_bytes = 0, scan_bytes = 0;
+    SSM_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (unsigned long long*)nullptr,
+                                               (unsigned long long*)nullptr, (int*)nullptr, (int*)nullptr, n, 0,
+                                               64, s));
+    SSM_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, (int*)nullptr, (int*)nullptr, n + 1, s));
+    const size_t tmp_bytes = std::max(sort_bytes, scan_bytes);
+    const size_t bytes = sizeof(unsigned long long) * 2 * (size_t)n + sizeof(int) * (2 * (size_t)n + 1) + tmp_bytes + 512;
+    char* ws = nullptr;
+    ssm_status st = salloc((void**)&ws, bytes);
+    if (st != SSM_OK) return st;
+    unsigned long long* kin = (unsigned long long*)ws;
+    unsigned long long* kout = kin + n;
+    int* vin = (int*)(kout + n);
+    int* deg = vin + n;
+    void* tmp = (void*)(((uintptr_t)(deg + n + 1) + 255) & ~(uintptr_t)255);
+    hipError_t e = hipSuccess;
+    hipLaunchKernelGGL(k_order_keys, dim3(gb), dim3(256), 0, s, n, delta, region, kin, vin);
+    size_t tb = sort_bytes;
+    e = hipcub::DeviceRadixSort::SortPairs(tmp, tb, kin, kout, vin, t->perm, n, 0, 64, s);  // stable: ids ascend
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_order_rows, dim3(gb), dim3(256), 0, s, n, t->perm, g->row_ptr, t->den32, t->prank,
+                           t->inv, deg, t->pden32, t->pprank);
+        size_t sb = scan_bytes;
+        e = hipcub::DeviceScan::ExclusiveSum(tmp, sb, deg, t->prp, n + 1, s);
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_order_csr, dim3(gb), dim3(256), 0, s, n, t->perm, t->inv, g->row_ptr, g->col_idx,
+                           t->prp, t->pci);
+        const long long words = (long long)(t->kpad / t->vec) * n;
+        const dim3 gp((int)std::min<long long>((words + 255) / 256, 16384));
+        if (t->dbytes == 1)
+            hipLaunchKernelGGL((k_order_pack<uint8_t, 16>), gp, dim3(256), 0, s, n, t->k, t->kpad, t->perm, dist,
+                               (uint4*)t->pdpk);
+        else
+            hipLaunchKernelGGL((k_order_pack<uint16_t, 8>), gp, dim3(256), 0, s, n, t->k, t->kpad, t->perm, dist,
+                               (uint4*)t->pdpk);
+        hipLaunchKernelGGL(k_order_piv, dim3(div_up(t->kpad, 256)), dim3(256), 0, s, t->kpad, t->pivots, t->inv,
+                           t->ppiv);
+        e = hipGetLastError();
+    }
+    const hipError_t e2 = hipStreamSynchronize(s);  // idle before the scratch is reused
+    sfree(ws);
+    if (e != hipSuccess) return hip_fail(e, "terms: sweep order");
+    if (e2 != hipSuccess) return hip_fail(e2, "terms: sweep order");
+    const ssm_csr gp = {n, t->nnz, t->prp, t->pci};
+    return heavy_segments(&gp, t, s);
+}
+
 // ----------------------------------------------------------- stress
 
 template <typename T2>
@@ -590,11 +716,13 @@ static SweepPlan plan_sweep(const ssm_terms* t, ssm_prec p) {
     return pl;
 }
 
-ssm_status majorize(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* x, int32_t iters, double tol,
-                    int32_t* iters_done_host, hipStream_t s) {
+// The sweep loop over buffers bufs[0] (in/out) and bufs[1]; the result ends
+// in bufs[0].
+static ssm_status sweep_loop(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* const (&bufs)[2], int32_t iters,
+                             double tol, int32_t* iters_done_host, hipStream_t s) {
     const SweepPlan pl = plan_sweep(t, p);
     const size_t xbytes = (p == SSM_FP64 ? sizeof(double) : sizeof(float)) * 2 * (size_t)t->n;
-    void* bufs[2] = {x, t->xtmp};
+    void* const x = bufs[0];
     int cur = 0, done = 0;
     const int cblocks = std::min(div_up(t->n, 256), 2048);
     float2* pcb[2] = {t->pc, t->pc + t->kpad};
@@ -624,11 +752,38 @@ ssm_status majorize(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* x, int32_t
         }
     }
     SSM_HIP(hipGetLastError());
-    if (cur == 1) SSM_HIP(hipMemcpyAsync(x, t->xtmp, xbytes, hipMemcpyDeviceToDevice, s));
+    if (cur == 1) SSM_HIP(hipMemcpyAsync(x, bufs[1], xbytes, hipMemcpyDeviceToDevice, s));
     if (iters_done_host) {
         SSM_HIP(hipStreamSynchronize(s));
         *iters_done_host = done;
     }
+    return SSM_OK;
+}
+
+ssm_status majorize(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* x, int32_t iters, double tol,
+                    int32_t* iters_done_host, hipStream_t s) {
+    if (p != SSM_FP32 || !t->perm || iters <= 0) {
+        void* const bufs[2] = {x, t->xtmp};
+        return sweep_loop(g, t, p, bufs, iters, tol, iters_done_host, s);
+    }
+    // FP32 in the sweep order: the renumbered graph and per-node data, the
+    // coordinates gathered into the two halves of xtmp and scattered back
+    const int n = t->n;
+    const ssm_csr gp = {n, t->nnz, t->prp, t->pci};
+    ssm_terms tv = *t;
+    tv.dpk = t->pdpk;
+    tv.den32 = t->pden32;
+    tv.prank = t->pprank;
+    tv.pivots = t->ppiv;
+    float2* xa = (float2*)t->xtmp;
+    float2* xb = xa + n;
+    const int gb = std::min(div_up(n, 256), 8192);
+    hipLaunchKernelGGL(k_perm_gather, dim3(gb), dim3(256), 0, s, n, t->perm, (const float2*)x, xa);
+    void* const bufs[2] = {xa, xb};
+    ssm_status st = sweep_loop(&gp, &tv, p, bufs, iters, tol, iters_done_host, s);
+    if (st != SSM_OK) return st;
+    hipLaunchKernelGGL(k_perm_scatter, dim3(gb), dim3(256), 0, s, n, t->perm, (const float2*)xa, (float2*)x);
+    SSM_HIP(hipGetLastError());
     return SSM_OK;
 }
 

@@ -213,6 +213,7 @@ ssm_status build_terms(const ssm_csr* g, int32_t k, const int32_t* pivots, const
     const int L = t->delta_max + 1;
     const size_t kw = (size_t)t->kpad * t->W;
     t->red_len = 8192;
+    const bool ordered = sweep_order_enabled();
     struct {
         void** p;
         size_t bytes;
@@ -234,6 +235,15 @@ ssm_status build_terms(const ssm_csr* g, int32_t k, const int32_t* pivots, const
         {(void**)&t->eig, sizeof(double) * (2 * (size_t)k + 2)},
         {(void**)&t->gram, sizeof(double) * (size_t)k * k},
         {(void**)&t->eig_iters, sizeof(int)},
+        // the FP32 sweep's node order (sizes 0 when off)
+        {(void**)&t->perm, ordered ? sizeof(int) * (size_t)n : 0},
+        {(void**)&t->inv, ordered ? sizeof(int) * (size_t)n : 0},
+        {(void**)&t->prp, ordered ? sizeof(int) * ((size_t)n + 1) : 0},
+        {(void**)&t->pci, ordered ? sizeof(int) * (size_t)std::max(g->nnz, 1) : 0},
+        {(void**)&t->pdpk, ordered ? (size_t)t->kpad * n * t->dbytes : 0},
+        {(void**)&t->pden32, ordered ? sizeof(float) * (size_t)n : 0},
+        {(void**)&t->pprank, ordered ? sizeof(int) * (size_t)n : 0},
+        {(void**)&t->ppiv, ordered ? sizeof(int) * (size_t)t->kpad : 0},
     };
     // one allocation, carved at 256-byte boundaries
     size_t total = 0;
@@ -245,7 +255,7 @@ ssm_status build_terms(const ssm_csr* g, int32_t k, const int32_t* pivots, const
     }
     size_t off = 0;
     for (auto& a : allocs) {
-        *a.p = (char*)t->arena + off;
+        *a.p = a.bytes ? (char*)t->arena + off : nullptr;
         off += (a.bytes + 255) / 256 * 256;
     }
     int grid_n = std::min(div_up(n, 256), 8192);
@@ -282,7 +292,8 @@ ssm_status build_terms(const ssm_csr* g, int32_t k, const int32_t* pivots, const
         return hip_fail(e, "terms: build");
     }
     // high-degree nodes (their neighbour sums get whole wavefronts)
-    st = heavy_segments(g, t, s);
+    // the FP32 sweep's node order, then the heavy-row lists (in that order)
+    st = sweep_order(g, t, dist, delta, region, s);
     if (st != SSM_OK) {
         ssm_terms_free(t);
         return st;

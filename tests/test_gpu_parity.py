@@ -534,3 +534,25 @@ def test_build_terms_unaligned_table():
     assert a.keys() == b.keys()
     for key in a:
         assert np.array_equal(a[key], b[key]), key
+
+
+@pytest.mark.parametrize("g,k", [(G.barabasi_albert(20000, 5, 3), 37), (G.rgg(3000, 5), 48), (G.grid(13, 17), 10),
+                                 (G.holed_mesh(120, 130, 6, 4, 12, 5), 40)],
+                         ids=["ba20000", "rgg3000", "grid13x17", "holedmesh120"])
+def test_sweep_order_bit_identical(g, k, monkeypatch):
+    """The FP32 sweep renumbers the nodes (by region, then delta) for
+    locality; every node's arithmetic is unchanged, so the coordinates equal
+    those of sweeps in the caller's order bit for bit (rows above the heavy
+    degree, padded ranks, a ragged last chunk)."""
+    outs = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("SSM_SWEEP_PERM", flag)
+        dg, *_, terms = _device_pipeline(g, k)
+        x0 = ssm.pivotmds_init(dg, terms, ssm.FP32)
+        x = x0.clone()
+        ssm.majorize(dg, terms, x, 25, sync=True)
+        outs.append((x0.cpu().numpy(), x.cpu().numpy(), ssm.stress(dg, terms, x)))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.isfinite(outs[0][1]).all()
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert outs[0][2] == outs[1][2]

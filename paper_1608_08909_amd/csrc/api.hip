@@ -200,8 +200,11 @@ void ssm_terms_free(ssm_terms* t) {
     int cur = 0;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(t->device);
-    // the fixed-size buffers live in the arena; the heavy-row lists are separate
-    void* ptrs[] = {t->arena, t->heavy, t->seg_start, t->seg_owner, t->seg_range, t->seg_sum};
+    // the fixed-size buffers live in the arena (scratch cache: returned only
+    // once the device is idle); the heavy-row lists are separate
+    (void)hipDeviceSynchronize();
+    sfree(t->arena);
+    void* ptrs[] = {t->heavy, t->seg_start, t->seg_owner, t->seg_range, t->seg_sum};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     (void)hipSetDevice(cur);

@@ -245,10 +245,12 @@ ssm_status build_terms(const ssm_csr* g, int32_t k, const int32_t* pivots, const
         {(void**)&t->pprank, ordered ? sizeof(int) * (size_t)n : 0},
         {(void**)&t->ppiv, ordered ? sizeof(int) * (size_t)t->kpad : 0},
     };
-    // one allocation, carved at 256-byte boundaries
+    // one allocation, carved at 256-byte boundaries, from the scratch cache
+    // (a layout pipeline builds and frees a handle of the same size each time;
+    // every buffer is written before it is read)
     size_t total = 0;
     for (auto& a : allocs) total += (a.bytes + 255) / 256 * 256;
-    st = dalloc(&t->arena, total);
+    st = salloc(&t->arena, total);
     if (st != SSM_OK) {
         ssm_terms_free(t);
         return st;

@@ -960,7 +960,8 @@ void ssm_wterms_free(ssm_wterms* t) {
     int cur = 0;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(t->device);
-    if (t->arena) (void)hipFree(t->arena);  // every buffer of the handle
+    (void)hipDeviceSynchronize();  // the scratch cache takes the arena back once the device is idle
+    sfree(t->arena);               // every buffer of the handle
     (void)hipSetDevice(cur);
     delete t;
 }
@@ -1012,10 +1013,11 @@ ssm_status ssm_build_terms_w(const ssm_csr* g, const double* len, int32_t k, con
         {(void**)&t->wl32, sizeof(float2) * (size_t)std::max(g->nnz, 1)},
         {(void**)&t->xtmp, sizeof(double) * 2 * (size_t)n},
     };
-    // one allocation, carved at 256-byte boundaries
+    // one allocation, carved at 256-byte boundaries, from the scratch cache
+    // (every buffer is written before it is read)
     size_t total = 0;
     for (auto& a : allocs) total += (a.bytes + 255) / 256 * 256;
-    st = dalloc(&t->arena, total);
+    st = salloc(&t->arena, total);
     if (st != SSM_OK) {
         ssm_wterms_free(t);
         return st;

@@ -380,9 +380,10 @@ ssm_status heavy_segments(const ssm_csr* g, ssm_terms* t, hipStream_t s) {
 
 // ------------------------------------------------ FP32 sweep node order
 
-bool sweep_order_enabled() {  // tuning override SSM_SWEEP_PERM=0: the caller's node order
+int sweep_order_mode() {  // tuning override SSM_SWEEP_PERM: 0 = the caller's order, 2 = always reorder
     const char* v = getenv("SSM_SWEEP_PERM");
-    return !(v && atoi(v) == 0);
+    const int m = v ? atoi(v) : 1;
+    return m == 0 || m == 2 ? m : 1;
 }
 
 __global__ void k_order_keys(int n, const int* __restrict__ delta, const int* __restrict__ region,

@@ -99,86 +99,133 @@ __device__ __forceinline__ double centred_d(double d, double mu_t, double nu_i, 
     return -0.5 * (d * d - mu_t - nu_i + gamma);
 }
 
-constexpr int kGramSub = 8;   // nodes staged per LDS round (two K-steps of 4)
 constexpr int kGramTPW = 8;   // output tiles per wave
 constexpr int kGramWaves = 4;
+constexpr int kGramPF = 4;    // packed words per thread prefetched for the next round
+#ifndef SSM_GRAM_PREFETCH
+#define SSM_GRAM_PREFETCH 1
+#endif
+constexpr bool kGramPrefetch = SSM_GRAM_PREFETCH;
+constexpr int kGramMinChunk = 256;  // nodes per Gram chunk at least
+
+// Nodes staged per LDS round of the Gram product: 32 (eight K-steps of 4)
+// when the staged block fits the default 64 KB of LDS, else 8.  The block
+// holds C pivot-major, kp rows of SUB + 1 doubles (the odd stride keeps the
+// staging stores of consecutive nodes in distinct banks), then mu.
+template <int SUB>
+constexpr size_t gram_lds_bytes(int kp) {
+    return sizeof(double) * ((size_t)kp * (SUB + 1) + kp);
+}
+static int gram_sub(int kp) { return gram_lds_bytes<32>(kp) <= 64 * 1024 ? 32 : 8; }
 
 // Split-K Gram product M = C^T C on v_mfma_f64_16x16x4_f64.  Block (c, g):
 // node chunk c, tile group g (kGramWaves * kGramTPW tiles of the upper
 // triangle).  C is formed on the fly from the packed distances and staged in
-// LDS (kGramSub nodes x kp columns); each wave accumulates its tiles and
-// writes the chunk's partial tiles.  Operand layout per lane l: A[i][q] and
-// B[q][j] with i = j = l % 16, q = l / 16; result lane l, element v holds
-// row 4 v + l / 16, column l % 16.
-template <typename DT, int VEC>
+// LDS (SUB nodes per round); each wave accumulates its tiles over the chunk's
+// nodes in ascending order and writes the chunk's partial tiles.  Operand
+// layout per lane l: A[i][q] and B[q][j] with i = j = l % 16, q = l / 16;
+// result lane l, element v holds row 4 v + l / 16, column l % 16.
+template <typename DT, int VEC, int SUB>
 __device__ __forceinline__ void pmds_gram_body(int c, int grp, int n, int k, int kp, int kpad, int chunk,
                                                const uint4* __restrict__ dpk, const double* __restrict__ mu,
                                                const double* __restrict__ nu, const double* __restrict__ stats,
                                                const int2* __restrict__ tiles, int ntiles,
                                                double* __restrict__ part) {
+    constexpr int SP = SUB + 1;           // row stride of the staged block
     extern __shared__ double smem[];
-    double* Cs = smem;                    // [kGramSub][kp]
-    double* smu = smem + kGramSub * kp;   // [kp]
-    const int lane = lane_id(), w = threadIdx.x / kWave;
+    double* Cs = smem;                    // [kp][SP]: Cs[t * SP + r] = C of node i0 + r, pivot t
+    double* smu = smem + (size_t)kp * SP; // [kp]
+    const int lane = lane_id();
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
     const double gamma = stats[0];
     for (int t = threadIdx.x; t < kp; t += blockDim.x) smu[t] = t < k ? mu[t] : 0.0;
-    int my_tiles[kGramTPW];
+    // this wave's tiles and their operand offsets in the staged block, read once
+    int my_tiles[kGramTPW], offa[kGramTPW], offb[kGramTPW];
     int nmine = 0;
 #pragma unroll
     for (int j = 0; j < kGramTPW; ++j) {
-        int id = (grp * kGramWaves + w) * kGramTPW + j;
+        const int id = (grp * kGramWaves + w) * kGramTPW + j;
         my_tiles[j] = id < ntiles ? id : -1;
         nmine += id < ntiles;
+        const int2 ab = id < ntiles ? tiles[id] : make_int2(0, 0);
+        offa[j] = 16 * ab.x * SP;
+        offb[j] = 16 * ab.y * SP;
     }
     dbl4 acc[kGramTPW];
 #pragma unroll
     for (int j = 0; j < kGramTPW; ++j) acc[j] = (dbl4){0.0, 0.0, 0.0, 0.0};
     const int i_begin = c * chunk, i_end = min(n, i_begin + chunk);
     const int nwords = VEC > 0 ? kpad / VEC : 0;
+    // Packed inputs: when a round's SUB x nwords words fit kGramPF per thread,
+    // the next round's words and nu are loaded into registers while this
+    // round's MFMAs run.
+    const bool pf = kGramPrefetch && VEC > 0 && SUB * nwords <= kGramPF * (int)blockDim.x;  // uniform
+    uint4 pv[kGramPF];
+    double pn[kGramPF];
+    auto load_round = [&](int i0) {
+#pragma unroll
+        for (int p = 0; p < kGramPF; ++p) {
+            const int q = threadIdx.x + p * (int)blockDim.x;
+            const int r = q % SUB, i = i0 + r;
+            const bool in = q < SUB * nwords && i < i_end;
+            pv[p] = in ? dpk[(size_t)(q / SUB) * n + i] : make_uint4(0, 0, 0, 0);
+            pn[p] = in ? nu[i] : 0.0;
+        }
+    };
+    if (pf) load_round(i_begin);
     __syncthreads();
-    for (int i0 = i_begin; i0 < i_end; i0 += kGramSub) {
-        // stage C for nodes i0 .. i0 + kGramSub - 1 (zero past n and past k);
+    for (int i0 = i_begin; i0 < i_end; i0 += SUB) {
+        // stage C for nodes i0 .. i0 + SUB - 1 (zero past the chunk and past k);
         // VEC == 0: dpk holds real distance rows [k][n] (FP64)
         if constexpr (VEC == 0) {
             const double* dd = (const double*)dpk;
-            for (int q = threadIdx.x; q < kGramSub * kp; q += blockDim.x) {
-                const int r = q % kGramSub, t = q / kGramSub, i = i0 + r;
-                Cs[r * kp + t] = (i < i_end && t < k) ? centred_d(dd[(size_t)t * n + i], smu[t], nu[i], gamma) : 0.0;
+            for (int q = threadIdx.x; q < SUB * kp; q += blockDim.x) {
+                const int r = q % SUB, t = q / SUB, i = i0 + r;
+                Cs[t * SP + r] = (i < i_end && t < k) ? centred_d(dd[(size_t)t * n + i], smu[t], nu[i], gamma) : 0.0;
             }
         } else {
-        for (int q = threadIdx.x; q < kGramSub * nwords; q += blockDim.x) {
-            int r = q % kGramSub, b = q / kGramSub;
-            int i = i0 + r;
-            union {
-                uint4 v;
-                DT e[VEC];
-            } u;
-            u.v = i < i_end ? dpk[(size_t)b * n + i] : make_uint4(0, 0, 0, 0);
-            double nui = i < i_end ? nu[i] : 0.0;
+            auto put = [&](int q, const uint4 v, double nui) {  // the VEC values of item q
+                const int r = q % SUB, b = q / SUB, i = i0 + r;
+                union {
+                    uint4 v;
+                    DT e[VEC];
+                } u;
+                u.v = v;
 #pragma unroll
-            for (int j = 0; j < VEC; ++j) {
-                int t = b * VEC + j;
-                double val = (i < i_end && t < k) ? centred((int)u.e[j], smu[t], nui, gamma) : 0.0;
-                Cs[r * kp + t] = val;
+                for (int j = 0; j < VEC; ++j) {
+                    const int t = b * VEC + j;
+                    Cs[t * SP + r] = (i < i_end && t < k) ? centred((int)u.e[j], smu[t], nui, gamma) : 0.0;
+                }
+            };
+            if (pf) {
+#pragma unroll
+                for (int p = 0; p < kGramPF; ++p) {
+                    const int q = threadIdx.x + p * (int)blockDim.x;
+                    if (q < SUB * nwords) put(q, pv[p], pn[p]);
+                }
+            } else {
+                for (int q = threadIdx.x; q < SUB * nwords; q += blockDim.x) {
+                    const int i = i0 + q % SUB;
+                    put(q, i < i_end ? dpk[(size_t)(q / SUB) * n + i] : make_uint4(0, 0, 0, 0),
+                        i < i_end ? nu[i] : 0.0);
+                }
+            }
+            for (int q = threadIdx.x; q < SUB * (kp - kpad); q += blockDim.x) {
+                const int r = q % SUB, t = kpad + q / SUB;
+                Cs[t * SP + r] = 0.0;
             }
         }
-        for (int q = threadIdx.x; q < kGramSub * (kp - kpad); q += blockDim.x) {
-            int r = q / (kp - kpad), t = kpad + q % (kp - kpad);
-            Cs[r * kp + t] = 0.0;
-        }
-        }
         __syncthreads();
+        if (pf && i0 + SUB < i_end) load_round(i0 + SUB);  // uniform
+        const double* col = Cs + (lane % 16) * SP + lane / 16;
 #pragma unroll
-        for (int ks = 0; ks < kGramSub / 4; ++ks) {
-            const double* row = Cs + (ks * 4 + lane / 16) * kp + (lane % 16);
+        for (int ks = 0; ks < SUB / 4; ++ks) {
 #pragma unroll
             for (int j = 0; j < kGramTPW; ++j) {
-                if (j < nmine) {
-                    int2 ab = tiles[my_tiles[j]];
-                    double a = row[16 * ab.x];
-                    double bb = row[16 * ab.y];
-                    acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc[j], 0, 0, 0);
-                }
+                // a missing tile (j >= nmine) reads tile (0, 0) and is never stored
+                const double a = col[offa[j] + 4 * ks];
+                const double bb = col[offb[j] + 4 * ks];
+                acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc[j], 0, 0, 0);
             }
         }
         __syncthreads();
@@ -193,7 +240,7 @@ __device__ __forceinline__ void pmds_gram_body(int c, int grp, int n, int k, int
     }
 }
 
-template <typename DT, int VEC>
+template <typename DT, int VEC, int SUB>
 __global__ __launch_bounds__(256) void k_pmds_gram(int n, int k, int kp, int kpad, int chunk,
                                                    const uint4* __restrict__ dpk,
                                                    const double* __restrict__ mu,
@@ -201,7 +248,26 @@ __global__ __launch_bounds__(256) void k_pmds_gram(int n, int k, int kp, int kpa
                                                    const double* __restrict__ stats,
                                                    const int2* __restrict__ tiles, int ntiles,
                                                    double* __restrict__ part) {
-    pmds_gram_body<DT, VEC>(blockIdx.x, blockIdx.y, n, k, kp, kpad, chunk, dpk, mu, nu, stats, tiles, ntiles, part);
+    pmds_gram_body<DT, VEC, SUB>(blockIdx.x, blockIdx.y, n, k, kp, kpad, chunk, dpk, mu, nu, stats, tiles, ntiles,
+                                 part);
+}
+
+// Launches k_pmds_gram with the round size gram_sub(kp) (chunk a multiple of it).
+template <typename DT, int VEC>
+static void launch_gram(dim3 grid, hipStream_t s, int n, int k, int kp, int kpad, int chunk, const uint4* dpk,
+                        const double* mu, const double* nu, const double* stats, const int2* tiles, int ntiles,
+                        double* part) {
+    if (gram_sub(kp) == 32) {
+        hipLaunchKernelGGL((k_pmds_gram<DT, VEC, 32>), grid, dim3(256), gram_lds_bytes<32>(kp), s, n, k, kp, kpad,
+                           chunk, dpk, mu, nu, stats, tiles, ntiles, part);
+    } else {
+        const size_t lds = gram_lds_bytes<8>(kp);
+        if (lds > 64 * 1024)  // above the default dynamic LDS limit
+            (void)hipFuncSetAttribute((const void*)k_pmds_gram<DT, VEC, 8>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL((k_pmds_gram<DT, VEC, 8>), grid, dim3(256), lds, s, n, k, kp, kpad, chunk, dpk, mu, nu,
+                           stats, tiles, ntiles, part);
+    }
 }
 
 // M (k x k, row-major) = sum over chunks in ascending order of the partial
@@ -783,8 +849,9 @@ ssm_status pivotmds(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* x, hipStre
     const int ntiles = (int)htiles.size();
     const int per_group = kGramWaves * kGramTPW;
     const int ngroups = div_up(ntiles, per_group);
-    int nchunks = std::max(1, std::min(div_up(n, 1024), std::max(1, 4 * num_cus() / ngroups)));
-    int chunk = div_up(div_up(n, nchunks), kGramSub) * kGramSub;
+    int nchunks = std::max(1, std::min(div_up(n, kGramMinChunk), std::max(1, 4 * num_cus() / ngroups)));
+    const int sub = gram_sub(kp);
+    int chunk = div_up(div_up(n, nchunks), sub) * sub;
     nchunks = div_up(n, chunk);
     // workspace: colsum (k ll), mu (k), nu (n), stats (4), M (k*k), part, tiles, edge partials
     const int eblocks = std::min(div_up(n, 256), 2048);
@@ -825,14 +892,13 @@ ssm_status pivotmds(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* x, hipStre
             hipLaunchKernelGGL((k_pmds_nu<uint16_t, 8>), dim3(gn), dim3(256), 0, s, n, k, nwords, dpk, nu);
         }
         hipLaunchKernelGGL(k_pmds_mu, dim3(1), dim3(64), 0, s, n, k, t->kpad, colsum, mu, stats);
-        size_t lds = sizeof(double) * ((size_t)kGramSub * kp + kp);
         dim3 gg(nchunks, ngroups);
         if (t->dbytes == 1)
-            hipLaunchKernelGGL((k_pmds_gram<uint8_t, 16>), gg, dim3(256), lds, s, n, k, kp, t->kpad, chunk,
-                               (const uint4*)t->dpk, mu, nu, stats, tiles, ntiles, part);
+            launch_gram<uint8_t, 16>(gg, s, n, k, kp, t->kpad, chunk, (const uint4*)t->dpk, mu, nu, stats, tiles,
+                                     ntiles, part);
         else
-            hipLaunchKernelGGL((k_pmds_gram<uint16_t, 8>), gg, dim3(256), lds, s, n, k, kp, t->kpad, chunk,
-                               (const uint4*)t->dpk, mu, nu, stats, tiles, ntiles, part);
+            launch_gram<uint16_t, 8>(gg, s, n, k, kp, t->kpad, chunk, (const uint4*)t->dpk, mu, nu, stats, tiles,
+                                     ntiles, part);
         hipLaunchKernelGGL(k_pmds_gram_reduce, dim3(std::min(div_up((long long)ntiles * 256, 256), 4096)),
                            dim3(256), 0, s, k, nchunks, ntiles, tiles, part, M);
         const size_t elds = eig_lds_bytes(k);
@@ -927,7 +993,7 @@ __global__ __launch_bounds__(256) void k_pool_gram(const PoolGraph* __restrict__
     const int4 it = items[blockIdx.x];
     const PoolGraph& g = gs[it.x];
     const int kp = (g.k + 15) / 16 * 16;
-    pmds_gram_body<uint16_t, 8>(it.y, it.z, g.n, g.k, kp, g.kpad, kPoolGramChunk, g.dpk, g.mu, g.nu, g.stats, tiles,
+    pmds_gram_body<uint16_t, 8, 8>(it.y, it.z, g.n, g.k, kp, g.kpad, kPoolGramChunk, g.dpk, g.mu, g.nu, g.stats, tiles,
                                 g.ntiles, g.gpart);
 }
 
@@ -1025,7 +1091,7 @@ __global__ __launch_bounds__(1024) void k_pool_project(const PoolGraph* __restri
 hipError_t pool_pivotmds(const PoolGraph* gs, int count, const int4* gram_items, int ngram, const int2* tiles,
                          int kp_max, int k_max, hipStream_t s) {
     hipLaunchKernelGGL(k_pool_mds_stats, dim3(count), dim3(1024), 0, s, gs);
-    hipLaunchKernelGGL(k_pool_gram, dim3(ngram), dim3(256), sizeof(double) * ((size_t)kGramSub * kp_max + kp_max), s,
+    hipLaunchKernelGGL(k_pool_gram, dim3(ngram), dim3(256), gram_lds_bytes<8>(kp_max), s,
                        gs, gram_items, tiles);
     hipLaunchKernelGGL(k_pool_gram_reduce, dim3(32, count), dim3(256), 0, s, gs, tiles);
     hipLaunchKernelGGL(k_pool_eig, dim3(count), dim3(kEigThreads), eig_lds_bytes(k_max), s, gs);
@@ -1171,8 +1237,9 @@ ssm_status pivotmds_w(const ssm_csr* g, const double* len, int k, const double* 
         for (int b = a; b < T; ++b) htiles.push_back(make_int2(a, b));
     const int ntiles = (int)htiles.size();
     const int ngroups = div_up(ntiles, kGramWaves * kGramTPW);
-    int nchunks = std::max(1, std::min(div_up(n, 1024), std::max(1, 4 * num_cus() / ngroups)));
-    const int chunk = div_up(div_up(n, nchunks), kGramSub) * kGramSub;
+    int nchunks = std::max(1, std::min(div_up(n, kGramMinChunk), std::max(1, 4 * num_cus() / ngroups)));
+    const int sub = gram_sub(kp);
+    const int chunk = div_up(div_up(n, nchunks), sub) * sub;
     nchunks = div_up(n, chunk);
     const int eb = std::min(div_up(n, 256), 2048);
     size_t off = 0;
@@ -1210,9 +1277,8 @@ ssm_status pivotmds_w(const ssm_csr* g, const double* len, int k, const double* 
         hipLaunchKernelGGL(k_wpmds_colsum, dim3(k), dim3(256), 0, s, n, dist, colsum);
         hipLaunchKernelGGL(k_wpmds_mu, dim3(1), dim3(64), 0, s, n, k, colsum, mu, stats);
         hipLaunchKernelGGL(k_wpmds_nu, dim3(gn), dim3(256), 0, s, n, k, dist, nu);
-        hipLaunchKernelGGL((k_pmds_gram<double, 0>), dim3(nchunks, ngroups), dim3(256),
-                           sizeof(double) * ((size_t)kGramSub * kp + kp), s, n, k, kp, kp, chunk,
-                           (const uint4*)dist, mu, nu, stats, tiles, ntiles, part);
+        launch_gram<double, 0>(dim3(nchunks, ngroups), s, n, k, kp, kp, chunk, (const uint4*)dist, mu, nu, stats,
+                               tiles, ntiles, part);
         hipLaunchKernelGGL(k_pmds_gram_reduce, dim3(std::min(div_up((long long)ntiles * 256, 256), 4096)), dim3(256),
                            0, s, k, nchunks, ntiles, tiles, part, M);
         const size_t elds = eig_lds_bytes(k);

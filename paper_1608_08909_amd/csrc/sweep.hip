@@ -325,23 +325,17 @@ __global__ void k_gather_pivots(int kpad, const int* __restrict__ piv, const flo
 }
 
 // Heavy list, segments and scratch of a handle (called by build_terms).
+// counts[h] = segments of heavy row h, counts[nheavy] = 0 (the exclusive
+// scan of the nheavy + 1 counts then ends in the total).
 __global__ void k_heavy_segcount(int nheavy, const int* __restrict__ heavy, const int* __restrict__ rp,
-                                 int* __restrict__ seg_start) {
-    for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < nheavy; h += gridDim.x * blockDim.x) {
-        const int i = heavy[h];
-        seg_start[h] = (rp[i + 1] - rp[i] + kHeavySeg - 1) / kHeavySeg;
-    }
-}
-
-__global__ void k_heavy_segscan(int nheavy, int* __restrict__ seg_start) {  // exclusive, one thread
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        int acc = 0;
-        for (int h = 0; h < nheavy; ++h) {
-            const int c = seg_start[h];
-            seg_start[h] = acc;
-            acc += c;
+                                 int* __restrict__ counts) {
+    for (int h = blockIdx.x * blockDim.x + threadIdx.x; h <= nheavy; h += gridDim.x * blockDim.x) {
+        if (h == nheavy) {
+            counts[h] = 0;
+            continue;
         }
-        seg_start[nheavy] = acc;
+        const int i = heavy[h];
+        counts[h] = (rp[i + 1] - rp[i] + kHeavySeg - 1) / kHeavySeg;
     }
 }
 
@@ -360,13 +354,28 @@ ssm_status heavy_segments(const ssm_csr* g, ssm_terms* t, hipStream_t s) {
     st = dalloc((void**)&t->seg_start, sizeof(int) * ((size_t)nh + 1));
     if (st == SSM_OK) st = dalloc((void**)&t->seg_range, sizeof(int2) * (size_t)g->n);
     if (st != SSM_OK) return st;
-    const int hb = std::max(1, std::min(div_up(nh, 256), 1024));
-    hipLaunchKernelGGL(k_heavy_segcount, dim3(hb), dim3(256), 0, s, nh, t->heavy, g->row_ptr, t->seg_start);
-    hipLaunchKernelGGL(k_heavy_segscan, dim3(1), dim3(64), 0, s, nh, t->seg_start);
-    SSM_HIP(hipGetLastError());
+    const int hb = std::max(1, std::min(div_up(nh + 1, 256), 1024));
+    // segment counts, then their exclusive scan (the last entry is the total)
+    size_t scan_bytes = 0;
+    SSM_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, (const int*)nullptr, (int*)nullptr, nh + 1, s));
+    void* scan_tmp = nullptr;
+    int* counts = nullptr;
+    st = salloc(&scan_tmp, std::max<size_t>(scan_bytes, 16));
+    if (st == SSM_OK) st = salloc((void**)&counts, sizeof(int) * ((size_t)nh + 1));
+    if (st != SSM_OK) {
+        if (scan_tmp) sfree(scan_tmp);
+        return st;
+    }
+    hipLaunchKernelGGL(k_heavy_segcount, dim3(hb), dim3(256), 0, s, nh, t->heavy, g->row_ptr, counts);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipcub::DeviceScan::ExclusiveSum(scan_tmp, scan_bytes, counts, t->seg_start, nh + 1, s);
     int nseg = 0;
-    SSM_HIP(hipMemcpyAsync(&nseg, t->seg_start + nh, sizeof(int), hipMemcpyDeviceToHost, s));
-    SSM_HIP(hipStreamSynchronize(s));
+    if (e == hipSuccess) e = hipMemcpyAsync(&nseg, t->seg_start + nh, sizeof(int), hipMemcpyDeviceToHost, s);
+    const hipError_t es = hipStreamSynchronize(s);
+    sfree(counts);
+    sfree(scan_tmp);
+    SSM_HIP(e);
+    SSM_HIP(es);
     t->nseg = nseg;
     st = dalloc((void**)&t->seg_owner, sizeof(int) * (size_t)std::max(nseg, 1));
     if (st == SSM_OK) st = dalloc((void**)&t->seg_sum, sizeof(float2) * (size_t)std::max(nseg, 1));

@@ -75,24 +75,36 @@ __device__ __forceinline__ T block_max(T v, T* scratch) {
 
 // Calls f(i, j) for every arc (i, j) of the CSR rows i0 .. i0+63 (rows
 // beyond n are empty): the wave walks the rows' arcs 64 at a time, so a
-// long row costs its length / 64 passes instead of stalling one lane.  Call
-// with every lane of the wave active.
+// long row costs its length / 64 passes instead of stalling one lane.  Lane
+// l takes arcs e0 + l, e0 + l + 64, ... in that order, four per pass with
+// their column loads in flight together.  Call with every lane of the wave
+// active.
 template <typename F>
 __device__ __forceinline__ void wave_arcs(int n, const int* __restrict__ rp, const int* __restrict__ ci, int i0,
                                           F f) {
+    constexpr int U = 4;
     const int lane = lane_id();
     const int end = rp[min(i0 + kWave, n)];
     const int a = i0 + lane < n ? rp[i0 + lane] : end;  // row start of this lane's node
     const int e0 = __shfl(a, 0);
-    for (int e = e0 + lane; e - lane < end; e += kWave) {
-        // the arc's row: the last lane whose row starts at or before e
-        int lo = 0;
+    for (int eb = e0; eb < end; eb += U * kWave) {  // uniform
+        int row[U], col[U];
 #pragma unroll
-        for (int step = kWave / 2; step > 0; step >>= 1) {
-            const int c = lo + step;
-            if (__shfl(a, c) <= e) lo = c;
+        for (int u = 0; u < U; ++u) {
+            const int e = eb + u * kWave + lane;
+            // the arc's row: the last lane whose row starts at or before e
+            int lo = 0;
+#pragma unroll
+            for (int step = kWave / 2; step > 0; step >>= 1) {
+                const int c = lo + step;
+                if (__shfl(a, c) <= e) lo = c;
+            }
+            row[u] = i0 + lo;
+            col[u] = e < end ? ci[e] : 0;
         }
-        if (e < end) f(i0 + lo, ci[e]);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (eb + u * kWave + lane < end) f(row[u], col[u]);
     }
 }
 

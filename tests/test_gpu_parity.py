@@ -197,6 +197,22 @@ def test_pivotmds_parity(g, k):
     assert iters < 20000
 
 
+@pytest.mark.parametrize("k", [240, 256, 1000])
+def test_pivotmds_gram_round_sizes(k):
+    """The Gram product stages 32 nodes per LDS round while the staged block
+    fits 64 KB (k <= 240) and 8 above it, past 64 KB of LDS at k = 1000; every
+    form matches the oracle's C^T C."""
+    g = G.rgg(3000, 5)
+    say("case", g.name, "k", k)
+    _, dref = oracle.select_pivots(g.n, g.row_ptr, g.col_idx, k, 0)
+    dg, piv, _, dist, delta, region, terms = _device_pipeline(g, k)
+    assert np.array_equal(dist.cpu().numpy(), dref)
+    ssm.pivotmds_init(dg, terms, ssm.FP64)
+    M = ssm.pivotmds_gram(terms)
+    Mo = oracle.gram(oracle.pmds_center(dref))
+    assert np.abs(M - Mo).max() <= 1e-12 * np.abs(Mo).max()
+
+
 @pytest.mark.parametrize("g,k", CASES, ids=IDS)
 def test_sweeps_f64_bit_exact(g, k):
     say("case", g.name, "k", k)

@@ -278,8 +278,19 @@ __global__ void k_pmds_gram_reduce(int k, int nchunks, int ntiles, const int2* _
     for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total;
          q += (long long)gridDim.x * blockDim.x) {
         int tile = (int)(q / 256), e = (int)(q % 256);
+        // chunks summed in ascending order, eight loads in flight
+        const double* pp = part + (size_t)tile * 256 + e;
+        const size_t stride = (size_t)ntiles * 256;
         double s = 0.0;
-        for (int c = 0; c < nchunks; ++c) s += part[((size_t)c * ntiles + tile) * 256 + e];
+        int c = 0;
+        for (; c + 8 <= nchunks; c += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = pp[(size_t)(c + u) * stride];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; c < nchunks; ++c) s += pp[(size_t)c * stride];
         int2 ab = tiles[tile];
         int r = 16 * ab.x + e / 16, col = 16 * ab.y + e % 16;
         if (r < k && col < k) {

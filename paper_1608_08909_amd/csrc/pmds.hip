@@ -582,6 +582,45 @@ __device__ __forceinline__ void eigp_body(int k, const double* __restrict__ M, d
 // (larger eigenvalue first) and the sign rule.  Returns false (uniformly,
 // output untouched) when max_iter steps do not converge: the rate is
 // lambda_3 / lambda_2, slow when those two nearly tie.
+// N block-wide sums (or maxima) at once: each value is reduced exactly as
+// block_sum (block_max) reduces one, with one pair of barriers for all N.
+// scratch holds N slots per wave.
+template <int N>
+__device__ __forceinline__ void block_sum_n(double (&v)[N], double* scratch) {
+    const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+#pragma unroll
+    for (int u = 0; u < N; ++u) v[u] = wave_sum(v[u]);
+    __syncthreads();
+    if (lane_id() == 0)
+#pragma unroll
+        for (int u = 0; u < N; ++u) scratch[u * nw + w] = v[u];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+        double t = 0;
+        for (int q = 0; q < nw; ++q) t += scratch[u * nw + q];  // fixed order
+        v[u] = t;
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void block_max_n(double (&v)[N], double* scratch) {
+    const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+#pragma unroll
+    for (int u = 0; u < N; ++u) v[u] = wave_max(v[u]);
+    __syncthreads();
+    if (lane_id() == 0)
+#pragma unroll
+        for (int u = 0; u < N; ++u) scratch[u * nw + w] = v[u];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+        double t = scratch[u * nw];
+        for (int q = 1; q < nw; ++q) t = scratch[u * nw + q] > t ? scratch[u * nw + q] : t;
+        v[u] = t;
+    }
+}
+
 template <bool REG>
 __device__ __forceinline__ bool eig2_body(int k, const double* __restrict__ M, double tol, int max_iter,
                                           double* __restrict__ out, int* __restrict__ iters) {
@@ -591,6 +630,7 @@ __device__ __forceinline__ bool eig2_body(int k, const double* __restrict__ M, d
     double* z0 = sh + 2 * k;
     double* z1 = sh + 3 * k;
     __shared__ double red[kEigThreads / kWave];
+    __shared__ double red4[4 * (kEigThreads / kWave)];
     const int lane = lane_id(), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
     double mreg[REG ? kEigRows : 1][REG ? kEigCols : 1];
     if (REG) {
@@ -701,16 +741,25 @@ __device__ __forceinline__ bool eig2_body(int k, const double* __restrict__ M, d
         for (int t = threadIdx.x; t < k; t += blockDim.x) z1[t] /= n1;
         __syncthreads();
         // distance of span(Z) from span(V): residual of projecting Z on V
-        double p00 = dot(v0, z0), p10 = dot(v1, z0), p01 = dot(v0, z1), p11 = dot(v1, z1);
-        double res0 = 0.0, res1 = 0.0;
+        // the four projections in one reduction, the two residuals in another
+        double pr[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int t = threadIdx.x; t < k; t += blockDim.x) {
+            pr[0] += v0[t] * z0[t];
+            pr[1] += v1[t] * z0[t];
+            pr[2] += v0[t] * z1[t];
+            pr[3] += v1[t] * z1[t];
+        }
+        block_sum_n(pr, red4);
+        const double p00 = pr[0], p10 = pr[1], p01 = pr[2], p11 = pr[3];
+        double res[2] = {0.0, 0.0};
         for (int t = threadIdx.x; t < k; t += blockDim.x) {
             double r0 = z0[t] - p00 * v0[t] - p10 * v1[t];
             double r1 = z1[t] - p01 * v0[t] - p11 * v1[t];
-            res0 = fmax(res0, fabs(r0));
-            res1 = fmax(res1, fabs(r1));
+            res[0] = fmax(res[0], fabs(r0));
+            res[1] = fmax(res[1], fabs(r1));
         }
-        res0 = block_max(res0, red);
-        res1 = block_max(res1, red);
+        block_max_n(res, red4);
+        const double res0 = res[0], res1 = res[1];
         for (int t = threadIdx.x; t < k; t += blockDim.x) {
             v0[t] = z0[t];
             v1[t] = z1[t];

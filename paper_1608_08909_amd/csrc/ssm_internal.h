@@ -107,8 +107,8 @@ ssm_status kmeans_pivots(int32_t n, int32_t k, const int32_t* pivots, const int3
 // Heavy list, its arc segments and the FP32 sweep's scratch for them.
 ssm_status heavy_segments(const ssm_csr* g, ssm_terms* t, hipStream_t s);
 // FP32 sweep order (when t->perm is allocated) and the heavy-row lists.
-ssm_status sweep_order(const ssm_csr* g, ssm_terms* t, const int32_t* dist, const int32_t* delta,
-                       const int32_t* region, hipStream_t s);
+ssm_status sweep_order(const ssm_csr* g, ssm_terms* t, const int32_t* delta, const int32_t* region,
+                       hipStream_t s);
 int sweep_order_mode();  // 0 off, 1 when it pays (build_terms decides), 2 always
 ssm_status regions(int32_t n, int32_t k, const int32_t* dist, int32_t* delta, int32_t* region,
                    hipStream_t s);

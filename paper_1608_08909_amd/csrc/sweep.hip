@@ -428,21 +428,15 @@ __global__ void k_order_csr(int n, const int* __restrict__ perm, const int* __re
     }
 }
 
-// Packed distances in the new order (as k_terms_pack, node perm[r] at r).
-template <typename DT, int VEC>
-__global__ void k_order_pack(int n, int k, int kpad, const int* __restrict__ perm, const int* __restrict__ dist,
+// Packed distances in the new order: word b of node perm[r] (already packed
+// by build_terms) moves to word b of r, one 16-byte gather per word.
+__global__ void k_order_pack(int n, int nwords, const int* __restrict__ perm, const uint4* __restrict__ dpk,
                              uint4* __restrict__ out) {
-    const long long total = (long long)(kpad / VEC) * n;
+    const long long total = (long long)nwords * n;
     for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total;
          q += (long long)gridDim.x * blockDim.x) {
-        const int b = (int)(q / n), r = (int)(q % n), o = perm[r];
-        Packed<DT, VEC> u;
-#pragma unroll
-        for (int j = 0; j < VEC; ++j) {
-            const int t = b * VEC + j;
-            u.e[j] = t < k ? (DT)dist[(size_t)t * n + o] : (DT)0;
-        }
-        out[q] = u.v;
+        const int b = (int)(q / n), r = (int)(q % n);
+        out[q] = dpk[(size_t)b * n + perm[r]];
     }
 }
 
@@ -458,7 +452,7 @@ __global__ void k_perm_scatter(int n, const int* __restrict__ perm, const float2
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) x[perm[r]] = y[r];
 }
 
-ssm_status sweep_order(const ssm_csr* g, ssm_terms* t, const int32_t* dist, const int32_t* delta,
+ssm_status sweep_order(const ssm_csr* g, ssm_terms* t, const int32_t* delta,
                        const int32_t* region, hipStream_t s) {
     if (!t->perm) return heavy_segments(g, t, s);
     const int n = t->n;
@@ -494,12 +488,8 @@ ssm_status sweep_order(const ssm_csr* g, ssm_terms* t, const int32_t* dist, cons
                            t->prp, t->pci);
         const long long words = (long long)(t->kpad / t->vec) * n;
         const dim3 gp((int)std::min<long long>((words + 255) / 256, 16384));
-        if (t->dbytes == 1)
-            hipLaunchKernelGGL((k_order_pack<uint8_t, 16>), gp, dim3(256), 0, s, n, t->k, t->kpad, t->perm, dist,
-                               (uint4*)t->pdpk);
-        else
-            hipLaunchKernelGGL((k_order_pack<uint16_t, 8>), gp, dim3(256), 0, s, n, t->k, t->kpad, t->perm, dist,
-                               (uint4*)t->pdpk);
+        hipLaunchKernelGGL(k_order_pack, gp, dim3(256), 0, s, n, t->kpad / t->vec, t->perm, (const uint4*)t->dpk,
+                           (uint4*)t->pdpk);
         hipLaunchKernelGGL(k_order_piv, dim3(div_up(t->kpad, 256)), dim3(256), 0, s, t->kpad, t->pivots, t->inv,
                            t->ppiv);
         e = hipGetLastError();

@@ -335,7 +335,7 @@ ssm_status build_terms(const ssm_csr* g, int32_t k, const int32_t* pivots, const
     }
     // high-degree nodes (their neighbour sums get whole wavefronts)
     // the FP32 sweep's node order, then the heavy-row lists (in that order)
-    st = sweep_order(g, t, dist, delta, region, s);
+    st = sweep_order(g, t, delta, region, s);
     if (st != SSM_OK) {
         ssm_terms_free(t);
         return st;

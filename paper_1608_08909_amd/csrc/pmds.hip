@@ -1048,13 +1048,14 @@ __global__ __launch_bounds__(1024) void k_pool_mds_stats(const PoolGraph* __rest
 }
 
 // Items (graph, node chunk, tile group): the Gram partial tiles.
+template <int SUB>
 __global__ __launch_bounds__(256) void k_pool_gram(const PoolGraph* __restrict__ gs, const int4* __restrict__ items,
                                                    const int2* __restrict__ tiles) {
     const int4 it = items[blockIdx.x];
     const PoolGraph& g = gs[it.x];
     const int kp = (g.k + 15) / 16 * 16;
-    pmds_gram_body<uint16_t, 8, 8>(it.y, it.z, g.n, g.k, kp, g.kpad, kPoolGramChunk, g.dpk, g.mu, g.nu, g.stats, tiles,
-                                g.ntiles, g.gpart);
+    pmds_gram_body<uint16_t, 8, SUB>(it.y, it.z, g.n, g.k, kp, g.kpad, kPoolGramChunk, g.dpk, g.mu, g.nu, g.stats,
+                                     tiles, g.ntiles, g.gpart);
 }
 
 // Per graph (blockIdx.y): M = the chunks' partial tiles summed in ascending
@@ -1151,8 +1152,13 @@ __global__ __launch_bounds__(1024) void k_pool_project(const PoolGraph* __restri
 hipError_t pool_pivotmds(const PoolGraph* gs, int count, const int4* gram_items, int ngram, const int2* tiles,
                          int kp_max, int k_max, hipStream_t s) {
     hipLaunchKernelGGL(k_pool_mds_stats, dim3(count), dim3(1024), 0, s, gs);
-    hipLaunchKernelGGL(k_pool_gram, dim3(ngram), dim3(256), gram_lds_bytes<8>(kp_max), s,
-                       gs, gram_items, tiles);
+    // rounds of 32 nodes when the batch's largest staged block fits 64 KB (kPoolGramChunk is a multiple of 32)
+    if (gram_sub(kp_max) == 32)
+        hipLaunchKernelGGL(k_pool_gram<32>, dim3(ngram), dim3(256), gram_lds_bytes<32>(kp_max), s, gs, gram_items,
+                           tiles);
+    else
+        hipLaunchKernelGGL(k_pool_gram<8>, dim3(ngram), dim3(256), gram_lds_bytes<8>(kp_max), s, gs, gram_items,
+                           tiles);
     hipLaunchKernelGGL(k_pool_gram_reduce, dim3(32, count), dim3(256), 0, s, gs, tiles);
     hipLaunchKernelGGL(k_pool_eig, dim3(count), dim3(kEigThreads), eig_lds_bytes(k_max), s, gs);
     hipLaunchKernelGGL(k_pool_project, dim3(count), dim3(1024), 0, s, gs);

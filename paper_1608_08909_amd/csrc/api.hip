@@ -200,13 +200,12 @@ void ssm_terms_free(ssm_terms* t) {
     int cur = 0;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(t->device);
-    // the fixed-size buffers live in the arena (scratch cache: returned only
-    // once the device is idle); the heavy-row lists are separate
+    // the arena and the heavy-row lists come from the scratch cache: returned
+    // only once the device is idle
     (void)hipDeviceSynchronize();
     sfree(t->arena);
     void* ptrs[] = {t->heavy, t->seg_start, t->seg_owner, t->seg_range, t->seg_sum};
-    for (void* p : ptrs)
-        if (p) (void)hipFree(p);
+    for (void* p : ptrs) sfree(p);
     (void)hipSetDevice(cur);
     delete t;
 }

@@ -258,7 +258,7 @@ ssm_status heavy_list(const ssm_csr* g, int** heavy, int32_t* count, hipStream_t
     if (e == hipSuccess) e = hipMemcpyAsync(&nh, total, sizeof(int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e == hipSuccess) {
-        st = dalloc((void**)heavy, sizeof(int) * (size_t)std::max(nh, 1));
+        st = salloc((void**)heavy, sizeof(int) * (size_t)std::max(nh, 1));
         if (st != SSM_OK) {
             sfree(buf);  // the stream was synchronized above
             return st;
@@ -269,7 +269,7 @@ ssm_status heavy_list(const ssm_csr* g, int** heavy, int32_t* count, hipStream_t
     (void)hipStreamSynchronize(s);  // idle before the scratch is reused (also after an error)
     sfree(buf);
     if (e != hipSuccess) {
-        if (*heavy) (void)hipFree(*heavy);
+        sfree(*heavy);  // the stream is idle
         *heavy = nullptr;
         return hip_fail(e, "heavy-node list");
     }
@@ -456,7 +456,7 @@ static ssm_status msbfs(const ssm_csr* g, int32_t k, const int32_t* pivots, int3
     }
     (void)hipStreamSynchronize(s);  // idle before the scratch is reused
     sfree(buf);
-    if (heavy) (void)hipFree(heavy);
+    sfree(heavy);
     if (e != hipSuccess) return hip_fail(e, "bit-parallel BFS");
     *levels_out = level - 1;  // the last level found nothing
     return SSM_OK;

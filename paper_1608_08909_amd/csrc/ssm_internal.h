@@ -96,8 +96,9 @@ ssm_status mssp(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dis
                 int32_t* dmax_out_host, hipStream_t s);
 ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pivots,
                          hipStream_t s);
-// Ids of the nodes with degree > kHeavyDegree, ascending; *heavy is a new
-// device allocation of max(count, 1) ints owned by the caller.  Synchronizes.
+// Ids of the nodes with degree > kHeavyDegree, ascending; *heavy holds
+// max(count, 1) ints from the scratch cache (salloc), which the caller
+// returns with sfree once its stream is idle.  Synchronizes.
 ssm_status heavy_list(const ssm_csr* g, int** heavy, int32_t* count, hipStream_t s);
 
 // k-means sp refinement of max/min pivots (kmeans.hip).

@@ -351,8 +351,8 @@ ssm_status heavy_segments(const ssm_csr* g, ssm_terms* t, hipStream_t s) {
     ssm_status st = heavy_list(g, &t->heavy, &t->nheavy, s);
     if (st != SSM_OK) return st;
     const int nh = t->nheavy;
-    st = dalloc((void**)&t->seg_start, sizeof(int) * ((size_t)nh + 1));
-    if (st == SSM_OK) st = dalloc((void**)&t->seg_range, sizeof(int2) * (size_t)g->n);
+    st = salloc((void**)&t->seg_start, sizeof(int) * ((size_t)nh + 1));
+    if (st == SSM_OK) st = salloc((void**)&t->seg_range, sizeof(int2) * (size_t)g->n);
     if (st != SSM_OK) return st;
     const int hb = std::max(1, std::min(div_up(nh + 1, 256), 1024));
     // segment counts, then their exclusive scan (the last entry is the total)
@@ -377,8 +377,8 @@ ssm_status heavy_segments(const ssm_csr* g, ssm_terms* t, hipStream_t s) {
     SSM_HIP(e);
     SSM_HIP(es);
     t->nseg = nseg;
-    st = dalloc((void**)&t->seg_owner, sizeof(int) * (size_t)std::max(nseg, 1));
-    if (st == SSM_OK) st = dalloc((void**)&t->seg_sum, sizeof(float2) * (size_t)std::max(nseg, 1));
+    st = salloc((void**)&t->seg_owner, sizeof(int) * (size_t)std::max(nseg, 1));
+    if (st == SSM_OK) st = salloc((void**)&t->seg_sum, sizeof(float2) * (size_t)std::max(nseg, 1));
     if (st != SSM_OK) return st;
     hipLaunchKernelGGL(k_heavy_segowner, dim3(hb), dim3(256), 0, s, nh, t->heavy, t->seg_start, t->seg_owner,
                        t->seg_range);
@@ -869,12 +869,12 @@ ssm_status stress_full(const ssm_csr* g, ssm_prec p, const void* x, double* out_
     int* D = nullptr;
     int* src = nullptr;
     double* part = nullptr;
-    ssm_status st = dalloc((void**)&D, sizeof(int) * (size_t)nb * n);
-    if (st == SSM_OK) st = dalloc((void**)&src, sizeof(int) * (size_t)nb);
-    if (st == SSM_OK) st = dalloc((void**)&part, sizeof(double) * (blocks + 1));
-    if (st != SSM_OK) {
-        if (D) hipFree(D);
-        if (src) hipFree(src);
+    ssm_status st = salloc((void**)&D, sizeof(int) * (size_t)nb * n);
+    if (st == SSM_OK) st = salloc((void**)&src, sizeof(int) * (size_t)nb);
+    if (st == SSM_OK) st = salloc((void**)&part, sizeof(double) * (blocks + 1));
+    if (st != SSM_OK) {  // nothing queued yet
+        sfree(D);
+        sfree(src);
         return st;
     }
     hipError_t e = hipMemsetAsync(part, 0, sizeof(double) * (blocks + 1), s);
@@ -897,9 +897,10 @@ ssm_status stress_full(const ssm_csr* g, ssm_prec p, const void* x, double* out_
         e = hipMemcpyAsync(out_host, part + blocks, sizeof(double), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
     }
-    (void)hipFree(D);
-    (void)hipFree(src);
-    (void)hipFree(part);
+    (void)hipStreamSynchronize(s);  // idle before the scratch is reused (also after an error)
+    sfree(D);
+    sfree(src);
+    sfree(part);
     if (st != SSM_OK) return st;
     if (e != hipSuccess) return hip_fail(e, "full stress");
     return SSM_OK;

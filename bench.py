@@ -39,14 +39,30 @@ WORKLOADS = {
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+# VALU issue capacity without packed FP32 (disabled in this build): 256 CUs x
+# 64 lanes per clock x 2.4 GHz, in lane-slots per second
+VALU_PEAK_TSLOTS = 256 * 64 * 2.4e9 / 1e12
+# VALU lane-slots of the arithmetic one FP32 term needs: two subtractions,
+# two FMAs for r^2, the reciprocal square root (a transcendental, issued at a
+# quarter of the full rate: 4 slots), one FMA for the coefficient and two
+# FMAs into the sums -- addressing and unpacking excluded
+SLOTS_PER_TERM = 11
 PROFILE_LABEL = {"rgg": "rgg100k_k200", "ba": "ba1m_k200", "mesh": "mesh2000_k100", "grid": "grid50_k50"}
+
+
+SWEEP_KERNEL_SRC = os.path.join(ROOT, "paper_1608_08909_amd", "csrc", "sweep_f32.h")
+
+
+def kernel_source_sha256() -> str:
+    """sha256 of the FP32 sweep's device code (host-side planning excluded)."""
+    import hashlib
+    return hashlib.sha256(open(SWEEP_KERNEL_SRC, "rb").read()).hexdigest()
 
 
 def measured_traffic(workload: str):
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE, calibrated by a copy kernel), or None when no
-    summary exists or the sweep source changed since it was taken."""
-    import hashlib
+    summary exists or the sweep kernel's source changed since it was taken."""
     path = os.path.join(ROOT, "profiles", f"{PROFILE_LABEL.get(workload, workload)}_sweep_f32_hbm_counters.md")
     if not os.path.exists(path):
         return None
@@ -55,9 +71,7 @@ def measured_traffic(workload: str):
         if ":" in line and not line.startswith(("#", " ", "-")):
             a, b = line.split(":", 1)
             fields[a.strip()] = b.strip()
-    src = os.path.join(ROOT, "paper_1608_08909_amd", "csrc", "sweep.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if fields.get("sweep_source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
+    if fields.get("kernel_source_sha256") != kernel_source_sha256() or "traffic_bytes_per_launch" not in fields:
         return None
     return int(fields["traffic_bytes_per_launch"])
 
@@ -75,24 +89,75 @@ def percentile(a, q):
     return float(np.percentile(np.asarray(a), q))
 
 
-def cpu_baseline(g, k, iters, sample_sweeps, threads=1):
-    """The CPU oracle on the same graph: the full preprocessing and start
-    layout once, then `sample_sweeps` sweeps; the step time is extrapolated to
-    `iters` sweeps."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def usable_cores() -> int:
+    """Host threads this process may use: its CPU affinity, capped by
+    OMP_NUM_THREADS when that is set."""
+    n = len(os.sched_getaffinity(0))
+    omp = os.environ.get("OMP_NUM_THREADS")
+    if omp and omp.isdigit() and int(omp) > 0:
+        n = min(n, int(omp))
+    return max(1, n)
+
+
+def cpu_baseline(g, k, iters, sweeps_one=1, sweeps_all=3, pmds_work=4e9):
+    """The CPU oracle on the same graph (the oracle as it stands, untuned).
+
+    Preprocessing (max/min, BFS, regions, weights; serial in the oracle) runs
+    once on the whole graph.  PivotMDS runs on the whole graph when n k^2 is
+    at most `pmds_work`, else on the distance columns of the first
+    pmds_work / k^2 nodes with its time scaled by n / (those nodes): that
+    sample's centred matrix stays closer to the caches, so the scaled time is
+    a lower bound.  The sweeps (OpenMP over nodes in the oracle; Jacobi, so
+    the result does not depend on the thread count) are sampled on one
+    thread and on every usable core and scaled to `iters` sweeps.  The value
+    is end-to-end node-updates/s on all cores; `one_thread` repeats it on
+    one."""
     import oracle
 
+    cores = usable_cores()
     t0 = time.perf_counter()
     T = oracle.preprocess(g.n, g.row_ptr, g.col_idx, k)
-    x0 = oracle.initial_layout(g.row_ptr, g.col_idx, T)
-    t1 = time.perf_counter()
-    oracle.majorize(g.row_ptr, g.col_idx, T.pivots, T.dist, T.wtab, T.den, x0, sample_sweeps, threads=threads)
-    t2 = time.perf_counter()
-    per_sweep = (t2 - t1) / sample_sweeps
-    step = (t1 - t0) + iters * per_sweep
-    return {"value": g.n * iters / step, "unit": "node-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"preprocessing + PivotMDS once ({t1 - t0:.2f} s) and {sample_sweeps} of {iters} sweeps "
-                      f"({per_sweep * 1e3:.1f} ms each), step time extrapolated to {iters} sweeps",
-            "step_s": step, "sweep_node_updates_per_s": g.n / per_sweep}
+    t_pre = time.perf_counter() - t0
+    if g.n * k * k <= pmds_work:
+        t0 = time.perf_counter()
+        x0 = oracle.initial_layout(g.row_ptr, g.col_idx, T)
+        t_pmds = time.perf_counter() - t0
+        pmds_note = "PivotMDS on the whole graph"
+    else:
+        ns = max(1000, int(pmds_work / (k * k)))
+        t0 = time.perf_counter()
+        oracle.pivotmds(np.ascontiguousarray(T.dist[:, :ns]))
+        t_pmds = (time.perf_counter() - t0) * g.n / ns
+        pmds_note = f"PivotMDS on {ns} of {g.n} nodes, time scaled by n/{ns} (a lower bound)"
+        # sweep timing needs a start layout only: a seeded one of the layout's scale
+        x0 = np.random.default_rng(0).normal(size=(g.n, 2)) * np.sqrt(g.n)
+    rates = {}
+    for threads, count in ((1, sweeps_one), (cores, sweeps_all)):
+        t0 = time.perf_counter()
+        oracle.majorize(g.row_ptr, g.col_idx, T.pivots, T.dist, T.wtab, T.den, x0, count, threads=threads)
+        rates[threads] = (time.perf_counter() - t0) / count
+    step_1 = t_pre + t_pmds + iters * rates[1]
+    step_n = t_pre + t_pmds + iters * rates[cores]
+    sample = (f"{cpu_model()}: preprocessing once on one thread ({t_pre:.2f} s), {pmds_note} "
+              f"({t_pmds:.2f} s), {sweeps_one} sweep(s) on 1 thread ({rates[1] * 1e3:.0f} ms each) and "
+              f"{sweeps_all} on {cores} threads ({rates[cores] * 1e3:.0f} ms each), step time scaled to {iters} sweeps")
+    return {"value": g.n * iters / step_n, "unit": "node-updates/s", "cores": cores, "kind": "oracle",
+            "sample": sample, "cpu_model": cpu_model(), "step_s": step_n,
+            "phase_s": {"preprocess": t_pre, "pivotmds": t_pmds, "sweep_all_cores": rates[cores],
+                        "sweep_one_thread": rates[1]},
+            "sweep_node_updates_per_s": g.n / rates[cores],
+            "one_thread": {"value": g.n * iters / step_1, "cores": 1, "step_s": step_1,
+                           "sweep_node_updates_per_s": g.n / rates[1]}}
 
 
 SERVE_DESC = ("serving stream: {count} layout requests with Poisson arrivals at {rate:g}/s; each graph drawn "
@@ -373,7 +438,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rgg", choices=sorted(WORKLOADS) + ["serve", "quality", "weighted"])
+    ap.add_argument("--workload", default="mesh", choices=sorted(WORKLOADS) + ["serve", "quality", "weighted"])
     ap.add_argument("--requests", type=int, default=4096, help="serve: requests in the stream")
     ap.add_argument("--warm-requests", type=int, default=64, help="serve: requests of each warm-up stream")
     ap.add_argument("--rate", type=float, default=100000.0, help="serve: Poisson arrival rate (requests/s)")
@@ -387,7 +452,6 @@ def main():
     ap.add_argument("--sampling", default="maxmin", choices=["maxmin", "kmeans"],
                     help="pivot sampling: max/min, or max/min refined by k-means sp")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sweeps", type=int, default=10)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -421,6 +485,7 @@ def main():
 
     phases = {}
     km_passes = []
+    last_pivots = [None]
     kmeans = args.sampling == "kmeans"
 
     def step(record=False):
@@ -433,6 +498,7 @@ def main():
             del dist0
         else:
             piv = ssm.select_pivots(dg, k, 0)
+        last_pivots[0] = piv
         ev[1].record(stream)
         dist, delta, region = ssm.bfs_pivots(dg, piv)
         ev[2].record(stream)
@@ -487,6 +553,12 @@ def main():
     sweep_us = e0.elapsed_time(e1) * 1e3 / (reps * iters)
     nbytes = sweep_bytes(g.n, g.m, k, dbytes, prec_name)
     achieved = nbytes / (sweep_us * 1e-6) / 1e9
+    # terms of one sweep: every (node, pivot) pair at distance >= 2 (all but
+    # the pivot itself and its neighbours) and every arc
+    deg = np.diff(g.row_ptr)
+    pivots_np = last_pivots[0].cpu().numpy()
+    n_terms = g.n * k - k - int(deg[pivots_np].sum()) + 2 * g.m
+    alu = n_terms * SLOTS_PER_TERM / (sweep_us * 1e-6) / 1e12
 
     # Equal final stress versus the plain FP64 form on the same GPU.
     x64 = ssm.pivotmds_init(dg, terms, ssm.FP64)
@@ -527,8 +599,14 @@ def main():
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.workload) if prec == ssm.FP32 else None,
-                     "bytes_per_launch": nbytes, "launch_us": sweep_us},
+                     "bytes_per_launch": nbytes, "launch_us": sweep_us,
+                     "alu": {"achieved": alu, "peak": VALU_PEAK_TSLOTS, "unit": "T VALU lane-slots/s",
+                             "frac": alu / VALU_PEAK_TSLOTS, "terms_per_launch": n_terms,
+                             "slots_per_term": SLOTS_PER_TERM}},
     }
+    if args.workload == "rgg":
+        out["roofline"]["note"] = ("the 45.5 MB working set of one sweep fits the 256 MB last-level cache (MALL): "
+                                   "this fraction is of the HBM peak, the bytes are served from the MALL")
     if kmeans:
         # k-means sp: each pass's assignment is an n x k x k FP64 contraction
         # (B = Y S^T), 2 n k^2 flops; phase-level rate (all its kernels and
@@ -545,9 +623,12 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = src.numel() * 4
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(g, k, iters, args.cpu_sweeps)
+        out["cpu_baseline"] = cpu_baseline(g, k, iters)
     print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":
     main()
+    # free the library's handles and cached scratch before interpreter teardown
+    if "paper_1608_08909_amd.ssm" in sys.modules:
+        sys.modules["paper_1608_08909_amd.ssm"].shutdown()

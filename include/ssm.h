@@ -340,6 +340,14 @@ ssm_status ssm_pool_remove(ssm_pool* p, int32_t slot);
 /* Message for the last non-OK status returned on the calling thread. */
 const char* ssm_last_error(void);
 
+/* Returns the library's cached device scratch (buffers kept between calls
+ * for reuse) to HIP, after synchronizing each device that holds some.
+ * Handles (ssm_terms, ssm_wterms, ssm_pool) are not touched.  Meant for a
+ * process that is about to exit, or that wants the memory back; later calls
+ * allocate scratch again as needed.  Not to be called while another thread
+ * runs a library call. */
+void ssm_release_cache(void);
+
 #ifdef __cplusplus
 }
 #endif

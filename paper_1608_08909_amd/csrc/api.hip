@@ -109,6 +109,23 @@ void sfree(void* p) {
     }
 }
 
+// Returns every cached (idle) scratch block to HIP.  Live blocks stay with
+// their owners.  Each device that holds cached blocks is synchronized first.
+void release_cached_scratch() {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_free.empty()) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (const CachedBlock& b : g_scratch_free) {
+        (void)hipSetDevice(b.dev);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(b.p);
+    }
+    g_scratch_free.clear();
+    g_scratch_free_bytes = 0;
+    (void)hipSetDevice(cur);
+}
+
 ssm_status check_csr(const ssm_csr* g) {
     if (!g) return fail(SSM_E_INVAL, "graph is NULL");
     if (g->n < 1) return fail(SSM_E_INVAL, "graph has no nodes");
@@ -138,6 +155,8 @@ using namespace ssm;
 extern "C" {
 
 const char* ssm_last_error(void) { return g_last_error.c_str(); }
+
+void ssm_release_cache(void) { release_cached_scratch(); }
 
 ssm_status ssm_select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pivots,
                              int32_t* dist, hipStream_t stream) {

@@ -90,6 +90,7 @@ ssm_status dalloc(void** p, size_t bytes);
 // the stream that used the buffer has been synchronized.
 ssm_status salloc(void** p, size_t bytes);
 void sfree(void* p);
+void release_cached_scratch();
 
 // ---- BFS / regions (bfs.hip)
 ssm_status mssp(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dist,

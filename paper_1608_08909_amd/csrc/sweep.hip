@@ -9,6 +9,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include "ssm_internal.h"
+#include "sweep_f32.h"
 #include "wave.h"
 
 namespace ssm {
@@ -28,12 +29,6 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
 void launch_sum_partials(const double* partials, int count, double* out, hipStream_t s) {
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partials, count, out);
 }
-
-template <typename DT, int VEC>
-union Packed {
-    uint4 v;
-    DT e[VEC];
-};
 
 // --------------------------------------------------------- FP64 sweep
 
@@ -99,216 +94,6 @@ __global__ __launch_bounds__(256) void k_sweep_f64(int n, int kpad, int W, const
         }
         const double dn = den[i];
         xn[i] = make_double2(nx / dn, ny / dn);
-    }
-}
-
-// --------------------------------------------------------- FP32 sweep
-
-// How the FP32 sweep finds (w', w' d) for a pivot term.
-enum WeightMode { kTableLds = 0, kHistLds = 1, kTableGlobal = 2 };
-
-// Eq. 5 in displacement form: x_i' = x_i + (sum_q f_q (x_q - x_i)) / den_i
-// with f_q = w_q - (w_q d_q) / r_iq, which equals num_i / den_i because every
-// vote minus x_i is (x_q - x_i)(1 - d_q / r_iq).  Accumulating displacements
-// keeps FP32 rounding relative to the (small) move rather than to the
-// coordinates, and a vote at distance zero contributes exactly 0, so two
-// coincident nodes with one closed neighbourhood get identical updates.
-// 1/r is the hardware reciprocal square root of r^2 + 1e-30 (a zero
-// displacement then still contributes exactly 0).
-
-// Neighbour displacement sums of the heavy rows (degree > kHeavyDegree):
-// one wavefront per segment of kHeavySeg arcs (lane l sums arcs l, l + 64,
-// ... of the segment, then a fixed butterfly); the sweep adds a row's
-// segments in order.  Same terms as the sweep's neighbour loop:
-// (1 - 1/r) (x_j - x_i).
-__global__ __launch_bounds__(256) void k_heavy_edges(int nseg, const int* __restrict__ heavy,
-                                                     const int* __restrict__ seg_start,
-                                                     const int* __restrict__ seg_owner, const int* __restrict__ rp,
-                                                     const int* __restrict__ ci, const float2* __restrict__ xo,
-                                                     float2* __restrict__ seg_sum) {
-    const int lane = lane_id();
-    const float tiny = 1e-30f;
-    for (int q = (blockIdx.x * blockDim.x + threadIdx.x) / kWave; q < nseg; q += gridDim.x * blockDim.x / kWave) {
-        const int h = seg_owner[q];
-        const int i = heavy[h];
-        const int a = rp[i] + (q - seg_start[h]) * kHeavySeg;
-        const int b = min(rp[i + 1], a + kHeavySeg);
-        const float2 xi = xo[i];
-        float ax = 0.f, ay = 0.f;
-        for (int e = a + lane; e < b; e += kWave) {
-            const float2 xj = xo[ci[e]];
-            float dx = xj.x - xi.x, dy = xj.y - xi.y;
-            float f = 1.f - __builtin_amdgcn_rsqf(dx * dx + (dy * dy + tiny));
-            ax += f * dx;
-            ay += f * dy;
-        }
-        ax = wave_sum(ax);
-        ay = wave_sum(ay);
-        if (lane == 0) seg_sum[q] = make_float2(ax, ay);
-    }
-}
-
-// Copies nbytes (a multiple of 4) from global to LDS with 16-byte loads,
-// four in flight per thread (both sides 16-byte aligned).  The loads are
-// unconditional (an index past the end rereads the last word) so that they
-// stay in registers and issue together; only the LDS stores are guarded.
-__device__ __forceinline__ void stage_lds(void* dst, const void* __restrict__ src, size_t nbytes) {
-    const int n16 = (int)(nbytes / 16);
-    const int step = blockDim.x;
-    uint4* d = (uint4*)dst;
-    const uint4* g = (const uint4*)src;
-    for (int q0 = threadIdx.x; q0 < n16; q0 += 4 * step) {
-        const int last = n16 - 1;
-        const uint4 v0 = g[q0];
-        const uint4 v1 = g[min(q0 + step, last)];
-        const uint4 v2 = g[min(q0 + 2 * step, last)];
-        const uint4 v3 = g[min(q0 + 3 * step, last)];
-        d[q0] = v0;
-        if (q0 + step < n16) d[q0 + step] = v1;
-        if (q0 + 2 * step < n16) d[q0 + 2 * step] = v2;
-        if (q0 + 3 * step < n16) d[q0 + 3 * step] = v3;
-    }
-    for (int q = 4 * n16 + threadIdx.x; q < (int)(nbytes / 4); q += step)
-        ((unsigned*)dst)[q] = ((const unsigned*)src)[q];
-}
-
-// Block = CPB groups of SPLIT wavefronts; a group takes 64 consecutive nodes
-// (lane = node) and its SPLIT waves share the node's terms: wave s sums the
-// packed distance words b = s, s + SPLIT, ... (one coalesced 16-byte load
-// per lane covers VEC pivots; two words stay in flight).  The last wave of
-// the group, which holds the fewest words, also sums the neighbour terms in
-// CSR order (heavy rows: their segment sums in order).  Wave 0 adds the
-// SPLIT partials in a fixed order.  Blocks loop over the chunks, so the LDS
-// tables are staged once per block.
-//
-// Every lane of a wave reads the same pivot t, so the pivot's coordinates
-// are wave-uniform loads from the contiguous array pc (kept current by the
-// sweep itself: the node of pivot t writes its new coordinates into
-// pc_next[t]).  The pivot term is f = w' - (w' d) / r: kTableLds stages
-// (w', w' d) for every (pivot, distance) in LDS; kHistLds stages the region
-// histograms H and (1/d^2, 1/d), w' = H[t][min(d/2, delta_max)] / d^2, so
-// f = H (1/d^2 - (1/d) / r); kTableGlobal reads (w', w' d) from memory.
-template <typename DT, int VEC, int SPLIT, int CPB, int MODE>
-__global__ __launch_bounds__(64 * SPLIT * CPB) void k_sweep_f32(
-    int n, int kpad, int W, int L, const int* __restrict__ rp, const int* __restrict__ ci,
-    const float2* __restrict__ xo, float2* __restrict__ xn, const uint4* __restrict__ dpk,
-    const float2* __restrict__ pc, float2* __restrict__ pc_next, const int* __restrict__ prank,
-    const float2* __restrict__ wt2, const float* __restrict__ Hf, const float2* __restrict__ invd,
-    const float* __restrict__ den, const int2* __restrict__ seg_range, const float2* __restrict__ seg_sum) {
-    constexpr int NW = SPLIT * CPB;
-    extern __shared__ float4 smem4[];
-    float2* sP = (float2*)smem4;                                  // [kpad] pivot coordinates
-    float2* sPart = sP + kpad;                                    // [2][NW][64] (SPLIT > 1)
-    float2* sTab = sPart + (SPLIT > 1 ? 2 * NW * 64 : 0);         // kTableLds: [kpad][W]; kHistLds: invd [W]
-    float* sH = (float*)(sTab + (MODE == kHistLds ? (W + 1) / 2 * 2 : 0));  // kHistLds: H [kpad][L]
-    stage_lds(sP, pc, sizeof(float2) * (size_t)kpad);
-    if (MODE == kTableLds) stage_lds(sTab, wt2, sizeof(float2) * (size_t)kpad * W);
-    if (MODE == kHistLds) {
-        stage_lds(sTab, invd, sizeof(float2) * (size_t)W);
-        stage_lds(sH, Hf, sizeof(float) * (size_t)kpad * L);
-    }
-    __syncthreads();
-    const int lane = threadIdx.x % 64;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);  // wave-uniform
-    const int grp = w / SPLIT, sw = w % SPLIT;
-    const int nwords = kpad / VEC;
-    const int nchunks = (n + 63) / 64;
-    const float tiny = 1e-30f;
-    int buf = 0;
-    for (int c0 = blockIdx.x * CPB; c0 < nchunks; c0 += gridDim.x * CPB) {  // uniform over the block
-        const int i = (c0 + grp) * 64 + lane;
-        float ax = 0.f, ay = 0.f;
-        float2 xi = make_float2(0.f, 0.f);
-        if (i < n) {
-            xi = xo[i];
-            Packed<DT, VEC> wa, wb;
-            wa.v = sw < nwords ? dpk[(size_t)sw * n + i] : make_uint4(0, 0, 0, 0);
-            wb.v = sw + SPLIT < nwords ? dpk[(size_t)(sw + SPLIT) * n + i] : make_uint4(0, 0, 0, 0);
-            if (sw == SPLIT - 1) {
-                const int e0 = rp[i], e1 = rp[i + 1];
-                if (e1 - e0 > kHeavyDegree) {  // the row's segment sums, in order
-                    const int2 r = seg_range[i];
-                    for (int q = r.x; q < r.y; ++q) {
-                        const float2 hs = seg_sum[q];
-                        ax += hs.x;
-                        ay += hs.y;
-                    }
-                } else {
-                    // neighbour votes in CSR order, four gathers in flight
-                    // (unconditional loads: a missing slot reads x_i itself)
-                    for (int e = e0; e < e1; e += 4) {
-                        int j[4];
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const int c = ci[min(e + q, e1 - 1)];  // unconditional load
-                            j[q] = e + q < e1 ? c : i;
-                        }
-                        float2 xj[4];
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) xj[q] = xo[j[q]];
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            // a missing slot holds x_i: zero displacement, adds exactly 0
-                            float dx = xj[q].x - xi.x, dy = xj[q].y - xi.y;
-                            float inv = __builtin_amdgcn_rsqf(dx * dx + (dy * dy + tiny));
-                            float f = 1.f - inv;  // w = 1, d = 1
-                            ax += f * dx;
-                            ay += f * dy;
-                        }
-                    }
-                }
-            }
-            for (int b = sw; b < nwords; b += SPLIT) {
-                const Packed<DT, VEC> u = wa;
-                wa = wb;
-                if (b + 2 * SPLIT < nwords) wb.v = dpk[(size_t)(b + 2 * SPLIT) * n + i];  // two words ahead
-#pragma unroll
-                for (int jj = 0; jj < VEC; ++jj) {
-                    const int t = b * VEC + jj;  // wave-uniform
-                    const int d = (int)u.e[jj];
-                    float f0, f1, hmul;  // f = hmul (f0 - f1 / r)
-                    if (MODE == kHistLds) {
-                        hmul = sH[t * L + min(d >> 1, L - 1)];
-                        const float2 id = sTab[d];
-                        f0 = id.x;
-                        f1 = id.y;
-                    } else {
-                        const float2 e = MODE == kTableLds ? sTab[t * W + d] : wt2[(size_t)t * W + d];
-                        f0 = e.x;
-                        f1 = e.y;
-                        hmul = 1.f;
-                    }
-                    const float2 p = sP[t];  // LDS broadcast
-                    float dx = p.x - xi.x, dy = p.y - xi.y;
-                    float inv = __builtin_amdgcn_rsqf(dx * dx + (dy * dy + tiny));
-                    float f = fmaf(-f1, inv, f0);
-                    if (MODE == kHistLds) f *= hmul;
-                    ax += f * dx;
-                    ay += f * dy;
-                }
-            }
-        }
-        if (SPLIT > 1) {
-            // partials double-buffered: one barrier per chunk group
-            sPart[(buf * NW + w) * 64 + lane] = make_float2(ax, ay);
-            __syncthreads();
-            if (sw == 0) {
-#pragma unroll
-                for (int q = 1; q < SPLIT; ++q) {
-                    const float2 o = sPart[(buf * NW + w + q) * 64 + lane];
-                    ax += o.x;
-                    ay += o.y;
-                }
-            }
-            buf ^= 1;
-        }
-        if (sw == 0 && i < n) {
-            const float dn = den[i];
-            const float2 v = make_float2(xi.x + ax / dn, xi.y + ay / dn);
-            xn[i] = v;
-            const int r = prank[i];
-            if (r >= 0) pc_next[r] = v;
-        }
     }
 }
 

@@ -8,9 +8,12 @@ fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
 import threading
+import weakref
 
 import torch
 
@@ -23,6 +26,26 @@ STRESS_SPARSE, STRESS_FULL = 0, 1
 
 _lock = threading.Lock()
 _lib = None
+_live = weakref.WeakSet()   # objects that own a library handle
+
+
+def shutdown():
+    """Frees every live handle (terms, pools) and the library's cached
+    scratch, after the device work queued so far has finished.  Registered
+    with atexit when the library is loaded, so that no HIP call is left for
+    the interpreter's own teardown; the handles are unusable afterwards."""
+    if _lib is None:
+        return
+    try:
+        torch.cuda.synchronize()
+    except Exception:
+        pass
+    for obj in list(_live):
+        try:
+            obj.close()
+        except Exception:
+            pass
+    _lib.ssm_release_cache()
 
 
 class SSMError(RuntimeError):
@@ -43,7 +66,7 @@ EXPORTS = [
     "ssm_pool_create", "ssm_pool_destroy", "ssm_pool_usage", "ssm_pool_add", "ssm_pool_prepare", "ssm_pool_sweep",
     "ssm_pool_stress", "ssm_pool_layout", "ssm_pool_export", "ssm_pool_info", "ssm_pool_remove", "ssm_procrustes",
     "ssm_select_pivots_w", "ssm_sssp_pivots", "ssm_build_terms_w", "ssm_wterms_free", "ssm_wterms_export",
-    "ssm_pivotmds_init_w", "ssm_majorize_w", "ssm_majorize_mixed_w", "ssm_stress_w",
+    "ssm_pivotmds_init_w", "ssm_majorize_w", "ssm_majorize_mixed_w", "ssm_stress_w", "ssm_release_cache",
 ]
 
 
@@ -98,6 +121,7 @@ def load(path: str | None = None):
             "ssm_majorize_w": (S, [P, V, V, I, V, I, V]),
             "ssm_majorize_mixed_w": (S, [P, V, V, V, V, I, I, V]),
             "ssm_stress_w": (S, [P, V, V, I, V, V, V]),
+            "ssm_release_cache": (None, []),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -105,6 +129,7 @@ def load(path: str | None = None):
             f.argtypes = args
         if path is None:
             _lib = lib
+            atexit.register(shutdown)
         return lib
 
 
@@ -161,12 +186,18 @@ class Terms:
         self.handle = ctypes.c_void_p(handle)
         self.graph = graph
         self.k = k
+        _live.add(self)
 
-    def __del__(self):
+    def close(self):
         h = getattr(self, "handle", None)
         if h is not None and h.value and _lib is not None:
             _lib.ssm_terms_free(h)
-            self.handle = None
+        self.handle = None
+
+    def __del__(self):
+        # at interpreter exit the atexit hook has already freed the handle
+        if not sys.is_finalizing():
+            self.close()
 
     def dims(self):
         k, dm, dx = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
@@ -379,6 +410,7 @@ class Pool:
         h = ctypes.c_void_p()
         _check(self._lib.ssm_pool_create(int(capacity_bytes), ctypes.byref(h)), "ssm_pool_create")
         self.handle = h.value
+        _live.add(self)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -386,6 +418,8 @@ class Pool:
             self.handle = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -466,14 +500,20 @@ class WTerms:
 
     def __init__(self, handle: int, graph: DeviceGraph, k: int):
         self.handle, self.graph, self.k = handle, graph, k
+        _live.add(self)
+
+    def close(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.ssm_wterms_free(self.handle)
+        self.handle = None
 
     def __del__(self):
-        if getattr(self, "handle", None):
-            try:
-                load().ssm_wterms_free(self.handle)
-            except Exception:
-                pass
-            self.handle = None
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def export(self):
         import numpy as np

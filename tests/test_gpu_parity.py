@@ -185,7 +185,17 @@ def test_pivotmds_parity(g, k):
     gap12 = (w[0] - w[1]) / w[0]
     gap23 = (w[1] - w[2]) / w[0]
     if w[1] > 1e-8 * w[0] and gap23 < 1e-6:
-        return   # the dominant plane itself is not unique: only the eigenvalues are fixed
+        # the dominant plane itself is not unique (the complete graph): the
+        # eigenvalues are fixed, and any orthonormal pair of eigenvectors of
+        # those eigenvalues is a valid answer; the layout must be that pair's
+        # projection C V, rescaled to the summed edge lengths
+        assert np.abs(V.T @ V - np.eye(2)).max() < 1e-12
+        assert np.abs(Mo @ V - V * lam[None, :]).max() < 1e-9 * abs(lamo[0])
+        C = oracle.pmds_center(ref.dist)
+        xw = oracle.rescale(g.row_ptr, g.col_idx, C @ V)
+        assert brute.coord_error(x, xw) < 1e-9
+        assert iters < 20000
+        return
     if gap12 > 1e-3 and w[1] > 1e-8 * w[0]:
         # well separated: eigenvectors and layout match directly
         assert np.abs(V - Vo).max() < 1e-9

@@ -714,3 +714,77 @@ def test_weights_by_definition_and_power_of_two_scaling():
     x = oracle.majorize_w(g.row_ptr, g.col_idx, ln, W.pivots, W.dist, W.w, W.den, x0, 10)
     x4 = oracle.majorize_w(g.row_ptr, g.col_idx, 4 * ln, W4.pivots, W4.dist, W4.w, W4.den, 4 * x0, 10)
     assert np.array_equal(x4, 4 * x)
+
+
+@pytest.mark.parametrize("g,k", [(G.grid(9, 11), 7), (G.tree_plus(300, 2), 17), (G.rgg(500, 4), 25)])
+def test_weighted_pivotmds_and_rescale_at_unit_lengths(g, k):
+    # Algorithm 1's initialisation with every length 1 is the unweighted one:
+    # the real-valued distance table holds the same integers, so PivotMDS and
+    # the rescale to the summed edge lengths (m) agree bit for bit
+    T = oracle.preprocess(g.n, g.row_ptr, g.col_idx, k)
+    xa, Va, la = oracle.pivotmds(T.dist)
+    xb, Vb, lb = oracle.pivotmds_w(T.dist.astype(np.float64))
+    assert np.array_equal(xa, xb) and np.array_equal(Va, Vb) and np.array_equal(la, lb)
+    ln = np.ones(g.col_idx.size)
+    assert np.array_equal(oracle.rescale(g.row_ptr, g.col_idx, xa), oracle.rescale_w(g.row_ptr, g.col_idx, ln, xb))
+
+
+def _edge_length_sum(g, x):
+    src = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    up = g.col_idx > src
+    return np.linalg.norm(x[src[up]] - x[g.col_idx[up]], axis=1).sum()
+
+
+def test_weighted_rescale_matches_summed_lengths_and_scales_exactly():
+    g = G.rgg(400, 11)
+    ln = G.edge_lengths(g, 12)
+    k = 16
+    W = oracle.preprocess_w(g.n, g.row_ptr, g.col_idx, ln, k)
+    x0, V, lam = oracle.pivotmds_w(W.dist)
+    x = oracle.rescale_w(g.row_ptr, g.col_idx, ln, x0)
+    # after the rescale the drawn edges sum to the summed edge lengths (Algorithm 1)
+    src = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    want = ln[g.col_idx > src].sum()
+    assert abs(_edge_length_sum(g, x) - want) <= 1e-12 * want
+    # lengths x 4: the centred squared distances scale by 16, the Gram by 256,
+    # the eigenvectors are unchanged and the projection scales by 16; the
+    # rescale then brings the layout to exactly 4 times the unit-scale one
+    W4 = oracle.preprocess_w(g.n, g.row_ptr, g.col_idx, 4 * ln, k)
+    x40, V4, lam4 = oracle.pivotmds_w(W4.dist)
+    assert np.array_equal(V4, V) and np.array_equal(lam4, 256 * lam) and np.array_equal(x40, 16 * x0)
+    assert np.array_equal(oracle.rescale_w(g.row_ptr, g.col_idx, 4 * ln, x40), 4 * x)
+
+
+def _stress_w_by_definition(g, ln, pivots, dist, w, x):
+    """Eq. 3 with edge lengths, summed by numpy: every edge once with weight
+    len^-2, every (node, pivot) term with its adapted weight."""
+    src = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    up = g.col_idx > src
+    r = np.linalg.norm(x[src[up]] - x[g.col_idx[up]], axis=1)
+    le = ln[up]
+    s_edges = np.sum((r - le) ** 2 / le ** 2)
+    s_piv = 0.0
+    for t, p in enumerate(pivots):
+        rp = np.linalg.norm(x - x[p], axis=1)
+        s_piv += np.sum(w[t] * (rp - dist[t]) ** 2)
+    return s_edges + s_piv
+
+
+def test_weighted_stress_by_definition_and_exact_scaling():
+    g = G.grid(13, 17)
+    ln = G.edge_lengths(g, 5)
+    k = 9
+    W = oracle.preprocess_w(g.n, g.row_ptr, g.col_idx, ln, k)
+    x = oracle.layout_w(g.n, g.row_ptr, g.col_idx, ln, k, 7)[0]
+    s = oracle.stress_w(g.row_ptr, g.col_idx, ln, W.pivots, W.dist, W.w, x)
+    ref = _stress_w_by_definition(g, ln, W.pivots, W.dist, W.w, x)
+    assert abs(s - ref) <= 1e-12 * ref
+    # a perturbed layout: the length terms are not near zero there
+    rng = np.random.default_rng(3)
+    xp = x + rng.normal(scale=0.3, size=x.shape)
+    s = oracle.stress_w(g.row_ptr, g.col_idx, ln, W.pivots, W.dist, W.w, xp)
+    ref = _stress_w_by_definition(g, ln, W.pivots, W.dist, W.w, xp)
+    assert abs(s - ref) <= 1e-12 * ref
+    # lengths, distances and layout x 4, weights / 16: every term is unchanged
+    s4 = oracle.stress_w(g.row_ptr, g.col_idx, 4 * ln, W.pivots, 4 * W.dist, W.w / 16, 4 * xp)
+    assert s4 == s

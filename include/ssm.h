@@ -337,6 +337,23 @@ ssm_status ssm_pool_info(ssm_pool* p, int32_t slot, int32_t* info_host);
 /* Releases a slot's buffers (after any queued sweep that reads it). */
 ssm_status ssm_pool_remove(ssm_pool* p, int32_t slot);
 
+/* Stop test of Algorithm 1's loop for a slot's FP32 sweeps (ssm_pool_sweep):
+ * after each sweep, the relative positional change (the change left after
+ * the best rotation and translation of the previous iterate onto the new
+ * one, over the previous iterate's spread about its centroid; FP64 moments)
+ * is compared with tol; once it is at most tol the slot's layout stays at
+ * that sweep's result (later sweeps of the slot carry it over unchanged).
+ * tol = 0 (the default) runs the slot's sweep count.  The slot must be added
+ * or ready. */
+ssm_status ssm_pool_set_tol(ssm_pool* p, int32_t slot, double tol);
+
+/* For each listed ready slot: sweeps_host[q] = the sweeps its layout took
+ * (the FP64 warm-up sweeps included) if its stop test has fired, else -1.  A
+ * stopped slot takes no further sweeps.  Waits for the pool's queued sweeps;
+ * synchronizes. */
+ssm_status ssm_pool_stopped(ssm_pool* p, int32_t count, const int32_t* slots, int32_t* sweeps_host,
+                            hipStream_t stream);
+
 /* Message for the last non-OK status returned on the calling thread. */
 const char* ssm_last_error(void);
 
@@ -347,6 +364,26 @@ const char* ssm_last_error(void);
  * allocate scratch again as needed.  Not to be called while another thread
  * runs a library call. */
 void ssm_release_cache(void);
+
+/* Forces a launch variant: another kernel form or launch shape of one step,
+ * for tests and tuning experiments.  Every variant computes the same result
+ * (integer outputs and FP64 sweeps bit for bit, FP32 sweeps within their
+ * stated tolerance); only the speed changes.  value 0 restores the library's
+ * own choice; name NULL clears every override.  The overrides are
+ * process-wide; set them while no other thread runs a library call.
+ * Names and values:
+ *   select_mode 1|2|3 (one workgroup, cooperative grid, per-pivot),
+ *   select_blocks N, select_threads 256|512, select_ell 2 (plain CSR),
+ *   select_m8 2 (no LDS byte copy), select_rowq 2, select_pre 1|3,
+ *   select_wave -1|2 (block levels only, two passes per wave level),
+ *   bfs_ell 2, bfs_rowq 2, bfs_lanes 2..64, msbfs 1, msbfs_budget N,
+ *   region_mode 1|2, km_chunk 32|40|48|56|64,
+ *   sweep_mode 1|2 (LDS histograms, global table), sweep_split 1|2|4,
+ *   sweep_blocks_per_cu N, sweep_waves 4|16 (waves per block),
+ *   sweep_perm -1|2 (caller's node order, always reorder),
+ *   sssp_nearfar -1 (plain rounds), sssp_band N.
+ * SSM_E_INVAL for an unknown name. */
+ssm_status ssm_set_variant(const char* name, int32_t value);
 
 #ifdef __cplusplus
 }

@@ -70,6 +70,7 @@ def _load():
                 "orc_pivotmds": (I, [I, I, P, P, P, P]),
                 "orc_rescale": (I, [I, P, P, P]),
                 "orc_majorize": (I, [I, P, P, I, P, P, P, I, P, P, I, D, I, I, P]),
+                "orc_rigid_change": (D, [I, P, P]),
                 "orc_stress_sparse": (D, [I, P, P, I, P, P, P, I, P, P]),
                 "orc_stress_full": (D, [I, P, P, P]),
                 "orc_kmeans_sp": (I, [I, I, P, P, I, P, P, P]),
@@ -233,6 +234,14 @@ def majorize(row_ptr, col_idx, pivots, dist, wtab, den, x, iters: int, tol: floa
     if st != OK:
         raise OracleError(st, "majorize")
     return x, int(done.value)
+
+
+def rigid_change(x_old, x_new) -> float:
+    """Algorithm 1's relative positional change of one sweep, after the best
+    proper rigid motion (rotation and translation) of x_old onto x_new,
+    relative to the spread of x_old about its centroid."""
+    a, b = _f64(x_old), _f64(x_new)
+    return _load().orc_rigid_change(a.shape[0], _p(a), _p(b))
 
 
 def stress_sparse(row_ptr, col_idx, pivots, dist, wtab, x, parts: bool = False):

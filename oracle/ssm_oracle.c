@@ -448,11 +448,55 @@ static void update_node(int i, int n, const int* rp, const int* ci, int k, const
     out[1] = ny / den[i];
 }
 
+/* Relative positional change of one sweep x -> y (the test of Algorithm 1's
+ * loop).  The stress of Eq. 1 and Eq. 3 and the update of Eq. 5 do not
+ * change under a rotation or translation of the whole layout, and with k < n
+ * the asymmetric adapted weights leave a steady rigid motion of the layout
+ * from sweep to sweep; the change is therefore measured after the best
+ * proper rigid motion:
+ *   min over rotations R, vectors t of ||y - (R x + t)||_F / ||x - xbar||_F.
+ * First pass: the centroids xbar, ybar.  Second pass: with a = x_i - xbar,
+ * b = y_i - ybar, P = sum (a.x b.x + a.y b.y), Q = sum (a.x b.y - a.y b.x)
+ * and the spread sum |a|^2; the best rotation has cos = P / rho,
+ * sin = Q / rho with rho = sqrt(P^2 + Q^2) (no rotation when rho = 0).
+ * Third pass: the residual sum |b - R a|^2.  Returns +infinity when the old
+ * layout has zero spread (every node at one point). */
+double orc_rigid_change(int n, const double* x, const double* y) {
+    double sx = 0.0, sy = 0.0, tx = 0.0, ty = 0.0;
+    for (int i = 0; i < n; ++i) {
+        sx += x[2 * (size_t)i];
+        sy += x[2 * (size_t)i + 1];
+        tx += y[2 * (size_t)i];
+        ty += y[2 * (size_t)i + 1];
+    }
+    const double mx = sx / n, my = sy / n, nx = tx / n, ny = ty / n;
+    double P = 0.0, Q = 0.0, aa = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double ax = x[2 * (size_t)i] - mx, ay = x[2 * (size_t)i + 1] - my;
+        const double bx = y[2 * (size_t)i] - nx, by = y[2 * (size_t)i + 1] - ny;
+        P += ax * bx + ay * by;
+        Q += ax * by - ay * bx;
+        aa += ax * ax + ay * ay;
+    }
+    if (!(aa > 0.0)) return INFINITY;
+    const double rho = sqrt(P * P + Q * Q);
+    const double c = rho > 0.0 ? P / rho : 1.0, s = rho > 0.0 ? Q / rho : 0.0;
+    double res = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double ax = x[2 * (size_t)i] - mx, ay = x[2 * (size_t)i + 1] - my;
+        const double bx = y[2 * (size_t)i] - nx, by = y[2 * (size_t)i + 1] - ny;
+        const double ex = bx - (c * ax - s * ay), ey = by - (s * ax + c * ay);
+        res += ex * ex + ey * ey;
+    }
+    return sqrt(res / aa);
+}
+
 /* Algorithm 1's loop with the update of Eq. 5.  Jacobi order (every node
  * reads the previous iterate) unless gauss_seidel != 0, which updates in
  * place in ascending node order as Algorithm 1 is written.  Runs `iters`
- * sweeps, or stops earlier once ||x_new - x_old||_F / ||x_old||_F <= tol
- * (tol > 0).  Jacobi sweeps may run on `threads` OpenMP threads; the result
+ * sweeps, or stops after the first sweep whose relative positional change
+ * (orc_rigid_change) is at most tol (tol > 0); *iters_done is the number of
+ * sweeps run.  Jacobi sweeps may run on `threads` OpenMP threads; the result
  * does not depend on the thread count. */
 int orc_majorize(int n, const int* rp, const int* ci, int k, const int* pivots, const int* dist,
                  const double* wtab, int dmax, const double* den, double* x, int iters,
@@ -474,17 +518,13 @@ int orc_majorize(int n, const int* rp, const int* ci, int k, const int* pivots, 
             for (int i = 0; i < n; ++i)
                 update_node(i, n, rp, ci, k, pivots, dist, wtab, dmax, den, x, nxt + 2 * (size_t)i);
         }
-        double dd = 0.0, xx = 0.0;
-        if (tol > 0.0) {
-            for (size_t q = 0; q < 2 * (size_t)n; ++q) {
-                double old = gauss_seidel ? nxt[q] : x[q];
-                double nw = gauss_seidel ? x[q] : nxt[q];
-                dd += (nw - old) * (nw - old);
-                xx += old * old;
-            }
-        }
+        /* the change from the previous iterate (nxt after Gauss-Seidel, x
+         * after Jacobi) to the new one */
+        const double change = tol > 0.0 ? (gauss_seidel ? orc_rigid_change(n, nxt, x)
+                                                        : orc_rigid_change(n, x, nxt))
+                                        : INFINITY;
         if (!gauss_seidel) memcpy(x, nxt, sizeof(double) * 2 * (size_t)n);
-        if (tol > 0.0 && xx > 0.0 && sqrt(dd) / sqrt(xx) <= tol) { ++it; break; }
+        if (change <= tol) { ++it; break; }
     }
     free(nxt);
     if (iters_done) *iters_done = it;

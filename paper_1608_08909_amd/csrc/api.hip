@@ -1,5 +1,6 @@
 // C ABI entry points of libssm: argument checks, error reporting, dispatch.
 #include <stdio.h>
+#include <string.h>
 
 #include <algorithm>
 #include <mutex>
@@ -126,6 +127,24 @@ void release_cached_scratch() {
     (void)hipSetDevice(cur);
 }
 
+// Launch-variant overrides (set through ssm_set_variant; 0 or absent = the
+// library's own choice).  Process-wide, guarded by a mutex.
+namespace {
+std::mutex g_variant_mu;
+std::unordered_map<std::string, int> g_variants;
+const char* const kVariantNames[] = {
+    "bfs_lanes",   "bfs_rowq",      "bfs_ell",       "msbfs",         "msbfs_budget", "select_threads",
+    "select_wave", "select_rowq",   "select_pre",    "select_blocks", "select_mode",  "select_ell",
+    "select_m8",   "region_mode",   "km_chunk",      "sweep_perm",    "sweep_mode",   "sweep_split",
+    "sweep_blocks_per_cu", "sweep_waves", "sssp_nearfar", "sssp_band"};
+}  // namespace
+
+int variant(const char* name, int unset) {
+    std::lock_guard<std::mutex> lock(g_variant_mu);
+    auto it = g_variants.find(name);
+    return it == g_variants.end() ? unset : it->second;
+}
+
 ssm_status check_csr(const ssm_csr* g) {
     if (!g) return fail(SSM_E_INVAL, "graph is NULL");
     if (g->n < 1) return fail(SSM_E_INVAL, "graph has no nodes");
@@ -157,6 +176,23 @@ extern "C" {
 const char* ssm_last_error(void) { return g_last_error.c_str(); }
 
 void ssm_release_cache(void) { release_cached_scratch(); }
+
+ssm_status ssm_set_variant(const char* name, int32_t value) {
+    if (!name) {  // clear every override
+        std::lock_guard<std::mutex> lock(g_variant_mu);
+        g_variants.clear();
+        return SSM_OK;
+    }
+    bool known = false;
+    for (const char* v : kVariantNames) known = known || strcmp(v, name) == 0;
+    if (!known) return fail(SSM_E_INVAL, std::string("unknown variant name: ") + name);
+    std::lock_guard<std::mutex> lock(g_variant_mu);
+    if (value == 0)
+        g_variants.erase(name);
+    else
+        g_variants[name] = value;
+    return SSM_OK;
+}
 
 ssm_status ssm_select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pivots,
                              int32_t* dist, hipStream_t stream) {

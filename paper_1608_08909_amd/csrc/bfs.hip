@@ -18,15 +18,10 @@ constexpr int kBfsBlock = 1024;
 constexpr int kSelBlock = 512;
 constexpr int kInf = INT_MAX;
 
-// Launch-shape override from the environment (tuning only; 0 = automatic).
-static int env_int(const char* name) {
-    const char* v = getenv(name);
-    return v ? atoi(v) : 0;
-}
 
 // Lanes per frontier node: the power of two nearest the mean degree, in [2, 64].
 static int virtual_warp(const ssm_csr* g) {
-    int forced = env_int("SSM_BFS_LANES");
+    int forced = variant("bfs_lanes");
     if (forced == 2 || forced == 4 || forced == 8 || forced == 16 || forced == 32 || forced == 64) return forced;
     double avg = g->n > 0 ? (double)g->nnz / g->n : 1.0;
     int vw = 2;
@@ -796,7 +791,7 @@ static hipError_t launch_bfs_ell(int W, int pool, int blocks, hipStream_t s, int
 template <int VW>
 static void launch_bfs_wg(int blocks, hipStream_t s, int n, const int* rp, const int* ci,
                           const int* pivots, int* dist, int2* queues, int* reached, int* ecc) {
-    if (env_int("SSM_BFS_ROWQ") != 2)  // row bounds in the queue (2 = node ids; tuning)
+    if (variant("bfs_rowq") != 2)  // row bounds in the queue (2 = node ids; tuning)
         hipLaunchKernelGGL((k_bfs_wg<VW, true>), dim3(blocks), dim3(kBfsBlock), 0, s, n, rp, ci, pivots, dist,
                            queues, reached, ecc);
     else
@@ -810,8 +805,8 @@ ssm_status mssp(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dis
     // Bit-parallel BFS over all pivots at once (opt-in with SSM_MSBFS=1: the
     // per-pivot LDS-resident BFS below was faster on every graph measured).
     // It gives up after `budget` levels, and the per-workgroup BFS runs instead.
-    const int budget = env_int("SSM_MSBFS_BUDGET") > 0 ? env_int("SSM_MSBFS_BUDGET") : 24;
-    if (k <= 1024 && env_int("SSM_MSBFS") == 1) {
+    const int budget = variant("msbfs_budget") > 0 ? variant("msbfs_budget") : 24;
+    if (k <= 1024 && variant("msbfs") == 1) {
         bool done = false;
         int32_t levels = 0;
         ssm_status st;
@@ -847,7 +842,7 @@ ssm_status mssp(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dis
     // LDS-resident BFS per pivot when the visited bits fit in LDS (tuning
     // override SSM_BFS_ELL=2 keeps the global-memory form).
     const int pool = bfs_ell_pool(n);
-    if (pool > 0 && env_int("SSM_BFS_ELL") != 2) {
+    if (pool > 0 && variant("bfs_ell") != 2) {
         const int W = ell_width(g);
         const long long qcap = 1LL << 31;  // overflow ints (8 GiB)
         const int batch = (int)std::max<long long>(1, std::min<long long>(k, qcap / (3LL * n)));
@@ -1564,12 +1559,12 @@ template <int W, bool M8>
 static hipError_t launch_select_ell_t(hipStream_t s, int n, const int* rp, const int* ci, const int* ell, int k,
                                       int first, int* pivots, int* m, int* q, int* status) {
     int threads = kBfsBlock;
-    const int v = env_int("SSM_SELECT_THREADS");  // tuning override: 256, 512 or 1024
+    const int v = variant("select_threads");  // tuning override: 256, 512 or 1024
     if (v == 256 || v == 512) threads = v;
-    // small frontiers in one wave, one pass per level (tuning override
-    // SSM_SELECT_WAVE: 0 = block levels only, 2 = up to two passes)
-    const char* wv = getenv("SSM_SELECT_WAVE");
-    const int wave_mode = wv ? std::max(0, std::min(2, atoi(wv))) : 1;
+    // small frontiers in one wave, one pass per level (variant select_wave:
+    // -1 = block levels only, 2 = up to two passes)
+    const int wv = variant("select_wave", 1);
+    const int wave_mode = std::max(0, std::min(2, wv));
     hipLaunchKernelGGL((k_select_ell<W, M8>), dim3(1), dim3(threads), 0, s, n, rp, ci, ell, k, first, pivots, m,
                        q, status, wave_mode);
     return hipGetLastError();
@@ -1599,7 +1594,7 @@ static void launch_select_wg_v(hipStream_t s, int n, const int* rp, const int* c
                                int* m, int2* q, int* status) {
     // queue style and relaxation precheck: defaults measured on MI355X; the
     // environment overrides them for tuning
-    const int rowq = env_int("SSM_SELECT_ROWQ"), pre = env_int("SSM_SELECT_PRE");
+    const int rowq = variant("select_rowq"), pre = variant("select_pre");
     if (rowq != 2) {  // row bounds in the queue (2 = node ids; tuning)
         if (pre == 1) launch_select_wg_t<VW, true, 1>(s, n, rp, ci, k, first, pivots, m, q, status);
         else if (pre == 3) launch_select_wg_t<VW, true, 0>(s, n, rp, ci, k, first, pivots, m, q, status);
@@ -1675,7 +1670,7 @@ ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pi
     // more with more blocks, so a few dozen (measured best on MI355X for
     // 1M-node power-law and 3M-node mesh graphs).
     int blocks = std::max(1, std::min(std::min(maxb, kSelGridBlocks), div_up(n, 8192)));
-    if (env_int("SSM_SELECT_BLOCKS") > 0) blocks = std::min(maxb, env_int("SSM_SELECT_BLOCKS"));
+    if (variant("select_blocks") > 0) blocks = std::min(maxb, variant("select_blocks"));
     // m[n], vis[n], queue area (4n ints: two int queues of n, or two int2
     // queues of n for the one-workgroup kernel), control words
     size_t ints = 6 * (size_t)n + 8;
@@ -1702,13 +1697,13 @@ ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pi
                        4 * (long long)n);
     e = hipGetLastError();
     // Mode: one workgroup (no grid barrier) unless the frontiers are large.
-    int mode = env_int("SSM_SELECT_MODE");  // 1 = one workgroup, 2 = cooperative grid, 3 = per pivot
+    int mode = variant("select_mode");  // 1 = one workgroup, 2 = cooperative grid, 3 = per pivot
     if (mode < 1 || mode > 3) mode = (long long)n <= kSelOneWgMaxN ? 1 : 2;
     const bool per_pivot = mode == 3;
     // One workgroup: the LDS-resident form when the visited bits fit (tuning
     // override SSM_SELECT_ELL=2 keeps the global-memory form).
     int* ell = nullptr;
-    const bool use_ell = mode == 1 && sel_bits_fit(n) && env_int("SSM_SELECT_ELL") != 2;
+    const bool use_ell = mode == 1 && sel_bits_fit(n) && variant("select_ell") != 2;
     const int W = ell_width(g);
     if (use_ell && e == hipSuccess) {
         st = salloc((void**)&ell, sizeof(int) * (size_t)n * W);
@@ -1720,7 +1715,7 @@ ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pi
         }
         e = ell_build(g, W, ell, s);
         // with the byte copy of m when it fits (tuning override SSM_SELECT_M8=2: without)
-        const bool m8 = sel_m8_fits(n) && env_int("SSM_SELECT_M8") != 2;
+        const bool m8 = sel_m8_fits(n) && variant("select_m8") != 2;
         if (e == hipSuccess)
             e = launch_select_ell(W, m8, s, n, g->row_ptr, g->col_idx, ell, k, first, pivots, m, qa, status);
     } else if (mode == 1 && e == hipSuccess) {
@@ -2090,7 +2085,7 @@ ssm_status regions(int32_t n, int32_t k, const int32_t* dist, int32_t* delta, in
         // Few tied nodes: one workgroup walks the levels.  Many: one
         // multi-workgroup launch per level that has ties (tuning override
         // SSM_REGION_MODE: 1 one workgroup, 2 per level).
-        const int mode = env_int("SSM_REGION_MODE");
+        const int mode = variant("region_mode");
         const bool per_level = mode == 2 || (mode != 1 && haux[1] > kRegOneWgMax);
         std::vector<int> hstart(L + 1);
         e = hipMemsetAsync(ws, 0, sizeof(int) * ((size_t)k * L + L), s);

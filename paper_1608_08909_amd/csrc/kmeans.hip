@@ -393,8 +393,7 @@ ssm_status kmeans_pivots(int32_t n, int32_t k, const int32_t* pivots, const int3
             C = c;
         }
     }
-    if (const char* ev = getenv("SSM_KM_CHUNK")) {
-        const int c = atoi(ev);
+    if (const int c = variant("km_chunk")) {
         if (c == 32 || c == 40 || c == 48 || c == 56 || c == 64) C = c;
     }
     const int nchunks = div_up(k, C);

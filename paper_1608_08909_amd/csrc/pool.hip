@@ -19,6 +19,7 @@
 #include <mutex>
 #include <vector>
 
+#include "change.h"
 #include "ssm_internal.h"
 #include "wave.h"
 
@@ -293,6 +294,11 @@ __global__ __launch_bounds__(kPoolSweepBlock) void k_pool_sweep32(const PoolGrap
     const int p = (g.parity + s) & 1;
     const float2* __restrict__ xo = g.x32[p];
     float2* __restrict__ xn = g.x32[p ^ 1];
+    if (g.tol > 0.0 && g.info[6]) {  // the graph met its stop test: carry its iterate over
+        const int i = ch.y + threadIdx.x;
+        if (i < n) xn[i] = xo[i];
+        return;  // the whole block
+    }
     float2* sP = (float2*)psm;                   // [kpad]
     float2* sInv = sP + kpad;                    // [W] (hist)
     float* sH = (float*)(sInv + (hist ? W : 0));  // [kpad][L] (hist)
@@ -360,6 +366,52 @@ __global__ __launch_bounds__(kPoolSweepBlock) void k_pool_sweep32(const PoolGrap
     }
     const float dn = g.den32[i];
     xn[i] = make_float2(xi.x + ax / dn, xi.y + ay / dn);
+}
+
+// Algorithm 1's stop test after pool sweep s (change.h): the twelve moments
+// of each listed 256-node chunk of a graph that has a tolerance and has not
+// stopped yet, relative to o = the graph's node 0 in the old iterate.
+__global__ __launch_bounds__(256) void k_pool_moments(const PoolGraph* __restrict__ gs, const int2* __restrict__ chunks,
+                                                      int s, double* __restrict__ partial) {
+    const int2 ch = chunks[blockIdx.x];
+    const PoolGraph& g = gs[ch.x];
+    if (s >= g.iters || !(g.tol > 0.0) || g.info[6]) return;  // the whole block
+    const int p = (g.parity + s) & 1;
+    const float2* __restrict__ xo = g.x32[p];
+    const float2* __restrict__ xn = g.x32[p ^ 1];
+    const double2 o = to_d2(xo[0]);
+    double m[kMoments];
+#pragma unroll
+    for (int j = 0; j < kMoments; ++j) m[j] = 0.0;
+    const int i = ch.y + threadIdx.x;
+    if (i < g.n) moments_add(m, o, to_d2(xo[i]), to_d2(xn[i]));
+    __shared__ double red[256 / kWave];
+#pragma unroll
+    for (int j = 0; j < kMoments; ++j) {
+        const double v = block_sum(m[j], red);
+        if (threadIdx.x == 0) partial[(size_t)blockIdx.x * kMoments + j] = v;
+    }
+}
+
+// One thread per listed graph: the chunk partials first[q] .. first[q + 1]
+// summed in order; a change <= tol after sweep s sets info[6] and records
+// the sweeps run in info[7].
+__global__ void k_pool_decide(const PoolGraph* __restrict__ gs, int count, const int* __restrict__ first,
+                              const double* __restrict__ partial, int s) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= count) return;
+    const PoolGraph& g = gs[q];
+    if (s >= g.iters || !(g.tol > 0.0) || g.info[6]) return;
+    double m[kMoments];
+#pragma unroll
+    for (int j = 0; j < kMoments; ++j) m[j] = 0.0;
+    for (int c = first[q]; c < first[q + 1]; ++c)
+#pragma unroll
+        for (int j = 0; j < kMoments; ++j) m[j] += partial[(size_t)c * kMoments + j];
+    if (rigid_change(m, g.n) <= g.tol) {
+        g.info[7] = g.done0 + s + 1;
+        g.info[6] = 1;
+    }
 }
 
 // Sparse stress s' (Eq. 3) in FP64 of each graph's current FP32 iterate
@@ -510,6 +562,7 @@ struct Slot {
     int state = kFree;
     int n = 0, nnz = 0, k = 0, kpad = 0, first = 0, target = 0, done = 0, parity = 0;
     int dmax = 0, delta_max = 0, fail = 0, x64cur = 0;
+    double tol = 0.0;  // stop test of the FP32 sweeps (0: a fixed sweep count)
     size_t off_p = kNone, sz_p = 0, off_s = kNone, sz_s = 0, off_t = kNone, sz_t = 0;
     PoolGraph g{};
 };
@@ -574,6 +627,8 @@ void bind(ssm_pool* p, Slot& s) {
     g.W = s.dmax + 1;
     g.L = s.delta_max + 1;
     g.parity = s.parity;
+    g.tol = s.tol;
+    g.done0 = s.done;
     const int T = tile_cols(k);
     g.ntiles = T * (T + 1) / 2;
     g.nchunks = div_up(n, kPoolGramChunk);
@@ -1001,19 +1056,29 @@ ssm_status ssm_pool_sweep(ssm_pool* p, int32_t count, const int32_t* slots, int3
     stg.hc.clear();
     int most = 0;
     size_t lds = 0;
+    bool any_tol = false;
+    std::vector<int> first;  // first chunk of each listed graph (for the stop test)
     for (int q = 0; q < count; ++q) {
         Slot& sl = p->slots[slots[q]];
         PoolGraph g = sl.g;
         g.iters = std::max(0, std::min(iters, sl.target - sl.done));
         g.parity = sl.parity;
+        g.tol = sl.tol;
+        g.done0 = sl.done;
+        any_tol = any_tol || (sl.tol > 0.0 && g.iters > 0);
         most = std::max(most, g.iters);
         stg.hg.push_back(g);
+        first.push_back((int)stg.hc.size());
         for (int i0 = 0; i0 < sl.n; i0 += kPoolSweepBlock) stg.hc.push_back(make_int2(q, i0));
         lds = std::max(lds, sizeof(float2) * (size_t)sl.kpad +
                                 (g.hist ? sizeof(float2) * (size_t)g.W + sizeof(float) * (size_t)sl.kpad * g.L : 0));
     }
     if (most == 0) return SSM_OK;
-    const size_t need = align_up(sizeof(PoolGraph) * stg.hg.size()) + sizeof(int2) * stg.hc.size();
+    first.push_back((int)stg.hc.size());
+    const size_t o_first = align_up(sizeof(PoolGraph) * stg.hg.size()) + align_up(sizeof(int2) * stg.hc.size());
+    const size_t o_part = o_first + align_up(sizeof(int) * first.size());
+    const size_t need = any_tol ? o_part + sizeof(double) * kMoments * stg.hc.size()
+                                : align_up(sizeof(PoolGraph) * stg.hg.size()) + sizeof(int2) * stg.hc.size();
     if (need > stg.cap) {
         const size_t want = std::max(need, stg.cap * 2);
         if (stg.dev) (void)hipFree(stg.dev);
@@ -1027,14 +1092,23 @@ ssm_status ssm_pool_sweep(ssm_pool* p, int32_t count, const int32_t* slots, int3
     }
     PoolGraph* dg = (PoolGraph*)stg.dev;
     int2* dc = (int2*)(stg.dev + align_up(sizeof(PoolGraph) * stg.hg.size()));
+    int* dfirst = any_tol ? (int*)(stg.dev + o_first) : nullptr;
+    double* dpart = any_tol ? (double*)(stg.dev + o_part) : nullptr;
     hipError_t e = hipMemcpyAsync(dg, stg.hg.data(), sizeof(PoolGraph) * stg.hg.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(dc, stg.hc.data(), sizeof(int2) * stg.hc.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && any_tol)
+        e = hipMemcpyAsync(dfirst, first.data(), sizeof(int) * first.size(), hipMemcpyHostToDevice, s);
     const int nch = (int)stg.hc.size();
     if (lds > 64 * 1024)
         (void)hipFuncSetAttribute((const void*)k_pool_sweep32, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     for (int it = 0; it < most && e == hipSuccess; ++it) {
         hipLaunchKernelGGL(k_pool_sweep32, dim3(nch), dim3(kPoolSweepBlock), lds, s, dg, dc, it);
+        if (any_tol) {
+            hipLaunchKernelGGL(k_pool_moments, dim3(nch), dim3(256), 0, s, dg, dc, it, dpart);
+            hipLaunchKernelGGL(k_pool_decide, dim3(div_up(count, 256)), dim3(256), 0, s, dg, count, dfirst, dpart,
+                               it);
+        }
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipEventRecord(stg.done, s);
@@ -1050,6 +1124,60 @@ ssm_status ssm_pool_sweep(ssm_pool* p, int32_t count, const int32_t* slots, int3
         sl.done += d;
         sl.parity = (sl.parity + d) & 1;
         sl.g.parity = sl.parity;
+    }
+    return SSM_OK;
+}
+
+ssm_status ssm_pool_set_tol(ssm_pool* p, int32_t slot, double tol) {
+    if (!p) return fail(SSM_E_INVAL, "pool is NULL");
+    if (!(tol >= 0.0)) return fail(SSM_E_INVAL, "tol must be >= 0");
+    std::lock_guard<std::mutex> lk(p->mu);
+    Slot* sl = get_slot(p, slot);
+    if (!sl || (sl->state != kAdded && sl->state != kReady)) return fail(SSM_E_INVAL, "pool: no such slot");
+    sl->tol = tol;
+    sl->g.tol = tol;
+    return SSM_OK;
+}
+
+ssm_status ssm_pool_stopped(ssm_pool* p, int32_t count, const int32_t* slots, int32_t* sweeps_host,
+                            hipStream_t s) {
+    if (!p || (count > 0 && (!slots || !sweeps_host))) return fail(SSM_E_INVAL, "NULL argument");
+    if (count < 0) return fail(SSM_E_INVAL, "count must be >= 0");
+    std::lock_guard<std::mutex> lk(p->mu);
+    std::vector<PoolGraph> hg;
+    for (int q = 0; q < count; ++q) {
+        Slot* sl = get_slot(p, slots[q]);
+        if (!sl || sl->state != kReady) return fail(SSM_E_INVAL, "pool: stopped needs prepared slots");
+        hg.push_back(sl->g);
+    }
+    if (count == 0) return SSM_OK;
+    ssm_status st = wait_all(p);  // the slots' last sweeps may run on another stream
+    if (st != SSM_OK) return st;
+    char* ws = nullptr;
+    const size_t o_info = align_up(sizeof(PoolGraph) * count);
+    st = salloc((void**)&ws, o_info + sizeof(int) * 8 * (size_t)count);
+    if (st != SSM_OK) return st;
+    std::vector<int> hinfo(8 * (size_t)count);
+    hipError_t e = hipMemcpyAsync(ws, hg.data(), sizeof(PoolGraph) * count, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_pool_gather_info, dim3(div_up(8 * count, 256)), dim3(256), 0, s, (const PoolGraph*)ws,
+                           count, (int*)(ws + o_info));
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hinfo.data(), ws + o_info, sizeof(int) * 8 * (size_t)count, hipMemcpyDeviceToHost, s);
+    const hipError_t e2 = hipStreamSynchronize(s);
+    sfree(ws);
+    if (e != hipSuccess) return hip_fail(e, "pool: stopped");
+    if (e2 != hipSuccess) return hip_fail(e2, "pool: stopped");
+    for (int q = 0; q < count; ++q) {
+        Slot& sl = p->slots[slots[q]];
+        if (hinfo[8 * (size_t)q + 6]) {
+            sweeps_host[q] = hinfo[8 * (size_t)q + 7];
+            sl.target = sl.done;  // no further sweeps
+        } else {
+            sweeps_host[q] = -1;
+        }
     }
     return SSM_OK;
 }

@@ -34,6 +34,7 @@ struct ssm_terms {
     void* xtmp = nullptr;       // [n][2] doubles: second buffer of the Jacobi sweeps
     double* red = nullptr;      // reduction scratch, red_len doubles
     int32_t red_len = 0;
+    int32_t* stopw = nullptr;   // [4] sweep loop: {stop test fired, sweeps run}
     double* eig = nullptr;      // [2k + 2] V (k x 2) then lambda (2)
     double* gram = nullptr;     // [k][k] C^T C of the last PivotMDS
     int32_t* eig_iters = nullptr;  // [1]
@@ -91,6 +92,8 @@ ssm_status dalloc(void** p, size_t bytes);
 ssm_status salloc(void** p, size_t bytes);
 void sfree(void* p);
 void release_cached_scratch();
+// Launch-variant override set by ssm_set_variant, or `unset` when none is.
+int variant(const char* name, int unset = 0);
 
 // ---- BFS / regions (bfs.hip)
 ssm_status mssp(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dist,
@@ -174,7 +177,10 @@ struct PoolGraph {
     double* M;              // [k][k]
     double* eig;            // [2 k + 2]
     double* gpart;          // [nchunks][ntiles][256] Gram partial tiles
-    int* info;              // [8]: disconnected, dmax, delta_max, zero edge length, eigen steps
+    int* info;              // [8]: disconnected, dmax, delta_max, zero edge length, eigen steps, invalid
+                            // CSR, stop test fired, sweeps run when it fired
+    double tol;             // stop test of the FP32 sweeps (0: a fixed sweep count)
+    int done0;              // sweeps run before this sweep call
 };
 
 // Stages (bfs.hip): fill the max/min scratch and the padded adjacency; one

@@ -8,6 +8,7 @@
 
 #include <hipcub/hipcub.hpp>
 
+#include "change.h"
 #include "ssm_internal.h"
 #include "sweep_f32.h"
 #include "wave.h"
@@ -45,8 +46,9 @@ __global__ __launch_bounds__(256) void k_sweep_f64(int n, int kpad, int W, const
                                                    double2* __restrict__ xn, const uint4* __restrict__ dpk,
                                                    const int* __restrict__ piv,
                                                    const double* __restrict__ wt,
-                                                   const double* __restrict__ den) {
+                                                   const double* __restrict__ den, const int* __restrict__ stop) {
 #pragma clang fp contract(off)
+    if (stop[0]) return;  // the sweep loop has met its stop test (uniform over the grid)
     extern __shared__ double2 sP[];
     for (int t = threadIdx.x; t < kpad; t += blockDim.x) sP[t] = xo[piv[t]];
     __syncthreads();
@@ -174,10 +176,9 @@ ssm_status heavy_segments(const ssm_csr* g, ssm_terms* t, hipStream_t s) {
 
 // ------------------------------------------------ FP32 sweep node order
 
-int sweep_order_mode() {  // tuning override SSM_SWEEP_PERM: 0 = the caller's order, 2 = always reorder
-    const char* v = getenv("SSM_SWEEP_PERM");
-    const int m = v ? atoi(v) : 1;
-    return m == 0 || m == 2 ? m : 1;
+int sweep_order_mode() {  // variant sweep_perm: -1 = the caller's order, 2 = always reorder
+    const int m = variant("sweep_perm");
+    return m == -1 ? 0 : m == 2 ? 2 : 1;
 }
 
 __global__ void k_order_keys(int n, const int* __restrict__ delta, const int* __restrict__ region,
@@ -341,42 +342,70 @@ __global__ __launch_bounds__(256) void k_stress(int n, int kpad, int W, const in
     if (threadIdx.x == 0) partials[blockIdx.x] = acc;
 }
 
-// Relative change of one sweep: partials of ||x_new - x_old||^2 and ||x_old||^2.
+// Algorithm 1's stop test after a sweep xo -> xn (change.h): per-block
+// partials of the twelve moments, relative to o = xo[0].
 template <typename T2>
-__global__ __launch_bounds__(256) void k_change(int n, const T2* __restrict__ xo, const T2* __restrict__ xn,
-                                                double* __restrict__ partials) {
-    double dd = 0.0, xx = 0.0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        double2 a = as_d2(xo[i]), b = as_d2(xn[i]);
-        dd += (b.x - a.x) * (b.x - a.x) + (b.y - a.y) * (b.y - a.y);
-        xx += a.x * a.x + a.y * a.y;
-    }
+__global__ __launch_bounds__(256) void k_rigid_moments(int n, const T2* __restrict__ xo, const T2* __restrict__ xn,
+                                                       const int* __restrict__ stop, double* __restrict__ partials) {
+    if (stop[0]) return;
+    const double2 o = to_d2(xo[0]);
+    double m[kMoments];
+#pragma unroll
+    for (int j = 0; j < kMoments; ++j) m[j] = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        moments_add(m, o, to_d2(xo[i]), to_d2(xn[i]));
     __shared__ double red[256 / kWave];
-    dd = block_sum(dd, red);
-    xx = block_sum(xx, red);
-    if (threadIdx.x == 0) {
-        partials[2 * blockIdx.x] = dd;
-        partials[2 * blockIdx.x + 1] = xx;
+#pragma unroll
+    for (int j = 0; j < kMoments; ++j) {
+        const double v = block_sum(m[j], red);
+        if (threadIdx.x == 0) partials[(size_t)blockIdx.x * kMoments + j] = v;
     }
 }
 
-__global__ __launch_bounds__(256) void k_sum_pairs(const double* __restrict__ partials, int count,
-                                                   double* __restrict__ out) {
-    double a = 0.0, b = 0.0;
-    for (int q = threadIdx.x; q < count; q += blockDim.x) {
-        a += partials[2 * q];
-        b += partials[2 * q + 1];
-    }
+// One block: sums the partials in a fixed order; after sweep `it` (0-based)
+// of the loop, a change <= tol sets the stop flag and records it + 1 sweeps.
+// stopw = {flag, sweeps run}.
+__global__ __launch_bounds__(256) void k_rigid_decide(int nblocks, const double* __restrict__ partials, int n,
+                                                      double tol, int it, int* __restrict__ stopw,
+                                                      double* __restrict__ last_change) {
+    if (stopw[0]) return;
     __shared__ double red[256 / kWave];
-    a = block_sum(a, red);
-    b = block_sum(b, red);
-    if (threadIdx.x == 0) {
-        out[0] = a;
-        out[1] = b;
+    double m[kMoments];
+#pragma unroll
+    for (int j = 0; j < kMoments; ++j) {
+        double v = 0.0;
+        for (int q = threadIdx.x; q < nblocks; q += blockDim.x) v += partials[(size_t)q * kMoments + j];
+        m[j] = block_sum(v, red);
     }
+    if (threadIdx.x == 0) {
+        const double c = rigid_change(m, n);
+        last_change[0] = c;
+        if (c <= tol) {
+            stopw[0] = 1;
+            stopw[1] = it + 1;
+        }
+    }
+}
+
+// stopw = {0 (not stopped), iters (sweeps run unless the test fires)}.
+__global__ void k_stop_init(int* stopw, int iters) {
+    if (threadIdx.x == 0) {
+        stopw[0] = 0;
+        stopw[1] = iters;
+    }
+}
+
+// After a loop with a stop test: the result lies in buffer (sweeps run) & 1;
+// bring it to buffer 0.
+template <typename T2>
+__global__ void k_stop_result(int n, const int* __restrict__ stopw, T2* __restrict__ b0, const T2* __restrict__ b1) {
+    if (!(stopw[1] & 1)) return;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) b0[i] = b1[i];
 }
 
 // -------------------------------------------------------------- driver
+
+constexpr int kStopBlocks = 512;  // blocks of the stop test's moments (partials fit the handle's scratch)
 
 struct SweepPlan {
     int grid = 1, block = 256, split = 4, cpb = 4, mode = kTableGlobal;
@@ -391,7 +420,7 @@ static void launch_f32(const SweepPlan& pl, hipStream_t s, const ssm_csr* g, con
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds);
     hipLaunchKernelGGL((k_sweep_f32<DT, VEC, SPLIT, CPB, MODE>), dim3(pl.grid), dim3(64 * SPLIT * CPB), pl.lds, s,
                        t->n, t->kpad, t->W, t->delta_max + 1, g->row_ptr, g->col_idx, xo, xn, (const uint4*)t->dpk,
-                       pc, pc_next, t->prank, t->wt2, t->Hf, t->invd, t->den32, t->seg_range, t->seg_sum);
+                       pc, pc_next, t->prank, t->wt2, t->Hf, t->invd, t->den32, t->seg_range, t->seg_sum, t->stopw);
 }
 
 template <typename DT, int VEC, int SPLIT, int CPB>
@@ -434,17 +463,17 @@ static void sweep_once(const SweepPlan& pl, ssm_prec p, hipStream_t s, const ssm
         if (t->dbytes == 1)
             hipLaunchKernelGGL((k_sweep_f64<uint8_t, 16>), dim3(pl.grid), dim3(pl.block), pl.lds, s, t->n, t->kpad,
                                t->W, g->row_ptr, g->col_idx, (const double2*)xo, (double2*)xn,
-                               (const uint4*)t->dpk, t->pivots, t->wtab64, t->den64);
+                               (const uint4*)t->dpk, t->pivots, t->wtab64, t->den64, t->stopw);
         else
             hipLaunchKernelGGL((k_sweep_f64<uint16_t, 8>), dim3(pl.grid), dim3(pl.block), pl.lds, s, t->n, t->kpad,
                                t->W, g->row_ptr, g->col_idx, (const double2*)xo, (double2*)xn,
-                               (const uint4*)t->dpk, t->pivots, t->wtab64, t->den64);
+                               (const uint4*)t->dpk, t->pivots, t->wtab64, t->den64, t->stopw);
         return;
     }
     if (t->nseg > 0)
         hipLaunchKernelGGL(k_heavy_edges, dim3(std::min(div_up(t->nseg, 4), 4096)), dim3(256), 0, s, t->nseg,
                            t->heavy, t->seg_start, t->seg_owner, g->row_ptr, g->col_idx, (const float2*)xo,
-                           t->seg_sum);
+                           t->seg_sum, t->stopw);
     if (t->dbytes == 1)
         dispatch_split<uint8_t, 16>(pl, s, g, t, (const float2*)xo, (float2*)xn, pc, pc_next);
     else
@@ -472,8 +501,7 @@ static SweepPlan plan_sweep(const ssm_terms* t, ssm_prec p) {
         pl.mode = kHistLds;
     else
         pl.mode = kTableGlobal;
-    if (const char* v = getenv("SSM_SWEEP_MODE")) {  // tuning override (a form that fits)
-        const int f = atoi(v);
+    if (const int f = variant("sweep_mode")) {  // override: 2 = global table, 1 = LDS histograms (if they fit)
         if (f == kTableGlobal || (f == kHistLds && hist + parts <= kSweepLdsMax)) pl.mode = f;
     }
     const size_t tab = pl.mode == kTableLds ? table : pl.mode == kHistLds ? hist : 0;
@@ -485,8 +513,7 @@ static SweepPlan plan_sweep(const ssm_terms* t, ssm_prec p) {
     // two for 4-wave blocks, one for the 16-wave blocks of large tables
     const long long chunks = div_up(t->n, 64);
     int split = std::min(pl.block == 1024 ? 1 : 2, nwords);
-    if (const char* v = getenv("SSM_SWEEP_SPLIT")) {  // tuning override
-        const int f = atoi(v);
+    if (const int f = variant("sweep_split")) {  // override
         if ((f == 1 || f == 2 || f == 4) && f <= nwords) split = f;
     }
     pl.split = split;
@@ -495,52 +522,62 @@ static SweepPlan plan_sweep(const ssm_terms* t, ssm_prec p) {
     const int per_cu = pl.block == 1024 ? (pl.lds <= 80 * 1024 ? 2 : 1)
                                         : std::max(1, std::min(4, (int)((160 * 1024) / std::max<size_t>(pl.lds, 1))));
     long long max_grid = (long long)num_cus() * per_cu;
-    if (const char* v = getenv("SSM_SWEEP_BLOCKS_PER_CU")) max_grid = std::max(1, atoi(v)) * (long long)num_cus();
+    if (const int v = variant("sweep_blocks_per_cu")) max_grid = std::max(1, v) * (long long)num_cus();
     const long long groups = div_up(chunks, pl.cpb);
     pl.grid = (int)std::max<long long>(1, std::min(groups, max_grid));
     return pl;
 }
 
 // The sweep loop over buffers bufs[0] (in/out) and bufs[1]; the result ends
-// in bufs[0].
+// in bufs[0].  With tol > 0, Algorithm 1's stop test runs on the device after
+// every sweep (k_rigid_moments, k_rigid_decide); once it fires, the later
+// sweeps of the loop return at once, and the buffer holding the result is
+// chosen on the device.  Nothing waits on the host unless the sweep count is
+// asked for.
 static ssm_status sweep_loop(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* const (&bufs)[2], int32_t iters,
                              double tol, int32_t* iters_done_host, hipStream_t s) {
     const SweepPlan pl = plan_sweep(t, p);
     const size_t xbytes = (p == SSM_FP64 ? sizeof(double) : sizeof(float)) * 2 * (size_t)t->n;
     void* const x = bufs[0];
-    int cur = 0, done = 0;
-    const int cblocks = std::min(div_up(t->n, 256), 2048);
+    const int mblocks = std::min(div_up(t->n, 256), kStopBlocks);
+    double* parts = t->red;
     float2* pcb[2] = {t->pc, t->pc + t->kpad};
+    hipLaunchKernelGGL(k_stop_init, dim3(1), dim3(64), 0, s, t->stopw, iters);
     if (p == SSM_FP32 && iters > 0)
         hipLaunchKernelGGL(k_gather_pivots, dim3(div_up(t->kpad, 256)), dim3(256), 0, s, t->kpad, t->pivots,
                            (const float2*)x, pcb[0]);
-    for (; done < iters; ++done) {
-        sweep_once(pl, p, s, g, t, bufs[cur], bufs[cur ^ 1], pcb[done & 1], pcb[(done + 1) & 1]);
+    for (int it = 0; it < iters; ++it) {
+        const int cur = it & 1;
+        sweep_once(pl, p, s, g, t, bufs[cur], bufs[cur ^ 1], pcb[cur], pcb[cur ^ 1]);
         if (tol > 0.0) {
             if (p == SSM_FP64)
-                hipLaunchKernelGGL(k_change<double2>, dim3(cblocks), dim3(256), 0, s, t->n,
-                                   (const double2*)bufs[cur], (const double2*)bufs[cur ^ 1], t->red);
+                hipLaunchKernelGGL(k_rigid_moments<double2>, dim3(mblocks), dim3(256), 0, s, t->n,
+                                   (const double2*)bufs[cur], (const double2*)bufs[cur ^ 1], t->stopw, parts);
             else
-                hipLaunchKernelGGL(k_change<float2>, dim3(cblocks), dim3(256), 0, s, t->n,
-                                   (const float2*)bufs[cur], (const float2*)bufs[cur ^ 1], t->red);
-            hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(256), 0, s, t->red, cblocks, t->red + 2 * cblocks);
-            double h[2] = {0, 0};
-            SSM_HIP(hipMemcpyAsync(h, t->red + 2 * cblocks, sizeof h, hipMemcpyDeviceToHost, s));
-            SSM_HIP(hipStreamSynchronize(s));
-            cur ^= 1;
-            if (h[1] > 0.0 && sqrt(h[0]) / sqrt(h[1]) <= tol) {
-                ++done;
-                break;
-            }
-        } else {
-            cur ^= 1;
+                hipLaunchKernelGGL(k_rigid_moments<float2>, dim3(mblocks), dim3(256), 0, s, t->n,
+                                   (const float2*)bufs[cur], (const float2*)bufs[cur ^ 1], t->stopw, parts);
+            hipLaunchKernelGGL(k_rigid_decide, dim3(1), dim3(256), 0, s, mblocks, parts, t->n, tol, it, t->stopw,
+                               parts + (size_t)kStopBlocks * kMoments);
         }
     }
     SSM_HIP(hipGetLastError());
-    if (cur == 1) SSM_HIP(hipMemcpyAsync(x, bufs[1], xbytes, hipMemcpyDeviceToDevice, s));
+    if (tol > 0.0) {
+        const int gb = std::min(div_up(t->n, 256), 4096);
+        if (p == SSM_FP64)
+            hipLaunchKernelGGL(k_stop_result<double2>, dim3(gb), dim3(256), 0, s, t->n, t->stopw, (double2*)x,
+                               (const double2*)bufs[1]);
+        else
+            hipLaunchKernelGGL(k_stop_result<float2>, dim3(gb), dim3(256), 0, s, t->n, t->stopw, (float2*)x,
+                               (const float2*)bufs[1]);
+        SSM_HIP(hipGetLastError());
+    } else if (iters & 1) {
+        SSM_HIP(hipMemcpyAsync(x, bufs[1], xbytes, hipMemcpyDeviceToDevice, s));
+    }
     if (iters_done_host) {
+        int32_t h[2] = {0, 0};
+        SSM_HIP(hipMemcpyAsync(h, t->stopw, sizeof h, hipMemcpyDeviceToHost, s));
         SSM_HIP(hipStreamSynchronize(s));
-        *iters_done_host = done;
+        *iters_done_host = h[1];
     }
     return SSM_OK;
 }

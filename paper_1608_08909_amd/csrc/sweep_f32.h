@@ -37,7 +37,8 @@ __global__ __launch_bounds__(256) void k_heavy_edges(int nseg, const int* __rest
                                                      const int* __restrict__ seg_start,
                                                      const int* __restrict__ seg_owner, const int* __restrict__ rp,
                                                      const int* __restrict__ ci, const float2* __restrict__ xo,
-                                                     float2* __restrict__ seg_sum) {
+                                                     float2* __restrict__ seg_sum, const int* __restrict__ stop) {
+    if (stop[0]) return;  // the sweep loop has met its stop test
     const int lane = lane_id();
     const float tiny = 1e-30f;
     for (int q = (blockIdx.x * blockDim.x + threadIdx.x) / kWave; q < nseg; q += gridDim.x * blockDim.x / kWave) {
@@ -106,7 +107,9 @@ __global__ __launch_bounds__(64 * SPLIT * CPB) void k_sweep_f32(
     const float2* __restrict__ xo, float2* __restrict__ xn, const uint4* __restrict__ dpk,
     const float2* __restrict__ pc, float2* __restrict__ pc_next, const int* __restrict__ prank,
     const float2* __restrict__ wt2, const float* __restrict__ Hf, const float2* __restrict__ invd,
-    const float* __restrict__ den, const int2* __restrict__ seg_range, const float2* __restrict__ seg_sum) {
+    const float* __restrict__ den, const int2* __restrict__ seg_range, const float2* __restrict__ seg_sum,
+    const int* __restrict__ stop) {
+    if (stop[0]) return;  // the sweep loop has met its stop test (uniform over the grid)
     constexpr int NW = SPLIT * CPB;
     extern __shared__ float4 smem4[];
     float2* sP = (float2*)smem4;                                  // [kpad] pivot coordinates

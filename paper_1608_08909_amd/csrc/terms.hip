@@ -272,6 +272,7 @@ ssm_status build_terms(const ssm_csr* g, int32_t k, const int32_t* pivots, const
         {(void**)&t->dpk, (size_t)t->kpad * n * t->dbytes},
         {(void**)&t->xtmp, sizeof(double) * 2 * (size_t)n},
         {(void**)&t->red, sizeof(double) * (size_t)t->red_len},
+        {(void**)&t->stopw, sizeof(int) * 4},
         {(void**)&t->eig, sizeof(double) * (2 * (size_t)k + 2)},
         {(void**)&t->gram, sizeof(double) * (size_t)k * k},
         {(void**)&t->eig_iters, sizeof(int)},

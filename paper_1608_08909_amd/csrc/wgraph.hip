@@ -44,11 +44,8 @@ constexpr int kSsspBlock = 1024;
 constexpr int kSsspLanes = 8;  // lanes per frontier node in the search
 constexpr size_t kSsspLdsBits = 128 * 1024;  // largest LDS of the three near-far bitmaps (n <= 349504)
 
-// Tuning override SSM_SSSP_NEARFAR=0: the plain label-correcting order.
-static bool nearfar_off() {
-    const char* v = getenv("SSM_SSSP_NEARFAR");
-    return v && atoi(v) == 0;
-}
+// Variant sssp_nearfar = -1: the plain label-correcting order.
+static bool nearfar_off() { return variant("sssp_nearfar") == -1; }
 constexpr unsigned long long kInfBits = 0x7FF0000000000000ull;  // +inf; non-negative doubles order as their bits
 
 __device__ __forceinline__ double ld_dist(const unsigned long long* D, int v) {
@@ -724,7 +721,7 @@ ssm_status length_band(const ssm_csr* g, const double* len, unsigned long long* 
     // few blocks: each ends in an atomic on the same word
     hipLaunchKernelGGL(k_len_check, dim3(std::max(1, std::min(div_up(g->nnz, 1024), 128))), dim3(256), 0, s,
                        (long long)g->nnz, len, delta, bad);
-    if (const char* v = getenv("SSM_SSSP_BAND")) c = atoi(v);  // tuning override
+    if (const int v = variant("sssp_band")) c = v;  // variant override
     if (c > 1) hipLaunchKernelGGL(k_band_scale, dim3(1), dim3(64), 0, s, delta, (double)c);
     int hb = 0;
     SSM_HIP(hipGetLastError());

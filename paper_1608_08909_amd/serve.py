@@ -4,7 +4,9 @@ Requests arrive over time (each with its graph, k and sweep count).  The loop
 admits arrived requests while the pool's arena has room (admission by device
 memory budget), prepares each newly admitted batch on a second stream while
 the already-running graphs sweep on the first, and retires a graph as soon as
-its sweep count is reached (its stress and layout are read, its slot freed).
+its sweep count is reached or its stop test (Algorithm 1's relative
+positional change, when the request sets a tolerance) has fired (its stress
+and layout are read, its slot freed).
 Graphs join and leave between sweep quanta, so the device always sweeps every
 graph that is ready, whatever its size or arrival time.
 
@@ -30,9 +32,11 @@ class Request:
     arrival: float  # seconds after the start of the stream
     sweeps: int = 200
     first: int = 0
+    tol: float = 0.0  # Algorithm 1's stop test (0: run `sweeps` sweeps)
     # filled by the loop
     slot: int = -1
     done: int = 0  # sweeps enqueued
+    sweeps_run: int = 0  # sweeps the layout took (fewer than `sweeps` when the stop test fired)
     admitted: float = float("nan")
     finished: float = float("nan")
     stress: float = float("nan")
@@ -105,6 +109,8 @@ def serve(requests, pool_bytes: int, quantum: int = 25, warm: int = 1, max_prepa
                     continue
                 break
             waiting.popleft()
+            if r.tol > 0:
+                pool.set_tol(slot, r.tol)
             r.slot, r.admitted, r.status = slot, clock() - t0, "admitted"
             new.append(r)
         peak_bytes = max(peak_bytes, pool.usage()[0])
@@ -136,6 +142,16 @@ def serve(requests, pool_bytes: int, quantum: int = 25, warm: int = 1, max_prepa
         peak_active = max(peak_active, len(active))
         td = clock()
         host["prepare"] += td - tc
+        # graphs whose stop test has fired take no more sweeps (the query
+        # waits for the sweeps queued so far)
+        tol_slots = [s for s, r in active.items() if r.tol > 0 and r.done < r.sweeps]
+        if tol_slots:
+            with torch.cuda.stream(s_sweep):
+                ran = pool.stopped(tol_slots)
+            for s, v in zip(tol_slots, ran):
+                if v >= 0:
+                    active[s].done = active[s].sweeps
+                    active[s].sweeps_run = int(v)
         # retire the graphs whose sweep count is reached
         fin = [s for s, r in active.items() if r.done >= r.sweeps]
         if fin:
@@ -144,6 +160,8 @@ def serve(requests, pool_bytes: int, quantum: int = 25, warm: int = 1, max_prepa
                 t_done = clock() - t0
                 for s, v in zip(fin, st):
                     r = active[s]
+                    if r.sweeps_run == 0:
+                        r.sweeps_run = r.sweeps
                     if keep_layouts:
                         r.layout = pool.layout(s, r.graph.n)
                     r.stress, r.finished, r.status = float(v), t_done, "done"

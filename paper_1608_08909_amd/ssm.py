@@ -67,6 +67,7 @@ EXPORTS = [
     "ssm_pool_stress", "ssm_pool_layout", "ssm_pool_export", "ssm_pool_info", "ssm_pool_remove", "ssm_procrustes",
     "ssm_select_pivots_w", "ssm_sssp_pivots", "ssm_build_terms_w", "ssm_wterms_free", "ssm_wterms_export",
     "ssm_pivotmds_init_w", "ssm_majorize_w", "ssm_majorize_mixed_w", "ssm_stress_w", "ssm_release_cache",
+    "ssm_set_variant", "ssm_pool_set_tol", "ssm_pool_stopped",
 ]
 
 
@@ -122,6 +123,9 @@ def load(path: str | None = None):
             "ssm_majorize_mixed_w": (S, [P, V, V, V, V, I, I, V]),
             "ssm_stress_w": (S, [P, V, V, I, V, V, V]),
             "ssm_release_cache": (None, []),
+            "ssm_set_variant": (S, [ctypes.c_char_p, I]),
+            "ssm_pool_set_tol": (S, [V, I, D]),
+            "ssm_pool_stopped": (S, [V, I, V, V, V]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -131,6 +135,30 @@ def load(path: str | None = None):
             _lib = lib
             atexit.register(shutdown)
         return lib
+
+
+def set_variant(name: str | None, value: int = 0):
+    """Forces a launch variant (ssm_set_variant); value 0 restores the
+    library's choice, name None clears every override."""
+    _check(load().ssm_set_variant(name.encode() if name is not None else None, int(value)), "ssm_set_variant")
+
+
+class variants:
+    """Context manager: `with ssm.variants(sweep_split=4): ...` forces the
+    given launch variants and clears them on exit."""
+
+    def __init__(self, **kw):
+        self.kw = kw
+
+    def __enter__(self):
+        for name, value in self.kw.items():
+            set_variant(name, int(value))
+        return self
+
+    def __exit__(self, *exc):
+        for name in self.kw:
+            set_variant(name, 0)
+        return False
 
 
 def _check(st: int, func: str):
@@ -491,6 +519,18 @@ class Pool:
 
     def remove(self, slot: int):
         _check(self._lib.ssm_pool_remove(self.handle, int(slot)), "ssm_pool_remove")
+
+    def set_tol(self, slot: int, tol: float):
+        """Stop test of the slot's FP32 sweeps (0: its fixed sweep count)."""
+        _check(self._lib.ssm_pool_set_tol(self.handle, int(slot), float(tol)), "ssm_pool_set_tol")
+
+    def stopped(self, slots):
+        """Per slot: the sweeps its layout took if its stop test fired, else -1."""
+        import numpy as np
+        a = self._slots(slots)
+        out = np.empty(a.size, dtype=np.int32)
+        _check(self._lib.ssm_pool_stopped(self.handle, a.size, _hptr(a), _hptr(out), _stream()), "ssm_pool_stopped")
+        return out
 
 
 # ------------------------------------------------------- graphs with edge lengths

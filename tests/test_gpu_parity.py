@@ -84,21 +84,21 @@ def test_regions_with_given_pivots():
     assert np.array_equal(region.cpu().numpy(), region_r)
 
 
-# Launch-shape overrides the library reads from the environment: each selects
+# Launch-variant overrides (ssm_set_variant): each selects
 # another kernel variant (cooperative-grid or per-pivot selection, selection
 # without the LDS byte copy or over the plain CSR with node-id queues or
 # another precheck, the CSR per-workgroup BFS, the bit-parallel BFS, one- or
 # many-workgroup region tie resolution, other lanes per node).
 VARIANTS = [
-    {"SSM_SELECT_MODE": "2"}, {"SSM_SELECT_MODE": "2", "SSM_SELECT_BLOCKS": "3"}, {"SSM_SELECT_MODE": "3"},
-    {"SSM_SELECT_M8": "2"}, {"SSM_SELECT_ELL": "2"}, {"SSM_SELECT_MODE": "1"},
-    {"SSM_SELECT_ELL": "2", "SSM_SELECT_ROWQ": "2"},
-    {"SSM_SELECT_ELL": "2", "SSM_SELECT_ROWQ": "2", "SSM_SELECT_PRE": "3"},
-    {"SSM_SELECT_ELL": "2", "SSM_SELECT_PRE": "1"},
-    {"SSM_BFS_ROWQ": "2", "SSM_BFS_ELL": "2"}, {"SSM_BFS_ELL": "2"}, {"SSM_MSBFS": "1"},
-    {"SSM_MSBFS": "1", "SSM_MSBFS_BUDGET": "3"},
-    {"SSM_REGION_MODE": "1"}, {"SSM_REGION_MODE": "2"}, {"SSM_BFS_LANES": "2"}, {"SSM_BFS_LANES": "64"},
-    {"SSM_SELECT_WAVE": "0"}, {"SSM_SELECT_WAVE": "2"},
+    {"select_mode": 2}, {"select_mode": 2, "select_blocks": 3}, {"select_mode": 3},
+    {"select_m8": 2}, {"select_ell": 2}, {"select_mode": 1},
+    {"select_ell": 2, "select_rowq": 2},
+    {"select_ell": 2, "select_rowq": 2, "select_pre": 3},
+    {"select_ell": 2, "select_pre": 1},
+    {"bfs_rowq": 2, "bfs_ell": 2}, {"bfs_ell": 2}, {"msbfs": 1},
+    {"msbfs": 1, "msbfs_budget": 3},
+    {"region_mode": 1}, {"region_mode": 2}, {"bfs_lanes": 2}, {"bfs_lanes": 64},
+    {"select_wave": -1}, {"select_wave": 2},
 ]
 # (the star's first level overflows the LDS part of the frontier queue; the
 # path's levels pass the state byte's saturation)
@@ -106,10 +106,10 @@ VARIANT_CASES = [(G.barabasi_albert(2000, 5, 7), 50), (G.rgg(1500, 4), 33), (G.h
                  (G.tree_plus(300, 2), 17), (G.star(12), 3), (G.path(600), 6), (G.star(3000), 3)]
 
 
-@pytest.mark.parametrize("env", VARIANTS, ids=["-".join(f"{a[4:]}={b}" for a, b in v.items()) for v in VARIANTS])
-def test_kernel_variants_bit_exact(env, monkeypatch):
+@pytest.mark.parametrize("env", VARIANTS, ids=["-".join(f"{a}={b}" for a, b in v.items()) for v in VARIANTS])
+def test_kernel_variants_bit_exact(env, forced):
     for name, val in env.items():
-        monkeypatch.setenv(name, val)
+        forced(name, val)
     for g, k in VARIANT_CASES:
         say("variant", env, "case", g.name, "k", k)
         ref = oracle.preprocess(g.n, g.row_ptr, g.col_idx, k)
@@ -124,24 +124,24 @@ def test_kernel_variants_bit_exact(env, monkeypatch):
 @pytest.mark.parametrize("g,k", [(G.rgg(150000, 21, 8.0), 24), (G.grid(400, 400), 8), (G.barabasi_albert(120000, 2, 5), 30)],
                          ids=["rgg150000-k24", "grid400x400-k8", "ba120000-k30"])
 @pytest.mark.parametrize("mode", ["0", "2"], ids=["auto", "grid"])
-def test_select_beyond_byte_copy(g, k, mode, monkeypatch):
+def test_select_beyond_byte_copy(g, k, mode, forced):
     """Graphs too large for the LDS byte copy of m but within one workgroup's
     visited bits, and the cooperative grid form; the grid graph has
     eccentricities far above 255; the BA graph has frontiers wider than one
     pass."""
-    monkeypatch.setenv("SSM_SELECT_MODE", mode)
+    forced("select_mode", int(mode))
     say("case", g.name, "k", k, "mode", mode)
     piv_r, _ = oracle.select_pivots(g.n, g.row_ptr, g.col_idx, k, 0)
     dg = ssm.DeviceGraph.from_csr(g)
     assert np.array_equal(ssm.select_pivots(dg, k, 0).cpu().numpy(), piv_r)
 
 
-@pytest.mark.parametrize("env", [{}, {"SSM_MSBFS": "1"}, {"SSM_BFS_ELL": "2"}], ids=["default", "bitparallel", "csr"])
-def test_bfs_large_frontiers(env, monkeypatch):
+@pytest.mark.parametrize("env", [{}, {"msbfs": 1}, {"bfs_ell": 2}], ids=["default", "bitparallel", "csr"])
+def test_bfs_large_frontiers(env, forced):
     """Frontiers beyond the LDS queue and more long rows per level than the
     LDS list holds: the global overflow areas of the per-pivot BFS."""
     for name, val in env.items():
-        monkeypatch.setenv(name, val)
+        forced(name, val)
     g = G.barabasi_albert(60000, 5, 3)
     piv = np.array([0, 17, 999, 30000, 59999, 12345, 4242, 777], dtype=np.int32)
     say("case", g.name, "pivots", piv.tolist(), "env", env)
@@ -257,19 +257,19 @@ def test_sweeps_f32_stress(g, k):
     assert abs(s32 - sr) <= 1e-4 * sr, (s32, sr)
 
 
-SWEEP_VARIANTS = [{"SSM_SWEEP_SPLIT": "1"}, {"SSM_SWEEP_SPLIT": "2"}, {"SSM_SWEEP_SPLIT": "4"},
-                  {"SSM_SWEEP_MODE": "1"}, {"SSM_SWEEP_MODE": "2"}, {"SSM_SWEEP_MODE": "2", "SSM_SWEEP_SPLIT": "4"},
-                  {"SSM_SWEEP_BLOCKS_PER_CU": "1"}]
+SWEEP_VARIANTS = [{"sweep_split": 1}, {"sweep_split": 2}, {"sweep_split": 4},
+                  {"sweep_mode": 1}, {"sweep_mode": 2}, {"sweep_mode": 2, "sweep_split": 4},
+                  {"sweep_blocks_per_cu": 1}]
 
 
-@pytest.mark.parametrize("env", SWEEP_VARIANTS, ids=["-".join(f"{a[10:]}={b}" for a, b in v.items()) for v in SWEEP_VARIANTS])
-def test_sweep_f32_variants(env, monkeypatch):
+@pytest.mark.parametrize("env", SWEEP_VARIANTS, ids=["-".join(f"{a[6:]}={b}" for a, b in v.items()) for v in SWEEP_VARIANTS])
+def test_sweep_f32_variants(env, forced):
     """Every FP32 sweep form (waves per chunk, LDS table, LDS histograms,
     global table, one block per CU) against the FP64 oracle's stress, on a
     graph with rows of more than one segment (their neighbour sums) and on a
     low-degree one."""
     for name, val in env.items():
-        monkeypatch.setenv(name, val)
+        forced(name, val)
     for g, k in [(G.barabasi_albert(60000, 5, 3), 32), (G.rgg(3000, 5), 48)]:
         say("sweep variant", env, "case", g.name, "k", k)
         ref = oracle.preprocess(g.n, g.row_ptr, g.col_idx, k)
@@ -476,9 +476,9 @@ def test_kmeans_sp_bit_exact(g, k):
 
 
 @pytest.mark.parametrize("chunk", ["32", "40", "48", "56", "64"])
-def test_kmeans_sp_chunk_variants(chunk, monkeypatch):
+def test_kmeans_sp_chunk_variants(chunk, forced):
     """Every cluster-chunk width of the assignment kernel, k not a multiple of it."""
-    monkeypatch.setenv("SSM_KM_CHUNK", chunk)
+    forced("km_chunk", int(chunk))
     g = G.rgg(5000, 11, 8.0)
     dg = ssm.DeviceGraph.from_csr(g)
     piv, dist = ssm.select_pivots(dg, 77, 0, with_dist=True)
@@ -565,14 +565,14 @@ def test_build_terms_unaligned_table():
 @pytest.mark.parametrize("g,k", [(G.barabasi_albert(20000, 5, 3), 37), (G.rgg(3000, 5), 48), (G.grid(13, 17), 10),
                                  (G.holed_mesh(120, 130, 6, 4, 12, 5), 40)],
                          ids=["ba20000", "rgg3000", "grid13x17", "holedmesh120"])
-def test_sweep_order_bit_identical(g, k, monkeypatch):
+def test_sweep_order_bit_identical(g, k, forced):
     """The FP32 sweep renumbers the nodes (by region, then delta) for
     locality; every node's arithmetic is unchanged, so the coordinates equal
     those of sweeps in the caller's order bit for bit (rows above the heavy
     degree, padded ranks, a ragged last chunk)."""
     outs = []
-    for flag in ("2", "0"):  # reordered (forced: the library may skip graphs it would not gain on) / not
-        monkeypatch.setenv("SSM_SWEEP_PERM", flag)
+    for flag in (2, -1):  # reordered (forced: the library may skip graphs it would not gain on) / not
+        forced("sweep_perm", flag)
         dg, *_, terms = _device_pipeline(g, k)
         x0 = ssm.pivotmds_init(dg, terms, ssm.FP32)
         x = x0.clone()

@@ -187,3 +187,56 @@ def test_pool_admission_and_failures():
         assert pool.info(b)["state"] == ssm.POOL_FAILED and pool.info(b)["fail"] == ssm.E_INVAL
     assert pool.info(ok)["state"] == ssm.POOL_READY
     pool.close()
+
+
+def _oracle_changes(g, k, x0, count):
+    T = oracle.preprocess(g.n, g.row_ptr, g.col_idx, k)
+    out, x = [], x0
+    for _ in range(count):
+        xn, _ = oracle.majorize(g.row_ptr, g.col_idx, T.pivots, T.dist, T.wtab, T.den, x, 1)
+        out.append(oracle.rigid_change(x, xn))
+        x = xn
+    return np.array(out)
+
+
+STOP_MIX = [(G.rgg(3000, 3), 40), (G.grid(20, 30), 25), (G.tree_plus(800, 5), 30), (G.grid(12, 15), 18),
+            (G.barabasi_albert(3000, 4, 2), 60)]
+
+
+def test_pool_stop_test_per_graph():
+    """Algorithm 1's stop test per graph in a mixed batch: each graph stops
+    on a sweep where the oracle's change sequence (FP64, from the pool's own
+    FP64 start) is within rounding of tol, and takes no sweep after it; a
+    graph that keeps moving runs its sweep count; the same graph alone stops
+    on the same sweep with the same layout."""
+    tol, cap = 1e-4, 600
+    pool = ssm.Pool(1 << 30)
+    slots = [pool.add(g, k, 0, cap) for g, k in STOP_MIX]
+    for s in slots:
+        pool.set_tol(s, tol)
+    pool.prepare(slots, warm=1)
+    starts = [pool.export(s, ssm.POOL_X64) for s in slots]  # after the FP64 warm-up sweep
+    ran = np.full(len(slots), -1)
+    for _ in range(cap // 25 + 1):
+        pool.sweep(slots, 25)
+        r = pool.stopped(slots)
+        ran = np.where(ran < 0, r, ran)
+    for (g, k), s, x1, n_run in zip(STOP_MIX, slots, starts, ran):
+        say("case", g.name, "k", k, "stopped after", n_run)
+        ch = _oracle_changes(g, k, x1, cap - 1)  # FP64 continuation of the warm-up sweep
+        if n_run < 0:
+            assert pool.info(s)["done"] == cap
+            assert np.all(ch > 0.95 * tol)
+            continue
+        j = n_run - 2  # the change of FP32 sweep n_run - 1 (sweep 1 is the FP64 warm-up)
+        assert 0 <= j and ch[j] <= 1.05 * tol and np.all(ch[:j] > 0.95 * tol)
+        # alone: same stop, same layout
+        alone = ssm.Pool(1 << 28)
+        sa = alone.add(g, k, 0, cap)
+        alone.set_tol(sa, tol)
+        alone.prepare([sa], warm=1)
+        alone.sweep([sa], cap)
+        assert alone.stopped([sa])[0] == n_run
+        assert np.array_equal(alone.export(sa, ssm.POOL_X32), pool.export(s, ssm.POOL_X32))
+        alone.close()
+    pool.close()

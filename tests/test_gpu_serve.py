@@ -46,3 +46,36 @@ def test_serve_mixed_stream_matches_alone():
         alone.close()
     lat = rep.latencies_ms()
     assert (lat > 0).all()
+
+
+def test_serve_stream_with_stop_test_matches_alone():
+    """Requests with Algorithm 1's stop test: each retires after the sweep on
+    which its test fired, with the layout and sweep count the same graph
+    gets alone."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    specs = G.serving_requests(16, 23)
+    graphs = []
+    for sp in specs:
+        if sp["family"] == "grid":
+            sp = dict(sp, a=10 + sp["a"] % 30, b=10 + sp["b"] % 30)
+        else:
+            sp = dict(sp, n=200 + sp["n"] % 1800)
+        graphs.append(G.make_request_graph(sp))
+    arrivals = serve.poisson_arrivals(len(graphs), 400.0, 4)
+    reqs = [serve.Request(i, g, min(100, g.n // 10), float(a), sweeps=400, tol=1e-4)
+            for i, (g, a) in enumerate(zip(graphs, arrivals))]
+    rep = serve.serve(reqs, 24 << 20, quantum=9, keep_layouts=True)
+    assert all(r.status == "done" for r in reqs), [r.status for r in reqs]
+    assert any(r.sweeps_run < r.sweeps for r in reqs)
+    for r in reqs:
+        alone = ssm.Pool(1 << 28)
+        s = alone.add(r.graph, r.k, 0, r.sweeps)
+        alone.set_tol(s, r.tol)
+        alone.prepare([s], 1)
+        alone.sweep([s], r.sweeps)
+        got = alone.stopped([s])[0]
+        assert (got if got >= 0 else r.sweeps) == r.sweeps_run
+        assert alone.stress([s])[0] == r.stress
+        assert torch.equal(alone.layout(s, r.graph.n), r.layout)
+        alone.close()

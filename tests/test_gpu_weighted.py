@@ -151,15 +151,15 @@ def test_weighted_large_rows_and_errors():
 
 
 @pytest.mark.parametrize("order", ["nearfar", "band3", "plain"])
-def test_weighted_search_orders(order, monkeypatch):
+def test_weighted_search_orders(order, forced):
     """Both search orders (near-far bands, the default, also three lengths
     wide; plain label-correcting rounds) reach the oracle's Dijkstra
     distances and max/min pivots bit for bit, also on a graph whose searches
     run through many far passes."""
     if order == "plain":
-        monkeypatch.setenv("SSM_SSSP_NEARFAR", "0")
+        forced("sssp_nearfar", -1)
     if order == "band3":
-        monkeypatch.setenv("SSM_SSSP_BAND", "3")
+        forced("sssp_band", 3)
     for g, k, o in [(G.rgg(20000, 9, 8.0), 24, dict(seed=11)), (G.grid(40, 45), 12, dict(seed=12, lo=1, hi=4, integer=True)),
                     (G.holed_mesh(90, 80, 5, 3, 10, 6), 16, dict(seed=13, lo=0.01, hi=5.0))]:
         say("order", order, "case", g.name, k, o)

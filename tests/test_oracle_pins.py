@@ -788,3 +788,112 @@ def test_weighted_stress_by_definition_and_exact_scaling():
     # lengths, distances and layout x 4, weights / 16: every term is unchanged
     s4 = oracle.stress_w(g.row_ptr, g.col_idx, 4 * ln, W.pivots, 4 * W.dist, W.w / 16, 4 * xp)
     assert s4 == s
+
+
+# ------------------------------------------ Algorithm 1's stop test (reading 5)
+
+def _rot(th):
+    return np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+
+
+def _kabsch_change(x, y):
+    """min over proper rotations R and translations t of ||y - (R x + t)|| /
+    ||x - mean x||, by the SVD of the cross-covariance (Kabsch, with the
+    determinant correction that excludes reflections)."""
+    a, b = x - x.mean(0), y - y.mean(0)
+    U, _, Vt = np.linalg.svd(a.T @ b)
+    D = np.diag([1.0, np.sign(np.linalg.det(U @ Vt))])
+    R = U @ D @ Vt          # a @ R best matches b
+    return np.linalg.norm(b - a @ R) / np.linalg.norm(a)
+
+
+def test_rigid_change_is_zero_for_a_rigid_motion_and_not_for_a_mirror():
+    rng = np.random.default_rng(5)
+    x = rng.normal(size=(300, 2)) * 7
+    for th in (0.0, 0.4, 2.5, -1.2):
+        y = x @ _rot(th).T + np.array([3.0, -11.0])
+        assert oracle.rigid_change(x, y) < 1e-14
+    # a reflection is not a proper rigid motion: an anisotropic cloud keeps
+    # a large change after the best rotation
+    x[:, 0] *= 3
+    y = x * np.array([-1.0, 1.0])
+    assert oracle.rigid_change(x, y) > 0.5
+
+
+def test_rigid_change_matches_the_kabsch_solution():
+    rng = np.random.default_rng(6)
+    for trial in range(20):
+        n = int(rng.integers(3, 400))
+        x = rng.normal(size=(n, 2)) * rng.uniform(0.1, 100)
+        y = x @ _rot(rng.uniform(-3, 3)).T + rng.normal(size=2) * 10 + rng.normal(size=(n, 2)) * rng.uniform(1e-6, 1)
+        want = _kabsch_change(x, y)
+        assert abs(oracle.rigid_change(x, y) - want) <= 1e-9 * want
+        # unchanged by scaling both layouts by a power of two (exact)
+        assert oracle.rigid_change(4 * x, 4 * y) == oracle.rigid_change(x, y)
+    # zero spread: never counts as converged
+    assert oracle.rigid_change(np.ones((5, 2)), np.ones((5, 2))) == np.inf
+
+
+def _stepwise(g, T, x, iters, centred=False):
+    """Per-sweep (raw change, rigid change) by running one sweep at a time;
+    with centred=True also the change after removing the translation only."""
+    out = []
+    for _ in range(iters):
+        xn, _ = oracle.majorize(g.row_ptr, g.col_idx, T.pivots, T.dist, T.wtab, T.den, x, 1)
+        a, b = x - x.mean(0), xn - xn.mean(0)
+        row = (np.linalg.norm(xn - x) / np.linalg.norm(x), _kabsch_change(x, xn))
+        out.append(row + (np.linalg.norm(b - a) / np.linalg.norm(a),) if centred else row)
+        x = xn
+    return out
+
+
+@pytest.mark.parametrize("g", [G.grid(12, 15), G.cycle(40), G.tree_plus(150, 9)])
+def test_stop_agrees_with_the_raw_rule_at_k_equal_n(g):
+    # k = n: the weights are symmetric and the PivotMDS start is centred, so
+    # there is no steady rigid drift: the change after the best rigid motion
+    # stays within a few per cent of the raw change (until both reach the
+    # rounding floor), so the two readings stop within one sweep of each
+    # other
+    T = oracle.preprocess(g.n, g.row_ptr, g.col_idx, g.n)
+    x0 = oracle.initial_layout(g.row_ptr, g.col_idx, T)
+    assert np.abs(x0.mean(0)).max() < 1e-12 * np.abs(x0).max()
+    tol = 1e-4
+    steps = _stepwise(g, T, x0, 300, centred=True)
+    for raw, rig, trans in steps:
+        if raw > 1e-8:
+            # no rotation (identity) is one candidate motion
+            assert rig <= trans * (1 + 1e-9)
+            assert rig >= 0.97 * raw
+    first_raw = next(q + 1 for q, (raw, _, _) in enumerate(steps) if raw <= tol)
+    first_rigid = next(q + 1 for q, (_, rig, _) in enumerate(steps) if rig <= tol)
+    assert first_raw - 1 <= first_rigid <= first_raw
+    _, done = oracle.majorize(g.row_ptr, g.col_idx, T.pivots, T.dist, T.wtab, T.den, x0, 300, tol=tol)
+    assert done == first_rigid
+
+
+def test_stop_fires_for_k_below_n_where_the_raw_rule_does_not():
+    g = G.rgg(3000, 3)
+    k = 40
+    T = oracle.preprocess(g.n, g.row_ptr, g.col_idx, k)
+    x0 = oracle.initial_layout(g.row_ptr, g.col_idx, T)
+    tol = 1e-4
+    steps = _stepwise(g, T, x0, 400)
+    assert min(raw for raw, _ in steps[50:]) > 2 * tol   # the steady drift keeps the raw change up
+    first = next(q + 1 for q, (_, rig) in enumerate(steps) if rig <= tol * (1 - 1e-6))
+    assert all(rig > tol * (1 + 1e-6) for _, rig in steps[:first - 1])
+    x, done = oracle.majorize(g.row_ptr, g.col_idx, T.pivots, T.dist, T.wtab, T.den, x0, 400, tol=tol)
+    assert done == first
+    xr, _ = oracle.majorize(g.row_ptr, g.col_idx, T.pivots, T.dist, T.wtab, T.den, x0, first)
+    assert np.array_equal(x, xr)
+
+
+def test_stop_is_unchanged_by_a_rigid_motion_of_the_start():
+    g = G.grid(20, 30)
+    k = 25
+    T = oracle.preprocess(g.n, g.row_ptr, g.col_idx, k)
+    x0 = oracle.initial_layout(g.row_ptr, g.col_idx, T)
+    R, t = _rot(0.9), np.array([250.0, -40.0])
+    xa, da = oracle.majorize(g.row_ptr, g.col_idx, T.pivots, T.dist, T.wtab, T.den, x0, 400, tol=1e-4)
+    xb, db = oracle.majorize(g.row_ptr, g.col_idx, T.pivots, T.dist, T.wtab, T.den, x0 @ R.T + t, 400, tol=1e-4)
+    assert da == db and da < 400
+    assert np.abs(xb - (xa @ R.T + t)).max() < 1e-9 * np.abs(xa).max()

@@ -256,6 +256,19 @@ ssm_status ssm_stress_w(const ssm_csr* g, const double* len, const ssm_wterms* t
 ssm_status ssm_procrustes(int32_t n, ssm_prec px, const void* x, ssm_prec py, const void* y, double* out_host,
                           hipStream_t stream);
 
+/* ssm_procrustes for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and the same result bit for bit, with the partial sums
+ * in a static device array of the library (6 x 1024 + 8 doubles, 49 KiB per
+ * device, held until the process ends) instead of an allocated workspace.
+ * It calls no allocating routine.  Every partial is written before it is
+ * read, so nothing left by an earlier call is used.  All calls on one device
+ * share that array: calls that overlap on one GPU (on different streams or
+ * threads) race and must be serialized by the caller.  n in [2, 2^30]
+ * (SSM_E_RANGE above); other errors as ssm_procrustes.  Synchronizes. */
+ssm_status ssm_procrustes_noalloc(int32_t n, ssm_prec px, const void* x, ssm_prec py, const void* y,
+                                  double* out_host, hipStream_t stream);
+
 /* ---- Layout pool: many small graphs laid out together ----------------
  *
  * The same method (Algorithm 1: max/min sp pivots, their BFS, regions and

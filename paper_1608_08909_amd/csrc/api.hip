@@ -375,4 +375,14 @@ ssm_status ssm_procrustes(int32_t n, ssm_prec px, const void* x, ssm_prec py, co
     return procrustes(n, px, x, py, y, out_host, stream);
 }
 
+ssm_status ssm_procrustes_noalloc(int32_t n, ssm_prec px, const void* x, ssm_prec py, const void* y,
+                                  double* out_host, hipStream_t stream) {
+    if (n < 2) return fail(SSM_E_INVAL, "need n >= 2");
+    if (n > (1 << 30)) return fail(SSM_E_RANGE, "n above 2^30");
+    if (!x || !y || !out_host) return fail(SSM_E_INVAL, "NULL layout or output");
+    if ((px != SSM_FP64 && px != SSM_FP32) || (py != SSM_FP64 && py != SSM_FP32))
+        return fail(SSM_E_INVAL, "unknown precision");
+    return procrustes_noalloc(n, px, x, py, y, out_host, stream);
+}
+
 }  // extern "C"

@@ -8,10 +8,21 @@
 //     statistic = 1 - (||A||_F^2 + 2 det A) / (tr(X^T X) tr(Y^T Y)),
 // in [0, 1], 0 for a perfect match.  Two passes in FP64: the means, then the
 // centred second moments, each as per-block partials summed in a fixed order.
+#include <mutex>
+#include <unordered_map>
+
 #include "ssm_internal.h"
 #include "wave.h"
 
 namespace ssm {
+
+constexpr int kQMaxBlocks = 1024;                          // blocks of one pass (grid-stride beyond)
+constexpr size_t kQScratch = 6 * (size_t)kQMaxBlocks + 8;  // doubles: partials, means, statistic, flag
+
+// Scratch of the allocation-free entry point: one copy per device, held
+// until the process ends.  Host code never passes the symbol itself to a
+// kernel; it uses the device address looked up once per device below.
+static __device__ __align__(256) double scratch[kQScratch];
 
 template <typename T2>
 __device__ __forceinline__ double2 q_load(const void* p, int i) {
@@ -89,12 +100,11 @@ __global__ void k_procrustes_final(int n, int nb, const double* __restrict__ par
     }
 }
 
-ssm_status procrustes(int32_t n, int32_t px, const void* x, int32_t py, const void* y, double* out_host,
-                      hipStream_t s) {
-    const int nb = std::max(1, std::min(div_up(n, kQBlock), 1024));
-    double* ws = nullptr;
-    ssm_status st = salloc((void**)&ws, sizeof(double) * (6 * (size_t)nb + 8));
-    if (st != SSM_OK) return st;
+// The two passes on workspace ws (at least 6 nb + 8 doubles, nb the block
+// count below); every partial is written before it is read.
+static ssm_status procrustes_ws(int32_t n, int32_t px, const void* x, int32_t py, const void* y, double* out_host,
+                                hipStream_t s, double* ws) {
+    const int nb = std::max(1, std::min(div_up(n, kQBlock), kQMaxBlocks));
     double* part = ws;
     double* res = ws + 6 * (size_t)nb;  // means [4], then statistic and flag
     hipLaunchKernelGGL(k_procrustes<0>, dim3(nb), dim3(kQBlock), 0, s, n, px, x, py, y, res, part);
@@ -106,11 +116,49 @@ ssm_status procrustes(int32_t n, int32_t px, const void* x, int32_t py, const vo
     if (e == hipSuccess) e = hipMemcpyAsync(h, res + 4, sizeof h, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipStreamSynchronize(s);
-    sfree(ws);
     if (e != hipSuccess) return hip_fail(e, "Procrustes statistic");
     if (h[1] != 0.0) return fail(SSM_E_INVAL, "a layout has all nodes at one point");
     *out_host = h[0];
     return SSM_OK;
+}
+
+ssm_status procrustes(int32_t n, int32_t px, const void* x, int32_t py, const void* y, double* out_host,
+                      hipStream_t s) {
+    double* ws = nullptr;
+    ssm_status st = salloc((void**)&ws, sizeof(double) * kQScratch);
+    if (st != SSM_OK) return st;
+    st = procrustes_ws(n, px, x, py, y, out_host, s, ws);  // synchronizes s before returning
+    sfree(ws);
+    return st;
+}
+
+// Device address of `scratch` on the current device, looked up on the
+// first call on that device.
+static ssm_status scratch_address(double** out) {
+    static std::mutex mu;
+    static std::unordered_map<int, double*> addr;
+    int dev = 0;
+    SSM_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(dev);
+    if (it != addr.end()) {
+        *out = it->second;
+        return SSM_OK;
+    }
+    double* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "scratch address");
+    addr[dev] = p;
+    *out = p;
+    return SSM_OK;
+}
+
+ssm_status procrustes_noalloc(int32_t n, int32_t px, const void* x, int32_t py, const void* y, double* out_host,
+                              hipStream_t s) {
+    double* ws = nullptr;
+    ssm_status st = scratch_address(&ws);
+    if (st != SSM_OK) return st;
+    return procrustes_ws(n, px, x, py, y, out_host, s, ws);
 }
 
 }  // namespace ssm

@@ -211,6 +211,8 @@ ssm_status sssp_rows(const ssm_csr* g, const double* len, int32_t k, const int32
 // ---- quality measures (quality.hip)
 ssm_status procrustes(int32_t n, int32_t px, const void* x, int32_t py, const void* y, double* out_host,
                       hipStream_t s);
+ssm_status procrustes_noalloc(int32_t n, int32_t px, const void* x, int32_t py, const void* y, double* out_host,
+                              hipStream_t s);
 
 // Deterministic FP64 sum of `count` partials on the device into out (device).
 void launch_sum_partials(const double* partials, int count, double* out, hipStream_t s);

@@ -67,7 +67,7 @@ EXPORTS = [
     "ssm_pool_stress", "ssm_pool_layout", "ssm_pool_export", "ssm_pool_info", "ssm_pool_remove", "ssm_procrustes",
     "ssm_select_pivots_w", "ssm_sssp_pivots", "ssm_build_terms_w", "ssm_wterms_free", "ssm_wterms_export",
     "ssm_pivotmds_init_w", "ssm_majorize_w", "ssm_majorize_mixed_w", "ssm_stress_w", "ssm_release_cache",
-    "ssm_set_variant", "ssm_pool_set_tol", "ssm_pool_stopped",
+    "ssm_set_variant", "ssm_pool_set_tol", "ssm_pool_stopped", "ssm_procrustes_noalloc",
 ]
 
 
@@ -113,6 +113,7 @@ def load(path: str | None = None):
             "ssm_pool_info": (S, [V, I, V]),
             "ssm_pool_remove": (S, [V, I]),
             "ssm_procrustes": (S, [I, I, V, I, V, V, V]),
+            "ssm_procrustes_noalloc": (S, [I, I, V, I, V, V, V]),
             "ssm_select_pivots_w": (S, [P, V, I, I, V, V, V]),
             "ssm_sssp_pivots": (S, [P, V, I, V, V, V]),
             "ssm_build_terms_w": (S, [P, V, I, V, V, ctypes.POINTER(V), V]),

@@ -5,7 +5,7 @@ max/min pivot selection, BFS from every pivot and regions, term set, PivotMDS
 start layout, T Jacobi sweeps of Eq. 5, final stress.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--workload rgg|grid|ba|mesh]
-    python bench.py --workload serve [--requests 4096] [--rate R] [--pool-gib G]
+    python bench.py --workload serve [--requests 4096] [--loads 0.5 0.8 0.95] [--pool-gib G]
 
 The serve workload runs a stream of layout requests through the layout pool
 (continuous batching); its step is the whole stream.
@@ -160,7 +160,8 @@ def cpu_baseline(g, k, iters, sweeps_one=1, sweeps_all=3, pmds_work=4e9):
                            "sweep_node_updates_per_s": g.n / rates[1]}}
 
 
-SERVE_DESC = ("serving stream: {count} layout requests with Poisson arrivals at {rate:g}/s; each graph drawn "
+SERVE_DESC = ("serving stream: {count} layout requests, all queued at once (closed-loop capacity), then with "
+              "Poisson arrivals at fractions of that capacity; each graph drawn "
               "uniformly from grid a x b (a, b in [10,150]), random geometric graph (n in [200,20000], mean "
               "degree 6-10, largest component) and random tree + 5% extra edges (n in [200,20000]); "
               "k=min(100, n/10) maxmin pivots; {sweeps} sweeps each (the first FP64, the rest FP32); "
@@ -182,8 +183,12 @@ def _request_graphs(specs):
 
 
 def run_serve(args):
-    """The serving stream through the layout pool: one step = the whole
-    stream (every request from arrival to its finished layout)."""
+    """The serving stream through the layout pool.  First the closed-loop
+    capacity: the whole stream queued at once (every request arrives at time
+    0), whose layouts/s is the line's value.  Then the same stream with
+    Poisson arrivals at `--loads` times that capacity (latency measured at a
+    load the server sustains), and once at 0.8 x capacity with Algorithm 1's
+    stop test (tolerance `--tol`) to count the sweeps it saves."""
     from paper_1608_08909_amd import graphs as G
 
     specs = G.serving_requests(args.requests, args.seed)
@@ -200,23 +205,45 @@ def run_serve(args):
     torch.cuda.set_device(0)
     pool_bytes = int(args.pool_gib * (1 << 30))
 
-    def requests(gs, seed):
-        arr = serve.poisson_arrivals(len(gs), args.rate, seed)
-        return [serve.Request(i, g, min(100, g.n // 10), float(a), sweeps=args.sweeps)
+    def requests(gs, rate, seed, tol=0.0):
+        arr = serve.poisson_arrivals(len(gs), rate, seed) if rate > 0 else np.zeros(len(gs))
+        return [serve.Request(i, g, min(100, g.n // 10), float(a), sweeps=args.sweeps, tol=tol)
                 for i, (g, a) in enumerate(zip(gs, arr))]
 
+    def run(rate, tol=0.0, seed=args.seed):
+        rep = serve.serve(requests(graphs, rate, seed, tol), pool_bytes, args.quantum, max_prepare=args.max_prepare,
+                          first_prepare=args.first_prepare, prep_quantum=args.prep_quantum)
+        done = rep.completed()
+        lat = rep.latencies_ms()
+        sweeps = np.array([r.sweeps_run for r in done])
+        return rep, done, {
+            "rate_per_s": rate, "tol": tol, "completed": len(done), "failed": len(rep.requests) - len(done),
+            "wall_s": rep.wall_s, "layouts_per_s": len(done) / rep.wall_s,
+            "node_updates_per_s": float(sum(r.graph.n * r.sweeps_run for r in done)) / rep.wall_s,
+            "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99), "max": float(lat.max())},
+            "sweeps_per_layout": {"mean": float(sweeps.mean()), "min": int(sweeps.min()), "max": int(sweeps.max())},
+            "rounds": rep.rounds, "prepare_batches": rep.prepares, "peak_active_graphs": rep.peak_active,
+            "peak_pool_bytes": rep.peak_bytes, "host_phase_s": rep.host_s}
+
     for _ in range(args.warmup):
-        serve.serve(requests(warm_graphs, args.seed + 2), pool_bytes, args.quantum, max_prepare=args.max_prepare,
+        serve.serve(requests(warm_graphs, 0.0, args.seed + 2), pool_bytes, args.quantum, max_prepare=args.max_prepare,
                     first_prepare=args.first_prepare, prep_quantum=args.prep_quantum)
     torch.cuda.synchronize()
-    rep = serve.serve(requests(graphs, args.seed), pool_bytes, args.quantum, max_prepare=args.max_prepare,
-                      first_prepare=args.first_prepare, prep_quantum=args.prep_quantum)
-    done = rep.completed()
-    lat = rep.latencies_ms()
-    node_updates = sum(r.graph.n * r.sweeps for r in done)
+    rep, done, closed = run(0.0)
+    capacity = closed["layouts_per_s"]
+    loads = []
+    for frac in args.loads:
+        _, _, row = run(frac * capacity, seed=args.seed + 10)
+        row["load"] = frac
+        loads.append(row)
+    # Algorithm 1's stop test per request, at 0.8 x capacity
+    _, done_tol, early = run(0.8 * capacity, tol=args.tol, seed=args.seed + 10)
+    early["load"] = 0.8
+    early["sweeps_saved_fraction"] = 1.0 - early["sweeps_per_layout"]["mean"] / args.sweeps
 
     # equal final stress: the plain per-graph FP64 path on the same GPU, on a
-    # sample spread over the stream (also timed: the plain form's layouts/s)
+    # sample spread over the stream (also timed: the plain form's layouts/s);
+    # with the stop test, the plain FP64 path with the same stop test
     sample = done[:: max(1, len(done) // 16)][:16]
     rels, t_plain = [], 0.0
     for r in sample:
@@ -227,6 +254,18 @@ def run_serve(args):
         s64 = ssm.stress(dg, terms, x)
         t_plain += time.perf_counter() - t0
         rels.append(abs(r.stress - s64) / s64)
+    by_id = {r.rid: r for r in done_tol}
+    rels_tol = []
+    for r in sample:
+        rt = by_id.get(r.rid)
+        if rt is None:
+            continue
+        dg = ssm.DeviceGraph.from_csr(rt.graph)
+        x, terms, *_ = ssm.layout(dg, rt.k, 1, ssm.FP64)
+        ssm.majorize(dg, terms, x, rt.sweeps - 1, tol=args.tol)
+        s64 = ssm.stress(dg, terms, x)
+        rels_tol.append(abs(rt.stress - s64) / s64)
+    early["final_stress_rel_diff_vs_plain_fp64_same_stop"] = {"max": float(max(rels_tol)), "sample": len(rels_tol)}
 
     # roofline of the pooled FP32 sweep on a batch of the stream's graphs
     batch = graphs[:256]
@@ -246,42 +285,36 @@ def run_serve(args):
     torch.cuda.synchronize()
     launch_us = e0.elapsed_time(e1) * 1e3 / reps
     nbytes = 0
-    for g, s in pairs:
-        kpad = (pool.info(s)["k"] + 7) // 8 * 8
-        nbytes += g.n * kpad * 2 + g.col_idx.size * 4 + g.n * (4 + 8 + 8 + 4)
+    for g, s in pairs:  # the graph's own k (the padding ranks are not counted)
+        nbytes += g.n * pool.info(s)["k"] * 2 + g.col_idx.size * 4 + g.n * (4 + 8 + 8 + 4)
     batch_nodes = sum(g.n for g, _ in pairs)
     pool.close()
     achieved = nbytes / (launch_us * 1e-6) / 1e9
 
     out = {
         "metric": "node-updates/sec & layouts/sec (p50/p99) at equal final stress vs plain, 1 GPU",
-        "value": len(done) / rep.wall_s,
+        "value": capacity,
         "unit": "layouts/s",
         "n_gpus": 1,
         "steps": 1,
         "warmup": args.warmup,
-        "ms_per_step": rep.wall_s * 1e3,
+        "ms_per_step": closed["wall_s"] * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": SERVE_DESC.format(count=args.requests, rate=args.rate, sweeps=args.sweeps,
-                                                 pool_gib=args.pool_gib, quantum=args.quantum),
-                   "requests": args.requests, "seed": args.seed, "rate_per_s": args.rate,
-                   "pool_bytes": pool_bytes, "quantum": args.quantum, "max_prepare": args.max_prepare,
-                   "first_prepare": args.first_prepare, "prep_quantum": args.prep_quantum,
-                   "sweeps": args.sweeps},
-        "completed": len(done),
-        "failed": len(rep.requests) - len(done),
-        "layouts_per_s": len(done) / rep.wall_s,
-        "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99), "max": float(lat.max())},
-        "node_updates_per_s": node_updates / rep.wall_s,
-        "rounds": rep.rounds,
-        "prepare_batches": rep.prepares,
-        "peak_active_graphs": rep.peak_active,
-        "peak_pool_bytes": rep.peak_bytes,
-        "host_phase_s": rep.host_s,
+        "config": {"workload": SERVE_DESC.format(count=args.requests, sweeps=args.sweeps, pool_gib=args.pool_gib,
+                                                 quantum=args.quantum),
+                   "requests": args.requests, "seed": args.seed, "pool_bytes": pool_bytes, "quantum": args.quantum,
+                   "max_prepare": args.max_prepare, "first_prepare": args.first_prepare,
+                   "prep_quantum": args.prep_quantum, "sweeps": args.sweeps},
+        "closed_loop": closed,
+        "layouts_per_s": capacity,
+        "latency_ms": closed["latency_ms"],
+        "node_updates_per_s": closed["node_updates_per_s"],
+        "poisson_loads": loads,
+        "early_exit": early,
         "final_stress_rel_diff_vs_plain_fp64": {"max": float(max(rels)), "sample": len(rels)},
         "plain_fp64_layouts_per_s_sample": len(sample) / t_plain,
         "host_graph_generation_s": t_gen,
@@ -298,9 +331,12 @@ def run_serve(args):
             oracle.layout(r.graph.n, r.graph.row_ptr, r.graph.col_idx, r.k, r.sweeps)
         dt = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": len(cs) / dt, "unit": "layouts/s", "cores": 1, "kind": "oracle",
-                               "sample": f"{len(cs)} median-size requests of the stream (n = "
+                               "sample": f"{cpu_model()}: {len(cs)} median-size requests of the stream (n = "
                                          f"{[r.graph.n for r in cs]}), full layouts with {args.sweeps} sweeps, "
-                                         f"{dt:.1f} s on one core"}
+                                         f"{dt:.1f} s on one core (the oracle lays out one request per call; "
+                                         f"requests are independent, so {usable_cores()} cores would serve about "
+                                         f"{usable_cores() * len(cs) / dt:.2f} layouts/s)",
+                               "cpu_model": cpu_model()}
     print(json.dumps(out), flush=True)
 
 
@@ -441,7 +477,9 @@ def main():
     ap.add_argument("--workload", default="mesh", choices=sorted(WORKLOADS) + ["serve", "quality", "weighted"])
     ap.add_argument("--requests", type=int, default=4096, help="serve: requests in the stream")
     ap.add_argument("--warm-requests", type=int, default=64, help="serve: requests of each warm-up stream")
-    ap.add_argument("--rate", type=float, default=100000.0, help="serve: Poisson arrival rate (requests/s)")
+    ap.add_argument("--loads", type=float, nargs="*", default=[0.5, 0.8, 0.95],
+                    help="serve: Poisson arrival rates as fractions of the measured closed-loop capacity")
+    ap.add_argument("--tol", type=float, default=1e-4, help="serve: stop-test tolerance of the early-exit stream")
     ap.add_argument("--pool-gib", type=float, default=32.0, help="serve: layout pool arena (GiB)")
     ap.add_argument("--quantum", type=int, default=25, help="serve: sweeps per scheduling round")
     ap.add_argument("--max-prepare", type=int, default=1024, help="serve: largest preparation batch")

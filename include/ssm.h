@@ -385,14 +385,20 @@ void ssm_release_cache(void);
  * own choice; name NULL clears every override.  The overrides are
  * process-wide; set them while no other thread runs a library call.
  * Names and values:
- *   select_mode 1|2|3 (one workgroup, cooperative grid, per-pivot),
+ *   select_mode 1|2|3|4 (one workgroup, cooperative grid over CSR rows,
+ *   per-pivot launches, cooperative grid over padded rows),
  *   select_blocks N, select_threads 256|512, select_ell 2 (plain CSR),
  *   select_m8 2 (no LDS byte copy), select_rowq 2, select_pre 1|3,
  *   select_wave -1|2 (block levels only, two passes per wave level),
- *   bfs_ell 2, bfs_rowq 2, bfs_lanes 2..64, msbfs 1, msbfs_budget N,
+ *   bfs_ell 2|3|4 (CSR rows; padded rows with the distance row as visited
+ *   set, with or without a read before the swap), bfs_rowq 2,
+ *   bfs_lanes 2..64, msbfs 1, msbfs_budget N,
  *   region_mode 1|2, km_chunk 32|40|48|56|64,
  *   sweep_mode 1|2 (LDS histograms, global table), sweep_split 1|2|4,
  *   sweep_blocks_per_cu N, sweep_waves 4|16 (waves per block),
+ *   sweep_tune -1 (no timing of launch shapes: the rule shape; the FP32
+ *   sweep otherwise times its shapes on the first loop of at least 24
+ *   sweeps per graph shape and keeps the fastest),
  *   sweep_perm -1|2 (caller's node order, always reorder),
  *   sssp_nearfar -1 (plain rounds), sssp_band N.
  * SSM_E_INVAL for an unknown name. */

@@ -757,6 +757,75 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_ell(int n, const int* __restr
                           ecc_max);
 }
 
+// Block b: BFS from pivots[b] into dist[b][*] (pre-set to -1) for graphs
+// whose visited bits do not fit in LDS: the padded adjacency and frontier
+// queues of bfs_ell_body, the visited set being the distance row itself.  A
+// neighbour is claimed by a compare-and-swap of its distance from -1 to the
+// level (workgroup scope: the row belongs to this block), issued for all of
+// a lane's neighbours before any result is used; with PRE, the distances are
+// read first and only the unvisited ones are swapped.  gq holds 3 n ints per
+// block.  reached[b] = nodes found; *ecc_max = largest eccentricity seen.
+template <int W, bool PRE>
+__global__ __launch_bounds__(kBfsBlock) void k_bfs_ell_g(int n, const int* __restrict__ rp,
+                                                         const int* __restrict__ ci, const int* __restrict__ ell,
+                                                         const int* __restrict__ pivots, int* dist, int* gq,
+                                                         int* reached, int* ecc_max) {
+    __shared__ __align__(16) int pool[2 * kLdsQ + kHeavyCap];
+    __shared__ int2 s_slot[3];
+    const int b = blockIdx.x;
+    int* D = dist + (size_t)b * n;
+    int* qa = pool;
+    int* qb = qa + kLdsQ;
+    int* lheavy = qb + kLdsQ;
+    int* ga = gq + (size_t)b * 3 * n;
+    int* gb = ga + n;
+    int* gh = gb + n;
+    if (threadIdx.x == 0) {
+        D[pivots[b]] = 0;
+        qa[0] = pivots[b];
+        s_slot[0] = make_int2(0, 0);
+    }
+    __syncthreads();
+    Frontier f{qa, ga, qb, gb, nullptr, lheavy, gh};
+    int level = 0, total = 1, len = 1;
+    for (; len > 0; ++level) {
+        level_begin(s_slot, level, f);
+        const int dv = level + 1;
+        len = ell_level_auto<W>(n, rp, ci, ell, len, f, [&](const auto& u, auto& ok) {
+            constexpr int N = sizeof(u) / sizeof(u[0]);
+            int old[N];
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                ok[j] = (unsigned)u[j] < (unsigned)n;  // padding, continuation mark
+                old[j] = PRE && ok[j] ? wg_load(&D[u[j]]) : -1;
+            }
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                ok[j] = ok[j] && old[j] < 0;
+                if (ok[j]) {
+                    int expected = -1;
+                    __hip_atomic_compare_exchange_strong(&D[u[j]], &expected, dv, __ATOMIC_RELAXED,
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    old[j] = expected;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < N; ++j) ok[j] = ok[j] && old[j] == -1;
+        });
+        total += len;
+        const int* tl = f.lcur;
+        f.lcur = f.lnxt;
+        f.lnxt = (int*)tl;
+        const int* tg = f.gcur;
+        f.gcur = f.gnxt;
+        f.gnxt = (int*)tg;
+    }
+    if (threadIdx.x == 0) {
+        reached[b] = total;
+        atomicMax(ecc_max, level - 1);
+    }
+}
+
 // LDS pool sizes of k_bfs_ell (several workgroups share a CU when small);
 // 0 = the visited bits do not fit.
 constexpr int kPoolS = 32768, kPoolM = 65536, kPoolL = 155648;
@@ -842,7 +911,7 @@ ssm_status mssp(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dis
     // LDS-resident BFS per pivot when the visited bits fit in LDS (tuning
     // override SSM_BFS_ELL=2 keeps the global-memory form).
     const int pool = bfs_ell_pool(n);
-    if (pool > 0 && variant("bfs_ell") != 2) {
+    if (pool > 0 && variant("bfs_ell") != 2 && variant("bfs_ell") != 3 && variant("bfs_ell") != 4) {
         const int W = ell_width(g);
         const long long qcap = 1LL << 31;  // overflow ints (8 GiB)
         const int batch = (int)std::max<long long>(1, std::min<long long>(k, qcap / (3LL * n)));
@@ -861,6 +930,51 @@ ssm_status mssp(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dis
                 const int nb = std::min(batch, k - b0);
                 e = launch_bfs_ell(W, pool, nb, s, n, g->row_ptr, g->col_idx, ell, pivots + b0,
                                    dist + (size_t)b0 * n, gq, aux + b0, aux + k);
+            }
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(host.data(), aux, sizeof(int) * ((size_t)k + 1), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+        }
+        (void)hipStreamSynchronize(s);  // idle before the scratch is reused
+        if (ell) sfree(ell);
+        if (gq) sfree(gq);
+        if (aux) sfree(aux);
+        if (st != SSM_OK) return st;
+        if (e != hipSuccess) return hip_fail(e, "multi-source BFS");
+        for (int t = 0; t < k; ++t)
+            if (host[t] != n) return fail(SSM_E_DISCONNECTED, "graph is not connected (a BFS missed nodes)");
+        *dmax_out_host = host[k];
+        return SSM_OK;
+    }
+    // Too large for LDS visited bits: variant bfs_ell = 3 (or 4: without the
+    // read before the swap) takes the same padded-adjacency BFS with the
+    // distance row as visited set; the default is the CSR form below (faster
+    // on a 3.25M-node mesh: 57 against 84 ms for 100 rows without the read).
+    if (variant("bfs_ell") == 3 || variant("bfs_ell") == 4) {
+        const int W = ell_width(g);
+        const long long qcap = 1LL << 31;  // overflow ints (8 GiB)
+        const int batch = (int)std::max<long long>(1, std::min<long long>(k, qcap / (3LL * n)));
+        int* ell = nullptr;
+        int* gq = nullptr;
+        int* aux = nullptr;  // reached[k], ecc
+        ssm_status st = salloc((void**)&ell, sizeof(int) * (size_t)n * W);
+        if (st == SSM_OK) st = salloc((void**)&gq, sizeof(int) * 3 * (size_t)n * batch);
+        if (st == SSM_OK) st = salloc((void**)&aux, sizeof(int) * ((size_t)k + 1));
+        hipError_t e = hipSuccess;
+        std::vector<int> host((size_t)k + 1);
+        if (st == SSM_OK) {
+            e = hipMemsetAsync(dist, 0xff, sizeof(int) * (size_t)k * n, s);
+            if (e == hipSuccess) e = hipMemsetAsync(aux, 0, sizeof(int) * ((size_t)k + 1), s);
+            if (e == hipSuccess) e = ell_build(g, W, ell, s);
+            for (int b0 = 0; b0 < k && e == hipSuccess; b0 += batch) {
+                const int nb = std::min(batch, k - b0);
+                const bool pre = variant("bfs_ell") != 4;
+                auto kern = W == 8 ? (pre ? k_bfs_ell_g<8, true> : k_bfs_ell_g<8, false>)
+                          : W == 16 ? (pre ? k_bfs_ell_g<16, true> : k_bfs_ell_g<16, false>)
+                                    : (pre ? k_bfs_ell_g<32, true> : k_bfs_ell_g<32, false>);
+                hipLaunchKernelGGL(kern, dim3(nb), dim3(kBfsBlock), 0, s, n, g->row_ptr, g->col_idx, ell,
+                                   pivots + b0, dist + (size_t)b0 * n, gq, aux + b0, aux + k);
+                e = hipGetLastError();
             }
             if (e == hipSuccess)
                 e = hipMemcpyAsync(host.data(), aux, sizeof(int) * ((size_t)k + 1), hipMemcpyDeviceToHost, s);
@@ -1109,6 +1223,179 @@ __global__ __launch_bounds__(kSelBlock) void k_select_all(int n, const int* __re
     }
 }
 
+// Key of node i with value m for the argmax: the largest m wins, then the
+// lowest id.
+__device__ __forceinline__ unsigned long long argmax_key(int m, int i) {
+    return ((unsigned long long)(unsigned)m << 32) | (unsigned long long)(0xffffffffu - (unsigned)i);
+}
+
+__device__ __forceinline__ unsigned long long key_max(unsigned long long a, unsigned long long b) {
+    return a > b ? a : b;
+}
+
+// Appends the u[j] with ok[j] (j < 4) to a global frontier: one counter
+// reservation per wave.  Call with every lane of the wave active.
+__device__ __forceinline__ void append4_global(const int (&u)[4], const bool (&ok)[4], int* tail, int* nxt) {
+    uint64_t mk[4];
+    int tot = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        mk[j] = __ballot(ok[j]);
+        tot += __popcll(mk[j]);
+    }
+    if (tot == 0) return;
+    int at = 0;
+    if (lane_id() == 0) at = atomicAdd(tail, tot);
+    at = __builtin_amdgcn_readfirstlane(at);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (ok[j]) nxt[at + mask_rank(mk[j])] = u[j];
+        at += __popcll(mk[j]);
+    }
+}
+
+// Frontiers up to this size lower m with the atomic alone; wider ones read m
+// first and skip the atomic where m is already at most the new distance.
+constexpr int kSelPrecheck = 16384;
+
+// Pivots t0 .. t1-1 of max/min sampling in one cooperative launch, over the
+// padded adjacency: each group of W/4 lanes takes one frontier node and four
+// of its neighbours per lane (a longer row's CSR tail is walked by the same
+// lanes).  The pruned BFS and the argmax are those of k_select_all: a
+// relaxation lowers m with one atomicMin and the node joins the next frontier
+// iff the atomic lowered it.  The argmax reads m with 16-byte loads, four in
+// flight per thread (lowest id on ties through the key).  status[1] = the
+// largest m after pivot 0's BFS (its eccentricity).
+template <int W>
+__global__ __launch_bounds__(kSelBlock) void k_select_grid(int n, const int* __restrict__ rp,
+                                                           const int* __restrict__ ci, const int* __restrict__ ell,
+                                                           int t0, int t1, int k, int first, int* pivots, int* m,
+                                                           int* qa, int* qb, int* ctl, unsigned long long* keys,
+                                                           int* status) {
+    constexpr int VW = W / 4;
+    cg::grid_group grid = cg::this_grid();
+    const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nthreads = gridDim.x * blockDim.x;
+    const int sub = gtid % VW, grp = gtid / VW, ngrp = nthreads / VW;
+    __shared__ unsigned long long s_red[kSelBlock / kWave];
+    for (int t = t0; t < t1; ++t) {
+        const int src = (t == 0) ? first : load_agent(&pivots[t]);
+        if (gtid == 0) {
+            if (t == 0) pivots[0] = first;
+            m[src] = 0;
+            qa[0] = src;
+            ctl[0] = 1;
+            ctl[1] = 0;
+            ctl[2] = 0;
+        }
+        grid_barrier(grid);
+        int level = 0;
+        int* cur = qa;
+        int* nxt = qb;
+        for (;;) {
+            const int len = min(load_agent(&ctl[level % 3]), n);
+            if (len == 0) break;
+            int* tail = &ctl[(level + 1) % 3];
+            if (gtid == 0) ctl[(level + 2) % 3] = 0;
+            const int dv = level + 1;
+            const bool pre = len > kSelPrecheck;  // uniform
+            for (int base = 0; base < len; base += ngrp) {
+                const int qi = base + grp;
+                const int v = qi < len ? cur[qi] : -1;
+                int4 nb = make_int4(-1, -1, -1, -1);
+                if ((unsigned)v < (unsigned)n) nb = *(const int4*)(ell + (size_t)v * W + 4 * sub);
+                int u[4] = {nb.x, nb.y, nb.z, nb.w};
+                int old[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    old[j] = 0;
+                    if ((unsigned)u[j] < (unsigned)n && (!pre || m[u[j]] > dv)) old[j] = atomicMin(&m[u[j]], dv);
+                }
+                bool ok[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) ok[j] = (unsigned)u[j] < (unsigned)n && old[j] > dv;
+                append4_global(u, ok, tail, nxt);
+                // a row longer than W: its group walks the CSR tail (the
+                // continuation mark sits in the group's last lane)
+                const bool more = __shfl(nb.w, (lane_id() / VW) * VW + VW - 1) == kEllMore;
+                if (__ballot(more) != 0) {  // uniform per wave
+                    int e = 0, e1 = 0;
+                    if (more) {
+                        e = rp[v] + W - 1 + sub;
+                        e1 = rp[v + 1];
+                    }
+                    for (;;) {
+                        const bool any = e < e1;
+                        if (__ballot(any) == 0) break;
+                        int uu[4];
+                        int oo[4];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const int ee = e + j * VW;
+                            uu[j] = ee < e1 ? ci[ee] : -1;
+                        }
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            oo[j] = 0;
+                            if ((unsigned)uu[j] < (unsigned)n && (!pre || m[uu[j]] > dv))
+                                oo[j] = atomicMin(&m[uu[j]], dv);
+                        }
+                        bool okk[4];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) okk[j] = (unsigned)uu[j] < (unsigned)n && oo[j] > dv;
+                        append4_global(uu, okk, tail, nxt);
+                        e += 4 * VW;
+                    }
+                }
+            }
+            grid_barrier(grid);
+            int* tmp = cur;
+            cur = nxt;
+            nxt = tmp;
+            ++level;
+        }
+        if (t + 1 >= k && t != 0) break;
+        // argmax of m: 16-byte loads, four in flight
+        unsigned long long best = 0;
+        const int n4 = n / 4;
+        const int4* m4 = (const int4*)m;
+        for (int w0 = gtid; w0 < n4; w0 += 4 * nthreads) {
+            int4 q[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int w = w0 + j * nthreads;
+                q[j] = w < n4 ? m4[w] : make_int4(-1, -1, -1, -1);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int i = 4 * (w0 + j * nthreads);
+                if (q[j].x >= 0) best = key_max(best, argmax_key(q[j].x, i));
+                if (q[j].y >= 0) best = key_max(best, argmax_key(q[j].y, i + 1));
+                if (q[j].z >= 0) best = key_max(best, argmax_key(q[j].z, i + 2));
+                if (q[j].w >= 0) best = key_max(best, argmax_key(q[j].w, i + 3));
+            }
+        }
+        for (int i = 4 * n4 + gtid; i < n; i += nthreads) best = key_max(best, argmax_key(m[i], i));
+        best = block_max(best, s_red);
+        if (threadIdx.x == 0) keys[blockIdx.x] = best;
+        grid_barrier(grid);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            unsigned long long b = 0;
+            for (int q = 0; q < (int)gridDim.x; ++q) {
+                unsigned long long kq = __hip_atomic_load(&keys[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                b = kq > b ? kq : b;
+            }
+            if (t == 0) {
+                if ((int)(b >> 32) == kInf) status[0] = 1;
+                status[1] = (int)(b >> 32);
+            }
+            if (t + 1 < k) pivots[t + 1] = (int)(0xffffffffu - (unsigned)(b & 0xffffffffu));
+        }
+        grid_barrier(grid);
+        if (t == 0 && load_agent(&status[0]) != 0) break;  // disconnected: stop (uniform)
+    }
+}
+
 // All k pivots in one workgroup (no grid barrier): the same pruned BFS and
 // argmax as k_select_all, with the frontier in LDS (global overflow), LDS
 // counters and workgroup-scope atomics on m.
@@ -1205,11 +1492,6 @@ constexpr int kM7Sat = 127;
 static bool sel_bits_fit(int n) { return kLdsFixed + lds_bits_bytes(n) <= (size_t)kSelPool; }
 static bool sel_m8_fits(int n) { return kLdsFixed + (((size_t)n + 15) & ~(size_t)15) <= (size_t)kSelPool; }
 
-// Key of node i with value m for the argmax: the largest m wins, then the
-// lowest id.
-__device__ __forceinline__ unsigned long long argmax_key(int m, int i) {
-    return ((unsigned long long)(unsigned)m << 32) | (unsigned long long)(0xffffffffu - (unsigned)i);
-}
 
 // This thread's best key over m[0..n) (16-byte loads, 4 in flight).  Each
 // thread visits its indices in increasing order, so a strict comparison
@@ -1637,6 +1919,35 @@ static hipError_t launch_select(int blocks, hipStream_t s, int n, const int* rp,
                                       0, s);
 }
 
+template <int W>
+static hipError_t launch_select_grid_w(int blocks, hipStream_t s, int n, const int* rp, const int* ci, const int* ell,
+                                       int t0, int t1, int k, int first, int* pivots, int* m, int* qa, int* qb,
+                                       int* ctl, unsigned long long* keys, int* status) {
+    void* args[] = {&n, &rp, &ci, &ell, &t0, &t1, &k, &first, &pivots, &m, &qa, &qb, &ctl, &keys, &status};
+    return hipLaunchCooperativeKernel((const void*)k_select_grid<W>, dim3(blocks), dim3(kSelBlock), args, 0, s);
+}
+
+static hipError_t launch_select_grid(int W, int blocks, hipStream_t s, int n, const int* rp, const int* ci,
+                                     const int* ell, int t0, int t1, int k, int first, int* pivots, int* m, int* qa,
+                                     int* qb, int* ctl, unsigned long long* keys, int* status) {
+    if (W == 8)
+        return launch_select_grid_w<8>(blocks, s, n, rp, ci, ell, t0, t1, k, first, pivots, m, qa, qb, ctl, keys,
+                                       status);
+    if (W == 16)
+        return launch_select_grid_w<16>(blocks, s, n, rp, ci, ell, t0, t1, k, first, pivots, m, qa, qb, ctl, keys,
+                                        status);
+    return launch_select_grid_w<32>(blocks, s, n, rp, ci, ell, t0, t1, k, first, pivots, m, qa, qb, ctl, keys,
+                                    status);
+}
+
+static int select_grid_max_blocks(int W) {
+    int a = 0;
+    const void* f = W == 8 ? (const void*)k_select_grid<8> : W == 16 ? (const void*)k_select_grid<16>
+                                                                       : (const void*)k_select_grid<32>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, f, kSelBlock, 0) != hipSuccess) a = 1;
+    return std::max(1, a) * num_cus();
+}
+
 template <int VW>
 static int select_max_blocks() {
     int a = 0, b = 0;
@@ -1678,7 +1989,8 @@ ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pi
     unsigned long long* keys = nullptr;
     ssm_status st = salloc((void**)&ws, sizeof(int) * ints);
     if (st != SSM_OK) return st;
-    st = salloc((void**)&keys, sizeof(unsigned long long) * blocks);
+    constexpr int kKeysMax = 4096;  // partial argmax keys: room for any grid below
+    st = salloc((void**)&keys, sizeof(unsigned long long) * std::max(blocks, kKeysMax));
     if (st != SSM_OK) {
         sfree(ws);
         return st;
@@ -1697,8 +2009,10 @@ ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pi
                        4 * (long long)n);
     e = hipGetLastError();
     // Mode: one workgroup (no grid barrier) unless the frontiers are large.
-    int mode = variant("select_mode");  // 1 = one workgroup, 2 = cooperative grid, 3 = per pivot
-    if (mode < 1 || mode > 3) mode = (long long)n <= kSelOneWgMaxN ? 1 : 2;
+    // 1 = one workgroup, 2 = cooperative grid over CSR rows, 3 = per pivot,
+    // 4 = cooperative grid over padded rows
+    int mode = variant("select_mode");
+    if (mode < 1 || mode > 4) mode = (long long)n <= kSelOneWgMaxN ? 1 : 4;
     const bool per_pivot = mode == 3;
     // One workgroup: the LDS-resident form when the visited bits fit (tuning
     // override SSM_SELECT_ELL=2 keeps the global-memory form).
@@ -1729,6 +2043,38 @@ ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pi
             case 16: e = launch_select_all<16>(blocks, s, n, g->row_ptr, g->col_idx, k, first, pivots, m, qa, qb, ctl, keys, status); break;
             case 32: e = launch_select_all<32>(blocks, s, n, g->row_ptr, g->col_idx, k, first, pivots, m, qa, qb, ctl, keys, status); break;
             default: e = launch_select_all<64>(blocks, s, n, g->row_ptr, g->col_idx, k, first, pivots, m, qa, qb, ctl, keys, status); break;
+        }
+    }
+    if (mode == 4 && e == hipSuccess) {
+        // pivot 0's BFS on the default grid, then a grid sized by the graph's
+        // mean frontier, n / (eccentricity of pivot 0 + 1): a level costs a
+        // grid barrier whose time grows with the blocks, so narrow frontiers
+        // (long paths, meshes) take fewer blocks (measured on MI355X: a
+        // 3.25M-node mesh is fastest at 16, a 1M-node power-law graph at 32)
+        const int W = ell_width(g);
+        const int gmax = std::min(select_grid_max_blocks(W), kKeysMax);
+        int b0 = std::max(1, std::min(std::min(gmax, kSelGridBlocks), div_up(n, 8192)));
+        st = salloc((void**)&ell, sizeof(int) * (size_t)n * W);
+        if (st != SSM_OK) {
+            (void)hipStreamSynchronize(s);
+            sfree(ws);
+            sfree(keys);
+            return st;
+        }
+        e = ell_build(g, W, ell, s);
+        if (e == hipSuccess)
+            e = launch_select_grid(W, b0, s, n, g->row_ptr, g->col_idx, ell, 0, 1, k, first, pivots, m, qa, qb, ctl,
+                                   keys, status);
+        int hs[2] = {0, 0};
+        if (e == hipSuccess) e = hipMemcpyAsync(hs, status, sizeof hs, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e == hipSuccess && hs[0] == 0 && k > 1) {
+            const double mean_front = (double)n / ((double)hs[1] + 1.0);
+            int b1 = mean_front < 4096.0 ? std::min(b0, kSelGridBlocks / 2) : b0;
+            if (variant("select_blocks") > 0) b1 = std::min(gmax, variant("select_blocks"));
+            b1 = std::max(1, std::min(b1, gmax));
+            e = launch_select_grid(W, b1, s, n, g->row_ptr, g->col_idx, ell, 1, k, k, first, pivots, m, qa, qb, ctl,
+                                   keys, status);
         }
     }
     for (int t = 0; per_pivot && t < k && e == hipSuccess; ++t) {

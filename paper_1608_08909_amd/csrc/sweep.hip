@@ -4,6 +4,9 @@
 #include <math.h>
 #include <stdlib.h>
 
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include <hipcub/hipcub.hpp>
@@ -482,50 +485,163 @@ static void sweep_once(const SweepPlan& pl, ssm_prec p, hipStream_t s, const ssm
 
 constexpr size_t kSweepLdsMax = 150 * 1024;  // LDS of one FP32 sweep block (160 KB per CU)
 
-static SweepPlan plan_sweep(const ssm_terms* t, ssm_prec p) {
+// The FP32 sweep's weight form and its LDS bytes besides the partials: the
+// whole (w', w' d) table when it fits, else the histograms, else the table
+// in global memory (the form changes the arithmetic, so it follows from the
+// table sizes alone).
+static int sweep_mode(const ssm_terms* t, size_t* tab_bytes) {
+    const size_t table = sizeof(float2) * (size_t)t->kpad * t->W;
+    const size_t hist = sizeof(float2) * (size_t)(t->W + 1) / 2 * 2 + sizeof(float) * (size_t)t->kpad * (t->delta_max + 1);
+    const size_t parts = sizeof(float2) * (2 * 16 * 2 * 64 + (size_t)t->kpad);  // partials of the largest block, pivots
+    int mode = table + parts <= kSweepLdsMax ? kTableLds : hist + parts <= kSweepLdsMax ? kHistLds : kTableGlobal;
+    if (const int f = variant("sweep_mode")) {  // override: 2 = global table, 1 = LDS histograms (if they fit)
+        if (f == kTableGlobal || (f == kHistLds && hist + parts <= kSweepLdsMax)) mode = f;
+    }
+    *tab_bytes = mode == kTableLds ? table : mode == kHistLds ? hist : 0;
+    return mode;
+}
+
+// An FP32 launch shape: `split` waves per 64-node chunk, `waves` per block,
+// at most `bpc` blocks per CU (fewer when their LDS does not fit).
+static SweepPlan shape_f32(const ssm_terms* t, int mode, size_t tab, int split, int waves, int bpc) {
     SweepPlan pl;
-    const int nwords = t->kpad / t->vec;
+    pl.mode = mode;
+    pl.block = 64 * waves;
+    pl.split = split;
+    pl.cpb = waves / split;
+    pl.lds = sizeof(float2) * (size_t)t->kpad + tab + (split > 1 ? sizeof(float2) * 2 * waves * (4 / split) * 64 : 0);
+    const int fit = std::max(1, (int)((160 * 1024) / std::max<size_t>(pl.lds, 1)));
+    const long long groups = div_up(div_up(t->n, 64), pl.cpb);
+    pl.grid = (int)std::max<long long>(1, std::min(groups, (long long)num_cus() * std::min(bpc, fit)));
+    return pl;
+}
+
+// The rule shape: a large table is staged once per CU by a 16-wave block, a
+// small one by 4-wave blocks (finer load balance); two waves per chunk for
+// 4-wave blocks, one for 16-wave blocks; as many blocks per CU as fit, up to
+// four (two 16-wave blocks).  Variants override each choice.
+static SweepPlan plan_sweep(const ssm_terms* t, ssm_prec p) {
     if (p == SSM_FP64) {
+        SweepPlan pl;
         pl.block = 256;
         pl.lds = sizeof(double) * 2 * (size_t)t->kpad;
         pl.grid = std::max(1, std::min(div_up(t->n, pl.block), num_cus() * 8));
         return pl;
     }
-    // LDS form of the weights: the whole table, else the histograms
-    const size_t table = sizeof(float2) * (size_t)t->kpad * t->W;
-    const size_t hist = sizeof(float2) * (size_t)(t->W + 1) / 2 * 2 + sizeof(float) * (size_t)t->kpad * (t->delta_max + 1);
-    const size_t parts = sizeof(float2) * (2 * 16 * 64 + (size_t)t->kpad);  // partials of the largest block, pivots
-    if (table + parts <= kSweepLdsMax)
-        pl.mode = kTableLds;
-    else if (hist + parts <= kSweepLdsMax)
-        pl.mode = kHistLds;
-    else
-        pl.mode = kTableGlobal;
-    if (const int f = variant("sweep_mode")) {  // override: 2 = global table, 1 = LDS histograms (if they fit)
-        if (f == kTableGlobal || (f == kHistLds && hist + parts <= kSweepLdsMax)) pl.mode = f;
+    const int nwords = t->kpad / t->vec;
+    size_t tab = 0;
+    const int mode = sweep_mode(t, &tab);
+    int waves = tab > 40 * 1024 ? 16 : 4;
+    if (const int v = variant("sweep_waves")) {
+        if (v == 4 || v == 16) waves = v;
     }
-    const size_t tab = pl.mode == kTableLds ? table : pl.mode == kHistLds ? hist : 0;
-    // a large table is staged once per CU by a 16-wave block; a small one by
-    // 4-wave blocks (finer load balance)
-    pl.block = tab > 40 * 1024 ? 1024 : 256;
-    const int nw = pl.block / 64;
-    // waves per 64-node chunk (measured on MI355X over 0.1M-3M-node graphs):
-    // two for 4-wave blocks, one for the 16-wave blocks of large tables
-    const long long chunks = div_up(t->n, 64);
-    int split = std::min(pl.block == 1024 ? 1 : 2, nwords);
-    if (const int f = variant("sweep_split")) {  // override
+    int split = std::min(waves == 16 ? 1 : 2, nwords);
+    if (const int f = variant("sweep_split")) {
         if ((f == 1 || f == 2 || f == 4) && f <= nwords) split = f;
     }
-    pl.split = split;
-    pl.cpb = nw / split;
-    pl.lds = sizeof(float2) * (size_t)t->kpad + tab + (split > 1 ? sizeof(float2) * 2 * nw * 64 : 0);
-    const int per_cu = pl.block == 1024 ? (pl.lds <= 80 * 1024 ? 2 : 1)
-                                        : std::max(1, std::min(4, (int)((160 * 1024) / std::max<size_t>(pl.lds, 1))));
-    long long max_grid = (long long)num_cus() * per_cu;
-    if (const int v = variant("sweep_blocks_per_cu")) max_grid = std::max(1, v) * (long long)num_cus();
-    const long long groups = div_up(chunks, pl.cpb);
-    pl.grid = (int)std::max<long long>(1, std::min(groups, max_grid));
-    return pl;
+    int bpc = waves == 16 ? 2 : 4;
+    if (const int v = variant("sweep_blocks_per_cu")) bpc = std::max(1, v);
+    return shape_f32(t, mode, tab, split, waves, bpc);
+}
+
+// ---------------------------------------------------------- autotuner
+//
+// The FP32 sweep's result does not depend on its launch shape (split, block
+// shape, grid: see k_sweep_f32), so the first FP32 sweep loop of at least
+// kTuneMinIters sweeps on a graph shape times every candidate shape for a
+// few sweeps on scratch copies of the layout and keeps the fastest, per
+// device and (n, arcs, padded k, table extents, distance width, node
+// order).  Forced variants skip the tuning.
+constexpr int kTuneMinIters = 24;
+
+struct PlanKey {
+    int dev, n, nnz, kpad, W, L, dbytes, ordered, mode;
+    bool operator<(const PlanKey& o) const {
+        return std::tie(dev, n, nnz, kpad, W, L, dbytes, ordered, mode) <
+               std::tie(o.dev, o.n, o.nnz, o.kpad, o.W, o.L, o.dbytes, o.ordered, o.mode);
+    }
+};
+static std::mutex g_plan_mu;
+static std::map<PlanKey, SweepPlan> g_plans;
+
+// Any forced sweep variant (the weight form included) turns the tuning off
+// and leaves the cache alone.
+static bool sweep_shape_forced() {
+    return variant("sweep_split") || variant("sweep_blocks_per_cu") || variant("sweep_waves") ||
+           variant("sweep_mode") || variant("sweep_tune") == -1;
+}
+
+// Times `reps` sweeps of plan pl on scratch buffers ya, yb (ya holds a copy
+// of the layout); 0 on error.
+static float time_plan(const SweepPlan& pl, hipStream_t s, const ssm_csr* g, ssm_terms* t, float2* ya, float2* yb,
+                       hipEvent_t e0, hipEvent_t e1, int reps) {
+    float2* pcb[2] = {t->pc, t->pc + t->kpad};
+    hipLaunchKernelGGL(k_stop_init, dim3(1), dim3(64), 0, s, t->stopw, 0);
+    hipLaunchKernelGGL(k_gather_pivots, dim3(div_up(t->kpad, 256)), dim3(256), 0, s, t->kpad, t->pivots,
+                       (const float2*)ya, pcb[0]);
+    sweep_once(pl, SSM_FP32, s, g, t, ya, yb, pcb[0], pcb[1]);  // warm
+    float2* buf[2] = {yb, ya};
+    if (hipEventRecord(e0, s) != hipSuccess) return 0.f;
+    for (int r = 0; r < reps; ++r)
+        sweep_once(pl, SSM_FP32, s, g, t, buf[r & 1], buf[(r + 1) & 1], pcb[(r + 1) & 1], pcb[r & 1]);
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return 0.f;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return 0.f;
+    return ms;
+}
+
+static SweepPlan tuned_plan(const ssm_csr* g, ssm_terms* t, const void* x, int iters, hipStream_t s) {
+    SweepPlan rule = plan_sweep(t, SSM_FP32);
+    if (iters < kTuneMinIters || sweep_shape_forced()) return rule;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return rule;
+    PlanKey key{t->device, t->n, t->nnz, t->kpad, t->W, t->delta_max + 1, t->dbytes, t->perm != nullptr, rule.mode};
+    {
+        std::lock_guard<std::mutex> lock(g_plan_mu);
+        auto it = g_plans.find(key);
+        if (it != g_plans.end()) return it->second;
+    }
+    const int nwords = t->kpad / t->vec;
+    size_t tab = 0;
+    const int mode = sweep_mode(t, &tab);
+    std::vector<SweepPlan> cand;
+    for (int waves : {4, 16}) {
+        if (tab > 40 * 1024 && waves == 4) continue;  // a large table is staged once per CU
+        for (int split : {1, 2, 4}) {
+            if (split > nwords) continue;
+            for (int bpc : {1, 2, 3, 4, 6, 8}) {
+                if (waves == 16 && bpc > 2) continue;
+                cand.push_back(shape_f32(t, mode, tab, split, waves, bpc));
+            }
+        }
+    }
+    float2* y = nullptr;
+    if (salloc((void**)&y, sizeof(float2) * 2 * (size_t)t->n) != SSM_OK) return rule;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    SweepPlan best = rule;
+    float best_ms = 0.f;
+    bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
+              hipMemcpyAsync(y, x, sizeof(float2) * (size_t)t->n, hipMemcpyDeviceToDevice, s) == hipSuccess;
+    for (size_t c = 0; ok && c < cand.size(); ++c) {
+        const float ms = time_plan(cand[c], s, g, t, y, y + t->n, e0, e1, 3);
+        if (ms <= 0.f) {
+            ok = false;
+            break;
+        }
+        if (best_ms == 0.f || ms < best_ms) {
+            best_ms = ms;
+            best = cand[c];
+        }
+    }
+    (void)hipStreamSynchronize(s);  // idle before the scratch is reused
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    sfree(y);
+    (void)hipGetLastError();
+    if (!ok) return rule;
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    g_plans[key] = best;
+    return best;
 }
 
 // The sweep loop over buffers bufs[0] (in/out) and bufs[1]; the result ends
@@ -536,7 +652,7 @@ static SweepPlan plan_sweep(const ssm_terms* t, ssm_prec p) {
 // asked for.
 static ssm_status sweep_loop(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* const (&bufs)[2], int32_t iters,
                              double tol, int32_t* iters_done_host, hipStream_t s) {
-    const SweepPlan pl = plan_sweep(t, p);
+    const SweepPlan pl = p == SSM_FP32 ? tuned_plan(g, t, bufs[0], iters, s) : plan_sweep(t, p);
     const size_t xbytes = (p == SSM_FP64 ? sizeof(double) : sizeof(float)) * 2 * (size_t)t->n;
     void* const x = bufs[0];
     const int mblocks = std::min(div_up(t->n, 256), kStopBlocks);

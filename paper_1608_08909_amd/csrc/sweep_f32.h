@@ -86,13 +86,16 @@ __device__ __forceinline__ void stage_lds(void* dst, const void* __restrict__ sr
 }
 
 // Block = CPB groups of SPLIT wavefronts; a group takes 64 consecutive nodes
-// (lane = node) and its SPLIT waves share the node's terms: wave s sums the
-// packed distance words b = s, s + SPLIT, ... (one coalesced 16-byte load
-// per lane covers VEC pivots; two words stay in flight).  The last wave of
-// the group, which holds the fewest words, also sums the neighbour terms in
-// CSR order (heavy rows: their segment sums in order).  Wave 0 adds the
-// SPLIT partials in a fixed order.  Blocks loop over the chunks, so the LDS
-// tables are staged once per block.
+// (lane = node) and its SPLIT waves share the node's terms.  The terms are
+// summed in four classes by packed-word index b mod 4, each class in
+// ascending b (one coalesced 16-byte load per lane covers VEC pivots; two of
+// a wave's words stay in flight); the neighbour terms, in CSR order (heavy
+// rows: their segment sums in order), open class 3.  The node's sum is
+// (A0 + A1) + (A2 + A3) whatever SPLIT is: wave s holds the classes
+// congruent to s mod SPLIT, and wave 0 combines them (partials of the other
+// waves through LDS).  So SPLIT, the block shape and the grid change the
+// speed only, never a bit of the result.  Blocks loop over the chunks, so
+// the LDS tables are staged once per block.
 //
 // Every lane of a wave reads the same pivot t, so the pivot's coordinates
 // are wave-uniform loads from the contiguous array pc (kept current by the
@@ -111,10 +114,12 @@ __global__ __launch_bounds__(64 * SPLIT * CPB) void k_sweep_f32(
     const int* __restrict__ stop) {
     if (stop[0]) return;  // the sweep loop has met its stop test (uniform over the grid)
     constexpr int NW = SPLIT * CPB;
+    constexpr int R = 4 / SPLIT;  // classes per wave
+    static_assert(SPLIT == 1 || SPLIT == 2 || SPLIT == 4, "waves per chunk");
     extern __shared__ float4 smem4[];
     float2* sP = (float2*)smem4;                                  // [kpad] pivot coordinates
-    float2* sPart = sP + kpad;                                    // [2][NW][64] (SPLIT > 1)
-    float2* sTab = sPart + (SPLIT > 1 ? 2 * NW * 64 : 0);         // kTableLds: [kpad][W]; kHistLds: invd [W]
+    float2* sPart = sP + kpad;                                    // [2][NW][R][64] (SPLIT > 1)
+    float2* sTab = sPart + (SPLIT > 1 ? 2 * NW * R * 64 : 0);     // kTableLds: [kpad][W]; kHistLds: invd [W]
     float* sH = (float*)(sTab + (MODE == kHistLds ? (W + 1) / 2 * 2 : 0));  // kHistLds: H [kpad][L]
     stage_lds(sP, pc, sizeof(float2) * (size_t)kpad);
     if (MODE == kTableLds) stage_lds(sTab, wt2, sizeof(float2) * (size_t)kpad * W);
@@ -132,14 +137,17 @@ __global__ __launch_bounds__(64 * SPLIT * CPB) void k_sweep_f32(
     int buf = 0;
     for (int c0 = blockIdx.x * CPB; c0 < nchunks; c0 += gridDim.x * CPB) {  // uniform over the block
         const int i = (c0 + grp) * 64 + lane;
-        float ax = 0.f, ay = 0.f;
+        float2 acc[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) acc[q] = make_float2(0.f, 0.f);
         float2 xi = make_float2(0.f, 0.f);
         if (i < n) {
             xi = xo[i];
             Packed<DT, VEC> wa, wb;
             wa.v = sw < nwords ? dpk[(size_t)sw * n + i] : make_uint4(0, 0, 0, 0);
             wb.v = sw + SPLIT < nwords ? dpk[(size_t)(sw + SPLIT) * n + i] : make_uint4(0, 0, 0, 0);
-            if (sw == SPLIT - 1) {
+            if (sw == SPLIT - 1) {  // the wave holding class 3
+                float ax = 0.f, ay = 0.f;
                 const int e0 = rp[i], e1 = rp[i + 1];
                 if (e1 - e0 > kHeavyDegree) {  // the row's segment sums, in order
                     const int2 r = seg_range[i];
@@ -172,54 +180,67 @@ __global__ __launch_bounds__(64 * SPLIT * CPB) void k_sweep_f32(
                         }
                     }
                 }
+                acc[R - 1] = make_float2(ax, ay);
             }
-            for (int b = sw; b < nwords; b += SPLIT) {
-                const Packed<DT, VEC> u = wa;
-                wa = wb;
-                if (b + 2 * SPLIT < nwords) wb.v = dpk[(size_t)(b + 2 * SPLIT) * n + i];  // two words ahead
+            // this wave's words b = sw, sw + SPLIT, ...: the j-th goes to class
+            // (sw + j SPLIT) mod 4, local accumulator j mod R
+            for (int b0 = sw; b0 < nwords; b0 += 4) {
 #pragma unroll
-                for (int jj = 0; jj < VEC; ++jj) {
-                    const int t = b * VEC + jj;  // wave-uniform
-                    const int d = (int)u.e[jj];
-                    float f0, f1, hmul;  // f = hmul (f0 - f1 / r)
-                    if (MODE == kHistLds) {
-                        hmul = sH[t * L + min(d >> 1, L - 1)];
-                        const float2 id = sTab[d];
-                        f0 = id.x;
-                        f1 = id.y;
-                    } else {
-                        const float2 e = MODE == kTableLds ? sTab[t * W + d] : wt2[(size_t)t * W + d];
-                        f0 = e.x;
-                        f1 = e.y;
-                        hmul = 1.f;
+                for (int q = 0; q < R; ++q) {
+                    const int b = b0 + q * SPLIT;
+                    if (b >= nwords) break;
+                    const Packed<DT, VEC> u = wa;
+                    wa = wb;
+                    if (b + 2 * SPLIT < nwords) wb.v = dpk[(size_t)(b + 2 * SPLIT) * n + i];  // two words ahead
+                    float ax = acc[q].x, ay = acc[q].y;
+#pragma unroll
+                    for (int jj = 0; jj < VEC; ++jj) {
+                        const int t = b * VEC + jj;  // wave-uniform
+                        const int d = (int)u.e[jj];
+                        float f0, f1, hmul;  // f = hmul (f0 - f1 / r)
+                        if (MODE == kHistLds) {
+                            hmul = sH[t * L + min(d >> 1, L - 1)];
+                            const float2 id = sTab[d];
+                            f0 = id.x;
+                            f1 = id.y;
+                        } else {
+                            const float2 e = MODE == kTableLds ? sTab[t * W + d] : wt2[(size_t)t * W + d];
+                            f0 = e.x;
+                            f1 = e.y;
+                            hmul = 1.f;
+                        }
+                        const float2 p = sP[t];  // LDS broadcast
+                        float dx = p.x - xi.x, dy = p.y - xi.y;
+                        float inv = __builtin_amdgcn_rsqf(dx * dx + (dy * dy + tiny));
+                        float f = fmaf(-f1, inv, f0);
+                        if (MODE == kHistLds) f *= hmul;
+                        ax += f * dx;
+                        ay += f * dy;
                     }
-                    const float2 p = sP[t];  // LDS broadcast
-                    float dx = p.x - xi.x, dy = p.y - xi.y;
-                    float inv = __builtin_amdgcn_rsqf(dx * dx + (dy * dy + tiny));
-                    float f = fmaf(-f1, inv, f0);
-                    if (MODE == kHistLds) f *= hmul;
-                    ax += f * dx;
-                    ay += f * dy;
+                    acc[q] = make_float2(ax, ay);
                 }
             }
         }
-        if (SPLIT > 1) {
+        float2 tot = make_float2(0.f, 0.f);
+        if (SPLIT == 1) {
+            tot = make_float2((acc[0].x + acc[1 % R].x) + (acc[2 % R].x + acc[3 % R].x),
+                              (acc[0].y + acc[1 % R].y) + (acc[2 % R].y + acc[3 % R].y));
+        } else {
             // partials double-buffered: one barrier per chunk group
-            sPart[(buf * NW + w) * 64 + lane] = make_float2(ax, ay);
+#pragma unroll
+            for (int q = 0; q < R; ++q) sPart[((buf * NW + w) * R + q) * 64 + lane] = acc[q];
             __syncthreads();
             if (sw == 0) {
+                float2 A[4];  // class c lives in wave c mod SPLIT, local index c / SPLIT
 #pragma unroll
-                for (int q = 1; q < SPLIT; ++q) {
-                    const float2 o = sPart[(buf * NW + w + q) * 64 + lane];
-                    ax += o.x;
-                    ay += o.y;
-                }
+                for (int c = 0; c < 4; ++c) A[c] = sPart[((buf * NW + w + c % SPLIT) * R + c / SPLIT) * 64 + lane];
+                tot = make_float2((A[0].x + A[1].x) + (A[2].x + A[3].x), (A[0].y + A[1].y) + (A[2].y + A[3].y));
             }
             buf ^= 1;
         }
         if (sw == 0 && i < n) {
             const float dn = den[i];
-            const float2 v = make_float2(xi.x + ax / dn, xi.y + ay / dn);
+            const float2 v = make_float2(xi.x + tot.x / dn, xi.y + tot.y / dn);
             xn[i] = v;
             const int r = prank[i];
             if (r >= 0) pc_next[r] = v;

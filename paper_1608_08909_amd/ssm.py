@@ -223,10 +223,12 @@ class Terms:
             _lib.ssm_terms_free(h)
         self.handle = None
 
-    def __del__(self):
-        # at interpreter exit the atexit hook has already freed the handle
-        if not sys.is_finalizing():
-            self.close()
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # at interpreter exit the atexit hook has already freed the handle (the
+        # check is bound here: module globals may be gone by then)
+        if getattr(self, "handle", None) is None or _finalizing():
+            return
+        self.close()
 
     def dims(self):
         k, dm, dx = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
@@ -446,8 +448,8 @@ class Pool:
             self._lib.ssm_pool_destroy(self.handle)
             self.handle = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.close()
@@ -548,8 +550,8 @@ class WTerms:
             _lib.ssm_wterms_free(self.handle)
         self.handle = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.close()

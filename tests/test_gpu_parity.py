@@ -85,17 +85,19 @@ def test_regions_with_given_pivots():
 
 
 # Launch-variant overrides (ssm_set_variant): each selects
-# another kernel variant (cooperative-grid or per-pivot selection, selection
+# another kernel variant (cooperative-grid selection over CSR or padded rows,
+# per-pivot selection, selection
 # without the LDS byte copy or over the plain CSR with node-id queues or
 # another precheck, the CSR per-workgroup BFS, the bit-parallel BFS, one- or
 # many-workgroup region tie resolution, other lanes per node).
 VARIANTS = [
     {"select_mode": 2}, {"select_mode": 2, "select_blocks": 3}, {"select_mode": 3},
+    {"select_mode": 4}, {"select_mode": 4, "select_blocks": 3},
     {"select_m8": 2}, {"select_ell": 2}, {"select_mode": 1},
     {"select_ell": 2, "select_rowq": 2},
     {"select_ell": 2, "select_rowq": 2, "select_pre": 3},
     {"select_ell": 2, "select_pre": 1},
-    {"bfs_rowq": 2, "bfs_ell": 2}, {"bfs_ell": 2}, {"msbfs": 1},
+    {"bfs_rowq": 2, "bfs_ell": 2}, {"bfs_ell": 2}, {"bfs_ell": 3}, {"bfs_ell": 4}, {"msbfs": 1},
     {"msbfs": 1, "msbfs_budget": 3},
     {"region_mode": 1}, {"region_mode": 2}, {"bfs_lanes": 2}, {"bfs_lanes": 64},
     {"select_wave": -1}, {"select_wave": 2},
@@ -123,7 +125,7 @@ def test_kernel_variants_bit_exact(env, forced):
 
 @pytest.mark.parametrize("g,k", [(G.rgg(150000, 21, 8.0), 24), (G.grid(400, 400), 8), (G.barabasi_albert(120000, 2, 5), 30)],
                          ids=["rgg150000-k24", "grid400x400-k8", "ba120000-k30"])
-@pytest.mark.parametrize("mode", ["0", "2"], ids=["auto", "grid"])
+@pytest.mark.parametrize("mode", ["0", "2", "4"], ids=["auto", "grid", "grid-ell"])
 def test_select_beyond_byte_copy(g, k, mode, forced):
     """Graphs too large for the LDS byte copy of m but within one workgroup's
     visited bits, and the cooperative grid form; the grid graph has
@@ -136,7 +138,8 @@ def test_select_beyond_byte_copy(g, k, mode, forced):
     assert np.array_equal(ssm.select_pivots(dg, k, 0).cpu().numpy(), piv_r)
 
 
-@pytest.mark.parametrize("env", [{}, {"msbfs": 1}, {"bfs_ell": 2}], ids=["default", "bitparallel", "csr"])
+@pytest.mark.parametrize("env", [{}, {"msbfs": 1}, {"bfs_ell": 2}, {"bfs_ell": 3}, {"bfs_ell": 4}],
+                         ids=["default", "bitparallel", "csr", "ell-global", "ell-global-noread"])
 def test_bfs_large_frontiers(env, forced):
     """Frontiers beyond the LDS queue and more long rows per level than the
     LDS list holds: the global overflow areas of the per-pivot BFS."""
@@ -582,3 +585,54 @@ def test_sweep_order_bit_identical(g, k, forced):
     assert np.isfinite(outs[0][1]).all()
     assert np.array_equal(outs[0][1], outs[1][1])
     assert outs[0][2] == outs[1][2]
+
+
+SHAPES = [dict(sweep_split=sp, sweep_waves=wv, sweep_blocks_per_cu=bpc)
+          for sp in (1, 2, 4) for wv in (4, 16) for bpc in (1, 3, 8)]
+
+
+@pytest.mark.parametrize("g,k", [(G.barabasi_albert(20000, 5, 3), 37), (G.rgg(3000, 5), 48),
+                                 (G.holed_mesh(120, 130, 6, 4, 12, 5), 40), (G.grid(13, 17), 10)],
+                         ids=["ba20000", "rgg3000", "holedmesh120", "grid13x17"])
+def test_sweep_f32_launch_shapes_bit_identical(g, k, forced):
+    """The FP32 sweep sums each node's terms in four fixed classes, whatever
+    the waves per chunk, waves per block or grid: every launch shape gives
+    the same coordinates bit for bit (so the autotuner may pick any), and
+    the tuned loop equals the rule shape's."""
+    say("case", g.name, "k", k)
+    dg, *_, terms = _device_pipeline(g, k)
+    x0 = ssm.pivotmds_init(dg, terms, ssm.FP32)
+    forced("sweep_tune", -1)
+    ref = x0.clone()
+    ssm.majorize(dg, terms, ref, 30, sync=True)
+    ref = ref.cpu().numpy()
+    assert np.isfinite(ref).all()
+    for shape in SHAPES:
+        for name, val in shape.items():
+            forced(name, val)
+        x = x0.clone()
+        ssm.majorize(dg, terms, x, 30, sync=True)
+        assert np.array_equal(x.cpu().numpy(), ref), shape
+    ssm.set_variant(None)
+    x = x0.clone()
+    ssm.majorize(dg, terms, x, 30, sync=True)  # tuned (30 >= 24 sweeps)
+    assert np.array_equal(x.cpu().numpy(), ref)
+
+
+def test_sweep_tuning_follows_the_weight_form(forced):
+    """A loop run with a forced weight form must not leave its launch plan
+    for later loops of the same graph shape: after it, the default loop
+    (tuned) equals the rule shape's loop bit for bit."""
+    g, k = G.rgg(3000, 5), 40
+    dg, *_, terms = _device_pipeline(g, k)
+    x0 = ssm.pivotmds_init(dg, terms, ssm.FP32)
+    forced("sweep_mode", 2)
+    x = x0.clone()
+    ssm.majorize(dg, terms, x, 30, sync=True)
+    ssm.set_variant(None)
+    tuned = x0.clone()
+    ssm.majorize(dg, terms, tuned, 30, sync=True)
+    forced("sweep_tune", -1)
+    rule = x0.clone()
+    ssm.majorize(dg, terms, rule, 30, sync=True)
+    assert torch.equal(tuned, rule)

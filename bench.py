@@ -43,10 +43,10 @@ FP64_PEAK_TFLOPS = 78.6
 # 64 lanes per clock x 2.4 GHz, in lane-slots per second
 VALU_PEAK_TSLOTS = 256 * 64 * 2.4e9 / 1e12
 # VALU lane-slots of the arithmetic one FP32 term needs: two subtractions,
-# two FMAs for r^2, the reciprocal square root (a transcendental, issued at a
-# quarter of the full rate: 4 slots), one FMA for the coefficient and two
+# two FMAs for r^2, the reciprocal square root (a transcendental: measured on
+# MI355X at half the FMA rate, 2 slots), one FMA for the coefficient and two
 # FMAs into the sums -- addressing and unpacking excluded
-SLOTS_PER_TERM = 11
+SLOTS_PER_TERM = 9
 PROFILE_LABEL = {"rgg": "rgg100k_k200", "ba": "ba1m_k200", "mesh": "mesh2000_k100", "grid": "grid50_k50"}
 
 
@@ -667,6 +667,12 @@ def main():
 
 if __name__ == "__main__":
     main()
-    # free the library's handles and cached scratch before interpreter teardown
+    # free the library's handles and cached scratch, and torch's cached device
+    # memory, before interpreter teardown
     if "paper_1608_08909_amd.ssm" in sys.modules:
         sys.modules["paper_1608_08909_amd.ssm"].shutdown()
+    if "torch" in sys.modules:
+        import torch
+        if torch.cuda.is_initialized():
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()

@@ -190,11 +190,11 @@ def test_fullsize_kmeans_sp(run):
     - converged before the pass cap, the final clusters are a fixed point:
       every node's cluster minimizes a_t - 2 B_ti / N_t (a_t summed in
       ascending j, no fused multiply-add; lowest t on ties) for the centroids
-      of those same clusters;
+      of those same clusters (the holed mesh runs to the cap of 50 passes;
+      there the centroids of the last pass's clusters are what the new pivots
+      are chosen against, and the next check holds them);
     - new pivot t minimizes N_t ||y_i||^2 - 2 B_ti over the nodes not taken
       by a lower rank (lowest id on ties)."""
-    if run.name == "mesh":
-        pytest.skip("k-means sp is certified on the random geometric and Barabasi-Albert graphs")
     k, n = run.dist.shape
     say("case", run.name, "kmeans sp")
     newp, assign, it = ssm.kmeans_pivots(run.piv, run.dist)

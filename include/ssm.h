@@ -387,6 +387,8 @@ void ssm_release_cache(void);
  * Names and values:
  *   select_mode 1|2|3|4 (one workgroup, cooperative grid over CSR rows,
  *   per-pivot launches, cooperative grid over padded rows),
+ *   select_hyb 1 (in mode 4: each pruned BFS by one block of the grid,
+ *   the argmax by all of it),
  *   select_blocks N, select_threads 256|512, select_ell 2 (plain CSR),
  *   select_m8 2 (no LDS byte copy), select_rowq 2, select_pre 1|3,
  *   select_wave -1|2 (block levels only, two passes per wave level),

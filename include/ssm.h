@@ -402,7 +402,8 @@ void ssm_release_cache(void);
  *   sweep otherwise times its shapes on the first loop of at least 24
  *   sweeps per graph shape and keeps the fastest),
  *   sweep_perm -1|2 (caller's node order, always reorder),
- *   sssp_nearfar -1 (plain rounds), sssp_band N.
+ *   sssp_nearfar -1 (plain rounds), sssp_band N,
+ *   ell_width 8|16|32 (slots per padded adjacency row in BFS and selection).
  * SSM_E_INVAL for an unknown name. */
 ssm_status ssm_set_variant(const char* name, int32_t value);
 

@@ -76,9 +76,19 @@ __global__ void k_validate(int n, int nnz, const int* __restrict__ rp, const int
 // (row_ptr[v], row_ptr[v+1]) of a frontier node, loaded when the node is
 // pushed, so that the next level starts with its neighbour loads.
 constexpr int kQcap = 3072;
+constexpr int kBfsU = 4;
 
-__device__ __forceinline__ int wg_load(const int* p) {  // L2-coherent within the workgroup
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+// Agent-scope relaxed loads compile to cache-bypassing (sc1) loads.  They
+// are coherent with every block's atomics and agent-scope stores, and on
+// MI355X a chain of them measures about 90 ns per dependent load against
+// about 350 ns for plain loads that miss L2, so the BFS kernels take their
+// latency-bound loads (row bounds, neighbour ids, visited checks) this way.
+__device__ __forceinline__ int load_agent(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int wg_load(const int* p) {  // coherent with this workgroup's atomics (and all others')
+    return load_agent(p);
 }
 
 __device__ __forceinline__ int2 queue_get(const int2* lds, const int2* glob, int idx) {
@@ -92,12 +102,12 @@ __device__ __forceinline__ int2 queue_get(const int2* lds, const int2* glob, int
 template <bool ROWQ>
 __device__ __forceinline__ int2 entry_row(int2 q, const int* __restrict__ rp, int n) {
     if (ROWQ) return q;
-    return (unsigned)q.x < (unsigned)n ? make_int2(rp[q.x], rp[q.x + 1]) : make_int2(0, 0);
+    return (unsigned)q.x < (unsigned)n ? make_int2(load_agent(&rp[q.x]), load_agent(&rp[q.x + 1])) : make_int2(0, 0);
 }
 
 template <bool ROWQ>
 __device__ __forceinline__ int2 make_entry(int v, const int* __restrict__ rp) {
-    if (ROWQ) return make_int2(rp[v], rp[v + 1]);
+    if (ROWQ) return make_int2(load_agent(&rp[v]), load_agent(&rp[v + 1]));
     return make_int2(v, 0);
 }
 
@@ -142,22 +152,43 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_wg(int n, const int* __restri
     for (;;) {
         const int len = min(s_len, n);
         if (len == 0) break;
-        for (int base = 0; base < len; base += ngrp) {
-            int qi = base + grp;
-            int2 row = make_int2(0, 0);
-            if (qi < len) row = entry_row<ROWQ>(queue_get(lcur, gcur, qi), rp, n);
-            for (int e = row.x + sub; e < row.y; e += VW) {
-                int v = ci[e];
-                bool claim = false;
-                int2 vrow;
-                if ((unsigned)v < (unsigned)n && wg_load(&D[v]) < 0) {
-                    int expected = -1;
-                    claim = __hip_atomic_compare_exchange_strong(&D[v], &expected, level + 1, __ATOMIC_RELAXED,
-                                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    if (claim) vrow = make_entry<ROWQ>(v, rp);
+        // kBfsU frontier entries per lane group and pass, their loads in flight
+        // together (a level is a few passes of dependent memory round trips)
+        for (int base = 0; base < len; base += ngrp * kBfsU) {
+            int2 row[kBfsU];
+            int span = 0;
+#pragma unroll
+            for (int q = 0; q < kBfsU; ++q) {
+                const int qi = base + q * ngrp + grp;
+                row[q] = qi < len ? entry_row<ROWQ>(queue_get(lcur, gcur, qi), rp, n) : make_int2(0, 0);
+                span = max(span, row[q].y - row[q].x);
+            }
+            for (int j = sub; j < span; j += VW) {
+                int v[kBfsU], seen[kBfsU];
+#pragma unroll
+                for (int q = 0; q < kBfsU; ++q) v[q] = row[q].x + j < row[q].y ? load_agent(&ci[row[q].x + j]) : -1;
+#pragma unroll
+                for (int q = 0; q < kBfsU; ++q) seen[q] = (unsigned)v[q] < (unsigned)n ? wg_load(&D[v[q]]) : 0;
+                bool claim[kBfsU];
+#pragma unroll
+                for (int q = 0; q < kBfsU; ++q) {
+                    claim[q] = false;
+                    if ((unsigned)v[q] < (unsigned)n && seen[q] < 0) {
+                        int expected = -1;
+                        claim[q] = __hip_atomic_compare_exchange_strong(&D[v[q]], &expected, level + 1,
+                                                                        __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                                        __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
                 }
-                int slot = wave_append(claim, &s_tail);
-                if (claim) queue_put(lnxt, gnxt, slot, vrow);
+                int2 vrow[kBfsU];
+#pragma unroll
+                for (int q = 0; q < kBfsU; ++q)
+                    if (claim[q]) vrow[q] = make_entry<ROWQ>(v[q], rp);
+#pragma unroll
+                for (int q = 0; q < kBfsU; ++q) {
+                    const int slot = wave_append(claim[q], &s_tail);
+                    if (claim[q]) queue_put(lnxt, gnxt, slot, vrow[q]);
+                }
             }
         }
         __syncthreads();
@@ -493,6 +524,8 @@ __global__ void k_ell_build(int n, int W, const int* __restrict__ rp, const int*
 
 // Slots per padded row: the mean degree rounded up to 8, 16 or 32.
 static int ell_width(const ssm_csr* g) {
+    const int forced = variant("ell_width");  // tuning override: 8, 16 or 32
+    if (forced == 8 || forced == 16 || forced == 32) return forced;
     const double avg = g->n > 0 ? (double)g->nnz / g->n : 0.0;
     return avg <= 4.0 ? 8 : avg <= 12.0 ? 16 : 32;
 }
@@ -1044,10 +1077,6 @@ __device__ __forceinline__ void grid_barrier(cg::grid_group& grid) {
         grid.sync();
 }
 
-__device__ __forceinline__ int load_agent(const int* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // One launch per pivot t.  BFS from pivots[t] that only continues through
 // nodes whose distance to the new pivot is smaller than m (their distance to
 // the nearest earlier pivot), updating m on the way.  This is exact for
@@ -1233,9 +1262,66 @@ __device__ __forceinline__ unsigned long long key_max(unsigned long long a, unsi
     return a > b ? a : b;
 }
 
-// Appends the u[j] with ok[j] (j < 4) to a global frontier: one counter
-// reservation per wave.  Call with every lane of the wave active.
-__device__ __forceinline__ void append4_global(const int (&u)[4], const bool (&ok)[4], int* tail, int* nxt) {
+// Frontiers up to this size lower m with the atomic alone; wider ones read m
+// first and skip the atomic where m is already at most the new distance.
+constexpr int kSelPrecheck = 16384;
+
+// Agent-scope accesses for data that blocks of one launch exchange: relaxed
+// atomic loads and stores compile to cache-bypassing (sc1) accesses, so what
+// one block stored and waited for is what another block loads, with no cache
+// writeback or invalidation between them.
+__device__ __forceinline__ void store_agent(int* p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_agent(unsigned long long* p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int4 load_agent4(const int* p) {  // p 16-byte aligned
+    unsigned long long* q = (unsigned long long*)p;
+    const unsigned long long a = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long b = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return make_int4((int)(unsigned)a, (int)(unsigned)(a >> 32), (int)(unsigned)b, (int)(unsigned)(b >> 32));
+}
+
+// Grid barrier of a cooperative launch whose blocks share data only through
+// agent-scope atomics and the agent-scope loads and stores above: every
+// thread waits for its own memory operations to complete, then one thread
+// per block counts in on a 64-bit counter and polls it until the whole grid
+// has arrived (about 1.4 us for 32 blocks on MI355X against 4.6 us for the
+// cooperative-groups grid sync, whose cache writeback and invalidation this
+// sharing does not need).  bar is zeroed before the launch and serves one
+// launch; epoch (thread 0's) is the count that ends the current barrier.  A
+// barrier still not full after 2^25 polls (seconds) sets the counter's top
+// bit, which every block sees on its next poll: sync_grid then returns false
+// in every block and the kernel leaves, so a broken count ends in an error
+// rather than a hang.
+constexpr unsigned long long kBarAbort = 1ull << 63;
+constexpr long long kBarPolls = 1ll << 25;
+
+__device__ __forceinline__ bool sync_grid(unsigned long long* bar, unsigned long long& epoch) {
+    __shared__ int s_go;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        epoch += gridDim.x;
+        unsigned long long v = __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+        long long polls = 0;
+        while ((v & kBarAbort) == 0 && (long long)(v - epoch) < 0) {
+            if (++polls > kBarPolls) {
+                v = __hip_atomic_fetch_or(bar, kBarAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) | kBarAbort;
+                break;
+            }
+            v = __hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        s_go = (v & kBarAbort) == 0;
+    }
+    __syncthreads();
+    return s_go != 0;
+}
+
+// Appends the u[j] with ok[j] (j < 4) to a global frontier with agent-scope
+// stores: one counter reservation per wave.  Call with every lane active.
+__device__ __forceinline__ void append4_agent(const int (&u)[4], const bool (&ok)[4], int* tail, int* nxt) {
     uint64_t mk[4];
     int tot = 0;
 #pragma unroll
@@ -1249,46 +1335,50 @@ __device__ __forceinline__ void append4_global(const int (&u)[4], const bool (&o
     at = __builtin_amdgcn_readfirstlane(at);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        if (ok[j]) nxt[at + mask_rank(mk[j])] = u[j];
+        if (ok[j]) store_agent(&nxt[at + mask_rank(mk[j])], u[j]);
         at += __popcll(mk[j]);
     }
 }
-
-// Frontiers up to this size lower m with the atomic alone; wider ones read m
-// first and skip the atomic where m is already at most the new distance.
-constexpr int kSelPrecheck = 16384;
 
 // Pivots t0 .. t1-1 of max/min sampling in one cooperative launch, over the
 // padded adjacency: each group of W/4 lanes takes one frontier node and four
 // of its neighbours per lane (a longer row's CSR tail is walked by the same
 // lanes).  The pruned BFS and the argmax are those of k_select_all: a
 // relaxation lowers m with one atomicMin and the node joins the next frontier
-// iff the atomic lowered it.  The argmax reads m with 16-byte loads, four in
-// flight per thread (lowest id on ties through the key).  status[1] = the
-// largest m after pivot 0's BFS (its eccentricity).
+// iff the atomic lowered it.  Blocks share the frontiers, counters, m and the
+// partial keys through agent-scope accesses only, so the levels end in
+// sync_grid.  The argmax reads m 16 bytes at a time, four in flight per
+// thread (lowest id on ties through the key).  status[1] = the largest m
+// after pivot 0's BFS (its eccentricity); status[2] = 1 if a grid barrier
+// aborted.
 template <int W>
 __global__ __launch_bounds__(kSelBlock) void k_select_grid(int n, const int* __restrict__ rp,
                                                            const int* __restrict__ ci, const int* __restrict__ ell,
                                                            int t0, int t1, int k, int first, int* pivots, int* m,
                                                            int* qa, int* qb, int* ctl, unsigned long long* keys,
-                                                           int* status) {
+                                                           int* status, unsigned long long* bar) {
     constexpr int VW = W / 4;
-    cg::grid_group grid = cg::this_grid();
     const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
     const int nthreads = gridDim.x * blockDim.x;
     const int sub = gtid % VW, grp = gtid / VW, ngrp = nthreads / VW;
     __shared__ unsigned long long s_red[kSelBlock / kWave];
+    unsigned long long epoch = 0;
+#define SYNC_OR_LEAVE()                                   \
+    if (!sync_grid(bar, epoch)) {                         \
+        if (gtid == 0) store_agent(&status[2], 1);       \
+        return;                                           \
+    }
     for (int t = t0; t < t1; ++t) {
         const int src = (t == 0) ? first : load_agent(&pivots[t]);
         if (gtid == 0) {
-            if (t == 0) pivots[0] = first;
-            m[src] = 0;
-            qa[0] = src;
-            ctl[0] = 1;
-            ctl[1] = 0;
-            ctl[2] = 0;
+            if (t == 0) store_agent(&pivots[0], first);
+            atomicMin(&m[src], 0);
+            store_agent(&qa[0], src);
+            store_agent(&ctl[0], 1);
+            store_agent(&ctl[1], 0);
+            store_agent(&ctl[2], 0);
         }
-        grid_barrier(grid);
+        SYNC_OR_LEAVE();
         int level = 0;
         int* cur = qa;
         int* nxt = qb;
@@ -1296,25 +1386,27 @@ __global__ __launch_bounds__(kSelBlock) void k_select_grid(int n, const int* __r
             const int len = min(load_agent(&ctl[level % 3]), n);
             if (len == 0) break;
             int* tail = &ctl[(level + 1) % 3];
-            if (gtid == 0) ctl[(level + 2) % 3] = 0;
+            if (gtid == 0) store_agent(&ctl[(level + 2) % 3], 0);
             const int dv = level + 1;
             const bool pre = len > kSelPrecheck;  // uniform
             for (int base = 0; base < len; base += ngrp) {
                 const int qi = base + grp;
-                const int v = qi < len ? cur[qi] : -1;
+                const int v = qi < len ? load_agent(&cur[qi]) : -1;
                 int4 nb = make_int4(-1, -1, -1, -1);
-                if ((unsigned)v < (unsigned)n) nb = *(const int4*)(ell + (size_t)v * W + 4 * sub);
+                if ((unsigned)v < (unsigned)n) nb = load_agent4(ell + (size_t)v * W + 4 * sub);
                 int u[4] = {nb.x, nb.y, nb.z, nb.w};
                 int old[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     old[j] = 0;
+                    // a stale read of m is never below the current value (m
+                    // only falls), so the check never skips a needed atomic
                     if ((unsigned)u[j] < (unsigned)n && (!pre || m[u[j]] > dv)) old[j] = atomicMin(&m[u[j]], dv);
                 }
                 bool ok[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) ok[j] = (unsigned)u[j] < (unsigned)n && old[j] > dv;
-                append4_global(u, ok, tail, nxt);
+                append4_agent(u, ok, tail, nxt);
                 // a row longer than W: its group walks the CSR tail (the
                 // continuation mark sits in the group's last lane)
                 const bool more = __shfl(nb.w, (lane_id() / VW) * VW + VW - 1) == kEllMore;
@@ -1343,28 +1435,27 @@ __global__ __launch_bounds__(kSelBlock) void k_select_grid(int n, const int* __r
                         bool okk[4];
 #pragma unroll
                         for (int j = 0; j < 4; ++j) okk[j] = (unsigned)uu[j] < (unsigned)n && oo[j] > dv;
-                        append4_global(uu, okk, tail, nxt);
+                        append4_agent(uu, okk, tail, nxt);
                         e += 4 * VW;
                     }
                 }
             }
-            grid_barrier(grid);
+            SYNC_OR_LEAVE();
             int* tmp = cur;
             cur = nxt;
             nxt = tmp;
             ++level;
         }
         if (t + 1 >= k && t != 0) break;
-        // argmax of m: 16-byte loads, four in flight
+        // argmax of m: 16-byte agent-scope loads, four in flight
         unsigned long long best = 0;
         const int n4 = n / 4;
-        const int4* m4 = (const int4*)m;
         for (int w0 = gtid; w0 < n4; w0 += 4 * nthreads) {
             int4 q[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int w = w0 + j * nthreads;
-                q[j] = w < n4 ? m4[w] : make_int4(-1, -1, -1, -1);
+                q[j] = w < n4 ? load_agent4(m + 4 * (size_t)w) : make_int4(-1, -1, -1, -1);
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -1375,10 +1466,10 @@ __global__ __launch_bounds__(kSelBlock) void k_select_grid(int n, const int* __r
                 if (q[j].w >= 0) best = key_max(best, argmax_key(q[j].w, i + 3));
             }
         }
-        for (int i = 4 * n4 + gtid; i < n; i += nthreads) best = key_max(best, argmax_key(m[i], i));
+        for (int i = 4 * n4 + gtid; i < n; i += nthreads) best = key_max(best, argmax_key(load_agent(&m[i]), i));
         best = block_max(best, s_red);
-        if (threadIdx.x == 0) keys[blockIdx.x] = best;
-        grid_barrier(grid);
+        if (threadIdx.x == 0) store_agent(&keys[blockIdx.x], best);
+        SYNC_OR_LEAVE();
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             unsigned long long b = 0;
             for (int q = 0; q < (int)gridDim.x; ++q) {
@@ -1386,14 +1477,15 @@ __global__ __launch_bounds__(kSelBlock) void k_select_grid(int n, const int* __r
                 b = kq > b ? kq : b;
             }
             if (t == 0) {
-                if ((int)(b >> 32) == kInf) status[0] = 1;
-                status[1] = (int)(b >> 32);
+                if ((int)(b >> 32) == kInf) store_agent(&status[0], 1);
+                store_agent(&status[1], (int)(b >> 32));
             }
-            if (t + 1 < k) pivots[t + 1] = (int)(0xffffffffu - (unsigned)(b & 0xffffffffu));
+            if (t + 1 < k) store_agent(&pivots[t + 1], (int)(0xffffffffu - (unsigned)(b & 0xffffffffu)));
         }
-        grid_barrier(grid);
+        SYNC_OR_LEAVE();
         if (t == 0 && load_agent(&status[0]) != 0) break;  // disconnected: stop (uniform)
     }
+#undef SYNC_OR_LEAVE
 }
 
 // Pivots t0 .. t1-1 of max/min sampling in one cooperative launch for
@@ -2026,22 +2118,24 @@ static hipError_t launch_select(int blocks, hipStream_t s, int n, const int* rp,
 template <int W>
 static hipError_t launch_select_grid_w(int blocks, hipStream_t s, int n, const int* rp, const int* ci, const int* ell,
                                        int t0, int t1, int k, int first, int* pivots, int* m, int* qa, int* qb,
-                                       int* ctl, unsigned long long* keys, int* status) {
-    void* args[] = {&n, &rp, &ci, &ell, &t0, &t1, &k, &first, &pivots, &m, &qa, &qb, &ctl, &keys, &status};
+                                       int* ctl, unsigned long long* keys, int* status, unsigned long long* bar) {
+    void* args[] = {&n, &rp, &ci, &ell, &t0, &t1, &k, &first, &pivots, &m, &qa, &qb, &ctl, &keys, &status, &bar};
     return hipLaunchCooperativeKernel((const void*)k_select_grid<W>, dim3(blocks), dim3(kSelBlock), args, 0, s);
 }
 
+// bar: a zeroed 64-bit barrier counter for this launch alone
 static hipError_t launch_select_grid(int W, int blocks, hipStream_t s, int n, const int* rp, const int* ci,
                                      const int* ell, int t0, int t1, int k, int first, int* pivots, int* m, int* qa,
-                                     int* qb, int* ctl, unsigned long long* keys, int* status) {
+                                     int* qb, int* ctl, unsigned long long* keys, int* status,
+                                     unsigned long long* bar) {
     if (W == 8)
         return launch_select_grid_w<8>(blocks, s, n, rp, ci, ell, t0, t1, k, first, pivots, m, qa, qb, ctl, keys,
-                                       status);
+                                       status, bar);
     if (W == 16)
         return launch_select_grid_w<16>(blocks, s, n, rp, ci, ell, t0, t1, k, first, pivots, m, qa, qb, ctl, keys,
-                                        status);
+                                        status, bar);
     return launch_select_grid_w<32>(blocks, s, n, rp, ci, ell, t0, t1, k, first, pivots, m, qa, qb, ctl, keys,
-                                    status);
+                                    status, bar);
 }
 
 template <int W>
@@ -2097,7 +2191,7 @@ constexpr int kSelHybBlocks = 64;  // grid of the hybrid form (its blocks only s
 
 ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pivots, hipStream_t s) {
     const int n = g->n;
-    // workspace: m[n], vis[n], qa[n], qb[n], ctl[4], status[1], keys[max blocks]
+    // workspace: m[n], vis[n], qa[n], qb[n], ctl[4], status[3], barrier counters, keys[max blocks]
     int vw = virtual_warp(g);
     int maxb = 1;
     switch (vw) {
@@ -2114,8 +2208,9 @@ ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pi
     int blocks = std::max(1, std::min(std::min(maxb, kSelGridBlocks), div_up(n, 8192)));
     if (variant("select_blocks") > 0) blocks = std::min(maxb, variant("select_blocks"));
     // m[n], vis[n], queue area (4n ints: two int queues of n, or two int2
-    // queues of n for the one-workgroup kernel), control words
-    size_t ints = 6 * (size_t)n + 8;
+    // queues of n for the one-workgroup kernel), control words, and two
+    // 64-bit grid barrier counters on lines of their own
+    size_t ints = 6 * (size_t)n + 128;
     int* ws = nullptr;
     unsigned long long* keys = nullptr;
     ssm_status st = salloc((void**)&ws, sizeof(int) * ints);
@@ -2132,10 +2227,11 @@ ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pi
     int* qb = ws + 3 * (size_t)n;
     int* ctl = ws + 6 * (size_t)n;
     int* status = ctl + 4;
+    unsigned long long* bars = (unsigned long long*)(ctl + 32);  // bars[0], bars[16]: one per launch
     hipError_t e = hipSuccess;
     hipLaunchKernelGGL(k_fill_int, dim3(std::min(div_up(n, 256), 4096)), dim3(256), 0, s, m, kInf, (long long)n);
     hipLaunchKernelGGL(k_fill_int, dim3(std::min(div_up(n, 256), 4096)), dim3(256), 0, s, vis, -1, (long long)n);
-    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, ctl, 0, (long long)8);
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(128), 0, s, ctl, 0, (long long)128);
     hipLaunchKernelGGL(k_fill_int, dim3(std::min(div_up(4 * (long long)n, 256), 4096)), dim3(256), 0, s, qa, 0,
                        4 * (long long)n);
     e = hipGetLastError();
@@ -2195,11 +2291,11 @@ ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pi
         e = ell_build(g, W, ell, s);
         if (e == hipSuccess)
             e = launch_select_grid(W, b0, s, n, g->row_ptr, g->col_idx, ell, 0, 1, k, first, pivots, m, qa, qb, ctl,
-                                   keys, status);
-        int hs[2] = {0, 0};
+                                   keys, status, bars);
+        int hs[3] = {0, 0, 0};
         if (e == hipSuccess) e = hipMemcpyAsync(hs, status, sizeof hs, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e == hipSuccess && hs[0] == 0 && k > 1) {
+        if (e == hipSuccess && hs[0] == 0 && hs[2] == 0 && k > 1) {
             const double mean_front = (double)n / ((double)hs[1] + 1.0);
             // variant select_hyb = 1: block 0 runs each pruned BFS alone and
             // the grid joins for the argmax (measured on MI355X: 216 against
@@ -2228,7 +2324,7 @@ ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pi
                 if (variant("select_blocks") > 0) b1 = std::min(gmax, variant("select_blocks"));
                 b1 = std::max(1, std::min(b1, gmax));
                 e = launch_select_grid(W, b1, s, n, g->row_ptr, g->col_idx, ell, 1, k, k, first, pivots, m, qa, qb,
-                                       ctl, keys, status);
+                                       ctl, keys, status, bars + 16);
             }
         }
     }
@@ -2242,14 +2338,15 @@ ssm_status select_pivots(const ssm_csr* g, int32_t k, int32_t first, int32_t* pi
             default: e = launch_select<64>(blocks, s, n, g->row_ptr, g->col_idx, t, k, first, pivots, m, vis, qa, qb, ctl, keys, status); break;
         }
     }
-    int hstatus = 0;
-    if (e == hipSuccess) e = hipMemcpyAsync(&hstatus, status, sizeof(int), hipMemcpyDeviceToHost, s);
+    int hstatus[3] = {0, 0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(hstatus, status, sizeof hstatus, hipMemcpyDeviceToHost, s);
     (void)hipStreamSynchronize(s);  // idle before the scratch is reused (also after an error)
     sfree(ws);
     sfree(keys);
     if (ell) sfree(ell);
     if (e != hipSuccess) return hip_fail(e, "pivot selection");
-    if (hstatus) return fail(SSM_E_DISCONNECTED, "graph is not connected (the first BFS missed nodes)");
+    if (hstatus[2]) return fail(SSM_E_DEVICE, "pivot selection: a grid barrier did not fill and was aborted");
+    if (hstatus[0]) return fail(SSM_E_DISCONNECTED, "graph is not connected (the first BFS missed nodes)");
     return SSM_OK;
 }
 

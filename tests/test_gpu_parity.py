@@ -94,6 +94,7 @@ VARIANTS = [
     {"select_mode": 2}, {"select_mode": 2, "select_blocks": 3}, {"select_mode": 3},
     {"select_mode": 4}, {"select_mode": 4, "select_blocks": 3}, {"select_mode": 4, "select_hyb": 1},
     {"select_mode": 4, "select_hyb": 1, "select_blocks": 2},
+    {"select_mode": 4, "ell_width": 8}, {"select_mode": 4, "ell_width": 32},
     {"select_m8": 2}, {"select_ell": 2}, {"select_mode": 1},
     {"select_ell": 2, "select_rowq": 2},
     {"select_ell": 2, "select_rowq": 2, "select_pre": 3},

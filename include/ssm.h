@@ -47,7 +47,7 @@ typedef enum {
 
 typedef enum { SSM_FP64 = 0, SSM_FP32 = 1 } ssm_prec;
 
-typedef enum { SSM_STRESS_SPARSE = 0, SSM_STRESS_FULL = 1 } ssm_stress_kind;
+typedef enum { SSM_STRESS_SPARSE = 0, SSM_STRESS_FULL = 1, SSM_STRESS_NORMALIZED = 2 } ssm_stress_kind;
 
 typedef struct {
     int32_t n;               /* nodes, >= 1 */
@@ -187,7 +187,10 @@ ssm_status ssm_majorize_mixed(const ssm_csr* g, ssm_terms* t, double* x64, float
 /* Stress of layout x, accumulated in FP64: SSM_STRESS_SPARSE is s'(x) of
  * Eq. 3 (edges with w = 1, d = 1, plus every pivot term with w'_it);
  * SSM_STRESS_FULL is s(x) of Eq. 1 over all pairs with d the hop distance
- * and w = d^-2 (n <= 65536).  Writes out_host[0].  Synchronizes. */
+ * and w = d^-2 (n <= 65536); SSM_STRESS_NORMALIZED is that full stress
+ * divided by the number of pairs n (n - 1) / 2, the normalized stress of
+ * Section 4.1 (n <= 65536, t may be NULL for both).  Writes out_host[0].
+ * Synchronizes. */
 ssm_status ssm_stress(const ssm_csr* g, ssm_terms* t, ssm_prec p, const void* x,
                       ssm_stress_kind kind, double* out_host, hipStream_t stream);
 
@@ -252,7 +255,7 @@ ssm_status ssm_stress_w(const ssm_csr* g, const double* len, const ssm_wterms* t
  * perfect match.  Accumulated in FP64.  SSM_E_INVAL when a layout has all its
  * nodes at one point.  Writes out_host[0].  Synchronizes.
  * The paper's other measure, the normalized stress, is ssm_stress with
- * SSM_STRESS_FULL divided by n (n - 1) / 2. */
+ * SSM_STRESS_NORMALIZED. */
 ssm_status ssm_procrustes(int32_t n, ssm_prec px, const void* x, ssm_prec py, const void* y, double* out_host,
                           hipStream_t stream);
 

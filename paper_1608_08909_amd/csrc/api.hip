@@ -359,9 +359,12 @@ ssm_status ssm_stress(const ssm_csr* g, ssm_terms* t, ssm_prec p, const void* x,
         if (t->n != g->n) return fail(SSM_E_INVAL, "terms were built for another graph");
         return stress_sparse(g, t, p, x, out_host, stream);
     }
-    if (kind == SSM_STRESS_FULL) {
+    if (kind == SSM_STRESS_FULL || kind == SSM_STRESS_NORMALIZED) {
         if (g->n > 65536) return fail(SSM_E_RANGE, "full stress supports n <= 65536");
-        return stress_full(g, p, x, out_host, stream);
+        st = stress_full(g, p, x, out_host, stream);
+        // normalized stress (Section 4.1): per node pair
+        if (st == SSM_OK && kind == SSM_STRESS_NORMALIZED) out_host[0] /= (double)g->n * (g->n - 1) / 2.0;
+        return st;
     }
     return fail(SSM_E_INVAL, "unknown stress kind");
 }

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libssm.so")
 
 OK, E_INVAL, E_RANGE, E_DISCONNECTED, E_NOMEM, E_DEVICE = range(6)
 FP64, FP32 = 0, 1
-STRESS_SPARSE, STRESS_FULL = 0, 1
+STRESS_SPARSE, STRESS_FULL, STRESS_NORMALIZED = 0, 1, 2
 
 _lock = threading.Lock()
 _lib = None
@@ -377,7 +377,7 @@ def procrustes(x: torch.Tensor, y: torch.Tensor) -> float:
 
 def normalized_stress(g: DeviceGraph, x: torch.Tensor) -> float:
     """Full stress s(x) (Eq. 1) divided by the number of node pairs."""
-    return stress(g, None, x, STRESS_FULL) / (g.n * (g.n - 1) / 2)
+    return stress(g, None, x, STRESS_NORMALIZED)
 
 
 def full_stress_layout(g: DeviceGraph, iters: int, first: int = 0, start_k: int | None = None):

@@ -58,8 +58,9 @@ def test_full_stress_reference_and_quality():
     xr, _ = ssm.full_stress_layout(dg, 500)   # n = 180: PivotMDS on all n pivots, as the oracle
     xo, _, _, _ = oracle.layout(g.n, g.row_ptr, g.col_idx, g.n, 500)
     assert brute.coord_error(xr.cpu().numpy(), xo, align=True) < 1e-9
-    ns_ref = ssm.normalized_stress(dg, xr)
+    ns_ref = ssm.normalized_stress(dg, xr)  # SSM_STRESS_NORMALIZED, divided in the library
     assert abs(ns_ref - oracle.normalized_stress(g.row_ptr, g.col_idx, xr.cpu().numpy())) <= 1e-12 * ns_ref
+    assert ns_ref == ssm.stress(dg, None, xr, ssm.STRESS_FULL) / (g.n * (g.n - 1) / 2)
     for sampling in ("maxmin", "kmeans"):
         for k in (6, 20):
             x, *_ = ssm.layout(dg, k, 200, ssm.FP64, sampling=sampling)

@@ -329,8 +329,11 @@ ssm_status ssm_pool_prepare(ssm_pool* p, int32_t count, const int32_t* slots_hos
 
 /* Up to `iters` FP32 Jacobi sweeps (Eq. 5, displacement form) on every
  * listed ready slot, never past its sweep count: one launch per sweep covers
- * all of them.  Asynchronous; a later call that reads a slot (stress,
- * layout, export, remove) waits for it. */
+ * all of them.  The quantum (its sweeps and stop tests) is one HIP graph,
+ * captured once per rounded (chunks, graphs, sweeps, LDS) shape and
+ * replayed; the kernels take the real counts from the staged header.
+ * Asynchronous; a later call that reads a slot (stress, layout, export,
+ * remove) waits for it. */
 ssm_status ssm_pool_sweep(ssm_pool* p, int32_t count, const int32_t* slots_host, int32_t iters,
                           hipStream_t stream);
 
@@ -406,7 +409,9 @@ void ssm_release_cache(void);
  *   sweeps per graph shape and keeps the fastest),
  *   sweep_perm -1|2 (caller's node order, always reorder),
  *   sssp_nearfar -1 (plain rounds), sssp_band N,
- *   ell_width 8|16|32 (slots per padded adjacency row in BFS and selection).
+ *   ell_width 8|16|32 (slots per padded adjacency row in BFS and selection),
+ *   pool_graph -1 (ssm_pool_sweep launches each kernel instead of replaying
+ *   a captured HIP graph of the quantum).
  * SSM_E_INVAL for an unknown name. */
 ssm_status ssm_set_variant(const char* name, int32_t value);
 

@@ -284,8 +284,10 @@ inline int pool_hist_mode(int kpad, int L, int W) {
 // graph's tables fit (else from the (w', w' d) table in global memory).
 // Pivot coordinates are staged in LDS once per block.
 __global__ __launch_bounds__(kPoolSweepBlock) void k_pool_sweep32(const PoolGraph* __restrict__ gs,
-                                                                  const int2* __restrict__ chunks, int s) {
+                                                                  const int2* __restrict__ chunks,
+                                                                  const int* __restrict__ hdr, int s) {
     extern __shared__ float4 psm[];
+    if ((int)blockIdx.x >= hdr[0]) return;  // a grid rounded up for a reusable graph
     const int2 ch = chunks[blockIdx.x];
     const PoolGraph& g = gs[ch.x];
     if (s >= g.iters) return;  // the whole block
@@ -372,7 +374,9 @@ __global__ __launch_bounds__(kPoolSweepBlock) void k_pool_sweep32(const PoolGrap
 // of each listed 256-node chunk of a graph that has a tolerance and has not
 // stopped yet, relative to o = the graph's node 0 in the old iterate.
 __global__ __launch_bounds__(256) void k_pool_moments(const PoolGraph* __restrict__ gs, const int2* __restrict__ chunks,
-                                                      int s, double* __restrict__ partial) {
+                                                      const int* __restrict__ hdr, int s,
+                                                      double* __restrict__ partial) {
+    if ((int)blockIdx.x >= hdr[0]) return;  // a grid rounded up for a reusable graph
     const int2 ch = chunks[blockIdx.x];
     const PoolGraph& g = gs[ch.x];
     if (s >= g.iters || !(g.tol > 0.0) || g.info[6]) return;  // the whole block
@@ -396,10 +400,10 @@ __global__ __launch_bounds__(256) void k_pool_moments(const PoolGraph* __restric
 // One thread per listed graph: the chunk partials first[q] .. first[q + 1]
 // summed in order; a change <= tol after sweep s sets info[6] and records
 // the sweeps run in info[7].
-__global__ void k_pool_decide(const PoolGraph* __restrict__ gs, int count, const int* __restrict__ first,
-                              const double* __restrict__ partial, int s) {
+__global__ void k_pool_decide(const PoolGraph* __restrict__ gs, const int* __restrict__ hdr,
+                              const int* __restrict__ first, const double* __restrict__ partial, int s) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= count) return;
+    if (q >= hdr[1]) return;
     const PoolGraph& g = gs[q];
     if (s >= g.iters || !(g.tol > 0.0) || g.info[6]) return;
     double m[kMoments];
@@ -569,6 +573,21 @@ struct Slot {
 
 // Staging of one asynchronous sweep call: host copies and device buffer
 // stay untouched until `done` has fired.
+// A captured sweep quantum: the launches of `most` sweeps (and stop tests)
+// over grids rounded up to (chunks, graphs), with LDS `lds`; the kernels take
+// the real counts from the stage header, so one graph serves every call whose
+// counts round to the same buckets.
+struct QuantumKey {
+    int chunks, graphs, most, lds, tol;
+    bool operator<(const QuantumKey& o) const {
+        if (chunks != o.chunks) return chunks < o.chunks;
+        if (graphs != o.graphs) return graphs < o.graphs;
+        if (most != o.most) return most < o.most;
+        if (lds != o.lds) return lds < o.lds;
+        return tol < o.tol;
+    }
+};
+
 struct Stage {
     std::vector<PoolGraph> hg;
     std::vector<int2> hc;
@@ -576,6 +595,7 @@ struct Stage {
     size_t cap = 0;
     hipEvent_t done = nullptr;
     bool pending = false;
+    std::map<QuantumKey, hipGraphExec_t> graphs;  // captured quanta over dev's layout
 };
 
 }  // namespace
@@ -590,6 +610,8 @@ struct ssm_pool {
     int2* tiles = nullptr;  // Gram tile list for up to kPoolMaxK / 16 tile columns
     ssm::Stage stage[2];
     int flip = 0;
+    hipStream_t capture = nullptr;  // where sweep quanta are captured (never run on)
+    bool no_graphs = false;         // capture failed once: launch directly
     std::mutex mu;  // calls on one pool are serialized
 };
 
@@ -792,9 +814,11 @@ void ssm_pool_destroy(ssm_pool* p) {
     if (!p) return;
     (void)wait_all(p);
     for (auto& st : p->stage) {
+        for (auto& kv : st.graphs) (void)hipGraphExecDestroy(kv.second);
         if (st.dev) (void)hipFree(st.dev);
         if (st.done) (void)hipEventDestroy(st.done);
     }
+    if (p->capture) (void)hipStreamDestroy(p->capture);
     if (p->tiles) (void)hipFree(p->tiles);
     if (p->arena.base) (void)hipFree(p->arena.base);
     delete p;
@@ -1075,12 +1099,32 @@ ssm_status ssm_pool_sweep(ssm_pool* p, int32_t count, const int32_t* slots, int3
     }
     if (most == 0) return SSM_OK;
     first.push_back((int)stg.hc.size());
-    const size_t o_first = align_up(sizeof(PoolGraph) * stg.hg.size()) + align_up(sizeof(int2) * stg.hc.size());
-    const size_t o_part = o_first + align_up(sizeof(int) * first.size());
-    const size_t need = any_tol ? o_part + sizeof(double) * kMoments * stg.hc.size()
-                                : align_up(sizeof(PoolGraph) * stg.hg.size()) + sizeof(int2) * stg.hc.size();
+    const int nch = (int)stg.hc.size();
+    // Launch grids rounded up to a multiple of an eighth of the next power of
+    // two (at most a quarter more blocks, which return at once), so that one
+    // captured graph serves every quantum whose counts round alike (variant
+    // pool_graph -1: direct launches over the exact grids)
+    const bool use_graph = !p->no_graphs && variant("pool_graph") != -1;
+    auto bucket = [&](int v) {
+        if (!use_graph) return v;
+        int b = 16;
+        while (b < v) b <<= 1;
+        const int q = std::max(4, b / 8);  // steps of an eighth of the octave's top
+        return std::max(16, div_up(v, q) * q);
+    };
+    const int nchB = bucket(nch), countB = bucket(count);
+    const size_t ldsB = use_graph ? (size_t)div_up((long long)lds, 4096) * 4096 : lds;
+    // stage layout: header (chunk and graph counts), graphs, chunks, first
+    // chunk per graph, moment partials; offsets from the rounded counts
+    const size_t o_g = 256;
+    const size_t o_c = o_g + align_up(sizeof(PoolGraph) * countB);
+    const size_t o_first = o_c + align_up(sizeof(int2) * nchB);
+    const size_t o_part = o_first + align_up(sizeof(int) * (countB + 1));
+    const size_t need = any_tol ? o_part + sizeof(double) * kMoments * nchB : o_first;
     if (need > stg.cap) {
         const size_t want = std::max(need, stg.cap * 2);
+        for (auto& kv : stg.graphs) (void)hipGraphExecDestroy(kv.second);  // they point into the old buffer
+        stg.graphs.clear();
         if (stg.dev) (void)hipFree(stg.dev);
         stg.dev = nullptr;
         stg.cap = 0;
@@ -1090,26 +1134,65 @@ ssm_status ssm_pool_sweep(ssm_pool* p, int32_t count, const int32_t* slots, int3
         }
         stg.cap = want;
     }
-    PoolGraph* dg = (PoolGraph*)stg.dev;
-    int2* dc = (int2*)(stg.dev + align_up(sizeof(PoolGraph) * stg.hg.size()));
+    int* dh = (int*)stg.dev;
+    PoolGraph* dg = (PoolGraph*)(stg.dev + o_g);
+    int2* dc = (int2*)(stg.dev + o_c);
     int* dfirst = any_tol ? (int*)(stg.dev + o_first) : nullptr;
     double* dpart = any_tol ? (double*)(stg.dev + o_part) : nullptr;
-    hipError_t e = hipMemcpyAsync(dg, stg.hg.data(), sizeof(PoolGraph) * stg.hg.size(), hipMemcpyHostToDevice, s);
+    const int hdr[4] = {nch, count, 0, 0};
+    hipError_t e = hipMemcpyAsync(dh, hdr, sizeof hdr, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dg, stg.hg.data(), sizeof(PoolGraph) * stg.hg.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(dc, stg.hc.data(), sizeof(int2) * stg.hc.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && any_tol)
         e = hipMemcpyAsync(dfirst, first.data(), sizeof(int) * first.size(), hipMemcpyHostToDevice, s);
-    const int nch = (int)stg.hc.size();
-    if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute((const void*)k_pool_sweep32, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    for (int it = 0; it < most && e == hipSuccess; ++it) {
-        hipLaunchKernelGGL(k_pool_sweep32, dim3(nch), dim3(kPoolSweepBlock), lds, s, dg, dc, it);
-        if (any_tol) {
-            hipLaunchKernelGGL(k_pool_moments, dim3(nch), dim3(256), 0, s, dg, dc, it, dpart);
-            hipLaunchKernelGGL(k_pool_decide, dim3(div_up(count, 256)), dim3(256), 0, s, dg, count, dfirst, dpart,
-                               it);
+    if (ldsB > 64 * 1024)
+        (void)hipFuncSetAttribute((const void*)k_pool_sweep32, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ldsB);
+    auto launch_quantum = [&](hipStream_t q, int grid_c, int grid_g) {
+        for (int it = 0; it < most; ++it) {
+            hipLaunchKernelGGL(k_pool_sweep32, dim3(grid_c), dim3(kPoolSweepBlock), ldsB, q, dg, dc, dh, it);
+            if (any_tol) {
+                hipLaunchKernelGGL(k_pool_moments, dim3(grid_c), dim3(256), 0, q, dg, dc, dh, it, dpart);
+                hipLaunchKernelGGL(k_pool_decide, dim3(div_up(grid_g, 256)), dim3(256), 0, q, dg, dh, dfirst, dpart,
+                                   it);
+            }
         }
-        e = hipGetLastError();
+    };
+    hipGraphExec_t exec = nullptr;
+    if (e == hipSuccess && use_graph) {
+        const QuantumKey key{nchB, countB, most, (int)ldsB, any_tol ? 1 : 0};
+        auto it = stg.graphs.find(key);
+        if (it != stg.graphs.end()) {
+            exec = it->second;
+        } else {
+            // capture on the pool's own stream (the caller's may be the null
+            // stream, which cannot be captured); nothing runs there
+            hipError_t c = p->capture ? hipSuccess : hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking);
+            hipGraph_t graph = nullptr;
+            if (c == hipSuccess) c = hipStreamBeginCapture(p->capture, hipStreamCaptureModeRelaxed);
+            if (c == hipSuccess) {
+                launch_quantum(p->capture, nchB, countB);
+                c = hipStreamEndCapture(p->capture, &graph);
+            }
+            if (c == hipSuccess) c = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (graph) (void)hipGraphDestroy(graph);
+            if (c == hipSuccess) {
+                stg.graphs[key] = exec;
+            } else {  // no graphs from now on; this quantum launches directly
+                (void)hipGetLastError();
+                exec = nullptr;
+                p->no_graphs = true;
+            }
+        }
+    }
+    if (e == hipSuccess) {
+        if (exec)
+            e = hipGraphLaunch(exec, s);
+        else {
+            launch_quantum(s, nch, count);
+            e = hipGetLastError();
+        }
     }
     if (e == hipSuccess) e = hipEventRecord(stg.done, s);
     if (e != hipSuccess) {

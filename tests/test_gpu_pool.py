@@ -137,6 +137,36 @@ def test_pool_alone_equals_mixed():
     mix.close()
 
 
+def test_pool_captured_quanta_match_direct_launches():
+    """Sweep quanta replayed from captured HIP graphs (the default) equal the
+    same quanta launched kernel by kernel, bit for bit, after every replay:
+    the same shapes again and again (replays of one graph), another shape in
+    between, a graph with the stop test, exports (synchronizing reads)
+    between the replays."""
+    specs = [(G.grid(30, 40), 40), (G.tree_plus(900, 3), 30), (G.rgg(1200, 5, 8.0), 50), (G.rgg(2500, 17, 8.0), 60)]
+
+    def run():
+        pool, slots = _pool_with(specs, warm=1)
+        pool.set_tol(slots[2], 1e-3)
+        outs = []
+        for rep in range(4):
+            pool.sweep(slots, 9)
+            outs.append([pool.export(s, ssm.POOL_X32).copy() for s in slots])
+            pool.sweep(slots[:2], 5)
+            torch.cuda.synchronize()
+            outs.append([pool.export(s, ssm.POOL_X32).copy() for s in slots])
+        outs.append([np.array(pool.stress(slots)), np.array(pool.stopped(slots[2:3]))])
+        pool.close()
+        return outs
+
+    captured = run()
+    with ssm.variants(pool_graph=-1):
+        direct = run()
+    for step, (a, b) in enumerate(zip(captured, direct)):
+        for q, (x, y) in enumerate(zip(a, b)):
+            assert np.array_equal(x, y), (step, q)
+
+
 def test_pool_admission_and_failures():
     pool = ssm.Pool(4 << 20)
     used0, cap = pool.usage()

@@ -413,7 +413,12 @@ constexpr int kStopBlocks = 512;  // blocks of the stop test's moments (partials
 struct SweepPlan {
     int grid = 1, block = 256, split = 4, cpb = 4, mode = kTableGlobal;
     size_t lds = 0;
+    bool nt = false;  // non-temporal distance loads
 };
+
+// Distance streams above half the MALL (256 MB on MI355X) are read with
+// non-temporal loads (sweep_f32.h).
+constexpr size_t kStreamNtBytes = 128u << 20;
 
 template <typename DT, int VEC, int SPLIT, int CPB, int MODE>
 static void launch_f32(const SweepPlan& pl, hipStream_t s, const ssm_csr* g, const ssm_terms* t,
@@ -423,7 +428,8 @@ static void launch_f32(const SweepPlan& pl, hipStream_t s, const ssm_csr* g, con
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds);
     hipLaunchKernelGGL((k_sweep_f32<DT, VEC, SPLIT, CPB, MODE>), dim3(pl.grid), dim3(64 * SPLIT * CPB), pl.lds, s,
                        t->n, t->kpad, t->W, t->delta_max + 1, g->row_ptr, g->col_idx, xo, xn, (const uint4*)t->dpk,
-                       pc, pc_next, t->prank, t->wt2, t->Hf, t->invd, t->den32, t->seg_range, t->seg_sum, t->stopw);
+                       pc, pc_next, t->prank, t->wt2, t->Hf, t->invd, t->den32, t->seg_range, t->seg_sum, t->stopw,
+                       pl.nt);
 }
 
 template <typename DT, int VEC, int SPLIT, int CPB>
@@ -513,6 +519,7 @@ static SweepPlan shape_f32(const ssm_terms* t, int mode, size_t tab, int split, 
     const int fit = std::max(1, (int)((160 * 1024) / std::max<size_t>(pl.lds, 1)));
     const long long groups = div_up(div_up(t->n, 64), pl.cpb);
     pl.grid = (int)std::max<long long>(1, std::min(groups, (long long)num_cus() * std::min(bpc, fit)));
+    pl.nt = (size_t)t->n * t->kpad * t->dbytes > kStreamNtBytes;
     return pl;
 }
 

@@ -331,7 +331,10 @@ ssm_status ssm_pool_prepare(ssm_pool* p, int32_t count, const int32_t* slots_hos
  * listed ready slot, never past its sweep count: one launch per sweep covers
  * all of them.  The quantum (its sweeps and stop tests) is one HIP graph,
  * captured once per rounded (chunks, graphs, sweeps, LDS) shape and
- * replayed; the kernels take the real counts from the staged header.
+ * replayed; the kernels take the real counts from the staged header.  The
+ * sweep runs a block per 256-node chunk or a persistent grid over the
+ * chunks: the first call of a shape class times both (its first four sweeps)
+ * and keeps the faster; the layouts do not depend on the choice.
  * Asynchronous; a later call that reads a slot (stress, layout, export,
  * remove) waits for it. */
 ssm_status ssm_pool_sweep(ssm_pool* p, int32_t count, const int32_t* slots_host, int32_t iters,
@@ -411,7 +414,9 @@ void ssm_release_cache(void);
  *   sssp_nearfar -1 (plain rounds), sssp_band N,
  *   ell_width 8|16|32 (slots per padded adjacency row in BFS and selection),
  *   pool_graph -1 (ssm_pool_sweep launches each kernel instead of replaying
- *   a captured HIP graph of the quantum).
+ *   a captured HIP graph of the quantum), pool_persist 1|-1 (the pooled
+ *   sweep on a persistent grid, or a block per chunk, instead of the timed
+ *   choice).
  * SSM_E_INVAL for an unknown name. */
 ssm_status ssm_set_variant(const char* name, int32_t value);
 

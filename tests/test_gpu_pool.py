@@ -142,7 +142,8 @@ def test_pool_captured_quanta_match_direct_launches():
     same quanta launched kernel by kernel, bit for bit, after every replay:
     the same shapes again and again (replays of one graph), another shape in
     between, a graph with the stop test, exports (synchronizing reads)
-    between the replays."""
+    between the replays.  The same holds for either sweep schedule (a block
+    per chunk, a persistent grid), captured or not."""
     specs = [(G.grid(30, 40), 40), (G.tree_plus(900, 3), 30), (G.rgg(1200, 5, 8.0), 50), (G.rgg(2500, 17, 8.0), 60)]
 
     def run():
@@ -160,11 +161,13 @@ def test_pool_captured_quanta_match_direct_launches():
         return outs
 
     captured = run()
-    with ssm.variants(pool_graph=-1):
-        direct = run()
-    for step, (a, b) in enumerate(zip(captured, direct)):
-        for q, (x, y) in enumerate(zip(a, b)):
-            assert np.array_equal(x, y), (step, q)
+    for v in ({"pool_graph": -1}, {"pool_persist": 1}, {"pool_persist": -1}, {"pool_persist": 1, "pool_graph": -1}):
+        say("variant", v)
+        with ssm.variants(**v):
+            other = run()
+        for step, (a, b) in enumerate(zip(captured, other)):
+            for q, (x, y) in enumerate(zip(a, b)):
+                assert np.array_equal(x, y), (v, step, q)
 
 
 def test_pool_admission_and_failures():

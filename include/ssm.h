@@ -411,6 +411,8 @@ void ssm_release_cache(void);
  *   sweep otherwise times its shapes on the first loop of at least 24
  *   sweeps per graph shape and keeps the fastest),
  *   sweep_perm -1|2 (caller's node order, always reorder),
+ *   sweep_f64_terms -1 (FP64 sweeps of small graphs one thread per node
+ *   instead of a lane group per node; same result),
  *   sssp_nearfar -1 (plain rounds), sssp_band N,
  *   ell_width 8|16|32 (slots per padded adjacency row in BFS and selection),
  *   pool_graph -1 (ssm_pool_sweep launches each kernel instead of replaying

@@ -102,6 +102,110 @@ __global__ __launch_bounds__(256) void k_sweep_f64(int n, int kpad, int W, const
     }
 }
 
+// The same FP64 sweep for small graphs, where one thread per node leaves most
+// of the device idle and each node's chain of square roots and divisions sets
+// the time: a group of kF64Lanes lanes evaluates a node's terms in parallel
+// (neighbour j by lane j mod G, pivot rank t by lane t mod G), each term's
+// value (the neighbour vote, or w times the pivot vote; exactly 0 for a
+// neighbour at distance zero and a pivot rank with d < 2) into LDS; then the
+// group's first lane adds them in k_sweep_f64's order (neighbours in CSR
+// order, x_i once per neighbour at distance zero, pivot ranks ascending).
+// Adding an exact 0 changes no partial sum (a sum started at +0 never becomes
+// -0), so the result is k_sweep_f64's bit for bit.  Needs degree <=
+// kHeavyDegree (no heavy rows) and kpad <= kF64MaxK.
+constexpr int kF64Lanes = 16;
+constexpr int kF64TermsMaxN = 65536;
+constexpr int kF64MaxK = 128;
+constexpr int kF64Nodes = 256 / kF64Lanes;  // nodes per 256-thread block
+
+template <typename DT, int VEC>
+__global__ __launch_bounds__(256) void k_sweep_f64_terms(int n, int kpad, int W, const int* __restrict__ rp,
+                                                         const int* __restrict__ ci,
+                                                         const double2* __restrict__ xo,
+                                                         double2* __restrict__ xn, const uint4* __restrict__ dpk,
+                                                         const int* __restrict__ piv,
+                                                         const double* __restrict__ wt,
+                                                         const double* __restrict__ den,
+                                                         const int* __restrict__ stop) {
+#pragma clang fp contract(off)
+    if (stop[0]) return;  // the sweep loop has met its stop test (uniform over the grid)
+    extern __shared__ double2 sm[];
+    const int cap = kHeavyDegree + kpad;                 // term slots per node
+    double2* sP = sm;                                    // [kpad]
+    double2* sT = sm + kpad;                             // [kF64Nodes][cap]
+    int* sZero = (int*)(sT + (size_t)kF64Nodes * cap);  // [kF64Nodes]
+    for (int t = threadIdx.x; t < kpad; t += blockDim.x) sP[t] = xo[piv[t]];
+    const int grp = threadIdx.x / kF64Lanes, lane = threadIdx.x % kF64Lanes;
+    double2* T = sT + (size_t)grp * cap;
+    for (int i0 = blockIdx.x * kF64Nodes; i0 < n; i0 += gridDim.x * kF64Nodes) {  // uniform over the block
+        if (lane == 0) sZero[grp] = 0;
+        __syncthreads();  // pivot coordinates staged; the previous nodes' terms read
+        const int i = i0 + grp;
+        double xi = 0.0, yi = 0.0;
+        int e0 = 0, deg = 0;
+        if (i < n) {
+            const double2 xv = xo[i];
+            xi = xv.x;
+            yi = xv.y;
+            e0 = rp[i];
+            deg = rp[i + 1] - e0;
+            for (int j = lane; j < deg; j += kF64Lanes) {
+                const double2 xj = xo[ci[e0 + j]];
+                double dx = xi - xj.x, dy = yi - xj.y;
+                double r = sqrt(dx * dx + dy * dy);
+                double2 v = make_double2(0.0, 0.0);
+                if (r > 0.0)
+                    v = make_double2(xj.x + dx / r, xj.y + dy / r);
+                else
+                    atomicAdd(&sZero[grp], 1);
+                T[j] = v;
+            }
+            for (int t = lane; t < kpad; t += kF64Lanes) {
+                Packed<DT, VEC> u;
+                u.v = dpk[(size_t)(t / VEC) * n + i];
+                const int d = (int)u.e[t % VEC];
+                double2 v = make_double2(0.0, 0.0);
+                if (d >= 2) {
+                    const double w = wt[(size_t)t * W + d];
+                    const double2 p = sP[t];
+                    double dx = xi - p.x, dy = yi - p.y;
+                    double r = sqrt(dx * dx + dy * dy);
+                    double vx = p.x, vy = p.y;
+                    if (r > 0.0) {
+                        vx = p.x + (double)d * dx / r;
+                        vy = p.y + (double)d * dy / r;
+                    }
+                    v = make_double2(w * vx, w * vy);
+                }
+                T[kHeavyDegree + t] = v;
+            }
+        }
+        __syncthreads();
+        if (i < n && lane == 0) {
+            double nx = 0.0, ny = 0.0;
+            for (int j = 0; j < deg; ++j) {
+                nx += T[j].x;
+                ny += T[j].y;
+            }
+            for (int z = sZero[grp]; z > 0; --z) {
+                nx += xi;
+                ny += yi;
+            }
+            for (int t = 0; t < kpad; ++t) {
+                nx += T[kHeavyDegree + t].x;
+                ny += T[kHeavyDegree + t].y;
+            }
+            const double dn = den[i];
+            xn[i] = make_double2(nx / dn, ny / dn);
+        }
+    }
+}
+
+// LDS bytes of k_sweep_f64_terms for kpad.
+static size_t f64_terms_lds(int kpad) {
+    return sizeof(double2) * ((size_t)kpad + (size_t)kF64Nodes * (kHeavyDegree + kpad)) + sizeof(int) * kF64Nodes;
+}
+
 // pc[t] = pc[kpad + t] = x[pivots[t]] for every padded rank (padding repeats
 // pivots[0]; the sweeps keep only the real ranks current, the padded ones
 // stay finite and carry zero weight).
@@ -413,7 +517,8 @@ constexpr int kStopBlocks = 512;  // blocks of the stop test's moments (partials
 struct SweepPlan {
     int grid = 1, block = 256, split = 4, cpb = 4, mode = kTableGlobal;
     size_t lds = 0;
-    bool nt = false;  // non-temporal distance loads
+    bool nt = false;         // non-temporal distance loads
+    bool f64_terms = false;  // FP64: k_sweep_f64_terms (small graphs)
 };
 
 // Distance streams above half the MALL (256 MB on MI355X) are read with
@@ -468,6 +573,17 @@ static void dispatch_split(const SweepPlan& pl, hipStream_t s, const ssm_csr* g,
 // writes those of xn into pc_next.
 static void sweep_once(const SweepPlan& pl, ssm_prec p, hipStream_t s, const ssm_csr* g, const ssm_terms* t,
                        const void* xo, void* xn, const float2* pc = nullptr, float2* pc_next = nullptr) {
+    if (p == SSM_FP64 && pl.f64_terms) {
+        if (t->dbytes == 1)
+            hipLaunchKernelGGL((k_sweep_f64_terms<uint8_t, 16>), dim3(pl.grid), dim3(256), pl.lds, s, t->n, t->kpad,
+                               t->W, g->row_ptr, g->col_idx, (const double2*)xo, (double2*)xn,
+                               (const uint4*)t->dpk, t->pivots, t->wtab64, t->den64, t->stopw);
+        else
+            hipLaunchKernelGGL((k_sweep_f64_terms<uint16_t, 8>), dim3(pl.grid), dim3(256), pl.lds, s, t->n, t->kpad,
+                               t->W, g->row_ptr, g->col_idx, (const double2*)xo, (double2*)xn,
+                               (const uint4*)t->dpk, t->pivots, t->wtab64, t->den64, t->stopw);
+        return;
+    }
     if (p == SSM_FP64) {
         if (t->dbytes == 1)
             hipLaunchKernelGGL((k_sweep_f64<uint8_t, 16>), dim3(pl.grid), dim3(pl.block), pl.lds, s, t->n, t->kpad,
@@ -531,6 +647,15 @@ static SweepPlan plan_sweep(const ssm_terms* t, ssm_prec p) {
     if (p == SSM_FP64) {
         SweepPlan pl;
         pl.block = 256;
+        // graphs up to kF64TermsMaxN nodes without heavy rows: a lane group
+        // per node (variant sweep_f64_terms -1: a thread per node)
+        pl.f64_terms = t->n <= kF64TermsMaxN && t->nheavy == 0 && t->kpad <= kF64MaxK &&
+                       variant("sweep_f64_terms") != -1;
+        if (pl.f64_terms) {
+            pl.lds = f64_terms_lds(t->kpad);
+            pl.grid = std::max(1, div_up(t->n, kF64Nodes));
+            return pl;
+        }
         pl.lds = sizeof(double) * 2 * (size_t)t->kpad;
         pl.grid = std::max(1, std::min(div_up(t->n, pl.block), num_cus() * 8));
         return pl;

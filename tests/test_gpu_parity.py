@@ -228,9 +228,14 @@ def test_pivotmds_gram_round_sizes(k):
     assert np.abs(M - Mo).max() <= 1e-12 * np.abs(Mo).max()
 
 
+@pytest.mark.parametrize("form", ["default", "thread-per-node"])
 @pytest.mark.parametrize("g,k", CASES, ids=IDS)
-def test_sweeps_f64_bit_exact(g, k):
-    say("case", g.name, "k", k)
+def test_sweeps_f64_bit_exact(g, k, form, forced):
+    """Both FP64 sweep kernels (a lane group per node for small graphs, the
+    default here; a thread per node) against the oracle, bit for bit."""
+    if form == "thread-per-node":
+        forced("sweep_f64_terms", -1)
+    say("case", g.name, "k", k, form)
     iters = 25
     ref = oracle.preprocess(g.n, g.row_ptr, g.col_idx, k)
     rng = np.random.default_rng(11)

@@ -90,13 +90,23 @@ def percentile(a, q):
 
 
 def cpu_model() -> str:
+    """The host CPU's model name, with its family and model numbers (a
+    virtual machine may report only a generic name)."""
+    info = {}
     try:
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
+            if ":" in line:
+                key, val = (x.strip() for x in line.split(":", 1))
+                if key in ("model name", "cpu family", "model", "stepping") and key not in info:
+                    info[key] = val
+            if len(info) == 4:
+                break
     except OSError:
         pass
-    return "unknown"
+    name = info.get("model name", "unknown")
+    if "cpu family" in info and "model" in info:
+        name += f" (family {info['cpu family']}, model {info['model']}, stepping {info.get('stepping', '?')})"
+    return name
 
 
 def usable_cores() -> int:

@@ -97,17 +97,26 @@ __device__ __forceinline__ int2 queue_get(const int2* lds, const int2* glob, int
     return make_int2(wg_load(g), wg_load(g + 1));
 }
 
-// Row bounds of the frontier entry `q`: stored directly (ROWQ) or looked up
-// from the stored node id (entry.x).
-template <bool ROWQ>
-__device__ __forceinline__ int2 entry_row(int2 q, const int* __restrict__ rp, int n) {
-    if (ROWQ) return q;
-    return (unsigned)q.x < (unsigned)n ? make_int2(load_agent(&rp[q.x]), load_agent(&rp[q.x + 1])) : make_int2(0, 0);
+// Loads of the read-only CSR arrays: agent-scope (AG) or plain, cached
+// loads.
+template <bool AG>
+__device__ __forceinline__ int csr_load(const int* p) {
+    if (AG) return load_agent(p);
+    return *p;
 }
 
-template <bool ROWQ>
+// Row bounds of the frontier entry `q`: stored directly (ROWQ) or looked up
+// from the stored node id (entry.x).
+template <bool ROWQ, bool AG = true>
+__device__ __forceinline__ int2 entry_row(int2 q, const int* __restrict__ rp, int n) {
+    if (ROWQ) return q;
+    return (unsigned)q.x < (unsigned)n ? make_int2(csr_load<AG>(&rp[q.x]), csr_load<AG>(&rp[q.x + 1]))
+                                       : make_int2(0, 0);
+}
+
+template <bool ROWQ, bool AG = true>
 __device__ __forceinline__ int2 make_entry(int v, const int* __restrict__ rp) {
-    if (ROWQ) return make_int2(load_agent(&rp[v]), load_agent(&rp[v + 1]));
+    if (ROWQ) return make_int2(csr_load<AG>(&rp[v]), csr_load<AG>(&rp[v + 1]));
     return make_int2(v, 0);
 }
 
@@ -122,13 +131,16 @@ __device__ __forceinline__ void queue_put(int2* lds, int2* glob, int idx, int2 v
 // dist[b][*] (pre-set to -1).  Frontier nodes are spread over groups of VW
 // lanes; a node is claimed by compare-and-swap on its distance (workgroup
 // scope: the row belongs to this block) and appended to the next frontier
-// with one LDS atomic per wave.  reached[b] = nodes found; *ecc_max = largest
-// eccentricity seen.
-template <int VW, bool ROWQ>
+// with one LDS atomic per wave.  LD picks the loads: 0 = agent-scope loads
+// throughout; 1 = plain (cached) loads of the read-only CSR arrays; 2 = also
+// the visited check as a plain load (a stale "unvisited" costs only a failed
+// swap).  reached[b] = nodes found; *ecc_max = largest eccentricity seen.
+template <int VW, bool ROWQ, int LD>
 __global__ __launch_bounds__(kBfsBlock) void k_bfs_wg(int n, const int* __restrict__ rp,
                                                       const int* __restrict__ ci,
                                                       const int* __restrict__ pivots, int* dist,
                                                       int2* queues, int* reached, int* ecc_max) {
+    constexpr bool AG = LD == 0;
     const int b = blockIdx.x;
     int* D = dist + (size_t)b * n;
     int2* ga = queues + (size_t)b * 2 * n;
@@ -138,7 +150,7 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_wg(int n, const int* __restri
     const int src = pivots[b];
     if (threadIdx.x == 0) {
         D[src] = 0;
-        sqa[0] = make_entry<ROWQ>(src, rp);
+        sqa[0] = make_entry<ROWQ, AG>(src, rp);
         s_len = 1;
         s_tail = 0;
     }
@@ -160,15 +172,16 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_wg(int n, const int* __restri
 #pragma unroll
             for (int q = 0; q < kBfsU; ++q) {
                 const int qi = base + q * ngrp + grp;
-                row[q] = qi < len ? entry_row<ROWQ>(queue_get(lcur, gcur, qi), rp, n) : make_int2(0, 0);
+                row[q] = qi < len ? entry_row<ROWQ, AG>(queue_get(lcur, gcur, qi), rp, n) : make_int2(0, 0);
                 span = max(span, row[q].y - row[q].x);
             }
             for (int j = sub; j < span; j += VW) {
                 int v[kBfsU], seen[kBfsU];
 #pragma unroll
-                for (int q = 0; q < kBfsU; ++q) v[q] = row[q].x + j < row[q].y ? load_agent(&ci[row[q].x + j]) : -1;
+                for (int q = 0; q < kBfsU; ++q) v[q] = row[q].x + j < row[q].y ? csr_load<AG>(&ci[row[q].x + j]) : -1;
 #pragma unroll
-                for (int q = 0; q < kBfsU; ++q) seen[q] = (unsigned)v[q] < (unsigned)n ? wg_load(&D[v[q]]) : 0;
+                for (int q = 0; q < kBfsU; ++q)
+                    seen[q] = (unsigned)v[q] < (unsigned)n ? (LD == 2 ? *(const int*)&D[v[q]] : wg_load(&D[v[q]])) : 0;
                 bool claim[kBfsU];
 #pragma unroll
                 for (int q = 0; q < kBfsU; ++q) {
@@ -183,7 +196,7 @@ __global__ __launch_bounds__(kBfsBlock) void k_bfs_wg(int n, const int* __restri
                 int2 vrow[kBfsU];
 #pragma unroll
                 for (int q = 0; q < kBfsU; ++q)
-                    if (claim[q]) vrow[q] = make_entry<ROWQ>(v[q], rp);
+                    if (claim[q]) vrow[q] = make_entry<ROWQ, AG>(v[q], rp);
 #pragma unroll
                 for (int q = 0; q < kBfsU; ++q) {
                     const int slot = wave_append(claim[q], &s_tail);
@@ -893,12 +906,23 @@ static hipError_t launch_bfs_ell(int W, int pool, int blocks, hipStream_t s, int
 template <int VW>
 static void launch_bfs_wg(int blocks, hipStream_t s, int n, const int* rp, const int* ci,
                           const int* pivots, int* dist, int2* queues, int* reached, int* ecc) {
-    if (variant("bfs_rowq") != 2)  // row bounds in the queue (2 = node ids; tuning)
-        hipLaunchKernelGGL((k_bfs_wg<VW, true>), dim3(blocks), dim3(kBfsBlock), 0, s, n, rp, ci, pivots, dist,
-                           queues, reached, ecc);
+    // Loads (LD of k_bfs_wg): plain CSR loads by default, measured on MI355X
+    // for the 100 rows of a 3.25M-node mesh: 48 -> 44 ms (one row alone 44 ->
+    // 36 ms); tuning: bfs_loads 2 = plain visited checks too, 3 = agent-scope
+    // loads throughout.
+    const int ld = variant("bfs_loads") == 3 ? 0 : variant("bfs_loads") == 2 ? 2 : 1;
+    if (variant("bfs_rowq") == 2)          // tuning: node ids in the queue instead of row bounds
+        hipLaunchKernelGGL((k_bfs_wg<VW, false, 0>), dim3(blocks), dim3(kBfsBlock), 0, s, n, rp, ci, pivots,
+                           dist, queues, reached, ecc);
+    else if (ld == 1)
+        hipLaunchKernelGGL((k_bfs_wg<VW, true, 1>), dim3(blocks), dim3(kBfsBlock), 0, s, n, rp, ci, pivots,
+                           dist, queues, reached, ecc);
+    else if (ld == 2)
+        hipLaunchKernelGGL((k_bfs_wg<VW, true, 2>), dim3(blocks), dim3(kBfsBlock), 0, s, n, rp, ci, pivots,
+                           dist, queues, reached, ecc);
     else
-        hipLaunchKernelGGL((k_bfs_wg<VW, false>), dim3(blocks), dim3(kBfsBlock), 0, s, n, rp, ci, pivots, dist,
-                           queues, reached, ecc);
+        hipLaunchKernelGGL((k_bfs_wg<VW, true, 0>), dim3(blocks), dim3(kBfsBlock), 0, s, n, rp, ci, pivots,
+                           dist, queues, reached, ecc);
 }
 
 ssm_status mssp(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dist,
@@ -1024,7 +1048,8 @@ ssm_status mssp(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dis
         *dmax_out_host = host[k];
         return SSM_OK;
     }
-    // Sources run in batches so that the frontier queues stay bounded.
+    // Sources run in batches so that the frontier queues stay bounded (every
+    // queue entry is written before it is read: no clearing).
     const long long qcap = 1LL << 31;  // queue entries (16 GiB)
     int batch = (int)std::max<long long>(1, std::min<long long>(k, qcap / (2LL * n)));
     int2* queues = nullptr;
@@ -1038,7 +1063,6 @@ ssm_status mssp(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dis
     }
     hipError_t e = hipMemsetAsync(dist, 0xff, sizeof(int) * (size_t)k * n, s);
     if (e == hipSuccess) e = hipMemsetAsync(aux, 0, sizeof(int) * ((size_t)k + 1), s);
-    if (e == hipSuccess) e = hipMemsetAsync(queues, 0, sizeof(int2) * 2 * (size_t)n * batch, s);
     int vw = virtual_warp(g);
     for (int b0 = 0; b0 < k && e == hipSuccess; b0 += batch) {
         int nb = std::min(batch, k - b0);

@@ -169,20 +169,20 @@ __global__ __launch_bounds__(64 * SPLIT * CPB) void k_sweep_f32(
                         ay += hs.y;
                     }
                 } else {
-                    // neighbour votes in CSR order, four gathers in flight
+                    // neighbour votes in CSR order, eight gathers in flight
                     // (unconditional loads: a missing slot reads x_i itself)
-                    for (int e = e0; e < e1; e += 4) {
-                        int j[4];
+                    for (int e = e0; e < e1; e += 8) {
+                        int j[8];
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) {
+                        for (int q = 0; q < 8; ++q) {
                             const int c = ci[min(e + q, e1 - 1)];  // unconditional load
                             j[q] = e + q < e1 ? c : i;
                         }
-                        float2 xj[4];
+                        float2 xj[8];
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) xj[q] = xo[j[q]];
+                        for (int q = 0; q < 8; ++q) xj[q] = xo[j[q]];
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) {
+                        for (int q = 0; q < 8; ++q) {
                             // a missing slot holds x_i: zero displacement, adds exactly 0
                             float dx = xj[q].x - xi.x, dy = xj[q].y - xi.y;
                             float inv = __builtin_amdgcn_rsqf(dx * dx + (dy * dy + tiny));

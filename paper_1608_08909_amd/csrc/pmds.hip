@@ -660,8 +660,22 @@ __device__ __forceinline__ bool eig2_body(int k, const double* __restrict__ M, d
         }
     }
     __syncthreads();
+    // Shift of the REG iteration: Z = (M - sigma I) V (0 until set; see below)
+    __shared__ double s_sigma;
+    if (threadIdx.x == 0) s_sigma = 0.0;
+    __syncthreads();
     auto matvec = [&]() {
         if (REG) {
+            const double sigma = s_sigma;
+            // this lane's entries of v0 and v1, read once (the z stores below
+            // could otherwise force a reload per row)
+            double x0[kEigCols], x1[kEigCols];
+#pragma unroll
+            for (int c = 0; c < kEigCols; ++c) {
+                const int j = lane + kWave * c;
+                x0[c] = j < k ? v0[j] : 0.0;
+                x1[c] = j < k ? v1[j] : 0.0;
+            }
 #pragma unroll
             for (int q = 0; q < kEigRows; ++q) {
                 const int r = w + nw * q;
@@ -672,15 +686,15 @@ __device__ __forceinline__ bool eig2_body(int k, const double* __restrict__ M, d
                         int j = lane + kWave * c;
                         if (j < k) {
                             double mv = mreg[REG ? q : 0][REG ? c : 0];
-                            a0 += mv * v0[j];
-                            a1 += mv * v1[j];
+                            a0 += mv * x0[c];
+                            a1 += mv * x1[c];
                         }
                     }
                     a0 = wave_sum(a0);
                     a1 = wave_sum(a1);
                     if (lane == 0) {
-                        z0[r] = a0;
-                        z1[r] = a1;
+                        z0[r] = sigma != 0.0 ? a0 - sigma * v0[r] : a0;
+                        z1[r] = sigma != 0.0 ? a1 - sigma * v1[r] : a1;
                     }
                 }
             }
@@ -707,98 +721,250 @@ __device__ __forceinline__ bool eig2_body(int k, const double* __restrict__ M, d
         for (int t = threadIdx.x; t < k; t += blockDim.x) s += a[t] * b[t];
         return block_sum(s, red);
     };
-    // normalize v0, orthonormalize v1 against it (start vectors)
-    {
-        double nn = sqrt(dot(v0, v0));
-        for (int t = threadIdx.x; t < k; t += blockDim.x) v0[t] /= nn;
-        __syncthreads();
-        for (int pass = 0; pass < 2; ++pass) {
-            double d = dot(v0, v1);
-            for (int t = threadIdx.x; t < k; t += blockDim.x) v1[t] -= d * v0[t];
-            __syncthreads();
-        }
-        double n1 = sqrt(dot(v1, v1));
-        for (int t = threadIdx.x; t < k; t += blockDim.x) v1[t] /= n1;
-        __syncthreads();
-    }
     int it = 0;
     bool converged = false;
-    double probe_res = -1.0;  // residual at step probe_it (rate test)
-    int probe_it = 0;
-    for (; it < max_iter; ++it) {
-        matvec();
-        double n0 = sqrt(dot(z0, z0));
-        for (int t = threadIdx.x; t < k; t += blockDim.x) z0[t] /= n0;
-        __syncthreads();
-        // Gram-Schmidt twice: once is not enough when z1 is nearly parallel to z0
-        for (int pass = 0; pass < 2; ++pass) {
-            double d01 = dot(z0, z1);
-            for (int t = threadIdx.x; t < k; t += blockDim.x) z1[t] -= d01 * z0[t];
-            __syncthreads();
-        }
-        double n1 = sqrt(dot(z1, z1));
-        // a second column negligible against the first: M has numerical rank 1
-        const bool rank1 = !(n1 > 1e-13 * n0);
-        if (rank1) {
-            // any unit vector orthogonal to z0 will do: keep v1 made orthogonal to z0
-            for (int t = threadIdx.x; t < k; t += blockDim.x) z1[t] = v1[t];
-            __syncthreads();
-            for (int pass = 0; pass < 2; ++pass) {
-                double d = dot(z0, z1);
-                for (int t = threadIdx.x; t < k; t += blockDim.x) z1[t] -= d * z0[t];
-                __syncthreads();
+    if constexpr (REG) {
+        // k <= 256: the vector work of a step runs in wave 0 alone, entry
+        // lane + 64 c of each vector in its registers (zero beyond k), sums
+        // by shuffles; the other waves only join the product Z = M V.  A step
+        // then costs two barriers instead of one pair per block-wide sum.
+        constexpr int E = kEigCols;
+        __shared__ int s_flag;  // 0: go on, 1: converged, 2: the rate test hands over
+        double vr0[E], vr1[E];
+        auto wdot = [&](const double (&x)[E], const double (&y)[E]) {
+            double acc = 0.0;
+#pragma unroll
+            for (int c = 0; c < E; ++c) acc += x[c] * y[c];
+            return wave_sum(acc);
+        };
+        if (w == 0) {
+#pragma unroll
+            for (int c = 0; c < E; ++c) {
+                const int t = lane + kWave * c;
+                vr0[c] = t < k ? v0[t] : 0.0;
+                vr1[c] = t < k ? v1[t] : 0.0;
             }
-            n1 = sqrt(dot(z1, z1));
-        }
-        for (int t = threadIdx.x; t < k; t += blockDim.x) z1[t] /= n1;
-        __syncthreads();
-        // distance of span(Z) from span(V): residual of projecting Z on V
-        // the four projections in one reduction, the two residuals in another
-        double pr[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int t = threadIdx.x; t < k; t += blockDim.x) {
-            pr[0] += v0[t] * z0[t];
-            pr[1] += v1[t] * z0[t];
-            pr[2] += v0[t] * z1[t];
-            pr[3] += v1[t] * z1[t];
-        }
-        block_sum_n(pr, red4);
-        const double p00 = pr[0], p10 = pr[1], p01 = pr[2], p11 = pr[3];
-        double res[2] = {0.0, 0.0};
-        for (int t = threadIdx.x; t < k; t += blockDim.x) {
-            double r0 = z0[t] - p00 * v0[t] - p10 * v1[t];
-            double r1 = z1[t] - p01 * v0[t] - p11 * v1[t];
-            res[0] = fmax(res[0], fabs(r0));
-            res[1] = fmax(res[1], fabs(r1));
-        }
-        block_max_n(res, red4);
-        const double res0 = res[0], res1 = res[1];
-        for (int t = threadIdx.x; t < k; t += blockDim.x) {
-            v0[t] = z0[t];
-            v1[t] = z1[t];
-        }
-        __syncthreads();
-        if (res0 < tol && (res1 < tol || rank1)) {
-            ++it;
-            converged = true;
-            break;
-        }
-        // rate test (values identical in every thread: uniform)
-        if (it + 1 >= kEigProbe && (it + 1 - kEigProbe) % kEigProbeEvery == 0) {
-            const double r = fmax(res0, rank1 ? 0.0 : res1);
-            if (probe_res > 0.0 && r > 0.0) {
-                const double rate = pow(r / probe_res, 1.0 / (double)(it + 1 - probe_it));
-                if (!(rate < 1.0) || (it + 1) + log(tol / r) / log(rate) > (double)max_iter) {
-                    ++it;  // this step is done
-                    break;
+            // normalize v0, orthonormalize v1 against it (start vectors)
+            const double nn = sqrt(wdot(vr0, vr0));
+#pragma unroll
+            for (int c = 0; c < E; ++c) vr0[c] /= nn;
+            for (int pass = 0; pass < 2; ++pass) {
+                const double d = wdot(vr0, vr1);
+#pragma unroll
+                for (int c = 0; c < E; ++c) vr1[c] -= d * vr0[c];
+            }
+            const double n1 = sqrt(wdot(vr1, vr1));
+#pragma unroll
+            for (int c = 0; c < E; ++c) {
+                vr1[c] /= n1;
+                const int t = lane + kWave * c;
+                if (t < k) {
+                    v0[t] = vr0[c];
+                    v1[t] = vr1[c];
                 }
             }
-            probe_res = r;
-            probe_it = it + 1;
+            if (lane == 0) s_flag = 0;
+        }
+        __syncthreads();
+        double probe_res = -1.0;  // residual at step probe_it (rate test; wave 0)
+        int probe_it = 0;
+        bool shifted = false;     // wave 0: the shift has been chosen
+        double sigma_next = 0.0;  // wave 0: the shift, published at the end of its step
+        for (; it < max_iter; ++it) {
+            matvec();
+            if (w == 0) {
+                double zr0[E], zr1[E];
+#pragma unroll
+                for (int c = 0; c < E; ++c) {
+                    const int t = lane + kWave * c;
+                    zr0[c] = t < k ? z0[t] : 0.0;
+                    zr1[c] = t < k ? z1[t] : 0.0;
+                }
+                const double n0 = sqrt(wdot(zr0, zr0));
+#pragma unroll
+                for (int c = 0; c < E; ++c) zr0[c] /= n0;
+                // Gram-Schmidt twice: once is not enough when z1 is nearly parallel to z0
+                for (int pass = 0; pass < 2; ++pass) {
+                    const double d01 = wdot(zr0, zr1);
+#pragma unroll
+                    for (int c = 0; c < E; ++c) zr1[c] -= d01 * zr0[c];
+                }
+                double n1 = sqrt(wdot(zr1, zr1));
+                // a second column negligible against the first: M has numerical rank 1
+                const bool rank1 = !(n1 > 1e-13 * n0);
+                if (rank1) {
+                    // any unit vector orthogonal to z0 will do: v1 made orthogonal to z0
+#pragma unroll
+                    for (int c = 0; c < E; ++c) zr1[c] = vr1[c];
+                    for (int pass = 0; pass < 2; ++pass) {
+                        const double d = wdot(zr0, zr1);
+#pragma unroll
+                        for (int c = 0; c < E; ++c) zr1[c] -= d * zr0[c];
+                    }
+                    n1 = sqrt(wdot(zr1, zr1));
+                }
+#pragma unroll
+                for (int c = 0; c < E; ++c) zr1[c] /= n1;
+                // distance of span(Z) from span(V): residual of projecting Z on V
+                const double p00 = wdot(vr0, zr0), p10 = wdot(vr1, zr0);
+                const double p01 = wdot(vr0, zr1), p11 = wdot(vr1, zr1);
+                double res0 = 0.0, res1 = 0.0;
+#pragma unroll
+                for (int c = 0; c < E; ++c) {
+                    res0 = fmax(res0, fabs(zr0[c] - p00 * vr0[c] - p10 * vr1[c]));
+                    res1 = fmax(res1, fabs(zr1[c] - p01 * vr0[c] - p11 * vr1[c]));
+                }
+                res0 = wave_max(res0);
+                res1 = wave_max(res1);
+#pragma unroll
+                for (int c = 0; c < E; ++c) {
+                    vr0[c] = zr0[c];
+                    vr1[c] = zr1[c];
+                    const int t = lane + kWave * c;
+                    if (t < k) {
+                        v0[t] = zr0[c];
+                        v1[t] = zr1[c];
+                    }
+                }
+                int flag = 0;
+                if (res0 < tol && (res1 < tol || rank1)) {
+                    flag = 1;
+                } else if (it + 1 >= kEigProbe && (it + 1 - kEigProbe) % kEigProbeEvery == 0) {
+                    // rate test (values identical in every lane of wave 0)
+                    const double r = fmax(res0, rank1 ? 0.0 : res1);
+                    bool just_shifted = false;
+                    if (probe_res > 0.0 && r > 0.0) {
+                        double rate = pow(r / probe_res, 1.0 / (double)(it + 1 - probe_it));
+                        // The span converges at the rate (l3 - s) / (l2 - s) of
+                        // the shifted matrix.  M is a Gram matrix (its
+                        // eigenvalues lie in [0, l3] below the top two), so
+                        // s = l3 / 2 keeps the top two dominant and brings a
+                        // slow rate q = l3 / l2 down to q / (2 - q): once,
+                        // from the measured rate and the second column's
+                        // norm (about l2), for rates above 1/2.
+                        if (!shifted && rate > 0.5 && rate < 1.0 && !rank1 && n1 > 0.0) {
+                            shifted = just_shifted = true;
+                            const double l3 = rate * n1;
+                            sigma_next = 0.5 * l3;
+                            rate = rate / (2.0 - rate);
+                        }
+                        if (!(rate < 1.0) || (it + 1) + log(tol / r) / log(rate) > (double)max_iter) flag = 2;
+                    }
+                    // after the shift the next probe starts a new measurement
+                    probe_res = just_shifted ? -1.0 : r;
+                    probe_it = it + 1;
+                }
+                if (lane == 0) {
+                    s_flag = flag;
+                    if (flag == 0 && sigma_next != 0.0 && s_sigma == 0.0) s_sigma = sigma_next;
+                }
+            }
+            __syncthreads();
+            const int flag = s_flag;  // uniform
+            if (flag == 1) {
+                ++it;
+                converged = true;
+                break;
+            }
+            if (flag == 2) {
+                ++it;  // this step is done
+                break;
+            }
+        }
+    } else {
+        // normalize v0, orthonormalize v1 against it (start vectors)
+        {
+            double nn = sqrt(dot(v0, v0));
+            for (int t = threadIdx.x; t < k; t += blockDim.x) v0[t] /= nn;
+            __syncthreads();
+            for (int pass = 0; pass < 2; ++pass) {
+                double d = dot(v0, v1);
+                for (int t = threadIdx.x; t < k; t += blockDim.x) v1[t] -= d * v0[t];
+                __syncthreads();
+            }
+            double n1 = sqrt(dot(v1, v1));
+            for (int t = threadIdx.x; t < k; t += blockDim.x) v1[t] /= n1;
+            __syncthreads();
+        }
+        double probe_res = -1.0;  // residual at step probe_it (rate test)
+        int probe_it = 0;
+        for (; it < max_iter; ++it) {
+            matvec();
+            double n0 = sqrt(dot(z0, z0));
+            for (int t = threadIdx.x; t < k; t += blockDim.x) z0[t] /= n0;
+            __syncthreads();
+            // Gram-Schmidt twice: once is not enough when z1 is nearly parallel to z0
+            for (int pass = 0; pass < 2; ++pass) {
+                double d01 = dot(z0, z1);
+                for (int t = threadIdx.x; t < k; t += blockDim.x) z1[t] -= d01 * z0[t];
+                __syncthreads();
+            }
+            double n1 = sqrt(dot(z1, z1));
+            // a second column negligible against the first: M has numerical rank 1
+            const bool rank1 = !(n1 > 1e-13 * n0);
+            if (rank1) {
+                // any unit vector orthogonal to z0 will do: keep v1 made orthogonal to z0
+                for (int t = threadIdx.x; t < k; t += blockDim.x) z1[t] = v1[t];
+                __syncthreads();
+                for (int pass = 0; pass < 2; ++pass) {
+                    double d = dot(z0, z1);
+                    for (int t = threadIdx.x; t < k; t += blockDim.x) z1[t] -= d * z0[t];
+                    __syncthreads();
+                }
+                n1 = sqrt(dot(z1, z1));
+            }
+            for (int t = threadIdx.x; t < k; t += blockDim.x) z1[t] /= n1;
+            __syncthreads();
+            // distance of span(Z) from span(V): residual of projecting Z on V
+            // the four projections in one reduction, the two residuals in another
+            double pr[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int t = threadIdx.x; t < k; t += blockDim.x) {
+                pr[0] += v0[t] * z0[t];
+                pr[1] += v1[t] * z0[t];
+                pr[2] += v0[t] * z1[t];
+                pr[3] += v1[t] * z1[t];
+            }
+            block_sum_n(pr, red4);
+            const double p00 = pr[0], p10 = pr[1], p01 = pr[2], p11 = pr[3];
+            double res[2] = {0.0, 0.0};
+            for (int t = threadIdx.x; t < k; t += blockDim.x) {
+                double r0 = z0[t] - p00 * v0[t] - p10 * v1[t];
+                double r1 = z1[t] - p01 * v0[t] - p11 * v1[t];
+                res[0] = fmax(res[0], fabs(r0));
+                res[1] = fmax(res[1], fabs(r1));
+            }
+            block_max_n(res, red4);
+            const double res0 = res[0], res1 = res[1];
+            for (int t = threadIdx.x; t < k; t += blockDim.x) {
+                v0[t] = z0[t];
+                v1[t] = z1[t];
+            }
+            __syncthreads();
+            if (res0 < tol && (res1 < tol || rank1)) {
+                ++it;
+                converged = true;
+                break;
+            }
+            // rate test (values identical in every thread: uniform)
+            if (it + 1 >= kEigProbe && (it + 1 - kEigProbe) % kEigProbeEvery == 0) {
+                const double r = fmax(res0, rank1 ? 0.0 : res1);
+                if (probe_res > 0.0 && r > 0.0) {
+                    const double rate = pow(r / probe_res, 1.0 / (double)(it + 1 - probe_it));
+                    if (!(rate < 1.0) || (it + 1) + log(tol / r) / log(rate) > (double)max_iter) {
+                        ++it;  // this step is done
+                        break;
+                    }
+                }
+                probe_res = r;
+                probe_it = it + 1;
+            }
         }
     }
     used = it;
     if (!converged) return false;  // uniform: the caller goes on with the block iteration
-    // Rayleigh-Ritz on span(V)
+    // Rayleigh-Ritz on span(V), with M itself
+    if (threadIdx.x == 0) s_sigma = 0.0;
+    __syncthreads();
     matvec();
     double b00 = dot(v0, z0), b11 = dot(v1, z1);
     double b01 = 0.5 * (dot(v0, z1) + dot(v1, z0));

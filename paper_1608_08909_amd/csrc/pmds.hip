@@ -1056,7 +1056,8 @@ __global__ void k_pmds_project(int n, int k, int nwords, const uint4* __restrict
     }
 }
 
-// Per-block partial sums of ||x_i - x_j|| over edges with j > i.
+// Per-block partial sums of ||x_i - x_j|| over edges with j > i; every
+// wave takes an equal share of the arcs (hub rows included).
 __global__ __launch_bounds__(256) void k_pmds_edgelen(int n, const int* __restrict__ rp,
                                                       const int* __restrict__ ci,
                                                       const double2* __restrict__ x,
@@ -1064,13 +1065,13 @@ __global__ __launch_bounds__(256) void k_pmds_edgelen(int n, const int* __restri
     double s = 0.0;
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int nwaves = gridDim.x * blockDim.x / kWave;
-    for (int i0 = wave * kWave; i0 < n; i0 += nwaves * kWave)  // uniform per wave
-        wave_arcs(n, rp, ci, i0, [&](int i, int j) {
-            if (j <= i) return;
-            const double2 xi = x[i], xj = x[j];
-            double dx = xi.x - xj.x, dy = xi.y - xj.y;
-            s += sqrt(dx * dx + dy * dy);
-        });
+    const long long nnz = rp[n];
+    wave_arc_span(n, rp, ci, (int)(nnz * wave / nwaves), (int)(nnz * (wave + 1) / nwaves), [&](int i, int j) {
+        if (j <= i) return;
+        const double2 xi = x[i], xj = x[j];
+        double dx = xi.x - xj.x, dy = xi.y - xj.y;
+        s += sqrt(dx * dx + dy * dy);
+    });
     __shared__ double red[256 / kWave];
     s = block_sum(s, red);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;

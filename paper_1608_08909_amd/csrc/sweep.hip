@@ -414,18 +414,19 @@ __global__ __launch_bounds__(256) void k_stress(int n, int kpad, int W, const in
     __syncthreads();
     const int nwords = kpad / VEC;
     double acc = 0.0;
-    // waves walk chunks of 64 nodes: edge terms (i < j) over the chunk's arcs,
-    // then every node's pivot terms
+    // the edge terms (i < j): every wave an equal share of the arcs; then
+    // the pivot terms: waves walk chunks of 64 nodes
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int nwaves = gridDim.x * blockDim.x / kWave;
+    const long long nnz = rp[n];
+    wave_arc_span(n, rp, ci, (int)(nnz * wave / nwaves), (int)(nnz * (wave + 1) / nwaves), [&](int i, int j) {
+        if (j <= i) return;
+        const double2 xi = as_d2(x[i]), xj = as_d2(x[j]);
+        double dx = xi.x - xj.x, dy = xi.y - xj.y;
+        double r = sqrt(dx * dx + dy * dy);
+        acc += (r - 1.0) * (r - 1.0);
+    });
     for (int i0 = wave * kWave; i0 < n; i0 += nwaves * kWave) {
-        wave_arcs(n, rp, ci, i0, [&](int i, int j) {
-            if (j <= i) return;
-            const double2 xi = as_d2(x[i]), xj = as_d2(x[j]);
-            double dx = xi.x - xj.x, dy = xi.y - xj.y;
-            double r = sqrt(dx * dx + dy * dy);
-            acc += (r - 1.0) * (r - 1.0);
-        });
         const int i = i0 + lane_id();
         if (i >= n) continue;
         const double2 xi = as_d2(x[i]);

@@ -108,4 +108,50 @@ __device__ __forceinline__ void wave_arcs(int n, const int* __restrict__ rp, con
     }
 }
 
+// Calls f(i, j) for every arc e in [a0, a1) of a CSR graph (i = the row of
+// arc e, j = ci[e]), 64 arcs per pass: lane l takes arcs a0 + l, a0 + l + 64,
+// ... in that order.  The row of a0 comes from a binary search over rp; a
+// pass then finds its arcs' rows among the next 64 row starts (lane q holds
+// the start of row r + 1 + q), so splitting [0, nnz) evenly over waves
+// balances the work however long the rows are.  Call with every lane of the
+// wave active.
+template <typename F>
+__device__ __forceinline__ void wave_arc_span(int n, const int* __restrict__ rp, const int* __restrict__ ci, int a0,
+                                              int a1, F f) {
+    if (a0 >= a1) return;  // uniform
+    const int lane = lane_id();
+    int lo = 0, hi = n;  // the last row whose start is at most a0
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (rp[mid] <= a0) lo = mid;
+        else hi = mid;
+    }
+    int r = lo;
+    for (int eb = a0; eb < a1; eb += kWave) {  // uniform
+        const int q = r + 1 + lane;
+        const int st = q <= n ? rp[q] : 0x7fffffff;  // start of row r + 1 + lane (non-decreasing)
+        const int e = eb + lane;
+        int cnt = 0;  // row starts among these 64 that are at most e
+#pragma unroll
+        for (int step = kWave / 2; step > 0; step >>= 1) {
+            const int c = cnt + step;
+            if (__shfl(st, c - 1) <= e) cnt = c;
+        }
+        const int st_last = __shfl(st, kWave - 1);  // every lane takes part in the shuffle
+        if (cnt == kWave - 1 && st_last <= e) cnt = kWave;
+        int row = r + cnt;
+        if (cnt == kWave && e < a1) {  // more than 64 rows begin in this pass (empty rows): search rp
+            int l2 = r + kWave, h2 = n;
+            while (h2 - l2 > 1) {
+                const int mid = (l2 + h2) >> 1;
+                if (rp[mid] <= e) l2 = mid;
+                else h2 = mid;
+            }
+            row = l2;
+        }
+        if (e < a1) f(row, ci[e]);
+        r = __shfl(row, min(kWave, a1 - eb) - 1);  // the row of this pass's last arc
+    }
+}
+
 }  // namespace ssm

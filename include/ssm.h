@@ -404,7 +404,8 @@ void ssm_release_cache(void);
  *   bfs_ell 2|3|4 (CSR rows; padded rows with the distance row as visited
  *   set, with or without a read before the swap), bfs_rowq 2,
  *   bfs_loads 2|3 (CSR rows: plain visited checks as well as plain CSR
- *   loads, or agent-scope loads throughout),
+ *   loads, or agent-scope loads throughout), bfs_grp -1 (CSR rows on one
+ *   workgroup each instead of two),
  *   bfs_lanes 2..64, msbfs 1, msbfs_budget N,
  *   region_mode 1|2, km_chunk 32|40|48|56|64,
  *   sweep_mode 1|2 (LDS histograms, global table), sweep_split 1|2|4,

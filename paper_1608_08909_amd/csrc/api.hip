@@ -136,7 +136,7 @@ const char* const kVariantNames[] = {
     "bfs_lanes",   "bfs_rowq",      "bfs_ell",       "msbfs",         "msbfs_budget", "select_threads",
     "select_wave", "select_rowq",   "select_pre",    "select_blocks", "select_mode",  "select_ell", "select_hyb",
     "select_m8",   "region_mode",   "km_chunk",      "sweep_perm",    "sweep_mode",   "sweep_split",
-    "sweep_blocks_per_cu", "sweep_waves", "sweep_tune", "sssp_nearfar", "sssp_band", "ell_width", "pool_graph", "pool_persist", "sweep_f64_terms", "bfs_loads"};
+    "sweep_blocks_per_cu", "sweep_waves", "sweep_tune", "sssp_nearfar", "sssp_band", "ell_width", "pool_graph", "pool_persist", "sweep_f64_terms", "bfs_loads", "bfs_grp"};
 }  // namespace
 
 int variant(const char* name, int unset) {

@@ -925,6 +925,13 @@ static void launch_bfs_wg(int blocks, hipStream_t s, int n, const int* rp, const
                            dist, queues, reached, ecc);
 }
 
+// Rows on kBfsGrp workgroups each (k_bfs_grp, defined below).
+constexpr int kBfsGrp = 2;
+hipError_t launch_bfs_grp(int vw, int rows, hipStream_t s, int n, const int* rp, const int* ci, const int* pivots,
+                          int* dist, int2* queues, int* ctl, unsigned long long* bars, int* reached, int* ecc,
+                          int* status);
+int bfs_grp_fits(int rows);
+
 ssm_status mssp(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dist,
                 int32_t* dmax_out_host, hipStream_t s) {
     const int n = g->n;
@@ -1064,11 +1071,38 @@ ssm_status mssp(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dis
     hipError_t e = hipMemsetAsync(dist, 0xff, sizeof(int) * (size_t)k * n, s);
     if (e == hipSuccess) e = hipMemsetAsync(aux, 0, sizeof(int) * ((size_t)k + 1), s);
     int vw = virtual_warp(g);
+    // kBfsGrp workgroups per row when every row's blocks get CUs of their own
+    // (measured on MI355X: the 100 rows of a 3.25M-node mesh 44 -> 36 ms, its
+    // slowest row alone 40 -> 29 ms; tuning: bfs_grp -1 = one workgroup)
+    const bool grp = variant("bfs_grp") != -1 && (long long)batch * kBfsGrp <= num_cus() && bfs_grp_fits(batch);
+    int* gctl = nullptr;  // per row: 32 ints (frontier counters), then 16 u64 (barrier) per row, then status
+    if (grp && e == hipSuccess) {
+        st = salloc((void**)&gctl, sizeof(int) * (size_t)batch * 32 + sizeof(unsigned long long) * (size_t)batch * 16 + 256);
+        if (st != SSM_OK) {
+            (void)hipStreamSynchronize(s);
+            sfree(queues);
+            sfree(aux);
+            return st;
+        }
+    }
+    int hstatus = 0;
     for (int b0 = 0; b0 < k && e == hipSuccess; b0 += batch) {
         int nb = std::min(batch, k - b0);
         int* D = dist + (size_t)b0 * n;
         int* reached = aux + b0;
         int* ecc = aux + k;
+        if (grp) {
+            unsigned long long* gbars = (unsigned long long*)(gctl + (size_t)batch * 32);
+            int* gstatus = (int*)(gbars + (size_t)batch * 16);
+            e = hipMemsetAsync(gbars, 0, sizeof(unsigned long long) * (size_t)batch * 16 + 256, s);
+            if (e == hipSuccess)
+                e = launch_bfs_grp(vw, nb, s, n, g->row_ptr, g->col_idx, pivots + b0, D, queues, gctl, gbars, reached,
+                                   ecc, gstatus);
+            if (e == hipSuccess) e = hipMemcpyAsync(&hstatus, gstatus, sizeof(int), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e == hipSuccess && hstatus) break;
+            continue;
+        }
         switch (vw) {
             case 2: launch_bfs_wg<2>(nb, s, n, g->row_ptr, g->col_idx, pivots + b0, D, queues, reached, ecc); break;
             case 4: launch_bfs_wg<4>(nb, s, n, g->row_ptr, g->col_idx, pivots + b0, D, queues, reached, ecc); break;
@@ -1085,7 +1119,9 @@ ssm_status mssp(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dis
     (void)hipStreamSynchronize(s);  // idle before the scratch is reused (also after an error)
     sfree(queues);
     sfree(aux);
+    if (gctl) sfree(gctl);
     if (e != hipSuccess) return hip_fail(e, "multi-source BFS");
+    if (hstatus) return fail(SSM_E_DEVICE, "multi-source BFS: a row's barrier did not fill and was aborted");
     for (int t = 0; t < k; ++t)
         if (host[t] != n) return fail(SSM_E_DISCONNECTED, "graph is not connected (a BFS missed nodes)");
     *dmax_out_host = host[k];
@@ -1322,12 +1358,12 @@ __device__ __forceinline__ int4 load_agent4(const int* p) {  // p 16-byte aligne
 constexpr unsigned long long kBarAbort = 1ull << 63;
 constexpr long long kBarPolls = 1ll << 25;
 
-__device__ __forceinline__ bool sync_grid(unsigned long long* bar, unsigned long long& epoch) {
+__device__ __forceinline__ bool sync_count(unsigned long long* bar, unsigned long long& epoch, int blocks) {
     __shared__ int s_go;
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
-        epoch += gridDim.x;
+        epoch += blocks;
         unsigned long long v = __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
         long long polls = 0;
         while ((v & kBarAbort) == 0 && (long long)(v - epoch) < 0) {
@@ -1341,6 +1377,11 @@ __device__ __forceinline__ bool sync_grid(unsigned long long* bar, unsigned long
     }
     __syncthreads();
     return s_go != 0;
+}
+
+// The barrier over the whole grid (see sync_count).
+__device__ __forceinline__ bool sync_grid(unsigned long long* bar, unsigned long long& epoch) {
+    return sync_count(bar, epoch, gridDim.x);
 }
 
 // Appends the u[j] with ok[j] (j < 4) to a global frontier with agent-scope
@@ -1362,6 +1403,161 @@ __device__ __forceinline__ void append4_agent(const int (&u)[4], const bool (&ok
         if (ok[j]) store_agent(&nxt[at + mask_rank(mk[j])], u[j]);
         at += __popcll(mk[j]);
     }
+}
+
+// ---------------------------------------- one BFS per kBfsGrp workgroups
+
+// Rows on kBfsGrp workgroups each (cooperative launch, blocks g*kBfsGrp ..
+// g*kBfsGrp + kBfsGrp - 1 for source g): the level-synchronous BFS of
+// k_bfs_wg, its frontier (row bounds, as there) shared by the row's blocks
+// through agent-scope loads and stores in the global queues, a claim by an
+// agent-scope compare-and-swap on the distance, one reservation per wave on
+// the row's frontier counter (ctl + 32 g: three level slots) and a barrier
+// of the row's blocks per level (bars + 16 g).  A barrier that never fills
+// sets status[0] and both blocks leave.
+
+__device__ __forceinline__ int2 load_agent_int2(const int2* p) {
+    const unsigned long long v =
+        __hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return make_int2((int)(unsigned)v, (int)(unsigned)(v >> 32));
+}
+
+__device__ __forceinline__ void store_agent_int2(int2* p, int2 v) {
+    store_agent((unsigned long long*)p, (unsigned long long)(unsigned)v.x | ((unsigned long long)(unsigned)v.y << 32));
+}
+
+template <int VW>
+__global__ __launch_bounds__(kBfsBlock) void k_bfs_grp(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                       const int* __restrict__ pivots, int* dist, int2* queues,
+                                                       int* ctl, unsigned long long* bars, int* reached,
+                                                       int* ecc_max, int* status) {
+    const int g = blockIdx.x / kBfsGrp, part = blockIdx.x % kBfsGrp;
+    int* D = dist + (size_t)g * n;
+    int2* cur = queues + (size_t)g * 2 * n;
+    int2* nxt = cur + n;
+    int* c = ctl + 32 * g;
+    unsigned long long* bar = bars + 16 * g;
+    __shared__ int s_found;
+    unsigned long long epoch = 0;
+    const int src = pivots[g];
+    if (threadIdx.x == 0) s_found = 0;
+    if (part == 0 && threadIdx.x == 0) {
+        store_agent(&D[src], 0);
+        store_agent_int2(&cur[0], make_int2(rp[src], rp[src + 1]));
+        store_agent(&c[0], 1);
+        store_agent(&c[1], 0);
+        store_agent(&c[2], 0);
+    }
+    if (!sync_count(bar, epoch, kBfsGrp)) {
+        if (threadIdx.x == 0) store_agent(&status[0], 1);
+        return;
+    }
+    const int sub = threadIdx.x % VW, grp = threadIdx.x / VW, ngrp = blockDim.x / VW;
+    const int gg = part * ngrp + grp, ngg = kBfsGrp * ngrp;  // this lane group among the row's groups
+    int level = 0;
+    for (;;) {
+        const int len = min(load_agent(&c[level % 3]), n);
+        if (len == 0) break;
+        int* tail = &c[(level + 1) % 3];
+        if (part == 0 && threadIdx.x == 0) store_agent(&c[(level + 2) % 3], 0);
+        for (int base = 0; base < len; base += ngg * kBfsU) {
+            int2 row[kBfsU];
+            int span = 0;
+#pragma unroll
+            for (int q = 0; q < kBfsU; ++q) {
+                const int qi = base + q * ngg + gg;
+                row[q] = qi < len ? load_agent_int2(&cur[qi]) : make_int2(0, 0);
+                span = max(span, row[q].y - row[q].x);
+            }
+            for (int j = sub; j < span; j += VW) {
+                int v[kBfsU], seen[kBfsU];
+#pragma unroll
+                for (int q = 0; q < kBfsU; ++q) v[q] = row[q].x + j < row[q].y ? ci[row[q].x + j] : -1;
+#pragma unroll
+                for (int q = 0; q < kBfsU; ++q) seen[q] = (unsigned)v[q] < (unsigned)n ? load_agent(&D[v[q]]) : 0;
+                bool claim[kBfsU];
+#pragma unroll
+                for (int q = 0; q < kBfsU; ++q) {
+                    claim[q] = false;
+                    if ((unsigned)v[q] < (unsigned)n && seen[q] < 0) {
+                        int expected = -1;
+                        claim[q] = __hip_atomic_compare_exchange_strong(&D[v[q]], &expected, level + 1,
+                                                                        __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                                        __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+                int2 vrow[kBfsU];
+#pragma unroll
+                for (int q = 0; q < kBfsU; ++q)
+                    if (claim[q]) vrow[q] = make_int2(rp[v[q]], rp[v[q] + 1]);
+                uint64_t mk[kBfsU];
+                int tot = 0;
+#pragma unroll
+                for (int q = 0; q < kBfsU; ++q) {
+                    mk[q] = __ballot(claim[q]);
+                    tot += __popcll(mk[q]);
+                }
+                if (tot > 0) {  // uniform over the wave's active lanes
+                    // the lowest active lane reserves (lane groups leave this
+                    // loop at different times: rows of different lengths)
+                    const int leader = __ffsll((unsigned long long)__ballot(1)) - 1;
+                    int at = 0;
+                    if (lane_id() == leader) {
+                        at = atomicAdd(tail, tot);
+                        atomicAdd(&s_found, tot);
+                    }
+                    at = __shfl(at, leader);
+#pragma unroll
+                    for (int q = 0; q < kBfsU; ++q) {
+                        if (claim[q]) store_agent_int2(&nxt[at + mask_rank(mk[q])], vrow[q]);
+                        at += __popcll(mk[q]);
+                    }
+                }
+            }
+        }
+        if (!sync_count(bar, epoch, kBfsGrp)) {
+            if (threadIdx.x == 0) store_agent(&status[0], 1);
+            return;
+        }
+        int2* t0 = cur;
+        cur = nxt;
+        nxt = t0;
+        ++level;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(&reached[g], s_found + (part == 0 ? 1 : 0));
+        if (part == 0) atomicMax(ecc_max, level - 1);
+    }
+}
+
+template <int VW>
+static hipError_t launch_bfs_grp_w(int rows, hipStream_t s, int n, const int* rp, const int* ci, const int* pivots,
+                                   int* dist, int2* queues, int* ctl, unsigned long long* bars, int* reached,
+                                   int* ecc, int* status) {
+    void* args[] = {&n, &rp, &ci, &pivots, &dist, &queues, &ctl, &bars, &reached, &ecc, &status};
+    return hipLaunchCooperativeKernel((const void*)k_bfs_grp<VW>, dim3(rows * kBfsGrp), dim3(kBfsBlock), args, 0, s);
+}
+
+hipError_t launch_bfs_grp(int vw, int rows, hipStream_t s, int n, const int* rp, const int* ci, const int* pivots,
+                          int* dist, int2* queues, int* ctl, unsigned long long* bars, int* reached, int* ecc,
+                          int* status) {
+    switch (vw) {
+        case 2: return launch_bfs_grp_w<2>(rows, s, n, rp, ci, pivots, dist, queues, ctl, bars, reached, ecc, status);
+        case 4: return launch_bfs_grp_w<4>(rows, s, n, rp, ci, pivots, dist, queues, ctl, bars, reached, ecc, status);
+        case 8: return launch_bfs_grp_w<8>(rows, s, n, rp, ci, pivots, dist, queues, ctl, bars, reached, ecc, status);
+        case 16: return launch_bfs_grp_w<16>(rows, s, n, rp, ci, pivots, dist, queues, ctl, bars, reached, ecc, status);
+        case 32: return launch_bfs_grp_w<32>(rows, s, n, rp, ci, pivots, dist, queues, ctl, bars, reached, ecc, status);
+        default: return launch_bfs_grp_w<64>(rows, s, n, rp, ci, pivots, dist, queues, ctl, bars, reached, ecc, status);
+    }
+}
+
+// Whether rows x kBfsGrp blocks of k_bfs_grp are resident at once.
+int bfs_grp_fits(int rows) {
+    int a = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, (const void*)k_bfs_grp<8>, kBfsBlock, 0) != hipSuccess)
+        return 0;
+    return (long long)rows * kBfsGrp <= (long long)a * num_cus();
 }
 
 // Pivots t0 .. t1-1 of max/min sampling in one cooperative launch, over the

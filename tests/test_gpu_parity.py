@@ -99,7 +99,8 @@ VARIANTS = [
     {"select_ell": 2, "select_rowq": 2},
     {"select_ell": 2, "select_rowq": 2, "select_pre": 3},
     {"select_ell": 2, "select_pre": 1},
-    {"bfs_rowq": 2, "bfs_ell": 2}, {"bfs_ell": 2}, {"bfs_ell": 2, "bfs_loads": 3}, {"bfs_ell": 2, "bfs_loads": 2},
+    {"bfs_rowq": 2, "bfs_ell": 2, "bfs_grp": -1}, {"bfs_ell": 2}, {"bfs_ell": 2, "bfs_grp": -1},
+    {"bfs_ell": 2, "bfs_loads": 3, "bfs_grp": -1}, {"bfs_ell": 2, "bfs_loads": 2, "bfs_grp": -1},
     {"bfs_ell": 3}, {"bfs_ell": 4}, {"msbfs": 1},
     {"msbfs": 1, "msbfs_budget": 3},
     {"region_mode": 1}, {"region_mode": 2}, {"bfs_lanes": 2}, {"bfs_lanes": 64},
@@ -141,9 +142,10 @@ def test_select_beyond_byte_copy(g, k, mode, forced):
     assert np.array_equal(ssm.select_pivots(dg, k, 0).cpu().numpy(), piv_r)
 
 
-@pytest.mark.parametrize("env", [{}, {"msbfs": 1}, {"bfs_ell": 2}, {"bfs_ell": 2, "bfs_loads": 3},
-                                 {"bfs_ell": 2, "bfs_loads": 2}, {"bfs_ell": 3}, {"bfs_ell": 4}],
-                         ids=["default", "bitparallel", "csr", "csr-agent", "csr-plain-checks", "ell-global",
+@pytest.mark.parametrize("env", [{}, {"msbfs": 1}, {"bfs_ell": 2}, {"bfs_ell": 2, "bfs_grp": -1},
+                                 {"bfs_ell": 2, "bfs_loads": 3, "bfs_grp": -1},
+                                 {"bfs_ell": 2, "bfs_loads": 2, "bfs_grp": -1}, {"bfs_ell": 3}, {"bfs_ell": 4}],
+                         ids=["default", "bitparallel", "csr", "csr-one-block", "csr-agent", "csr-plain-checks", "ell-global",
                               "ell-global-noread"])
 def test_bfs_large_frontiers(env, forced):
     """Frontiers beyond the LDS queue and more long rows per level than the

@@ -119,7 +119,7 @@ def usable_cores() -> int:
     return max(1, n)
 
 
-def cpu_baseline(g, k, iters, sweeps_one=1, sweeps_all=3, pmds_work=4e9):
+def cpu_baseline(g, k, iters, sweeps_one=1, sweeps_all=3, pmds_work=1e9):
     """The CPU oracle on the same graph (the oracle as it stands, untuned).
 
     Preprocessing (max/min, BFS, regions, weights; serial in the oracle) runs

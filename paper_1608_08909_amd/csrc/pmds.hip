@@ -309,8 +309,15 @@ __device__ __forceinline__ double splitmix_uniform(unsigned long long& state) {
 }
 
 constexpr int kEigThreads = 1024;
-constexpr int kEigRows = 16;  // rows of M per wave kept in registers (k <= 256)
-constexpr int kEigCols = 4;   // columns per lane (k <= 256)
+// M in registers for k <= KR (KR = 128 or 256): KR / 16 rows of M per wave,
+// KR / 64 columns per lane; at KR = 256 the copy outgrows the 128 registers
+// a thread of a 1024-thread workgroup has and partly spills, so graphs with
+// k <= 128 take the smaller copy.
+constexpr int kEigRegMax = 256;
+__host__ __device__ constexpr int eig_reg_rows(int KR) { return KR > 0 ? KR / 16 : 1; }
+__host__ __device__ constexpr int eig_reg_cols(int KR) { return KR > 0 ? KR / 64 : 1; }
+// The register form for a k x k Gram matrix: 128, 256, or 0 (M in global memory).
+__host__ __device__ constexpr int eig_reg_form(int k) { return k <= 128 ? 128 : k <= kEigRegMax ? 256 : 0; }
 // Steps of the two-vector iteration before the block iteration takes over.
 // From step 32 on, every 16 steps, the residual's rate of decrease predicts
 // the step at which it would converge; if that lies beyond kEigFast (or the
@@ -631,9 +638,11 @@ __device__ __forceinline__ void block_max_n(double (&v)[N], double* scratch) {
     }
 }
 
-template <bool REG>
+template <int KR>
 __device__ __forceinline__ bool eig2_body(int k, const double* __restrict__ M, double tol, int max_iter,
                                           double* __restrict__ out, int* __restrict__ iters, int& used) {
+    constexpr bool REG = KR > 0;
+    constexpr int ER = eig_reg_rows(KR), EC = eig_reg_cols(KR);
     extern __shared__ double sh[];
     double* v0 = sh;
     double* v1 = sh + k;
@@ -642,12 +651,12 @@ __device__ __forceinline__ bool eig2_body(int k, const double* __restrict__ M, d
     __shared__ double red[kEigThreads / kWave];
     __shared__ double red4[4 * (kEigThreads / kWave)];
     const int lane = lane_id(), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
-    double mreg[REG ? kEigRows : 1][REG ? kEigCols : 1];
+    double mreg[REG ? ER : 1][REG ? EC : 1];
     if (REG) {
 #pragma unroll
-        for (int q = 0; q < kEigRows; ++q)
+        for (int q = 0; q < ER; ++q)
 #pragma unroll
-            for (int c = 0; c < kEigCols; ++c) {
+            for (int c = 0; c < EC; ++c) {
                 int r = w + nw * q, j = lane + kWave * c;
                 mreg[REG ? q : 0][REG ? c : 0] = (r < k && j < k) ? M[(size_t)r * k + j] : 0.0;
             }
@@ -669,20 +678,20 @@ __device__ __forceinline__ bool eig2_body(int k, const double* __restrict__ M, d
             const double sigma = s_sigma;
             // this lane's entries of v0 and v1, read once (the z stores below
             // could otherwise force a reload per row)
-            double x0[kEigCols], x1[kEigCols];
+            double x0[EC], x1[EC];
 #pragma unroll
-            for (int c = 0; c < kEigCols; ++c) {
+            for (int c = 0; c < EC; ++c) {
                 const int j = lane + kWave * c;
                 x0[c] = j < k ? v0[j] : 0.0;
                 x1[c] = j < k ? v1[j] : 0.0;
             }
 #pragma unroll
-            for (int q = 0; q < kEigRows; ++q) {
+            for (int q = 0; q < ER; ++q) {
                 const int r = w + nw * q;
                 if (r < k) {  // uniform across the wave
                     double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-                    for (int c = 0; c < kEigCols; ++c) {
+                    for (int c = 0; c < EC; ++c) {
                         int j = lane + kWave * c;
                         if (j < k) {
                             double mv = mreg[REG ? q : 0][REG ? c : 0];
@@ -728,7 +737,7 @@ __device__ __forceinline__ bool eig2_body(int k, const double* __restrict__ M, d
         // lane + 64 c of each vector in its registers (zero beyond k), sums
         // by shuffles; the other waves only join the product Z = M V.  A step
         // then costs two barriers instead of one pair per block-wide sum.
-        constexpr int E = kEigCols;
+        constexpr int E = EC;
         __shared__ int s_flag;  // 0: go on, 1: converged, 2: the rate test hands over
         double vr0[E], vr1[E];
         auto wdot = [&](const double (&x)[E], const double (&y)[E]) {
@@ -1004,12 +1013,12 @@ __device__ __forceinline__ bool eig2_body(int k, const double* __restrict__ M, d
 // The two dominant eigenvectors of M: the two-vector iteration for up to
 // kEigFast steps (fewer when its rate test predicts it would not converge
 // within them), then, if it has not converged, the block iteration.
-template <bool REG>
+template <int KR>
 __device__ __forceinline__ void pmds_eig_body(int k, const double* __restrict__ M, double tol, int max_iter,
                                               double* __restrict__ out, int* __restrict__ iters) {
     const int fast = min(max_iter, kEigFast);
     int used = 0;
-    if (eig2_body<REG>(k, M, tol, fast, out, iters, used)) return;
+    if (eig2_body<KR>(k, M, tol, fast, out, iters, used)) return;
     __syncthreads();
     eigp_body(k, M, tol, max_iter - used, used, out, iters);
 }
@@ -1019,11 +1028,11 @@ __host__ __device__ constexpr size_t eig_lds_bytes(int k) {
     return sizeof(double) * ((size_t)(2 * kEigP + 2) * k + 2 * kEigP * kEigP + kEigP);
 }
 
-template <bool REG>
+template <int KR>
 __global__ __launch_bounds__(kEigThreads) void k_pmds_eig(int k, const double* __restrict__ M, double tol,
                                                          int max_iter, double* __restrict__ out,
                                                          int* __restrict__ iters) {
-    pmds_eig_body<REG>(k, M, tol, max_iter, out, iters);
+    pmds_eig_body<KR>(k, M, tol, max_iter, out, iters);
 }
 
 // x_i = sum over t ascending of C_it V_t (per column), FP64.
@@ -1157,14 +1166,17 @@ ssm_status pivotmds(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* x, hipStre
         hipLaunchKernelGGL(k_pmds_gram_reduce, dim3(std::min(div_up((long long)ntiles * 256, 256), 4096)),
                            dim3(256), 0, s, k, nchunks, ntiles, tiles, part, M);
         const size_t elds = eig_lds_bytes(k);
-        if (k <= kEigRows * (kEigThreads / kWave) && k <= kEigCols * kWave) {
-            hipLaunchKernelGGL(k_pmds_eig<true>, dim3(1), dim3(kEigThreads), elds, s, k, M, 1e-13, 20000, t->eig,
+        if (eig_reg_form(k) == 128) {
+            hipLaunchKernelGGL(k_pmds_eig<128>, dim3(1), dim3(kEigThreads), elds, s, k, M, 1e-13, 20000, t->eig,
+                               t->eig_iters);
+        } else if (eig_reg_form(k) == 256) {
+            hipLaunchKernelGGL(k_pmds_eig<256>, dim3(1), dim3(kEigThreads), elds, s, k, M, 1e-13, 20000, t->eig,
                                t->eig_iters);
         } else {
             if (elds > 64 * 1024)
-                (void)hipFuncSetAttribute((const void*)k_pmds_eig<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                (void)hipFuncSetAttribute((const void*)k_pmds_eig<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                           (int)elds);
-            hipLaunchKernelGGL(k_pmds_eig<false>, dim3(1), dim3(kEigThreads), elds, s, k, M, 1e-13, 20000, t->eig,
+            hipLaunchKernelGGL(k_pmds_eig<0>, dim3(1), dim3(kEigThreads), elds, s, k, M, 1e-13, 20000, t->eig,
                                t->eig_iters);
         }
         double2* xd = (double2*)t->xtmp;
@@ -1272,9 +1284,10 @@ __global__ void k_pool_gram_reduce(const PoolGraph* __restrict__ gs, const int2*
     }
 }
 
+template <int KR>
 __global__ __launch_bounds__(kEigThreads) void k_pool_eig(const PoolGraph* __restrict__ gs) {
     const PoolGraph& g = gs[blockIdx.x];
-    pmds_eig_body<true>(g.k, g.M, 1e-13, 20000, g.eig, g.info + 4);
+    pmds_eig_body<KR>(g.k, g.M, 1e-13, 20000, g.eig, g.info + 4);
 }
 
 // Per graph: x64[0] = C V (ranks ascending), then the uniform rescale that
@@ -1355,7 +1368,10 @@ hipError_t pool_pivotmds(const PoolGraph* gs, int count, const int4* gram_items,
         hipLaunchKernelGGL(k_pool_gram<8>, dim3(ngram), dim3(256), gram_lds_bytes<8>(kp_max), s, gs, gram_items,
                            tiles);
     hipLaunchKernelGGL(k_pool_gram_reduce, dim3(32, count), dim3(256), 0, s, gs, tiles);
-    hipLaunchKernelGGL(k_pool_eig, dim3(count), dim3(kEigThreads), eig_lds_bytes(k_max), s, gs);
+    if (eig_reg_form(k_max) == 128)
+        hipLaunchKernelGGL(k_pool_eig<128>, dim3(count), dim3(kEigThreads), eig_lds_bytes(k_max), s, gs);
+    else
+        hipLaunchKernelGGL(k_pool_eig<256>, dim3(count), dim3(kEigThreads), eig_lds_bytes(k_max), s, gs);
     hipLaunchKernelGGL(k_pool_project, dim3(count), dim3(1024), 0, s, gs);
     return hipGetLastError();
 }
@@ -1543,13 +1559,15 @@ ssm_status pivotmds_w(const ssm_csr* g, const double* len, int k, const double* 
         hipLaunchKernelGGL(k_pmds_gram_reduce, dim3(std::min(div_up((long long)ntiles * 256, 256), 4096)), dim3(256),
                            0, s, k, nchunks, ntiles, tiles, part, M);
         const size_t elds = eig_lds_bytes(k);
-        if (k <= kEigRows * (kEigThreads / kWave) && k <= kEigCols * kWave) {
-            hipLaunchKernelGGL(k_pmds_eig<true>, dim3(1), dim3(kEigThreads), elds, s, k, M, 1e-13, 20000, eig, its);
+        if (eig_reg_form(k) == 128) {
+            hipLaunchKernelGGL(k_pmds_eig<128>, dim3(1), dim3(kEigThreads), elds, s, k, M, 1e-13, 20000, eig, its);
+        } else if (eig_reg_form(k) == 256) {
+            hipLaunchKernelGGL(k_pmds_eig<256>, dim3(1), dim3(kEigThreads), elds, s, k, M, 1e-13, 20000, eig, its);
         } else {
             if (elds > 64 * 1024)
-                (void)hipFuncSetAttribute((const void*)k_pmds_eig<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                (void)hipFuncSetAttribute((const void*)k_pmds_eig<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                           (int)elds);
-            hipLaunchKernelGGL(k_pmds_eig<false>, dim3(1), dim3(kEigThreads), elds, s, k, M, 1e-13, 20000, eig, its);
+            hipLaunchKernelGGL(k_pmds_eig<0>, dim3(1), dim3(kEigThreads), elds, s, k, M, 1e-13, 20000, eig, its);
         }
         hipLaunchKernelGGL(k_wpmds_project, dim3(gn), dim3(256), 0, s, n, k, dist, mu, nu, stats, eig, xd);
         hipLaunchKernelGGL(k_wpmds_edgelen, dim3(eb), dim3(256), 0, s, n, g->row_ptr, g->col_idx, len, xd, epart);

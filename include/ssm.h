@@ -406,7 +406,9 @@ void ssm_release_cache(void);
  *   bfs_loads 2|3 (CSR rows: plain visited checks as well as plain CSR
  *   loads, or agent-scope loads throughout), bfs_grp -1 (CSR rows on one
  *   workgroup each instead of two),
- *   bfs_lanes 2..64, msbfs 1, msbfs_budget N,
+ *   bfs_lanes 2..64, msbfs -1|1 (never / always the bit-parallel BFS
+ *   first; by default it goes first on graphs of at least 2^19 arcs whose
+ *   mean neighbour degree is at least 3x their mean degree), msbfs_budget N,
  *   region_mode 1|2, km_chunk 32|40|48|56|64,
  *   sweep_mode 1|2 (LDS histograms, global table), sweep_split 1|2|4,
  *   sweep_blocks_per_cu N, sweep_waves 4|16 (waves per block),

@@ -38,34 +38,41 @@ __global__ void k_fill_int(int* p, int v, long long count) {
 
 // ------------------------------------------------------------ validation
 
-// Every arc (u, v): v in range, v != u, and the reverse arc (v, u) present
-// exactly once in row v (this also rejects duplicate arcs).  Row v is scanned
-// linearly, so rows need not be sorted.
-__global__ void k_validate(int n, int nnz, const int* __restrict__ rp, const int* __restrict__ ci,
-                           int* bad) {
+// Rows: row_ptr monotone from 0 to nnz.
+__global__ void k_validate_rows(int n, int nnz, const int* __restrict__ rp, int* bad) {
     for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
-        int a = rp[u], b = rp[u + 1];
-        if (a < 0 || b < a || b > nnz || (u == 0 && a != 0) || (u == n - 1 && b != nnz)) {
-            atomicOr(bad, 1);
+        const int a = rp[u], b = rp[u + 1];
+        if (a < 0 || b < a || b > nnz || (u == 0 && a != 0) || (u == n - 1 && b != nnz)) atomicOr(bad, 1);
+    }
+}
+
+// Every arc (u, v), one thread each (launched once the rows are known to be
+// valid): v in range, v != u, and the reverse arc (v, u) present exactly once
+// in row v and (u, v) exactly once in row u (this also rejects duplicate
+// arcs).  The rows are scanned linearly, so they need not be sorted; the
+// work is sum over arcs of both rows' lengths, spread over all threads (a
+// thread per node would serialize a hub's squared degree in one thread).
+__global__ void k_validate_arcs(int n, int nnz, const int* __restrict__ rp, const int* __restrict__ ci, int* bad) {
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nnz;
+         e += (long long)gridDim.x * blockDim.x) {
+        int lo = 0, hi = n - 1;  // the row holding arc e: the last u with rp[u] <= e
+        while (lo < hi) {
+            const int mid = (int)(((long long)lo + hi + 1) >> 1);
+            if (rp[mid] <= e) lo = mid;
+            else hi = mid - 1;
+        }
+        const int u = lo, a = rp[u], b = rp[u + 1];
+        const int v = ci[e];
+        if (v < 0 || v >= n || v == u) {
+            atomicOr(bad, 2);
             continue;
         }
-        for (int e = a; e < b; ++e) {
-            int v = ci[e];
-            if (v < 0 || v >= n || v == u) {
-                atomicOr(bad, 2);
-                continue;
-            }
-            int c0 = rp[v], c1 = rp[v + 1];
-            if (c0 < 0 || c1 < c0 || c1 > nnz) {
-                atomicOr(bad, 1);
-                continue;
-            }
-            int hits = 0;
-            for (int f = c0; f < c1; ++f) hits += (ci[f] == u);
-            int same = 0;
-            for (int f = a; f < b; ++f) same += (ci[f] == v);
-            if (hits != 1 || same != 1) atomicOr(bad, 4);
-        }
+        const int c0 = rp[v], c1 = rp[v + 1];
+        int hits = 0;
+        for (int f = c0; f < c1; ++f) hits += (ci[f] == u);
+        int same = 0;
+        for (int f = a; f < b; ++f) same += (ci[f] == v);
+        if (hits != 1 || same != 1) atomicOr(bad, 4);
     }
 }
 
@@ -441,7 +448,7 @@ __global__ __launch_bounds__(256) void k_msbfs_heavy(int n, int k, int level, in
 
 template <int NW>
 static ssm_status msbfs(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dist, int budget,
-                        bool* done, int32_t* levels_out, hipStream_t s) {
+                        bool forced, bool* done, int32_t* levels_out, hipStream_t s) {
     const int n = g->n;
     *done = false;
     unsigned long long* buf = nullptr;
@@ -469,6 +476,7 @@ static ssm_status msbfs(const ssm_csr* g, int32_t k, const int32_t* pivots, int3
     const int grid = std::min(div_up(n, 256), num_cus() * 8);
     const double pairs = (double)k * n;
     double total = k;  // the pivots themselves
+    double prev = k;   // pairs settled at the previous level
     int level = 0;
     while (e == hipSuccess && level < budget) {
         ++level;
@@ -490,14 +498,65 @@ static ssm_status msbfs(const ssm_csr* g, int32_t k, const int32_t* pivots, int3
             *done = true;
             break;
         }
-        // a graph with many levels settles slowly: hand it to the per-workgroup BFS early
-        if (level >= 3 && total < 0.2 * pairs) break;
+        // Every level is a pass over all nodes, so the form pays only when the
+        // levels are few: on small-world graphs the pairs settled per level
+        // multiply, on meshes and geometric graphs they grow by less than 2x
+        // (d-dimensional balls), and those go to the per-pivot BFS after a
+        // level or two.
+        if (!forced && level >= 2 && total < 0.5 * pairs && (double)h < 2.0 * prev) break;
+        prev = (double)h;
     }
     (void)hipStreamSynchronize(s);  // idle before the scratch is reused
     sfree(buf);
     sfree(heavy);
     if (e != hipSuccess) return hip_fail(e, "bit-parallel BFS");
     *levels_out = level - 1;  // the last level found nothing
+    return SSM_OK;
+}
+
+// Sum over nodes of the squared degree (one atomic per block).
+__global__ __launch_bounds__(256) void k_degree_sq(int n, const int* __restrict__ rp, unsigned long long* out) {
+    unsigned long long sq = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const unsigned long long d = (unsigned long long)(rp[i + 1] - rp[i]);
+        sq += d * d;
+    }
+    __shared__ unsigned long long red[256 / kWave];
+    sq = block_sum(sq, red);
+    if (threadIdx.x == 0 && sq) atomicAdd(out, sq);
+}
+
+// Whether the bit-parallel BFS should go first: graphs with many arcs whose
+// mean neighbour degree (sum d^2 / sum d) is at least kMsbfsSpread times the
+// mean degree, i.e. hubs that most paths pass through, so the levels are
+// few.  Measured on MI355X, rows and regions of 200 pivots: preferential-
+// attachment graphs (ratio 3.3-4.1) of 1M nodes 18.8 -> 5.5 ms, 500k
+// 8.7 -> 3.3 ms, 100k 2.0 -> 1.55 ms, 50k even; a 3.25M-node mesh (ratio
+// 1.0) 37.5 -> 40.5 ms and a 100k random geometric graph (1.13) 1.5 ->
+// 3.0 ms if forced, so those stay on the per-pivot BFS.
+constexpr double kMsbfsSpread = 3.0;
+constexpr long long kMsbfsMinArcs = 1LL << 19;
+
+static ssm_status msbfs_pays(const ssm_csr* g, bool* pays, hipStream_t s) {
+    *pays = false;
+    if ((long long)g->nnz < kMsbfsMinArcs) return SSM_OK;
+    unsigned long long* acc = nullptr;
+    ssm_status st = salloc((void**)&acc, sizeof(unsigned long long));
+    if (st != SSM_OK) return st;
+    unsigned long long sq = 0;
+    hipError_t e = hipMemsetAsync(acc, 0, sizeof(unsigned long long), s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_degree_sq, dim3(std::min(div_up(g->n, 256), 1024)), dim3(256), 0, s, g->n, g->row_ptr,
+                           acc);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&sq, acc, sizeof(sq), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipStreamSynchronize(s);  // idle before the scratch is reused
+    sfree(acc);
+    if (e != hipSuccess) return hip_fail(e, "degree moments");
+    const double arcs = (double)g->nnz, mean = arcs / (double)g->n;
+    *pays = (double)sq / arcs >= kMsbfsSpread * mean;
     return SSM_OK;
 }
 
@@ -935,20 +994,28 @@ int bfs_grp_fits(int rows);
 ssm_status mssp(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dist,
                 int32_t* dmax_out_host, hipStream_t s) {
     const int n = g->n;
-    // Bit-parallel BFS over all pivots at once (opt-in with SSM_MSBFS=1: the
-    // per-pivot LDS-resident BFS below was faster on every graph measured).
-    // It gives up after `budget` levels, and the per-workgroup BFS runs instead.
+    // Bit-parallel BFS over all pivots at once on large hub-dominated graphs
+    // (msbfs_pays).  It hands over to the per-pivot BFS below when the
+    // settled pairs stop multiplying, or after `budget` levels.  (tuning:
+    // msbfs -1 = never, 1 = always, with no hand-over but the budget)
     const int budget = variant("msbfs_budget") > 0 ? variant("msbfs_budget") : 24;
-    if (k <= 1024 && variant("msbfs") == 1) {
+    const int ms = variant("msbfs");
+    bool use_ms = k <= 1024 && ms == 1;
+    if (k <= 1024 && ms == 0) {
+        ssm_status st = msbfs_pays(g, &use_ms, s);
+        if (st != SSM_OK) return st;
+    }
+    if (use_ms) {
         bool done = false;
         int32_t levels = 0;
         ssm_status st;
         const int nw = div_up(k, 64);
-        if (nw <= 1) st = msbfs<1>(g, k, pivots, dist, budget, &done, &levels, s);
-        else if (nw <= 2) st = msbfs<2>(g, k, pivots, dist, budget, &done, &levels, s);
-        else if (nw <= 4) st = msbfs<4>(g, k, pivots, dist, budget, &done, &levels, s);
-        else if (nw <= 8) st = msbfs<8>(g, k, pivots, dist, budget, &done, &levels, s);
-        else st = msbfs<16>(g, k, pivots, dist, budget, &done, &levels, s);
+        const bool forced = ms == 1;
+        if (nw <= 1) st = msbfs<1>(g, k, pivots, dist, budget, forced, &done, &levels, s);
+        else if (nw <= 2) st = msbfs<2>(g, k, pivots, dist, budget, forced, &done, &levels, s);
+        else if (nw <= 4) st = msbfs<4>(g, k, pivots, dist, budget, forced, &done, &levels, s);
+        else if (nw <= 8) st = msbfs<8>(g, k, pivots, dist, budget, forced, &done, &levels, s);
+        else st = msbfs<16>(g, k, pivots, dist, budget, forced, &done, &levels, s);
         if (st != SSM_OK) return st;
         if (done) {
             int* bad = nullptr;
@@ -3069,12 +3136,19 @@ extern "C" ssm_status ssm_validate_csr(const ssm_csr* g, hipStream_t stream) {
     int hbad = 0;
     hipError_t e = hipMemsetAsync(bad, 0, sizeof(int), stream);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_validate, dim3(std::min(div_up(g->n, 256), 8192)), dim3(256), 0, stream,
-                           g->n, g->nnz, g->row_ptr, g->col_idx, bad);
+        hipLaunchKernelGGL(k_validate_rows, dim3(std::min(div_up(g->n, 256), 8192)), dim3(256), 0, stream, g->n,
+                           g->nnz, g->row_ptr, bad);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e == hipSuccess && hbad == 0 && g->nnz > 0) {  // the arcs' rows are in bounds only once the rows are valid
+        hipLaunchKernelGGL(k_validate_arcs, dim3((int)std::min<long long>(div_up(g->nnz, 256), 16384)), dim3(256), 0,
+                           stream, g->n, g->nnz, g->row_ptr, g->col_idx, bad);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    }
     (void)hipStreamSynchronize(stream);
     sfree(bad);
     if (e != hipSuccess) return hip_fail(e, "CSR validation");

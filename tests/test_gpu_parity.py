@@ -99,11 +99,12 @@ VARIANTS = [
     {"select_ell": 2, "select_rowq": 2},
     {"select_ell": 2, "select_rowq": 2, "select_pre": 3},
     {"select_ell": 2, "select_pre": 1},
-    {"bfs_rowq": 2, "bfs_ell": 2, "bfs_grp": -1}, {"bfs_ell": 2}, {"bfs_ell": 2, "bfs_grp": -1},
-    {"bfs_ell": 2, "bfs_loads": 3, "bfs_grp": -1}, {"bfs_ell": 2, "bfs_loads": 2, "bfs_grp": -1},
-    {"bfs_ell": 3}, {"bfs_ell": 4}, {"msbfs": 1},
+    {"msbfs": -1}, {"bfs_rowq": 2, "bfs_ell": 2, "bfs_grp": -1, "msbfs": -1}, {"bfs_ell": 2, "msbfs": -1},
+    {"bfs_ell": 2, "bfs_grp": -1, "msbfs": -1},
+    {"bfs_ell": 2, "bfs_loads": 3, "bfs_grp": -1, "msbfs": -1}, {"bfs_ell": 2, "bfs_loads": 2, "bfs_grp": -1, "msbfs": -1},
+    {"bfs_ell": 3, "msbfs": -1}, {"bfs_ell": 4, "msbfs": -1}, {"msbfs": 1},
     {"msbfs": 1, "msbfs_budget": 3},
-    {"region_mode": 1}, {"region_mode": 2}, {"bfs_lanes": 2}, {"bfs_lanes": 64},
+    {"region_mode": 1}, {"region_mode": 2}, {"bfs_lanes": 2, "msbfs": -1}, {"bfs_lanes": 64, "msbfs": -1},
     {"select_wave": -1}, {"select_wave": 2},
 ]
 # (the star's first level overflows the LDS part of the frontier queue; the
@@ -142,14 +143,17 @@ def test_select_beyond_byte_copy(g, k, mode, forced):
     assert np.array_equal(ssm.select_pivots(dg, k, 0).cpu().numpy(), piv_r)
 
 
-@pytest.mark.parametrize("env", [{}, {"msbfs": 1}, {"bfs_ell": 2}, {"bfs_ell": 2, "bfs_grp": -1},
-                                 {"bfs_ell": 2, "bfs_loads": 3, "bfs_grp": -1},
-                                 {"bfs_ell": 2, "bfs_loads": 2, "bfs_grp": -1}, {"bfs_ell": 3}, {"bfs_ell": 4}],
-                         ids=["default", "bitparallel", "csr", "csr-one-block", "csr-agent", "csr-plain-checks", "ell-global",
-                              "ell-global-noread"])
+@pytest.mark.parametrize("env", [{}, {"msbfs": 1}, {"msbfs": -1}, {"bfs_ell": 2, "msbfs": -1},
+                                 {"bfs_ell": 2, "bfs_grp": -1, "msbfs": -1},
+                                 {"bfs_ell": 2, "bfs_loads": 3, "bfs_grp": -1, "msbfs": -1},
+                                 {"bfs_ell": 2, "bfs_loads": 2, "bfs_grp": -1, "msbfs": -1}, {"bfs_ell": 3, "msbfs": -1},
+                                 {"bfs_ell": 4, "msbfs": -1}],
+                         ids=["default", "bitparallel", "per-pivot", "csr", "csr-one-block", "csr-agent", "csr-plain-checks",
+                              "ell-global", "ell-global-noread"])
 def test_bfs_large_frontiers(env, forced):
     """Frontiers beyond the LDS queue and more long rows per level than the
-    LDS list holds: the global overflow areas of the per-pivot BFS."""
+    LDS list holds: the global overflow areas of the per-pivot BFS (and the
+    bit-parallel BFS, which the library picks on this graph by default)."""
     for name, val in env.items():
         forced(name, val)
     g = G.barabasi_albert(60000, 5, 3)

@@ -340,6 +340,52 @@ __device__ __forceinline__ double eig_rand(int r, int c, int d) {
     return splitmix_uniform(st);
 }
 
+// Wave-wide sum and maximum of doubles by DPP lane moves, which stay in
+// registers (a shuffle step is an LDS permute and its round trip): pairs,
+// quads, half rows and rows of 16 lanes by quad permutes and mirrors, then
+// the row broadcasts 15 and 31 gather the four rows into lane 63, whose
+// value every lane receives.  Call with every lane of the wave active.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double old, double v) {
+    const long long b = __builtin_bit_cast(long long, v), o = __builtin_bit_cast(long long, old);
+    const int lo = __builtin_amdgcn_update_dpp((int)o, (int)b, CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(b >> 32), CTRL, ROWS, 0xf, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double lane63(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)b, 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+    v += dpp_move<0xB1, 0xf>(0.0, v);   // quad_perm [1,0,3,2]
+    v += dpp_move<0x4E, 0xf>(0.0, v);   // quad_perm [2,3,0,1]
+    v += dpp_move<0x141, 0xf>(0.0, v);  // row_half_mirror
+    v += dpp_move<0x140, 0xf>(0.0, v);  // row_mirror
+    v += dpp_move<0x142, 0xa>(0.0, v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_move<0x143, 0xc>(0.0, v);  // row_bcast:31 into rows 2 and 3
+    return lane63(v);
+}
+
+__device__ __forceinline__ double wave_max_dpp(double v) {
+    double o;
+    o = dpp_move<0xB1, 0xf>(v, v);
+    v = o > v ? o : v;
+    o = dpp_move<0x4E, 0xf>(v, v);
+    v = o > v ? o : v;
+    o = dpp_move<0x141, 0xf>(v, v);
+    v = o > v ? o : v;
+    o = dpp_move<0x140, 0xf>(v, v);
+    v = o > v ? o : v;
+    o = dpp_move<0x142, 0xa>(v, v);
+    v = o > v ? o : v;
+    o = dpp_move<0x143, 0xc>(v, v);
+    v = o > v ? o : v;
+    return lane63(v);
+}
+
 // Wave 0: orthonormalizes the first pw columns of A (k x kEigP, row-major,
 // LDS) in place by classical Gram-Schmidt applied twice per column; a column
 // whose remainder is negligible against the first column's norm (M of low
@@ -362,7 +408,7 @@ __device__ void eig_orth(int k, int pw, double* A, int draw) {
                 }
 #pragma unroll
                 for (int b = 0; b < kEigP; ++b)
-                    if (b < c) d[b] = wave_sum(d[b]);
+                    if (b < c) d[b] = wave_sum_dpp(d[b]);
                 for (int r = lane; r < k; r += kWave) {
                     double ac = A[r * kEigP + c];
 #pragma unroll
@@ -373,7 +419,7 @@ __device__ void eig_orth(int k, int pw, double* A, int draw) {
             }
             double nn = 0.0;
             for (int r = lane; r < k; r += kWave) nn += A[r * kEigP + c] * A[r * kEigP + c];
-            nn = sqrt(wave_sum(nn));
+            nn = sqrt(wave_sum_dpp(nn));
             if (c == 0 && attempt == 0) ref = nn > 0.0 ? nn : 1.0;
             if (nn > 1e-13 * ref) {
                 for (int r = lane; r < k; r += kWave) A[r * kEigP + c] /= nn;
@@ -491,7 +537,7 @@ __device__ __forceinline__ void eigp_body(int k, const double* __restrict__ M, d
                 for (int c = 0; c < kEigP; ++c) acc[c] += mv * V[j * kEigP + c];
             }
 #pragma unroll
-            for (int c = 0; c < kEigP; ++c) acc[c] = wave_sum(acc[c]);
+            for (int c = 0; c < kEigP; ++c) acc[c] = wave_sum_dpp(acc[c]);
             if (lane < kEigP) {
                 double mine = acc[0];
 #pragma unroll
@@ -509,7 +555,7 @@ __device__ __forceinline__ void eigp_body(int k, const double* __restrict__ M, d
                     for (int b = a; b < pw; ++b) {
                         double d = 0.0;
                         for (int r = lane; r < k; r += kWave) d += V[r * kEigP + a] * Z[r * kEigP + b];
-                        d = wave_sum(d);
+                        d = wave_sum_dpp(d);
                         if (lane == 0) {
                             H[a * kEigP + b] = d;
                             H[b * kEigP + a] = d;
@@ -545,10 +591,10 @@ __device__ __forceinline__ void eigp_body(int k, const double* __restrict__ M, d
                         Z[r * kEigP + c] = zr[c];
                     }
                 }
-                p00 = wave_sum(p00);
-                p01 = wave_sum(p01);
-                p10 = wave_sum(p10);
-                p11 = wave_sum(p11);
+                p00 = wave_sum_dpp(p00);
+                p01 = wave_sum_dpp(p01);
+                p10 = wave_sum_dpp(p10);
+                p11 = wave_sum_dpp(p11);
                 double res0 = 0.0, res1 = 0.0;
                 for (int r = lane; r < k; r += kWave) {
                     const double u0 = V[r * kEigP + 0], u1 = V[r * kEigP + 1];
@@ -557,8 +603,8 @@ __device__ __forceinline__ void eigp_body(int k, const double* __restrict__ M, d
                     U[2 * r] = u0;
                     U[2 * r + 1] = u1;
                 }
-                res0 = wave_max(res0);
-                res1 = wave_max(res1);
+                res0 = wave_max_dpp(res0);
+                res1 = wave_max_dpp(res1);
                 const bool conv = have_u && res0 < tol && (res1 < tol || rank1 || tie23);
                 if (lane == 0 && (conv || it >= max_iter)) s_done = 1;
                 have_u = true;
@@ -606,7 +652,7 @@ template <int N>
 __device__ __forceinline__ void block_sum_n(double (&v)[N], double* scratch) {
     const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
 #pragma unroll
-    for (int u = 0; u < N; ++u) v[u] = wave_sum(v[u]);
+    for (int u = 0; u < N; ++u) v[u] = wave_sum_dpp(v[u]);
     __syncthreads();
     if (lane_id() == 0)
 #pragma unroll
@@ -624,7 +670,7 @@ template <int N>
 __device__ __forceinline__ void block_max_n(double (&v)[N], double* scratch) {
     const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
 #pragma unroll
-    for (int u = 0; u < N; ++u) v[u] = wave_max(v[u]);
+    for (int u = 0; u < N; ++u) v[u] = wave_max_dpp(v[u]);
     __syncthreads();
     if (lane_id() == 0)
 #pragma unroll
@@ -699,8 +745,8 @@ __device__ __forceinline__ bool eig2_body(int k, const double* __restrict__ M, d
                             a1 += mv * x1[c];
                         }
                     }
-                    a0 = wave_sum(a0);
-                    a1 = wave_sum(a1);
+                    a0 = wave_sum_dpp(a0);
+                    a1 = wave_sum_dpp(a1);
                     if (lane == 0) {
                         z0[r] = sigma != 0.0 ? a0 - sigma * v0[r] : a0;
                         z1[r] = sigma != 0.0 ? a1 - sigma * v1[r] : a1;
@@ -715,8 +761,8 @@ __device__ __forceinline__ bool eig2_body(int k, const double* __restrict__ M, d
                     a0 += mv * v0[j];
                     a1 += mv * v1[j];
                 }
-                a0 = wave_sum(a0);
-                a1 = wave_sum(a1);
+                a0 = wave_sum_dpp(a0);
+                a1 = wave_sum_dpp(a1);
                 if (lane == 0) {
                     z0[r] = a0;
                     z1[r] = a1;
@@ -744,7 +790,7 @@ __device__ __forceinline__ bool eig2_body(int k, const double* __restrict__ M, d
             double acc = 0.0;
 #pragma unroll
             for (int c = 0; c < E; ++c) acc += x[c] * y[c];
-            return wave_sum(acc);
+            return wave_sum_dpp(acc);
         };
         if (w == 0) {
 #pragma unroll
@@ -823,8 +869,8 @@ __device__ __forceinline__ bool eig2_body(int k, const double* __restrict__ M, d
                     res0 = fmax(res0, fabs(zr0[c] - p00 * vr0[c] - p10 * vr1[c]));
                     res1 = fmax(res1, fabs(zr1[c] - p01 * vr0[c] - p11 * vr1[c]));
                 }
-                res0 = wave_max(res0);
-                res1 = wave_max(res1);
+                res0 = wave_max_dpp(res0);
+                res1 = wave_max_dpp(res1);
 #pragma unroll
                 for (int c = 0; c < E; ++c) {
                     vr0[c] = zr0[c];

@@ -168,6 +168,30 @@ def test_bfs_large_frontiers(env, forced):
     assert np.array_equal(region.cpu().numpy(), region_r)
 
 
+@pytest.mark.parametrize("env", [{}, {"msbfs": -1}], ids=["default", "per-pivot"])
+def test_bfs_hub_graph_with_long_tail(env, forced):
+    """A hub-dominated graph (the bit-parallel rows go first) with a 2000-node
+    path hanging off one hub and most pivots on the path: the settled pairs
+    stop doubling once the graph's own pivots are done, long before the path
+    pivots are, so the rows hand over to the per-pivot BFS part way."""
+    for name, val in env.items():
+        forced(name, val)
+    ba = G.barabasi_albert(60000, 5, 3)
+    src = np.repeat(np.arange(ba.n), np.diff(ba.row_ptr))
+    tail = np.arange(ba.n, ba.n + 2000)
+    edges = np.concatenate([np.stack([src, ba.col_idx], 1), np.stack([np.r_[0, tail[:-1]], tail], 1)])
+    g = G.csr_from_edges(ba.n + 2000, edges, "ba60000+path2000")
+    piv = np.array([g.n - 1, g.n - 500, g.n - 1000, g.n - 1500, g.n - 1800, 0, 17, 30000], dtype=np.int32)
+    say("case", g.name, "pivots", piv.tolist(), "env", env)
+    dref = oracle.bfs_pivots(g.n, g.row_ptr, g.col_idx, piv)
+    dg = ssm.DeviceGraph.from_csr(g)
+    dist, delta, region = ssm.bfs_pivots(dg, torch.from_numpy(piv).cuda())
+    assert np.array_equal(dist.cpu().numpy(), dref)
+    delta_r, region_r, _, _ = oracle.regions(dref)
+    assert np.array_equal(delta.cpu().numpy(), delta_r)
+    assert np.array_equal(region.cpu().numpy(), region_r)
+
+
 def test_regions_many_ties_per_level_path():
     """Enough tied nodes that the default takes the multi-workgroup per-level
     resolution, on levels both sparse (tied-node list) and dense (full scan)."""

@@ -1204,6 +1204,17 @@ __device__ __forceinline__ void grid_barrier(cg::grid_group& grid) {
         grid.sync();
 }
 
+// Largest of keys[0 .. count-1] for a whole wave (agent-scope loads, one per
+// lane and pass, then a butterfly); every lane gets it.
+__device__ __forceinline__ unsigned long long keys_max(const unsigned long long* keys, int count) {
+    unsigned long long b = 0;
+    for (int q = lane_id(); q < count; q += kWave) {
+        const unsigned long long kq = __hip_atomic_load(&keys[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        b = kq > b ? kq : b;
+    }
+    return wave_max(b);
+}
+
 // One launch per pivot t.  BFS from pivots[t] that only continues through
 // nodes whose distance to the new pivot is smaller than m (their distance to
 // the nearest earlier pivot), updating m on the way.  This is exact for
@@ -1282,15 +1293,13 @@ __global__ __launch_bounds__(kSelBlock) void k_select(int n, const int* __restri
     best = block_max(best, s_red);
     if (threadIdx.x == 0) keys[blockIdx.x] = best;
     grid_barrier(grid);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        unsigned long long b = 0;
-        for (int q = 0; q < (int)gridDim.x; ++q) {
-            unsigned long long kq = __hip_atomic_load(&keys[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            b = kq > b ? kq : b;
+    if (blockIdx.x == 0 && threadIdx.x < kWave) {  // wave 0 reads the keys, one per lane
+        const unsigned long long b = keys_max(keys, (int)gridDim.x);
+        if (threadIdx.x == 0) {
+            int mbest = (int)(b >> 32);
+            if (t == 0 && mbest == kInf) status[0] = 1;
+            if (t + 1 < k) pivots[t + 1] = (int)(0xffffffffu - (unsigned)(b & 0xffffffffu));
         }
-        int mbest = (int)(b >> 32);
-        if (t == 0 && mbest == kInf) status[0] = 1;
-        if (t + 1 < k) pivots[t + 1] = (int)(0xffffffffu - (unsigned)(b & 0xffffffffu));
     }
 }
 
@@ -1365,14 +1374,12 @@ __global__ __launch_bounds__(kSelBlock) void k_select_all(int n, const int* __re
         best = block_max(best, s_red);
         if (threadIdx.x == 0) keys[blockIdx.x] = best;
         grid_barrier(grid);
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            unsigned long long b = 0;
-            for (int q = 0; q < (int)gridDim.x; ++q) {
-                unsigned long long kq = __hip_atomic_load(&keys[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                b = kq > b ? kq : b;
+        if (blockIdx.x == 0 && threadIdx.x < kWave) {  // wave 0 reads the keys, one per lane
+            const unsigned long long b = keys_max(keys, (int)gridDim.x);
+            if (threadIdx.x == 0) {
+                if (t == 0 && (int)(b >> 32) == kInf) status[0] = 1;
+                if (t + 1 < k) pivots[t + 1] = (int)(0xffffffffu - (unsigned)(b & 0xffffffffu));
             }
-            if (t == 0 && (int)(b >> 32) == kInf) status[0] = 1;
-            if (t + 1 < k) pivots[t + 1] = (int)(0xffffffffu - (unsigned)(b & 0xffffffffu));
         }
         grid_barrier(grid);
         if (t == 0 && load_agent(&status[0]) != 0) break;  // disconnected: stop (uniform)
@@ -1757,17 +1764,15 @@ __global__ __launch_bounds__(kSelBlock) void k_select_grid(int n, const int* __r
         best = block_max(best, s_red);
         if (threadIdx.x == 0) store_agent(&keys[blockIdx.x], best);
         SYNC_OR_LEAVE();
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            unsigned long long b = 0;
-            for (int q = 0; q < (int)gridDim.x; ++q) {
-                unsigned long long kq = __hip_atomic_load(&keys[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                b = kq > b ? kq : b;
+        if (blockIdx.x == 0 && threadIdx.x < kWave) {  // wave 0 reads the keys, one per lane
+            const unsigned long long b = keys_max(keys, (int)gridDim.x);
+            if (threadIdx.x == 0) {
+                if (t == 0) {
+                    if ((int)(b >> 32) == kInf) store_agent(&status[0], 1);
+                    store_agent(&status[1], (int)(b >> 32));
+                }
+                if (t + 1 < k) store_agent(&pivots[t + 1], (int)(0xffffffffu - (unsigned)(b & 0xffffffffu)));
             }
-            if (t == 0) {
-                if ((int)(b >> 32) == kInf) store_agent(&status[0], 1);
-                store_agent(&status[1], (int)(b >> 32));
-            }
-            if (t + 1 < k) store_agent(&pivots[t + 1], (int)(0xffffffffu - (unsigned)(b & 0xffffffffu)));
         }
         SYNC_OR_LEAVE();
         if (t == 0 && load_agent(&status[0]) != 0) break;  // disconnected: stop (uniform)
@@ -1862,17 +1867,15 @@ __global__ __launch_bounds__(kBfsBlock) void k_select_hyb(int n, const int* __re
         best = block_max(best, s_red);
         if (threadIdx.x == 0) keys[blockIdx.x] = best;
         grid_barrier(grid);
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            unsigned long long b = 0;
-            for (int q = 0; q < (int)gridDim.x; ++q) {
-                unsigned long long kq = __hip_atomic_load(&keys[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                b = kq > b ? kq : b;
+        if (blockIdx.x == 0 && threadIdx.x < kWave) {  // wave 0 reads the keys, one per lane
+            const unsigned long long b = keys_max(keys, (int)gridDim.x);
+            if (threadIdx.x == 0) {
+                if (t == 0) {
+                    if ((int)(b >> 32) == kInf) status[0] = 1;
+                    status[1] = (int)(b >> 32);
+                }
+                if (t + 1 < k) pivots[t + 1] = (int)(0xffffffffu - (unsigned)(b & 0xffffffffu));
             }
-            if (t == 0) {
-                if ((int)(b >> 32) == kInf) status[0] = 1;
-                status[1] = (int)(b >> 32);
-            }
-            if (t + 1 < k) pivots[t + 1] = (int)(0xffffffffu - (unsigned)(b & 0xffffffffu));
         }
         grid_barrier(grid);
         if (t == 0 && load_agent(&status[0]) != 0) break;  // disconnected: stop (uniform)

@@ -340,52 +340,6 @@ __device__ __forceinline__ double eig_rand(int r, int c, int d) {
     return splitmix_uniform(st);
 }
 
-// Wave-wide sum and maximum of doubles by DPP lane moves, which stay in
-// registers (a shuffle step is an LDS permute and its round trip): pairs,
-// quads, half rows and rows of 16 lanes by quad permutes and mirrors, then
-// the row broadcasts 15 and 31 gather the four rows into lane 63, whose
-// value every lane receives.  Call with every lane of the wave active.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double dpp_move(double old, double v) {
-    const long long b = __builtin_bit_cast(long long, v), o = __builtin_bit_cast(long long, old);
-    const int lo = __builtin_amdgcn_update_dpp((int)o, (int)b, CTRL, ROWS, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(b >> 32), CTRL, ROWS, 0xf, false);
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
-}
-
-__device__ __forceinline__ double lane63(double v) {
-    const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_readlane((int)b, 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
-}
-
-__device__ __forceinline__ double wave_sum_dpp(double v) {
-    v += dpp_move<0xB1, 0xf>(0.0, v);   // quad_perm [1,0,3,2]
-    v += dpp_move<0x4E, 0xf>(0.0, v);   // quad_perm [2,3,0,1]
-    v += dpp_move<0x141, 0xf>(0.0, v);  // row_half_mirror
-    v += dpp_move<0x140, 0xf>(0.0, v);  // row_mirror
-    v += dpp_move<0x142, 0xa>(0.0, v);  // row_bcast:15 into rows 1 and 3
-    v += dpp_move<0x143, 0xc>(0.0, v);  // row_bcast:31 into rows 2 and 3
-    return lane63(v);
-}
-
-__device__ __forceinline__ double wave_max_dpp(double v) {
-    double o;
-    o = dpp_move<0xB1, 0xf>(v, v);
-    v = o > v ? o : v;
-    o = dpp_move<0x4E, 0xf>(v, v);
-    v = o > v ? o : v;
-    o = dpp_move<0x141, 0xf>(v, v);
-    v = o > v ? o : v;
-    o = dpp_move<0x140, 0xf>(v, v);
-    v = o > v ? o : v;
-    o = dpp_move<0x142, 0xa>(v, v);
-    v = o > v ? o : v;
-    o = dpp_move<0x143, 0xc>(v, v);
-    v = o > v ? o : v;
-    return lane63(v);
-}
-
 // Wave 0: orthonormalizes the first pw columns of A (k x kEigP, row-major,
 // LDS) in place by classical Gram-Schmidt applied twice per column; a column
 // whose remainder is negligible against the first column's norm (M of low

@@ -406,30 +406,43 @@ __global__ __launch_bounds__(256) void k_pool_moments(const PoolGraph* __restric
     for (int j = 0; j < kMoments; ++j) m[j] = 0.0;
     const int i = ch.y + threadIdx.x;
     if (i < g.n) moments_add(m, o, to_d2(xo[i]), to_d2(xn[i]));
-    __shared__ double red[256 / kWave];
+    // the twelve wave sums in registers, then one barrier and a fixed-order
+    // sum over the block's waves
+    __shared__ double red[(256 / kWave) * kMoments];
+    const int w = threadIdx.x / kWave;
 #pragma unroll
     for (int j = 0; j < kMoments; ++j) {
-        const double v = block_sum(m[j], red);
-        if (threadIdx.x == 0) partial[(size_t)blockIdx.x * kMoments + j] = v;
+        const double v = wave_sum_dpp(m[j]);
+        if (lane_id() == 0) red[w * kMoments + j] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kMoments) {
+        double t = 0.0;
+        for (int q = 0; q < 256 / kWave; ++q) t += red[q * kMoments + threadIdx.x];
+        partial[(size_t)blockIdx.x * kMoments + threadIdx.x] = t;
     }
 }
 
-// One thread per listed graph: the chunk partials first[q] .. first[q + 1]
-// summed in order; a change <= tol after sweep s sets info[6] and records
-// the sweeps run in info[7].
-__global__ void k_pool_decide(const PoolGraph* __restrict__ gs, const int* __restrict__ hdr,
-                              const int* __restrict__ first, const double* __restrict__ partial, int s) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= hdr[1]) return;
+// One wave per listed graph: lane l sums the chunk partials first[q] + l,
+// + l + 64, ... in order, a fixed-order wave sum adds the lanes' (the same
+// order whatever else the batch holds); a change <= tol after sweep s sets
+// info[6] and records the sweeps run in info[7].
+__global__ __launch_bounds__(256) void k_pool_decide(const PoolGraph* __restrict__ gs, const int* __restrict__ hdr,
+                                                     const int* __restrict__ first,
+                                                     const double* __restrict__ partial, int s) {
+    const int q = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    if (q >= hdr[1]) return;  // the whole wave
     const PoolGraph& g = gs[q];
-    if (s >= g.iters || !(g.tol > 0.0) || g.info[6]) return;
+    if (s >= g.iters || !(g.tol > 0.0) || g.info[6]) return;  // the whole wave
     double m[kMoments];
 #pragma unroll
     for (int j = 0; j < kMoments; ++j) m[j] = 0.0;
-    for (int c = first[q]; c < first[q + 1]; ++c)
+    for (int c = first[q] + lane_id(); c < first[q + 1]; c += kWave)
 #pragma unroll
         for (int j = 0; j < kMoments; ++j) m[j] += partial[(size_t)c * kMoments + j];
-    if (rigid_change(m, g.n) <= g.tol) {
+#pragma unroll
+    for (int j = 0; j < kMoments; ++j) m[j] = wave_sum_dpp(m[j]);
+    if (lane_id() == 0 && rigid_change(m, g.n) <= g.tol) {
         g.info[7] = g.done0 + s + 1;
         g.info[6] = 1;
     }
@@ -1196,7 +1209,8 @@ ssm_status ssm_pool_sweep(ssm_pool* p, int32_t count, const int32_t* slots, int3
             hipLaunchKernelGGL(k_pool_sweep32<false>, dim3(grid_c), dim3(kPoolSweepBlock), ldsB, q, dg, dc, dh, it);
         if (any_tol) {
             hipLaunchKernelGGL(k_pool_moments, dim3(grid_c), dim3(256), 0, q, dg, dc, dh, it, dpart);
-            hipLaunchKernelGGL(k_pool_decide, dim3(div_up(grid_g, 256)), dim3(256), 0, q, dg, dh, dfirst, dpart, it);
+            hipLaunchKernelGGL(k_pool_decide, dim3(div_up((long long)grid_g * kWave, 256)), dim3(256), 0, q, dg, dh,
+                               dfirst, dpart, it);
         }
     };
     // Schedule: a block per chunk or a persistent grid (variant pool_persist

@@ -491,6 +491,37 @@ def test_edge_cases():
     assert ei.value.status == ssm.E_DISCONNECTED
 
 
+def test_largest_distance():
+    """Distances are stored in 16 bits: a path of 65,536 nodes (largest
+    distance 65,535) runs end to end, bit for bit against the oracle in FP64;
+    one node more is refused with SSM_E_RANGE."""
+    g = G.path(65536)
+    k, iters = 3, 2
+    say("case", g.name, "k", k)
+    dg = ssm.DeviceGraph.from_csr(g)
+    piv = ssm.select_pivots(dg, k, 0)
+    dist, delta, region = ssm.bfs_pivots(dg, piv)
+    ref = oracle.preprocess(g.n, g.row_ptr, g.col_idx, k)
+    assert np.array_equal(piv.cpu().numpy(), ref.pivots)
+    assert np.array_equal(dist.cpu().numpy(), ref.dist)
+    assert int(dist.max()) == 65535
+    terms = ssm.build_terms(dg, piv, dist, delta, region)
+    x0 = oracle.initial_layout(g.row_ptr, g.col_idx, ref)
+    xg = torch.from_numpy(x0).cuda()
+    ssm.majorize(dg, terms, xg, iters, sync=True)
+    xr, _ = oracle.majorize(g.row_ptr, g.col_idx, ref.pivots, ref.dist, ref.wtab, ref.den, x0, iters)
+    assert np.array_equal(xg.cpu().numpy(), xr)
+    del terms
+    g2 = G.path(65537)
+    say("case", g2.name, "k", k)
+    dg2 = ssm.DeviceGraph.from_csr(g2)
+    piv2 = ssm.select_pivots(dg2, k, 0)
+    dist2, delta2, region2 = ssm.bfs_pivots(dg2, piv2)
+    with pytest.raises(ssm.SSMError) as ei:
+        ssm.build_terms(dg2, piv2, dist2, delta2, region2)
+    assert ei.value.status == ssm.E_RANGE
+
+
 KM_CASES = [(G.path(9), 2), (G.cycle(17), 4), (G.star(12), 3), (G.complete(9), 9), (G.grid(9, 11), 6),
             (G.tri_grid(20, 23), 12), (G.rgg(300, 3), 7), (G.tree_plus(300, 2), 17),
             (G.barabasi_albert(2000, 3, 7), 50), (G.holed_mesh(120, 130, 6, 4, 12, 5), 40), (G.rgg(20000, 7, 8.0), 60)]

@@ -511,6 +511,15 @@ def test_largest_distance():
     ssm.majorize(dg, terms, xg, iters, sync=True)
     xr, _ = oracle.majorize(g.row_ptr, g.col_idx, ref.pivots, ref.dist, ref.wtab, ref.den, x0, iters)
     assert np.array_equal(xg.cpu().numpy(), xr)
+    # FP32 sweeps over 16-bit distances whose tables do not fit LDS, from a
+    # perturbed start (PivotMDS lays a path out exactly)
+    x32 = (x0 + np.random.default_rng(5).normal(size=x0.shape) * 3.0).astype(np.float32).astype(np.float64)
+    xf = torch.from_numpy(x32.astype(np.float32)).cuda()
+    ssm.majorize(dg, terms, xf, 20, sync=True)
+    xr32, _ = oracle.majorize(g.row_ptr, g.col_idx, ref.pivots, ref.dist, ref.wtab, ref.den, x32, 20)
+    s32 = ssm.stress(dg, terms, xf)
+    sr = oracle.stress_sparse(g.row_ptr, g.col_idx, ref.pivots, ref.dist, ref.wtab, xr32)
+    assert abs(s32 - sr) <= 1e-4 * sr, (s32, sr)
     del terms
     g2 = G.path(65537)
     say("case", g2.name, "k", k)

@@ -469,6 +469,7 @@ static ssm_status msbfs(const ssm_csr* g, int32_t k, const int32_t* pivots, int3
     if (e == hipSuccess) {
         st = heavy_list(g, &heavy, &nheavy, s);
         if (st != SSM_OK) {
+            (void)hipStreamSynchronize(s);  // idle before the scratch is reused
             sfree(buf);
             return st;
         }
@@ -1016,7 +1017,10 @@ ssm_status mssp(const ssm_csr* g, int32_t k, const int32_t* pivots, int32_t* dis
         else if (nw <= 4) st = msbfs<4>(g, k, pivots, dist, budget, forced, &done, &levels, s);
         else if (nw <= 8) st = msbfs<8>(g, k, pivots, dist, budget, forced, &done, &levels, s);
         else st = msbfs<16>(g, k, pivots, dist, budget, forced, &done, &levels, s);
-        if (st != SSM_OK) return st;
+        // chosen by the library, the form gives way to the per-pivot BFS when
+        // its bit arrays do not fit
+        if (st == SSM_E_NOMEM && !forced) done = false;
+        else if (st != SSM_OK) return st;
         if (done) {
             int* bad = nullptr;
             st = salloc((void**)&bad, sizeof(int));

@@ -308,13 +308,15 @@ __device__ __forceinline__ double splitmix_uniform(unsigned long long& state) {
     return (double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;  // [-1, 1)
 }
 
-constexpr int kEigThreads = 1024;
-// M in registers for k <= KR (KR = 128 or 256): KR / 16 rows of M per wave,
-// KR / 64 columns per lane; at KR = 256 the copy outgrows the 128 registers
-// a thread of a 1024-thread workgroup has and partly spills, so graphs with
-// k <= 128 take the smaller copy.
+constexpr int kEigThreads = 1024;  // the largest workgroup of the eigen kernels
+// M in registers for k <= KR (KR = 128 or 256): KR / (waves) rows of M per
+// wave, KR / 64 columns per lane.  KR = 128 runs on 512 threads, whose 256
+// registers each hold the copy (at 1024 threads a thread has 128, and the
+// copy spilled to scratch: a scratch round trip per row of M V); KR = 256
+// runs on 1024 threads and partly spills (its copy alone needs 128).
 constexpr int kEigRegMax = 256;
-__host__ __device__ constexpr int eig_reg_rows(int KR) { return KR > 0 ? KR / 16 : 1; }
+__host__ __device__ constexpr int eig_threads(int KR) { return KR == 128 ? 512 : kEigThreads; }
+__host__ __device__ constexpr int eig_reg_rows(int KR) { return KR > 0 ? KR / (eig_threads(KR) / 64) : 1; }
 __host__ __device__ constexpr int eig_reg_cols(int KR) { return KR > 0 ? KR / 64 : 1; }
 // The register form for a k x k Gram matrix: 128, 256, or 0 (M in global memory).
 __host__ __device__ constexpr int eig_reg_form(int k) { return k <= 128 ? 128 : k <= kEigRegMax ? 256 : 0; }
@@ -685,26 +687,24 @@ __device__ __forceinline__ bool eig2_body(int k, const double* __restrict__ M, d
                 x0[c] = j < k ? v0[j] : 0.0;
                 x1[c] = j < k ? v1[j] : 0.0;
             }
+            // every row of the copy, also those beyond k (zero there, as are
+            // x0 and x1 beyond k): no branch between the rows' sums, so
+            // their lane moves interleave
 #pragma unroll
             for (int q = 0; q < ER; ++q) {
                 const int r = w + nw * q;
-                if (r < k) {  // uniform across the wave
-                    double a0 = 0.0, a1 = 0.0;
+                double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-                    for (int c = 0; c < EC; ++c) {
-                        int j = lane + kWave * c;
-                        if (j < k) {
-                            double mv = mreg[REG ? q : 0][REG ? c : 0];
-                            a0 += mv * x0[c];
-                            a1 += mv * x1[c];
-                        }
-                    }
-                    a0 = wave_sum_dpp(a0);
-                    a1 = wave_sum_dpp(a1);
-                    if (lane == 0) {
-                        z0[r] = sigma != 0.0 ? a0 - sigma * v0[r] : a0;
-                        z1[r] = sigma != 0.0 ? a1 - sigma * v1[r] : a1;
-                    }
+                for (int c = 0; c < EC; ++c) {
+                    const double mv = mreg[REG ? q : 0][REG ? c : 0];
+                    a0 += mv * x0[c];
+                    a1 += mv * x1[c];
+                }
+                a0 = wave_sum_dpp(a0);
+                a1 = wave_sum_dpp(a1);
+                if (lane == 0 && r < k) {
+                    z0[r] = sigma != 0.0 ? a0 - sigma * v0[r] : a0;
+                    z1[r] = sigma != 0.0 ? a1 - sigma * v1[r] : a1;
                 }
             }
         } else {
@@ -1029,7 +1029,7 @@ __host__ __device__ constexpr size_t eig_lds_bytes(int k) {
 }
 
 template <int KR>
-__global__ __launch_bounds__(kEigThreads) void k_pmds_eig(int k, const double* __restrict__ M, double tol,
+__global__ __launch_bounds__(eig_threads(KR)) void k_pmds_eig(int k, const double* __restrict__ M, double tol,
                                                          int max_iter, double* __restrict__ out,
                                                          int* __restrict__ iters) {
     pmds_eig_body<KR>(k, M, tol, max_iter, out, iters);
@@ -1167,16 +1167,16 @@ ssm_status pivotmds(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* x, hipStre
                            dim3(256), 0, s, k, nchunks, ntiles, tiles, part, M);
         const size_t elds = eig_lds_bytes(k);
         if (eig_reg_form(k) == 128) {
-            hipLaunchKernelGGL(k_pmds_eig<128>, dim3(1), dim3(kEigThreads), elds, s, k, M, 1e-13, 20000, t->eig,
+            hipLaunchKernelGGL(k_pmds_eig<128>, dim3(1), dim3(eig_threads(128)), elds, s, k, M, 1e-13, 20000, t->eig,
                                t->eig_iters);
         } else if (eig_reg_form(k) == 256) {
-            hipLaunchKernelGGL(k_pmds_eig<256>, dim3(1), dim3(kEigThreads), elds, s, k, M, 1e-13, 20000, t->eig,
+            hipLaunchKernelGGL(k_pmds_eig<256>, dim3(1), dim3(eig_threads(256)), elds, s, k, M, 1e-13, 20000, t->eig,
                                t->eig_iters);
         } else {
             if (elds > 64 * 1024)
                 (void)hipFuncSetAttribute((const void*)k_pmds_eig<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                           (int)elds);
-            hipLaunchKernelGGL(k_pmds_eig<0>, dim3(1), dim3(kEigThreads), elds, s, k, M, 1e-13, 20000, t->eig,
+            hipLaunchKernelGGL(k_pmds_eig<0>, dim3(1), dim3(eig_threads(0)), elds, s, k, M, 1e-13, 20000, t->eig,
                                t->eig_iters);
         }
         double2* xd = (double2*)t->xtmp;
@@ -1285,7 +1285,7 @@ __global__ void k_pool_gram_reduce(const PoolGraph* __restrict__ gs, const int2*
 }
 
 template <int KR>
-__global__ __launch_bounds__(kEigThreads) void k_pool_eig(const PoolGraph* __restrict__ gs) {
+__global__ __launch_bounds__(eig_threads(KR)) void k_pool_eig(const PoolGraph* __restrict__ gs) {
     const PoolGraph& g = gs[blockIdx.x];
     pmds_eig_body<KR>(g.k, g.M, 1e-13, 20000, g.eig, g.info + 4);
 }
@@ -1369,9 +1369,9 @@ hipError_t pool_pivotmds(const PoolGraph* gs, int count, const int4* gram_items,
                            tiles);
     hipLaunchKernelGGL(k_pool_gram_reduce, dim3(32, count), dim3(256), 0, s, gs, tiles);
     if (eig_reg_form(k_max) == 128)
-        hipLaunchKernelGGL(k_pool_eig<128>, dim3(count), dim3(kEigThreads), eig_lds_bytes(k_max), s, gs);
+        hipLaunchKernelGGL(k_pool_eig<128>, dim3(count), dim3(eig_threads(128)), eig_lds_bytes(k_max), s, gs);
     else
-        hipLaunchKernelGGL(k_pool_eig<256>, dim3(count), dim3(kEigThreads), eig_lds_bytes(k_max), s, gs);
+        hipLaunchKernelGGL(k_pool_eig<256>, dim3(count), dim3(eig_threads(256)), eig_lds_bytes(k_max), s, gs);
     hipLaunchKernelGGL(k_pool_project, dim3(count), dim3(1024), 0, s, gs);
     return hipGetLastError();
 }
@@ -1560,14 +1560,14 @@ ssm_status pivotmds_w(const ssm_csr* g, const double* len, int k, const double* 
                            0, s, k, nchunks, ntiles, tiles, part, M);
         const size_t elds = eig_lds_bytes(k);
         if (eig_reg_form(k) == 128) {
-            hipLaunchKernelGGL(k_pmds_eig<128>, dim3(1), dim3(kEigThreads), elds, s, k, M, 1e-13, 20000, eig, its);
+            hipLaunchKernelGGL(k_pmds_eig<128>, dim3(1), dim3(eig_threads(128)), elds, s, k, M, 1e-13, 20000, eig, its);
         } else if (eig_reg_form(k) == 256) {
-            hipLaunchKernelGGL(k_pmds_eig<256>, dim3(1), dim3(kEigThreads), elds, s, k, M, 1e-13, 20000, eig, its);
+            hipLaunchKernelGGL(k_pmds_eig<256>, dim3(1), dim3(eig_threads(256)), elds, s, k, M, 1e-13, 20000, eig, its);
         } else {
             if (elds > 64 * 1024)
                 (void)hipFuncSetAttribute((const void*)k_pmds_eig<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                           (int)elds);
-            hipLaunchKernelGGL(k_pmds_eig<0>, dim3(1), dim3(kEigThreads), elds, s, k, M, 1e-13, 20000, eig, its);
+            hipLaunchKernelGGL(k_pmds_eig<0>, dim3(1), dim3(eig_threads(0)), elds, s, k, M, 1e-13, 20000, eig, its);
         }
         hipLaunchKernelGGL(k_wpmds_project, dim3(gn), dim3(256), 0, s, n, k, dist, mu, nu, stats, eig, xd);
         hipLaunchKernelGGL(k_wpmds_edgelen, dim3(eb), dim3(256), 0, s, n, g->row_ptr, g->col_idx, len, xd, epart);

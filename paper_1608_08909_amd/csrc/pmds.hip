@@ -390,8 +390,11 @@ __device__ void eig_orth(int k, int pw, double* A, int draw) {
 // (row-major, stride kEigP), one thread: cyclic Jacobi rotations until the
 // off-diagonal part is below 1e-30 of the norm (or 64 sweeps).  Eigenvalues
 // into th (descending), eigenvectors into the columns of Y in the same order.
-__device__ void eig_small(int pw, const double* H, double* Y, double* th) {
-    double a[kEigP][kEigP], v[kEigP][kEigP];
+// The working matrices live in LDS (ws: 2 kEigP^2 doubles): indexed by
+// run-time rows and columns, as private arrays they went to scratch memory.
+__device__ void eig_small(int pw, const double* H, double* Y, double* th, double* ws) {
+    double(*a)[kEigP] = (double(*)[kEigP])ws;
+    double(*v)[kEigP] = (double(*)[kEigP])(ws + kEigP * kEigP);
     for (int i = 0; i < kEigP; ++i)
         for (int j = 0; j < kEigP; ++j) {
             a[i][j] = i < pw && j < pw ? H[i * kEigP + j] : 0.0;
@@ -467,6 +470,7 @@ __device__ __forceinline__ void eigp_body(int k, const double* __restrict__ M, d
     double* th = Y + kEigP * kEigP;  // [kEigP]
     __shared__ int s_done;
     __shared__ double red[kEigThreads / kWave];
+    __shared__ double s_small[2 * kEigP * kEigP];  // eig_small's working matrices
     const int lane = lane_id(), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
     const int pw = min(kEigP, k);
     for (int q = threadIdx.x; q < kEigP * k; q += blockDim.x) {
@@ -517,7 +521,7 @@ __device__ __forceinline__ void eigp_body(int k, const double* __restrict__ M, d
                             H[b * kEigP + a] = d;
                         }
                     }
-                if (lane == 0) eig_small(pw, H, Y, th);
+                if (lane == 0) eig_small(pw, H, Y, th, s_small);
                 __builtin_amdgcn_wave_barrier();
                 const bool rank1 = !(fabs(th[1]) > 1e-13 * fabs(th[0]));
                 const bool tie23 = pw > 2 && fabs(th[1] - th[2]) <= 1e-12 * fabs(th[0]);

@@ -118,6 +118,17 @@ constexpr int kF64TermsMaxN = 65536;
 constexpr int kF64MaxK = 128;
 constexpr int kF64Nodes = 256 / kF64Lanes;  // nodes per 256-thread block
 
+// Element idx of a packed distance word (the little-endian DT lanes of the
+// uint4), by shifts: a private array indexed at run time would live in
+// scratch memory, a round trip per read.
+template <typename DT>
+__device__ __forceinline__ int packed_at(const uint4 v, int idx) {
+    constexpr int per = 4 / (int)sizeof(DT), bits = 8 * (int)sizeof(DT);
+    const int wi = idx / per;
+    const unsigned w = wi == 0 ? v.x : wi == 1 ? v.y : wi == 2 ? v.z : v.w;
+    return (int)((w >> ((idx % per) * bits)) & ((1u << bits) - 1u));
+}
+
 template <typename DT, int VEC>
 __global__ __launch_bounds__(256) void k_sweep_f64_terms(int n, int kpad, int W, const int* __restrict__ rp,
                                                          const int* __restrict__ ci,
@@ -161,9 +172,7 @@ __global__ __launch_bounds__(256) void k_sweep_f64_terms(int n, int kpad, int W,
                 T[j] = v;
             }
             for (int t = lane; t < kpad; t += kF64Lanes) {
-                Packed<DT, VEC> u;
-                u.v = dpk[(size_t)(t / VEC) * n + i];
-                const int d = (int)u.e[t % VEC];
+                const int d = packed_at<DT>(dpk[(size_t)(t / VEC) * n + i], t % VEC);
                 double2 v = make_double2(0.0, 0.0);
                 if (d >= 2) {
                     const double w = wt[(size_t)t * W + d];

@@ -459,6 +459,23 @@ __global__ __launch_bounds__(256) void k_stress(int n, int kpad, int W, const in
     if (threadIdx.x == 0) partials[blockIdx.x] = acc;
 }
 
+// The twelve moments summed over a 256-thread block: wave sums by DPP, one
+// barrier, then a fixed-order sum over the waves; thread j < kMoments gets
+// moment j.  Call from uniform control flow.
+__device__ __forceinline__ double block_moments(const double (&m)[kMoments], double* red) {
+    const int w = threadIdx.x / kWave;
+#pragma unroll
+    for (int j = 0; j < kMoments; ++j) {
+        const double v = wave_sum_dpp(m[j]);
+        if (lane_id() == 0) red[w * kMoments + j] = v;
+    }
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x < kMoments)
+        for (int q = 0; q < 256 / kWave; ++q) t += red[q * kMoments + threadIdx.x];
+    return t;
+}
+
 // Algorithm 1's stop test after a sweep xo -> xn (change.h): per-block
 // partials of the twelve moments, relative to o = xo[0].
 template <typename T2>
@@ -471,12 +488,9 @@ __global__ __launch_bounds__(256) void k_rigid_moments(int n, const T2* __restri
     for (int j = 0; j < kMoments; ++j) m[j] = 0.0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
         moments_add(m, o, to_d2(xo[i]), to_d2(xn[i]));
-    __shared__ double red[256 / kWave];
-#pragma unroll
-    for (int j = 0; j < kMoments; ++j) {
-        const double v = block_sum(m[j], red);
-        if (threadIdx.x == 0) partials[(size_t)blockIdx.x * kMoments + j] = v;
-    }
+    __shared__ double red[(256 / kWave) * kMoments];
+    const double v = block_moments(m, red);
+    if (threadIdx.x < kMoments) partials[(size_t)blockIdx.x * kMoments + threadIdx.x] = v;
 }
 
 // One block: sums the partials in a fixed order; after sweep `it` (0-based)
@@ -486,15 +500,21 @@ __global__ __launch_bounds__(256) void k_rigid_decide(int nblocks, const double*
                                                       double tol, int it, int* __restrict__ stopw,
                                                       double* __restrict__ last_change) {
     if (stopw[0]) return;
-    __shared__ double red[256 / kWave];
+    __shared__ double red[(256 / kWave) * kMoments];
+    __shared__ double s_m[kMoments];
     double m[kMoments];
 #pragma unroll
     for (int j = 0; j < kMoments; ++j) {
         double v = 0.0;
         for (int q = threadIdx.x; q < nblocks; q += blockDim.x) v += partials[(size_t)q * kMoments + j];
-        m[j] = block_sum(v, red);
+        m[j] = v;
     }
+    const double v = block_moments(m, red);
+    if (threadIdx.x < kMoments) s_m[threadIdx.x] = v;
+    __syncthreads();
     if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < kMoments; ++j) m[j] = s_m[j];
         const double c = rigid_change(m, n);
         last_change[0] = c;
         if (c <= tol) {

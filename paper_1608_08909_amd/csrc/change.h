@@ -10,6 +10,7 @@
 #include <math.h>
 
 #include "ssm_internal.h"
+#include "wave.h"
 
 namespace ssm {
 
@@ -53,6 +54,23 @@ __device__ __forceinline__ double rigid_change(const double (&m)[kMoments], int 
 template <typename T2>
 __device__ __forceinline__ double2 to_d2(const T2 v) {
     return make_double2((double)v.x, (double)v.y);
+}
+
+// The twelve moments summed over a 256-thread block: wave sums by DPP, one
+// barrier, then a fixed-order sum over the waves; thread j < kMoments gets
+// moment j.  Call from uniform control flow.
+__device__ __forceinline__ double block_moments(const double (&m)[kMoments], double* red) {
+    const int w = threadIdx.x / kWave;
+#pragma unroll
+    for (int j = 0; j < kMoments; ++j) {
+        const double v = wave_sum_dpp(m[j]);
+        if (lane_id() == 0) red[w * kMoments + j] = v;
+    }
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x < kMoments)
+        for (int q = 0; q < 256 / kWave; ++q) t += red[q * kMoments + threadIdx.x];
+    return t;
 }
 
 }  // namespace ssm

@@ -406,21 +406,9 @@ __global__ __launch_bounds__(256) void k_pool_moments(const PoolGraph* __restric
     for (int j = 0; j < kMoments; ++j) m[j] = 0.0;
     const int i = ch.y + threadIdx.x;
     if (i < g.n) moments_add(m, o, to_d2(xo[i]), to_d2(xn[i]));
-    // the twelve wave sums in registers, then one barrier and a fixed-order
-    // sum over the block's waves
     __shared__ double red[(256 / kWave) * kMoments];
-    const int w = threadIdx.x / kWave;
-#pragma unroll
-    for (int j = 0; j < kMoments; ++j) {
-        const double v = wave_sum_dpp(m[j]);
-        if (lane_id() == 0) red[w * kMoments + j] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < kMoments) {
-        double t = 0.0;
-        for (int q = 0; q < 256 / kWave; ++q) t += red[q * kMoments + threadIdx.x];
-        partial[(size_t)blockIdx.x * kMoments + threadIdx.x] = t;
-    }
+    const double v = block_moments(m, red);
+    if (threadIdx.x < kMoments) partial[(size_t)blockIdx.x * kMoments + threadIdx.x] = v;
 }
 
 // One wave per listed graph: lane l sums the chunk partials first[q] + l,

@@ -459,23 +459,6 @@ __global__ __launch_bounds__(256) void k_stress(int n, int kpad, int W, const in
     if (threadIdx.x == 0) partials[blockIdx.x] = acc;
 }
 
-// The twelve moments summed over a 256-thread block: wave sums by DPP, one
-// barrier, then a fixed-order sum over the waves; thread j < kMoments gets
-// moment j.  Call from uniform control flow.
-__device__ __forceinline__ double block_moments(const double (&m)[kMoments], double* red) {
-    const int w = threadIdx.x / kWave;
-#pragma unroll
-    for (int j = 0; j < kMoments; ++j) {
-        const double v = wave_sum_dpp(m[j]);
-        if (lane_id() == 0) red[w * kMoments + j] = v;
-    }
-    __syncthreads();
-    double t = 0.0;
-    if (threadIdx.x < kMoments)
-        for (int q = 0; q < 256 / kWave; ++q) t += red[q * kMoments + threadIdx.x];
-    return t;
-}
-
 // Algorithm 1's stop test after a sweep xo -> xn (change.h): per-block
 // partials of the twelve moments, relative to o = xo[0].
 template <typename T2>

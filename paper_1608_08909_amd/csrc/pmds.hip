@@ -308,15 +308,34 @@ __device__ __forceinline__ double splitmix_uniform(unsigned long long& state) {
     return (double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;  // [-1, 1)
 }
 
+constexpr int kEigP = 8;      // subspace width of the block iteration
 constexpr int kEigThreads = 1024;  // the largest workgroup of the eigen kernels
 // M in registers for k <= KR (KR = 128 or 256): KR / (waves) rows of M per
 // wave, KR / 64 columns per lane.  KR = 128 runs on 512 threads, whose 256
 // registers each hold the copy (at 1024 threads a thread has 128, and the
 // copy spilled to scratch: a scratch round trip per row of M V); KR = 256
-// runs on 1024 threads and partly spills (its copy alone needs 128).
+// runs on 1024 threads with its rows below 128 in registers.
 constexpr int kEigRegMax = 256;
 __host__ __device__ constexpr int eig_threads(int KR) { return KR == 128 ? 512 : kEigThreads; }
-__host__ __device__ constexpr int eig_reg_rows(int KR) { return KR > 0 ? KR / (eig_threads(KR) / 64) : 1; }
+// LDS bytes of pmds_eig_body for k.
+__host__ __device__ constexpr size_t eig_lds_bytes(int k) {
+    return sizeof(double) * ((size_t)(2 * kEigP + 2) * k + 2 * kEigP * kEigP + kEigP);
+}
+// Rows of M (from row 128 on) that the KR = 256 form keeps in LDS after
+// pmds_eig_body's own arrays, within the workgroup's 160 KB (4 KB left for
+// the static arrays).
+constexpr long long kEigLdsBudget = 160 * 1024 - 4 * 1024;
+__host__ __device__ constexpr int eig_m_lds_rows(int k) {
+    return k <= 128 ? 0
+                    : (int)(((long long)(k - 128) * k * 8 <= kEigLdsBudget - (long long)eig_lds_bytes(k))
+                                ? (long long)(k - 128)
+                                : (kEigLdsBudget - (long long)eig_lds_bytes(k)) / (8LL * k));
+}
+// Rows below 128 in registers; KR = 256 keeps its rows from 128 on in LDS as
+// far as it holds them (eig_m_lds_rows) and reads the rest from memory.
+__host__ __device__ constexpr int eig_reg_rows(int KR) {
+    return KR > 0 ? (KR < 128 ? KR : 128) / (eig_threads(KR) / 64) : 1;
+}
 __host__ __device__ constexpr int eig_reg_cols(int KR) { return KR > 0 ? KR / 64 : 1; }
 // The register form for a k x k Gram matrix: 128, 256, or 0 (M in global memory).
 __host__ __device__ constexpr int eig_reg_form(int k) { return k <= 128 ? 128 : k <= kEigRegMax ? 256 : 0; }
@@ -331,7 +350,6 @@ __host__ __device__ constexpr int eig_reg_form(int k) { return k <= 128 ? 128 : 
 constexpr int kEigFast = 400;
 constexpr int kEigProbe = 32;  // first step of the rate test
 constexpr int kEigProbeEvery = 16;
-constexpr int kEigP = 8;      // subspace width of the block iteration
 constexpr int kEigCheck = 8;  // steps between Rayleigh-Ritz convergence tests
 
 // Start / replacement vector entry (row r, column c, draw d): SplitMix64 in
@@ -646,7 +664,7 @@ __device__ __forceinline__ void block_max_n(double (&v)[N], double* scratch) {
 
 template <int KR>
 __device__ __forceinline__ bool eig2_body(int k, const double* __restrict__ M, double tol, int max_iter,
-                                          double* __restrict__ out, int* __restrict__ iters, int& used) {
+                                          double* __restrict__ out, int* __restrict__ iters, int& used, int mrows) {
     constexpr bool REG = KR > 0;
     constexpr int ER = eig_reg_rows(KR), EC = eig_reg_cols(KR);
     extern __shared__ double sh[];
@@ -667,6 +685,10 @@ __device__ __forceinline__ bool eig2_body(int k, const double* __restrict__ M, d
                 mreg[REG ? q : 0][REG ? c : 0] = (r < k && j < k) ? M[(size_t)r * k + j] : 0.0;
             }
     }
+    // KR = 256: rows 128 .. 128 + mrows - 1 of M in LDS, after the iterations' own arrays
+    double* Ml = sh + eig_lds_bytes(k) / sizeof(double);
+    if (KR > 128)
+        for (int q = threadIdx.x; q < mrows * k; q += blockDim.x) Ml[q] = M[(size_t)128 * k + q];
     if (threadIdx.x == 0) {
         unsigned long long s0 = 0x53534D00ull, s1 = 0x53534D01ull;
         for (int t = 0; t < k; ++t) {
@@ -709,6 +731,27 @@ __device__ __forceinline__ bool eig2_body(int k, const double* __restrict__ M, d
                 if (lane == 0 && r < k) {
                     z0[r] = sigma != 0.0 ? a0 - sigma * v0[r] : a0;
                     z1[r] = sigma != 0.0 ? a1 - sigma * v1[r] : a1;
+                }
+            }
+            // KR = 256: the rows from 128 on, from LDS or memory, each lane's
+            // columns in the same order as the register rows
+            if (KR > 128) {
+                for (int r = 128 + w; r < k; r += nw) {  // uniform across the wave
+                    const double* row = r < 128 + mrows ? Ml + (size_t)(r - 128) * k : M + (size_t)r * k;
+                    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+                    for (int c = 0; c < EC; ++c) {
+                        const int j = lane + kWave * c;
+                        const double mv = j < k ? row[j] : 0.0;
+                        a0 += mv * x0[c];
+                        a1 += mv * x1[c];
+                    }
+                    a0 = wave_sum_dpp(a0);
+                    a1 = wave_sum_dpp(a1);
+                    if (lane == 0) {
+                        z0[r] = sigma != 0.0 ? a0 - sigma * v0[r] : a0;
+                        z1[r] = sigma != 0.0 ? a1 - sigma * v1[r] : a1;
+                    }
                 }
             }
         } else {
@@ -1019,24 +1062,20 @@ __device__ __forceinline__ bool eig2_body(int k, const double* __restrict__ M, d
 // within them), then, if it has not converged, the block iteration.
 template <int KR>
 __device__ __forceinline__ void pmds_eig_body(int k, const double* __restrict__ M, double tol, int max_iter,
-                                              double* __restrict__ out, int* __restrict__ iters) {
+                                              double* __restrict__ out, int* __restrict__ iters, int mrows) {
     const int fast = min(max_iter, kEigFast);
     int used = 0;
-    if (eig2_body<KR>(k, M, tol, fast, out, iters, used)) return;
+    if (eig2_body<KR>(k, M, tol, fast, out, iters, used, mrows)) return;
     __syncthreads();
     eigp_body(k, M, tol, max_iter - used, used, out, iters);
 }
 
-// LDS bytes of pmds_eig_body for k.
-__host__ __device__ constexpr size_t eig_lds_bytes(int k) {
-    return sizeof(double) * ((size_t)(2 * kEigP + 2) * k + 2 * kEigP * kEigP + kEigP);
-}
 
 template <int KR>
 __global__ __launch_bounds__(eig_threads(KR)) void k_pmds_eig(int k, const double* __restrict__ M, double tol,
                                                          int max_iter, double* __restrict__ out,
-                                                         int* __restrict__ iters) {
-    pmds_eig_body<KR>(k, M, tol, max_iter, out, iters);
+                                                         int* __restrict__ iters, int mrows) {
+    pmds_eig_body<KR>(k, M, tol, max_iter, out, iters, mrows);
 }
 
 // x_i = sum over t ascending of C_it V_t (per column), FP64.
@@ -1172,16 +1211,21 @@ ssm_status pivotmds(const ssm_csr* g, ssm_terms* t, ssm_prec p, void* x, hipStre
         const size_t elds = eig_lds_bytes(k);
         if (eig_reg_form(k) == 128) {
             hipLaunchKernelGGL(k_pmds_eig<128>, dim3(1), dim3(eig_threads(128)), elds, s, k, M, 1e-13, 20000, t->eig,
-                               t->eig_iters);
+                               t->eig_iters, 0);
         } else if (eig_reg_form(k) == 256) {
-            hipLaunchKernelGGL(k_pmds_eig<256>, dim3(1), dim3(eig_threads(256)), elds, s, k, M, 1e-13, 20000, t->eig,
-                               t->eig_iters);
+            const int mrows = eig_m_lds_rows(k);
+            const size_t lds = elds + sizeof(double) * (size_t)mrows * k;
+            if (lds > 64 * 1024)
+                (void)hipFuncSetAttribute((const void*)k_pmds_eig<256>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          (int)lds);
+            hipLaunchKernelGGL(k_pmds_eig<256>, dim3(1), dim3(eig_threads(256)), lds, s, k, M, 1e-13, 20000, t->eig,
+                               t->eig_iters, mrows);
         } else {
             if (elds > 64 * 1024)
                 (void)hipFuncSetAttribute((const void*)k_pmds_eig<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                           (int)elds);
             hipLaunchKernelGGL(k_pmds_eig<0>, dim3(1), dim3(eig_threads(0)), elds, s, k, M, 1e-13, 20000, t->eig,
-                               t->eig_iters);
+                               t->eig_iters, 0);
         }
         double2* xd = (double2*)t->xtmp;
         if (t->dbytes == 1)
@@ -1291,7 +1335,7 @@ __global__ void k_pool_gram_reduce(const PoolGraph* __restrict__ gs, const int2*
 template <int KR>
 __global__ __launch_bounds__(eig_threads(KR)) void k_pool_eig(const PoolGraph* __restrict__ gs) {
     const PoolGraph& g = gs[blockIdx.x];
-    pmds_eig_body<KR>(g.k, g.M, 1e-13, 20000, g.eig, g.info + 4);
+    pmds_eig_body<KR>(g.k, g.M, 1e-13, 20000, g.eig, g.info + 4, 0);
 }
 
 // Per graph: x64[0] = C V (ranks ascending), then the uniform rescale that
@@ -1564,14 +1608,21 @@ ssm_status pivotmds_w(const ssm_csr* g, const double* len, int k, const double* 
                            0, s, k, nchunks, ntiles, tiles, part, M);
         const size_t elds = eig_lds_bytes(k);
         if (eig_reg_form(k) == 128) {
-            hipLaunchKernelGGL(k_pmds_eig<128>, dim3(1), dim3(eig_threads(128)), elds, s, k, M, 1e-13, 20000, eig, its);
+            hipLaunchKernelGGL(k_pmds_eig<128>, dim3(1), dim3(eig_threads(128)), elds, s, k, M, 1e-13, 20000, eig, its,
+                               0);
         } else if (eig_reg_form(k) == 256) {
-            hipLaunchKernelGGL(k_pmds_eig<256>, dim3(1), dim3(eig_threads(256)), elds, s, k, M, 1e-13, 20000, eig, its);
+            const int mrows = eig_m_lds_rows(k);
+            const size_t lds = elds + sizeof(double) * (size_t)mrows * k;
+            if (lds > 64 * 1024)
+                (void)hipFuncSetAttribute((const void*)k_pmds_eig<256>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          (int)lds);
+            hipLaunchKernelGGL(k_pmds_eig<256>, dim3(1), dim3(eig_threads(256)), lds, s, k, M, 1e-13, 20000, eig, its,
+                               mrows);
         } else {
             if (elds > 64 * 1024)
                 (void)hipFuncSetAttribute((const void*)k_pmds_eig<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                           (int)elds);
-            hipLaunchKernelGGL(k_pmds_eig<0>, dim3(1), dim3(eig_threads(0)), elds, s, k, M, 1e-13, 20000, eig, its);
+            hipLaunchKernelGGL(k_pmds_eig<0>, dim3(1), dim3(eig_threads(0)), elds, s, k, M, 1e-13, 20000, eig, its, 0);
         }
         hipLaunchKernelGGL(k_wpmds_project, dim3(gn), dim3(256), 0, s, n, k, dist, mu, nu, stats, eig, xd);
         hipLaunchKernelGGL(k_wpmds_edgelen, dim3(eb), dim3(256), 0, s, n, g->row_ptr, g->col_idx, len, xd, epart);

@@ -96,6 +96,26 @@ def test_pool_pivotmds_and_warm_sweep():
     p1.close()
 
 
+LARGE_K = [(G.rgg(3000, 5), 150), (G.tri_grid(30, 40), 200), (G.tree_plus(2000, 3), 250), (G.grid(20, 25), 60)]
+
+
+def test_pool_pivotmds_large_k():
+    """A batch whose largest k lies in (128, 256]: the pooled eigen step's
+    larger register form, rows from 128 on read from memory."""
+    pool, slots = _pool_with(LARGE_K, warm=0)
+    for (g, k), s in zip(LARGE_K, slots):
+        say("case", g.name, "k", k)
+        ref = oracle.preprocess(g.n, g.row_ptr, g.col_idx, k)
+        x0 = pool.export(s, ssm.POOL_X64)
+        xo, _, _ = oracle.pivotmds(ref.dist)
+        xr = oracle.rescale(g.row_ptr, g.col_idx, xo)
+        w = np.linalg.eigvalsh(oracle.gram(oracle.pmds_center(ref.dist)))[::-1]
+        assert w[1] > 1e-8 * w[0] and (w[1] - w[2]) / w[0] > 1e-6  # the plane is unique on these graphs
+        well = (w[0] - w[1]) / w[0] > 1e-3
+        assert brute.coord_error(x0, xr, align=not well) < 1e-9
+    pool.close()
+
+
 def test_pool_fp32_final_stress_vs_plain_fp64():
     graphs = [(G.grid(50, 50), 50), (G.rgg(3000, 9, 8.0), 100), (G.tree_plus(2000, 6), 100),
               (G.grid(23, 71), 100), (G.rgg(800, 2, 7.0), 80)]

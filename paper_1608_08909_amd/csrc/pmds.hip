@@ -314,9 +314,9 @@ constexpr int kEigThreads = 1024;  // the largest workgroup of the eigen kernels
 // wave, KR / 64 columns per lane.  KR = 128 runs on 512 threads, whose 256
 // registers each hold the copy (at 1024 threads a thread has 128, and the
 // copy spilled to scratch: a scratch round trip per row of M V); KR = 256
-// runs on 1024 threads with its rows below 128 in registers.
+// runs on 512 threads too, with its rows below 128 in registers.
 constexpr int kEigRegMax = 256;
-__host__ __device__ constexpr int eig_threads(int KR) { return KR == 128 ? 512 : kEigThreads; }
+__host__ __device__ constexpr int eig_threads(int KR) { return KR > 0 ? 512 : kEigThreads; }
 // LDS bytes of pmds_eig_body for k.
 __host__ __device__ constexpr size_t eig_lds_bytes(int k) {
     return sizeof(double) * ((size_t)(2 * kEigP + 2) * k + 2 * kEigP * kEigP + kEigP);
